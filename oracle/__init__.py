@@ -1,0 +1,275 @@
+"""CPU oracle for the FS-1 Sinkhorn method (arXiv 2202.10042).
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the CPU-baseline leg of
+the benchmark use this package to check the GPU library; the library itself never
+imports it.  The arithmetic lives in ``fs1_oracle.c`` (plain binary64 C, no code
+shared with the GPU path); this module only marshals numpy arrays.
+
+What each routine follows in the paper:
+
+* ``kv_dense`` / ``kv_log_dense``: K x and ln K e^x with K_ij = exp(-|i-j| h/eps)
+  formed entry by entry (Sec. 2, the kernel of the scaling form; Sec. 3, the full
+  Toeplitz expansion of K psi).
+* ``kv_fs1`` / ``kv_fs1_log``: the Sec. 3 recursions for the lower part p and the
+  strict upper part q (Qin Jiushao / Horner form), and the same recursions on
+  logarithms.
+* ``sinkhorn_dense`` / ``sinkhorn_log_dense``: the Sinkhorn update of Sec. 2 (psi
+  first, then phi) inside Algorithm 1's loop, stopping rule and return value, with
+  K dense.
+* ``fs1`` / ``fs1_log``: Algorithm 1 (FS-1) with the recursions; the log variant
+  is the limit of the log-domain absorption (Sec. 2 and Sec. 3 remarks) where
+  all of phi and psi is absorbed at every step.
+* ``cost_*`` / ``marginal_err_*``: the returned double sum and the stopping-test
+  double sum of Algorithm 1, literally (``*_dense``) and by recursions (``*_fs1``).
+
+Pins: every routine is checked in ``tests/test_oracle_pins.py`` against facts the
+paper or the mathematics fixes (closed form of K 1 from the stability analysis of
+Sec. 3, library products, Dirac marginals, the N = 2 closed form, the 1-D linear
+programme / CDF formula, the entropic bound, the smooth-dual Newton solve, the
+invariants and the plan differences of Tables 1 and 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fs1_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libfs1_oracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile fs1_oracle.c with gcc (-O2, IEEE semantics, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    d = ctypes.c_double
+    i64 = ctypes.c_int64
+    p = ctypes.c_void_p
+    sig = {
+        "or_kv_dense": (ctypes.c_int, [i64, p, d, d, p]),
+        "or_kv_dense_rows": (ctypes.c_int, [i64, p, d, d, p, i64, p]),
+        "or_kv_log_dense": (ctypes.c_int, [i64, p, d, d, p]),
+        "or_kv_log_dense_rows": (ctypes.c_int, [i64, p, d, d, p, i64, p]),
+        "or_kv_fs1": (ctypes.c_int, [i64, p, d, d, p]),
+        "or_kv_fs1_log": (ctypes.c_int, [i64, p, d, d, p]),
+        "or_marginal_err_dense": (d, [i64, p, p, p, d, d]),
+        "or_cost_dense": (d, [i64, p, p, d, d]),
+        "or_marginal_err_log_dense": (d, [i64, p, p, p, d, d]),
+        "or_cost_log_dense": (d, [i64, p, p, d, d]),
+        "or_marginal_err_fs1": (d, [i64, p, p, p, d, d]),
+        "or_cost_fs1": (d, [i64, p, p, d, d]),
+        "or_marginal_err_fs1_log": (d, [i64, p, p, p, d, d]),
+        "or_cost_fs1_log": (d, [i64, p, p, d, d]),
+        "or_sinkhorn_dense": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
+        "or_sinkhorn_log_dense": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
+        "or_fs1": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
+        "or_fs1_log": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
+        "or_num_threads": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+# --------------------------------------------------------------------------
+# kernel application
+# --------------------------------------------------------------------------
+
+def kv_dense(x, h: float, eps: float, rows=None) -> np.ndarray:
+    """(K x)_i for all i (or the listed rows), K_ij = exp(-|i-j| h/eps)."""
+    x = _f64(x)
+    n = x.size
+    lib = _load()
+    if rows is None:
+        y = np.empty(n)
+        st = lib.or_kv_dense(n, _ptr(x), h, eps, _ptr(y))
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        y = np.empty(r.size)
+        st = lib.or_kv_dense_rows(n, _ptr(x), h, eps, _ptr(r), r.size, _ptr(y))
+    if st != 0:
+        raise ValueError(f"or_kv_dense: status {st}")
+    return y
+
+
+def kv_log_dense(lx, h: float, eps: float, rows=None) -> np.ndarray:
+    """ln (K e^{lx})_i, max-shifted; -inf entries allowed."""
+    lx = _f64(lx)
+    n = lx.size
+    lib = _load()
+    if rows is None:
+        y = np.empty(n)
+        st = lib.or_kv_log_dense(n, _ptr(lx), h, eps, _ptr(y))
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        y = np.empty(r.size)
+        st = lib.or_kv_log_dense_rows(n, _ptr(lx), h, eps, _ptr(r), r.size, _ptr(y))
+    if st != 0:
+        raise ValueError(f"or_kv_log_dense: status {st}")
+    return y
+
+
+def kv_fs1(x, h: float, eps: float) -> np.ndarray:
+    x = _f64(x)
+    y = np.empty(x.size)
+    st = _load().or_kv_fs1(x.size, _ptr(x), h, eps, _ptr(y))
+    if st != 0:
+        raise ValueError(f"or_kv_fs1: status {st}")
+    return y
+
+
+def kv_fs1_log(lx, h: float, eps: float) -> np.ndarray:
+    lx = _f64(lx)
+    y = np.empty(lx.size)
+    st = _load().or_kv_fs1_log(lx.size, _ptr(lx), h, eps, _ptr(y))
+    if st != 0:
+        raise ValueError(f"or_kv_fs1_log: status {st}")
+    return y
+
+
+# --------------------------------------------------------------------------
+# the two double sums of Algorithm 1
+# --------------------------------------------------------------------------
+
+def marginal_err_dense(phi, psi, nu, h, eps) -> float:
+    phi, psi, nu = _f64(phi), _f64(psi), _f64(nu)
+    return float(_load().or_marginal_err_dense(phi.size, _ptr(phi), _ptr(psi), _ptr(nu), h, eps))
+
+
+def cost_dense(phi, psi, h, eps) -> float:
+    phi, psi = _f64(phi), _f64(psi)
+    return float(_load().or_cost_dense(phi.size, _ptr(phi), _ptr(psi), h, eps))
+
+
+def marginal_err_log_dense(F, G, nu, h, eps) -> float:
+    F, G, nu = _f64(F), _f64(G), _f64(nu)
+    return float(_load().or_marginal_err_log_dense(F.size, _ptr(F), _ptr(G), _ptr(nu), h, eps))
+
+
+def cost_log_dense(F, G, h, eps) -> float:
+    F, G = _f64(F), _f64(G)
+    return float(_load().or_cost_log_dense(F.size, _ptr(F), _ptr(G), h, eps))
+
+
+def marginal_err_fs1(phi, psi, nu, h, eps) -> float:
+    phi, psi, nu = _f64(phi), _f64(psi), _f64(nu)
+    return float(_load().or_marginal_err_fs1(phi.size, _ptr(phi), _ptr(psi), _ptr(nu), h, eps))
+
+
+def cost_fs1(phi, psi, h, eps) -> float:
+    phi, psi = _f64(phi), _f64(psi)
+    return float(_load().or_cost_fs1(phi.size, _ptr(phi), _ptr(psi), h, eps))
+
+
+def marginal_err_fs1_log(F, G, nu, h, eps) -> float:
+    F, G, nu = _f64(F), _f64(G), _f64(nu)
+    return float(_load().or_marginal_err_fs1_log(F.size, _ptr(F), _ptr(G), _ptr(nu), h, eps))
+
+
+def cost_fs1_log(F, G, h, eps) -> float:
+    F, G = _f64(F), _f64(G)
+    return float(_load().or_cost_fs1_log(F.size, _ptr(F), _ptr(G), h, eps))
+
+
+# --------------------------------------------------------------------------
+# solvers
+# --------------------------------------------------------------------------
+
+@dataclass
+class OracleResult:
+    w1: float            # the value Algorithm 1 returns: sum phi_i psi_j K_ij |i-j| h
+    marginal_err: float  # final nu-side L1 marginal error
+    iterations: int      # completed (psi, phi) pairs
+    status: int          # 0 ok, -2 non-finite scaling (abnormal termination)
+    converged: bool      # stopping test met (err <= tol)
+    a: np.ndarray        # phi (linear solvers) or F = ln phi (log solvers)
+    b: np.ndarray        # psi (linear solvers) or G = ln psi (log solvers)
+
+
+def _solve(fname, mu, nu, h, eps, tol, itr_max) -> OracleResult:
+    mu, nu = _f64(mu), _f64(nu)
+    n = mu.size
+    if nu.size != n:
+        raise ValueError("mu and nu must have the same length")
+    a = np.empty(n)
+    b = np.empty(n)
+    res = np.zeros(5)
+    st = getattr(_load(), fname)(n, _ptr(mu), _ptr(nu), h, eps, tol, int(itr_max),
+                                 _ptr(a), _ptr(b), _ptr(res))
+    if st == -1:
+        raise ValueError(f"{fname}: invalid argument")
+    if st == -4:
+        raise MemoryError(fname)
+    return OracleResult(float(res[0]), float(res[1]), int(res[2]), int(res[3]),
+                        bool(res[4]), a, b)
+
+
+def sinkhorn_dense(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve("or_sinkhorn_dense", mu, nu, h, eps, tol, itr_max)
+
+
+def sinkhorn_log_dense(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve("or_sinkhorn_log_dense", mu, nu, h, eps, tol, itr_max)
+
+
+def fs1(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve("or_fs1", mu, nu, h, eps, tol, itr_max)
+
+
+def fs1_log(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve("or_fs1_log", mu, nu, h, eps, tol, itr_max)
+
+
+def plan_linear(phi, psi, h, eps) -> np.ndarray:
+    """P_ij = phi_i exp(-|i-j| h/eps) psi_j (the scaling form of Sec. 2)."""
+    phi, psi = _f64(phi), _f64(psi)
+    n = phi.size
+    d = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.float64)
+    return phi[:, None] * np.exp(-d * (h / eps)) * psi[None, :]
+
+
+def plan_log(F, G, h, eps) -> np.ndarray:
+    """P_ij = exp(F_i + G_j - |i-j| h/eps)."""
+    F, G = _f64(F), _f64(G)
+    n = F.size
+    d = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        t = F[:, None] + G[None, :] - d * (h / eps)
+    t = np.where(np.isnan(t), -np.inf, t)
+    return np.exp(t)

@@ -1,0 +1,509 @@
+/*
+ * fs1_oracle.c -- CPU reference for the FS-1 Sinkhorn method (Liao, Chen, Wang,
+ * Bai, Jin, Wu: "Fast Sinkhorn I: an O(N) algorithm for the Wasserstein-1
+ * metric", arXiv 2202.10042).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with the
+ * GPU library, and the GPU library never calls it.
+ *
+ * Everything is plain IEEE binary64 (no fast-math), written for readability:
+ *   - the dense routines follow the definitions (Sec. 2: the discrete entropic
+ *     problem, the scaling form gamma_ij = phi_i K_ij psi_j with
+ *     K_ij = exp(-|i-j| h / eps), and the Sinkhorn update that refreshes psi
+ *     first and then phi), with K formed entry by entry from its definition;
+ *   - the sequential routines follow Sec. 3: the split of row k of K psi into
+ *     the lower part p_k and the strict upper part q_k and their first-order
+ *     recursions (Qin Jiushao / Horner form), driven by Algorithm 1 (FS-1);
+ *   - the log-domain routines are the same iterations written on the
+ *     logarithms F = ln(phi), G = ln(psi): the limit of the absorption
+ *     stabilisation (Sec. 2, remark on log-domain stabilisation; Sec. 3, remark
+ *     on the stabilised FS-1) in which the whole of phi and psi is absorbed at
+ *     every step.
+ *
+ * Readings of points the paper leaves open (zero masses, the stopping rule, the
+ * returned value) are stated where they are used.
+ *
+ * Indices are 0..n-1 here (1..N in the paper).  c = h / eps = -ln(lambda).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_INVALID_ARG (-1)
+#define OR_ERR_NONFINITE (-2)
+#define OR_ERR_NO_MEMORY (-4)
+
+/* log(exp(a) + exp(b)) with exp(-inf) = 0; never produces NaN for -inf inputs. */
+static double lse2(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernel application, dense form (definition of K in Sec. 2; the full       */
+/* Toeplitz expansion of K psi in Sec. 3).                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Table of the n distinct kernel entries e^{-d h / eps}, d = |i - j|. */
+static double *kernel_table(int64_t n, double c) {
+    double *kd = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!kd) return NULL;
+    for (int64_t d = 0; d < n; ++d) kd[d] = exp(-(double)d * c);
+    return kd;
+}
+
+/* y_i = sum_j e^{-|i-j| h/eps} x_j for the rows listed in `rows` (all rows when
+ * rows == NULL; then nrows must equal n and y has length n). */
+int or_kv_dense_rows(int64_t n, const double *x, double h, double eps,
+                     const int64_t *rows, int64_t nrows, double *y) {
+    if (n < 1 || !(h > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    double c = h / eps;
+    double *kd = kernel_table(n, c);
+    if (!kd) return OR_ERR_NO_MEMORY;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t d = i > j ? i - j : j - i;
+            s += kd[d] * x[j];
+        }
+        y[r] = s;
+    }
+    free(kd);
+    return OR_OK;
+}
+
+int or_kv_dense(int64_t n, const double *x, double h, double eps, double *y) {
+    return or_kv_dense_rows(n, x, h, eps, NULL, n, y);
+}
+
+/* ly_i = log sum_j exp(lx_j - |i-j| h/eps), max-shifted; -inf entries allowed. */
+int or_kv_log_dense_rows(int64_t n, const double *lx, double h, double eps,
+                         const int64_t *rows, int64_t nrows, double *ly) {
+    if (n < 1 || !(h > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    double c = h / eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double m = -INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            double d = (double)(i > j ? i - j : j - i);
+            double t = lx[j] - d * c;
+            if (t > m) m = t;
+        }
+        if (m == -INFINITY) { ly[r] = -INFINITY; continue; }
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double d = (double)(i > j ? i - j : j - i);
+            s += exp(lx[j] - d * c - m);
+        }
+        ly[r] = m + log(s);
+    }
+    return OR_OK;
+}
+
+int or_kv_log_dense(int64_t n, const double *lx, double h, double eps, double *ly) {
+    return or_kv_log_dense_rows(n, lx, h, eps, NULL, n, ly);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernel application by the FS-1 recursions (Sec. 3).                       */
+/*   p_0 = x_0,      p_{k+1} = lambda p_k + x_{k+1}        (lower part)      */
+/*   q_{n-1} = 0,    q_k = lambda (q_{k+1} + x_{k+1})      (strict upper)    */
+/*   (K x)_k = p_k + q_k                                                     */
+/* ------------------------------------------------------------------------- */
+
+int or_kv_fs1(int64_t n, const double *x, double h, double eps, double *y) {
+    if (n < 1 || !(h > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    double lam = exp(-h / eps);
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    if (!q) return OR_ERR_NO_MEMORY;
+    q[n - 1] = 0.0;
+    for (int64_t k = n - 2; k >= 0; --k) q[k] = lam * (q[k + 1] + x[k + 1]);
+    double p = x[0];
+    y[0] = p + q[0];
+    for (int64_t k = 1; k < n; ++k) {
+        p = lam * p + x[k];
+        y[k] = p + q[k];
+    }
+    free(q);
+    return OR_OK;
+}
+
+/* The same recursions on logarithms: with X = ln x,
+ *   A_0 = X_0,        A_{k+1} = lse(A_k - c, X_{k+1})
+ *   B_{n-1} = -inf,   B_k = lse(B_{k+1}, X_{k+1}) - c
+ *   ln (K x)_k = lse(A_k, B_k). */
+int or_kv_fs1_log(int64_t n, const double *lx, double h, double eps, double *ly) {
+    if (n < 1 || !(h > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    double c = h / eps;
+    double *b = (double *)malloc((size_t)n * sizeof(double));
+    if (!b) return OR_ERR_NO_MEMORY;
+    b[n - 1] = -INFINITY;
+    for (int64_t k = n - 2; k >= 0; --k) {
+        double t = lse2(b[k + 1], lx[k + 1]);
+        b[k] = (t == -INFINITY) ? -INFINITY : t - c;
+    }
+    double a = lx[0];
+    ly[0] = lse2(a, b[0]);
+    for (int64_t k = 1; k < n; ++k) {
+        a = lse2(a == -INFINITY ? -INFINITY : a - c, lx[k]);
+        ly[k] = lse2(a, b[k]);
+    }
+    free(b);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Marginal error and transport cost written as the paper writes them        */
+/* (double sums in Algorithm 1: the stopping test and the returned value).   */
+/* ------------------------------------------------------------------------- */
+
+/* err = sum_i | psi_i * sum_j phi_j e^{-|i-j|c} - nu_i |  (nu-side L1 error) */
+double or_marginal_err_dense(int64_t n, const double *phi, const double *psi,
+                             const double *nu, double h, double eps) {
+    double c = h / eps;
+    double *kd = kernel_table(n, c);
+    if (!kd) return NAN;
+    double err = 0.0;
+#pragma omp parallel for reduction(+ : err) schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t d = i > j ? i - j : j - i;
+            s += phi[j] * kd[d];
+        }
+        err += fabs(psi[i] * s - nu[i]);
+    }
+    free(kd);
+    return err;
+}
+
+/* W = sum_{i,j} phi_i psi_j e^{-|i-j|c} |i-j| h  (the value Algorithm 1 returns) */
+double or_cost_dense(int64_t n, const double *phi, const double *psi, double h,
+                     double eps) {
+    double c = h / eps;
+    double *kd = kernel_table(n, c);
+    if (!kd) return NAN;
+    double w = 0.0;
+#pragma omp parallel for reduction(+ : w) schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t d = i > j ? i - j : j - i;
+            s += psi[j] * kd[d] * (double)d * h;
+        }
+        w += phi[i] * s;
+    }
+    free(kd);
+    return w;
+}
+
+/* Log-domain versions of the two sums (phi = e^F, psi = e^G). */
+double or_marginal_err_log_dense(int64_t n, const double *F, const double *G,
+                                 const double *nu, double h, double eps) {
+    double c = h / eps;
+    double err = 0.0;
+#pragma omp parallel for reduction(+ : err) schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        if (G[i] != -INFINITY) {
+            for (int64_t j = 0; j < n; ++j) {
+                double d = (double)(i > j ? i - j : j - i);
+                if (F[j] != -INFINITY) s += exp(F[j] + G[i] - d * c);
+            }
+        }
+        err += fabs(s - nu[i]);
+    }
+    return err;
+}
+
+double or_cost_log_dense(int64_t n, const double *F, const double *G, double h,
+                         double eps) {
+    double c = h / eps;
+    double w = 0.0;
+#pragma omp parallel for reduction(+ : w) schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (F[i] == -INFINITY) continue;
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (G[j] == -INFINITY) continue;
+            double d = (double)(i > j ? i - j : j - i);
+            s += exp(F[i] + G[j] - d * c) * d * h;
+        }
+        w += s;
+    }
+    return w;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pointwise division of the Sinkhorn update (psi = nu / (K^T phi),          */
+/* phi = mu / (K psi)).  Reading: a zero marginal entry gives a zero scaling */
+/* whatever the denominator; a positive entry over a zero or non-finite      */
+/* denominator is the failure the paper calls abnormal termination.          */
+/* ------------------------------------------------------------------------- */
+static int divide_update(int64_t n, const double *marg, const double *den,
+                         double *out) {
+    int bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (marg[i] == 0.0) { out[i] = 0.0; continue; }
+        double v = marg[i] / den[i];
+        if (!isfinite(v)) bad = 1;
+        out[i] = v;
+    }
+    return bad;
+}
+
+static int divide_update_log(int64_t n, const double *lmarg, const double *lden,
+                             double *out) {
+    int bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (lmarg[i] == -INFINITY) { out[i] = -INFINITY; continue; }
+        double v = lmarg[i] - lden[i];
+        if (!isfinite(v)) bad = 1;
+        out[i] = v;
+    }
+    return bad;
+}
+
+/* res layout for every solver: [0] = W (the returned transport cost),
+ * [1] = final marginal error, [2] = completed iterations, [3] = status,
+ * [4] = 1 if the stopping test was met (err <= tol) else 0. */
+static void pack_result(double *res, double w, double err, int64_t it, int st,
+                        int conv) {
+    res[0] = w;
+    res[1] = err;
+    res[2] = (double)it;
+    res[3] = (double)st;
+    res[4] = (double)conv;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense Sinkhorn, linear domain (Sec. 2 update; Algorithm 1's loop, stopping */
+/* rule and return value, with K applied as a dense matrix).                  */
+/* Loop: while it < itr_max and err(phi, psi) > tol:                          */
+/*         psi <- nu / (K^T phi); phi <- mu / (K psi); it++                   */
+/* phi, psi: outputs (length n); initial value 1/n each (Algorithm 1).        */
+/* ------------------------------------------------------------------------- */
+int or_sinkhorn_dense(int64_t n, const double *mu, const double *nu, double h,
+                      double eps, double tol, int64_t itr_max, double *phi,
+                      double *psi, double *res) {
+    if (n < 1 || !(h > 0) || !(eps > 0) || itr_max < 0) return OR_ERR_INVALID_ARG;
+    double *den = (double *)malloc((size_t)n * sizeof(double));
+    if (!den) return OR_ERR_NO_MEMORY;
+    for (int64_t i = 0; i < n; ++i) phi[i] = psi[i] = 1.0 / (double)n;
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = or_marginal_err_dense(n, phi, psi, nu, h, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        or_kv_dense(n, phi, h, eps, den);           /* K^T phi (K symmetric) */
+        if (divide_update(n, nu, den, psi)) { st = OR_ERR_NONFINITE; break; }
+        or_kv_dense(n, psi, h, eps, den);           /* K psi */
+        if (divide_update(n, mu, den, phi)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = or_marginal_err_dense(n, phi, psi, nu, h, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = (st == OR_OK) ? or_cost_dense(n, phi, psi, h, eps) : NAN;
+    pack_result(res, w, err, it, st, conv);
+    free(den);
+    return st;
+}
+
+/* Dense Sinkhorn on logarithms: G = ln nu - LSE_i(F_i - |i-j| c), then
+ * F = ln mu - LSE_j(G_j - |i-j| c); start F = G = -ln n.  In exact arithmetic
+ * the iterates are the logarithms of those of or_sinkhorn_dense. */
+int or_sinkhorn_log_dense(int64_t n, const double *mu, const double *nu, double h,
+                          double eps, double tol, int64_t itr_max, double *F,
+                          double *G, double *res) {
+    if (n < 1 || !(h > 0) || !(eps > 0) || itr_max < 0) return OR_ERR_INVALID_ARG;
+    double *lmu = (double *)malloc((size_t)n * sizeof(double));
+    double *lnu = (double *)malloc((size_t)n * sizeof(double));
+    double *lden = (double *)malloc((size_t)n * sizeof(double));
+    if (!lmu || !lnu || !lden) { free(lmu); free(lnu); free(lden); return OR_ERR_NO_MEMORY; }
+    for (int64_t i = 0; i < n; ++i) {
+        lmu[i] = mu[i] > 0 ? log(mu[i]) : -INFINITY;
+        lnu[i] = nu[i] > 0 ? log(nu[i]) : -INFINITY;
+        F[i] = G[i] = -log((double)n);
+    }
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = or_marginal_err_log_dense(n, F, G, nu, h, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        or_kv_log_dense(n, F, h, eps, lden);
+        if (divide_update_log(n, lnu, lden, G)) { st = OR_ERR_NONFINITE; break; }
+        or_kv_log_dense(n, G, h, eps, lden);
+        if (divide_update_log(n, lmu, lden, F)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = or_marginal_err_log_dense(n, F, G, nu, h, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = (st == OR_OK) ? or_cost_log_dense(n, F, G, h, eps) : NAN;
+    pack_result(res, w, err, it, st, conv);
+    free(lmu); free(lnu); free(lden);
+    return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sequential FS-1 (Algorithm 1): the same loop with every K-product done by  */
+/* the Sec. 3 recursions, so each iteration costs O(n).  The stopping test's  */
+/* inner sum sum_j phi_j lambda^{|i-j|} is the K^T phi of the recursions.     */
+/* The returned double sum is evaluated by two further recursions that follow */
+/* from the same splitting of |i-j| into j < i and j > i:                     */
+/*   L_0 = 0,       L_{i+1} = lambda (L_i + p_i)         (sum over j <= i)    */
+/*   U_{n-1} = 0,   U_{i-1} = lambda (U_i + q_i + psi_i) (sum over j >= i)    */
+/* with p, q the lower/strict-upper recursions applied to psi; then           */
+/*   W = h sum_i phi_i (L_i + U_i).                                           */
+/* ------------------------------------------------------------------------- */
+double or_cost_fs1(int64_t n, const double *phi, const double *psi, double h,
+                   double eps) {
+    double lam = exp(-h / eps);
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    double *U = (double *)malloc((size_t)n * sizeof(double));
+    if (!q || !U) { free(q); free(U); return NAN; }
+    q[n - 1] = 0.0;
+    for (int64_t k = n - 2; k >= 0; --k) q[k] = lam * (q[k + 1] + psi[k + 1]);
+    U[n - 1] = 0.0;
+    for (int64_t i = n - 1; i >= 1; --i) U[i - 1] = lam * (U[i] + q[i] + psi[i]);
+    double w = 0.0, p = 0.0, L = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        p = (i == 0) ? psi[0] : lam * p + psi[i];
+        w += phi[i] * (L + U[i]);
+        L = lam * (L + p);
+    }
+    free(q); free(U);
+    return w * h;
+}
+
+double or_marginal_err_fs1(int64_t n, const double *phi, const double *psi,
+                           const double *nu, double h, double eps) {
+    double *ktphi = (double *)malloc((size_t)n * sizeof(double));
+    if (!ktphi) return NAN;
+    or_kv_fs1(n, phi, h, eps, ktphi);
+    double err = 0.0;
+    for (int64_t i = 0; i < n; ++i) err += fabs(psi[i] * ktphi[i] - nu[i]);
+    free(ktphi);
+    return err;
+}
+
+int or_fs1(int64_t n, const double *mu, const double *nu, double h, double eps,
+           double tol, int64_t itr_max, double *phi, double *psi, double *res) {
+    if (n < 1 || !(h > 0) || !(eps > 0) || itr_max < 0) return OR_ERR_INVALID_ARG;
+    double *den = (double *)malloc((size_t)n * sizeof(double));
+    if (!den) return OR_ERR_NO_MEMORY;
+    for (int64_t i = 0; i < n; ++i) phi[i] = psi[i] = 1.0 / (double)n;
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = or_marginal_err_fs1(n, phi, psi, nu, h, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        or_kv_fs1(n, phi, h, eps, den);               /* r + s */
+        if (divide_update(n, nu, den, psi)) { st = OR_ERR_NONFINITE; break; }
+        or_kv_fs1(n, psi, h, eps, den);               /* p + q */
+        if (divide_update(n, mu, den, phi)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = or_marginal_err_fs1(n, phi, psi, nu, h, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = (st == OR_OK) ? or_cost_fs1(n, phi, psi, h, eps) : NAN;
+    pack_result(res, w, err, it, st, conv);
+    free(den);
+    return st;
+}
+
+/* Log-domain sequential FS-1: the recursions of or_kv_fs1_log inside the
+ * same loop; the cost recursions run on logarithms as well:
+ *   lnL_0 = -inf,  lnL_{i+1} = lse(lnL_i, A_i) - c
+ *   lnU_{n-1} = -inf, lnU_{i-1} = lse(lnU_i, B_i, G_i) - c
+ *   W = h sum_i exp(F_i + lse(lnL_i, lnU_i)). */
+double or_cost_fs1_log(int64_t n, const double *F, const double *G, double h,
+                       double eps) {
+    double c = h / eps;
+    double *B = (double *)malloc((size_t)n * sizeof(double));
+    double *lU = (double *)malloc((size_t)n * sizeof(double));
+    if (!B || !lU) { free(B); free(lU); return NAN; }
+    B[n - 1] = -INFINITY;
+    for (int64_t k = n - 2; k >= 0; --k) {
+        double t = lse2(B[k + 1], G[k + 1]);
+        B[k] = (t == -INFINITY) ? -INFINITY : t - c;
+    }
+    lU[n - 1] = -INFINITY;
+    for (int64_t i = n - 1; i >= 1; --i) {
+        double t = lse2(lse2(lU[i], B[i]), G[i]);
+        lU[i - 1] = (t == -INFINITY) ? -INFINITY : t - c;
+    }
+    double w = 0.0, A = -INFINITY, lL = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        A = (i == 0) ? G[0] : lse2(A == -INFINITY ? -INFINITY : A - c, G[i]);
+        double t = lse2(lL, lU[i]);
+        if (F[i] != -INFINITY && t != -INFINITY) w += exp(F[i] + t);
+        double u = lse2(lL, A);
+        lL = (u == -INFINITY) ? -INFINITY : u - c;
+    }
+    free(B); free(lU);
+    return w * h;
+}
+
+double or_marginal_err_fs1_log(int64_t n, const double *F, const double *G,
+                               const double *nu, double h, double eps) {
+    double *lk = (double *)malloc((size_t)n * sizeof(double));
+    if (!lk) return NAN;
+    or_kv_fs1_log(n, F, h, eps, lk);
+    double err = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = (G[i] == -INFINITY || lk[i] == -INFINITY) ? 0.0 : exp(G[i] + lk[i]);
+        err += fabs(v - nu[i]);
+    }
+    free(lk);
+    return err;
+}
+
+int or_fs1_log(int64_t n, const double *mu, const double *nu, double h, double eps,
+               double tol, int64_t itr_max, double *F, double *G, double *res) {
+    if (n < 1 || !(h > 0) || !(eps > 0) || itr_max < 0) return OR_ERR_INVALID_ARG;
+    double *lmu = (double *)malloc((size_t)n * sizeof(double));
+    double *lnu = (double *)malloc((size_t)n * sizeof(double));
+    double *lden = (double *)malloc((size_t)n * sizeof(double));
+    if (!lmu || !lnu || !lden) { free(lmu); free(lnu); free(lden); return OR_ERR_NO_MEMORY; }
+    for (int64_t i = 0; i < n; ++i) {
+        lmu[i] = mu[i] > 0 ? log(mu[i]) : -INFINITY;
+        lnu[i] = nu[i] > 0 ? log(nu[i]) : -INFINITY;
+        F[i] = G[i] = -log((double)n);
+    }
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = or_marginal_err_fs1_log(n, F, G, nu, h, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        or_kv_fs1_log(n, F, h, eps, lden);
+        if (divide_update_log(n, lnu, lden, G)) { st = OR_ERR_NONFINITE; break; }
+        or_kv_fs1_log(n, G, h, eps, lden);
+        if (divide_update_log(n, lmu, lden, F)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = or_marginal_err_fs1_log(n, F, G, nu, h, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = (st == OR_OK) ? or_cost_fs1_log(n, F, G, h, eps) : NAN;
+    pack_result(res, w, err, it, st, conv);
+    free(lmu); free(lnu); free(lden);
+    return st;
+}
+
+/* Number of OpenMP threads the dense routines use (1 without OpenMP). */
+int or_num_threads(void) {
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

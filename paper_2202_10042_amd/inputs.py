@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs for FS-1 solves.
+
+This module only draws histograms and request streams; it contains none of the
+method's arithmetic, so both the GPU path and the CPU oracle can be fed from it.
+Every generator is deterministic in its seed (numpy PCG64 ``default_rng``).
+
+Recipes
+-------
+* Uniform grid on [0, 1] with n cells, spacing h = 1/n, cell centres
+  x_i = (i + 1/2) h.
+* Gaussian mixture histogram: K components with means ~ U[0.2, 0.8], standard
+  deviations ~ U[0.03, 0.1], weights ~ U[0.3, 0.7] (then normalised); the density
+  is evaluated at the cell centres, a floor of 1e-6 is added to the density values,
+  and the result is normalised to total mass 1.
+* Pair (mu, nu): mu from seed s, nu from seed s + 1.
+* Shifted-noisy pair (large single-pair precision study): mu is a K-component
+  mixture; nu_i is proportional to p_mu(x_i - shift) * exp(sigma * Z_i),
+  Z ~ N(0, 1), plus the floor, normalised.
+* The paper's Sec. 5.1 workload ("1-D random distributions"): grid
+  x_i = (i-1) dx - 3, dx = 6/(N-1) on [-3, 3]; u_i, v_j ~ U[0, 1]; each divided
+  by its sum (L1 norm).
+* The paper's Sec. 5.2 workload (Ricker wavelet and its translate), squared and
+  normalised as in the paper's eq. (ricker), on a stated time window.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+FLOOR = 1e-6
+
+
+def grid(n: int) -> tuple[np.ndarray, float]:
+    """Cell centres of the uniform grid on [0, 1] and its spacing h = 1/n."""
+    h = 1.0 / n
+    return (np.arange(n, dtype=np.float64) + 0.5) * h, h
+
+
+def _mixture_params(rng: np.random.Generator, k: int):
+    means = rng.uniform(0.2, 0.8, size=k)
+    sds = rng.uniform(0.03, 0.1, size=k)
+    w = rng.uniform(0.3, 0.7, size=k)
+    return means, sds, w / w.sum()
+
+
+def _mixture_density(x: np.ndarray, means, sds, w) -> np.ndarray:
+    p = np.zeros_like(x)
+    for m, s, wk in zip(means, sds, w):
+        p += wk * np.exp(-0.5 * ((x - m) / s) ** 2) / (s * math.sqrt(2.0 * math.pi))
+    return p
+
+
+def mixture_hist(n: int, k: int, seed: int) -> np.ndarray:
+    """One K-component Gaussian-mixture histogram on the unit grid (sum 1)."""
+    rng = np.random.default_rng(seed)
+    x, _ = grid(n)
+    p = _mixture_density(x, *_mixture_params(rng, k)) + FLOOR
+    return p / p.sum()
+
+
+def mixture_pair(n: int, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """(mu, nu) with mu from ``seed`` and nu from ``seed + 1``."""
+    return mixture_hist(n, k, seed), mixture_hist(n, k, seed + 1)
+
+
+def random_k(seed: int, lo: int = 3, hi: int = 5) -> int:
+    """Number of mixture components drawn uniformly from {lo, ..., hi}."""
+    return int(np.random.default_rng(seed + 7919).integers(lo, hi + 1))
+
+
+def shifted_noisy_pair(n: int, k: int, seed: int, shift: float = 0.05,
+                       sigma: float = 0.05) -> tuple[np.ndarray, np.ndarray]:
+    """mu: K-component mixture; nu ~ mu(x - shift) * lognormal(0, sigma) noise."""
+    rng = np.random.default_rng(seed)
+    x, _ = grid(n)
+    params = _mixture_params(rng, k)
+    pm = _mixture_density(x, *params) + FLOOR
+    mu = pm / pm.sum()
+    z = np.random.default_rng(seed + 1).standard_normal(n)
+    pn = _mixture_density(x - shift, *params) * np.exp(sigma * z) + FLOOR
+    nu = pn / pn.sum()
+    return mu, nu
+
+
+def paper_uniform_pair(n: int, seed: int) -> tuple[np.ndarray, np.ndarray, float]:
+    """Sec. 5.1 workload: u, v ~ U[0,1] on the grid of [-3, 3], L1-normalised.
+
+    Returns (u, v, dx) with dx = 6 / (N - 1)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, size=n)
+    v = rng.uniform(0.0, 1.0, size=n)
+    return u / u.sum(), v / v.sum(), 6.0 / (n - 1)
+
+
+def ricker_pair(n: int, shift: float = -1.2032, delta: float = 1e-3,
+                t0: float = -4.0, t1: float = 4.0, f0: float = 1.0, amp: float = 1.0):
+    """Sec. 5.2 workload: R(t) and R(t - s), squared and normalised by eq. (ricker).
+
+    The paper does not state the time window nor L; here the window is [t0, t1]
+    sampled at n points (dt = (t1 - t0)/(n - 1)), ||f^2|| is the sum of f^2, and
+    L = n so that (f^2/||f^2|| + delta) / (1 + L delta) sums to one.
+    Returns (u, v, dt)."""
+    t = np.linspace(t0, t1, n)
+    dt = (t1 - t0) / (n - 1)
+
+    def ricker(tt):
+        a = (math.pi * f0 * tt) ** 2
+        return amp * (1.0 - 2.0 * a) * np.exp(-a)
+
+    f2 = ricker(t) ** 2
+    g2 = ricker(t - shift) ** 2
+    L = float(n)
+    u = (f2 / f2.sum() + delta) / (1.0 + L * delta)
+    v = (g2 / g2.sum() + delta) / (1.0 + L * delta)
+    return u, v, dt
+
+
+def dirac_pair(n: int, a: int, b: int) -> tuple[np.ndarray, np.ndarray]:
+    mu = np.zeros(n)
+    nu = np.zeros(n)
+    mu[a] = 1.0
+    nu[b] = 1.0
+    return mu, nu
+
+
+# --------------------------------------------------------------------------
+# batched and served workloads
+# --------------------------------------------------------------------------
+
+@dataclass
+class BatchSpec:
+    sizes: np.ndarray     # int64 [B]
+    eps: np.ndarray       # float64 [B]
+    seeds: np.ndarray     # int64 [B]  (mu from seed, nu from seed + 1)
+    ks: np.ndarray        # int64 [B]  mixture components
+
+
+def batch_spec(b: int, n_lo: int, n_hi: int, eps_choices, seed: int,
+               k_lo: int = 3, k_hi: int = 5) -> BatchSpec:
+    """B instances with N log-uniform in [n_lo, n_hi], eps uniform over the
+    choices, instance i seeded with seed + 2 i."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=b))).astype(np.int64)
+    sizes = np.clip(sizes, n_lo, n_hi)
+    eps = np.asarray(eps_choices, dtype=np.float64)[rng.integers(0, len(eps_choices), size=b)]
+    ks = rng.integers(k_lo, k_hi + 1, size=b).astype(np.int64)
+    seeds = seed + 1000 + 2 * np.arange(b, dtype=np.int64)
+    return BatchSpec(sizes, eps, seeds, ks)
+
+
+def batch_hists(spec: BatchSpec):
+    """Packed (mu, nu, offsets) for a BatchSpec: instance b lives in
+    [offsets[b], offsets[b+1])."""
+    offs = np.zeros(spec.sizes.size + 1, dtype=np.int64)
+    np.cumsum(spec.sizes, out=offs[1:])
+    mu = np.empty(int(offs[-1]))
+    nu = np.empty(int(offs[-1]))
+    for i, (n, s, k) in enumerate(zip(spec.sizes, spec.seeds, spec.ks)):
+        a, b = mixture_pair(int(n), int(k), int(s))
+        mu[offs[i]:offs[i + 1]] = a
+        nu[offs[i]:offs[i + 1]] = b
+    return mu, nu, offs
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate on [0, duration)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    chunk = max(16, int(rate * duration * 1.2) + 16)
+    while t < duration:
+        gaps = rng.exponential(1.0 / rate, size=chunk)
+        ts = t + np.cumsum(gaps)
+        out.append(ts[ts < duration])
+        t = float(ts[-1])
+    return np.concatenate(out) if out else np.zeros(0)
