@@ -1,0 +1,173 @@
+/*
+ * fs1.h -- C ABI of libfs1: FS-1 Sinkhorn iterations for the Wasserstein-1
+ * metric on a uniform 1-D grid, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liao, Chen, Wang, Bai, Jin, Wu, "Fast Sinkhorn I: an O(N) algorithm
+ * for the Wasserstein-1 metric" (arXiv 2202.10042).  On a uniform grid of
+ * spacing h the Gibbs kernel is K_ij = lambda^{|i-j|}, lambda = exp(-h/eps)
+ * (Sec. 2, scaling form of the entropic problem; Sec. 3, eq. (NBS_summation)),
+ * so every K x is the sum of a forward and a backward first-order recursion
+ * (Sec. 3, eq. (recursion)).  libfs1 evaluates those recursions as parallel
+ * scans on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: FS1_OK (0) or a negative fs1_status.
+ *    No C++ exception crosses this boundary.  After a non-zero status,
+ *    fs1_last_error() returns a message for the calling thread.
+ *  - Array arguments named as device arrays are device pointers (HIP global
+ *    memory) owned by the caller; libfs1 never frees or retains them past the
+ *    call.  Host arrays are named as such.
+ *  - Device arrays must be 16-byte aligned (any fresh HIP or PyTorch
+ *    allocation is); otherwise FS1_ERR_INVALID_ARG.
+ *  - Work is ordered on the stream given to fs1_ctx_create (0 = the null
+ *    stream).  kv_apply calls are asynchronous; solve calls block until their
+ *    result is written to the host struct.
+ *  - Argument validation happens before any launch; a failed validation
+ *    launches nothing and writes nothing.
+ *  - A context is used by one host thread at a time.  Different contexts may
+ *    be used concurrently on different streams.
+ *  - Indices run 0..n-1 (the paper's 1..N).
+ */
+#ifndef FS1_H
+#define FS1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FS1_OK = 0,
+    FS1_ERR_INVALID_ARG = -1, /* bad size, pointer, alignment, h, eps, tol or marginal */
+    FS1_ERR_NONFINITE = -2,   /* a scaling became non-finite ("abnormal termination",
+                                 Sec. 5.2 and 5.4 of the paper) */
+    FS1_ERR_HIP = -3,         /* a HIP runtime call failed */
+    FS1_ERR_NO_MEMORY = -4,   /* device or host allocation failed */
+    FS1_ERR_INTERNAL = -5     /* a device-side consistency check failed */
+} fs1_status;
+
+typedef enum {
+    FS1_F64 = 0, /* binary64 storage and scans */
+    FS1_F32 = 1  /* binary32 storage and scans; marginal error, cost and the
+                    accumulations that feed them stay binary64 */
+} fs1_dtype;
+
+typedef enum {
+    FS1_PLAIN = 0, /* Algorithm 1 as printed: scalings phi, psi in plain floating
+                      point; overflow/underflow ends the solve with
+                      FS1_ERR_NONFINITE */
+    FS1_LOG = 1    /* log-domain stabilised FS-1: phi and psi are kept as
+                      e^{alpha} * phi~ with the power-of-two part absorbed into a
+                      per-run exponent at every half-iteration (the absorption of
+                      the Sec. 2 and Sec. 3 remarks, threshold tau -> 0); results
+                      equal the plain iteration in exact arithmetic */
+} fs1_domain;
+
+typedef struct fs1_ctx fs1_ctx;
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL =
+ * null stream) on the device current at the time of the call.  The context
+ * owns its workspace (grown on demand, freed by fs1_ctx_destroy). */
+int fs1_ctx_create(void *stream, fs1_ctx **out);
+int fs1_ctx_destroy(fs1_ctx *ctx);
+/* Rebind the context to another stream (e.g. the caller's current stream). */
+int fs1_ctx_set_stream(fs1_ctx *ctx, void *stream);
+
+/* Thread-local message describing the last failure on this host thread. */
+const char *fs1_last_error(void);
+/* Library version string. */
+const char *fs1_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel application (Sec. 3: K psi split into the lower part p and the     */
+/* strict upper part q, each a first-order recursion; eq. (recursion)).      */
+/* ------------------------------------------------------------------------ */
+
+/* y_i = sum_j exp(-|i-j| h/eps) x_j,  i = 0..n-1.
+ * x, y: device arrays of n elements of dtype dt (double for FS1_F64, float for
+ * FS1_F32); any finite sign; must not overlap.  n >= 1; h > 0, eps > 0 finite.
+ * Non-finite entries of x propagate as IEEE arithmetic would in the dense
+ * product.  Asynchronous on the context stream. */
+int fs1_kv_apply(fs1_ctx *ctx, const void *x, void *y, int64_t n, double h, double eps,
+                 int dt);
+
+/* ly_i = ln sum_j exp(lx_j - |i-j| h/eps): the recursions of eq. (recursion)
+ * on logarithms (log-sum-exp semiring), as used by the log-domain stabilised
+ * method.  lx, ly: device arrays of n elements of dtype dt; must not overlap.
+ * lx may hold -inf (a zero of x); all -inf gives all -inf, never NaN.  +inf or
+ * NaN in lx propagate to every output.  |lx_j| must stay below 1e8.
+ * Asynchronous on the context stream. */
+int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h,
+                     double eps, int dt);
+
+/* ------------------------------------------------------------------------ */
+/* Solve (Algorithm 1, FS-1): psi = nu / (K^T phi), phi = mu / (K psi)       */
+/* (Sec. 2, Sinkhorn update, psi first), starting from phi = psi = 1/n,      */
+/* while iterations < itr_max and the nu-side marginal error                 */
+/*   err = sum_i | psi_i (K^T phi)_i - nu_i |                                */
+/* exceeds tol; returns the transport cost                                   */
+/*   w1 = sum_{i,j} phi_i psi_j lambda^{|i-j|} |i-j| h.                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double h;             /* grid spacing; <= 0 selects 1/n                         */
+    int32_t itr_max;      /* iteration cap; < 0 selects 10000                       */
+    int32_t dtype;        /* fs1_dtype of storage and scans                          */
+    int32_t domain;       /* fs1_domain                                              */
+    int32_t check_every;  /* evaluate the stopping test every k iterations (k >= 1;
+                             1 = Algorithm 1; k > 1 may run up to k-1 iterations
+                             past the first point where err <= tol)               */
+    int32_t sync_every;   /* host polls the device stop flag every s iterations
+                             (performance only; results do not depend on it)      */
+    int32_t flags;        /* bit 0: return potentials (see potentials_out)          */
+    double *potentials_out; /* device, 2n doubles: F = ln phi (n), then G = ln psi
+                             (n), written when flags bit 0 is set; -inf where the
+                             scaling is zero                                        */
+    double *err_history;  /* device, itr_max + 1 doubles or NULL: err at every
+                             checked iteration l (index l), NaN elsewhere         */
+} fs1_opts;
+
+/* Fill *o with the defaults (h = 1/n, itr_max 10000, FS1_F64, FS1_PLAIN,
+ * check_every 1, sync_every 16, no potentials, no history). */
+int fs1_opts_default(fs1_opts *o);
+
+typedef struct {
+    double w1;            /* transport cost <C, P> at the final (phi, psi)          */
+    double marginal_err;  /* nu-side L1 marginal error at the final (phi, psi),
+                             binary64                                              */
+    double mu_err;        /* mu-side L1 marginal error at the final (phi, psi)       */
+    int32_t iterations;   /* completed (psi, phi) pairs                             */
+    int32_t converged;    /* 1 if marginal_err <= tol at the returned state         */
+    int32_t status;       /* same value as the return code                           */
+    int32_t reserved;
+} fs1_result;
+
+/* mu, nu: device binary64 arrays of n entries, finite, >= 0, not all zero,
+ * |sum mu - sum nu| <= 1e-10 * sum mu (else FS1_ERR_INVALID_ARG; nothing is
+ * renormalised).  eps > 0, tol >= 0.  Blocks until *out (host memory) is
+ * written.  Reaching itr_max is not an error (status FS1_OK, converged 0), as in
+ * Algorithm 1.  A non-finite or zero-denominator scaling at a positive marginal
+ * returns FS1_ERR_NONFINITE with out->iterations = the completed iterations
+ * before the failing one. */
+int fs1_solve(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
+              double tol, const fs1_opts *opts, fs1_result *out);
+
+/* Ragged batch of independent solves.  Instance b occupies
+ * [offsets[b], offsets[b+1]) of mu_packed / nu_packed (device binary64);
+ * offsets: host int64 array of B+1 nondecreasing entries, offsets[0] = 0, every
+ * instance length >= 1.  eps, tol: host arrays of B entries.  opts->h is
+ * ignored: instance b uses h = 1 / n_b.  out: host array of B results.  Every
+ * instance runs the same arithmetic it would run alone (its result does not
+ * depend on the rest of the batch).  Blocks until every result is written.
+ * Returns FS1_OK if the call ran; per-instance failures are in out[b].status. */
+int fs1_solve_batched(fs1_ctx *ctx, const double *mu_packed, const double *nu_packed,
+                      const int64_t *offsets, int32_t B, const double *eps,
+                      const double *tol, const fs1_opts *opts, fs1_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FS1_H */

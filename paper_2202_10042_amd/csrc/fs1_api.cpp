@@ -1,0 +1,379 @@
+// fs1_api.cpp -- the C ABI of libfs1 (include/fs1.h): argument validation,
+// workspace, and the host loop of Algorithm 1 (FS-1).
+//
+// The solve loop launches, for every iteration l, the psi-half (K^T phi by the
+// scans, psi = nu / K^T phi, the stopping-test error of (phi^l, psi^l)) and the
+// phi-half (which closes the stopping test on the device and, unless it is met,
+// computes phi = mu / K psi).  Once the test is met every later launch returns
+// at once, so the host only has to look at the device flag every `sync_every`
+// iterations; the iteration at which the solve stops does not depend on that
+// interval.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fs1.h"
+#include "fs1_internal.h"
+
+using namespace fs1;
+
+struct fs1_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;      // device workspace
+  size_t ws_size = 0;
+  Ctrl* hctrl = nullptr;   // pinned host mirror of the control block
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_err(FS1_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Grow the context workspace to at least `bytes` (stream-synchronised when the
+// old buffer is released, because earlier asynchronous calls may still use it).
+int ensure_ws(fs1_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_size) return FS1_OK;
+  if (c->ws) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_size = 0;
+  }
+  const size_t sz = round_up(bytes, size_t(1) << 20);
+  hipError_t e = hipMalloc(&c->ws, sz);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    return set_err(FS1_ERR_NO_MEMORY, "hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+  }
+  c->ws_size = sz;
+  return FS1_OK;
+}
+
+// Bump allocator over a workspace.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(char* b) : base(b) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off = round_up(off + bytes, 256);
+    return p;
+  }
+};
+
+int check_h_eps(int64_t n, double h, double eps) {
+  if (n < 1) return set_err(FS1_ERR_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)n);
+  if (!(h > 0.0) || !std::isfinite(h)) return set_err(FS1_ERR_INVALID_ARG, "h must be finite and > 0");
+  if (!(eps > 0.0) || !std::isfinite(eps))
+    return set_err(FS1_ERR_INVALID_ARG, "eps must be finite and > 0");
+  // exponents of lambda^D over the whole grid must fit the extended-range format
+  if (double(n) * (h / eps) > 1.0e8)
+    return set_err(FS1_ERR_INVALID_ARG, "n*h/eps = %g exceeds 1e8", double(n) * (h / eps));
+  return FS1_OK;
+}
+
+int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double eps, int dt,
+              bool log) {
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (!x || !y) return set_err(FS1_ERR_INVALID_ARG, "null array");
+  if (dt != FS1_F64 && dt != FS1_F32) return set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", dt);
+  if (!aligned16(x) || !aligned16(y))
+    return set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
+  int st = check_h_eps(n, h, eps);
+  if (st) return st;
+  const size_t es = dt == FS1_F64 ? 8 : 4;
+  const char* xb = static_cast<const char*>(x);
+  const char* yb = static_cast<const char*>(y);
+  if (xb < yb + n * es && yb < xb + n * es)
+    return set_err(FS1_ERR_INVALID_ARG, "x and y must not overlap");
+  const int R = pick_run_length(dt, log, h / eps);
+  const int64_t C = int64_t(kBlock) * R;
+  const int64_t nchunks = (n + C - 1) / C;
+  if (nchunks > int64_t(INT32_MAX)) return set_err(FS1_ERR_INVALID_ARG, "n too large");
+  Carve cv(nullptr);
+  cv.take(nchunks * sizeof(ChunkAgg));
+  cv.take(nchunks * sizeof(ChunkAgg));
+  st = ensure_ws(ctx, cv.off);
+  if (st) return st;
+  Carve w(ctx->ws);
+  ChunkAgg* agg = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+  ChunkAgg* carry = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+  const ScanConsts k = make_scan_consts(h, eps, R);
+  const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
+  hipError_t e = log ? launch_kv_log(dt, x, y, n, k, kc, agg, carry, ctx->stream)
+                     : launch_kv_plain(dt, x, y, n, k, kc, agg, carry, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, log ? "fs1_kv_apply_log launch" : "fs1_kv_apply launch");
+  return FS1_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* fs1_last_error(void) { return g_err.c_str(); }
+
+const char* fs1_version(void) { return "fs1 0.1 (gfx950)"; }
+
+int fs1_ctx_create(void* stream, fs1_ctx** out) {
+  if (!out) return set_err(FS1_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  fs1_ctx* c = new (std::nothrow) fs1_ctx();
+  if (!c) return set_err(FS1_ERR_NO_MEMORY, "context allocation failed");
+  c->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipHostMalloc(reinterpret_cast<void**>(&c->hctrl), sizeof(Ctrl), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  *out = c;
+  return FS1_OK;
+}
+
+int fs1_ctx_destroy(fs1_ctx* c) {
+  if (!c) return FS1_OK;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->hctrl) (void)hipHostFree(c->hctrl);
+  delete c;
+  return FS1_OK;
+}
+
+int fs1_ctx_set_stream(fs1_ctx* c, void* stream) {
+  if (!c) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  c->stream = static_cast<hipStream_t>(stream);
+  return FS1_OK;
+}
+
+int fs1_kv_apply(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double eps, int dt) {
+  return kv_common(ctx, x, y, n, h, eps, dt, false);
+}
+
+int fs1_kv_apply_log(fs1_ctx* ctx, const void* lx, void* ly, int64_t n, double h, double eps,
+                     int dt) {
+  return kv_common(ctx, lx, ly, n, h, eps, dt, true);
+}
+
+int fs1_opts_default(fs1_opts* o) {
+  if (!o) return set_err(FS1_ERR_INVALID_ARG, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->h = 0.0;
+  o->itr_max = 10000;
+  o->dtype = FS1_F64;
+  o->domain = FS1_PLAIN;
+  o->check_every = 1;
+  o->sync_every = 16;
+  o->flags = 0;
+  o->potentials_out = nullptr;
+  o->err_history = nullptr;
+  return FS1_OK;
+}
+
+int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
+              const fs1_opts* opts_in, fs1_result* out) {
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (!out) return set_err(FS1_ERR_INVALID_ARG, "null result pointer");
+  std::memset(out, 0, sizeof(*out));
+  out->w1 = NAN;
+  out->marginal_err = NAN;
+  out->mu_err = NAN;
+  auto finish = [&](int st) {
+    out->status = st;
+    return st;
+  };
+  fs1_opts o;
+  fs1_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (o.itr_max < 0) o.itr_max = 10000;
+  if (o.check_every < 1) o.check_every = 1;
+  if (o.sync_every < 1) o.sync_every = 16;
+  const double h = o.h > 0.0 ? o.h : 1.0 / double(n);
+  if (!mu || !nu) return finish(set_err(FS1_ERR_INVALID_ARG, "null marginal"));
+  if (!aligned16(mu) || !aligned16(nu))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned"));
+  if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype));
+  if (o.domain != FS1_PLAIN && o.domain != FS1_LOG)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "bad domain %d", o.domain));
+  if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
+  if ((o.flags & 1) && !o.potentials_out)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
+  int st = check_h_eps(n, h, eps);
+  if (st) return finish(st);
+
+  const bool absorb = o.domain == FS1_LOG;
+  const int dt = o.dtype;
+  const size_t es = dt == FS1_F64 ? 8 : 4;
+  const int R = pick_run_length(dt, absorb, h / eps);
+  const int64_t C = int64_t(kBlock) * R;
+  const int64_t nchunks = (n + C - 1) / C;
+  if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));
+  const int64_t nruns = nchunks * kBlock;
+
+  // workspace layout
+  SolveBufs b{};
+  auto layout = [&](Carve& w) {
+    b.vF = w.take(n * es);
+    b.vG[0] = w.take(n * es);
+    b.vG[1] = w.take(n * es);
+    b.eF = static_cast<int*>(w.take(nruns * sizeof(int)));
+    b.eG[0] = static_cast<int*>(w.take(nruns * sizeof(int)));
+    b.eG[1] = static_cast<int*>(w.take(nruns * sizeof(int)));
+    b.mu32 = dt == FS1_F32 ? w.take(n * sizeof(float)) : nullptr;
+    b.nu32 = dt == FS1_F32 ? w.take(n * sizeof(float)) : nullptr;
+    b.aggF = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    b.aggG = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    b.carry = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    b.agg2 = w.take(nchunks * 48);
+    b.carry2 = w.take(nchunks * 48);
+    b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
+  };
+  {
+    Carve probe(nullptr);
+    layout(probe);
+    st = ensure_ws(ctx, probe.off);
+    if (st) return finish(st);
+    Carve w(ctx->ws);
+    layout(w);
+  }
+  b.dtype = dt;
+  b.absorb = absorb ? 1 : 0;
+  b.n = n;
+  b.nchunks = nchunks;
+  b.R = R;
+  b.mu = mu;
+  b.nu = nu;
+  b.err_hist = o.err_history;
+  hipStream_t s = ctx->stream;
+  Ctrl* hc = ctx->hctrl;
+
+  // a1: validate the marginals on the device (finite, >= 0, equal mass)
+  HIP_TRY(hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), s));
+  HIP_TRY(launch_setup(b, s));
+  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc->bad_input)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must be finite and >= 0"));
+  if (!(hc->sum_mu > 0.0) || !(hc->sum_nu > 0.0))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must have positive mass"));
+  if (std::fabs(hc->sum_mu - hc->sum_nu) > 1e-10 * hc->sum_mu)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "unequal masses: sum mu = %.17g, sum nu = %.17g",
+                          hc->sum_mu, hc->sum_nu));
+  if (o.err_history)
+    HIP_TRY(hipMemsetAsync(o.err_history, 0xFF, sizeof(double) * (size_t(o.itr_max) + 1), s));
+
+  const ScanConsts k = make_scan_consts(h, eps, R);
+  const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
+  HIP_TRY(launch_init_state(b, k, s));
+
+  // Algorithm 1: while l < itr_max and err(l) > tol
+  int l = 0;
+  bool stopped = false;
+  while (l < o.itr_max && !stopped) {
+    const int l_end = std::min(o.itr_max, l + o.sync_every);
+    for (; l < l_end; ++l) {
+      const int check = (l % o.check_every) == 0;
+      HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s));
+      HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s));
+    }
+    HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stopped = hc->done != 0;
+  }
+  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc->fail) {
+    out->iterations = hc->fail_iter;
+    out->converged = 0;
+    return finish(set_err(FS1_ERR_NONFINITE,
+                          "a scaling became non-finite at iteration %d (abnormal termination)",
+                          hc->fail_iter + 1));
+  }
+  int l_final = o.itr_max;
+  if (hc->done && hc->stop_iter >= 0) l_final = hc->stop_iter;
+  const int gbuf = l_final & 1;
+
+  HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
+  if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
+  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->w1 = hc->w1;
+  out->marginal_err = hc->err_final;
+  out->mu_err = hc->mu_err;
+  out->iterations = l_final;
+  out->converged = !(hc->err_final > tol) ? 1 : 0;
+  if (!std::isfinite(hc->w1) || !std::isfinite(hc->err_final)) {
+    return finish(set_err(FS1_ERR_NONFINITE, "non-finite cost or marginal error"));
+  }
+  return finish(FS1_OK);
+}
+
+int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
+                      const int64_t* offsets, int32_t B, const double* eps, const double* tol,
+                      const fs1_opts* opts, fs1_result* out) {
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (B < 0 || (B > 0 && (!offsets || !eps || !tol || !out || !mu_packed || !nu_packed)))
+    return set_err(FS1_ERR_INVALID_ARG, "bad batch arguments");
+  if (B > 0 && offsets[0] != 0) return set_err(FS1_ERR_INVALID_ARG, "offsets[0] must be 0");
+  for (int32_t i = 0; i < B; ++i)
+    if (offsets[i + 1] - offsets[i] < 1)
+      return set_err(FS1_ERR_INVALID_ARG, "instance %d is empty", i);
+  fs1_opts o;
+  fs1_opts_default(&o);
+  if (opts) o = *opts;
+  o.h = 0.0;
+  o.flags = 0;
+  o.potentials_out = nullptr;
+  o.err_history = nullptr;
+  for (int32_t i = 0; i < B; ++i) {
+    const int64_t a = offsets[i];
+    const int64_t n = offsets[i + 1] - a;
+    if (!aligned16(mu_packed + a) || !aligned16(nu_packed + a)) {
+      // instances must start on 16-byte boundaries for the vector loads
+      return set_err(FS1_ERR_INVALID_ARG, "instance %d is not 16-byte aligned", i);
+    }
+    fs1_solve(ctx, mu_packed + a, nu_packed + a, n, eps[i], tol[i], &o, &out[i]);
+  }
+  return FS1_OK;
+}
+
+}  // extern "C"

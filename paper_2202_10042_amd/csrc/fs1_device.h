@@ -1,0 +1,359 @@
+// fs1_device.h -- device building blocks of the FS-1 scans (gfx950, wave64).
+//
+// Every K x of the method is the sum of two first-order recursions (Sec. 3,
+// eq. (recursion)): the lower part p_k = lambda p_{k-1} + x_k and the strict
+// upper part q_k = lambda (q_{k+1} + x_{k+1}).  A recursion x -> lambda x + b is
+// an affine map; a run of L steps composes to x -> lambda^L x + (local sum),
+// so the recursion is a scan over (lambda^L, local sum) pairs.  The scan here is
+// hierarchical:
+//   thread run of R consecutive elements (plain FMA recursion, as in the paper)
+//   -> wavefront scan of the 64 run aggregates (Hillis-Steele over lanes)
+//   -> block combine of the wavefront aggregates through LDS
+//   -> chunk carries from the single-block carry kernel.
+// Every quantity above the thread run is an extended-range number m * 2^e
+// (mantissa in binary64 or binary32, int exponent).  The decay lambda^D between
+// levels is one such number computed from D * h/eps, so lambda^D never
+// underflows even when D h / eps is in the thousands (the concern of the Sec. 3
+// remark on forming lambda^m); contributions are dropped only when they are
+// below the working precision of the sum they join.
+#pragma once
+
+#include "fs1_internal.h"
+
+namespace fs1 {
+
+static constexpr double kLog2E = 1.4426950408889634074;
+static constexpr double kLn2 = 0.69314718055994530942;
+
+// ---------------------------------------------------------------------------
+// Extended-range numbers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct XF {
+  T m;
+  int e;
+};
+
+__device__ __forceinline__ double ldx(double m, int e) { return ldexp(m, e); }
+__device__ __forceinline__ float ldx(float m, int e) { return ldexpf(m, e); }
+__device__ __forceinline__ double frx(double m, int* e) { return frexp(m, e); }
+__device__ __forceinline__ float frx(float m, int* e) { return frexpf(m, e); }
+
+template <typename T>
+__device__ __forceinline__ XF<T> xzero() {
+  return {T(0), kExpZero};
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> xnorm(T m, int e) {
+  if (m == T(0)) return xzero<T>();
+  if (!isfinite(m)) return {m, 0};
+  int k;
+  T f = frx(m, &k);
+  return {f, e + k};
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> xnorm(XF<T> a) {
+  return xnorm(a.m, a.e);
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> xadd(XF<T> a, XF<T> b) {
+  const int e = max(a.e, b.e);
+  return {ldx(a.m, a.e - e) + ldx(b.m, b.e - e), e};
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> xmul(XF<T> a, XF<T> d) {
+  if (a.m == T(0)) return xzero<T>();
+  return {a.m * d.m, a.e + d.e};
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> from64(const XF64& a) {
+  return {T(a.m), a.e};
+}
+
+__device__ __forceinline__ XF64 to64(XF<double> a) { return {a.m, a.e, 0}; }
+__device__ __forceinline__ XF64 to64(XF<float> a) { return {double(a.m), a.e, 0}; }
+
+// Value of an extended number as a plain T (may overflow / underflow).
+template <typename T>
+__device__ __forceinline__ T xval(XF<T> a) {
+  return ldx(a.m, a.e);
+}
+
+// ---------------------------------------------------------------------------
+// Decays lambda^D
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Dec {
+  T m;
+  int e;
+  double dist;  // D (elements), used by the two-state cost recursion
+};
+
+template <typename T>
+__device__ __forceinline__ Dec<T> dec_of(const Decay& d, double dist) {
+  return {T(d.m), d.e, dist};
+}
+
+// lambda^D on the device from D * c * log2(e): mantissa 2^(k - t) in [1, 2),
+// exponent -k, k = ceil(t).
+__device__ __forceinline__ Decay dev_decay(double t) {
+  const double k = ceil(t);
+  return {exp2(k - t), -int(k), 0};
+}
+
+// ---------------------------------------------------------------------------
+// The lambda-recursion step in the working precision.
+//   lambda a + x:  fma(lambda, a, x), or (a + x) - mu a with mu = 1 - lambda when
+//   lambda > 1/2, so that a binary32 lambda near 1 does not perturb h/eps.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Lam {
+  T lam;
+  T mu;
+  bool use_mu;
+  __device__ __forceinline__ T axpy(T a, T x) const {
+    return use_mu ? fma(-mu, a, a + x) : fma(lam, a, x);
+  }
+  __device__ __forceinline__ T mul(T a) const { return use_mu ? fma(-mu, a, a) : lam * a; }
+};
+
+template <typename T>
+__device__ __forceinline__ Lam<T> lam_of(const ScanConsts& k) {
+  Lam<T> l;
+  l.lam = T(k.lam);
+  l.mu = T(k.mu);
+  l.use_mu = k.use_mu != 0;
+  return l;
+}
+
+// ---------------------------------------------------------------------------
+// One-state scan element (the K x recursions): an extended number.
+// Shifting a state by D elements with zero input multiplies it by lambda^D.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct S1 {
+  XF<T> v;
+  __device__ __forceinline__ static S1 zero() { return {xzero<T>()}; }
+  __device__ __forceinline__ S1 shift(const Dec<T>& d) const { return {xmul(v, XF<T>{d.m, d.e})}; }
+  __device__ __forceinline__ S1 add(const S1& o) const { return {xadd(v, o.v)}; }
+  __device__ __forceinline__ S1 norm() const { return {xnorm(v)}; }
+  __device__ __forceinline__ S1 shfl_up(int d) const {
+    return {{__shfl_up(v.m, d), __shfl_up(v.e, d)}};
+  }
+  __device__ __forceinline__ S1 shfl_down(int d) const {
+    return {{__shfl_down(v.m, d), __shfl_down(v.e, d)}};
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Two-state scan element for the transport cost: (p, D) with
+//   p_i = sum_{j<=i} x_j lambda^{i-j},  D_i = sum_{j<=i} x_j lambda^{i-j} (i-j)
+// (and the mirrored pair backwards).  Shifting by D elements with zero input:
+//   (p, D) -> (lambda^D p, lambda^D (D + D_elems p)).
+// Both components share one exponent.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct S2 {
+  T p;
+  T d;
+  int e;
+  __device__ __forceinline__ static S2 zero() { return {T(0), T(0), kExpZero}; }
+  __device__ __forceinline__ S2 shift(const Dec<T>& dc) const {
+    if (p == T(0) && d == T(0)) return zero();
+    return {p * dc.m, (d + T(dc.dist) * p) * dc.m, e + dc.e};
+  }
+  __device__ __forceinline__ S2 add(const S2& o) const {
+    const int ee = max(e, o.e);
+    return {ldx(p, e - ee) + ldx(o.p, o.e - ee), ldx(d, e - ee) + ldx(o.d, o.e - ee), ee};
+  }
+  __device__ __forceinline__ S2 norm() const {
+    const T big = fmax(fabs(p), fabs(d));
+    if (big == T(0)) return zero();
+    if (!isfinite(big)) return {p, d, 0};
+    int k;
+    frx(big, &k);
+    return {ldx(p, -k), ldx(d, -k), e + k};
+  }
+  __device__ __forceinline__ S2 shfl_up(int dd) const {
+    return {__shfl_up(p, dd), __shfl_up(d, dd), __shfl_up(e, dd)};
+  }
+  __device__ __forceinline__ S2 shfl_down(int dd) const {
+    return {__shfl_down(p, dd), __shfl_down(d, dd), __shfl_down(e, dd)};
+  }
+};
+
+// lambda^(l * unit) from the binary expansion of l (unit = the lane span).
+template <typename T>
+__device__ __forceinline__ Dec<T> lane_pow(int l, const Dec<T>* dec) {
+  Dec<T> r = {T(1), 0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    if ((l >> s) & 1) {
+      r.m *= dec[s].m;
+      r.e += dec[s].e;
+      r.dist += dec[s].dist;
+    }
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Block scan.  Each thread contributes the aggregates of its run:
+//   tf: forward state at the run's last element (run fed with zero),
+//   tb: inclusive backward state at the run's first element.
+// dec[s] = lambda^(run span * 2^s) for s = 0..5 and dec[6] = lambda^(wave span).
+// With block carries bcf (forward state just before the block) and bcb
+// (inclusive backward state just after the block) it returns each thread's
+// carries: cf = forward state just before its run, cb = inclusive backward
+// state just after its run.  It can also return the block aggregates.
+// ---------------------------------------------------------------------------
+template <typename S, int NW>
+struct ScanLds {
+  S f[NW];
+  S b[NW];
+};
+
+template <typename S, int NW, typename T>
+__device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const S& bcf,
+                                           const S& bcb, S* cf, S* cb, S* agg_f, S* agg_b,
+                                           ScanLds<S, NW>& sh) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  S incf = tf.norm();
+  S incb = tb.norm();
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 1 << s;
+    const S of = incf.shfl_up(d);
+    const S ob = incb.shfl_down(d);
+    if (lane >= d) incf = incf.add(of.shift(dec[s]));
+    if (lane + d < kWave) incb = incb.add(ob.shift(dec[s]));
+  }
+  incf = incf.norm();
+  incb = incb.norm();
+  S exf = incf.shfl_up(1);
+  S exb = incb.shfl_down(1);
+  if (lane == 0) exf = S::zero();
+  if (lane == kWave - 1) exb = S::zero();
+  if (lane == kWave - 1) sh.f[w] = incf;
+  if (lane == 0) sh.b[w] = incb;
+  __syncthreads();
+  if (cf) {
+    S accf = bcf;
+    for (int v = 0; v < w; ++v) accf = accf.shift(dec[6]).add(sh.f[v]);
+    S accb = bcb;
+    for (int v = NW - 1; v > w; --v) accb = accb.shift(dec[6]).add(sh.b[v]);
+    *cf = accf.shift(lane_pow(lane, dec)).add(exf).norm();
+    *cb = accb.shift(lane_pow(kWave - 1 - lane, dec)).add(exb).norm();
+  }
+  if (agg_f) {
+    S af = S::zero();
+    S ab = S::zero();
+    for (int v = 0; v < NW; ++v) af = af.shift(dec[6]).add(sh.f[v]);
+    for (int v = NW - 1; v >= 0; --v) ab = ab.shift(dec[6]).add(sh.b[v]);
+    *agg_f = af.norm();
+    *agg_b = ab.norm();
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block sum of a double (fixed reduction order).
+// ---------------------------------------------------------------------------
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_down(v, d);
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) t += sh[i];
+  }
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Run loads and stores (R consecutive elements per thread).  The vector path
+// needs 16-byte aligned arrays (checked by the host); the tail run is guarded.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void load_run(const T* __restrict__ p, int64_t base, int64_t n,
+                                         T (&x)[R], T fill) {
+  constexpr int V = Vec16<T>::n;
+  if constexpr (R % V == 0) {
+    if (base + R <= n) {
+      using VT = typename Vec16<T>::type;
+      const VT* q = reinterpret_cast<const VT*>(p + base);
+#pragma unroll
+      for (int i = 0; i < R / V; ++i) {
+        const VT v = q[i];
+        if constexpr (V == 2) {
+          x[2 * i] = v.x;
+          x[2 * i + 1] = v.y;
+        } else {
+          x[4 * i] = v.x;
+          x[4 * i + 1] = v.y;
+          x[4 * i + 2] = v.z;
+          x[4 * i + 3] = v.w;
+        }
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = (base + j < n) ? p[base + j] : fill;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void store_run(T* __restrict__ p, int64_t base, int64_t n,
+                                          const T (&x)[R]) {
+  constexpr int V = Vec16<T>::n;
+  if constexpr (R % V == 0) {
+    if (base + R <= n) {
+      using VT = typename Vec16<T>::type;
+      VT* q = reinterpret_cast<VT*>(p + base);
+#pragma unroll
+      for (int i = 0; i < R / V; ++i) {
+        VT v;
+        if constexpr (V == 2) {
+          v.x = x[2 * i];
+          v.y = x[2 * i + 1];
+        } else {
+          v.x = x[4 * i];
+          v.y = x[4 * i + 1];
+          v.z = x[4 * i + 2];
+          v.w = x[4 * i + 3];
+        }
+        q[i] = v;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (base + j < n) p[base + j] = x[j];
+}
+
+}  // namespace fs1

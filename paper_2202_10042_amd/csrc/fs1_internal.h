@@ -1,0 +1,140 @@
+// fs1_internal.h -- declarations shared by the HIP kernels (fs1_kernels.hip)
+// and the host driver (fs1_api.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs1 {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlock = 256;      // threads per chunk block (4 waves)
+constexpr int kCarryBlock = 1024;  // threads of the single-block carry scan
+constexpr int kExpZero = -(1 << 30);  // exponent of an exact zero in extended floats
+
+// Extended-range number m * 2^e stored in memory (aggregates, carries).
+struct XF64 {
+  double m;
+  int e;
+  int pad;
+};
+
+// Forward and backward aggregate (or carry) of one chunk.
+//  f: forward state (lower part p of eq. (recursion)) at the chunk's last element
+//     when the chunk is fed with zero from the left -- or, as a carry, the
+//     forward state at the element just before the chunk;
+//  b: inclusive backward state sum_{j>=k} x_j lambda^{j-k} at the chunk's first
+//     element k -- or, as a carry, that state at the element just after the chunk.
+struct ChunkAgg {
+  XF64 f;
+  XF64 b;
+};
+
+// lambda^D for a fixed distance D, as mantissa * 2^exponent (mantissa in [1,2)).
+struct Decay {
+  double m;
+  int e;
+  int pad;
+};
+
+// Per-launch constants of the chunk kernels.
+struct ScanConsts {
+  double lam;        // lambda = exp(-h/eps)
+  double mu;         // 1 - lambda (used when lambda > 1/2: lam*a + x = (a+x) - mu*a)
+  double c_log2e;    // (h/eps) * log2(e): log2 of 1/lambda
+  int use_mu;        // 1 when lambda > 1/2
+  int R;             // elements per thread run
+  Decay lane[7];     // lambda^(R * 2^s), s = 0..6 (s = 6: one wavefront span)
+  Decay chunk;       // lambda^(chunk length)
+};
+
+// Constants of the single-block carry scan over chunk aggregates.
+struct CarryConsts {
+  int64_t nchunks;
+  int64_t group;     // chunks per thread
+  int64_t chunk_len; // elements per chunk
+  Decay chunk;       // lambda^(chunk length)
+  Decay step[7];     // lambda^(group * chunk length * 2^s), s = 0..6
+};
+
+// Device-side control block of one solve.
+struct Ctrl {
+  int done;          // 1 once the stopping test is met or a failure is seen
+  int stop_iter;     // iteration l at which err(l) <= tol was found (-1 if none)
+  int fail;          // a scaling became non-finite
+  int fail_iter;     // first iteration whose update produced a non-finite value
+  int last_check;    // last iteration whose error was evaluated (-1 if none)
+  int pad[3];
+  double last_err;   // err at last_check
+  double w1;         // transport cost (finalisation)
+  double err_final;  // nu-side marginal error (finalisation)
+  double mu_err;     // mu-side marginal error (finalisation)
+  double sum_mu;     // setup: sum of mu
+  double sum_nu;     // setup: sum of nu
+  int bad_input;     // setup: a marginal entry is negative or non-finite
+  int pad2[3];
+};
+
+// ---------------------------------------------------------------------------
+// Host-side helpers (fs1_kernels.hip)
+// ---------------------------------------------------------------------------
+Decay make_decay(double dist_c_log2e);  // lambda^D from D * c * log2(e)
+ScanConsts make_scan_consts(double h, double eps, int R);
+CarryConsts make_carry_consts(double h, double eps, int64_t chunk_len, int64_t nchunks);
+int pick_run_length(int dtype, bool absorb, double c);  // R for a solve / log apply
+
+// ---------------------------------------------------------------------------
+// Launchers (fs1_kernels.hip).  All asynchronous on `s`; return hipError_t.
+// ---------------------------------------------------------------------------
+// Kernel application, plain values (dtype 0 = double, 1 = float).
+hipError_t launch_kv_plain(int dtype, const void* x, void* y, int64_t n, const ScanConsts& k,
+                           const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                           hipStream_t s);
+// Kernel application on logarithms.
+hipError_t launch_kv_log(int dtype, const void* lx, void* ly, int64_t n, const ScanConsts& k,
+                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                         hipStream_t s);
+
+// One solve's device buffers.
+struct SolveBufs {
+  int dtype;          // 0 double, 1 float
+  int absorb;         // 1: log-domain (per-run exponents renormalised every half)
+  int64_t n;
+  int64_t nchunks;
+  int R;
+  const double* mu;   // caller marginals (binary64)
+  const double* nu;
+  void* mu32;         // float copies (dtype 1)
+  void* nu32;
+  void* vF;           // phi values (n)
+  void* vG[2];        // psi values, double-buffered (n)
+  int* eF;            // phi run exponents (nruns)
+  int* eG[2];         // psi run exponents
+  ChunkAgg* aggF;     // chunk aggregates of phi
+  ChunkAgg* aggG;     // chunk aggregates of psi
+  ChunkAgg* carry;    // chunk carries of the current half
+  void* agg2;         // two-state chunk aggregates (transport cost)
+  void* carry2;       // two-state chunk carries (transport cost)
+  double* part;       // per-chunk partial sums (error / cost)
+  double* part2;      // second partial array (mu-side error)
+  Ctrl* ctrl;
+  double* err_hist;   // optional (itr_max + 1)
+};
+
+hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
+hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+// psi-half of iteration l: psi^{l+1} = nu / (K^T phi^l); error of (phi^l, psi^l)
+// when `check`.
+hipError_t launch_half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                           int l, int check, double tol, hipStream_t s);
+// phi-half of iteration l: phi^{l+1} = mu / (K psi^{l+1}); finalises the error of
+// iteration l (when checked) and sets the stop flag.
+hipError_t launch_half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                           int l, int check, double tol, hipStream_t s);
+// Final marginal errors and transport cost of (phi, psi = vG[gbuf]).
+hipError_t launch_finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                           int gbuf, double h, hipStream_t s);
+// Potentials F = ln phi, G = ln psi into out[0..n), out[n..2n).
+hipError_t launch_potentials(const SolveBufs& b, int gbuf, double* out, hipStream_t s);
+
+}  // namespace fs1

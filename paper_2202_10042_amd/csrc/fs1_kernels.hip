@@ -1,0 +1,943 @@
+// fs1_kernels.hip -- HIP kernels of the FS-1 hot path for gfx950.
+//
+// Kernel map (one "chunk" = one 256-thread block of R-element runs):
+//   k_agg        chunk aggregates of a vector (forward / backward recursion
+//                states, Sec. 3 eq. (recursion)), from plain, scaled or log
+//                values
+//   k_carry      single-block scan of the chunk aggregates -> chunk carries;
+//                in a solve it also closes the stopping test of Algorithm 1
+//   k_kv_apply   K x (plain) or ln K e^x (log-sum-exp semiring)
+//   k_half       one half of the Sinkhorn update (Sec. 2: psi = nu / K^T phi,
+//                then phi = mu / K psi), fused with the marginal error of
+//                Algorithm 1's stopping test and with the chunk aggregates the
+//                next half needs
+//   k_cost_*     the returned double sum of Algorithm 1,
+//                sum_{i,j} phi_i psi_j lambda^{|i-j|} |i-j| h, by a two-state
+//                recursion (distance-weighted lower / upper parts) and a
+//                binary64 reduction
+//   k_setup, k_init, k_sum, k_potentials: validation, initial state
+//                (phi = psi = 1/n), reductions, ln phi / ln psi.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "fs1_device.h"
+#include "fs1_internal.h"
+
+namespace fs1 {
+
+// ===========================================================================
+// Host helpers
+// ===========================================================================
+Decay make_decay(double t) {
+  // lambda^D = 2^-t, t = D * c * log2(e) >= 0:  2^(k - t) * 2^-k, k = ceil(t)
+  const double k = std::ceil(t);
+  Decay d;
+  d.m = std::exp2(k - t);
+  d.e = -int(k);
+  d.pad = 0;
+  return d;
+}
+
+ScanConsts make_scan_consts(double h, double eps, int R) {
+  ScanConsts k{};
+  const double c = h / eps;
+  k.lam = std::exp(-c);
+  k.mu = -std::expm1(-c);
+  k.use_mu = k.lam > 0.5 ? 1 : 0;
+  k.c_log2e = c * kLog2E;
+  k.R = R;
+  for (int s = 0; s < 7; ++s) k.lane[s] = make_decay(double(R) * double(1 << s) * k.c_log2e);
+  k.chunk = make_decay(double(kBlock) * double(R) * k.c_log2e);
+  return k;
+}
+
+CarryConsts make_carry_consts(double h, double eps, int64_t chunk_len, int64_t nchunks) {
+  CarryConsts kc{};
+  const double cl = (h / eps) * kLog2E;
+  kc.nchunks = nchunks;
+  kc.group = (nchunks + kCarryBlock - 1) / kCarryBlock;
+  kc.chunk_len = chunk_len;
+  kc.chunk = make_decay(double(chunk_len) * cl);
+  for (int s = 0; s < 7; ++s)
+    kc.step[s] = make_decay(double(kc.group) * double(chunk_len) * double(1 << s) * cl);
+  return kc;
+}
+
+int pick_run_length(int dtype, bool absorb, double c) {
+  // In scaled (log-domain) arithmetic every output of a run is within
+  // lambda^(R-1) of the largest contribution to the run, so (R-1) h/eps must
+  // stay well inside the exponent range of the working precision.
+  if (dtype == 0) return (!absorb || 7.0 * c <= 600.0) ? 8 : 1;
+  if (!absorb || 15.0 * c <= 60.0) return 16;
+  if (7.0 * c <= 60.0) return 8;
+  if (3.0 * c <= 60.0) return 4;
+  return 1;
+}
+
+// ===========================================================================
+// Device helpers
+// ===========================================================================
+enum InMode { IN_PLAIN = 0, IN_SCALED = 1, IN_LOG = 2 };
+
+template <typename T, int R>
+__device__ __forceinline__ void load_log_run(const T* __restrict__ lx, int64_t base, int64_t n,
+                                             T (&x)[R], int& E) {
+  T raw[R];
+  load_run<T, R>(lx, base, n, raw, T(-INFINITY));
+  double t[R];
+  double tmax = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    t[j] = double(raw[j]) * kLog2E;
+    if (isfinite(t[j])) tmax = fmax(tmax, t[j]);
+  }
+  double Ed = (tmax == -INFINITY) ? 0.0 : floor(tmax);
+  Ed = fmin(fmax(Ed, -4.0e8), 4.0e8);
+  E = int(Ed);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const double d = t[j] - Ed;  // <= 1 for finite entries
+    if constexpr (sizeof(T) == 8) {
+      x[j] = exp2(d);
+    } else {
+      // split so that the binary32 exponential sees only the fraction in [0, 1)
+      if (isfinite(d)) {
+        const double k = floor(d);
+        const float f = float(d - k);
+        x[j] = ldexpf(exp2f(f), int(fmax(k, -400.0)));
+      } else {
+        x[j] = float(exp2(d));  // 0, +inf or NaN
+      }
+    }
+  }
+}
+
+template <typename T, int R, int IN>
+__device__ __forceinline__ void load_input(const T* __restrict__ v, const int* __restrict__ ex,
+                                           int64_t run, int64_t n, T (&x)[R], int& E) {
+  const int64_t base = run * R;
+  if constexpr (IN == IN_LOG) {
+    load_log_run<T, R>(v, base, n, x, E);
+  } else {
+    load_run<T, R>(v, base, n, x, T(0));
+    E = (IN == IN_SCALED) ? ex[run] : 0;
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void run_aggs(const T (&x)[R], const Lam<T>& L, T& af, T& ab) {
+  T a = T(0), b = T(0);
+#pragma unroll
+  for (int j = 0; j < R; ++j) a = L.axpy(a, x[j]);
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) b = L.axpy(b, x[j]);
+  af = a;
+  ab = b;
+}
+
+template <typename T>
+__device__ __forceinline__ void lane_decays(const ScanConsts& k, Dec<T> (&dec)[7]) {
+#pragma unroll
+  for (int s = 0; s < 7; ++s) dec[s] = dec_of<T>(k.lane[s], double(k.R) * double(1 << s));
+}
+
+// Largest exponent of the local values: values < 2^eloc.
+template <typename T, int R>
+__device__ __forceinline__ int local_exponent(const T (&x)[R], int E) {
+  T mx = T(0);
+#pragma unroll
+  for (int j = 0; j < R; ++j) mx = fmax(mx, x[j]);
+  if (!(mx > T(0))) return kExpZero;
+  if (!isfinite(mx)) return E;
+  int k;
+  frx(mx, &k);
+  return E + k;
+}
+
+// Both recursions of eq. (recursion) over one run, in the run's frame:
+// y_k = p_k + q_k with p fed by cf (state before the run) and q by cb
+// (inclusive backward state after the run).
+template <typename T, int R>
+__device__ __forceinline__ void run_apply(const T (&xf)[R], T cf, T cb, const Lam<T>& L,
+                                          T (&y)[R]) {
+  T A = cf;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    A = L.axpy(A, xf[j]);
+    y[j] = A;
+  }
+  T P = cb;
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    const T B = L.mul(P);
+    y[j] += B;
+    P = B + xf[j];
+  }
+}
+
+// ===========================================================================
+// k_agg: chunk aggregates of a vector
+// ===========================================================================
+template <typename T, int R, int IN>
+__global__ __launch_bounds__(kBlock) void k_agg(const T* __restrict__ v, const int* __restrict__ ex,
+                                                int64_t n, ScanConsts k,
+                                                ChunkAgg* __restrict__ agg) {
+  __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  T x[R];
+  int E;
+  load_input<T, R, IN>(v, ex, run, n, x, E);
+  const Lam<T> L = lam_of<T>(k);
+  T af, ab;
+  run_aggs<T, R>(x, L, af, ab);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  S1<T> gf, gb;
+  block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(),
+                                       S1<T>::zero(), nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    agg[blockIdx.x].f = to64(gf.v);
+    agg[blockIdx.x].b = to64(gb.v);
+  }
+}
+
+// ===========================================================================
+// k_carry: single-block scan of chunk aggregates -> chunk carries
+//   MODE 0: plain.  MODE 1: psi-half of a solve (skip when stopped).
+//   MODE 2: phi-half of a solve: close the stopping test of iteration l.
+// ===========================================================================
+template <int MODE>
+__global__ __launch_bounds__(kCarryBlock) void k_carry(const ChunkAgg* __restrict__ agg,
+                                                       ChunkAgg* __restrict__ carry,
+                                                       CarryConsts kc, Ctrl* ctrl,
+                                                       const double* __restrict__ part,
+                                                       double* err_hist, int l, int check,
+                                                       double tol) {
+  constexpr int NW = kCarryBlock / kWave;
+  __shared__ ScanLds<S1<double>, NW> sh;
+  __shared__ double red[NW];
+  __shared__ int stop;
+  const int t = threadIdx.x;
+  const int64_t g0 = int64_t(t) * kc.group;
+  const int64_t g1 = (g0 + kc.group < kc.nchunks) ? g0 + kc.group : kc.nchunks;
+
+  if constexpr (MODE != 0) {
+    if (ctrl->done) return;
+    if (ctrl->fail) {
+      if (t == 0) ctrl->done = 1;
+      return;
+    }
+  }
+  if constexpr (MODE == 2) {
+    if (check) {
+      double s = 0.0;
+      for (int64_t c = g0; c < g1; ++c) s += part[c];
+      const double tot = block_sum<NW>(s, red);
+      if (t == 0) {
+        ctrl->last_err = tot;
+        ctrl->last_check = l;
+        if (err_hist) err_hist[l] = tot;
+        stop = !(tot > tol);
+        if (stop) {
+          ctrl->done = 1;
+          ctrl->stop_iter = l;
+        }
+      }
+      __syncthreads();
+      if (stop) return;
+    }
+  }
+
+  const Dec<double> cdec = dec_of<double>(kc.chunk, double(kc.chunk_len));
+  S1<double> gf = S1<double>::zero(), gb = S1<double>::zero();
+  for (int64_t c = g0; c < g1; ++c)
+    gf = gf.shift(cdec).add(S1<double>{{agg[c].f.m, agg[c].f.e}}).norm();
+  for (int64_t c = g1 - 1; c >= g0; --c)
+    gb = gb.shift(cdec).add(S1<double>{{agg[c].b.m, agg[c].b.e}}).norm();
+  // Every group spans `group` chunks in the block scan.  Only the last
+  // non-empty group can be cut short by nchunks; its forward aggregate feeds
+  // only later groups, which are empty, and its backward aggregate (state at
+  // the group start) is unaffected by the empty tail.
+  Dec<double> dec[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s)
+    dec[s] = dec_of<double>(kc.step[s], double(kc.group) * double(kc.chunk_len) * double(1 << s));
+  S1<double> cf, cb;
+  block_scan<S1<double>, NW, double>(gf, gb, dec, S1<double>::zero(), S1<double>::zero(), &cf,
+                                     &cb, nullptr, nullptr, sh);
+  S1<double> run = cf;
+  for (int64_t c = g0; c < g1; ++c) {
+    carry[c].f = to64(run.v);
+    run = run.shift(cdec).add(S1<double>{{agg[c].f.m, agg[c].f.e}}).norm();
+  }
+  run = cb;
+  for (int64_t c = g1 - 1; c >= g0; --c) {
+    carry[c].b = to64(run.v);
+    run = run.shift(cdec).add(S1<double>{{agg[c].b.m, agg[c].b.e}}).norm();
+  }
+}
+
+// ===========================================================================
+// k_kv_apply: y = K x (plain) or ly = ln K e^lx (log)
+// ===========================================================================
+template <typename T, int R, bool LOG>
+__global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
+                                                     T* __restrict__ y_out, int64_t n,
+                                                     ScanConsts k,
+                                                     const ChunkAgg* __restrict__ carry) {
+  __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  T x[R];
+  int E;
+  load_input<T, R, LOG ? IN_LOG : IN_PLAIN>(x_in, nullptr, run, n, x, E);
+  const Lam<T> L = lam_of<T>(k);
+  T af, ab;
+  run_aggs<T, R>(x, L, af, ab);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  const ChunkAgg cg = carry[blockIdx.x];
+  S1<T> cf, cb;
+  block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
+                                       S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
+                                       nullptr, nullptr, sh);
+  int eref = 0;
+  if constexpr (LOG) {
+    eref = max(local_exponent<T, R>(x, E), max(cf.v.e, cb.v.e));
+    if (eref == kExpZero) eref = 0;
+  }
+  T xf[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
+  T y[R];
+  run_apply<T, R>(xf, ldx(cf.v.m, cf.v.e - eref), ldx(cb.v.m, cb.v.e - eref), L, y);
+  if constexpr (LOG) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if constexpr (sizeof(T) == 8) {
+        y[j] = (log2(y[j]) + double(eref)) * kLn2;
+      } else {
+        const float yy = y[j];
+        if (yy > 0.0f && isfinite(yy)) {
+          int ke;
+          const float fm = frexpf(yy, &ke);
+          y[j] = float((double(log2f(fm)) + double(ke) + double(eref)) * kLn2);
+        } else {
+          y[j] = float(log2(double(yy)));  // -inf, +inf or NaN
+        }
+      }
+    }
+  }
+  store_run<T, R>(y_out, run * R, n, y);
+}
+
+// ===========================================================================
+// k_half: one half of the Sinkhorn update (Sec. 2), fused with the error of
+// Algorithm 1's stopping test and with the aggregates of the new vector.
+//   MODE_PSI: psi^{l+1} = nu / (K^T phi^l); when `check`, also
+//             err(l) = sum |psi^l (K^T phi^l) - nu| (per-chunk partials)
+//   MODE_PHI: phi^{l+1} = mu / (K psi^{l+1})
+//   MODE_ERR: only sum |own * (K in) - marg| (finalisation)
+// State layout: value_j = v_j * 2^(ex[run of j]); with ABSORB = false the run
+// exponents are identically 0 and the iteration is Algorithm 1 in plain
+// floating point.
+// ===========================================================================
+enum HalfMode { MODE_PSI = 0, MODE_PHI = 1, MODE_ERR = 2 };
+
+template <typename T>
+struct HalfArgs {
+  const T* vin;        // vector fed to K
+  const int* ein;
+  const double* m64;   // marginal, binary64 (error; update when T = double)
+  const float* m32;    // marginal, binary32 copy (update when T = float)
+  T* vout;             // updated vector
+  int* eout;
+  const T* vown;       // own vector for the error term
+  const int* eown;
+  const ChunkAgg* carry;
+  ChunkAgg* agg_out;
+  double* part;
+  Ctrl* ctrl;
+  int64_t n;
+  int l;
+  int check;
+};
+
+template <typename T, int R, bool ABSORB, int MODE>
+__global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
+  __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
+  __shared__ double red[kBlock / kWave];
+  if constexpr (MODE != MODE_ERR) {
+    if (a.ctrl->done) return;
+  }
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t base = run * R;
+  const int64_t n = a.n;
+  T x[R];
+  int E;
+  load_input<T, R, ABSORB ? IN_SCALED : IN_PLAIN>(a.vin, a.ein, run, n, x, E);
+  const Lam<T> L = lam_of<T>(k);
+  T af, ab;
+  run_aggs<T, R>(x, L, af, ab);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  const ChunkAgg cg = a.carry[blockIdx.x];
+  S1<T> cf, cb;
+  block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
+                                       S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
+                                       nullptr, nullptr, sh);
+  int eref = 0;
+  if constexpr (ABSORB) {
+    eref = max(local_exponent<T, R>(x, E), max(cf.v.e, cb.v.e));
+    if (eref == kExpZero) eref = 0;
+  }
+  T xf[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
+  T y[R];  // (K in)_j * 2^-eref
+  run_apply<T, R>(xf, ldx(cf.v.m, cf.v.e - eref), ldx(cb.v.m, cb.v.e - eref), L, y);
+
+  // error term sum_j | own_j (K in)_j - marg_j |, binary64
+  const bool want_err = (MODE == MODE_ERR) || (MODE == MODE_PSI && a.check);
+  if (want_err) {
+    T own[R];
+    load_run<T, R>(a.vown, base, n, own, T(0));
+    double mg[R];
+    load_run<double, R>(a.m64, base, n, mg, 0.0);
+    const int eo = ABSORB ? a.eown[run] : 0;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (base + j < n) {
+        const double pr = ldexp(double(own[j]) * double(y[j]), eo + eref);
+        s += fabs(pr - mg[j]);
+      }
+    }
+    const double tot = block_sum<kBlock / kWave>(s, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+  }
+  if constexpr (MODE == MODE_ERR) return;
+
+  // update: out_j = marg_j / (K in)_j  (zero marginal -> zero scaling)
+  T mg[R];
+  if constexpr (sizeof(T) == 8) {
+    load_run<T, R>(reinterpret_cast<const T*>(a.m64), base, n, mg, T(0));
+  } else {
+    load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, n, mg, T(0));
+  }
+  T q[R];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    q[j] = (mg[j] == T(0)) ? T(0) : mg[j] / y[j];
+    bad |= !isfinite(q[j]);
+  }
+  int Eo = 0;
+  if constexpr (ABSORB) {
+    // absorb the power-of-two part of the new run into its exponent
+    T qm = T(0);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (isfinite(q[j])) qm = fmax(qm, q[j]);
+    int kq = 0;
+    if (qm > T(0)) frx(qm, &kq);
+#pragma unroll
+    for (int j = 0; j < R; ++j) q[j] = ldx(q[j], -kq);
+    Eo = kq - eref;
+    a.eout[run] = Eo;
+  }
+  store_run<T, R>(a.vout, base, n, q);
+  if (bad) {
+    atomicOr(&a.ctrl->fail, 1);
+    atomicMin(&a.ctrl->fail_iter, a.l);
+  }
+  // aggregates of the new vector for the next half
+  T nf, nb;
+  run_aggs<T, R>(q, L, nf, nb);
+  S1<T> gf, gb;
+  block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{nf, Eo}}, S1<T>{{nb, Eo}}, dec, S1<T>::zero(),
+                                       S1<T>::zero(), nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    a.agg_out[blockIdx.x].f = to64(gf.v);
+    a.agg_out[blockIdx.x].b = to64(gb.v);
+  }
+}
+
+// ===========================================================================
+// Transport cost: W = h sum_i phi_i (D_i + E_i), with
+//   D_i = sum_{j<i} psi_j lambda^{i-j} (i-j),  E_i = sum_{j>i} psi_j lambda^{j-i} (j-i).
+// Forward pair (p, D): D <- lambda (D + p), p <- lambda p + psi_j; the
+// backward pair mirrors it.  These follow from splitting |i-j| in the double
+// sum of Algorithm 1's return into j < i and j > i.
+// ===========================================================================
+struct ChunkAgg2 {
+  double fp, fd;
+  int fe, pad0;
+  double bp, bd;
+  int be, pad1;
+};
+
+template <typename T>
+__device__ __forceinline__ S2<T> s2_of(double p, double d, int e) {
+  return {T(p), T(d), e};
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void run_aggs2(const T (&x)[R], const Lam<T>& L, T& fp, T& fd, T& bp,
+                                          T& bd) {
+  T p = T(0), d = T(0);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    d = L.mul(d + p);
+    p = L.axpy(p, x[j]);
+  }
+  T q = T(0), e = T(0);
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    e = L.mul(e + q);
+    q = L.axpy(q, x[j]);
+  }
+  fp = p;
+  fd = d;
+  bp = q;
+  bd = e;
+}
+
+template <typename T, int R, bool ABSORB>
+__global__ __launch_bounds__(kBlock) void k_cost_agg(const T* __restrict__ v,
+                                                     const int* __restrict__ ex, int64_t n,
+                                                     ScanConsts k, ChunkAgg2* __restrict__ agg) {
+  __shared__ ScanLds<S2<T>, kBlock / kWave> sh;
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  T x[R];
+  int E;
+  load_input<T, R, ABSORB ? IN_SCALED : IN_PLAIN>(v, ex, run, n, x, E);
+  const Lam<T> L = lam_of<T>(k);
+  T fp, fd, bp, bd;
+  run_aggs2<T, R>(x, L, fp, fd, bp, bd);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  S2<T> gf, gb;
+  block_scan<S2<T>, kBlock / kWave, T>(S2<T>{fp, fd, E}, S2<T>{bp, bd, E}, dec, S2<T>::zero(),
+                                       S2<T>::zero(), nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    ChunkAgg2 o;
+    o.fp = gf.p;
+    o.fd = gf.d;
+    o.fe = gf.e;
+    o.pad0 = 0;
+    o.bp = gb.p;
+    o.bd = gb.d;
+    o.be = gb.e;
+    o.pad1 = 0;
+    agg[blockIdx.x] = o;
+  }
+}
+
+__global__ __launch_bounds__(kCarryBlock) void k_cost_carry(const ChunkAgg2* __restrict__ agg,
+                                                            ChunkAgg2* __restrict__ carry,
+                                                            CarryConsts kc) {
+  constexpr int NW = kCarryBlock / kWave;
+  __shared__ ScanLds<S2<double>, NW> sh;
+  const int t = threadIdx.x;
+  const int64_t g0 = int64_t(t) * kc.group;
+  const int64_t g1 = (g0 + kc.group < kc.nchunks) ? g0 + kc.group : kc.nchunks;
+  const Dec<double> cdec = dec_of<double>(kc.chunk, double(kc.chunk_len));
+  S2<double> gf = S2<double>::zero(), gb = S2<double>::zero();
+  for (int64_t c = g0; c < g1; ++c)
+    gf = gf.shift(cdec).add(s2_of<double>(agg[c].fp, agg[c].fd, agg[c].fe)).norm();
+  // (a group cut short by nchunks only feeds empty groups; see k_carry)
+  for (int64_t c = g1 - 1; c >= g0; --c)
+    gb = gb.shift(cdec).add(s2_of<double>(agg[c].bp, agg[c].bd, agg[c].be)).norm();
+  Dec<double> dec[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s)
+    dec[s] = dec_of<double>(kc.step[s], double(kc.group) * double(kc.chunk_len) * double(1 << s));
+  S2<double> cf, cb;
+  block_scan<S2<double>, NW, double>(gf, gb, dec, S2<double>::zero(), S2<double>::zero(), &cf,
+                                     &cb, nullptr, nullptr, sh);
+  S2<double> r = cf;
+  for (int64_t c = g0; c < g1; ++c) {
+    carry[c].fp = r.p;
+    carry[c].fd = r.d;
+    carry[c].fe = r.e;
+    r = r.shift(cdec).add(s2_of<double>(agg[c].fp, agg[c].fd, agg[c].fe)).norm();
+  }
+  r = cb;
+  for (int64_t c = g1 - 1; c >= g0; --c) {
+    carry[c].bp = r.p;
+    carry[c].bd = r.d;
+    carry[c].be = r.e;
+    r = r.shift(cdec).add(s2_of<double>(agg[c].bp, agg[c].bd, agg[c].be)).norm();
+  }
+}
+
+template <typename T, int R, bool ABSORB>
+__global__ __launch_bounds__(kBlock) void k_cost_apply(const T* __restrict__ vphi,
+                                                       const int* __restrict__ ephi,
+                                                       const T* __restrict__ vpsi,
+                                                       const int* __restrict__ epsi, int64_t n,
+                                                       ScanConsts k,
+                                                       const ChunkAgg2* __restrict__ carry,
+                                                       double* __restrict__ part) {
+  __shared__ ScanLds<S2<T>, kBlock / kWave> sh;
+  __shared__ double red[kBlock / kWave];
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t base = run * R;
+  T x[R];
+  int E;
+  load_input<T, R, ABSORB ? IN_SCALED : IN_PLAIN>(vpsi, epsi, run, n, x, E);
+  const Lam<T> L = lam_of<T>(k);
+  T fp, fd, bp, bd;
+  run_aggs2<T, R>(x, L, fp, fd, bp, bd);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  const ChunkAgg2 cg = carry[blockIdx.x];
+  S2<T> cf, cb;
+  block_scan<S2<T>, kBlock / kWave, T>(S2<T>{fp, fd, E}, S2<T>{bp, bd, E}, dec,
+                                       s2_of<T>(cg.fp, cg.fd, cg.fe),
+                                       s2_of<T>(cg.bp, cg.bd, cg.be), &cf, &cb, nullptr, nullptr,
+                                       sh);
+  // frame: every source is brought below 2^eref
+  int eref = local_exponent<T, R>(x, E);
+  if (cf.p != T(0) || cf.d != T(0)) eref = max(eref, cf.e);
+  if (cb.p != T(0) || cb.d != T(0)) eref = max(eref, cb.e);
+  if (eref == kExpZero) eref = 0;
+  T xf[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
+  T p = ldx(cf.p, cf.e - eref), d = ldx(cf.d, cf.e - eref);
+  T w[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    d = L.mul(d + p);
+    p = L.axpy(p, xf[j]);
+    w[j] = d;
+  }
+  T q = ldx(cb.p, cb.e - eref), e = ldx(cb.d, cb.e - eref);
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    e = L.mul(e + q);
+    q = L.axpy(q, xf[j]);
+    w[j] += e;
+  }
+  T ph[R];
+  load_run<T, R>(vphi, base, n, ph, T(0));
+  const int ep = ABSORB ? ephi[run] : 0;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (base + j < n) s += ldexp(double(ph[j]) * double(w[j]), ep + eref);
+  const double tot = block_sum<kBlock / kWave>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// ===========================================================================
+// Small kernels: setup, initial state, reductions, potentials
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_setup(const double* __restrict__ mu,
+                                               const double* __restrict__ nu, int64_t n,
+                                               float* __restrict__ mu32,
+                                               float* __restrict__ nu32, Ctrl* ctrl) {
+  __shared__ double red[4];
+  double sm = 0.0, sn = 0.0;
+  int bad = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double a = mu[i], b = nu[i];
+    bad |= !(isfinite(a) && a >= 0.0) || !(isfinite(b) && b >= 0.0);
+    sm += a;
+    sn += b;
+    if (mu32) {
+      mu32[i] = float(a);
+      nu32[i] = float(b);
+    }
+  }
+  const double tm = block_sum<4>(sm, red);
+  const double tn = block_sum<4>(sn, red);
+  if (bad) atomicOr(&ctrl->bad_input, 1);
+  if (threadIdx.x == 0) {
+    atomicAdd(&ctrl->sum_mu, tm);
+    atomicAdd(&ctrl->sum_nu, tn);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(T* __restrict__ vf, T* __restrict__ vg, int* ef,
+                                              int* eg, int64_t n, int64_t nruns, Ctrl* ctrl) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const T v = T(1.0 / double(n));
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    vf[i] = v;
+    vg[i] = v;
+  }
+  if (ef) {
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < nruns; r += stride) {
+      ef[r] = 0;
+      eg[r] = 0;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->done = 0;
+    ctrl->stop_iter = -1;
+    ctrl->fail = 0;
+    ctrl->fail_iter = INT_MAX;
+    ctrl->last_check = -1;
+    ctrl->last_err = NAN;
+  }
+}
+
+// out = scale * sum(part[0..np)) in a fixed order
+__global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ part, int64_t np,
+                                              double scale, double* out) {
+  __shared__ double red[16];
+  const int64_t per = (np + 1023) / 1024;
+  const int64_t a = int64_t(threadIdx.x) * per;
+  const int64_t b = (a + per < np) ? a + per : np;
+  double s = 0.0;
+  for (int64_t i = a; i < b; ++i) s += part[i];
+  const double t = block_sum<16>(s, red);
+  if (threadIdx.x == 0) *out = t * scale;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potentials(const T* __restrict__ v,
+                                                    const int* __restrict__ ex, int R,
+                                                    int64_t n, double* __restrict__ out) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double x = double(v[i]);
+    const int e = ex ? ex[i / R] : 0;
+    out[i] = (x > 0.0) ? log(x) + double(e) * kLn2 : (x == 0.0 ? -INFINITY : NAN);
+  }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+static inline unsigned grid_of(int64_t nchunks) { return unsigned(nchunks); }
+
+template <typename T, int R>
+static hipError_t kv_plain_t(const void* x, void* y, int64_t n, const ScanConsts& k,
+                             const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                             hipStream_t s) {
+  const unsigned g = grid_of(kc.nchunks);
+  k_agg<T, R, IN_PLAIN><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg);
+  k_carry<0><<<1, kCarryBlock, 0, s>>>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0);
+  k_kv_apply<T, R, false><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), static_cast<T*>(y), n,
+                                               k, carry);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+static hipError_t kv_log_t(const void* x, void* y, int64_t n, const ScanConsts& k,
+                           const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                           hipStream_t s) {
+  const unsigned g = grid_of(kc.nchunks);
+  k_agg<T, R, IN_LOG><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg);
+  k_carry<0><<<1, kCarryBlock, 0, s>>>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0);
+  k_kv_apply<T, R, true><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), static_cast<T*>(y), n,
+                                              k, carry);
+  return hipGetLastError();
+}
+
+hipError_t launch_kv_plain(int dtype, const void* x, void* y, int64_t n, const ScanConsts& k,
+                           const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                           hipStream_t s) {
+  if (dtype == 0) {
+    if (k.R == 8) return kv_plain_t<double, 8>(x, y, n, k, kc, agg, carry, s);
+    return kv_plain_t<double, 1>(x, y, n, k, kc, agg, carry, s);
+  }
+  switch (k.R) {
+    case 16: return kv_plain_t<float, 16>(x, y, n, k, kc, agg, carry, s);
+    case 8: return kv_plain_t<float, 8>(x, y, n, k, kc, agg, carry, s);
+    case 4: return kv_plain_t<float, 4>(x, y, n, k, kc, agg, carry, s);
+    default: return kv_plain_t<float, 1>(x, y, n, k, kc, agg, carry, s);
+  }
+}
+
+hipError_t launch_kv_log(int dtype, const void* x, void* y, int64_t n, const ScanConsts& k,
+                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                         hipStream_t s) {
+  if (dtype == 0) {
+    if (k.R == 8) return kv_log_t<double, 8>(x, y, n, k, kc, agg, carry, s);
+    return kv_log_t<double, 1>(x, y, n, k, kc, agg, carry, s);
+  }
+  switch (k.R) {
+    case 16: return kv_log_t<float, 16>(x, y, n, k, kc, agg, carry, s);
+    case 8: return kv_log_t<float, 8>(x, y, n, k, kc, agg, carry, s);
+    case 4: return kv_log_t<float, 4>(x, y, n, k, kc, agg, carry, s);
+    default: return kv_log_t<float, 1>(x, y, n, k, kc, agg, carry, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve launchers: dispatch on (dtype, R, absorb)
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool AB>
+struct SolveOps {
+  static hipError_t setup_aggF(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
+    k_agg<T, R, AB ? IN_SCALED : IN_PLAIN><<<grid_of(b.nchunks), kBlock, 0, s>>>(
+        static_cast<const T*>(b.vF), b.eF, b.n, k, b.aggF);
+    return hipGetLastError();
+  }
+  static HalfArgs<T> args(const SolveBufs& b, int mode, int l, int check, int gbuf) {
+    HalfArgs<T> a{};
+    a.n = b.n;
+    a.l = l;
+    a.check = check;
+    a.ctrl = b.ctrl;
+    a.carry = b.carry;
+    a.part = b.part;
+    if (mode == MODE_PSI) {
+      const int cur = l & 1, nxt = (l + 1) & 1;
+      a.vin = static_cast<const T*>(b.vF);
+      a.ein = b.eF;
+      a.m64 = b.nu;
+      a.m32 = static_cast<const float*>(b.nu32);
+      a.vout = static_cast<T*>(b.vG[nxt]);
+      a.eout = b.eG[nxt];
+      a.vown = static_cast<const T*>(b.vG[cur]);
+      a.eown = b.eG[cur];
+      a.agg_out = b.aggG;
+    } else {
+      const int nxt = (l + 1) & 1;
+      a.vin = static_cast<const T*>(b.vG[nxt]);
+      a.ein = b.eG[nxt];
+      a.m64 = b.mu;
+      a.m32 = static_cast<const float*>(b.mu32);
+      a.vout = static_cast<T*>(b.vF);
+      a.eout = b.eF;
+      a.agg_out = b.aggF;
+    }
+    (void)gbuf;
+    return a;
+  }
+  static hipError_t half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                             int l, int check, double tol, hipStream_t s) {
+    k_carry<1><<<1, kCarryBlock, 0, s>>>(b.aggF, b.carry, kc, b.ctrl, nullptr, nullptr, l, 0,
+                                         tol);
+    k_half<T, R, AB, MODE_PSI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
+        args(b, MODE_PSI, l, check, 0), k);
+    return hipGetLastError();
+  }
+  static hipError_t half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                             int l, int check, double tol, hipStream_t s) {
+    k_carry<2><<<1, kCarryBlock, 0, s>>>(b.aggG, b.carry, kc, b.ctrl, b.part, b.err_hist, l,
+                                         check, tol);
+    k_half<T, R, AB, MODE_PHI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
+        args(b, MODE_PHI, l, check, 0), k);
+    return hipGetLastError();
+  }
+  static hipError_t finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                             int gbuf, double h, hipStream_t s) {
+    const unsigned g = grid_of(b.nchunks);
+    const T* vF = static_cast<const T*>(b.vF);
+    const T* vG = static_cast<const T*>(b.vG[gbuf]);
+    const int* eF = b.eF;
+    const int* eG = b.eG[gbuf];
+    // nu side: | psi (K^T phi) - nu |
+    k_agg<T, R, AB ? IN_SCALED : IN_PLAIN><<<g, kBlock, 0, s>>>(vF, eF, b.n, k, b.aggF);
+    k_carry<0><<<1, kCarryBlock, 0, s>>>(b.aggF, b.carry, kc, nullptr, nullptr, nullptr, 0, 0,
+                                         0.0);
+    HalfArgs<T> a{};
+    a.n = b.n;
+    a.ctrl = b.ctrl;
+    a.carry = b.carry;
+    a.part = b.part;
+    a.vin = vF;
+    a.ein = eF;
+    a.vown = vG;
+    a.eown = eG;
+    a.m64 = b.nu;
+    k_half<T, R, AB, MODE_ERR><<<g, kBlock, 0, s>>>(a, k);
+    k_sum<<<1, 1024, 0, s>>>(b.part, b.nchunks, 1.0, &b.ctrl->err_final);
+    // mu side: | phi (K psi) - mu |
+    k_agg<T, R, AB ? IN_SCALED : IN_PLAIN><<<g, kBlock, 0, s>>>(vG, eG, b.n, k, b.aggG);
+    k_carry<0><<<1, kCarryBlock, 0, s>>>(b.aggG, b.carry, kc, nullptr, nullptr, nullptr, 0, 0,
+                                         0.0);
+    a.vin = vG;
+    a.ein = eG;
+    a.vown = vF;
+    a.eown = eF;
+    a.m64 = b.mu;
+    k_half<T, R, AB, MODE_ERR><<<g, kBlock, 0, s>>>(a, k);
+    k_sum<<<1, 1024, 0, s>>>(b.part, b.nchunks, 1.0, &b.ctrl->mu_err);
+    // transport cost
+    ChunkAgg2* agg2 = static_cast<ChunkAgg2*>(b.agg2);
+    ChunkAgg2* car2 = static_cast<ChunkAgg2*>(b.carry2);
+    k_cost_agg<T, R, AB><<<g, kBlock, 0, s>>>(vG, eG, b.n, k, agg2);
+    k_cost_carry<<<1, kCarryBlock, 0, s>>>(agg2, car2, kc);
+    k_cost_apply<T, R, AB><<<g, kBlock, 0, s>>>(vF, eF, vG, eG, b.n, k, car2, b.part);
+    k_sum<<<1, 1024, 0, s>>>(b.part, b.nchunks, h, &b.ctrl->w1);
+    return hipGetLastError();
+  }
+  static hipError_t init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
+    const int64_t nruns = b.nchunks * kBlock;
+    const unsigned g = unsigned(std::min<int64_t>((std::max(b.n, nruns) + 255) / 256, 4096));
+    k_init<T><<<g, 256, 0, s>>>(static_cast<T*>(b.vF), static_cast<T*>(b.vG[0]),
+                                AB ? b.eF : nullptr, AB ? b.eG[0] : nullptr, b.n, nruns, b.ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return setup_aggF(b, k, s);
+  }
+  static hipError_t potentials(const SolveBufs& b, int gbuf, double* out, hipStream_t s) {
+    const unsigned g = unsigned(std::min<int64_t>((b.n + 255) / 256, 4096));
+    k_potentials<T><<<g, 256, 0, s>>>(static_cast<const T*>(b.vF), AB ? b.eF : nullptr, R, b.n,
+                                      out);
+    k_potentials<T><<<g, 256, 0, s>>>(static_cast<const T*>(b.vG[gbuf]),
+                                      AB ? b.eG[gbuf] : nullptr, R, b.n, out + b.n);
+    return hipGetLastError();
+  }
+};
+
+// Call F with the SolveOps instantiation matching the solve's configuration.
+template <typename F>
+static hipError_t dispatch(const SolveBufs& b, F&& f) {
+  if (b.dtype == 0) {
+    if (b.R == 8) return b.absorb ? f(SolveOps<double, 8, true>{}) : f(SolveOps<double, 8, false>{});
+    return b.absorb ? f(SolveOps<double, 1, true>{}) : f(SolveOps<double, 1, false>{});
+  }
+  switch (b.R) {
+    case 16:
+      return b.absorb ? f(SolveOps<float, 16, true>{}) : f(SolveOps<float, 16, false>{});
+    case 8:
+      return b.absorb ? f(SolveOps<float, 8, true>{}) : f(SolveOps<float, 8, false>{});
+    case 4:
+      return b.absorb ? f(SolveOps<float, 4, true>{}) : f(SolveOps<float, 4, false>{});
+    default:
+      return b.absorb ? f(SolveOps<float, 1, true>{}) : f(SolveOps<float, 1, false>{});
+  }
+}
+
+hipError_t launch_setup(const SolveBufs& b, hipStream_t s) {
+  const unsigned g = unsigned(std::min<int64_t>((b.n + 255) / 256, 2048));
+  k_setup<<<g, 256, 0, s>>>(b.mu, b.nu, b.n, static_cast<float*>(b.mu32),
+                            static_cast<float*>(b.nu32), b.ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::init(b, k, s); });
+}
+
+hipError_t launch_half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc, int l,
+                           int check, double tol, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::half_psi(b, k, kc, l, check, tol, s); });
+}
+
+hipError_t launch_half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc, int l,
+                           int check, double tol, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::half_phi(b, k, kc, l, check, tol, s); });
+}
+
+hipError_t launch_finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                           int gbuf, double h, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::finalize(b, k, kc, gbuf, h, s); });
+}
+
+hipError_t launch_potentials(const SolveBufs& b, int gbuf, double* out, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::potentials(b, gbuf, out, s); });
+}
+
+}  // namespace fs1

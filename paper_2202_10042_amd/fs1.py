@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libfs1 (include/fs1.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libfs1.so.  Torch tensors supply device memory and the stream.  There
+is no CPU fallback: if the library or a GPU is missing, calls raise.
+
+The functions keep the C names:
+  fs1_kv_apply(x, h, eps)            -> K x
+  fs1_kv_apply_log(lx, h, eps)       -> ln K e^lx
+  fs1_solve(mu, nu, eps, tol, ...)   -> Result (Algorithm 1, FS-1)
+  fs1_solve_batched(mu, nu, offsets, eps, tol, ...) -> list[Result]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfs1.so")
+
+FS1_OK = 0
+FS1_ERR_INVALID_ARG = -1
+FS1_ERR_NONFINITE = -2
+FS1_ERR_HIP = -3
+FS1_ERR_NO_MEMORY = -4
+FS1_ERR_INTERNAL = -5
+
+FS1_F64 = 0
+FS1_F32 = 1
+FS1_PLAIN = 0
+FS1_LOG = 1
+
+# every symbol include/fs1.h declares
+EXPORTS = (
+    "fs1_ctx_create", "fs1_ctx_destroy", "fs1_ctx_set_stream", "fs1_last_error",
+    "fs1_version", "fs1_kv_apply", "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve",
+    "fs1_solve_batched",
+)
+
+
+class Fs1Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libfs1 status {status}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("h", ctypes.c_double),
+        ("itr_max", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("domain", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("sync_every", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("potentials_out", ctypes.c_void_p),
+        ("err_history", ctypes.c_void_p),
+    ]
+
+
+class CResult(ctypes.Structure):
+    _fields_ = [
+        ("w1", ctypes.c_double),
+        ("marginal_err", ctypes.c_double),
+        ("mu_err", ctypes.c_double),
+        ("iterations", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+@dataclass
+class Result:
+    w1: float
+    marginal_err: float
+    mu_err: float
+    iterations: int
+    converged: bool
+    status: int
+    F: Optional[object] = None        # torch tensor ln(phi) when requested
+    G: Optional[object] = None        # torch tensor ln(psi) when requested
+    err_history: Optional[object] = None
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfs1.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfs1.so not found at {path}; build it with "
+                           "`python -m paper_2202_10042_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, d, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32
+    lib.fs1_ctx_create.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.fs1_ctx_create.restype = ctypes.c_int
+    lib.fs1_ctx_destroy.argtypes = [vp]
+    lib.fs1_ctx_destroy.restype = ctypes.c_int
+    lib.fs1_ctx_set_stream.argtypes = [vp, vp]
+    lib.fs1_ctx_set_stream.restype = ctypes.c_int
+    lib.fs1_last_error.argtypes = []
+    lib.fs1_last_error.restype = ctypes.c_char_p
+    lib.fs1_version.argtypes = []
+    lib.fs1_version.restype = ctypes.c_char_p
+    lib.fs1_kv_apply.argtypes = [vp, vp, vp, i64, d, d, ctypes.c_int]
+    lib.fs1_kv_apply.restype = ctypes.c_int
+    lib.fs1_kv_apply_log.argtypes = [vp, vp, vp, i64, d, d, ctypes.c_int]
+    lib.fs1_kv_apply_log.restype = ctypes.c_int
+    lib.fs1_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    lib.fs1_opts_default.restype = ctypes.c_int
+    lib.fs1_solve.argtypes = [vp, vp, vp, i64, d, d, ctypes.POINTER(Opts), ctypes.POINTER(CResult)]
+    lib.fs1_solve.restype = ctypes.c_int
+    lib.fs1_solve_batched.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32,
+                                      ctypes.POINTER(d), ctypes.POINTER(d),
+                                      ctypes.POINTER(Opts), ctypes.POINTER(CResult)]
+    lib.fs1_solve_batched.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().fs1_last_error().decode()
+
+
+def _check(st: int):
+    if st != FS1_OK:
+        raise Fs1Error(st, last_error())
+
+
+class Context:
+    """A libfs1 context bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libfs1 needs a ROCm GPU; none is visible")
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream_obj = stream
+        h = ctypes.c_void_p()
+        _check(lib.fs1_ctx_create(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        self._stream_obj = stream
+        _check(load().fs1_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().fs1_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    import torch
+    if _default_ctx is None:
+        _default_ctx = Context()
+    _default_ctx.set_stream(torch.cuda.current_stream())
+    return _default_ctx
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return FS1_F64
+    if t.dtype == torch.float32:
+        return FS1_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def fs1_kv_apply(x, h: float, eps: float, out=None, ctx: Optional[Context] = None):
+    """y = K x, K_ij = exp(-|i-j| h/eps)  (float64 or float32 tensor)."""
+    import torch
+    ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(load().fs1_kv_apply(ctx.handle, _dev(x, "x"), _dev(out, "out"), x.numel(),
+                               float(h), float(eps), _dtype_code(x)))
+    return out
+
+
+def fs1_kv_apply_log(lx, h: float, eps: float, out=None, ctx: Optional[Context] = None):
+    """ly = ln K e^lx (log-sum-exp semiring)."""
+    import torch
+    ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty_like(lx)
+    _check(load().fs1_kv_apply_log(ctx.handle, _dev(lx, "lx"), _dev(out, "out"), lx.numel(),
+                                   float(h), float(eps), _dtype_code(lx)))
+    return out
+
+
+def make_opts(h: Optional[float] = None, itr_max: int = 10000, dtype: str = "f64",
+              domain: str = "plain", check_every: int = 1, sync_every: int = 16) -> Opts:
+    o = Opts()
+    load().fs1_opts_default(ctypes.byref(o))
+    o.h = float(h) if h else 0.0
+    o.itr_max = int(itr_max)
+    o.dtype = {"f64": FS1_F64, "f32": FS1_F32}[dtype]
+    o.domain = {"plain": FS1_PLAIN, "log": FS1_LOG}[domain]
+    o.check_every = int(check_every)
+    o.sync_every = int(sync_every)
+    return o
+
+
+def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max: int = 10000,
+              dtype: str = "f64", domain: str = "plain", check_every: int = 1,
+              sync_every: int = 16, potentials: bool = False, err_history: bool = False,
+              ctx: Optional[Context] = None, raise_on_error: bool = False) -> Result:
+    """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors)."""
+    import torch
+    ctx = ctx or default_context()
+    n = mu.numel()
+    if nu.numel() != n:
+        raise ValueError("mu and nu must have the same length")
+    o = make_opts(h, itr_max, dtype, domain, check_every, sync_every)
+    pot = hist = None
+    if potentials:
+        pot = torch.empty(2 * n, dtype=torch.float64, device=mu.device)
+        o.flags |= 1
+        o.potentials_out = pot.data_ptr()
+    if err_history:
+        hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)
+        o.err_history = hist.data_ptr()
+    r = CResult()
+    st = load().fs1_solve(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps), float(tol),
+                          ctypes.byref(o), ctypes.byref(r))
+    if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
+            raise_on_error and st != FS1_OK):
+        raise Fs1Error(st, last_error())
+    res = Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), st)
+    if pot is not None and st == FS1_OK:
+        res.F, res.G = pot[:n], pot[n:]
+    if hist is not None:
+        res.err_history = hist
+    return res
+
+
+def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequence[float],
+                      tol: Sequence[float], itr_max: int = 10000, dtype: str = "f64",
+                      domain: str = "log", check_every: int = 1,
+                      ctx: Optional[Context] = None) -> list:
+    """Ragged batch: instance b is [offsets[b], offsets[b+1]) of the packed tensors."""
+    ctx = ctx or default_context()
+    B = len(offsets) - 1
+    offs = (ctypes.c_int64 * (B + 1))(*[int(v) for v in offsets])
+    e = (ctypes.c_double * B)(*[float(v) for v in eps])
+    t = (ctypes.c_double * B)(*[float(v) for v in tol])
+    o = make_opts(None, itr_max, dtype, domain, check_every)
+    res = (CResult * B)()
+    _check(load().fs1_solve_batched(ctx.handle, _dev(mu_packed, "mu"), _dev(nu_packed, "nu"),
+                                    offs, B, e, t, ctypes.byref(o), res))
+    return [Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
+            for r in res]

@@ -1,0 +1,88 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+the binding's struct layouts match the header, and validation fails fast."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2202_10042_amd import fs1
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fs1.h")
+
+
+def _lib():
+    if not os.path.exists(fs1.LIB_PATH):
+        from paper_2202_10042_amd import build
+        build.build()
+    return fs1.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fs1_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    assert set(names) == set(fs1.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", fs1.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (fs1_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fs1.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fs1_opts),
+         offsetof(fs1_opts, itr_max), offsetof(fs1_opts, check_every),
+         offsetof(fs1_opts, flags), offsetof(fs1_opts, potentials_out),
+         offsetof(fs1_opts, err_history), sizeof(fs1_result),
+         offsetof(fs1_result, iterations), offsetof(fs1_result, status),
+         offsetof(fs1_result, mu_err));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    O, R = fs1.Opts, fs1.CResult
+    want = [ctypes.sizeof(O), O.itr_max.offset, O.check_every.offset, O.flags.offset,
+            O.potentials_out.offset, O.err_history.offset, ctypes.sizeof(R),
+            R.iterations.offset, R.status.offset, R.mu_err.offset]
+    assert got == want
+
+
+def test_validation_before_any_launch():
+    lib = _lib()
+    # no context -> invalid argument, no device call
+    st = lib.fs1_kv_apply(None, ctypes.c_void_p(16), ctypes.c_void_p(4096), 10, 0.1, 0.1, 0)
+    assert st == fs1.FS1_ERR_INVALID_ARG
+    assert "context" in fs1.last_error()
+    r = fs1.CResult()
+    st = lib.fs1_solve(None, None, None, 10, 0.1, 0.0, None, ctypes.byref(r))
+    assert st == fs1.FS1_ERR_INVALID_ARG
+    o = fs1.Opts()
+    assert lib.fs1_opts_default(ctypes.byref(o)) == 0
+    assert o.itr_max == 10000 and o.check_every == 1 and o.dtype == 0 and o.domain == 0
+    assert lib.fs1_version().decode().startswith("fs1")
+
+
+def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(fs1, "_lib", None)
+    with pytest.raises(RuntimeError):
+        fs1.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,191 @@
+"""GPU parity of fs1_kv_apply / fs1_kv_apply_log against the CPU oracle.
+
+Tolerances (stated per test): the scan evaluates every output as a sum of
+non-negative (or, for signed x, absolutely bounded) terms through at most a few
+dozen rounding steps (R-step Horner run, 6 wavefront levels, the block and
+chunk levels), so the error is bounded by a small multiple of the unit
+roundoff times |K| |x|:  64 u for binary64, 256 u for binary32 (u = 2^-53,
+2^-24).  For logarithms the bound is absolute: 64 u (1 + |ly|) in binary64 and
+4e-6 + 2 u32 |ly| in binary32 (the binary32 scan error plus the rounding of the
+output).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def _fs1():
+    from paper_2202_10042_amd import fs1
+    return fs1
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a, dt=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=dt, device="cuda")
+
+
+SIZES = [1, 2, 3, 7, 8, 9, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049, 4095, 4096, 4097,
+         8191, 12289, 65537]
+CS = [1e-9, 1e-4, 0.02, 0.7, 5.0, 69.0]
+
+
+def _rows(n, k=97):
+    if n <= 4096:
+        return None
+    r = np.unique(np.concatenate([np.arange(0, 64), np.arange(n - 64, n),
+                                  np.linspace(0, n - 1, k).astype(np.int64)]))
+    return r
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("c", CS)
+def test_kv_plain_parity(dt, c):
+    fs1 = _fs1()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    u = U64 if dt == "f64" else U32
+    tolf = 64 * u if dt == "f64" else 256 * u
+    rng = np.random.default_rng(int(c * 1e6) % 1000)
+    worst = 0.0
+    for n in SIZES:
+        if n * c > 1e8:
+            continue
+        _say(f"kv_plain dt={dt} c={c} n={n}")
+        h = 1.0 / n
+        eps = h / c
+        x = rng.standard_normal(n)
+        if dt == "f32":
+            x = x.astype(np.float32).astype(np.float64)
+        y = fs1.fs1_kv_apply(dev(x, tdt), h, eps).double().cpu().numpy()
+        rows = _rows(n)
+        ref = oracle.kv_dense(x, h, eps, rows=rows)
+        scale = oracle.kv_dense(np.abs(x), h, eps, rows=rows)
+        yy = y if rows is None else y[rows]
+        err = np.max(np.abs(yy - ref) / scale)
+        worst = max(worst, err)
+        assert err <= tolf, (n, err)
+    _say(f"  worst relative error {worst:.3g} (bound {tolf:.3g})")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("c", CS)
+def test_kv_log_parity(dt, c):
+    fs1 = _fs1()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    rng = np.random.default_rng(7 + int(c * 1e6) % 1000)
+    worst = 0.0
+    for n in SIZES:
+        if n * c > 1e8:
+            continue
+        _say(f"kv_log dt={dt} c={c} n={n}")
+        h = 1.0 / n
+        eps = h / c
+        # potentials that grow at up to the decay rate, with zeros (-inf)
+        lx = 10.0 * rng.standard_normal(n) + 0.9 * c * np.arange(n) * rng.choice([-1.0, 1.0])
+        lx[rng.random(n) < 0.1] = -np.inf
+        if dt == "f32":
+            lx = lx.astype(np.float32).astype(np.float64)
+        y = fs1.fs1_kv_apply_log(dev(lx, tdt), h, eps).double().cpu().numpy()
+        rows = _rows(n)
+        ref = oracle.kv_log_dense(lx, h, eps, rows=rows)
+        yy = y if rows is None else y[rows]
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(yy), fin)
+        assert np.all(yy[~fin] == -np.inf)
+        if dt == "f64":
+            tol = 64 * U64 * (1 + np.abs(ref[fin]))
+        else:
+            tol = 4e-6 + 2 * U32 * np.abs(ref[fin])
+        err = np.abs(yy[fin] - ref[fin])
+        worst = max(worst, float(np.max(err / tol)) if err.size else 0.0)
+        assert np.all(err <= tol), (n, float(np.max(err)))
+    _say(f"  worst error / bound {worst:.3g}")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_k_one_closed_form(dt):
+    # (K 1)_k = (2 - lam^k - lam^(N-k+1)) / (1 - lam) - 1 (stability analysis, Sec. 3)
+    fs1 = _fs1()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    u = U64 if dt == "f64" else U32
+    for n, c in [(5000, 0.001), (100003, 1e-5), (777, 2.0)]:
+        _say(f"K1 dt={dt} n={n} c={c}")
+        lam = math.exp(-c)
+        k = np.arange(1, n + 1, dtype=np.float64)
+        ref = (2.0 - (lam ** k + lam ** (n - k + 1))) / (1.0 - lam) - 1.0
+        y = fs1.fs1_kv_apply(torch.ones(n, dtype=tdt, device="cuda"), 1.0 / n, 1.0 / n / c)
+        ly = fs1.fs1_kv_apply_log(torch.zeros(n, dtype=tdt, device="cuda"), 1.0 / n, 1.0 / n / c)
+        np.testing.assert_allclose(y.double().cpu().numpy(), ref, rtol=256 * u)
+        np.testing.assert_allclose(np.exp(ly.double().cpu().numpy()), ref,
+                                   rtol=(256 * u if dt == "f64" else 1e-5))
+
+
+def test_log_special_values():
+    fs1 = _fs1()
+    n = 5000
+    h, eps = 1.0 / n, 1.0 / n / 0.05
+    _say("kv_log all -inf")
+    y = fs1.fs1_kv_apply_log(torch.full((n,), -math.inf, dtype=torch.float64, device="cuda"), h, eps)
+    assert torch.all(y == -math.inf)
+    _say("kv_log single finite entry")
+    lx = np.full(n, -np.inf)
+    lx[1234] = 3.0
+    y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
+    ref = 3.0 - np.abs(np.arange(n) - 1234) * 0.05
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
+    _say("kv_log +inf and NaN propagate")
+    lx = np.zeros(n)
+    lx[10] = np.inf
+    y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
+    assert np.all(y == np.inf)
+    lx[10] = np.nan
+    y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
+    assert np.all(np.isnan(y))
+
+
+def test_kv_invalid_arguments():
+    fs1 = _fs1()
+    x = torch.ones(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x, 0.0, 1.0)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x, 0.1, -1.0)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x, 1.0, 1e-9)        # n h / eps above the exponent budget
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x[1:], 0.1, 0.1)     # misaligned view
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x, 0.1, 0.1, out=x)  # aliasing
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_kv_log_full_size_sampled(eps, dt):
+    # the single-pair workload size N = 2^20, sampled rows against the definition
+    fs1 = _fs1()
+    from paper_2202_10042_amd import inputs
+    n = 1 << 20
+    _say(f"kv_log full size n={n} eps={eps} dt={dt}")
+    h = 1.0 / n
+    mu, nu = inputs.mixture_pair(n, 4, 11)
+    lx = np.log(mu) + np.linspace(-3.0, 5.0, n)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    if dt == "f32":
+        lx = lx.astype(np.float32).astype(np.float64)
+    y = fs1.fs1_kv_apply_log(dev(lx, tdt), h, eps).double().cpu().numpy()
+    rows = _rows(n, 200)
+    ref = oracle.kv_log_dense(lx, h, eps, rows=rows)
+    tol = 64 * U64 * (1 + np.abs(ref)) if dt == "f64" else 4e-6 + 2 * U32 * np.abs(ref)
+    assert np.all(np.abs(y[rows] - ref) <= tol)
