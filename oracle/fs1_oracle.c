@@ -37,6 +37,19 @@
 #define OR_ERR_NONFINITE (-2)
 #define OR_ERR_NO_MEMORY (-4)
 
+/* Compensated (Neumaier) summation.  Every long sum in this file is a sum of
+ * up to ~1e8 terms that the definitions state exactly; accumulating them in
+ * plain binary64 would add an O(n u) error, so they are accumulated with a
+ * running compensation term instead. */
+typedef struct { double s, c; } nsum;
+static void nadd(nsum *a, double t) {
+    double u = a->s + t;
+    if (fabs(a->s) >= fabs(t)) a->c += (a->s - u) + t;
+    else a->c += (t - u) + a->s;
+    a->s = u;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
 /* log(exp(a) + exp(b)) with exp(-inf) = 0; never produces NaN for -inf inputs. */
 static double lse2(double a, double b) {
     if (a == -INFINITY) return b;
@@ -69,12 +82,12 @@ int or_kv_dense_rows(int64_t n, const double *x, double h, double eps,
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < nrows; ++r) {
         int64_t i = rows ? rows[r] : r;
-        double s = 0.0;
+        nsum s = {0.0, 0.0};
         for (int64_t j = 0; j < n; ++j) {
             int64_t d = i > j ? i - j : j - i;
-            s += kd[d] * x[j];
+            nadd(&s, kd[d] * x[j]);
         }
-        y[r] = s;
+        y[r] = nval(&s);
     }
     free(kd);
     return OR_OK;
@@ -99,12 +112,12 @@ int or_kv_log_dense_rows(int64_t n, const double *lx, double h, double eps,
             if (t > m) m = t;
         }
         if (m == -INFINITY) { ly[r] = -INFINITY; continue; }
-        double s = 0.0;
+        nsum s = {0.0, 0.0};
         for (int64_t j = 0; j < n; ++j) {
             double d = (double)(i > j ? i - j : j - i);
-            s += exp(lx[j] - d * c - m);
+            nadd(&s, exp(lx[j] - d * c - m));
         }
-        ly[r] = m + log(s);
+        ly[r] = m + log(nval(&s));
     }
     return OR_OK;
 }
@@ -171,19 +184,21 @@ double or_marginal_err_dense(int64_t n, const double *phi, const double *psi,
                              const double *nu, double h, double eps) {
     double c = h / eps;
     double *kd = kernel_table(n, c);
-    if (!kd) return NAN;
-    double err = 0.0;
-#pragma omp parallel for reduction(+ : err) schedule(static)
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!kd || !row) { free(kd); free(row); return NAN; }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
+        nsum s = {0.0, 0.0};
         for (int64_t j = 0; j < n; ++j) {
             int64_t d = i > j ? i - j : j - i;
-            s += phi[j] * kd[d];
+            nadd(&s, phi[j] * kd[d]);
         }
-        err += fabs(psi[i] * s - nu[i]);
+        row[i] = fabs(psi[i] * nval(&s) - nu[i]);
     }
-    free(kd);
-    return err;
+    nsum err = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nadd(&err, row[i]);
+    free(kd); free(row);
+    return nval(&err);
 }
 
 /* W = sum_{i,j} phi_i psi_j e^{-|i-j|c} |i-j| h  (the value Algorithm 1 returns) */
@@ -191,56 +206,67 @@ double or_cost_dense(int64_t n, const double *phi, const double *psi, double h,
                      double eps) {
     double c = h / eps;
     double *kd = kernel_table(n, c);
-    if (!kd) return NAN;
-    double w = 0.0;
-#pragma omp parallel for reduction(+ : w) schedule(static)
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!kd || !row) { free(kd); free(row); return NAN; }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
+        nsum s = {0.0, 0.0};
         for (int64_t j = 0; j < n; ++j) {
             int64_t d = i > j ? i - j : j - i;
-            s += psi[j] * kd[d] * (double)d * h;
+            nadd(&s, psi[j] * kd[d] * (double)d * h);
         }
-        w += phi[i] * s;
+        row[i] = phi[i] * nval(&s);
     }
-    free(kd);
-    return w;
+    nsum w = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nadd(&w, row[i]);
+    free(kd); free(row);
+    return nval(&w);
 }
 
 /* Log-domain versions of the two sums (phi = e^F, psi = e^G). */
 double or_marginal_err_log_dense(int64_t n, const double *F, const double *G,
                                  const double *nu, double h, double eps) {
     double c = h / eps;
-    double err = 0.0;
-#pragma omp parallel for reduction(+ : err) schedule(static)
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!row) return NAN;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
+        nsum s = {0.0, 0.0};
         if (G[i] != -INFINITY) {
             for (int64_t j = 0; j < n; ++j) {
                 double d = (double)(i > j ? i - j : j - i);
-                if (F[j] != -INFINITY) s += exp(F[j] + G[i] - d * c);
+                if (F[j] != -INFINITY) nadd(&s, exp(F[j] + G[i] - d * c));
             }
         }
-        err += fabs(s - nu[i]);
+        row[i] = fabs(nval(&s) - nu[i]);
     }
-    return err;
+    nsum err = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nadd(&err, row[i]);
+    free(row);
+    return nval(&err);
 }
 
 double or_cost_log_dense(int64_t n, const double *F, const double *G, double h,
                          double eps) {
     double c = h / eps;
-    double w = 0.0;
-#pragma omp parallel for reduction(+ : w) schedule(static)
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!row) return NAN;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        if (F[i] == -INFINITY) continue;
-        double s = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (G[j] == -INFINITY) continue;
-            double d = (double)(i > j ? i - j : j - i);
-            s += exp(F[i] + G[j] - d * c) * d * h;
+        nsum s = {0.0, 0.0};
+        if (F[i] != -INFINITY) {
+            for (int64_t j = 0; j < n; ++j) {
+                if (G[j] == -INFINITY) continue;
+                double d = (double)(i > j ? i - j : j - i);
+                nadd(&s, exp(F[i] + G[j] - d * c) * d * h);
+            }
         }
-        w += s;
+        row[i] = nval(&s);
     }
-    return w;
+    nsum w = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nadd(&w, row[i]);
+    free(row);
+    return nval(&w);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -374,14 +400,15 @@ double or_cost_fs1(int64_t n, const double *phi, const double *psi, double h,
     for (int64_t k = n - 2; k >= 0; --k) q[k] = lam * (q[k + 1] + psi[k + 1]);
     U[n - 1] = 0.0;
     for (int64_t i = n - 1; i >= 1; --i) U[i - 1] = lam * (U[i] + q[i] + psi[i]);
-    double w = 0.0, p = 0.0, L = 0.0;
+    nsum w = {0.0, 0.0};
+    double p = 0.0, L = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         p = (i == 0) ? psi[0] : lam * p + psi[i];
-        w += phi[i] * (L + U[i]);
+        nadd(&w, phi[i] * (L + U[i]));
         L = lam * (L + p);
     }
     free(q); free(U);
-    return w * h;
+    return nval(&w) * h;
 }
 
 double or_marginal_err_fs1(int64_t n, const double *phi, const double *psi,
@@ -389,10 +416,10 @@ double or_marginal_err_fs1(int64_t n, const double *phi, const double *psi,
     double *ktphi = (double *)malloc((size_t)n * sizeof(double));
     if (!ktphi) return NAN;
     or_kv_fs1(n, phi, h, eps, ktphi);
-    double err = 0.0;
-    for (int64_t i = 0; i < n; ++i) err += fabs(psi[i] * ktphi[i] - nu[i]);
+    nsum err = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nadd(&err, fabs(psi[i] * ktphi[i] - nu[i]));
     free(ktphi);
-    return err;
+    return nval(&err);
 }
 
 int or_fs1(int64_t n, const double *mu, const double *nu, double h, double eps,
@@ -441,16 +468,17 @@ double or_cost_fs1_log(int64_t n, const double *F, const double *G, double h,
         double t = lse2(lse2(lU[i], B[i]), G[i]);
         lU[i - 1] = (t == -INFINITY) ? -INFINITY : t - c;
     }
-    double w = 0.0, A = -INFINITY, lL = -INFINITY;
+    nsum w = {0.0, 0.0};
+    double A = -INFINITY, lL = -INFINITY;
     for (int64_t i = 0; i < n; ++i) {
         A = (i == 0) ? G[0] : lse2(A == -INFINITY ? -INFINITY : A - c, G[i]);
         double t = lse2(lL, lU[i]);
-        if (F[i] != -INFINITY && t != -INFINITY) w += exp(F[i] + t);
+        if (F[i] != -INFINITY && t != -INFINITY) nadd(&w, exp(F[i] + t));
         double u = lse2(lL, A);
         lL = (u == -INFINITY) ? -INFINITY : u - c;
     }
     free(B); free(lU);
-    return w * h;
+    return nval(&w) * h;
 }
 
 double or_marginal_err_fs1_log(int64_t n, const double *F, const double *G,
@@ -458,13 +486,13 @@ double or_marginal_err_fs1_log(int64_t n, const double *F, const double *G,
     double *lk = (double *)malloc((size_t)n * sizeof(double));
     if (!lk) return NAN;
     or_kv_fs1_log(n, F, h, eps, lk);
-    double err = 0.0;
+    nsum err = {0.0, 0.0};
     for (int64_t i = 0; i < n; ++i) {
         double v = (G[i] == -INFINITY || lk[i] == -INFINITY) ? 0.0 : exp(G[i] + lk[i]);
-        err += fabs(v - nu[i]);
+        nadd(&err, fabs(v - nu[i]));
     }
     free(lk);
-    return err;
+    return nval(&err);
 }
 
 int or_fs1_log(int64_t n, const double *mu, const double *nu, double h, double eps,
