@@ -88,17 +88,19 @@ const char *fs1_version(void);
 
 /* y_i = sum_j exp(-|i-j| h/eps) x_j,  i = 0..n-1.
  * x, y: device arrays of n elements of dtype dt (double for FS1_F64, float for
- * FS1_F32); any finite sign; must not overlap.  n >= 1; h > 0, eps > 0 finite.
- * Non-finite entries of x propagate as IEEE arithmetic would in the dense
- * product.  Asynchronous on the context stream. */
+ * FS1_F32); any finite sign; must not overlap.  n >= 1; h > 0, eps > 0 finite;
+ * n h / eps <= 1e8.  A non-finite entry of x (inf or NaN) makes the outputs it
+ * reaches non-finite (inf or NaN; which one is unspecified).  Asynchronous on
+ * the context stream. */
 int fs1_kv_apply(fs1_ctx *ctx, const void *x, void *y, int64_t n, double h, double eps,
                  int dt);
 
 /* ly_i = ln sum_j exp(lx_j - |i-j| h/eps): the recursions of eq. (recursion)
  * on logarithms (log-sum-exp semiring), as used by the log-domain stabilised
  * method.  lx, ly: device arrays of n elements of dtype dt; must not overlap.
- * lx may hold -inf (a zero of x); all -inf gives all -inf, never NaN.  +inf or
- * NaN in lx propagate to every output.  |lx_j| must stay below 1e8.
+ * lx may hold -inf (a zero of x); all -inf gives all -inf, never NaN.  A +inf or
+ * NaN entry makes the outputs it reaches non-finite (+inf or NaN, which one is
+ * unspecified).  Finite entries must satisfy |lx_j| < 1e8; n h / eps <= 1e8.
  * Asynchronous on the context stream. */
 int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h,
                      double eps, int dt);

@@ -95,20 +95,22 @@ __device__ __forceinline__ void load_log_run(const T* __restrict__ lx, int64_t b
   double Ed = (tmax == -INFINITY) ? 0.0 : floor(tmax);
   Ed = fmin(fmax(Ed, -4.0e8), 4.0e8);
   E = int(Ed);
+  // 2^(t_j - E) = 2^frac(t_j) * 2^(floor(t_j) - E): only the exact fractional
+  // part goes through the exponential, so entries far below the run maximum
+  // keep their relative precision
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const double d = t[j] - Ed;  // <= 1 for finite entries
-    if constexpr (sizeof(T) == 8) {
-      x[j] = exp2(d);
-    } else {
-      // split so that the binary32 exponential sees only the fraction in [0, 1)
-      if (isfinite(d)) {
-        const double k = floor(d);
-        const float f = float(d - k);
-        x[j] = ldexpf(exp2f(f), int(fmax(k, -400.0)));
+    if (isfinite(t[j])) {
+      const double k = floor(t[j]);
+      const double f = t[j] - k;  // exact, in [0, 1)
+      const int sh = int(fmax(k - Ed, -2000.0));
+      if constexpr (sizeof(T) == 8) {
+        x[j] = ldexp(exp2(f), sh);
       } else {
-        x[j] = float(exp2(d));  // 0, +inf or NaN
+        x[j] = ldexpf(exp2f(float(f)), sh);
       }
+    } else {
+      x[j] = T(exp2(t[j]));  // 0 for -inf; +inf or NaN propagate
     }
   }
 }
@@ -312,19 +314,22 @@ __global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
   T y[R];
   run_apply<T, R>(xf, ldx(cf.v.m, cf.v.e - eref), ldx(cb.v.m, cb.v.e - eref), L, y);
   if constexpr (LOG) {
+    // ln y = (log2 f + k + eref) ln 2 with y = f 2^k, f in [1/2, 1): only the
+    // mantissa goes through the logarithm, so outputs far below the run's
+    // frame keep their absolute precision
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      if constexpr (sizeof(T) == 8) {
-        y[j] = (log2(y[j]) + double(eref)) * kLn2;
-      } else {
-        const float yy = y[j];
-        if (yy > 0.0f && isfinite(yy)) {
-          int ke;
-          const float fm = frexpf(yy, &ke);
-          y[j] = float((double(log2f(fm)) + double(ke) + double(eref)) * kLn2);
+      const T yy = y[j];
+      if (yy > T(0) && isfinite(yy)) {
+        int ke;
+        const T fm = frx(yy, &ke);
+        if constexpr (sizeof(T) == 8) {
+          y[j] = (log2(fm) + double(ke + eref)) * kLn2;
         } else {
-          y[j] = float(log2(double(yy)));  // -inf, +inf or NaN
+          y[j] = float((double(log2f(fm)) + double(ke + eref)) * kLn2);
         }
+      } else {
+        y[j] = T(log2(double(yy)));  // -inf, +inf or NaN
       }
     }
   }
@@ -708,7 +713,13 @@ __global__ __launch_bounds__(256) void k_potentials(const T* __restrict__ v,
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double x = double(v[i]);
     const int e = ex ? ex[i / R] : 0;
-    out[i] = (x > 0.0) ? log(x) + double(e) * kLn2 : (x == 0.0 ? -INFINITY : NAN);
+    if (x > 0.0 && isfinite(x)) {
+      int k;
+      const double f = frexp(x, &k);
+      out[i] = log(f) + double(k + e) * kLn2;
+    } else {
+      out[i] = (x == 0.0) ? -INFINITY : NAN;
+    }
   }
 }
 

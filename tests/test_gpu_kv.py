@@ -122,9 +122,10 @@ def test_k_one_closed_form(dt):
     u = U64 if dt == "f64" else U32
     for n, c in [(5000, 0.001), (100003, 1e-5), (777, 2.0)]:
         _say(f"K1 dt={dt} n={n} c={c}")
-        lam = math.exp(-c)
+        # evaluated with 1 - lam = -expm1(-c), lam^k = exp(-k c) so that the
+        # reference itself is accurate to a few ulp
         k = np.arange(1, n + 1, dtype=np.float64)
-        ref = (2.0 - (lam ** k + lam ** (n - k + 1))) / (1.0 - lam) - 1.0
+        ref = (2.0 - (np.exp(-k * c) + np.exp(-(n - k + 1) * c))) / (-math.expm1(-c)) - 1.0
         y = fs1.fs1_kv_apply(torch.ones(n, dtype=tdt, device="cuda"), 1.0 / n, 1.0 / n / c)
         ly = fs1.fs1_kv_apply_log(torch.zeros(n, dtype=tdt, device="cuda"), 1.0 / n, 1.0 / n / c)
         np.testing.assert_allclose(y.double().cpu().numpy(), ref, rtol=256 * u)
@@ -145,13 +146,17 @@ def test_log_special_values():
     y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
     ref = 3.0 - np.abs(np.arange(n) - 1234) * 0.05
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
-    _say("kv_log +inf and NaN propagate")
+    _say("kv_log +inf and NaN make the outputs non-finite")
     lx = np.zeros(n)
     lx[10] = np.inf
     y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
-    assert np.all(y == np.inf)
+    assert not np.any(np.isfinite(y)) and not np.any(y == -np.inf)
     lx[10] = np.nan
     y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
+    assert np.all(np.isnan(y))
+    x = np.ones(n)
+    x[4000] = np.nan
+    y = fs1.fs1_kv_apply(dev(x), h, eps).cpu().numpy()
     assert np.all(np.isnan(y))
 
 
