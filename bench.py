@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark of the FS-1 hot path on one MI355X.
+
+A step is one full solve of the single-pair log-domain workload: N = 2^20 grid
+points on [0, 1] (h = 1/N), Gaussian-mixture marginals with 3-5 components,
+eps = 1e-3, stop at an L1 marginal error <= 1e-8 or 5000 iterations.  Every step
+runs the whole path: validation and set-up, the half-iteration kernels (scans,
+fused update, stopping-test error), the final marginal errors and the transport
+cost.  Inputs are resident in device memory before the timed region.
+
+Output: one JSON line (stdout).  `value` is grid-points x iterations per second
+over the timed steps.  `roofline` describes the dominant kernel (the
+half-iteration update), timed with HIP events on the solve stream inside the
+timed region.  `cpu_baseline` times the CPU oracle (the sequential FS-1 of
+Algorithm 1 in the log domain, one core) on a bounded sample of the same
+workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
+       python bench.py --copy-calibration   (plain copy of known size, for the
+                                             hardware-counter traffic scale)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s (vendor figure)
+PROFILE_STRIDE = 8             # time the update kernels of every 8th iteration
+N_C2 = 1 << 20
+SEED = 1
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_half_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_10042_amd", "csrc", f)
+                  for f in ("fs1_kernels.hip", "fs1_persist.hip", "fs1_device.h",
+                            "fs1_internal.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype: str, workload: str):
+    """Per-launch HBM/fabric traffic of the half-iteration kernel from the
+    committed counter summary, or None when the kernel changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    e = t.get("entries", {}).get(f"{workload}:{dtype}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def copy_calibration(mib: int = 1024):
+    """Plain device-to-device copy of a known size (read mib MiB, write mib MiB)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    gbs = 2 * n * 8 / dt / 1e9
+    log(f"copy {mib} MiB: {dt * 1e3:.3f} ms, {gbs:.1f} GB/s (read+write)")
+    return gbs
+
+
+def cpu_baseline(mu, nu, h, eps, iters: int):
+    """The CPU oracle as it stands: sequential log-domain FS-1, one core."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=iters)
+    dt = time.perf_counter() - t0
+    return {"value": mu.size * r.iterations / dt, "unit": "grid-points*iterations/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle.fs1_log (sequential log-domain Algorithm 1, binary64) on the "
+                      f"same N={mu.size} eps={eps} inputs, {r.iterations} fixed iterations "
+                      f"(tol 0), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--itr-max", type=int, default=5000)
+    ap.add_argument("--n", type=int, default=N_C2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the N=1e8 eps=1e-4 precision-study solve (f64 and f32)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2202_10042_amd import fs1, inputs
+    if not os.path.exists(fs1.LIB_PATH):
+        from paper_2202_10042_amd import build
+        build.build()
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    n = args.n
+    k = inputs.random_k(SEED)
+    mu_np, nu_np = inputs.mixture_pair(n, k, SEED)
+    h = 1.0 / n
+    mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
+    nu = torch.tensor(nu_np, dtype=torch.float64, device="cuda")
+    ctx = fs1.Context(torch.cuda.current_stream())
+
+    def solve(dtype, eps, itr_max=args.itr_max, tol=args.tol, m=mu, v=nu):
+        return fs1.fs1_solve(m, v, eps, tol, itr_max=itr_max, dtype=dtype, domain="log",
+                             sync_every=64, ctx=ctx)
+
+    log(f"workload: N={n} K={k} eps={args.eps} tol={args.tol} itr_max={args.itr_max} "
+        f"dtype={args.dtype}")
+    for _ in range(args.warmup):
+        r = solve(args.dtype, args.eps)
+        log(f"warmup: iterations {r.iterations} err {r.marginal_err:.3e} w1 {r.w1:.12g}")
+
+    ctx.set_profiling(PROFILE_STRIDE)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    its = 0
+    res = None
+    ev0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = solve(args.dtype, args.eps)
+        its += res.iterations
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kms, klaunch, kbytes = ctx.kernel_stats()
+    ctx.set_profiling(0)
+    if res is None or res.status != 0:
+        print(f"solve failed: {res}", file=sys.stderr)
+        sys.exit(1)
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * its / wall
+    log(f"timed: {args.steps} solves, {its} iterations, {wall:.3f} s wall ({gpu_ms:.1f} ms "
+        f"stream), {ms_per_step:.2f} ms/solve, {value:.4g} grid-pts*it/s, "
+        f"{wall / max(its, 1) * 1e6:.2f} us/iteration")
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    avg_us = kms * 1e3 / klaunch if klaunch else None
+    log(f"half-iteration kernel: {klaunch} launches, avg {avg_us:.2f} us, "
+        f"{achieved:.1f} GB/s algorithmic")
+    workload = "c2"
+    traffic = measured_traffic(args.dtype, workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "fs1::k_half (psi and phi halves)",
+                "avg_launch_us": round(avg_us, 3), "launches": klaunch,
+                "alg_bytes_per_launch": round(kbytes / klaunch)}
+
+    out = {
+        "metric": "grid-points*iterations/s",
+        "value": value,
+        "unit": "grid-points*iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded Gaussian-mixture histograms)",
+        "config": {
+            "workload": "single pair, log-domain stabilised FS-1, N=2^20 uniform grid on "
+                        "[0,1], 3-5 component Gaussian mixtures, eps=1e-3, tol 1e-8, "
+                        "itr_max 5000",
+            "n": n, "eps": args.eps, "tol": args.tol, "itr_max": args.itr_max,
+            "mixture_components": k, "seed": SEED, "domain": "log", "check_every": 1,
+            "iterations_per_solve": res.iterations, "converged": res.converged,
+            "marginal_err": res.marginal_err, "w1": res.w1,
+        },
+        "roofline": roofline,
+    }
+
+    if not args.no_variants:
+        variants = []
+        for dt in ("f64", "f32"):
+            for eps in (1e-3, 1e-4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = solve(dt, eps)
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+                variants.append({"dtype": dt, "eps": eps, "iterations": r.iterations,
+                                 "converged": r.converged, "marginal_err": r.marginal_err,
+                                 "w1": r.w1, "ms": round(w * 1e3, 2),
+                                 "grid_pts_it_per_s": n * r.iterations / w})
+                log(f"variant {dt} eps={eps}: {r.iterations} it, err {r.marginal_err:.3e}, "
+                    f"w1 {r.w1:.12g}, {w * 1e3:.1f} ms")
+        out["variants"] = variants
+
+    if args.large:
+        out["large_n"] = large_n_study(fs1, ctx, inputs, np, torch)
+
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle.fs1_log, {args.cpu_iters} iterations at N={n} ...")
+        out["cpu_baseline"] = cpu_baseline(mu_np, nu_np, h, args.eps, args.cpu_iters)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} grid-pts*it/s")
+
+    print(json.dumps(out), flush=True)
+
+
+def large_n_study(fs1, ctx, inputs, np, torch):
+    """N = 1e8, eps = 1e-4, 2000 iterations, log domain: binary64 and binary32,
+    with the CDF closed form of W1 for reference."""
+    n = 100_000_000
+    mu_np, nu_np = inputs.shifted_noisy_pair(n, 8, 3)
+    w1_cdf = float(np.abs(np.cumsum(mu_np) - np.cumsum(nu_np)).sum() / n)
+    mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
+    nu = torch.tensor(nu_np, dtype=torch.float64, device="cuda")
+    del mu_np, nu_np
+    rows = {}
+    for dt in ("f64", "f32"):
+        ctx.set_profiling(PROFILE_STRIDE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fs1.fs1_solve(mu, nu, 1e-4, 0.0, itr_max=2000, dtype=dt, domain="log",
+                          sync_every=64, ctx=ctx)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        kms, kl, kb = ctx.kernel_stats()
+        ctx.set_profiling(0)
+        rows[dt] = {"iterations": r.iterations, "w1": r.w1, "marginal_err": r.marginal_err,
+                    "s": round(w, 3), "grid_pts_it_per_s": n * r.iterations / w,
+                    "kernel_GBps": kb / (kms * 1e-3) / 1e9 if kms else None,
+                    "kernel_frac_hbm": (kb / (kms * 1e-3) / 1e9) / HBM_PEAK_GBS if kms else None}
+        log(f"large N f{dt}: {r.iterations} it in {w:.2f} s, w1 {r.w1:.12g}, "
+            f"err {r.marginal_err:.3e}, kernel {rows[dt]['kernel_GBps']:.0f} GB/s")
+    rows["w1_cdf"] = w1_cdf
+    rows["rel_w1_f32_vs_f64"] = abs(rows["f32"]["w1"] - rows["f64"]["w1"]) / rows["f64"]["w1"]
+    rows["rel_w1_f64_vs_cdf"] = abs(rows["f64"]["w1"] - w1_cdf) / w1_cdf
+    return rows
+
+
+if __name__ == "__main__":
+    main()

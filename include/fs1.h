@@ -76,6 +76,20 @@ int fs1_ctx_destroy(fs1_ctx *ctx);
 /* Rebind the context to another stream (e.g. the caller's current stream). */
 int fs1_ctx_set_stream(fs1_ctx *ctx, void *stream);
 
+/* Diagnostic timing for benchmarks.  With enable = k > 0, fs1_solve records
+ * HIP events on the context stream just before and after both half-iteration
+ * kernels (the psi = nu / K^T phi and phi = mu / K psi updates) of every k-th
+ * iteration that does work, and accumulates their durations and their
+ * algorithmic bytes (read the vector fed to K, read the marginal, write the
+ * new vector; checked psi-halves also read the old psi and, in binary32 mode,
+ * the binary64 nu).  enable = 0 turns timing off.  Every call resets the
+ * counters.  Results of the solve do not change. */
+int fs1_ctx_set_profiling(fs1_ctx *ctx, int enable);
+/* Accumulated half-iteration kernel time (ms), number of timed launches and
+ * algorithmic bytes since profiling was last enabled.  Any pointer may be NULL. */
+int fs1_ctx_kernel_stats(fs1_ctx *ctx, double *total_ms, int64_t *launches,
+                         double *alg_bytes);
+
 /* Thread-local message describing the last failure on this host thread. */
 const char *fs1_last_error(void);
 /* Library version string. */
@@ -114,6 +128,9 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 /*   w1 = sum_{i,j} phi_i psi_j lambda^{|i-j|} |i-j| h.                      */
 /* ------------------------------------------------------------------------ */
 
+#define FS1_FLAG_POTENTIALS 1
+#define FS1_FLAG_STREAMING 2
+
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
     int32_t itr_max;      /* iteration cap; < 0 selects 10000                       */
@@ -124,7 +141,10 @@ typedef struct {
                              past the first point where err <= tol)               */
     int32_t sync_every;   /* host polls the device stop flag every s iterations
                              (performance only; results do not depend on it)      */
-    int32_t flags;        /* bit 0: return potentials (see potentials_out)          */
+    int32_t flags;        /* bit 0 (FS1_FLAG_POTENTIALS): return potentials (see
+                             potentials_out); bit 1 (FS1_FLAG_STREAMING): never use
+                             the single-launch persistent solver (every half-
+                             iteration is its own launch)                         */
     double *potentials_out; /* device, 2n doubles: F = ln phi (n), then G = ln psi
                              (n), written when flags bit 0 is set; -inf where the
                              scaling is zero                                        */

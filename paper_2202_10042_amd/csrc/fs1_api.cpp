@@ -29,6 +29,12 @@ struct fs1_ctx {
   char* ws = nullptr;      // device workspace
   size_t ws_size = 0;
   Ctrl* hctrl = nullptr;   // pinned host mirror of the control block
+  // diagnostic timing of the half-iteration kernel (fs1_ctx_set_profiling)
+  int profiling = 0;
+  std::vector<hipEvent_t> events;  // 4 per iteration of one polling batch
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  double prof_bytes = 0.0;
 };
 
 namespace {
@@ -170,6 +176,7 @@ int fs1_ctx_create(void* stream, fs1_ctx** out) {
 int fs1_ctx_destroy(fs1_ctx* c) {
   if (!c) return FS1_OK;
   (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hctrl) (void)hipHostFree(c->hctrl);
   delete c;
@@ -179,6 +186,23 @@ int fs1_ctx_destroy(fs1_ctx* c) {
 int fs1_ctx_set_stream(fs1_ctx* c, void* stream) {
   if (!c) return set_err(FS1_ERR_INVALID_ARG, "null context");
   c->stream = static_cast<hipStream_t>(stream);
+  return FS1_OK;
+}
+
+int fs1_ctx_set_profiling(fs1_ctx* c, int enable) {
+  if (!c) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  c->profiling = enable > 0 ? enable : 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  c->prof_bytes = 0.0;
+  return FS1_OK;
+}
+
+int fs1_ctx_kernel_stats(fs1_ctx* c, double* total_ms, int64_t* launches, double* alg_bytes) {
+  if (!c) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (total_ms) *total_ms = c->prof_ms;
+  if (launches) *launches = c->prof_launches;
+  if (alg_bytes) *alg_bytes = c->prof_bytes;
   return FS1_OK;
 }
 
@@ -249,6 +273,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // workspace layout
   SolveBufs b{};
+  unsigned* bar = nullptr;
   auto layout = [&](Carve& w) {
     b.vF = w.take(n * es);
     b.vG[0] = w.take(n * es);
@@ -266,6 +291,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
+    bar = static_cast<unsigned*>(w.take(2 * sizeof(unsigned)));
   };
   {
     Carve probe(nullptr);
@@ -305,19 +331,89 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
   HIP_TRY(launch_init_state(b, k, s));
 
+  // diagnostic timing: events around every half-iteration kernel of a batch
+  const bool prof = ctx->profiling != 0;
+  if (prof && ctx->events.size() < size_t(4 * o.sync_every + 4)) {
+    while (ctx->events.size() < size_t(4 * o.sync_every + 4)) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      ctx->events.push_back(e);
+    }
+  }
+  // algorithmic bytes of one half-iteration kernel: read the vector fed to K,
+  // read the marginal, write the new vector; a checked psi-half also reads the
+  // old psi and the binary64 nu
+  const double bytes_half = double(n) * 3.0 * double(es);
+  const double bytes_check = double(n) * (double(es) + (dt == FS1_F64 ? 0.0 : 8.0));
+
+  // Mid-size grids whose vectors fit in the registers of the co-resident
+  // workgroups run all iterations in one cooperative launch.
+  const bool persistent = !(o.flags & FS1_FLAG_STREAMING) && usable_persistent(b, h / eps);
+  if (persistent) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+      e0 = ctx->events[0];
+      e1 = ctx->events[1];
+      HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), s));
+    HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, bar, s));
+    if (prof) HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc->barrier_timeout)
+      return finish(set_err(FS1_ERR_INTERNAL, "persistent solve: grid barrier timed out"));
+    if (prof) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const int its = hc->fail ? hc->fail_iter : hc->iters_done;
+      ctx->prof_ms += ms;
+      ctx->prof_launches += 1;
+      // per iteration: two halves, plus the checked psi-halves' extra reads
+      const int checks = its > 0 ? (its - 1) / o.check_every + 1 : 0;
+      ctx->prof_bytes += 2.0 * bytes_half * its + bytes_check * checks;
+    }
+  }
+
   // Algorithm 1: while l < itr_max and err(l) > tol
-  int l = 0;
-  bool stopped = false;
+  int l = persistent ? o.itr_max : 0;
+  bool stopped = persistent;
   while (l < o.itr_max && !stopped) {
+    const int l0 = l;
     const int l_end = std::min(o.itr_max, l + o.sync_every);
     for (; l < l_end; ++l) {
       const int check = (l % o.check_every) == 0;
-      HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s));
-      HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s));
+      // sampled: events only on every `profiling`-th iteration
+      hipEvent_t* ev = (prof && (l % ctx->profiling) == 0) ? &ctx->events[4 * (l - l0)] : nullptr;
+      HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s, ev ? ev[0] : nullptr,
+                              ev ? ev[1] : nullptr));
+      HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s, ev ? ev[2] : nullptr,
+                              ev ? ev[3] : nullptr));
     }
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stopped = hc->done != 0;
+    if (prof) {
+      // count only kernels that did their work: the psi-half runs up to and
+      // including the stopping iteration, the phi-half stops one short
+      const int last = (stopped && hc->stop_iter >= 0) ? hc->stop_iter : l - 1;
+      for (int i = l0; i < l; ++i) {
+        float ms = 0.0f;
+        if ((i % ctx->profiling) != 0) continue;
+        if (i <= last) {
+          HIP_TRY(hipEventElapsedTime(&ms, ctx->events[4 * (i - l0)], ctx->events[4 * (i - l0) + 1]));
+          ctx->prof_ms += ms;
+          ctx->prof_launches += 1;
+          ctx->prof_bytes += bytes_half + ((i % o.check_every) == 0 ? bytes_check : 0.0);
+        }
+        if (i < last || (!stopped && i == last)) {
+          HIP_TRY(hipEventElapsedTime(&ms, ctx->events[4 * (i - l0) + 2], ctx->events[4 * (i - l0) + 3]));
+          ctx->prof_ms += ms;
+          ctx->prof_launches += 1;
+          ctx->prof_bytes += bytes_half;
+        }
+      }
+    }
   }
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -330,7 +426,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
   int l_final = o.itr_max;
   if (hc->done && hc->stop_iter >= 0) l_final = hc->stop_iter;
-  const int gbuf = l_final & 1;
+  // the persistent kernel leaves its final psi in buffer 0
+  const int gbuf = persistent ? 0 : (l_final & 1);
 
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));

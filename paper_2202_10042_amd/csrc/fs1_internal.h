@@ -64,7 +64,10 @@ struct Ctrl {
   int fail;          // a scaling became non-finite
   int fail_iter;     // first iteration whose update produced a non-finite value
   int last_check;    // last iteration whose error was evaluated (-1 if none)
-  int pad[3];
+  int barrier_timeout;  // persistent solve: a grid barrier wait gave up
+  int iters_done;    // persistent solve: completed iterations at exit
+  int fail_half[2];  // persistent solve: failure seen in a psi-half [0] / phi-half [1]
+  int pad;
   double last_err;   // err at last_check
   double w1;         // transport cost (finalisation)
   double err_final;  // nu-side marginal error (finalisation)
@@ -121,16 +124,26 @@ struct SolveBufs {
   double* err_hist;   // optional (itr_max + 1)
 };
 
+// Persistent solve (all iterations in one cooperative launch; state kept in
+// registers).  usable_persistent() tells whether the configuration fits.
+bool usable_persistent(const SolveBufs& b, double c);
+hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_max,
+                             int check_every, double tol, unsigned* bar, hipStream_t s);
+
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
 hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
 // psi-half of iteration l: psi^{l+1} = nu / (K^T phi^l); error of (phi^l, psi^l)
 // when `check`.
+// ev0 / ev1 (optional): events recorded just before and just after the
+// half-iteration kernel itself (diagnostic timing).
 hipError_t launch_half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
-                           int l, int check, double tol, hipStream_t s);
+                           int l, int check, double tol, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // phi-half of iteration l: phi^{l+1} = mu / (K psi^{l+1}); finalises the error of
 // iteration l (when checked) and sets the stop flag.
 hipError_t launch_half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
-                           int l, int check, double tol, hipStream_t s);
+                           int l, int check, double tol, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Final marginal errors and transport cost of (phi, psi = vG[gbuf]).
 hipError_t launch_finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
                            int gbuf, double h, hipStream_t s);

@@ -76,109 +76,6 @@ int pick_run_length(int dtype, bool absorb, double c) {
 }
 
 // ===========================================================================
-// Device helpers
-// ===========================================================================
-enum InMode { IN_PLAIN = 0, IN_SCALED = 1, IN_LOG = 2 };
-
-template <typename T, int R>
-__device__ __forceinline__ void load_log_run(const T* __restrict__ lx, int64_t base, int64_t n,
-                                             T (&x)[R], int& E) {
-  T raw[R];
-  load_run<T, R>(lx, base, n, raw, T(-INFINITY));
-  double t[R];
-  double tmax = -INFINITY;
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    t[j] = double(raw[j]) * kLog2E;
-    if (isfinite(t[j])) tmax = fmax(tmax, t[j]);
-  }
-  double Ed = (tmax == -INFINITY) ? 0.0 : floor(tmax);
-  Ed = fmin(fmax(Ed, -4.0e8), 4.0e8);
-  E = int(Ed);
-  // 2^(t_j - E) = 2^frac(t_j) * 2^(floor(t_j) - E): only the exact fractional
-  // part goes through the exponential, so entries far below the run maximum
-  // keep their relative precision
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    if (isfinite(t[j])) {
-      const double k = floor(t[j]);
-      const double f = t[j] - k;  // exact, in [0, 1)
-      const int sh = int(fmax(k - Ed, -2000.0));
-      if constexpr (sizeof(T) == 8) {
-        x[j] = ldexp(exp2(f), sh);
-      } else {
-        x[j] = ldexpf(exp2f(float(f)), sh);
-      }
-    } else {
-      x[j] = T(exp2(t[j]));  // 0 for -inf; +inf or NaN propagate
-    }
-  }
-}
-
-template <typename T, int R, int IN>
-__device__ __forceinline__ void load_input(const T* __restrict__ v, const int* __restrict__ ex,
-                                           int64_t run, int64_t n, T (&x)[R], int& E) {
-  const int64_t base = run * R;
-  if constexpr (IN == IN_LOG) {
-    load_log_run<T, R>(v, base, n, x, E);
-  } else {
-    load_run<T, R>(v, base, n, x, T(0));
-    E = (IN == IN_SCALED) ? ex[run] : 0;
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void run_aggs(const T (&x)[R], const Lam<T>& L, T& af, T& ab) {
-  T a = T(0), b = T(0);
-#pragma unroll
-  for (int j = 0; j < R; ++j) a = L.axpy(a, x[j]);
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) b = L.axpy(b, x[j]);
-  af = a;
-  ab = b;
-}
-
-template <typename T>
-__device__ __forceinline__ void lane_decays(const ScanConsts& k, Dec<T> (&dec)[7]) {
-#pragma unroll
-  for (int s = 0; s < 7; ++s) dec[s] = dec_of<T>(k.lane[s], double(k.R) * double(1 << s));
-}
-
-// Largest exponent of the local values: values < 2^eloc.
-template <typename T, int R>
-__device__ __forceinline__ int local_exponent(const T (&x)[R], int E) {
-  T mx = T(0);
-#pragma unroll
-  for (int j = 0; j < R; ++j) mx = fmax(mx, x[j]);
-  if (!(mx > T(0))) return kExpZero;
-  if (!isfinite(mx)) return E;
-  int k;
-  frx(mx, &k);
-  return E + k;
-}
-
-// Both recursions of eq. (recursion) over one run, in the run's frame:
-// y_k = p_k + q_k with p fed by cf (state before the run) and q by cb
-// (inclusive backward state after the run).
-template <typename T, int R>
-__device__ __forceinline__ void run_apply(const T (&xf)[R], T cf, T cb, const Lam<T>& L,
-                                          T (&y)[R]) {
-  T A = cf;
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    A = L.axpy(A, xf[j]);
-    y[j] = A;
-  }
-  T P = cb;
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    const T B = L.mul(P);
-    y[j] += B;
-    P = B + xf[j];
-  }
-}
-
-// ===========================================================================
 // k_agg: chunk aggregates of a vector
 // ===========================================================================
 template <typename T, int R, int IN>
@@ -689,6 +586,10 @@ __global__ __launch_bounds__(256) void k_init(T* __restrict__ vf, T* __restrict_
     ctrl->fail_iter = INT_MAX;
     ctrl->last_check = -1;
     ctrl->last_err = NAN;
+    ctrl->barrier_timeout = 0;
+    ctrl->iters_done = 0;
+    ctrl->fail_half[0] = 0;
+    ctrl->fail_half[1] = 0;
   }
 }
 
@@ -825,19 +726,25 @@ struct SolveOps {
     return a;
   }
   static hipError_t half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
-                             int l, int check, double tol, hipStream_t s) {
+                             int l, int check, double tol, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
     k_carry<1><<<1, kCarryBlock, 0, s>>>(b.aggF, b.carry, kc, b.ctrl, nullptr, nullptr, l, 0,
                                          tol);
+    if (ev0) (void)hipEventRecord(ev0, s);
     k_half<T, R, AB, MODE_PSI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
         args(b, MODE_PSI, l, check, 0), k);
+    if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
   }
   static hipError_t half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
-                             int l, int check, double tol, hipStream_t s) {
+                             int l, int check, double tol, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
     k_carry<2><<<1, kCarryBlock, 0, s>>>(b.aggG, b.carry, kc, b.ctrl, b.part, b.err_hist, l,
                                          check, tol);
+    if (ev0) (void)hipEventRecord(ev0, s);
     k_half<T, R, AB, MODE_PHI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
         args(b, MODE_PHI, l, check, 0), k);
+    if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
   }
   static hipError_t finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
@@ -933,13 +840,17 @@ hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_
 }
 
 hipError_t launch_half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc, int l,
-                           int check, double tol, hipStream_t s) {
-  return dispatch(b, [&](auto ops) { return decltype(ops)::half_psi(b, k, kc, l, check, tol, s); });
+                           int check, double tol, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  return dispatch(
+      b, [&](auto ops) { return decltype(ops)::half_psi(b, k, kc, l, check, tol, s, ev0, ev1); });
 }
 
 hipError_t launch_half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc, int l,
-                           int check, double tol, hipStream_t s) {
-  return dispatch(b, [&](auto ops) { return decltype(ops)::half_phi(b, k, kc, l, check, tol, s); });
+                           int check, double tol, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  return dispatch(
+      b, [&](auto ops) { return decltype(ops)::half_phi(b, k, kc, l, check, tol, s, ev0, ev1); });
 }
 
 hipError_t launch_finalize(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,

@@ -31,12 +31,14 @@ FS1_F64 = 0
 FS1_F32 = 1
 FS1_PLAIN = 0
 FS1_LOG = 1
+FS1_FLAG_POTENTIALS = 1
+FS1_FLAG_STREAMING = 2
 
 # every symbol include/fs1.h declares
 EXPORTS = (
-    "fs1_ctx_create", "fs1_ctx_destroy", "fs1_ctx_set_stream", "fs1_last_error",
-    "fs1_version", "fs1_kv_apply", "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve",
-    "fs1_solve_batched",
+    "fs1_ctx_create", "fs1_ctx_destroy", "fs1_ctx_set_stream", "fs1_ctx_set_profiling",
+    "fs1_ctx_kernel_stats", "fs1_last_error", "fs1_version", "fs1_kv_apply",
+    "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
 )
 
 
@@ -104,6 +106,11 @@ def load(path: str = LIB_PATH):
     lib.fs1_ctx_destroy.restype = ctypes.c_int
     lib.fs1_ctx_set_stream.argtypes = [vp, vp]
     lib.fs1_ctx_set_stream.restype = ctypes.c_int
+    lib.fs1_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.fs1_ctx_set_profiling.restype = ctypes.c_int
+    lib.fs1_ctx_kernel_stats.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64),
+                                         ctypes.POINTER(d)]
+    lib.fs1_ctx_kernel_stats.restype = ctypes.c_int
     lib.fs1_last_error.argtypes = []
     lib.fs1_last_error.restype = ctypes.c_char_p
     lib.fs1_version.argtypes = []
@@ -151,6 +158,17 @@ class Context:
     def set_stream(self, stream):
         self._stream_obj = stream
         _check(load().fs1_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_profiling(self, stride: int):
+        """Time the half-iteration kernels of every `stride`-th iteration (0: off)."""
+        _check(load().fs1_ctx_set_profiling(self.handle, int(stride)))
+
+    def kernel_stats(self):
+        """(total ms, launches, algorithmic bytes) of timed half-iteration kernels."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(load().fs1_ctx_kernel_stats(self.handle, ctypes.byref(ms), ctypes.byref(n),
+                                           ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def close(self):
         if getattr(self, "handle", None):
@@ -232,18 +250,24 @@ def make_opts(h: Optional[float] = None, itr_max: int = 10000, dtype: str = "f64
 def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max: int = 10000,
               dtype: str = "f64", domain: str = "plain", check_every: int = 1,
               sync_every: int = 16, potentials: bool = False, err_history: bool = False,
-              ctx: Optional[Context] = None, raise_on_error: bool = False) -> Result:
-    """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors)."""
+              streaming: bool = False, ctx: Optional[Context] = None,
+              raise_on_error: bool = False) -> Result:
+    """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
+
+    streaming=True forbids the single-launch persistent solver (every
+    half-iteration is then its own kernel launch)."""
     import torch
     ctx = ctx or default_context()
     n = mu.numel()
     if nu.numel() != n:
         raise ValueError("mu and nu must have the same length")
     o = make_opts(h, itr_max, dtype, domain, check_every, sync_every)
+    if streaming:
+        o.flags |= FS1_FLAG_STREAMING
     pot = hist = None
     if potentials:
         pot = torch.empty(2 * n, dtype=torch.float64, device=mu.device)
-        o.flags |= 1
+        o.flags |= FS1_FLAG_POTENTIALS
         o.potentials_out = pot.data_ptr()
     if err_history:
         hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)

@@ -40,19 +40,25 @@ def _pot_close(got, ref_lin, mask, atol):
     assert np.max(np.abs(g - ref)) <= atol, float(np.max(np.abs(g - ref)))
 
 
+# "persistent" = the default choice (the log domain runs the single-launch
+# solver when it fits); "streaming" forbids it
+PATHS = ["persistent", "streaming"]
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("domain", ["plain", "log"])
 @pytest.mark.parametrize("n,seed,its", [(1000, 1, 5), (1000, 2, 60), (1, 0, 3), (2, 0, 4),
                                         (2049, 3, 25), (4097, 4, 25), (10001, 5, 12)])
-def test_solve_f64_fixed_iterations(domain, n, seed, its):
+def test_solve_f64_fixed_iterations(domain, n, seed, its, path):
     fs1 = _fs1()
-    _say(f"solve f64 {domain} n={n} seed={seed} its={its}")
+    _say(f"solve f64 {domain} n={n} seed={seed} its={its} {path}")
     mu, nu = inputs.mixture_pair(n, 2, seed) if n > 2 else (np.array([0.3, 0.7][:n]) / sum([0.3, 0.7][:n]), np.array([0.6, 0.4][:n]) / sum([0.6, 0.4][:n]))
     h = 1.0 / n
     eps = 0.01
     ref = oracle.fs1(mu, nu, h, eps, tol=0.0, itr_max=its) if n > 2000 else \
         oracle.sinkhorn_dense(mu, nu, h, eps, tol=0.0, itr_max=its)
     r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f64", domain=domain,
-                      potentials=True)
+                      potentials=True, streaming=(path == "streaming"))
     # (for n = 1 the initial error is exactly 0 and Algorithm 1 stops at once)
     assert r.status == 0 and r.iterations == ref.iterations
     assert r.w1 == pytest.approx(ref.w1, rel=1e-10, abs=1e-300)
@@ -64,17 +70,19 @@ def test_solve_f64_fixed_iterations(domain, n, seed, its):
     _pot_close(G, ref.b, nu > 0, 1e-9)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("domain", ["plain", "log"])
-def test_solve_c1_to_tolerance(domain):
+def test_solve_c1_to_tolerance(domain, path):
     # single pair, N = 1000, eps = 0.01, tol 1e-9 (stop on the nu-side L1 error)
     fs1 = _fs1()
     n = 1000
     h = 1.0 / n
     for seed in (1, 2, 4):
-        _say(f"solve C1 to tol {domain} seed={seed}")
+        _say(f"solve C1 to tol {domain} seed={seed} {path}")
         mu, nu = inputs.mixture_pair(n, 2, seed)
         ref = oracle.sinkhorn_dense(mu, nu, h, 0.01, tol=1e-9, itr_max=2000)
-        r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-9, itr_max=2000, domain=domain)
+        r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-9, itr_max=2000, domain=domain,
+                          streaming=(path == "streaming"))
         assert r.status == 0 and r.converged and ref.converged
         # the stopping iteration may differ by one where err(l) is within rounding of tol
         assert abs(r.iterations - ref.iterations) <= 1
@@ -85,15 +93,16 @@ def test_solve_c1_to_tolerance(domain):
         assert r.marginal_err <= 1e-9
 
 
-def test_solve_log_f32_against_f64_oracle():
+@pytest.mark.parametrize("path", PATHS)
+def test_solve_log_f32_against_f64_oracle(path):
     fs1 = _fs1()
     for n, eps, its in [(1000, 0.01, 80), (20000, 1e-3, 40), (4099, 3e-3, 30)]:
-        _say(f"solve f32 log n={n} eps={eps} its={its}")
+        _say(f"solve f32 log n={n} eps={eps} its={its} {path}")
         mu, nu = inputs.mixture_pair(n, 3, 21)
         h = 1.0 / n
         ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
         r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
-                          potentials=True)
+                          potentials=True, streaming=(path == "streaming"))
         assert r.status == 0
         assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
         m = nu > 0
@@ -164,13 +173,16 @@ def test_solve_invalid_marginals():
         fs1.fs1_solve(dev(np.zeros(n)), dev(np.zeros(n)), 0.01, 0.0, itr_max=2)
 
 
-def test_error_history_and_check_interval():
+@pytest.mark.parametrize("path", PATHS)
+def test_error_history_and_check_interval(path):
     fs1 = _fs1()
+    st = path == "streaming"
     n = 400
     mu, nu = inputs.mixture_pair(n, 2, 7)
     h = 1.0 / n
-    _say("error history")
-    r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 0.0, itr_max=12, domain="log", err_history=True)
+    _say(f"error history {path}")
+    r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 0.0, itr_max=12, domain="log", err_history=True,
+                      streaming=st)
     hist = r.err_history.cpu().numpy()
     for l in range(12):
         ref = oracle.fs1(mu, nu, h, 0.01, tol=0.0, itr_max=l).marginal_err
@@ -178,27 +190,49 @@ def test_error_history_and_check_interval():
     assert np.isnan(hist[12])
     # the result does not depend on the host polling interval; with check_every
     # k the stop happens at the first multiple of k with err <= tol
-    base = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log")
+    base = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", streaming=st)
     for se in (1, 5, 64):
-        r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", sync_every=se)
+        r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", sync_every=se,
+                          streaming=st)
         assert r.iterations == base.iterations and r.w1 == base.w1
-    r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", check_every=7)
+    r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", check_every=7,
+                      streaming=st)
     assert r.iterations % 7 == 0 and base.iterations <= r.iterations < base.iterations + 7
 
 
-def test_solve_deterministic():
+@pytest.mark.parametrize("path", PATHS)
+def test_solve_deterministic(path):
     fs1 = _fs1()
     n = 70001
     mu, nu = inputs.mixture_pair(n, 4, 3)
-    _say("determinism")
-    a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True)
-    b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True)
+    st = path == "streaming"
+    _say(f"determinism {path}")
+    a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True,
+                      streaming=st)
+    b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True,
+                      streaming=st)
     assert a.w1 == b.w1 and a.marginal_err == b.marginal_err
     assert torch.equal(a.F, b.F) and torch.equal(a.G, b.G)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_persistent_matches_streaming(dtype):
+    # the two solvers differ only in the in-chunk arithmetic (frame vs extended
+    # range), so they agree to rounding
+    fs1 = _fs1()
+    n = 300007
+    mu, nu = inputs.mixture_pair(n, 5, 8)
+    _say(f"persistent vs streaming {dtype}")
+    a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 1e-7, itr_max=800, domain="log", dtype=dtype)
+    b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 1e-7, itr_max=800, domain="log", dtype=dtype,
+                      streaming=True)
+    assert abs(a.iterations - b.iterations) <= 1
+    assert a.w1 == pytest.approx(b.w1, rel=1e-11 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("eps", [1e-3, 1e-4])
-def test_solve_full_size_f64_log(eps):
+def test_solve_full_size_f64_log(eps, path):
     # N = 2^20 (the single-pair workload), 6 iterations: the sequential FS-1
     # oracle in the log domain (its own recursion drifts by ~1e-11 in ln K)
     fs1 = _fs1()
@@ -208,12 +242,15 @@ def test_solve_full_size_f64_log(eps):
     h = 1.0 / n
     _say(f"full size f64 log eps={eps}")
     ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
-    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, domain="log", potentials=True)
+    st = path == "streaming"
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, domain="log", potentials=True,
+                      streaming=st)
     assert r.status == 0
     assert r.w1 == pytest.approx(ref.w1, rel=1e-9)
     assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6)
     G = r.G.cpu().numpy()
     assert np.max(np.abs(G - ref.b)) <= 1e-8
     _say(f"full size f32 log eps={eps}")
-    r32 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log")
+    r32 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
+                        streaming=st)
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
