@@ -38,8 +38,8 @@ N_C2 = 1 << 20
 SEED = 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_half_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_10042_amd", "csrc", f)
-                  for f in ("fs1_kernels.hip", "fs1_persist.hip", "fs1_device.h",
-                            "fs1_internal.h")]
+                  for f in ("fs1_kernels.hip", "fs1_fused.hip", "fs1_persist.hip",
+                            "fs1_device.h", "fs1_frame.h", "fs1_internal.h")]
 
 
 def log(*a):

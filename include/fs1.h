@@ -129,7 +129,8 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 /* ------------------------------------------------------------------------ */
 
 #define FS1_FLAG_POTENTIALS 1
-#define FS1_FLAG_STREAMING 2
+#define FS1_FLAG_GENERAL 2
+#define FS1_FLAG_PERSISTENT 4
 
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
@@ -142,9 +143,15 @@ typedef struct {
     int32_t sync_every;   /* host polls the device stop flag every s iterations
                              (performance only; results do not depend on it)      */
     int32_t flags;        /* bit 0 (FS1_FLAG_POTENTIALS): return potentials (see
-                             potentials_out); bit 1 (FS1_FLAG_STREAMING): never use
-                             the single-launch persistent solver (every half-
-                             iteration is its own launch)                         */
+                             potentials_out).  Solver selection (results agree to
+                             rounding; FS1_LOG only): by default a grid of at most
+                             4096 chunks whose chunk frame fits the working
+                             precision runs one fused kernel per half-iteration;
+                             bit 1 (FS1_FLAG_GENERAL) forces the general path
+                             (extended-range scans, separate carry kernel);
+                             bit 2 (FS1_FLAG_PERSISTENT) asks for the single-launch
+                             persistent solver when the grid fits in the registers
+                             of the co-resident workgroups                       */
     double *potentials_out; /* device, 2n doubles: F = ln phi (n), then G = ln psi
                              (n), written when flags bit 0 is set; -inf where the
                              scaling is zero                                        */

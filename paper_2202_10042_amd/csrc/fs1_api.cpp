@@ -348,7 +348,9 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // Mid-size grids whose vectors fit in the registers of the co-resident
   // workgroups run all iterations in one cooperative launch.
-  const bool persistent = !(o.flags & FS1_FLAG_STREAMING) && usable_persistent(b, h / eps);
+  const bool persistent = (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
+  const bool fused = !persistent && !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+  if (fused) HIP_TRY(launch_fused_init(b, k, s));
   if (persistent) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
@@ -385,10 +387,17 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
       const int check = (l % o.check_every) == 0;
       // sampled: events only on every `profiling`-th iteration
       hipEvent_t* ev = (prof && (l % ctx->profiling) == 0) ? &ctx->events[4 * (l - l0)] : nullptr;
-      HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s, ev ? ev[0] : nullptr,
-                              ev ? ev[1] : nullptr));
-      HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s, ev ? ev[2] : nullptr,
-                              ev ? ev[3] : nullptr));
+      if (fused) {
+        HIP_TRY(launch_fused_half(b, k, l, check, tol, true, s, ev ? ev[0] : nullptr,
+                                  ev ? ev[1] : nullptr));
+        HIP_TRY(launch_fused_half(b, k, l, check, tol, false, s, ev ? ev[2] : nullptr,
+                                  ev ? ev[3] : nullptr));
+      } else {
+        HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s, ev ? ev[0] : nullptr,
+                                ev ? ev[1] : nullptr));
+        HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s, ev ? ev[2] : nullptr,
+                                ev ? ev[3] : nullptr));
+      }
     }
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -1,0 +1,269 @@
+// fs1_fused.hip -- one kernel launch per half-iteration of Algorithm 1.
+//
+// Each workgroup owns one chunk.  A launch of k_fused
+//   * takes the stop decision of Algorithm 1 for the current iteration (every
+//     workgroup sums the previous launch's per-chunk error shares in the same
+//     fixed order, so all of them decide alike),
+//   * recomputes its chunk carries from the chunk aggregates the previous
+//     launch published (the whole workgroup, extended range; the aggregates
+//     are loaded at kernel start so the loads overlap the chunk's scans),
+//   * runs the in-chunk recursions of Sec. 3, eq. (recursion) on a per-chunk
+//     frame (fs1_frame.h) and the Sinkhorn update of Sec. 2
+//     (psi = nu / K^T phi, or phi = mu / K psi),
+//   * writes its share of the stopping error (psi-half of checked iterations),
+//   * publishes the chunk aggregates of the new vector for the next launch.
+// Kernel boundaries order everything: no inter-workgroup waiting.
+#include "fs1_device.h"
+#include "fs1_frame.h"
+#include "fs1_internal.h"
+
+namespace fs1 {
+
+namespace {
+
+constexpr int kCarryMax = 8;                      // chunks per carry thread
+constexpr int kMaxFusedChunks = kCarryMax * kBlock / 2;  // 1024
+constexpr double kFrameLog2Span64 = 900.0;
+constexpr double kFrameLog2Span32 = 80.0;
+
+enum FusedMode { F_PSI = 0, F_PHI = 1, F_ERR = 2 };
+
+struct FusedArgs {
+  const void* vin;        // vector fed to K (values, per-run exponents)
+  const int* ein;
+  const double* m64;      // marginal, binary64 (error; update when T = double)
+  const float* m32;       // marginal, binary32 (update when T = float)
+  void* vout;             // updated vector
+  int* eout;
+  const void* vown;       // own vector of the error term
+  const int* eown;
+  const ChunkAgg* A_in;   // chunk aggregates of vin
+  ChunkAgg* A_out;        // chunk aggregates of vout
+  double* part;           // per-chunk error shares
+  Ctrl* ctrl;
+  double* err_hist;
+  int64_t n;
+  int nchunks;
+  int l;
+  int check;
+  double tol;
+  Decay cpow[20];         // lambda^(chunk length * 2^s)
+};
+
+template <typename T, int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
+  __shared__ T sf[kNW];
+  __shared__ T sb[kNW];
+  __shared__ int smax[kNW];
+  __shared__ double red[kNW];
+  __shared__ XF64 scar[2];
+  __shared__ XF64 red4[kNW];
+  __shared__ int sdec;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t base = run * R;
+  const int64_t n = a.n;
+  const bool want_err = (MODE == F_ERR) || (MODE == F_PSI && a.check);
+
+  // Every global load of the launch is issued here, before any use, so the
+  // launch pays one memory round trip instead of one per phase.
+  // The stop and failure flags were written by earlier launches (kernel
+  // boundaries order them), so one plain load per workgroup suffices.
+  int done = 0, fail = 0;
+  double share = 0.0;
+  if constexpr (MODE != F_ERR) {
+    if (threadIdx.x < kWave) {
+      if (lane == 0) {
+        done = a.ctrl->done;
+        fail = a.ctrl->fail;
+      }
+      if (MODE == F_PHI && a.check)
+        for (int c = lane; c < a.nchunks; c += kWave) share += a.part[c];
+    }
+  }
+  CarryItems<kCarryMax> items;
+  carry_prefetch<kCarryMax>(a.A_in, blockIdx.x, a.nchunks, items);
+  T x[R];
+  load_run<T, R>(static_cast<const T*>(a.vin), base, n, x, T(0));
+  const int ex = a.ein[run];
+  T own[R];
+  double m64[R];
+  int eo = 0;
+  if (want_err) {
+    load_run<T, R>(static_cast<const T*>(a.vown), base, n, own, T(0));
+    eo = a.eown[run];
+  }
+  if (want_err || sizeof(T) == 8) load_run<double, R>(a.m64, base, n, m64, 0.0);
+  T mg[R];
+  if constexpr (MODE != F_ERR) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) mg[j] = T(m64[j]);
+    } else {
+      load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, n, mg, T(0));
+    }
+  }
+
+  if constexpr (MODE != F_ERR) {
+    // 3: already stopped; 2: a scaling became non-finite; 1: err(l) <= tol
+    if (threadIdx.x < kWave) {
+      done = __shfl(done, 0);
+      fail = __shfl(fail, 0);
+      int dec = 0;
+      if (done) {
+        dec = 3;
+      } else if (fail) {
+        dec = 2;
+      } else if (MODE == F_PHI && a.check) {
+        double s = share;
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        if (lane == 0 && blockIdx.x == 0) {
+          a.ctrl->last_err = s;
+          a.ctrl->last_check = a.l;
+          if (a.err_hist) a.err_hist[a.l] = s;
+        }
+        if (!(s > a.tol)) dec = 1;
+      }
+      if (lane == 0) sdec = dec;
+    }
+    __syncthreads();
+    if (sdec) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (sdec == 1) a.ctrl->stop_iter = a.l;
+        a.ctrl->done = 1;
+      }
+      return;
+    }
+  }
+
+  const Lam<T> L = lam_of<T>(k);
+  const FastDec<T> D = make_fast_dec<T>(k, lane);
+  HalfState<T, R> hs;
+  local_scan<T, R>(x, ex, L, D, sf, sb, smax, hs);
+  carry_finish<kCarryMax>(items, blockIdx.x, a.cpow, red4, scar);
+  T y[R];
+  const int eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
+
+  if (want_err) {
+    // entries past n load as zero and add nothing
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) s += fabs(ldexp(double(own[j]) * double(y[j]), eo + eap) - m64[j]);
+    const double tot = block_sum<kNW>(s, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+  }
+  if constexpr (MODE == F_ERR) return;
+
+  // the new vector is q * 2^-eap: every run of the chunk gets exponent -eap
+  T q[R];
+  bool bad = false;
+  update_frame<T, R>(mg, y, q, bad);
+  if (bad) {
+    atomicOr(&a.ctrl->fail, 1);
+    atomicMin(&a.ctrl->fail_iter, a.l);
+  }
+  store_run<T, R>(static_cast<T*>(a.vout), base, n, q);
+  a.eout[run] = -eap;
+  // aggregates of the new vector for the next launch
+  publish_frame<T, R>(q, -eap, L, D, sf, sb, a.A_out);
+}
+
+// Chunk aggregates of a stored vector (initial state, finalisation).
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_publish(const T* __restrict__ v,
+                                                    const int* __restrict__ ex, int64_t n,
+                                                    ScanConsts k, ChunkAgg* A) {
+  __shared__ T sf[kNW];
+  __shared__ T sb[kNW];
+  __shared__ int smax[kNW];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  T x[R];
+  load_run<T, R>(v, run * R, n, x, T(0));
+  const Lam<T> L = lam_of<T>(k);
+  const FastDec<T> D = make_fast_dec<T>(k, lane);
+  HalfState<T, R> hs;
+  local_scan<T, R>(x, ex[run], L, D, sf, sb, smax, hs);
+  publish<T>(D, sf, sb, hs.ein, A);
+}
+
+template <typename T, int R>
+struct FusedOps {
+  static FusedArgs base_args(const SolveBufs& b, const ScanConsts& k, double tol) {
+    FusedArgs a{};
+    a.part = b.part;
+    a.ctrl = b.ctrl;
+    a.err_hist = b.err_hist;
+    a.n = b.n;
+    a.nchunks = int(b.nchunks);
+    a.tol = tol;
+    const double cl = k.c_log2e * double(kBlock) * double(R);
+    for (int i = 0; i < 20; ++i) a.cpow[i] = make_decay(cl * double(1ll << i));
+    return a;
+  }
+  static hipError_t half(const SolveBufs& b, const ScanConsts& k, int l, int check, double tol,
+                         bool psi, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    FusedArgs a = base_args(b, k, tol);
+    a.l = l;
+    a.check = check;
+    const int cur = l & 1, nxt = (l + 1) & 1;
+    if (psi) {
+      a.vin = b.vF;
+      a.ein = b.eF;
+      a.m64 = b.nu;
+      a.m32 = static_cast<const float*>(b.nu32);
+      a.vout = b.vG[nxt];
+      a.eout = b.eG[nxt];
+      a.vown = b.vG[cur];
+      a.eown = b.eG[cur];
+      a.A_in = b.aggF;
+      a.A_out = b.aggG;
+    } else {
+      a.vin = b.vG[nxt];
+      a.ein = b.eG[nxt];
+      a.m64 = b.mu;
+      a.m32 = static_cast<const float*>(b.mu32);
+      a.vout = b.vF;
+      a.eout = b.eF;
+      a.A_in = b.aggG;
+      a.A_out = b.aggF;
+    }
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (psi)
+      k_fused<T, R, F_PSI><<<unsigned(b.nchunks), kBlock, 0, s>>>(a, k);
+    else
+      k_fused<T, R, F_PHI><<<unsigned(b.nchunks), kBlock, 0, s>>>(a, k);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    return hipGetLastError();
+  }
+  static hipError_t publish_state(const SolveBufs& b, const ScanConsts& k, const void* v,
+                                   const int* ex, ChunkAgg* A, hipStream_t s) {
+    k_publish<T, R><<<unsigned(b.nchunks), kBlock, 0, s>>>(static_cast<const T*>(v), ex, b.n, k, A);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+bool usable_fused(const SolveBufs& b, double c) {
+  if (!b.absorb) return false;  // the plain domain keeps the paper's unscaled arithmetic
+  if (b.nchunks > kMaxFusedChunks) return false;
+  const double span = double(kBlock) * double(b.R) * c * kLog2E;
+  if (b.dtype == 0) return b.R == 8 && span <= kFrameLog2Span64;
+  return b.R == 16 && span <= kFrameLog2Span32;
+}
+
+hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
+  if (b.dtype == 0) return FusedOps<double, 8>::publish_state(b, k, b.vF, b.eF, b.aggF, s);
+  return FusedOps<float, 16>::publish_state(b, k, b.vF, b.eF, b.aggF, s);
+}
+
+hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
+                             double tol, bool psi, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
+  if (b.dtype == 0) return FusedOps<double, 8>::half(b, k, l, check, tol, psi, s, ev0, ev1);
+  return FusedOps<float, 16>::half(b, k, l, check, tol, psi, s, ev0, ev1);
+}
+
+}  // namespace fs1

@@ -130,6 +130,14 @@ bool usable_persistent(const SolveBufs& b, double c);
 hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_max,
                              int check_every, double tol, unsigned* bar, hipStream_t s);
 
+// One launch per half-iteration with in-kernel chunk carries (log domain,
+// chunk frame valid, moderate chunk count).
+bool usable_fused(const SolveBufs& b, double c);
+hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
+                             double tol, bool psi, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
 hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
 // psi-half of iteration l: psi^{l+1} = nu / (K^T phi^l); error of (phi^l, psi^l)

@@ -24,13 +24,13 @@
 #include <climits>
 
 #include "fs1_device.h"
+#include "fs1_frame.h"
 #include "fs1_internal.h"
 
 namespace fs1 {
 
 namespace {
 
-constexpr int kNW = kBlock / kWave;
 constexpr int kMaxPersistChunks = 2048;
 // log2 span budget of the per-chunk frame (see the file comment)
 constexpr double kFrameLog2Span64 = 900.0;
@@ -100,215 +100,6 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, Ct
   return *sflag != 0;
 }
 
-template <typename T>
-struct FastDec {
-  T step[6];   // lambda^(R 2^s)
-  T wave;      // lambda^(64 R)
-  T lane_f;    // lambda^(lane R)
-  T lane_b;    // lambda^((63 - lane) R)
-};
-
-template <typename T>
-__device__ __forceinline__ T dec_val(const Decay& d) {
-  return T(ldexp(d.m, d.e));
-}
-
-template <typename T>
-__device__ __forceinline__ FastDec<T> make_fast_dec(const ScanConsts& k, int lane) {
-  FastDec<T> D;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) D.step[s] = dec_val<T>(k.lane[s]);
-  D.wave = dec_val<T>(k.lane[6]);
-  double mf = 1.0, mb = 1.0;
-  int ef = 0, eb = 0;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    if ((lane >> s) & 1) {
-      mf *= k.lane[s].m;
-      ef += k.lane[s].e;
-    }
-    if (((kWave - 1 - lane) >> s) & 1) {
-      mb *= k.lane[s].m;
-      eb += k.lane[s].e;
-    }
-  }
-  D.lane_f = T(ldexp(mf, ef));
-  D.lane_b = T(ldexp(mb, eb));
-  return D;
-}
-
-__device__ __forceinline__ int block_max_int(int v, int* sh) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  int r = sh[0];
-#pragma unroll
-  for (int i = 1; i < kNW; ++i) r = max(r, sh[i]);
-  __syncthreads();
-  return r;
-}
-
-// xfloat sum over the 64 lanes (same tree in every lane: every lane returns
-// the same value).
-__device__ __forceinline__ XF<double> wave_xsum(XF<double> v) {
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) {
-    const XF<double> o = {__shfl_xor(v.m, d), __shfl_xor(v.e, d)};
-    v = xadd(v, o);
-  }
-  return xnorm(v);
-}
-
-__device__ __forceinline__ XF<double> pow_bits(int64_t d, const Decay* p) {
-  XF<double> r = {1.0, 0};
-  for (int s = 0; d != 0 && s < 20; ++s, d >>= 1) {
-    if (d & 1) r = {r.m * p[s].m, r.e + p[s].e};
-  }
-  return r;
-}
-
-// Forward carry into chunk b (state at the element before the chunk) from the
-// forward aggregates of chunks 0..b-1, by one wavefront.
-__device__ XF<double> carry_fwd(const ChunkAgg* A, int b, const PersistArgs& a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int seg = (b + kWave - 1) / kWave;
-  const int lo = lane * seg;
-  const int hi = min(lo + seg, b);
-  XF<double> acc = xzero<double>();
-  if (lo < hi) {
-    const XF<double> cd = {a.cpow[0].m, a.cpow[0].e};
-    for (int c = lo; c < hi; ++c) acc = xnorm(xadd(xmul(acc, cd), XF<double>{A[c].f.m, A[c].f.e}));
-    acc = xmul(acc, pow_bits(b - hi, a.cpow));  // from the end of chunk hi-1 to the end of b-1
-  }
-  return wave_xsum(acc);
-}
-
-// Backward carry into chunk b (inclusive backward state at the element after
-// the chunk) from the backward aggregates of chunks b+1..nchunks-1.
-__device__ XF<double> carry_bwd(const ChunkAgg* A, int b, const PersistArgs& a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int first = b + 1;
-  const int cnt = a.nchunks - first;
-  const int seg = (cnt + kWave - 1) / kWave;
-  const int lo = first + lane * seg;
-  const int hi = min(lo + seg, a.nchunks);
-  XF<double> acc = xzero<double>();
-  if (cnt > 0 && lo < hi) {
-    const XF<double> cd = {a.cpow[0].m, a.cpow[0].e};
-    for (int c = hi - 1; c >= lo; --c)
-      acc = xnorm(xadd(xmul(acc, cd), XF<double>{A[c].b.m, A[c].b.e}));
-    acc = xmul(acc, pow_bits(lo - first, a.cpow));  // from the start of lo to the start of b+1
-  }
-  return wave_xsum(acc);
-}
-
-template <typename T, int R>
-struct HalfState {
-  T xf[R];     // input run in the chunk frame
-  T exf, exb;  // wave-exclusive carries (chunk frame)
-  int ein;     // chunk frame exponent of the input
-};
-
-// Phase 1 of a half: frame, thread aggregates, wave scans, chunk aggregates.
-template <typename T, int R>
-__device__ __forceinline__ void half_aggregate(const T (&x)[R], int ex, const Lam<T>& L,
-                                               const FastDec<T>& D, T* sf, T* sb, int* smax,
-                                               ChunkAgg* A, HalfState<T, R>& hs) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  const int eb = block_max_int(local_exponent<T, R>(x, ex), smax);
-  hs.ein = (eb == kExpZero) ? 0 : eb;
-#pragma unroll
-  for (int j = 0; j < R; ++j) hs.xf[j] = ldx(x[j], ex - hs.ein);
-  T f, b;
-  run_aggs<T, R>(hs.xf, L, f, b);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 1 << s;
-    const T of = __shfl_up(f, d);
-    const T ob = __shfl_down(b, d);
-    if (lane >= d) f = fma(D.step[s], of, f);
-    if (lane + d < kWave) b = fma(D.step[s], ob, b);
-  }
-  T ef = __shfl_up(f, 1);
-  T eb2 = __shfl_down(b, 1);
-  hs.exf = (lane == 0) ? T(0) : ef;
-  hs.exb = (lane == kWave - 1) ? T(0) : eb2;
-  if (lane == kWave - 1) sf[w] = f;
-  if (lane == 0) sb[w] = b;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T gf = T(0), gb = T(0);
-#pragma unroll
-    for (int v = 0; v < kNW; ++v) gf = fma(D.wave, gf, sf[v]);
-#pragma unroll
-    for (int v = kNW - 1; v >= 0; --v) gb = fma(D.wave, gb, sb[v]);
-    const XF<T> xfw = xnorm(gf, hs.ein);
-    const XF<T> xbw = xnorm(gb, hs.ein);
-    A[blockIdx.x].f = to64(xfw);
-    A[blockIdx.x].b = to64(xbw);
-  }
-}
-
-// Phase 3 of a half: chunk carries (waves 0 and 1), frame alignment, in-chunk
-// recursions.  Returns y = (K in) * 2^-eap in every thread's run.
-template <typename T, int R>
-__device__ __forceinline__ int half_apply(const ChunkAgg* A, const PersistArgs& a,
-                                          const Lam<T>& L, const FastDec<T>& D, const T* sf,
-                                          const T* sb, XF64* scar, HalfState<T, R>& hs,
-                                          T (&y)[R]) {
-  const int w = threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int b = blockIdx.x;
-  if (w == 0) {
-    const XF<double> cf = carry_fwd(A, b, a);
-    if (lane == 0) scar[0] = to64(cf);
-  } else if (w == 1) {
-    const XF<double> cb = carry_bwd(A, b, a);
-    if (lane == 0) scar[1] = to64(cb);
-  }
-  __syncthreads();
-  const XF64 cf = scar[0];
-  const XF64 cb = scar[1];
-  int eap = hs.ein;
-  if (cf.m != 0.0) eap = max(eap, cf.e);
-  if (cb.m != 0.0) eap = max(eap, cb.e);
-  const int sh = hs.ein - eap;  // <= 0: rescale the chunk-frame quantities
-  T accf = T(ldexp(cf.m, cf.e - eap));
-  T accb = T(ldexp(cb.m, cb.e - eap));
-  for (int v = 0; v < w; ++v) accf = fma(D.wave, accf, ldx(sf[v], sh));
-  for (int v = kNW - 1; v > w; --v) accb = fma(D.wave, accb, ldx(sb[v], sh));
-  const T tcf = fma(D.lane_f, accf, ldx(hs.exf, sh));
-  const T tcb = fma(D.lane_b, accb, ldx(hs.exb, sh));
-  T xf[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) xf[j] = ldx(hs.xf[j], sh);
-  run_apply<T, R>(xf, tcf, tcb, L, y);
-  return eap;
-}
-
-// New run values q = marg / y (zero marginal -> zero), renormalised so that the
-// run maximum is in [1/2, 1); returns the run exponent (y is in frame eap).
-template <typename T, int R>
-__device__ __forceinline__ int update_run(const T (&mg)[R], const T (&y)[R], int eap, T (&q)[R],
-                                          bool& bad) {
-  T qm = T(0);
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    q[j] = (mg[j] == T(0)) ? T(0) : mg[j] / y[j];
-    bad |= !isfinite(q[j]);
-    if (isfinite(q[j])) qm = fmax(qm, q[j]);
-  }
-  int kq = 0;
-  if (qm > T(0)) frx(qm, &kq);
-#pragma unroll
-  for (int j = 0; j < R; ++j) q[j] = ldx(q[j], -kq);
-  return kq - eap;
-}
-
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k) {
   __shared__ T sf[kNW];
@@ -352,7 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
   for (; l < a.itr_max; ++l) {
     const bool check = (l % a.check_every) == 0;
     // ---------------- psi-half: psi <- nu / K^T phi ----------------
-    half_aggregate<T, R>(ph, eph, L, D, sf, sb, smax, a.A0, hs);
+    local_scan<T, R>(ph, eph, L, D, sf, sb, smax, hs);
+    publish<T>(D, sf, sb, hs.ein, a.A0);
     if (!grid_barrier(a.bar, nblocks, a.ctrl, &sbar)) break;
     // failures of the previous phi-half: that slot is written only before this
     // barrier, so every workgroup reads the same value
@@ -363,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       failed = true;
       break;
     }
-    int eap = half_apply<T, R>(a.A0, a, L, D, sf, sb, scar, hs, y);
+    int eap = half_apply<T, R>(a.A0, a.nchunks, a.cpow, L, D, sf, sb, scar, hs, y);
     if (check) {
       double s = 0.0;
       double nu64[R];
@@ -391,7 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
     eps = eq;
 
     // ---------------- phi-half: phi <- mu / K psi ----------------
-    half_aggregate<T, R>(ps, eps, L, D, sf, sb, smax, a.A1, hs);
+    local_scan<T, R>(ps, eps, L, D, sf, sb, smax, hs);
+    publish<T>(D, sf, sb, hs.ein, a.A1);
     if (!grid_barrier(a.bar, nblocks, a.ctrl, &sbar)) break;
     // stopping test of iteration l (every workgroup sums the same shares in
     // the same order) and the failure flag
@@ -428,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       stop_iter = l;
       break;
     }
-    eap = half_apply<T, R>(a.A1, a, L, D, sf, sb, scar, hs, y);
+    eap = half_apply<T, R>(a.A1, a.nchunks, a.cpow, L, D, sf, sb, scar, hs, y);
     bad = false;
     const int ef = update_run<T, R>(mu, y, eap, q, bad);
     if (bad) {

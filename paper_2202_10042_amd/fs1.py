@@ -32,7 +32,8 @@ FS1_F32 = 1
 FS1_PLAIN = 0
 FS1_LOG = 1
 FS1_FLAG_POTENTIALS = 1
-FS1_FLAG_STREAMING = 2
+FS1_FLAG_GENERAL = 2
+FS1_FLAG_PERSISTENT = 4
 
 # every symbol include/fs1.h declares
 EXPORTS = (
@@ -250,20 +251,21 @@ def make_opts(h: Optional[float] = None, itr_max: int = 10000, dtype: str = "f64
 def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max: int = 10000,
               dtype: str = "f64", domain: str = "plain", check_every: int = 1,
               sync_every: int = 16, potentials: bool = False, err_history: bool = False,
-              streaming: bool = False, ctx: Optional[Context] = None,
+              solver: str = "auto", ctx: Optional[Context] = None,
               raise_on_error: bool = False) -> Result:
     """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
 
-    streaming=True forbids the single-launch persistent solver (every
-    half-iteration is then its own kernel launch)."""
+    solver: "auto" (fused one-launch-per-half kernels when they apply),
+    "general" (extended-range scans with a separate carry kernel) or
+    "persistent" (single cooperative launch when the grid fits)."""
     import torch
     ctx = ctx or default_context()
     n = mu.numel()
     if nu.numel() != n:
         raise ValueError("mu and nu must have the same length")
     o = make_opts(h, itr_max, dtype, domain, check_every, sync_every)
-    if streaming:
-        o.flags |= FS1_FLAG_STREAMING
+    o.flags |= {"auto": 0, "general": FS1_FLAG_GENERAL,
+                "persistent": FS1_FLAG_PERSISTENT}[solver]
     pot = hist = None
     if potentials:
         pot = torch.empty(2 * n, dtype=torch.float64, device=mu.device)

@@ -40,9 +40,9 @@ def _pot_close(got, ref_lin, mask, atol):
     assert np.max(np.abs(g - ref)) <= atol, float(np.max(np.abs(g - ref)))
 
 
-# "persistent" = the default choice (the log domain runs the single-launch
-# solver when it fits); "streaming" forbids it
-PATHS = ["persistent", "streaming"]
+# solver paths: "auto" (fused one-launch-per-half kernels where they apply),
+# "general" (extended-range scans + carry kernel), "persistent" (one launch)
+PATHS = ["auto", "general", "persistent"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -58,7 +58,7 @@ def test_solve_f64_fixed_iterations(domain, n, seed, its, path):
     ref = oracle.fs1(mu, nu, h, eps, tol=0.0, itr_max=its) if n > 2000 else \
         oracle.sinkhorn_dense(mu, nu, h, eps, tol=0.0, itr_max=its)
     r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f64", domain=domain,
-                      potentials=True, streaming=(path == "streaming"))
+                      potentials=True, solver=path)
     # (for n = 1 the initial error is exactly 0 and Algorithm 1 stops at once)
     assert r.status == 0 and r.iterations == ref.iterations
     assert r.w1 == pytest.approx(ref.w1, rel=1e-10, abs=1e-300)
@@ -82,7 +82,7 @@ def test_solve_c1_to_tolerance(domain, path):
         mu, nu = inputs.mixture_pair(n, 2, seed)
         ref = oracle.sinkhorn_dense(mu, nu, h, 0.01, tol=1e-9, itr_max=2000)
         r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-9, itr_max=2000, domain=domain,
-                          streaming=(path == "streaming"))
+                          solver=path)
         assert r.status == 0 and r.converged and ref.converged
         # the stopping iteration may differ by one where err(l) is within rounding of tol
         assert abs(r.iterations - ref.iterations) <= 1
@@ -102,7 +102,7 @@ def test_solve_log_f32_against_f64_oracle(path):
         h = 1.0 / n
         ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
         r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
-                          potentials=True, streaming=(path == "streaming"))
+                          potentials=True, solver=path)
         assert r.status == 0
         assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
         m = nu > 0
@@ -176,13 +176,12 @@ def test_solve_invalid_marginals():
 @pytest.mark.parametrize("path", PATHS)
 def test_error_history_and_check_interval(path):
     fs1 = _fs1()
-    st = path == "streaming"
     n = 400
     mu, nu = inputs.mixture_pair(n, 2, 7)
     h = 1.0 / n
     _say(f"error history {path}")
     r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 0.0, itr_max=12, domain="log", err_history=True,
-                      streaming=st)
+                      solver=path)
     hist = r.err_history.cpu().numpy()
     for l in range(12):
         ref = oracle.fs1(mu, nu, h, 0.01, tol=0.0, itr_max=l).marginal_err
@@ -190,13 +189,13 @@ def test_error_history_and_check_interval(path):
     assert np.isnan(hist[12])
     # the result does not depend on the host polling interval; with check_every
     # k the stop happens at the first multiple of k with err <= tol
-    base = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", streaming=st)
+    base = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", solver=path)
     for se in (1, 5, 64):
         r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", sync_every=se,
-                          streaming=st)
+                          solver=path)
         assert r.iterations == base.iterations and r.w1 == base.w1
     r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-8, itr_max=3000, domain="log", check_every=7,
-                      streaming=st)
+                      solver=path)
     assert r.iterations % 7 == 0 and base.iterations <= r.iterations < base.iterations + 7
 
 
@@ -205,29 +204,28 @@ def test_solve_deterministic(path):
     fs1 = _fs1()
     n = 70001
     mu, nu = inputs.mixture_pair(n, 4, 3)
-    st = path == "streaming"
     _say(f"determinism {path}")
     a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True,
-                      streaming=st)
+                      solver=path)
     b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=30, domain="log", potentials=True,
-                      streaming=st)
+                      solver=path)
     assert a.w1 == b.w1 and a.marginal_err == b.marginal_err
     assert torch.equal(a.F, b.F) and torch.equal(a.G, b.G)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_persistent_matches_streaming(dtype):
-    # the two solvers differ only in the in-chunk arithmetic (frame vs extended
-    # range), so they agree to rounding
+def test_solver_paths_agree(dtype):
+    # the solvers differ only in the in-chunk arithmetic (frame vs extended
+    # range) and the launch structure, so they agree to rounding
     fs1 = _fs1()
     n = 300007
     mu, nu = inputs.mixture_pair(n, 5, 8)
-    _say(f"persistent vs streaming {dtype}")
-    a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 1e-7, itr_max=800, domain="log", dtype=dtype)
-    b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 1e-7, itr_max=800, domain="log", dtype=dtype,
-                      streaming=True)
-    assert abs(a.iterations - b.iterations) <= 1
-    assert a.w1 == pytest.approx(b.w1, rel=1e-11 if dtype == "f64" else 1e-5)
+    _say(f"solver paths agree {dtype}")
+    rs = [fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 1e-7, itr_max=800, domain="log", dtype=dtype,
+                        solver=p) for p in PATHS]
+    for r in rs[1:]:
+        assert abs(r.iterations - rs[0].iterations) <= 1
+        assert r.w1 == pytest.approx(rs[0].w1, rel=1e-11 if dtype == "f64" else 1e-5)
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -242,9 +240,8 @@ def test_solve_full_size_f64_log(eps, path):
     h = 1.0 / n
     _say(f"full size f64 log eps={eps}")
     ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
-    st = path == "streaming"
     r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, domain="log", potentials=True,
-                      streaming=st)
+                      solver=path)
     assert r.status == 0
     assert r.w1 == pytest.approx(ref.w1, rel=1e-9)
     assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6)
@@ -252,5 +249,5 @@ def test_solve_full_size_f64_log(eps, path):
     assert np.max(np.abs(G - ref.b)) <= 1e-8
     _say(f"full size f32 log eps={eps}")
     r32 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
-                        streaming=st)
+                        solver=path)
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
