@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s (vendor figure)
-PROFILE_STRIDE = 8             # time the update kernels of every 8th iteration
+PROFILE_STRIDE = 4             # time every 4th polling batch of update kernels
 N_C2 = 1 << 20
 SEED = 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_half_traffic.json")

@@ -77,13 +77,15 @@ int fs1_ctx_destroy(fs1_ctx *ctx);
 int fs1_ctx_set_stream(fs1_ctx *ctx, void *stream);
 
 /* Diagnostic timing for benchmarks.  With enable = k > 0, fs1_solve records
- * HIP events on the context stream just before and after both half-iteration
- * kernels (the psi = nu / K^T phi and phi = mu / K psi updates) of every k-th
- * iteration that does work, and accumulates their durations and their
- * algorithmic bytes (read the vector fed to K, read the marginal, write the
- * new vector; checked psi-halves also read the old psi and, in binary32 mode,
- * the binary64 nu).  enable = 0 turns timing off.  Every call resets the
- * counters.  Results of the solve do not change. */
+ * HIP events on the context stream around every k-th polling batch of
+ * half-iteration launches (sync_every iterations; the psi = nu / K^T phi and
+ * phi = mu / K psi updates) in which every launch did its work, and
+ * accumulates the batch durations, the number of half-iteration launches and
+ * their algorithmic bytes (read the vector fed to K, read the marginal, write
+ * the new vector; checked psi-halves also read the old psi and, in binary32
+ * mode, the binary64 nu).  The persistent solver is timed as one launch.
+ * enable = 0 turns timing off.  Every call resets the counters.  Results of
+ * the solve do not change. */
 int fs1_ctx_set_profiling(fs1_ctx *ctx, int enable);
 /* Accumulated half-iteration kernel time (ms), number of timed launches and
  * algorithmic bytes since profiling was last enabled.  Any pointer may be NULL. */
@@ -131,6 +133,7 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 #define FS1_FLAG_POTENTIALS 1
 #define FS1_FLAG_GENERAL 2
 #define FS1_FLAG_PERSISTENT 4
+#define FS1_FLAG_NO_GRAPH 8
 
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
@@ -184,14 +187,25 @@ typedef struct {
 int fs1_solve(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
               double tol, const fs1_opts *opts, fs1_result *out);
 
-/* Ragged batch of independent solves.  Instance b occupies
- * [offsets[b], offsets[b+1]) of mu_packed / nu_packed (device binary64);
- * offsets: host int64 array of B+1 nondecreasing entries, offsets[0] = 0, every
- * instance length >= 1.  eps, tol: host arrays of B entries.  opts->h is
- * ignored: instance b uses h = 1 / n_b.  out: host array of B results.  Every
- * instance runs the same arithmetic it would run alone (its result does not
- * depend on the rest of the batch).  Blocks until every result is written.
- * Returns FS1_OK if the call ran; per-instance failures are in out[b].status. */
+/* Ragged batch of independent solves (Algorithm 1 per instance).  Instance b
+ * occupies [offsets[b], offsets[b+1]) of mu_packed / nu_packed (device
+ * binary64; the arrays themselves 16-byte aligned, instances anywhere in them);
+ * offsets: host int64 array of B+1 entries, offsets[0] = 0, every instance
+ * length >= 1.  eps, tol: host arrays of B entries, each validated as for
+ * fs1_solve.  Instance b uses h = 1 / n_b (opts->h is ignored), opts->dtype,
+ * itr_max and check_every; potentials and error history are not returned.
+ *  - FS1_LOG: every instance advances in the same launches, one per
+ *    half-iteration and run-length class, each with its own lambda, stopping
+ *    test and iteration count.  opts->sync_every iterations are captured in a
+ *    HIP graph that is replayed until every instance has stopped
+ *    (FS1_FLAG_NO_GRAPH in opts->flags launches the same kernels directly).  An
+ *    instance's run length, reduction order and result depend only on its own
+ *    (n, eps, tol, marginals) and opts, not on the rest of the batch.
+ *  - FS1_PLAIN: the instances run one after another through fs1_solve; each
+ *    must then start on a 16-byte boundary.
+ * out: host array of B results.  Blocks until every result is written.  Returns
+ * FS1_OK if the call ran (then per-instance failures, including invalid
+ * marginals, are in out[b].status), else an error before any launch. */
 int fs1_solve_batched(fs1_ctx *ctx, const double *mu_packed, const double *nu_packed,
                       const int64_t *offsets, int32_t B, const double *eps,
                       const double *tol, const fs1_opts *opts, fs1_result *out);

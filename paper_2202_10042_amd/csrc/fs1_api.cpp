@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -19,6 +20,7 @@
 #include <vector>
 
 #include "fs1.h"
+#include "fs1_batch.h"
 #include "fs1_internal.h"
 
 using namespace fs1;
@@ -35,6 +37,11 @@ struct fs1_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   double prof_bytes = 0.0;
+  // batched solves
+  void* hstage = nullptr;   // pinned host staging (per-instance states)
+  size_t hstage_size = 0;
+  hipStream_t capture = nullptr;  // stream used only to capture iteration graphs
+  hipEvent_t bev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -142,6 +149,205 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
   return FS1_OK;
 }
 
+// Pinned host staging of at least `bytes`.
+int ensure_hstage(fs1_ctx* c, size_t bytes) {
+  if (bytes <= c->hstage_size) return FS1_OK;
+  if (c->hstage) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipHostFree(c->hstage));
+    c->hstage = nullptr;
+    c->hstage_size = 0;
+  }
+  const size_t sz = round_up(bytes, size_t(1) << 16);
+  hipError_t e = hipHostMalloc(&c->hstage, sz, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    c->hstage = nullptr;
+    return set_err(FS1_ERR_NO_MEMORY, "hipHostMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+  }
+  c->hstage_size = sz;
+  return FS1_OK;
+}
+
+// Ragged batch in the log domain: every instance keeps its own lambda, run
+// length, stopping test and iteration count; all of them advance in the same
+// launches (fs1_batch.hip).
+int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t* offsets,
+                int32_t B, const double* eps, const double* tol, const fs1_opts& o,
+                fs1_result* out) {
+  const int dt = o.dtype;
+  const size_t es = dt == FS1_F64 ? 8 : 4;
+  hipStream_t s = ctx->stream;
+
+  // run length of each instance: a function of (n, eps, dtype) only, so an
+  // instance's arithmetic does not depend on the rest of the batch
+  std::vector<int> rlen(B);
+  for (int32_t i = 0; i < B; ++i) {
+    const double n = double(offsets[i + 1] - offsets[i]);
+    rlen[i] = pick_run_length(dt, true, (1.0 / n) / eps[i]);
+  }
+  std::vector<int> rs(rlen);
+  std::sort(rs.begin(), rs.end(), [](int a, int b) { return a > b; });
+  rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
+  std::vector<BatchGroup> groups;
+  std::vector<InstInfo> info(B);
+  std::vector<int> chunk_inst;
+  int64_t chunk = 0, elem = 0;
+  for (int r : rs) {
+    BatchGroup g{r, int(chunk), 0};
+    const int64_t C = int64_t(kBlock) * r;
+    for (int32_t i = 0; i < B; ++i) {
+      if (rlen[i] != r) continue;
+      const int64_t n = offsets[i + 1] - offsets[i];
+      const int64_t nch = (n + C - 1) / C;
+      if (chunk + nch > int64_t(INT32_MAX) / kBlock)
+        return set_err(FS1_ERR_INVALID_ARG, "batch too large");
+      info[i] = make_inst_info(offsets[i], elem, n, int(chunk), r, 1.0 / double(n), eps[i],
+                               tol[i], 0);
+      chunk_inst.insert(chunk_inst.end(), size_t(nch), int(i));
+      chunk += nch;
+      elem += nch * C;
+    }
+    g.nchunks = int(chunk - g.chunk0);
+    groups.push_back(g);
+  }
+  const int ngroups = int(groups.size());
+  const int64_t nchunks = chunk, nruns = chunk * kBlock, nelem = elem;
+
+  BatchBufs z{};
+  auto layout = [&](Carve& w) {
+    z.inst = static_cast<InstInfo*>(w.take(size_t(B) * sizeof(InstInfo)));
+    z.st = static_cast<InstState*>(w.take(size_t(B) * sizeof(InstState)));
+    z.chunk_inst = static_cast<int*>(w.take(nchunks * sizeof(int)));
+    z.iter_base = static_cast<int*>(w.take(2 * sizeof(int)));
+    z.mu64 = static_cast<double*>(w.take(nelem * sizeof(double)));
+    z.nu64 = static_cast<double*>(w.take(nelem * sizeof(double)));
+    z.mu32 = dt == FS1_F32 ? w.take(nelem * sizeof(float)) : nullptr;
+    z.nu32 = dt == FS1_F32 ? w.take(nelem * sizeof(float)) : nullptr;
+    z.vF = w.take(nelem * es);
+    z.vG[0] = w.take(nelem * es);
+    z.vG[1] = w.take(nelem * es);
+    z.eF = static_cast<int*>(w.take(nruns * sizeof(int)));
+    z.eG[0] = static_cast<int*>(w.take(nruns * sizeof(int)));
+    z.eG[1] = static_cast<int*>(w.take(nruns * sizeof(int)));
+    z.aggF = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    z.aggG = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    z.agg2 = w.take(nchunks * 48);
+    z.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    z.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    z.part3 = static_cast<double*>(w.take(nchunks * sizeof(double)));
+  };
+  {
+    Carve probe(nullptr);
+    layout(probe);
+    int st = ensure_ws(ctx, probe.off);
+    if (st) return st;
+    st = ensure_hstage(ctx, std::max(size_t(B) * sizeof(InstState), size_t(64)));
+    if (st) return st;
+    Carve w(ctx->ws);
+    layout(w);
+  }
+  z.ndone = z.iter_base + 1;
+  z.dtype = dt;
+  z.itr_max = o.itr_max;
+  z.check_every = o.check_every;
+  z.nchunks = nchunks;
+  z.nelem = nelem;
+
+  std::vector<InstState> init(B);
+  for (InstState& t : init) {
+    std::memset(&t, 0, sizeof(t));
+    t.stop_iter = -1;
+    t.fail_iter = INT_MAX;
+    t.last_check = -1;
+    t.last_err = NAN;
+  }
+  HIP_TRY(hipMemcpyAsync(z.inst, info.data(), size_t(B) * sizeof(InstInfo),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(z.st, init.data(), size_t(B) * sizeof(InstState),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(z.chunk_inst, chunk_inst.data(), nchunks * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(z.iter_base, 0, 2 * sizeof(int), s));
+  HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, mu, nu, B, s));
+
+  // `count` iterations per replay; every instance stops by iteration itr_max
+  const int count = std::max(1, std::min(o.sync_every, o.itr_max + 1));
+  const int64_t max_rounds = (int64_t(o.itr_max) + count) / count + 1;
+  hipGraphExec_t gexec = nullptr;
+  if (!(o.flags & FS1_FLAG_NO_GRAPH)) {
+    if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch_batch_iterations(z, groups.data(), ngroups, count, ctx->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(ctx->capture, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le, "batched iteration capture");
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+  }
+  struct GraphGuard {
+    hipGraphExec_t g;
+    ~GraphGuard() {
+      if (g) (void)hipGraphExecDestroy(g);
+    }
+  } guard{gexec};
+  for (hipEvent_t& e : ctx->bev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+  // replay until every instance has stopped; one replay stays queued ahead of
+  // the host's look at the stop counter
+  int* hdone = static_cast<int*>(ctx->hstage);
+  hdone[0] = hdone[1] = 0;
+  int stopped = 0;
+  for (int64_t r = 0; r <= max_rounds; ++r) {
+    if (gexec) {
+      HIP_TRY(hipGraphLaunch(gexec, s));
+    } else {
+      HIP_TRY(launch_batch_iterations(z, groups.data(), ngroups, count, s));
+    }
+    HIP_TRY(hipMemcpyAsync(&hdone[r & 1], z.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ctx->bev[r & 1], s));
+    if (r > 0) {
+      HIP_TRY(hipEventSynchronize(ctx->bev[(r - 1) & 1]));
+      stopped = hdone[(r - 1) & 1];
+      if (stopped >= B) break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  stopped = std::max(stopped, std::max(hdone[0], hdone[1]));
+  if (stopped != B)
+    return set_err(FS1_ERR_INTERNAL, "batched solve: %d of %d instances stopped", stopped, B);
+
+  HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, B, s));
+  InstState* hs = static_cast<InstState*>(ctx->hstage);
+  HIP_TRY(hipMemcpyAsync(hs, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < B; ++i) {
+    const InstState& t = hs[i];
+    fs1_result& r = out[i];
+    if (t.invalid) {
+      r.status = FS1_ERR_INVALID_ARG;
+      continue;
+    }
+    if (t.fail) {
+      r.iterations = t.fail_iter;
+      r.status = FS1_ERR_NONFINITE;
+      continue;
+    }
+    r.iterations = t.stop_iter >= 0 ? t.stop_iter : o.itr_max;
+    r.w1 = t.w1;
+    r.marginal_err = t.err;
+    r.mu_err = t.mu_err;
+    r.converged = !(t.err > tol[i]) ? 1 : 0;
+    r.status = (std::isfinite(t.w1) && std::isfinite(t.err)) ? FS1_OK : FS1_ERR_NONFINITE;
+  }
+  return FS1_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -177,6 +383,10 @@ int fs1_ctx_destroy(fs1_ctx* c) {
   if (!c) return FS1_OK;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->bev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->hstage) (void)hipHostFree(c->hstage);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hctrl) (void)hipHostFree(c->hctrl);
   delete c;
@@ -333,8 +543,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // diagnostic timing: events around every half-iteration kernel of a batch
   const bool prof = ctx->profiling != 0;
-  if (prof && ctx->events.size() < size_t(4 * o.sync_every + 4)) {
-    while (ctx->events.size() < size_t(4 * o.sync_every + 4)) {
+  if (prof && ctx->events.size() < 2) {
+    while (ctx->events.size() < 2) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e));
       ctx->events.push_back(e);
@@ -380,49 +590,40 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   // Algorithm 1: while l < itr_max and err(l) > tol
   int l = persistent ? o.itr_max : 0;
   bool stopped = persistent;
+  int batch = 0;
   while (l < o.itr_max && !stopped) {
     const int l0 = l;
     const int l_end = std::min(o.itr_max, l + o.sync_every);
+    // diagnostic timing brackets whole polling batches (every `profiling`-th
+    // one): back-to-back kernels run without gaps, so batch time / launches is
+    // the average kernel duration without per-launch event overhead
+    const bool timed = prof && (batch % ctx->profiling) == 0;
+    if (timed) HIP_TRY(hipEventRecord(ctx->events[0], s));
     for (; l < l_end; ++l) {
       const int check = (l % o.check_every) == 0;
-      // sampled: events only on every `profiling`-th iteration
-      hipEvent_t* ev = (prof && (l % ctx->profiling) == 0) ? &ctx->events[4 * (l - l0)] : nullptr;
       if (fused) {
-        HIP_TRY(launch_fused_half(b, k, l, check, tol, true, s, ev ? ev[0] : nullptr,
-                                  ev ? ev[1] : nullptr));
-        HIP_TRY(launch_fused_half(b, k, l, check, tol, false, s, ev ? ev[2] : nullptr,
-                                  ev ? ev[3] : nullptr));
+        HIP_TRY(launch_fused_half(b, k, l, check, tol, true, s));
+        HIP_TRY(launch_fused_half(b, k, l, check, tol, false, s));
       } else {
-        HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s, ev ? ev[0] : nullptr,
-                                ev ? ev[1] : nullptr));
-        HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s, ev ? ev[2] : nullptr,
-                                ev ? ev[3] : nullptr));
+        HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s));
+        HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s));
       }
     }
+    if (timed) HIP_TRY(hipEventRecord(ctx->events[1], s));
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stopped = hc->done != 0;
-    if (prof) {
-      // count only kernels that did their work: the psi-half runs up to and
-      // including the stopping iteration, the phi-half stops one short
-      const int last = (stopped && hc->stop_iter >= 0) ? hc->stop_iter : l - 1;
-      for (int i = l0; i < l; ++i) {
-        float ms = 0.0f;
-        if ((i % ctx->profiling) != 0) continue;
-        if (i <= last) {
-          HIP_TRY(hipEventElapsedTime(&ms, ctx->events[4 * (i - l0)], ctx->events[4 * (i - l0) + 1]));
-          ctx->prof_ms += ms;
-          ctx->prof_launches += 1;
-          ctx->prof_bytes += bytes_half + ((i % o.check_every) == 0 ? bytes_check : 0.0);
-        }
-        if (i < last || (!stopped && i == last)) {
-          HIP_TRY(hipEventElapsedTime(&ms, ctx->events[4 * (i - l0) + 2], ctx->events[4 * (i - l0) + 3]));
-          ctx->prof_ms += ms;
-          ctx->prof_launches += 1;
-          ctx->prof_bytes += bytes_half;
-        }
-      }
+    // a batch in which the solve stopped contains launches that returned at
+    // once; only batches in which every launch did its work are counted
+    if (timed && !stopped) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+      ctx->prof_ms += ms;
+      ctx->prof_launches += 2 * (l - l0);
+      for (int i = l0; i < l; ++i)
+        ctx->prof_bytes += 2.0 * bytes_half + ((i % o.check_every) == 0 ? bytes_check : 0.0);
     }
+    ++batch;
   }
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -459,27 +660,54 @@ int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_pa
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   if (B < 0 || (B > 0 && (!offsets || !eps || !tol || !out || !mu_packed || !nu_packed)))
     return set_err(FS1_ERR_INVALID_ARG, "bad batch arguments");
-  if (B > 0 && offsets[0] != 0) return set_err(FS1_ERR_INVALID_ARG, "offsets[0] must be 0");
-  for (int32_t i = 0; i < B; ++i)
-    if (offsets[i + 1] - offsets[i] < 1)
-      return set_err(FS1_ERR_INVALID_ARG, "instance %d is empty", i);
+  if (B == 0) return FS1_OK;
+  if (offsets[0] != 0) return set_err(FS1_ERR_INVALID_ARG, "offsets[0] must be 0");
   fs1_opts o;
   fs1_opts_default(&o);
   if (opts) o = *opts;
-  o.h = 0.0;
-  o.flags = 0;
-  o.potentials_out = nullptr;
-  o.err_history = nullptr;
+  if (o.itr_max < 0) o.itr_max = 10000;
+  if (o.check_every < 1) o.check_every = 1;
+  if (o.sync_every < 1) o.sync_every = 16;
+  if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
+    return set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype);
+  if (o.domain != FS1_PLAIN && o.domain != FS1_LOG)
+    return set_err(FS1_ERR_INVALID_ARG, "bad domain %d", o.domain);
+  if (!aligned16(mu_packed) || !aligned16(nu_packed))
+    return set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
   for (int32_t i = 0; i < B; ++i) {
-    const int64_t a = offsets[i];
-    const int64_t n = offsets[i + 1] - a;
-    if (!aligned16(mu_packed + a) || !aligned16(nu_packed + a)) {
-      // instances must start on 16-byte boundaries for the vector loads
-      return set_err(FS1_ERR_INVALID_ARG, "instance %d is not 16-byte aligned", i);
-    }
-    fs1_solve(ctx, mu_packed + a, nu_packed + a, n, eps[i], tol[i], &o, &out[i]);
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n < 1) return set_err(FS1_ERR_INVALID_ARG, "instance %d is empty", i);
+    if (n > int64_t(INT32_MAX) / 2) return set_err(FS1_ERR_INVALID_ARG, "instance %d too long", i);
+    if (!(tol[i] >= 0.0)) return set_err(FS1_ERR_INVALID_ARG, "instance %d: tol must be >= 0", i);
+    const int st = check_h_eps(n, 1.0 / double(n), eps[i]);
+    if (st) return set_err(st, "instance %d: %s", i, g_err.c_str());
   }
-  return FS1_OK;
+  for (int32_t i = 0; i < B; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    out[i].w1 = NAN;
+    out[i].marginal_err = NAN;
+    out[i].mu_err = NAN;
+  }
+  if (o.domain == FS1_PLAIN) {
+    // the plain domain keeps Algorithm 1's unscaled arithmetic: one solve at a time
+    fs1_opts so = o;
+    so.h = 0.0;
+    so.flags = 0;
+    so.potentials_out = nullptr;
+    so.err_history = nullptr;
+    for (int32_t i = 0; i < B; ++i) {
+      const int64_t a = offsets[i];
+      if (!aligned16(mu_packed + a) || !aligned16(nu_packed + a)) {
+        out[i].status = set_err(FS1_ERR_INVALID_ARG,
+                                "plain domain: instance %d must start 16-byte aligned", i);
+        continue;
+      }
+      fs1_solve(ctx, mu_packed + a, nu_packed + a, offsets[i + 1] - a, eps[i], tol[i], &so,
+                &out[i]);
+    }
+    return FS1_OK;
+  }
+  return batch_solve(ctx, mu_packed, nu_packed, offsets, B, eps, tol, o, out);
 }
 
 }  // extern "C"

@@ -1,0 +1,687 @@
+// fs1_batch.hip -- many independent FS-1 solves (Algorithm 1) of different
+// lengths in the same launches.
+//
+// Layout (fs1_batch.h): instance b owns chunks [chunk0_b, chunk0_b + nch_b) of
+// the padded work arrays; entries past n_b are zero and stay zero (a zero
+// marginal gives a zero scaling).  One launch per half-iteration and run-length
+// group covers every chunk of the group.  A workgroup looks up its instance,
+// takes that instance's stop decision (all workgroups of an instance sum the
+// same error shares in the same order, so they decide alike), computes its
+// chunk carries from that instance's chunk aggregates, and runs the
+// extended-range scans of eq. (recursion) with the instance's own lambda.  An
+// instance thus executes the same arithmetic whatever else is in the batch and
+// wherever it sits.  Iterations are counted on the device (iter_base), so a
+// fixed number of iterations can be captured in a HIP graph and replayed until
+// every instance has stopped.
+#include <climits>
+
+#include "fs1_batch.h"
+#include "fs1_device.h"
+#include "fs1_internal.h"
+
+namespace fs1 {
+
+namespace {
+
+constexpr int kNW = kBlock / kWave;
+
+enum BMode { B_PSI = 0, B_PHI = 1, B_ERR = 2 };
+// which of two buffers a kernel reads
+enum BSel { SEL_0 = 0, SEL_FINAL = 1, SEL_NEXT = 2, SEL_CUR = 3 };
+
+__device__ __forceinline__ XF<double> wave_xsum64(XF<double> v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const XF<double> o = {__shfl_xor(v.m, d), __shfl_xor(v.e, d)};
+    v = xadd(v, o);
+  }
+  return xnorm(v);
+}
+
+__device__ __forceinline__ S2<double> s2_wave_sum(S2<double> v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v = v.add(v.shfl_xor(d));
+  return v.norm();
+}
+
+// lambda^(chunk length * d) from the binary expansion of d
+__device__ __forceinline__ XF<double> pow_chunks(int64_t d, const Decay* p) {
+  XF<double> r = {1.0, 0};
+  for (int s = 0; d != 0 && s < kInstPow; ++s, d >>= 1)
+    if (d & 1) r = {r.m * p[s].m, r.e + p[s].e};
+  return r;
+}
+
+// Carries of local chunk j from the instance's chunk aggregates (extended
+// range): wave 0 the forward carry, wave 1 the backward one.
+__device__ __forceinline__ void inst_carries(const ChunkAgg* A, const InstInfo& in, int j,
+                                             XF64* scar) {
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (w == 0) {
+    XF<double> acc = xzero<double>();
+    for (int i = lane; i < j; i += kWave) {
+      const XF64 v = A[in.chunk0 + i].f;
+      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_chunks(j - 1 - i, in.cpow)));
+    }
+    acc = wave_xsum64(acc);
+    if (lane == 0) scar[0] = to64(acc);
+  } else if (w == 1) {
+    XF<double> acc = xzero<double>();
+    for (int i = j + 1 + lane; i < in.nch; i += kWave) {
+      const XF64 v = A[in.chunk0 + i].b;
+      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_chunks(i - j - 1, in.cpow)));
+    }
+    acc = wave_xsum64(acc);
+    if (lane == 0) scar[1] = to64(acc);
+  }
+}
+
+struct BArgs {
+  const InstInfo* inst;
+  InstState* st;
+  const int* chunk_inst;
+  const int* iter_base;
+  int* ndone;
+  const void* vin[2];     // vector fed to K
+  const int* ein[2];
+  const void* vown[2];    // own vector of the error term
+  const int* eown[2];
+  void* vout[2];          // updated vector
+  int* eout[2];
+  const double* m64;      // padded marginal, binary64
+  const float* m32;       // padded marginal, binary32
+  const ChunkAgg* A_in;   // chunk aggregates of vin
+  ChunkAgg* A_out;        // chunk aggregates of vout (or of vin for k_bpublish)
+  double* part;
+  int chunk_off;          // first global chunk of the launch's group
+  int l_local;            // iteration = *iter_base + l_local - l0
+  int itr_max;
+  int check_every;
+  int sel_in, sel_own, sel_out;
+};
+
+// psi buffer holding the returned state: the one of the stopping iteration,
+// else of itr_max
+__device__ __forceinline__ int final_buf(const InstState& s, int itr_max) {
+  return (s.stop_iter >= 0) ? (s.stop_iter & 1) : (itr_max & 1);
+}
+
+__device__ __forceinline__ int pick(int sel, int l, const InstState& s, int itr_max) {
+  switch (sel) {
+    case SEL_FINAL: return final_buf(s, itr_max);
+    case SEL_NEXT: return (l + 1) & 1;
+    case SEL_CUR: return l & 1;
+    default: return 0;
+  }
+}
+
+// One half of the Sinkhorn update (Sec. 2) for every chunk of a group:
+//   B_PSI: psi^{l+1} = nu / K^T phi^l, error share of (phi^l, psi^l) when checked;
+//   B_PHI: phi^{l+1} = mu / K psi^{l+1}, after the stopping test of iteration l;
+//   B_ERR: error share only (finalisation).
+template <typename T, int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
+  __shared__ ScanLds<S1<T>, kNW> sh;
+  __shared__ double red[kNW];
+  __shared__ XF64 scar[2];
+  __shared__ int sdec;
+  const int c = a.chunk_off + blockIdx.x;
+  const int b = a.chunk_inst[c];
+  const InstInfo& in = a.inst[b];
+  InstState& st = a.st[b];
+  const int j = c - in.chunk0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int l = (MODE == B_ERR) ? 0 : *a.iter_base + a.l_local - in.l0;
+
+  if constexpr (MODE != B_ERR) {
+    // 3: already stopped; 4: l reached itr_max; 2: a scaling became
+    // non-finite; 1: err(l) <= tol
+    if (threadIdx.x < kWave) {
+      int dec = 0;
+      if (st.done) {
+        dec = 3;
+      } else if (l >= a.itr_max) {
+        dec = 4;
+      } else if (st.fail) {
+        dec = 2;
+      } else if (MODE == B_PHI && (l % a.check_every) == 0) {
+        double e = 0.0;
+        for (int i = lane; i < in.nch; i += kWave) e += a.part[in.chunk0 + i];
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
+        if (j == 0 && lane == 0) {
+          st.last_err = e;
+          st.last_check = l;
+        }
+        if (!(e > in.tol)) dec = 1;
+      }
+      if (lane == 0) sdec = dec;
+    }
+    __syncthreads();
+    if (sdec) {
+      if (j == 0 && threadIdx.x == 0 && sdec != 3) {
+        if (sdec == 1) st.stop_iter = l;
+        if (sdec == 4) st.capped = 1;
+        st.done = 1;
+        atomicAdd(a.ndone, 1);
+      }
+      return;
+    }
+  }
+
+  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  const int64_t lim = in.base + in.n;  // entries past the instance are padding
+  const int si = pick(a.sel_in, l, st, a.itr_max);
+  T x[R];
+  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, lim, x, T(0));
+  const int E = a.ein[si][run];
+  const ScanConsts& k = in.k;
+  const Lam<T> L = lam_of<T>(k);
+  T af, ab;
+  run_aggs<T, R>(x, L, af, ab);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  inst_carries(a.A_in, in, j, scar);
+  __syncthreads();
+  const XF64 cf64 = scar[0], cb64 = scar[1];
+  S1<T> cf, cb;
+  block_scan<S1<T>, kNW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>{from64<T>(cf64)},
+                            S1<T>{from64<T>(cb64)}, &cf, &cb, nullptr, nullptr, sh);
+  // carries moved one step into the run, in extended range
+  const S1<T> lcf = cf.shift(step_decay<T>(k)), lcb = cb.shift(step_decay<T>(k));
+  int eref = max(local_exponent<T, R>(x, E), max(lcf.v.e, lcb.v.e));
+  if (eref == kExpZero) eref = 0;
+  T xf[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) xf[i] = ldx(x[i], E - eref);
+  T y[R];  // (K vin)_i * 2^-eref
+  run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
+
+  const bool want_err = (MODE == B_ERR) || (MODE == B_PSI && (l % a.check_every) == 0);
+  if (want_err) {
+    const int so = pick(a.sel_own, l, st, a.itr_max);
+    T own[R];
+    load_run<T, R>(static_cast<const T*>(a.vown[so]), base, lim, own, T(0));
+    double mg[R];
+    load_run<double, R>(a.m64, base, lim, mg, 0.0);
+    const int eo = a.eown[so][run];
+    // padding loads as zero and adds nothing
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) s += fabs(ldexp(double(own[i]) * double(y[i]), eo + eref) - mg[i]);
+    const double tot = block_sum<kNW>(s, red);
+    if (threadIdx.x == 0) a.part[c] = tot;
+  }
+  if constexpr (MODE == B_ERR) return;
+
+  // update: out = marg / (K vin)  (zero marginal -> zero scaling), with the
+  // power-of-two part of the run absorbed into its exponent
+  T mg[R];
+  if constexpr (sizeof(T) == 8) {
+    load_run<T, R>(reinterpret_cast<const T*>(a.m64), base, lim, mg, T(0));
+  } else {
+    load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, lim, mg, T(0));
+  }
+  T q[R];
+  bool bad = false;
+  T qm = T(0);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    q[i] = (mg[i] == T(0)) ? T(0) : mg[i] / y[i];
+    bad |= !isfinite(q[i]);
+    if (isfinite(q[i])) qm = fmax(qm, q[i]);
+  }
+  int kq = 0;
+  if (qm > T(0)) frx(qm, &kq);
+#pragma unroll
+  for (int i = 0; i < R; ++i) q[i] = ldx(q[i], -kq);
+  const int Eo = kq - eref;
+  const int sw = pick(a.sel_out, l, st, a.itr_max);
+  store_run<T, R>(static_cast<T*>(a.vout[sw]), base, lim, q);
+  a.eout[sw][run] = Eo;
+  if (bad) {
+    atomicOr(&st.fail, 1);
+    atomicMin(&st.fail_iter, l);
+  }
+  T nf, nb;
+  run_aggs<T, R>(q, L, nf, nb);
+  S1<T> gf, gb;
+  block_scan<S1<T>, kNW, T>(S1<T>{{nf, Eo}}, S1<T>{{nb, Eo}}, dec, S1<T>::zero(), S1<T>::zero(),
+                            nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    a.A_out[c].f = to64(gf.v);
+    a.A_out[c].b = to64(gb.v);
+  }
+}
+
+// Chunk aggregates of a stored vector (initial phi; final psi).
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
+  __shared__ ScanLds<S1<T>, kNW> sh;
+  const int c = a.chunk_off + blockIdx.x;
+  const int b = a.chunk_inst[c];
+  const InstInfo& in = a.inst[b];
+  const int j = c - in.chunk0;
+  const int si = pick(a.sel_in, 0, a.st[b], a.itr_max);
+  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  T x[R];
+  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, in.base + in.n, x, T(0));
+  const int E = a.ein[si][run];
+  const Lam<T> L = lam_of<T>(in.k);
+  T af, ab;
+  run_aggs<T, R>(x, L, af, ab);
+  Dec<T> dec[7];
+  lane_decays<T>(in.k, dec);
+  S1<T> gf, gb;
+  block_scan<S1<T>, kNW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(), S1<T>::zero(),
+                            nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    a.A_out[c].f = to64(gf.v);
+    a.A_out[c].b = to64(gb.v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transport cost per instance: w1 = h sum_i phi_i (D_i + E_i) with the
+// two-state recursions over the final psi.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_bcost_agg(BArgs a, ChunkAgg2* agg2) {
+  __shared__ ScanLds<S2<T>, kNW> sh;
+  const int c = a.chunk_off + blockIdx.x;
+  const int b = a.chunk_inst[c];
+  const InstInfo& in = a.inst[b];
+  const int j = c - in.chunk0;
+  const int si = final_buf(a.st[b], a.itr_max);
+  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  T x[R];
+  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, in.base + in.n, x, T(0));
+  const int E = a.ein[si][run];
+  const Lam<T> L = lam_of<T>(in.k);
+  T fp, fd, bp, bd;
+  run_aggs2<T, R>(x, L, fp, fd, bp, bd);
+  Dec<T> dec[7];
+  lane_decays<T>(in.k, dec);
+  S2<T> gf, gb;
+  block_scan<S2<T>, kNW, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, S2<T>::zero(),
+                            S2<T>::zero(), nullptr, nullptr, &gf, &gb, sh);
+  if (threadIdx.x == 0) {
+    ChunkAgg2 o;
+    s2_put_fwd(o, gf);
+    s2_put_bwd(o, gb);
+    agg2[c] = o;
+  }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_bcost_apply(BArgs a, const ChunkAgg2* agg2) {
+  __shared__ ScanLds<S2<T>, kNW> sh;
+  __shared__ double red[kNW];
+  __shared__ S2<double> scar[2];
+  const int c = a.chunk_off + blockIdx.x;
+  const int b = a.chunk_inst[c];
+  const InstInfo& in = a.inst[b];
+  const int j = c - in.chunk0;
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int si = final_buf(a.st[b], a.itr_max);
+  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  const int64_t lim = in.base + in.n;
+  // chunk carries of the two-state recursion: a state moved by D elements
+  // with zero input is (p, d) -> lambda^D (p, d + D p)
+  const double C = double(kBlock) * R;
+  if (w == 0) {
+    S2<double> acc = S2<double>::zero();
+    for (int i = lane; i < j; i += kWave) {
+      const ChunkAgg2 v = agg2[in.chunk0 + i];
+      const XF<double> p = pow_chunks(j - 1 - i, in.cpow);
+      acc = acc.add(
+          s2_fwd<double>(v).shift(Dec<double>{p.m, p.e, C * double(j - 1 - i)}));
+    }
+    acc = s2_wave_sum(acc);
+    if (lane == 0) scar[0] = acc;
+  } else if (w == 1) {
+    S2<double> acc = S2<double>::zero();
+    for (int i = j + 1 + lane; i < in.nch; i += kWave) {
+      const ChunkAgg2 v = agg2[in.chunk0 + i];
+      const XF<double> p = pow_chunks(i - j - 1, in.cpow);
+      acc = acc.add(
+          s2_bwd<double>(v).shift(Dec<double>{p.m, p.e, C * double(i - j - 1)}));
+    }
+    acc = s2_wave_sum(acc);
+    if (lane == 0) scar[1] = acc;
+  }
+  T x[R];
+  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, lim, x, T(0));
+  const int E = a.ein[si][run];
+  const Lam<T> L = lam_of<T>(in.k);
+  T fp, fd, bp, bd;
+  run_aggs2<T, R>(x, L, fp, fd, bp, bd);
+  Dec<T> dec[7];
+  lane_decays<T>(in.k, dec);
+  __syncthreads();
+  const S2<double> c0 = scar[0], c1 = scar[1];
+  S2<T> cf, cb;
+  block_scan<S2<T>, kNW, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, s2_cast<T>(c0),
+                            s2_cast<T>(c1), &cf, &cb, nullptr, nullptr, sh);
+  const S2<T> lcf = cf.shift(step_decay<T>(in.k)), lcb = cb.shift(step_decay<T>(in.k));
+  const int eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, E), in.k);
+  T xf[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) xf[i] = ldx(x[i], E - eref);
+  T wv[R];
+  run_cost<T, R>(xf, ldx(lcf.p.m, lcf.p.e - eref), ldx(lcf.d.m, lcf.d.e - eref),
+                 ldx(lcb.p.m, lcb.p.e - eref), ldx(lcb.d.m, lcb.d.e - eref), L, wv);
+  T ph[R];
+  load_run<T, R>(static_cast<const T*>(a.vown[0]), base, lim, ph, T(0));
+  const int ep = a.eown[0][run];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) s += ldexp(double(ph[i]) * double(wv[i]), ep + eref);
+  const double tot = block_sum<kNW>(s, red);
+  if (threadIdx.x == 0) a.part[c] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up and finalisation
+// ---------------------------------------------------------------------------
+// Pack the caller's marginals chunk-aligned (binary64, plus binary32 copies),
+// set phi = psi = 1/n with exponent 0, and write per-chunk masses.
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, const double* mu, const double* nu,
+                                                   double* mu64, double* nu64, float* mu32,
+                                                   float* nu32, T* vF, T* vG0, int* eF,
+                                                   int* eG0, double* pmu, double* pnu) {
+  __shared__ double red[kNW];
+  const int c = a.chunk_off + blockIdx.x;
+  const int b = a.chunk_inst[c];
+  const InstInfo& in = a.inst[b];
+  const int j = c - in.chunk0;
+  const int64_t local0 = int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t base = in.base + local0;
+  const T init = T(1.0 / double(in.n));
+  double sm = 0.0, sn = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int64_t loc = local0 + i;
+    double u = 0.0, v = 0.0;
+    if (loc < in.n) {
+      u = mu[in.off + loc];
+      v = nu[in.off + loc];
+      bad |= !(isfinite(u) && u >= 0.0) || !(isfinite(v) && v >= 0.0);
+    }
+    mu64[base + i] = u;
+    nu64[base + i] = v;
+    if (mu32) {
+      mu32[base + i] = float(u);
+      nu32[base + i] = float(v);
+    }
+    vF[base + i] = (loc < in.n) ? init : T(0);
+    vG0[base + i] = (loc < in.n) ? init : T(0);
+    sm += u;
+    sn += v;
+  }
+  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  eF[run] = 0;
+  eG0[run] = 0;
+  const double tm = block_sum<kNW>(sm, red);
+  const double tn = block_sum<kNW>(sn, red);
+  if (bad) atomicOr(&a.st[b].bad_input, 1);
+  if (threadIdx.x == 0) {
+    pmu[c] = tm;
+    pnu[c] = tn;
+  }
+}
+
+// Per instance (one thread each): masses positive, finite and equal to
+// 1e-10 relative; otherwise the instance is stopped before its first iteration.
+__global__ void k_bvalidate(const InstInfo* inst, InstState* st, const double* pmu,
+                            const double* pnu, int b0, int B, int* ndone) {
+  const int b = b0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= b0 + B) return;
+  const InstInfo& in = inst[b];
+  double sm = 0.0, sn = 0.0;
+  for (int i = 0; i < in.nch; ++i) {
+    sm += pmu[in.chunk0 + i];
+    sn += pnu[in.chunk0 + i];
+  }
+  InstState& s = st[b];
+  s.sum_mu = sm;
+  s.sum_nu = sn;
+  const bool ok = !s.bad_input && isfinite(sm) && isfinite(sn) && sm > 0.0 && sn > 0.0 &&
+                  fabs(sm - sn) <= 1e-10 * sm;
+  if (!ok) {
+    s.invalid = 1;
+    s.done = 1;
+    atomicAdd(ndone, 1);
+  }
+}
+
+__global__ void k_badvance(int* iter_base, int by) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iter_base += by;
+}
+
+// Per instance fixed-order sums of the per-chunk shares.
+__global__ void k_bfinal(const InstInfo* inst, InstState* st, const double* perr,
+                         const double* pmu, const double* pcost, int b0, int B) {
+  const int b = b0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= b0 + B) return;
+  const InstInfo& in = inst[b];
+  double e = 0.0, m = 0.0, w = 0.0;
+  for (int i = 0; i < in.nch; ++i) {
+    e += perr[in.chunk0 + i];
+    m += pmu[in.chunk0 + i];
+    w += pcost[in.chunk0 + i];
+  }
+  st[b].err = e;
+  st[b].mu_err = m;
+  st[b].w1 = w * in.h;
+}
+
+template <typename T, int R>
+struct BatchOps {
+  static BArgs base(const BatchBufs& z, const BatchGroup& g) {
+    BArgs a{};
+    a.inst = z.inst;
+    a.st = z.st;
+    a.chunk_inst = z.chunk_inst;
+    a.iter_base = z.iter_base;
+    a.ndone = z.ndone;
+    a.itr_max = z.itr_max;
+    a.check_every = z.check_every;
+    a.chunk_off = g.chunk0;
+    return a;
+  }
+  static void set_phi_in(BArgs& a, const BatchBufs& z) {
+    a.vin[0] = a.vin[1] = z.vF;
+    a.ein[0] = a.ein[1] = z.eF;
+  }
+  static void set_psi_in(BArgs& a, const BatchBufs& z, int sel) {
+    a.vin[0] = z.vG[0];
+    a.vin[1] = z.vG[1];
+    a.ein[0] = z.eG[0];
+    a.ein[1] = z.eG[1];
+    a.sel_in = sel;
+  }
+  static hipError_t setup(const BatchBufs& z, const BatchGroup& g, const double* mu,
+                          const double* nu, hipStream_t s) {
+    BArgs a = base(z, g);
+    k_bsetup<T, R><<<unsigned(g.nchunks), kBlock, 0, s>>>(
+        a, mu, nu, z.mu64, z.nu64, static_cast<float*>(z.mu32), static_cast<float*>(z.nu32),
+        static_cast<T*>(z.vF), static_cast<T*>(z.vG[0]), z.eF, z.eG[0], z.part, z.part2);
+    return hipGetLastError();
+  }
+  static hipError_t publish_phi(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
+    BArgs a = base(z, g);
+    set_phi_in(a, z);
+    a.A_out = z.aggF;
+    k_bpublish<T, R><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+  }
+  static hipError_t half(const BatchBufs& z, const BatchGroup& g, bool psi, int l_local,
+                         hipStream_t s) {
+    BArgs a = base(z, g);
+    a.l_local = l_local;
+    a.part = z.part;
+    if (psi) {
+      // psi^{l+1} = nu / K^T phi^l into buffer (l+1)&1; error of (phi^l, psi^l)
+      set_phi_in(a, z);
+      a.vown[0] = z.vG[0];
+      a.vown[1] = z.vG[1];
+      a.eown[0] = z.eG[0];
+      a.eown[1] = z.eG[1];
+      a.sel_own = SEL_CUR;
+      a.vout[0] = z.vG[0];
+      a.vout[1] = z.vG[1];
+      a.eout[0] = z.eG[0];
+      a.eout[1] = z.eG[1];
+      a.sel_out = SEL_NEXT;
+      a.m64 = z.nu64;
+      a.m32 = static_cast<const float*>(z.nu32);
+      a.A_in = z.aggF;
+      a.A_out = z.aggG;
+      k_bhalf<T, R, B_PSI><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+    } else {
+      // phi^{l+1} = mu / K psi^{l+1}
+      set_psi_in(a, z, SEL_NEXT);
+      a.vout[0] = a.vout[1] = z.vF;
+      a.eout[0] = a.eout[1] = z.eF;
+      a.m64 = z.mu64;
+      a.m32 = static_cast<const float*>(z.mu32);
+      a.A_in = z.aggG;
+      a.A_out = z.aggF;
+      k_bhalf<T, R, B_PHI><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+    }
+    return hipGetLastError();
+  }
+  static hipError_t finalize(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
+    const unsigned grid = unsigned(g.nchunks);
+    // nu side: | psi (K^T phi) - nu |; the aggregates of the final phi are in aggF
+    BArgs a = base(z, g);
+    set_phi_in(a, z);
+    a.vown[0] = z.vG[0];
+    a.vown[1] = z.vG[1];
+    a.eown[0] = z.eG[0];
+    a.eown[1] = z.eG[1];
+    a.sel_own = SEL_FINAL;
+    a.m64 = z.nu64;
+    a.A_in = z.aggF;
+    a.part = z.part;
+    k_bhalf<T, R, B_ERR><<<grid, kBlock, 0, s>>>(a);
+    // aggregates of the final psi, then mu side: | phi (K psi) - mu |
+    BArgs p = base(z, g);
+    set_psi_in(p, z, SEL_FINAL);
+    p.A_out = z.aggG;
+    k_bpublish<T, R><<<grid, kBlock, 0, s>>>(p);
+    BArgs m = base(z, g);
+    set_psi_in(m, z, SEL_FINAL);
+    m.vown[0] = m.vown[1] = z.vF;
+    m.eown[0] = m.eown[1] = z.eF;
+    m.m64 = z.mu64;
+    m.A_in = z.aggG;
+    m.part = z.part2;
+    k_bhalf<T, R, B_ERR><<<grid, kBlock, 0, s>>>(m);
+    // transport cost
+    BArgs w = base(z, g);
+    set_psi_in(w, z, SEL_FINAL);
+    w.vown[0] = w.vown[1] = z.vF;
+    w.eown[0] = w.eown[1] = z.eF;
+    w.part = z.part3;
+    k_bcost_agg<T, R><<<grid, kBlock, 0, s>>>(w, static_cast<ChunkAgg2*>(z.agg2));
+    k_bcost_apply<T, R><<<grid, kBlock, 0, s>>>(w, static_cast<const ChunkAgg2*>(z.agg2));
+    return hipGetLastError();
+  }
+};
+
+template <typename F>
+hipError_t bdispatch(int dtype, int R, F&& f) {
+  if (dtype == 0) {
+    switch (R) {
+      case 8: return f(BatchOps<double, 8>{});
+      case 1: return f(BatchOps<double, 1>{});
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (R) {
+    case 16: return f(BatchOps<float, 16>{});
+    case 8: return f(BatchOps<float, 8>{});
+    case 4: return f(BatchOps<float, 4>{});
+    case 1: return f(BatchOps<float, 1>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+InstInfo make_inst_info(int64_t off, int64_t base, int64_t n, int chunk0, int R, double h,
+                        double eps, double tol, int l0) {
+  InstInfo in{};
+  const int64_t C = int64_t(kBlock) * R;
+  in.off = off;
+  in.base = base;
+  in.n = int32_t(n);
+  in.nch = int32_t((n + C - 1) / C);
+  in.chunk0 = chunk0;
+  in.l0 = l0;
+  in.h = h;
+  in.tol = tol;
+  in.k = make_scan_consts(h, eps, R);
+  for (int s = 0; s < kInstPow; ++s) in.cpow[s] = make_decay(double(C) * double(1ll << s), h / eps);
+  return in;
+}
+
+hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
+                              const double* mu, const double* nu, int B, hipStream_t s) {
+  for (int i = 0; i < ngroups; ++i) {
+    const BatchGroup& g = groups[i];
+    const hipError_t e =
+        bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::setup(z, g, mu, nu, s); });
+    if (e != hipSuccess) return e;
+  }
+  k_bvalidate<<<unsigned((B + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2, 0, B,
+                                                       z.ndone);
+  for (int i = 0; i < ngroups; ++i) {
+    const BatchGroup& g = groups[i];
+    const hipError_t e =
+        bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::publish_phi(z, g, s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups, int ngroups,
+                                   int count, hipStream_t s) {
+  for (int l = 0; l < count; ++l) {
+    for (int psi = 1; psi >= 0; --psi) {
+      for (int i = 0; i < ngroups; ++i) {
+        const BatchGroup& g = groups[i];
+        const hipError_t e = bdispatch(
+            z.dtype, g.R, [&](auto ops) { return decltype(ops)::half(z, g, psi != 0, l, s); });
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  k_badvance<<<1, kWave, 0, s>>>(z.iter_base, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, int ngroups,
+                                 int B, hipStream_t s) {
+  for (int i = 0; i < ngroups; ++i) {
+    const BatchGroup& g = groups[i];
+    const hipError_t e =
+        bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::finalize(z, g, s); });
+    if (e != hipSuccess) return e;
+  }
+  k_bfinal<<<unsigned((B + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2, z.part3, 0,
+                                                    B);
+  return hipGetLastError();
+}
+
+}  // namespace fs1

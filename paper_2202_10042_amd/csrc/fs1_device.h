@@ -23,6 +23,7 @@
 namespace fs1 {
 
 static constexpr double kLog2E = 1.4426950408889634074;
+static constexpr double kLog2ELo = 2.0355273740931033e-17;  // log2(e) - kLog2E
 static constexpr double kLn2 = 0.69314718055994530942;
 
 // ---------------------------------------------------------------------------
@@ -99,13 +100,6 @@ __device__ __forceinline__ Dec<T> dec_of(const Decay& d, double dist) {
   return {T(d.m), d.e, dist};
 }
 
-// lambda^D on the device from D * c * log2(e): mantissa 2^(k - t) in [1, 2),
-// exponent -k, k = ceil(t).
-__device__ __forceinline__ Decay dev_decay(double t) {
-  const double k = ceil(t);
-  return {exp2(k - t), -int(k), 0};
-}
-
 // ---------------------------------------------------------------------------
 // The lambda-recursion step in the working precision.
 //   lambda a + x:  fma(lambda, a, x), or (a + x) - mu a with mu = 1 - lambda when
@@ -155,35 +149,31 @@ struct S1 {
 //   p_i = sum_{j<=i} x_j lambda^{i-j},  D_i = sum_{j<=i} x_j lambda^{i-j} (i-j)
 // (and the mirrored pair backwards).  Shifting by D elements with zero input:
 //   (p, D) -> (lambda^D p, lambda^D (D + D_elems p)).
-// Both components share one exponent.
+// Each component is its own extended number: D can sit far below p (by the
+// factor lambda when h/eps is large), beyond the range of one shared exponent.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct S2 {
-  T p;
-  T d;
-  int e;
-  __device__ __forceinline__ static S2 zero() { return {T(0), T(0), kExpZero}; }
+  XF<T> p;
+  XF<T> d;
+  __device__ __forceinline__ static S2 zero() { return {xzero<T>(), xzero<T>()}; }
+  __device__ __forceinline__ static S2 of(T p, T d, int e) { return {xnorm(p, e), xnorm(d, e)}; }
   __device__ __forceinline__ S2 shift(const Dec<T>& dc) const {
-    if (p == T(0) && d == T(0)) return zero();
-    return {p * dc.m, (d + T(dc.dist) * p) * dc.m, e + dc.e};
+    const XF<T> lam = {dc.m, dc.e};
+    const XF<T> dp = xadd(d, XF<T>{p.m * T(dc.dist), p.e});
+    return {xmul(p, lam), xmul(dp, lam)};
   }
-  __device__ __forceinline__ S2 add(const S2& o) const {
-    const int ee = max(e, o.e);
-    return {ldx(p, e - ee) + ldx(o.p, o.e - ee), ldx(d, e - ee) + ldx(o.d, o.e - ee), ee};
-  }
-  __device__ __forceinline__ S2 norm() const {
-    const T big = fmax(fabs(p), fabs(d));
-    if (big == T(0)) return zero();
-    if (!isfinite(big)) return {p, d, 0};
-    int k;
-    frx(big, &k);
-    return {ldx(p, -k), ldx(d, -k), e + k};
-  }
+  __device__ __forceinline__ S2 add(const S2& o) const { return {xadd(p, o.p), xadd(d, o.d)}; }
+  __device__ __forceinline__ S2 norm() const { return {xnorm(p), xnorm(d)}; }
   __device__ __forceinline__ S2 shfl_up(int dd) const {
-    return {__shfl_up(p, dd), __shfl_up(d, dd), __shfl_up(e, dd)};
+    return {{__shfl_up(p.m, dd), __shfl_up(p.e, dd)}, {__shfl_up(d.m, dd), __shfl_up(d.e, dd)}};
   }
   __device__ __forceinline__ S2 shfl_down(int dd) const {
-    return {__shfl_down(p, dd), __shfl_down(d, dd), __shfl_down(e, dd)};
+    return {{__shfl_down(p.m, dd), __shfl_down(p.e, dd)},
+            {__shfl_down(d.m, dd), __shfl_down(d.e, dd)}};
+  }
+  __device__ __forceinline__ S2 shfl_xor(int dd) const {
+    return {{__shfl_xor(p.m, dd), __shfl_xor(p.e, dd)}, {__shfl_xor(d.m, dd), __shfl_xor(d.e, dd)}};
   }
 };
 
@@ -366,11 +356,16 @@ __device__ __forceinline__ void load_log_run(const T* __restrict__ lx, int64_t b
                                              T (&x)[R], int& E) {
   T raw[R];
   load_run<T, R>(lx, base, n, raw, T(-INFINITY));
-  double t[R];
+  // t = lx log2(e) as t + te with log2(e) split into two doubles: the rounding
+  // of the product alone would be an absolute error of about u |lx| in the
+  // exponent, large against the output when lx is far from ln y
+  double t[R], te[R];
   double tmax = -INFINITY;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    t[j] = double(raw[j]) * kLog2E;
+    const double v = double(raw[j]);
+    t[j] = v * kLog2E;
+    te[j] = isfinite(t[j]) ? fma(v, kLog2E, -t[j]) + v * kLog2ELo : 0.0;
     if (isfinite(t[j])) tmax = fmax(tmax, t[j]);
   }
   double Ed = (tmax == -INFINITY) ? 0.0 : floor(tmax);
@@ -383,7 +378,7 @@ __device__ __forceinline__ void load_log_run(const T* __restrict__ lx, int64_t b
   for (int j = 0; j < R; ++j) {
     if (isfinite(t[j])) {
       const double k = floor(t[j]);
-      const double f = t[j] - k;  // exact, in [0, 1)
+      const double f = (t[j] - k) + te[j];  // t - k exact, in [0, 1)
       const int sh = int(fmax(k - Ed, -2000.0));
       if constexpr (sizeof(T) == 8) {
         x[j] = ldexp(exp2(f), sh);
@@ -439,23 +434,135 @@ __device__ __forceinline__ int local_exponent(const T (&x)[R], int E) {
 }
 
 // Both recursions of eq. (recursion) over one run, in the run's frame:
-// y_k = p_k + q_k with p fed by cf (state before the run) and q by cb
-// (inclusive backward state after the run).
+// y_k = p_k + q_k.  The carries come in already moved one step into the run:
+// lcf = lambda * (forward state before the run), lcb = lambda * (inclusive
+// backward state after the run).  Callers form them in extended range
+// (step_in), so a lambda below the working precision's normal range (large
+// h/eps, where runs have length 1) never multiplies a plain value.
 template <typename T, int R>
-__device__ __forceinline__ void run_apply(const T (&xf)[R], T cf, T cb, const Lam<T>& L,
+__device__ __forceinline__ void run_apply(const T (&xf)[R], T lcf, T lcb, const Lam<T>& L,
                                           T (&y)[R]) {
-  T A = cf;
+  T A = lcf + xf[0];
+  y[0] = A;
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
+  for (int j = 1; j < R; ++j) {
     A = L.axpy(A, xf[j]);
     y[j] = A;
   }
-  T P = cb;
+  T B = lcb;
+  y[R - 1] += B;
+  T P = B + xf[R - 1];
 #pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    const T B = L.mul(P);
+  for (int j = R - 2; j >= 0; --j) {
+    B = L.mul(P);
     y[j] += B;
     P = B + xf[j];
+  }
+}
+
+// lambda^1 as a decay (one grid step)
+template <typename T>
+__device__ __forceinline__ Dec<T> step_decay(const ScanConsts& k) {
+  return dec_of<T>(k.step1, 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// Transport cost: W = h sum_i phi_i (D_i + E_i), with
+//   D_i = sum_{j<i} psi_j lambda^{i-j} (i-j),  E_i = sum_{j>i} psi_j lambda^{j-i} (j-i).
+// Forward pair (p, D): D <- lambda (D + p), p <- lambda p + psi_j; the
+// backward pair mirrors it.  These follow from splitting |i-j| in the double
+// sum of Algorithm 1's return into j < i and j > i.
+// ---------------------------------------------------------------------------
+// Forward and backward two-state aggregates (or carries) of one chunk, with
+// the exponents of p and D.
+struct ChunkAgg2 {
+  double fp, fd;
+  int fpe, fde;
+  double bp, bd;
+  int bpe, bde;
+};
+
+template <typename T>
+__device__ __forceinline__ S2<T> s2_fwd(const ChunkAgg2& a) {
+  return {{T(a.fp), a.fpe}, {T(a.fd), a.fde}};
+}
+template <typename T>
+__device__ __forceinline__ S2<T> s2_bwd(const ChunkAgg2& a) {
+  return {{T(a.bp), a.bpe}, {T(a.bd), a.bde}};
+}
+template <typename T>
+__device__ __forceinline__ S2<T> s2_cast(const S2<double>& s) {
+  return {{T(s.p.m), s.p.e}, {T(s.d.m), s.d.e}};
+}
+template <typename T>
+__device__ __forceinline__ void s2_put_fwd(ChunkAgg2& o, const S2<T>& s) {
+  o.fp = double(s.p.m);
+  o.fpe = s.p.e;
+  o.fd = double(s.d.m);
+  o.fde = s.d.e;
+}
+template <typename T>
+__device__ __forceinline__ void s2_put_bwd(ChunkAgg2& o, const S2<T>& s) {
+  o.bp = double(s.p.m);
+  o.bpe = s.p.e;
+  o.bd = double(s.d.m);
+  o.bde = s.d.e;
+}
+
+// Frame of a run's cost outputs w = D + E: the shifted carries' D parts and,
+// within runs of R > 1, lambda times the largest local value (bounded so that
+// the local values themselves stay finite in the frame).
+template <typename T, int R>
+__device__ __forceinline__ int cost_frame(const S2<T>& lcf, const S2<T>& lcb, int eloc,
+                                          const ScanConsts& k) {
+  int eref = max(lcf.d.e, lcb.d.e);
+  if (R > 1 && eloc != kExpZero) eref = max(eref, eloc + max(k.step1.e + 1, -60));
+  return eref == kExpZero ? 0 : eref;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void run_aggs2(const T (&x)[R], const Lam<T>& L, T& fp, T& fd, T& bp,
+                                          T& bd) {
+  T p = T(0), d = T(0);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    d = L.mul(d + p);
+    p = L.axpy(p, x[j]);
+  }
+  T q = T(0), e = T(0);
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {
+    e = L.mul(e + q);
+    q = L.axpy(q, x[j]);
+  }
+  fp = p;
+  fd = d;
+  bp = q;
+  bd = e;
+}
+
+// w_k = D_k + E_k over one run, in the run's frame, from the two-state carries
+// moved one step into the run (S2::shift by lambda^1, in extended range):
+// (lfp, lfd) = lambda (p, D + p) of the state before the run, (lbp, lbd) the
+// same of the inclusive backward state after the run.
+template <typename T, int R>
+__device__ __forceinline__ void run_cost(const T (&xf)[R], T lfp, T lfd, T lbp, T lbd,
+                                         const Lam<T>& L, T (&w)[R]) {
+  T p = lfp + xf[0], d = lfd;
+  w[0] = d;
+#pragma unroll
+  for (int j = 1; j < R; ++j) {
+    d = L.mul(d + p);
+    p = L.axpy(p, xf[j]);
+    w[j] = d;
+  }
+  T q = lbp + xf[R - 1], e = lbd;
+  w[R - 1] += e;
+#pragma unroll
+  for (int j = R - 2; j >= 0; --j) {
+    e = L.mul(e + q);
+    q = L.axpy(q, xf[j]);
+    w[j] += e;
   }
 }
 

@@ -282,7 +282,7 @@ __device__ __forceinline__ int half_apply(const ChunkAgg* A, int nchunks, const 
   T xf[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) xf[j] = ldx(hs.xf[j], sh);
-  run_apply<T, R>(xf, tcf, tcb, L, y);
+  run_apply<T, R>(xf, L.mul(tcf), L.mul(tcb), L, y);
   return eap;
 }
 
@@ -307,7 +307,7 @@ __device__ __forceinline__ int frame_apply(const Lam<T>& L, const FastDec<T>& D,
   T xf[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) xf[j] = ldx(hs.xf[j], sh);
-  run_apply<T, R>(xf, tcf, tcb, L, y);
+  run_apply<T, R>(xf, L.mul(tcf), L.mul(tcb), L, y);
   return eap;
 }
 

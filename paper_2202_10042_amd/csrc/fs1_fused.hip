@@ -198,8 +198,8 @@ struct FusedOps {
     a.n = b.n;
     a.nchunks = int(b.nchunks);
     a.tol = tol;
-    const double cl = k.c_log2e * double(kBlock) * double(R);
-    for (int i = 0; i < 20; ++i) a.cpow[i] = make_decay(cl * double(1ll << i));
+    for (int i = 0; i < 20; ++i)
+      a.cpow[i] = make_decay(double(kBlock) * double(R) * double(1ll << i), k.c);
     return a;
   }
   static hipError_t half(const SolveBufs& b, const ScanConsts& k, int l, int check, double tol,

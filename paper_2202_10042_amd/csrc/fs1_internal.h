@@ -41,11 +41,13 @@ struct Decay {
 struct ScanConsts {
   double lam;        // lambda = exp(-h/eps)
   double mu;         // 1 - lambda (used when lambda > 1/2: lam*a + x = (a+x) - mu*a)
+  double c;          // h / eps
   double c_log2e;    // (h/eps) * log2(e): log2 of 1/lambda
   int use_mu;        // 1 when lambda > 1/2
   int R;             // elements per thread run
   Decay lane[7];     // lambda^(R * 2^s), s = 0..6 (s = 6: one wavefront span)
   Decay chunk;       // lambda^(chunk length)
+  Decay step1;       // lambda itself (one grid step), in extended range
 };
 
 // Constants of the single-block carry scan over chunk aggregates.
@@ -81,7 +83,7 @@ struct Ctrl {
 // ---------------------------------------------------------------------------
 // Host-side helpers (fs1_kernels.hip)
 // ---------------------------------------------------------------------------
-Decay make_decay(double dist_c_log2e);  // lambda^D from D * c * log2(e)
+Decay make_decay(double D, double c);  // lambda^D = exp(-D c), D a whole number
 ScanConsts make_scan_consts(double h, double eps, int R);
 CarryConsts make_carry_consts(double h, double eps, int64_t chunk_len, int64_t nchunks);
 int pick_run_length(int dtype, bool absorb, double c);  // R for a solve / log apply

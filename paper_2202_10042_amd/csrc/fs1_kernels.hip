@@ -29,11 +29,28 @@ namespace fs1 {
 // ===========================================================================
 // Host helpers
 // ===========================================================================
-Decay make_decay(double t) {
-  // lambda^D = 2^-t, t = D * c * log2(e) >= 0:  2^(k - t) * 2^-k, k = ceil(t)
-  const double k = std::ceil(t);
+Decay make_decay(double D, double c) {
+  // lambda^D = 2^-t, t = D c log2(e) >= 0:  2^(k - t) * 2^-k with k = ceil(t).
+  // t is formed as an unevaluated sum t_hi + t_lo (the product D c is exact as
+  // hi + lo for integer D, log2(e) is split into two doubles), so lambda^D keeps
+  // full relative precision however large D c gets.
+  constexpr double kL2eHi = 1.4426950408889634;     // log2(e) rounded
+  constexpr double kL2eLo = 2.0355273740931033e-17;  // log2(e) - kL2eHi
+  const double p_hi = D * c;
+  const double p_lo = std::fma(D, c, -p_hi);
+  const double t_hi = p_hi * kL2eHi;
+  const double t_lo = std::fma(p_hi, kL2eHi, -t_hi) + (p_hi * kL2eLo + p_lo * kL2eHi);
+  double k = std::ceil(t_hi);
+  double f = (k - t_hi) - t_lo;  // k - t_hi is exact
+  if (f < 0.0) {
+    k += 1.0;
+    f += 1.0;
+  } else if (f >= 1.0) {
+    k -= 1.0;
+    f -= 1.0;
+  }
   Decay d;
-  d.m = std::exp2(k - t);
+  d.m = std::exp2(f);
   d.e = -int(k);
   d.pad = 0;
   return d;
@@ -45,22 +62,23 @@ ScanConsts make_scan_consts(double h, double eps, int R) {
   k.lam = std::exp(-c);
   k.mu = -std::expm1(-c);
   k.use_mu = k.lam > 0.5 ? 1 : 0;
+  k.c = c;
   k.c_log2e = c * kLog2E;
   k.R = R;
-  for (int s = 0; s < 7; ++s) k.lane[s] = make_decay(double(R) * double(1 << s) * k.c_log2e);
-  k.chunk = make_decay(double(kBlock) * double(R) * k.c_log2e);
+  for (int s = 0; s < 7; ++s) k.lane[s] = make_decay(double(R) * double(1 << s), c);
+  k.chunk = make_decay(double(kBlock) * double(R), c);
+  k.step1 = make_decay(1.0, c);
   return k;
 }
 
 CarryConsts make_carry_consts(double h, double eps, int64_t chunk_len, int64_t nchunks) {
   CarryConsts kc{};
-  const double cl = (h / eps) * kLog2E;
   kc.nchunks = nchunks;
   kc.group = (nchunks + kCarryBlock - 1) / kCarryBlock;
   kc.chunk_len = chunk_len;
-  kc.chunk = make_decay(double(chunk_len) * cl);
+  kc.chunk = make_decay(double(chunk_len), h / eps);
   for (int s = 0; s < 7; ++s)
-    kc.step[s] = make_decay(double(kc.group) * double(chunk_len) * double(1 << s) * cl);
+    kc.step[s] = make_decay(double(kc.group) * double(chunk_len) * double(1 << s), h / eps);
   return kc;
 }
 
@@ -200,16 +218,18 @@ __global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
   block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
                                        S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
                                        nullptr, nullptr, sh);
+  // carries moved one step into the run, in extended range
+  const S1<T> lcf = cf.shift(step_decay<T>(k)), lcb = cb.shift(step_decay<T>(k));
   int eref = 0;
   if constexpr (LOG) {
-    eref = max(local_exponent<T, R>(x, E), max(cf.v.e, cb.v.e));
+    eref = max(local_exponent<T, R>(x, E), max(lcf.v.e, lcb.v.e));
     if (eref == kExpZero) eref = 0;
   }
   T xf[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
   T y[R];
-  run_apply<T, R>(xf, ldx(cf.v.m, cf.v.e - eref), ldx(cb.v.m, cb.v.e - eref), L, y);
+  run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
   if constexpr (LOG) {
     // ln y = (log2 f + k + eref) ln 2 with y = f 2^k, f in [1/2, 1): only the
     // mantissa goes through the logarithm, so outputs far below the run's
@@ -288,16 +308,17 @@ __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
   block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
                                        S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
                                        nullptr, nullptr, sh);
+  const S1<T> lcf = cf.shift(step_decay<T>(k)), lcb = cb.shift(step_decay<T>(k));
   int eref = 0;
   if constexpr (ABSORB) {
-    eref = max(local_exponent<T, R>(x, E), max(cf.v.e, cb.v.e));
+    eref = max(local_exponent<T, R>(x, E), max(lcf.v.e, lcb.v.e));
     if (eref == kExpZero) eref = 0;
   }
   T xf[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
   T y[R];  // (K in)_j * 2^-eref
-  run_apply<T, R>(xf, ldx(cf.v.m, cf.v.e - eref), ldx(cb.v.m, cb.v.e - eref), L, y);
+  run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
 
   // error term sum_j | own_j (K in)_j - marg_j |, binary64
   const bool want_err = (MODE == MODE_ERR) || (MODE == MODE_PSI && a.check);
@@ -366,45 +387,8 @@ __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
 }
 
 // ===========================================================================
-// Transport cost: W = h sum_i phi_i (D_i + E_i), with
-//   D_i = sum_{j<i} psi_j lambda^{i-j} (i-j),  E_i = sum_{j>i} psi_j lambda^{j-i} (j-i).
-// Forward pair (p, D): D <- lambda (D + p), p <- lambda p + psi_j; the
-// backward pair mirrors it.  These follow from splitting |i-j| in the double
-// sum of Algorithm 1's return into j < i and j > i.
+// Transport cost (two-state recursions of fs1_device.h)
 // ===========================================================================
-struct ChunkAgg2 {
-  double fp, fd;
-  int fe, pad0;
-  double bp, bd;
-  int be, pad1;
-};
-
-template <typename T>
-__device__ __forceinline__ S2<T> s2_of(double p, double d, int e) {
-  return {T(p), T(d), e};
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void run_aggs2(const T (&x)[R], const Lam<T>& L, T& fp, T& fd, T& bp,
-                                          T& bd) {
-  T p = T(0), d = T(0);
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    d = L.mul(d + p);
-    p = L.axpy(p, x[j]);
-  }
-  T q = T(0), e = T(0);
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    e = L.mul(e + q);
-    q = L.axpy(q, x[j]);
-  }
-  fp = p;
-  fd = d;
-  bp = q;
-  bd = e;
-}
-
 template <typename T, int R, bool ABSORB>
 __global__ __launch_bounds__(kBlock) void k_cost_agg(const T* __restrict__ v,
                                                      const int* __restrict__ ex, int64_t n,
@@ -420,18 +404,13 @@ __global__ __launch_bounds__(kBlock) void k_cost_agg(const T* __restrict__ v,
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
   S2<T> gf, gb;
-  block_scan<S2<T>, kBlock / kWave, T>(S2<T>{fp, fd, E}, S2<T>{bp, bd, E}, dec, S2<T>::zero(),
-                                       S2<T>::zero(), nullptr, nullptr, &gf, &gb, sh);
+  block_scan<S2<T>, kBlock / kWave, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec,
+                                       S2<T>::zero(), S2<T>::zero(), nullptr, nullptr, &gf, &gb,
+                                       sh);
   if (threadIdx.x == 0) {
     ChunkAgg2 o;
-    o.fp = gf.p;
-    o.fd = gf.d;
-    o.fe = gf.e;
-    o.pad0 = 0;
-    o.bp = gb.p;
-    o.bd = gb.d;
-    o.be = gb.e;
-    o.pad1 = 0;
+    s2_put_fwd(o, gf);
+    s2_put_bwd(o, gb);
     agg[blockIdx.x] = o;
   }
 }
@@ -447,10 +426,10 @@ __global__ __launch_bounds__(kCarryBlock) void k_cost_carry(const ChunkAgg2* __r
   const Dec<double> cdec = dec_of<double>(kc.chunk, double(kc.chunk_len));
   S2<double> gf = S2<double>::zero(), gb = S2<double>::zero();
   for (int64_t c = g0; c < g1; ++c)
-    gf = gf.shift(cdec).add(s2_of<double>(agg[c].fp, agg[c].fd, agg[c].fe)).norm();
+    gf = gf.shift(cdec).add(s2_fwd<double>(agg[c])).norm();
   // (a group cut short by nchunks only feeds empty groups; see k_carry)
   for (int64_t c = g1 - 1; c >= g0; --c)
-    gb = gb.shift(cdec).add(s2_of<double>(agg[c].bp, agg[c].bd, agg[c].be)).norm();
+    gb = gb.shift(cdec).add(s2_bwd<double>(agg[c])).norm();
   Dec<double> dec[7];
 #pragma unroll
   for (int s = 0; s < 7; ++s)
@@ -460,17 +439,13 @@ __global__ __launch_bounds__(kCarryBlock) void k_cost_carry(const ChunkAgg2* __r
                                      &cb, nullptr, nullptr, sh);
   S2<double> r = cf;
   for (int64_t c = g0; c < g1; ++c) {
-    carry[c].fp = r.p;
-    carry[c].fd = r.d;
-    carry[c].fe = r.e;
-    r = r.shift(cdec).add(s2_of<double>(agg[c].fp, agg[c].fd, agg[c].fe)).norm();
+    s2_put_fwd(carry[c], r);
+    r = r.shift(cdec).add(s2_fwd<double>(agg[c])).norm();
   }
   r = cb;
   for (int64_t c = g1 - 1; c >= g0; --c) {
-    carry[c].bp = r.p;
-    carry[c].bd = r.d;
-    carry[c].be = r.e;
-    r = r.shift(cdec).add(s2_of<double>(agg[c].bp, agg[c].bd, agg[c].be)).norm();
+    s2_put_bwd(carry[c], r);
+    r = r.shift(cdec).add(s2_bwd<double>(agg[c])).norm();
   }
 }
 
@@ -496,33 +471,18 @@ __global__ __launch_bounds__(kBlock) void k_cost_apply(const T* __restrict__ vph
   lane_decays<T>(k, dec);
   const ChunkAgg2 cg = carry[blockIdx.x];
   S2<T> cf, cb;
-  block_scan<S2<T>, kBlock / kWave, T>(S2<T>{fp, fd, E}, S2<T>{bp, bd, E}, dec,
-                                       s2_of<T>(cg.fp, cg.fd, cg.fe),
-                                       s2_of<T>(cg.bp, cg.bd, cg.be), &cf, &cb, nullptr, nullptr,
+  block_scan<S2<T>, kBlock / kWave, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec,
+                                       s2_fwd<T>(cg), s2_bwd<T>(cg), &cf, &cb, nullptr, nullptr,
                                        sh);
-  // frame: every source is brought below 2^eref
-  int eref = local_exponent<T, R>(x, E);
-  if (cf.p != T(0) || cf.d != T(0)) eref = max(eref, cf.e);
-  if (cb.p != T(0) || cb.d != T(0)) eref = max(eref, cb.e);
-  if (eref == kExpZero) eref = 0;
+  // carries moved one step into the run (extended range)
+  const S2<T> lcf = cf.shift(step_decay<T>(k)), lcb = cb.shift(step_decay<T>(k));
+  const int eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, E), k);
   T xf[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) xf[j] = ldx(x[j], E - eref);
-  T p = ldx(cf.p, cf.e - eref), d = ldx(cf.d, cf.e - eref);
   T w[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    d = L.mul(d + p);
-    p = L.axpy(p, xf[j]);
-    w[j] = d;
-  }
-  T q = ldx(cb.p, cb.e - eref), e = ldx(cb.d, cb.e - eref);
-#pragma unroll
-  for (int j = R - 1; j >= 0; --j) {
-    e = L.mul(e + q);
-    q = L.axpy(q, xf[j]);
-    w[j] += e;
-  }
+  run_cost<T, R>(xf, ldx(lcf.p.m, lcf.p.e - eref), ldx(lcf.d.m, lcf.d.e - eref),
+                 ldx(lcb.p.m, lcb.p.e - eref), ldx(lcb.d.m, lcb.d.e - eref), L, w);
   T ph[R];
   load_run<T, R>(vphi, base, n, ph, T(0));
   const int ep = ABSORB ? ephi[run] : 0;

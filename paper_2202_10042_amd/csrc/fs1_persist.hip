@@ -271,8 +271,8 @@ hipError_t persist_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int c
   a.itr_max = itr_max;
   a.check_every = check_every;
   a.tol = tol;
-  const double cl = k.c_log2e * double(kBlock) * double(R);
-  for (int i = 0; i < 20; ++i) a.cpow[i] = make_decay(cl * double(1ll << i));
+  for (int i = 0; i < 20; ++i)
+    a.cpow[i] = make_decay(double(kBlock) * double(R) * double(1ll << i), k.c);
   ScanConsts kk = k;
   void* args[] = {&a, &kk};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<T, R>),

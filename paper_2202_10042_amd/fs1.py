@@ -34,6 +34,7 @@ FS1_LOG = 1
 FS1_FLAG_POTENTIALS = 1
 FS1_FLAG_GENERAL = 2
 FS1_FLAG_PERSISTENT = 4
+FS1_FLAG_NO_GRAPH = 8
 
 # every symbol include/fs1.h declares
 EXPORTS = (
@@ -290,17 +291,27 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
 
 def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequence[float],
                       tol: Sequence[float], itr_max: int = 10000, dtype: str = "f64",
-                      domain: str = "log", check_every: int = 1,
-                      ctx: Optional[Context] = None) -> list:
-    """Ragged batch: instance b is [offsets[b], offsets[b+1]) of the packed tensors."""
+                      domain: str = "log", check_every: int = 1, sync_every: int = 16,
+                      graph: bool = True, ctx: Optional[Context] = None) -> list:
+    """Ragged batch: instance b is [offsets[b], offsets[b+1]) of the packed
+    float64 device tensors; eps and tol per instance.  Returns one Result per
+    instance (per-instance failures in Result.status).  With domain="log" all
+    instances advance in the same launches, `sync_every` iterations per
+    replayed HIP graph (graph=False launches the kernels directly)."""
     ctx = ctx or default_context()
     B = len(offsets) - 1
+    if len(eps) != B or len(tol) != B:
+        raise ValueError("eps and tol need one entry per instance")
+    if B > 0 and (int(offsets[-1]) > mu_packed.numel() or int(offsets[-1]) > nu_packed.numel()):
+        raise ValueError("offsets run past the packed marginals")
     offs = (ctypes.c_int64 * (B + 1))(*[int(v) for v in offsets])
-    e = (ctypes.c_double * B)(*[float(v) for v in eps])
-    t = (ctypes.c_double * B)(*[float(v) for v in tol])
-    o = make_opts(None, itr_max, dtype, domain, check_every)
-    res = (CResult * B)()
+    e = (ctypes.c_double * max(B, 1))(*[float(v) for v in eps])
+    t = (ctypes.c_double * max(B, 1))(*[float(v) for v in tol])
+    o = make_opts(None, itr_max, dtype, domain, check_every, sync_every)
+    if not graph:
+        o.flags |= FS1_FLAG_NO_GRAPH
+    res = (CResult * max(B, 1))()
     _check(load().fs1_solve_batched(ctx.handle, _dev(mu_packed, "mu"), _dev(nu_packed, "nu"),
                                     offs, B, e, t, ctypes.byref(o), res))
     return [Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
-            for r in res]
+            for r in res[:B]]

@@ -86,3 +86,22 @@ def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fs1, "_lib", None)
     with pytest.raises(RuntimeError):
         fs1.load(str(tmp_path / "missing.so"))
+
+
+def test_flag_and_enum_values_match_header():
+    text = open(HEADER).read()
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define (FS1_FLAG_\w+) (\d+)", text))
+    assert flags and all(getattr(fs1, k) == v for k, v in flags.items())
+    for name in ("FS1_OK", "FS1_ERR_INVALID_ARG", "FS1_ERR_NONFINITE", "FS1_F64", "FS1_F32",
+                 "FS1_PLAIN", "FS1_LOG"):
+        m = re.search(name + r"\s*=\s*(-?\d+)", text)
+        assert m and getattr(fs1, name) == int(m.group(1)), name
+
+
+def test_batched_validation_without_context():
+    lib = _lib()
+    r = (fs1.CResult * 1)()
+    offs = (ctypes.c_int64 * 2)(0, 4)
+    e = (ctypes.c_double * 1)(0.1)
+    st = lib.fs1_solve_batched(None, None, None, offs, 1, e, e, None, r)
+    assert st == fs1.FS1_ERR_INVALID_ARG and "context" in fs1.last_error()

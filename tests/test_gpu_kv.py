@@ -39,7 +39,9 @@ def dev(a, dt=torch.float64):
 
 SIZES = [1, 2, 3, 7, 8, 9, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049, 4095, 4096, 4097,
          8191, 12289, 65537]
-CS = [1e-9, 1e-4, 0.02, 0.7, 5.0, 69.0]
+# up to h/eps = 800: lambda below the binary32 (c > 87) and binary64 (c > 745)
+# normal ranges
+CS = [1e-9, 1e-4, 0.02, 0.7, 5.0, 69.0, 100.0, 800.0]
 
 
 def _rows(n, k=97):
