@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--large", action="store_true",
                     help="also run the N=1e8 eps=1e-4 precision-study solve (f64 and f32)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 4096-instance uneven batch (binary32, tol 1e-6)")
+    ap.add_argument("--batch", type=int, default=4096)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -189,7 +192,7 @@ def main():
     traffic = measured_traffic(args.dtype, workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "fs1::k_half (psi and phi halves)",
+                "traffic": traffic, "kernel": "fs1::k_fused (psi and phi halves)",
                 "avg_launch_us": round(avg_us, 3), "launches": klaunch,
                 "alg_bytes_per_launch": round(kbytes / klaunch)}
 
@@ -238,6 +241,9 @@ def main():
     if args.large:
         out["large_n"] = large_n_study(fs1, ctx, inputs, np, torch)
 
+    if not args.no_batched:
+        out["batched"] = batched_study(fs1, ctx, inputs, np, torch, args.batch)
+
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle.fs1_log, {args.cpu_iters} iterations at N={n} ...")
         out["cpu_baseline"] = cpu_baseline(mu_np, nu_np, h, args.eps, args.cpu_iters)
@@ -275,6 +281,73 @@ def large_n_study(fs1, ctx, inputs, np, torch):
     rows["w1_cdf"] = w1_cdf
     rows["rel_w1_f32_vs_f64"] = abs(rows["f32"]["w1"] - rows["f64"]["w1"]) / rows["f64"]["w1"]
     rows["rel_w1_f64_vs_cdf"] = abs(rows["f64"]["w1"] - w1_cdf) / w1_cdf
+    return rows
+
+
+def batched_study(fs1, ctx, inputs, np, torch, B: int):
+    """Uneven batch: B pairs, N log-uniform in [256, 65536], eps uniform over
+    {1e-2, 3e-3, 1e-3}, 3-5 component mixtures, tol 1e-6 per instance,
+    itr_max 5000.  The batched binary32 solve (one launch per half-iteration
+    and run-length class, graph-replayed) is timed as solves/s and set beside
+    the binary64 single-solve path (fs1_solve, log domain, one pair at a time)
+    timed on a sample of the same instances."""
+    seed = 2025
+    spec = inputs.batch_spec(B, 256, 65536, [1e-2, 3e-3, 1e-3], seed)
+    mu_np, nu_np, offs = inputs.batch_hists(spec)
+    mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
+    nu = torch.tensor(nu_np, dtype=torch.float64, device="cuda")
+    tol = [1e-6] * B
+    log(f"batched: B={B}, sum N={int(offs[-1])}")
+
+    def run(dt):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fs1.fs1_solve_batched(mu, nu, offs, spec.eps, tol, itr_max=5000, dtype=dt,
+                                    sync_every=32, ctx=ctx)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    run("f32")  # warm-up (graph instantiation, workspace growth)
+    rows = {}
+    for dt in ("f32", "f64"):
+        res, w = run(dt)
+        its = np.array([r.iterations for r in res])
+        ok = sum(r.status == 0 for r in res)
+        conv = sum(r.converged for r in res)
+        rows[dt] = {"s": round(w, 4), "solves_per_s": B / w, "converged": conv, "ok": ok,
+                    "iterations_median": float(np.median(its)), "iterations_max": int(its.max()),
+                    "grid_pts_it_per_s": float(np.sum(spec.sizes * its) / w),
+                    "max_marginal_err_converged": max(
+                        (r.marginal_err for r in res if r.converged), default=None)}
+        log(f"batched {dt}: {w * 1e3:.1f} ms, {B / w:.1f} solves/s, {conv}/{B} converged, "
+            f"iterations median {np.median(its):.0f} max {its.max()}")
+        if dt == "f32":
+            res32 = res
+    # binary64 single-solve path on a sample of the same instances
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(B, size=min(64, B), replace=False))
+    wsum = 0.0
+    rel = []
+    for i in sample:
+        a, b = int(offs[i]), int(offs[i + 1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fs1.fs1_solve(mu[a:b].clone(), nu[a:b].clone(), float(spec.eps[i]), 1e-6,
+                          itr_max=5000, dtype="f64", domain="log", sync_every=64, ctx=ctx)
+        torch.cuda.synchronize()
+        wsum += time.perf_counter() - t0
+        if r.status == 0 and res32[i].status == 0:
+            rel.append(abs(res32[i].w1 - r.w1) / abs(r.w1))
+    single = len(sample) / wsum
+    rows["single_f64"] = {"solves_per_s": single, "sample": int(len(sample)),
+                          "note": "fs1_solve per pair (log domain, binary64, tol 1e-6); "
+                                  "clone of each pair included in the timing"}
+    rows["speedup_f32_batched_vs_f64_single"] = rows["f32"]["solves_per_s"] / single
+    rows["max_rel_w1_f32_batched_vs_f64_single"] = max(rel) if rel else None
+    rows["config"] = {"B": B, "n_lo": 256, "n_hi": 65536, "eps": [1e-2, 3e-3, 1e-3],
+                      "tol": 1e-6, "itr_max": 5000, "seed": seed, "sum_n": int(offs[-1])}
+    log(f"single f64 path: {single:.1f} solves/s on {len(sample)} sampled pairs; "
+        f"batched f32 speedup {rows['speedup_f32_batched_vs_f64_single']:.1f}x")
     return rows
 
 

@@ -193,7 +193,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   std::vector<int> chunk_inst;
   int64_t chunk = 0, elem = 0;
   for (int r : rs) {
-    BatchGroup g{r, int(chunk), 0};
+    BatchGroup g{r, int(chunk), 0, nullptr, 0};
     const int64_t C = int64_t(kBlock) * r;
     for (int32_t i = 0; i < B; ++i) {
       if (rlen[i] != r) continue;
@@ -214,6 +214,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   const int64_t nchunks = chunk, nruns = chunk * kBlock, nelem = elem;
 
   BatchBufs z{};
+  int* clist = nullptr;  // device chunk lists of the groups (active instances only)
   auto layout = [&](Carve& w) {
     z.inst = static_cast<InstInfo*>(w.take(size_t(B) * sizeof(InstInfo)));
     z.st = static_cast<InstState*>(w.take(size_t(B) * sizeof(InstState)));
@@ -235,13 +236,15 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     z.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     z.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     z.part3 = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    clist = static_cast<int*>(w.take(nchunks * sizeof(int)));
   };
   {
     Carve probe(nullptr);
     layout(probe);
     int st = ensure_ws(ctx, probe.off);
     if (st) return st;
-    st = ensure_hstage(ctx, std::max(size_t(B) * sizeof(InstState), size_t(64)));
+    // pinned staging: stop counters, the per-instance states, the chunk lists
+    st = ensure_hstage(ctx, 64 + size_t(B) * sizeof(InstState) + size_t(nchunks) * sizeof(int));
     if (st) return st;
     Carve w(ctx->ws);
     layout(w);
@@ -273,8 +276,20 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   // `count` iterations per replay; every instance stops by iteration itr_max
   const int count = std::max(1, std::min(o.sync_every, o.itr_max + 1));
   const int64_t max_rounds = (int64_t(o.itr_max) + count) / count + 1;
+  const bool use_graph = !(o.flags & FS1_FLAG_NO_GRAPH);
   hipGraphExec_t gexec = nullptr;
-  if (!(o.flags & FS1_FLAG_NO_GRAPH)) {
+  struct GraphGuard {
+    hipGraphExec_t* g;
+    ~GraphGuard() {
+      if (*g) (void)hipGraphExecDestroy(*g);
+    }
+  } guard{&gexec};
+  auto capture = [&]() -> int {
+    if (gexec) {
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    if (!use_graph) return FS1_OK;
     if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     const hipError_t le = launch_batch_iterations(z, groups.data(), ngroups, count, ctx->capture);
@@ -288,21 +303,43 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
-  }
-  struct GraphGuard {
-    hipGraphExec_t g;
-    ~GraphGuard() {
-      if (g) (void)hipGraphExecDestroy(g);
-    }
-  } guard{gexec};
+    return FS1_OK;
+  };
   for (hipEvent_t& e : ctx->bev)
     if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
-  // replay until every instance has stopped; one replay stays queued ahead of
-  // the host's look at the stop counter
-  int* hdone = static_cast<int*>(ctx->hstage);
+  char* hb = static_cast<char*>(ctx->hstage);
+  int* hdone = reinterpret_cast<int*>(hb);
+  InstState* hst = reinterpret_cast<InstState*>(hb + 64);
+  int* hlist = reinterpret_cast<int*>(hb + 64 + size_t(B) * sizeof(InstState));
+  // Launch over the chunks of the instances still running.  The lists are
+  // rebuilt (and the graph recaptured) whenever an eighth of the instances
+  // that were running at the last rebuild have stopped, so launches late in
+  // the batch do not dispatch the chunks of finished instances.
+  auto rebuild_lists = [&](bool all) -> int {
+    if (!all) {
+      HIP_TRY(hipMemcpyAsync(hst, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    int64_t at = 0;
+    for (BatchGroup& g : groups) {
+      const int64_t start = at;
+      for (int c = g.chunk0; c < g.chunk0 + g.nchunks; ++c)
+        if (all || !hst[chunk_inst[c]].done) hlist[at++] = c;
+      g.list = clist + start;
+      g.nlist = int(at - start);
+    }
+    if (at > 0)
+      HIP_TRY(hipMemcpyAsync(clist, hlist, size_t(at) * sizeof(int), hipMemcpyHostToDevice, s));
+    // the pinned list is read by that copy: finish it before the host writes again
+    HIP_TRY(hipStreamSynchronize(s));
+    return capture();
+  };
+  int st = rebuild_lists(true);
+  if (st) return st;
+
   hdone[0] = hdone[1] = 0;
-  int stopped = 0;
+  int stopped = 0, stopped_at_rebuild = 0, running_at_rebuild = B;
   for (int64_t r = 0; r <= max_rounds; ++r) {
     if (gexec) {
       HIP_TRY(hipGraphLaunch(gexec, s));
@@ -312,18 +349,31 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     HIP_TRY(hipMemcpyAsync(&hdone[r & 1], z.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ctx->bev[r & 1], s));
     if (r > 0) {
+      // one replay stays queued ahead of the host's look at the stop counter
       HIP_TRY(hipEventSynchronize(ctx->bev[(r - 1) & 1]));
       stopped = hdone[(r - 1) & 1];
       if (stopped >= B) break;
+      if (stopped - stopped_at_rebuild >= std::max(1, running_at_rebuild / 8)) {
+        st = rebuild_lists(false);
+        if (st) return st;
+        stopped = hdone[r & 1];  // the queued replay has completed
+        if (stopped >= B) break;
+        stopped_at_rebuild = stopped;
+        running_at_rebuild = B - stopped;
+      }
     }
   }
   HIP_TRY(hipStreamSynchronize(s));
   stopped = std::max(stopped, std::max(hdone[0], hdone[1]));
   if (stopped != B)
     return set_err(FS1_ERR_INTERNAL, "batched solve: %d of %d instances stopped", stopped, B);
+  for (BatchGroup& g : groups) {
+    g.list = nullptr;
+    g.nlist = 0;
+  }
 
   HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, B, s));
-  InstState* hs = static_cast<InstState*>(ctx->hstage);
+  InstState* hs = hst;
   HIP_TRY(hipMemcpyAsync(hs, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int32_t i = 0; i < B; ++i) {

@@ -50,6 +50,8 @@ struct BatchGroup {
   int R;
   int chunk0;         // first global chunk of the group
   int nchunks;
+  const int* list;    // device list of the group's chunks to run, or null: all of them
+  int nlist;          // entries of `list`
 };
 
 struct BatchBufs {
@@ -87,8 +89,9 @@ InstInfo make_inst_info(int64_t off, int64_t base, int64_t n, int chunk0, int R,
 // instances' descriptions and initial states.
 hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                               const double* mu, const double* nu, int B, hipStream_t s);
-// `count` iterations (psi-half, phi-half) of every group, then advance the
-// iteration counter by `count`.  Safe to capture in a graph.
+// `count` iterations (psi-half, phi-half) of every group (over its chunk list
+// when it has one), then advance the iteration counter by `count`.  Safe to
+// capture in a graph.
 hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                                    int count, hipStream_t s);
 // Final marginal errors and transport costs of every instance.

@@ -94,6 +94,7 @@ struct BArgs {
   const ChunkAgg* A_in;   // chunk aggregates of vin
   ChunkAgg* A_out;        // chunk aggregates of vout (or of vin for k_bpublish)
   double* part;
+  const int* clist;       // global chunk of each workgroup, or null: chunk_off + blockIdx.x
   int chunk_off;          // first global chunk of the launch's group
   int l_local;            // iteration = *iter_base + l_local - l0
   int itr_max;
@@ -105,6 +106,10 @@ struct BArgs {
 // else of itr_max
 __device__ __forceinline__ int final_buf(const InstState& s, int itr_max) {
   return (s.stop_iter >= 0) ? (s.stop_iter & 1) : (itr_max & 1);
+}
+
+__device__ __forceinline__ int chunk_of(const BArgs& a) {
+  return a.clist ? a.clist[blockIdx.x] : a.chunk_off + int(blockIdx.x);
 }
 
 __device__ __forceinline__ int pick(int sel, int l, const InstState& s, int itr_max) {
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   __shared__ double red[kNW];
   __shared__ XF64 scar[2];
   __shared__ int sdec;
-  const int c = a.chunk_off + blockIdx.x;
+  const int c = chunk_of(a);
   const int b = a.chunk_inst[c];
   const InstInfo& in = a.inst[b];
   InstState& st = a.st[b];
@@ -170,20 +175,43 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
     }
   }
 
+  // every global load of the workgroup is issued before the scans, so the
+  // launch pays one memory round trip rather than one per phase
   const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
   const int64_t run = int64_t(c) * kBlock + threadIdx.x;
   const int64_t lim = in.base + in.n;  // entries past the instance are padding
+  const bool want_err = (MODE == B_ERR) || (MODE == B_PSI && (l % a.check_every) == 0);
   const int si = pick(a.sel_in, l, st, a.itr_max);
   T x[R];
   load_run<T, R>(static_cast<const T*>(a.vin[si]), base, lim, x, T(0));
   const int E = a.ein[si][run];
+  T own[R];
+  int eo = 0;
+  if (want_err) {
+    const int so = pick(a.sel_own, l, st, a.itr_max);
+    load_run<T, R>(static_cast<const T*>(a.vown[so]), base, lim, own, T(0));
+    eo = a.eown[so][run];
+  }
+  // binary64 marginal: the error term, and the update when T = double; the
+  // binary32 copy is the rounding of it, loaded only when the error is not due
+  double m64[R];
+  T mg[R];
+  if (want_err || sizeof(T) == 8) load_run<double, R>(a.m64, base, lim, m64, 0.0);
+  if constexpr (MODE != B_ERR) {
+    if (sizeof(T) == 8 || want_err) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) mg[i] = T(m64[i]);
+    } else {
+      load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, lim, mg, T(0));
+    }
+  }
+  inst_carries(a.A_in, in, j, scar);
   const ScanConsts& k = in.k;
   const Lam<T> L = lam_of<T>(k);
   T af, ab;
   run_aggs<T, R>(x, L, af, ab);
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
-  inst_carries(a.A_in, in, j, scar);
   __syncthreads();
   const XF64 cf64 = scar[0], cb64 = scar[1];
   S1<T> cf, cb;
@@ -199,18 +227,12 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   T y[R];  // (K vin)_i * 2^-eref
   run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
 
-  const bool want_err = (MODE == B_ERR) || (MODE == B_PSI && (l % a.check_every) == 0);
   if (want_err) {
-    const int so = pick(a.sel_own, l, st, a.itr_max);
-    T own[R];
-    load_run<T, R>(static_cast<const T*>(a.vown[so]), base, lim, own, T(0));
-    double mg[R];
-    load_run<double, R>(a.m64, base, lim, mg, 0.0);
-    const int eo = a.eown[so][run];
     // padding loads as zero and adds nothing
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < R; ++i) s += fabs(ldexp(double(own[i]) * double(y[i]), eo + eref) - mg[i]);
+    for (int i = 0; i < R; ++i)
+      s += fabs(ldexp(double(own[i]) * double(y[i]), eo + eref) - m64[i]);
     const double tot = block_sum<kNW>(s, red);
     if (threadIdx.x == 0) a.part[c] = tot;
   }
@@ -218,12 +240,6 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
 
   // update: out = marg / (K vin)  (zero marginal -> zero scaling), with the
   // power-of-two part of the run absorbed into its exponent
-  T mg[R];
-  if constexpr (sizeof(T) == 8) {
-    load_run<T, R>(reinterpret_cast<const T*>(a.m64), base, lim, mg, T(0));
-  } else {
-    load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, lim, mg, T(0));
-  }
   T q[R];
   bool bad = false;
   T qm = T(0);
@@ -260,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
   __shared__ ScanLds<S1<T>, kNW> sh;
-  const int c = a.chunk_off + blockIdx.x;
+  const int c = chunk_of(a);
   const int b = a.chunk_inst[c];
   const InstInfo& in = a.inst[b];
   const int j = c - in.chunk0;
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bcost_agg(BArgs a, ChunkAgg2* agg2) {
   __shared__ ScanLds<S2<T>, kNW> sh;
-  const int c = a.chunk_off + blockIdx.x;
+  const int c = chunk_of(a);
   const int b = a.chunk_inst[c];
   const InstInfo& in = a.inst[b];
   const int j = c - in.chunk0;
@@ -322,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_bcost_apply(BArgs a, const ChunkAgg2
   __shared__ ScanLds<S2<T>, kNW> sh;
   __shared__ double red[kNW];
   __shared__ S2<double> scar[2];
-  const int c = a.chunk_off + blockIdx.x;
+  const int c = chunk_of(a);
   const int b = a.chunk_inst[c];
   const InstInfo& in = a.inst[b];
   const int j = c - in.chunk0;
@@ -398,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, const double* mu, co
                                                    float* nu32, T* vF, T* vG0, int* eF,
                                                    int* eG0, double* pmu, double* pnu) {
   __shared__ double red[kNW];
-  const int c = a.chunk_off + blockIdx.x;
+  const int c = chunk_of(a);
   const int b = a.chunk_inst[c];
   const InstInfo& in = a.inst[b];
   const int j = c - in.chunk0;
@@ -496,8 +512,10 @@ struct BatchOps {
     a.itr_max = z.itr_max;
     a.check_every = z.check_every;
     a.chunk_off = g.chunk0;
+    a.clist = g.list;
     return a;
   }
+  static unsigned grid(const BatchGroup& g) { return unsigned(g.list ? g.nlist : g.nchunks); }
   static void set_phi_in(BArgs& a, const BatchBufs& z) {
     a.vin[0] = a.vin[1] = z.vF;
     a.ein[0] = a.ein[1] = z.eF;
@@ -512,7 +530,7 @@ struct BatchOps {
   static hipError_t setup(const BatchBufs& z, const BatchGroup& g, const double* mu,
                           const double* nu, hipStream_t s) {
     BArgs a = base(z, g);
-    k_bsetup<T, R><<<unsigned(g.nchunks), kBlock, 0, s>>>(
+    k_bsetup<T, R><<<grid(g), kBlock, 0, s>>>(
         a, mu, nu, z.mu64, z.nu64, static_cast<float*>(z.mu32), static_cast<float*>(z.nu32),
         static_cast<T*>(z.vF), static_cast<T*>(z.vG[0]), z.eF, z.eG[0], z.part, z.part2);
     return hipGetLastError();
@@ -521,7 +539,7 @@ struct BatchOps {
     BArgs a = base(z, g);
     set_phi_in(a, z);
     a.A_out = z.aggF;
-    k_bpublish<T, R><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+    k_bpublish<T, R><<<grid(g), kBlock, 0, s>>>(a);
     return hipGetLastError();
   }
   static hipError_t half(const BatchBufs& z, const BatchGroup& g, bool psi, int l_local,
@@ -546,7 +564,7 @@ struct BatchOps {
       a.m32 = static_cast<const float*>(z.nu32);
       a.A_in = z.aggF;
       a.A_out = z.aggG;
-      k_bhalf<T, R, B_PSI><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+      k_bhalf<T, R, B_PSI><<<grid(g), kBlock, 0, s>>>(a);
     } else {
       // phi^{l+1} = mu / K psi^{l+1}
       set_psi_in(a, z, SEL_NEXT);
@@ -556,12 +574,12 @@ struct BatchOps {
       a.m32 = static_cast<const float*>(z.mu32);
       a.A_in = z.aggG;
       a.A_out = z.aggF;
-      k_bhalf<T, R, B_PHI><<<unsigned(g.nchunks), kBlock, 0, s>>>(a);
+      k_bhalf<T, R, B_PHI><<<grid(g), kBlock, 0, s>>>(a);
     }
     return hipGetLastError();
   }
   static hipError_t finalize(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
-    const unsigned grid = unsigned(g.nchunks);
+    const unsigned grid = BatchOps::grid(g);
     // nu side: | psi (K^T phi) - nu |; the aggregates of the final phi are in aggF
     BArgs a = base(z, g);
     set_phi_in(a, z);
@@ -661,6 +679,7 @@ hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups,
     for (int psi = 1; psi >= 0; --psi) {
       for (int i = 0; i < ngroups; ++i) {
         const BatchGroup& g = groups[i];
+        if (g.list && g.nlist == 0) continue;
         const hipError_t e = bdispatch(
             z.dtype, g.R, [&](auto ops) { return decltype(ops)::half(z, g, psi != 0, l, s); });
         if (e != hipSuccess) return e;
