@@ -210,6 +210,79 @@ int fs1_solve_batched(fs1_ctx *ctx, const double *mu_packed, const double *nu_pa
                       const int64_t *offsets, int32_t B, const double *eps,
                       const double *tol, const fs1_opts *opts, fs1_result *out);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop with continuous batching (a library addition, not */
+/* part of the paper).  Each request is one solve as fs1_solve in the log    */
+/* domain (h = 1/n).  Requests wait in a queue and are admitted in           */
+/* submission order whenever an instance slot and room in the device memory  */
+/* budget are free; every step runs a fixed number of iterations of all      */
+/* admitted requests in the same launches (as fs1_solve_batched), then       */
+/* finalises and frees the requests that stopped.  Scaling vectors stay on   */
+/* the device from admission to completion.  A request's result does not     */
+/* depend on the other requests or on the step at which it was admitted.     */
+/* A server uses its context's stream and is driven by one host thread.      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct fs1_server fs1_server;
+
+typedef struct {
+    int64_t hbm_budget;      /* bytes of device memory for requests, allocated once
+                                by fs1_server_create (>= 16 MiB)                   */
+    int32_t max_active;      /* requests on the device at once (>= 1)              */
+    int32_t dtype;           /* fs1_dtype of storage and scans                     */
+    int32_t itr_max;         /* per request; < 0 selects 10000                     */
+    int32_t check_every;     /* as fs1_opts (>= 1)                                  */
+    int32_t iters_per_step;  /* iterations per fs1_server_step (>= 1)              */
+    int32_t flags;           /* FS1_FLAG_NO_GRAPH: launch the kernels directly
+                                instead of replaying a captured graph              */
+} fs1_server_opts;
+
+typedef struct {
+    int64_t ticket;          /* as returned by fs1_server_submit                   */
+    fs1_result result;       /* status FS1_OK, FS1_ERR_INVALID_ARG (marginals not
+                                finite, negative, zero or unequal in mass) or
+                                FS1_ERR_NONFINITE                                  */
+    int64_t admitted_step;   /* step that admitted the request                     */
+    int64_t completed_step;  /* step that completed it                             */
+} fs1_completion;
+
+typedef struct {
+    int64_t queued;          /* submitted, not yet admitted                        */
+    int64_t active;          /* admitted, not yet completed                        */
+    int64_t completed;       /* completions produced so far (polled or not)        */
+    int64_t steps;           /* fs1_server_step calls that ran                     */
+    int64_t bytes_in_use;    /* budget taken by admitted requests                  */
+    int64_t bytes_total;     /* budget usable for requests                         */
+} fs1_server_info;
+
+/* Defaults: 1 GiB budget, 4096 slots, FS1_F32, itr_max 10000, check_every 1,
+ * 16 iterations per step, graphs on. */
+int fs1_server_opts_default(fs1_server_opts *o);
+/* Create a server on ctx (which must outlive it).  FS1_ERR_NO_MEMORY if the
+ * budget cannot be allocated. */
+int fs1_server_create(fs1_ctx *ctx, const fs1_server_opts *o, fs1_server **out);
+/* Waits for the server's work on the stream, then frees it; requests still
+ * queued or active are dropped. */
+int fs1_server_destroy(fs1_server *srv);
+/* Queue one request.  mu, nu: device binary64 arrays of n entries (any
+ * alignment) that must stay valid and unchanged until the request completes;
+ * eps and tol as fs1_solve.  FS1_ERR_INVALID_ARG if an argument is invalid or
+ * the request could never fit the budget (nothing is queued then).  The
+ * marginals themselves are checked on the device at admission; a bad pair
+ * completes with status FS1_ERR_INVALID_ARG.  *ticket (may be NULL) receives
+ * the request's number, 0, 1, 2, ... in submission order. */
+int fs1_server_submit(fs1_server *srv, const double *mu, const double *nu, int64_t n,
+                      double eps, double tol, int64_t *ticket);
+/* One step: admit queued requests (in order, stopping at the first that does
+ * not fit), run iters_per_step iterations of every admitted request, finalise
+ * the ones that stopped.  Blocks until the step's work is done.  *completed (may
+ * be NULL) receives the number of completions this step produced. */
+int fs1_server_step(fs1_server *srv, int32_t *completed);
+/* Move up to max completions, oldest first, into out (host array); *count
+ * receives how many. */
+int fs1_server_poll(fs1_server *srv, fs1_completion *out, int32_t max, int32_t *count);
+int fs1_server_get_info(fs1_server *srv, fs1_server_info *out);
+
 #ifdef __cplusplus
 }
 #endif

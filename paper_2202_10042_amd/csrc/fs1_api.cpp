@@ -21,32 +21,19 @@
 
 #include "fs1.h"
 #include "fs1_batch.h"
+#include "fs1_host.h"
 #include "fs1_internal.h"
 
 using namespace fs1;
 
-struct fs1_ctx {
-  hipStream_t stream = nullptr;
-  int device = 0;
-  char* ws = nullptr;      // device workspace
-  size_t ws_size = 0;
-  Ctrl* hctrl = nullptr;   // pinned host mirror of the control block
-  // diagnostic timing of the half-iteration kernel (fs1_ctx_set_profiling)
-  int profiling = 0;
-  std::vector<hipEvent_t> events;  // 4 per iteration of one polling batch
-  double prof_ms = 0.0;
-  int64_t prof_launches = 0;
-  double prof_bytes = 0.0;
-  // batched solves
-  void* hstage = nullptr;   // pinned host staging (per-instance states)
-  size_t hstage_size = 0;
-  hipStream_t capture = nullptr;  // stream used only to capture iteration graphs
-  hipEvent_t bev[2] = {nullptr, nullptr};
-};
+namespace fs1 {
+namespace host {
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+const char* last_error_text() { return g_err.c_str(); }
 
 int set_err(int code, const char* fmt, ...) {
   char buf[512];
@@ -61,12 +48,6 @@ int set_err(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
   return set_err(FS1_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(call)                                  \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
-  } while (0)
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -92,17 +73,24 @@ int ensure_ws(fs1_ctx* c, size_t bytes) {
   return FS1_OK;
 }
 
-// Bump allocator over a workspace.
-struct Carve {
-  char* base;
-  size_t off = 0;
-  explicit Carve(char* b) : base(b) {}
-  void* take(size_t bytes) {
-    void* p = base ? base + off : nullptr;
-    off = round_up(off + bytes, 256);
-    return p;
+// Pinned host staging of at least `bytes`.
+int ensure_hstage(fs1_ctx* c, size_t bytes) {
+  if (bytes <= c->hstage_size) return FS1_OK;
+  if (c->hstage) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipHostFree(c->hstage));
+    c->hstage = nullptr;
+    c->hstage_size = 0;
   }
-};
+  const size_t sz = round_up(bytes, size_t(1) << 16);
+  hipError_t e = hipHostMalloc(&c->hstage, sz, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    c->hstage = nullptr;
+    return set_err(FS1_ERR_NO_MEMORY, "hipHostMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+  }
+  c->hstage_size = sz;
+  return FS1_OK;
+}
 
 int check_h_eps(int64_t n, double h, double eps) {
   if (n < 1) return set_err(FS1_ERR_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)n);
@@ -114,6 +102,36 @@ int check_h_eps(int64_t n, double h, double eps) {
     return set_err(FS1_ERR_INVALID_ARG, "n*h/eps = %g exceeds 1e8", double(n) * (h / eps));
   return FS1_OK;
 }
+
+int capture_iterations(fs1_ctx* ctx, const BatchBufs& z, const std::vector<BatchGroup>& groups,
+                       int count, hipGraphExec_t* out) {
+  *out = nullptr;
+  if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+  const hipError_t le =
+      launch_batch_iterations(z, groups.data(), int(groups.size()), count, ctx->capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(ctx->capture, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(le, "batched iteration capture");
+  }
+  if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+  const hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    *out = nullptr;
+    return hip_fail(ie, "hipGraphInstantiate");
+  }
+  return FS1_OK;
+}
+
+}  // namespace host
+}  // namespace fs1
+
+using namespace fs1::host;
+
+namespace {
 
 int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double eps, int dt,
               bool log) {
@@ -146,25 +164,6 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
   hipError_t e = log ? launch_kv_log(dt, x, y, n, k, kc, agg, carry, ctx->stream)
                      : launch_kv_plain(dt, x, y, n, k, kc, agg, carry, ctx->stream);
   if (e != hipSuccess) return hip_fail(e, log ? "fs1_kv_apply_log launch" : "fs1_kv_apply launch");
-  return FS1_OK;
-}
-
-// Pinned host staging of at least `bytes`.
-int ensure_hstage(fs1_ctx* c, size_t bytes) {
-  if (bytes <= c->hstage_size) return FS1_OK;
-  if (c->hstage) {
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipHostFree(c->hstage));
-    c->hstage = nullptr;
-    c->hstage_size = 0;
-  }
-  const size_t sz = round_up(bytes, size_t(1) << 16);
-  hipError_t e = hipHostMalloc(&c->hstage, sz, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    c->hstage = nullptr;
-    return set_err(FS1_ERR_NO_MEMORY, "hipHostMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
-  }
-  c->hstage_size = sz;
   return FS1_OK;
 }
 
@@ -201,8 +200,8 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
       const int64_t nch = (n + C - 1) / C;
       if (chunk + nch > int64_t(INT32_MAX) / kBlock)
         return set_err(FS1_ERR_INVALID_ARG, "batch too large");
-      info[i] = make_inst_info(offsets[i], elem, n, int(chunk), r, 1.0 / double(n), eps[i],
-                               tol[i], 0);
+      info[i] = make_inst_info(mu + offsets[i], nu + offsets[i], elem, n, int(chunk), r,
+                               1.0 / double(n), eps[i], tol[i], 0);
       chunk_inst.insert(chunk_inst.end(), size_t(nch), int(i));
       chunk += nch;
       elem += nch * C;
@@ -271,7 +270,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   HIP_TRY(hipMemcpyAsync(z.chunk_inst, chunk_inst.data(), nchunks * sizeof(int),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(z.iter_base, 0, 2 * sizeof(int), s));
-  HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, mu, nu, B, s));
+  HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, nullptr, B, s));
 
   // `count` iterations per replay; every instance stops by iteration itr_max
   const int count = std::max(1, std::min(o.sync_every, o.itr_max + 1));
@@ -289,21 +288,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
       (void)hipGraphExecDestroy(gexec);
       gexec = nullptr;
     }
-    if (!use_graph) return FS1_OK;
-    if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
-    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    const hipError_t le = launch_batch_iterations(z, groups.data(), ngroups, count, ctx->capture);
-    hipGraph_t graph = nullptr;
-    const hipError_t ce = hipStreamEndCapture(ctx->capture, &graph);
-    if (le != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return hip_fail(le, "batched iteration capture");
-    }
-    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
-    return FS1_OK;
+    return use_graph ? capture_iterations(ctx, z, groups, count, &gexec) : FS1_OK;
   };
   for (hipEvent_t& e : ctx->bev)
     if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -372,7 +357,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     g.nlist = 0;
   }
 
-  HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, B, s));
+  HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, nullptr, B, nullptr, s));
   InstState* hs = hst;
   HIP_TRY(hipMemcpyAsync(hs, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -405,7 +390,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
 // ===========================================================================
 extern "C" {
 
-const char* fs1_last_error(void) { return g_err.c_str(); }
+const char* fs1_last_error(void) { return last_error_text(); }
 
 const char* fs1_version(void) { return "fs1 0.1 (gfx950)"; }
 
@@ -730,7 +715,7 @@ int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_pa
     if (n > int64_t(INT32_MAX) / 2) return set_err(FS1_ERR_INVALID_ARG, "instance %d too long", i);
     if (!(tol[i] >= 0.0)) return set_err(FS1_ERR_INVALID_ARG, "instance %d: tol must be >= 0", i);
     const int st = check_h_eps(n, 1.0 / double(n), eps[i]);
-    if (st) return set_err(st, "instance %d: %s", i, g_err.c_str());
+    if (st) return set_err(st, "instance %d: %s", i, std::string(last_error_text()).c_str());
   }
   for (int32_t i = 0; i < B; ++i) {
     std::memset(&out[i], 0, sizeof(out[i]));

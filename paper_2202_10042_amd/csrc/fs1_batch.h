@@ -16,7 +16,8 @@ constexpr int kInstPow = 20;  // lambda^(chunk length * 2^s), s < 20: up to 2^20
 
 // Constant description of one instance (written once, at admission).
 struct InstInfo {
-  int64_t off;        // offset of the instance in the caller's packed marginals
+  const double* src_mu;  // the caller's marginals (read at set-up only)
+  const double* src_nu;
   int64_t base;       // first element in the padded work arrays
   int32_t n;          // grid size
   int32_t nch;        // chunks
@@ -65,6 +66,8 @@ struct BatchBufs {
   int* chunk_inst;    // global chunk -> instance
   int* iter_base;     // batch iteration counter (advanced on the device)
   int* ndone;         // instances stopped so far
+  int* ring;          // optional: instance index of the k-th stop at ring[k % ring_cap]
+  int ring_cap;
   double* mu64;       // padded marginals
   double* nu64;
   void* mu32;         // binary32 copies (dtype 1)
@@ -81,21 +84,29 @@ struct BatchBufs {
   double* part3;      // cost
 };
 
-InstInfo make_inst_info(int64_t off, int64_t base, int64_t n, int chunk0, int R, double h,
-                        double eps, double tol, int l0);
+InstInfo make_inst_info(const double* mu, const double* nu, int64_t base, int64_t n, int chunk0,
+                        int R, double h, double eps, double tol, int l0);
 
-// Pack the marginals, set phi = psi = 1/n, validate every instance and publish
-// the chunk aggregates of phi.  `inst` / `st` must already hold the
-// instances' descriptions and initial states.
+// Instances ilist[0..count) (or 0..count-1 when ilist is null) and the chunks
+// of the groups (their lists, or all their chunks): pack the marginals, set
+// phi = psi = 1/n, validate each instance and publish the chunk aggregates of
+// phi.  `inst` / `st` must already hold the instances' descriptions and
+// initial states.
 hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
-                              const double* mu, const double* nu, int B, hipStream_t s);
+                              const int* ilist, int count, hipStream_t s);
 // `count` iterations (psi-half, phi-half) of every group (over its chunk list
 // when it has one), then advance the iteration counter by `count`.  Safe to
 // capture in a graph.
 hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                                    int count, hipStream_t s);
-// Final marginal errors and transport costs of every instance.
+// Final marginal errors and transport costs of the instances ilist[0..count)
+// (or 0..count-1), whose chunks the groups list.  With `out` non-null their
+// states are then gathered to out[0..count).
 hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, int ngroups,
-                                 int B, hipStream_t s);
+                                 const int* ilist, int count, InstState* out, hipStream_t s);
+// Admission: copy count staged descriptions and states into the instance
+// slots idx[0..count) and map their chunks to them.
+hipError_t launch_batch_admit(const BatchBufs& z, const InstInfo* sinfo, const InstState* sstate,
+                              const int* idx, int count, hipStream_t s);
 
 }  // namespace fs1

@@ -83,6 +83,8 @@ struct BArgs {
   const int* chunk_inst;
   const int* iter_base;
   int* ndone;
+  int* ring;
+  int ring_cap;
   const void* vin[2];     // vector fed to K
   const int* ein[2];
   const void* vown[2];    // own vector of the error term
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
         if (sdec == 1) st.stop_iter = l;
         if (sdec == 4) st.capped = 1;
         st.done = 1;
-        atomicAdd(a.ndone, 1);
+        const int pos = atomicAdd(a.ndone, 1);
+        if (a.ring) a.ring[pos % a.ring_cap] = b;
       }
       return;
     }
@@ -409,8 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_bcost_apply(BArgs a, const ChunkAgg2
 // Pack the caller's marginals chunk-aligned (binary64, plus binary32 copies),
 // set phi = psi = 1/n with exponent 0, and write per-chunk masses.
 template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, const double* mu, const double* nu,
-                                                   double* mu64, double* nu64, float* mu32,
+__global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, double* mu64, double* nu64, float* mu32,
                                                    float* nu32, T* vF, T* vG0, int* eF,
                                                    int* eG0, double* pmu, double* pnu) {
   __shared__ double red[kNW];
@@ -428,8 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, const double* mu, co
     const int64_t loc = local0 + i;
     double u = 0.0, v = 0.0;
     if (loc < in.n) {
-      u = mu[in.off + loc];
-      v = nu[in.off + loc];
+      u = in.src_mu[loc];
+      v = in.src_nu[loc];
       bad |= !(isfinite(u) && u >= 0.0) || !(isfinite(v) && v >= 0.0);
     }
     mu64[base + i] = u;
@@ -458,9 +460,11 @@ __global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, const double* mu, co
 // Per instance (one thread each): masses positive, finite and equal to
 // 1e-10 relative; otherwise the instance is stopped before its first iteration.
 __global__ void k_bvalidate(const InstInfo* inst, InstState* st, const double* pmu,
-                            const double* pnu, int b0, int B, int* ndone) {
-  const int b = b0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= b0 + B) return;
+                            const double* pnu, const int* ilist, int count, int* ndone,
+                            int* ring, int ring_cap) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int b = ilist ? ilist[t] : t;
   const InstInfo& in = inst[b];
   double sm = 0.0, sn = 0.0;
   for (int i = 0; i < in.nch; ++i) {
@@ -475,7 +479,8 @@ __global__ void k_bvalidate(const InstInfo* inst, InstState* st, const double* p
   if (!ok) {
     s.invalid = 1;
     s.done = 1;
-    atomicAdd(ndone, 1);
+    const int pos = atomicAdd(ndone, 1);
+    if (ring) ring[pos % ring_cap] = b;
   }
 }
 
@@ -485,9 +490,11 @@ __global__ void k_badvance(int* iter_base, int by) {
 
 // Per instance fixed-order sums of the per-chunk shares.
 __global__ void k_bfinal(const InstInfo* inst, InstState* st, const double* perr,
-                         const double* pmu, const double* pcost, int b0, int B) {
-  const int b = b0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= b0 + B) return;
+                         const double* pmu, const double* pcost, const int* ilist, int count,
+                         InstState* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int b = ilist ? ilist[t] : t;
   const InstInfo& in = inst[b];
   double e = 0.0, m = 0.0, w = 0.0;
   for (int i = 0; i < in.nch; ++i) {
@@ -498,6 +505,21 @@ __global__ void k_bfinal(const InstInfo* inst, InstState* st, const double* perr
   st[b].err = e;
   st[b].mu_err = m;
   st[b].w1 = w * in.h;
+  if (out) out[t] = st[b];
+}
+
+// Admission: one workgroup per new instance copies its staged description and
+// state into its slot and maps its chunks to it.
+__global__ void k_badmit(const InstInfo* sinfo, const InstState* sstate, const int* idx,
+                         InstInfo* inst, InstState* st, int* chunk_inst) {
+  const int t = blockIdx.x;
+  const int b = idx[t];
+  if (threadIdx.x == 0) {
+    inst[b] = sinfo[t];
+    st[b] = sstate[t];
+  }
+  const InstInfo& in = sinfo[t];
+  for (int i = threadIdx.x; i < in.nch; i += blockDim.x) chunk_inst[in.chunk0 + i] = b;
 }
 
 template <typename T, int R>
@@ -509,6 +531,8 @@ struct BatchOps {
     a.chunk_inst = z.chunk_inst;
     a.iter_base = z.iter_base;
     a.ndone = z.ndone;
+    a.ring = z.ring;
+    a.ring_cap = z.ring_cap;
     a.itr_max = z.itr_max;
     a.check_every = z.check_every;
     a.chunk_off = g.chunk0;
@@ -527,11 +551,10 @@ struct BatchOps {
     a.ein[1] = z.eG[1];
     a.sel_in = sel;
   }
-  static hipError_t setup(const BatchBufs& z, const BatchGroup& g, const double* mu,
-                          const double* nu, hipStream_t s) {
+  static hipError_t setup(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
     BArgs a = base(z, g);
     k_bsetup<T, R><<<grid(g), kBlock, 0, s>>>(
-        a, mu, nu, z.mu64, z.nu64, static_cast<float*>(z.mu32), static_cast<float*>(z.nu32),
+        a, z.mu64, z.nu64, static_cast<float*>(z.mu32), static_cast<float*>(z.nu32),
         static_cast<T*>(z.vF), static_cast<T*>(z.vG[0]), z.eF, z.eG[0], z.part, z.part2);
     return hipGetLastError();
   }
@@ -637,11 +660,12 @@ hipError_t bdispatch(int dtype, int R, F&& f) {
 
 }  // namespace
 
-InstInfo make_inst_info(int64_t off, int64_t base, int64_t n, int chunk0, int R, double h,
-                        double eps, double tol, int l0) {
+InstInfo make_inst_info(const double* mu, const double* nu, int64_t base, int64_t n, int chunk0,
+                        int R, double h, double eps, double tol, int l0) {
   InstInfo in{};
   const int64_t C = int64_t(kBlock) * R;
-  in.off = off;
+  in.src_mu = mu;
+  in.src_nu = nu;
   in.base = base;
   in.n = int32_t(n);
   in.nch = int32_t((n + C - 1) / C);
@@ -654,18 +678,25 @@ InstInfo make_inst_info(int64_t off, int64_t base, int64_t n, int chunk0, int R,
   return in;
 }
 
+namespace {
+bool group_empty(const BatchGroup& g) { return g.list ? g.nlist == 0 : g.nchunks == 0; }
+}  // namespace
+
 hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
-                              const double* mu, const double* nu, int B, hipStream_t s) {
+                              const int* ilist, int count, hipStream_t s) {
   for (int i = 0; i < ngroups; ++i) {
     const BatchGroup& g = groups[i];
+    if (group_empty(g)) continue;
     const hipError_t e =
-        bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::setup(z, g, mu, nu, s); });
+        bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::setup(z, g, s); });
     if (e != hipSuccess) return e;
   }
-  k_bvalidate<<<unsigned((B + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2, 0, B,
-                                                       z.ndone);
+  if (count > 0)
+    k_bvalidate<<<unsigned((count + 255) / 256), 256, 0, s>>>(
+        z.inst, z.st, z.part, z.part2, ilist, count, z.ndone, z.ring, z.ring_cap);
   for (int i = 0; i < ngroups; ++i) {
     const BatchGroup& g = groups[i];
+    if (group_empty(g)) continue;
     const hipError_t e =
         bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::publish_phi(z, g, s); });
     if (e != hipSuccess) return e;
@@ -679,7 +710,7 @@ hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups,
     for (int psi = 1; psi >= 0; --psi) {
       for (int i = 0; i < ngroups; ++i) {
         const BatchGroup& g = groups[i];
-        if (g.list && g.nlist == 0) continue;
+        if (group_empty(g)) continue;
         const hipError_t e = bdispatch(
             z.dtype, g.R, [&](auto ops) { return decltype(ops)::half(z, g, psi != 0, l, s); });
         if (e != hipSuccess) return e;
@@ -691,15 +722,24 @@ hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups,
 }
 
 hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, int ngroups,
-                                 int B, hipStream_t s) {
+                                 const int* ilist, int count, InstState* out, hipStream_t s) {
   for (int i = 0; i < ngroups; ++i) {
     const BatchGroup& g = groups[i];
+    if (group_empty(g)) continue;
     const hipError_t e =
         bdispatch(z.dtype, g.R, [&](auto ops) { return decltype(ops)::finalize(z, g, s); });
     if (e != hipSuccess) return e;
   }
-  k_bfinal<<<unsigned((B + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2, z.part3, 0,
-                                                    B);
+  if (count > 0)
+    k_bfinal<<<unsigned((count + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2,
+                                                          z.part3, ilist, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_admit(const BatchBufs& z, const InstInfo* sinfo, const InstState* sstate,
+                              const int* idx, int count, hipStream_t s) {
+  if (count > 0)
+    k_badmit<<<unsigned(count), 256, 0, s>>>(sinfo, sstate, idx, z.inst, z.st, z.chunk_inst);
   return hipGetLastError();
 }
 

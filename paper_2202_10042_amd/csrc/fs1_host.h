@@ -1,0 +1,71 @@
+// fs1_host.h -- host-side pieces shared by the C ABI (fs1_api.cpp) and the
+// serving loop (fs1_server.cpp): the context object, error reporting,
+// workspace helpers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "fs1.h"
+#include "fs1_batch.h"
+#include "fs1_internal.h"
+
+struct fs1_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;      // device workspace
+  size_t ws_size = 0;
+  fs1::Ctrl* hctrl = nullptr;  // pinned host mirror of the control block
+  // diagnostic timing of the half-iteration kernels (fs1_ctx_set_profiling)
+  int profiling = 0;
+  std::vector<hipEvent_t> events;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  double prof_bytes = 0.0;
+  // batched solves
+  void* hstage = nullptr;   // pinned host staging (stop counters, states, lists)
+  size_t hstage_size = 0;
+  hipStream_t capture = nullptr;  // stream used only to capture iteration graphs
+  hipEvent_t bev[2] = {nullptr, nullptr};
+};
+
+namespace fs1 {
+namespace host {
+
+// Record a message for fs1_last_error() and return `code`.
+int set_err(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+const char* last_error_text();
+
+bool aligned16(const void* p);
+size_t round_up(size_t x, size_t a);
+int ensure_ws(fs1_ctx* c, size_t bytes);
+int ensure_hstage(fs1_ctx* c, size_t bytes);
+int check_h_eps(int64_t n, double h, double eps);
+// Capture `count` batched iterations over the groups into an executable graph.
+int capture_iterations(fs1_ctx* ctx, const BatchBufs& z, const std::vector<BatchGroup>& groups,
+                       int count, hipGraphExec_t* out);
+
+// Bump allocator over a workspace (a null base only measures).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(char* b) : base(b) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off = round_up(off + bytes, 256);
+    return p;
+  }
+};
+
+}  // namespace host
+}  // namespace fs1
+
+#define HIP_TRY(call)                                              \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return ::fs1::host::hip_fail(e_, #call); \
+  } while (0)

@@ -41,6 +41,8 @@ EXPORTS = (
     "fs1_ctx_create", "fs1_ctx_destroy", "fs1_ctx_set_stream", "fs1_ctx_set_profiling",
     "fs1_ctx_kernel_stats", "fs1_last_error", "fs1_version", "fs1_kv_apply",
     "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
+    "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
+    "fs1_server_step", "fs1_server_poll", "fs1_server_get_info",
 )
 
 
@@ -74,6 +76,32 @@ class CResult(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_int64),
+        ("max_active", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("itr_max", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("iters_per_step", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64),
+        ("result", CResult),
+        ("admitted_step", ctypes.c_int64),
+        ("completed_step", ctypes.c_int64),
+    ]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("queued", "active", "completed", "steps",
+                                              "bytes_in_use", "bytes_total")]
 
 
 @dataclass
@@ -129,6 +157,20 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(d), ctypes.POINTER(d),
                                       ctypes.POINTER(Opts), ctypes.POINTER(CResult)]
     lib.fs1_solve_batched.restype = ctypes.c_int
+    lib.fs1_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.fs1_server_opts_default.restype = ctypes.c_int
+    lib.fs1_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.fs1_server_create.restype = ctypes.c_int
+    lib.fs1_server_destroy.argtypes = [vp]
+    lib.fs1_server_destroy.restype = ctypes.c_int
+    lib.fs1_server_submit.argtypes = [vp, vp, vp, i64, d, d, ctypes.POINTER(i64)]
+    lib.fs1_server_submit.restype = ctypes.c_int
+    lib.fs1_server_step.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.fs1_server_step.restype = ctypes.c_int
+    lib.fs1_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)]
+    lib.fs1_server_poll.restype = ctypes.c_int
+    lib.fs1_server_get_info.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+    lib.fs1_server_get_info.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -315,3 +357,76 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
                                     offs, B, e, t, ctypes.byref(o), res))
     return [Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
             for r in res[:B]]
+
+
+class Server:
+    """Request loop with continuous batching (fs1_server_*): submit device
+    marginal pairs, call step() repeatedly, poll() completions.  The binding
+    keeps each request's tensors alive until its completion is polled."""
+
+    def __init__(self, hbm_budget: int = 1 << 30, max_active: int = 4096, dtype: str = "f32",
+                 itr_max: int = 10000, check_every: int = 1, iters_per_step: int = 16,
+                 graph: bool = True, ctx: Optional[Context] = None):
+        lib = load()
+        self.ctx = ctx or default_context()
+        o = ServerOpts()
+        _check(lib.fs1_server_opts_default(ctypes.byref(o)))
+        o.hbm_budget = int(hbm_budget)
+        o.max_active = int(max_active)
+        o.dtype = {"f64": FS1_F64, "f32": FS1_F32}[dtype]
+        o.itr_max = int(itr_max)
+        o.check_every = int(check_every)
+        o.iters_per_step = int(iters_per_step)
+        o.flags = 0 if graph else FS1_FLAG_NO_GRAPH
+        h = ctypes.c_void_p()
+        _check(lib.fs1_server_create(self.ctx.handle, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._held = {}
+        self._buf = (Completion * 1024)()
+
+    def submit(self, mu, nu, eps: float, tol: float) -> int:
+        if mu.numel() != nu.numel():
+            raise ValueError("mu and nu must have the same length")
+        t = ctypes.c_int64()
+        _check(load().fs1_server_submit(self.handle, _dev(mu, "mu"), _dev(nu, "nu"), mu.numel(),
+                                        float(eps), float(tol), ctypes.byref(t)))
+        self._held[t.value] = (mu, nu)
+        return t.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(load().fs1_server_step(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def poll(self) -> list:
+        """[(ticket, Result, admitted_step, completed_step), ...], oldest first."""
+        out = []
+        while True:
+            k = ctypes.c_int32()
+            _check(load().fs1_server_poll(self.handle, self._buf, len(self._buf),
+                                          ctypes.byref(k)))
+            for c in self._buf[:k.value]:
+                r = c.result
+                out.append((c.ticket, Result(r.w1, r.marginal_err, r.mu_err, r.iterations,
+                                             bool(r.converged), r.status),
+                            c.admitted_step, c.completed_step))
+                self._held.pop(c.ticket, None)
+            if k.value < len(self._buf):
+                return out
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(load().fs1_server_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().fs1_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

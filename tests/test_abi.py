@@ -105,3 +105,46 @@ def test_batched_validation_without_context():
     e = (ctypes.c_double * 1)(0.1)
     st = lib.fs1_solve_batched(None, None, None, offs, 1, e, e, None, r)
     assert st == fs1.FS1_ERR_INVALID_ARG and "context" in fs1.last_error()
+
+
+def test_server_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout2.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fs1.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fs1_server_opts),
+         offsetof(fs1_server_opts, max_active), offsetof(fs1_server_opts, iters_per_step),
+         offsetof(fs1_server_opts, flags), sizeof(fs1_completion),
+         offsetof(fs1_completion, result), offsetof(fs1_completion, admitted_step),
+         offsetof(fs1_completion, completed_step), sizeof(fs1_server_info),
+         offsetof(fs1_server_info, bytes_total));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout2"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    S, C, I = fs1.ServerOpts, fs1.Completion, fs1.ServerInfo
+    want = [ctypes.sizeof(S), S.max_active.offset, S.iters_per_step.offset, S.flags.offset,
+            ctypes.sizeof(C), C.result.offset, C.admitted_step.offset, C.completed_step.offset,
+            ctypes.sizeof(I), I.bytes_total.offset]
+    assert got == want
+
+
+def test_server_validation_without_gpu():
+    lib = _lib()
+    o = fs1.ServerOpts()
+    assert lib.fs1_server_opts_default(ctypes.byref(o)) == 0
+    assert o.dtype == fs1.FS1_F32 and o.iters_per_step == 16 and o.max_active == 4096
+    h = ctypes.c_void_p()
+    assert lib.fs1_server_create(None, ctypes.byref(o), ctypes.byref(h)) == fs1.FS1_ERR_INVALID_ARG
+    assert lib.fs1_server_step(None, None) == fs1.FS1_ERR_INVALID_ARG
+    t = ctypes.c_int64()
+    assert lib.fs1_server_submit(None, None, None, 4, 0.1, 0.0,
+                                 ctypes.byref(t)) == fs1.FS1_ERR_INVALID_ARG
+    assert lib.fs1_server_destroy(None) == 0
+
