@@ -36,10 +36,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s (vendor figure)
 PROFILE_STRIDE = 4             # time every 4th polling batch of update kernels
 N_C2 = 1 << 20
 SEED = 1
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_half_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_10042_amd", "csrc", f)
-                  for f in ("fs1_kernels.hip", "fs1_fused.hip", "fs1_persist.hip",
-                            "fs1_device.h", "fs1_frame.h", "fs1_internal.h")]
+                  for f in ("fs1_fused.hip", "fs1_frame.h", "fs1_device.h", "fs1_internal.h")]
 
 
 def log(*a):
@@ -115,11 +114,17 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="a 256 MiB device copy, then one fixed 300-iteration solve of the "
+                         "workload (for hardware-counter runs)")
     ap.add_argument("--large", action="store_true",
                     help="also run the N=1e8 eps=1e-4 precision-study solve (f64 and f32)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 4096-instance uneven batch (binary32, tol 1e-6)")
     ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the Poisson request stream through the server")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,6 +153,13 @@ def main():
     mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
     nu = torch.tensor(nu_np, dtype=torch.float64, device="cuda")
     ctx = fs1.Context(torch.cuda.current_stream())
+    if args.traffic_probe:
+        copy_calibration(256)
+        r = fs1.fs1_solve(mu, nu, args.eps, 0.0, itr_max=300, dtype=args.dtype, domain="log",
+                          sync_every=64, ctx=ctx)
+        torch.cuda.synchronize()
+        log(f"probe solve: {r.iterations} iterations, w1 {r.w1:.12g}")
+        return
 
     def solve(dtype, eps, itr_max=args.itr_max, tol=args.tol, m=mu, v=nu):
         return fs1.fs1_solve(m, v, eps, tol, itr_max=itr_max, dtype=dtype, domain="log",
@@ -243,6 +255,9 @@ def main():
 
     if not args.no_batched:
         out["batched"] = batched_study(fs1, ctx, inputs, np, torch, args.batch)
+
+    if not args.no_serving:
+        out["serving"] = serving_study(fs1, ctx, inputs, np, torch, args.serve_seconds)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle.fs1_log, {args.cpu_iters} iterations at N={n} ...")
@@ -349,6 +364,98 @@ def batched_study(fs1, ctx, inputs, np, torch, B: int):
     log(f"single f64 path: {single:.1f} solves/s on {len(sample)} sampled pairs; "
         f"batched f32 speedup {rows['speedup_f32_batched_vs_f64_single']:.1f}x")
     return rows
+
+
+def serve_run(fs1, srv, pool, np, arrivals, window: float, drain: bool):
+    """Feed `arrivals` (s, sorted) into the server in wall-clock time; requests
+    cycle through the pool of device pairs.  Returns latencies (s) of the
+    completed requests, completions inside the window and the elapsed time."""
+    t_arr = {}
+    lat = []
+    done_in_window = 0
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k] <= now and now < window:
+            m, v, e = pool[k % len(pool)]
+            t_arr[srv.submit(m, v, e, 1e-6)] = arrivals[k]
+            k += 1
+        srv.step()
+        now = time.perf_counter() - t0
+        for t, r, a, c in srv.poll():
+            lat.append(now - t_arr.pop(t))
+            if now <= window:
+                done_in_window += 1
+            if r.status != 0:
+                raise RuntimeError(f"request {t} failed: {r}")
+        info = srv.info()
+        if now >= window and (not drain or (info["queued"] == 0 and info["active"] == 0)):
+            return np.array(lat), done_in_window, now, info, k
+
+
+def serving_study(fs1, ctx, inputs, np, torch, seconds: float):
+    """Request stream: Poisson arrivals, each request a seeded mixture pair with
+    N log-uniform in [128, 2^20] and eps in {1e-2, 1e-3}, tol 1e-6, binary32
+    scans, 64 GB admission budget.  Requests cycle through a pool of 256
+    distinct device-resident pairs.  Two runs: the offered 20k requests/s
+    (saturating: solves/s is the server's capacity, latency includes the
+    growing queue) and half of the measured capacity (latency at a sustainable
+    rate, drained at the end)."""
+    seed = 77
+    P = 256
+    spec = inputs.batch_spec(P, 128, 1 << 20, [1e-2, 1e-3], seed)
+    mu_np, nu_np, offs = inputs.batch_hists(spec)
+    pool = []
+    for i in range(P):
+        a, b = int(offs[i]), int(offs[i + 1])
+        pool.append((torch.tensor(mu_np[a:b], dtype=torch.float64, device="cuda"),
+                     torch.tensor(nu_np[a:b], dtype=torch.float64, device="cuda"),
+                     float(spec.eps[i])))
+    torch.cuda.synchronize()
+    log(f"serving: pool of {P} pairs, mean N {offs[-1] / P:.0f}")
+    srv = fs1.Server(hbm_budget=64 << 30, max_active=4096, dtype="f32", itr_max=10000,
+                     iters_per_step=16, ctx=ctx)
+    # warm-up: a few requests through the server
+    for m, v, e in pool[:8]:
+        srv.submit(m, v, e, 1e-6)
+    while srv.info()["active"] or srv.info()["queued"]:
+        srv.step()
+        srv.poll()
+    out = {}
+    rate = 20000.0
+    arr = inputs.poisson_arrivals(rate, seconds, seed)
+    lat, nwin, el, info, sub = serve_run(fs1, srv, pool, np, arr, seconds, drain=False)
+    cap = nwin / seconds
+    out["offered_20k"] = {
+        "offered_per_s": rate, "window_s": seconds, "submitted": int(sub),
+        "completed_in_window": int(nwin), "solves_per_s": cap,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+        "left_queued": int(info["queued"]), "left_active": int(info["active"]),
+        "note": "offered load above capacity: latency includes a queue that grows "
+                "through the window"}
+    log(f"serving at 20k req/s offered: {cap:.1f} solves/s, p50 "
+        f"{out['offered_20k']['p50_latency_ms']:.1f} ms p99 "
+        f"{out['offered_20k']['p99_latency_ms']:.1f} ms, {info['queued']} still queued")
+    srv.close()
+    srv = fs1.Server(hbm_budget=64 << 30, max_active=4096, dtype="f32", itr_max=10000,
+                     iters_per_step=16, ctx=ctx)
+    rate2 = max(1.0, 0.5 * cap)
+    arr = inputs.poisson_arrivals(rate2, seconds, seed + 1)
+    lat, nwin, el, info, sub = serve_run(fs1, srv, pool, np, arr, seconds, drain=True)
+    out["half_capacity"] = {
+        "offered_per_s": rate2, "window_s": seconds, "submitted": int(sub),
+        "completed": int(lat.size), "solves_per_s": lat.size / el,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None}
+    log(f"serving at {rate2:.0f} req/s: p50 {out['half_capacity']['p50_latency_ms']:.1f} ms "
+        f"p99 {out['half_capacity']['p99_latency_ms']:.1f} ms")
+    srv.close()
+    out["config"] = {"pool": P, "n_lo": 128, "n_hi": 1 << 20, "eps": [1e-2, 1e-3], "tol": 1e-6,
+                     "hbm_budget_bytes": 64 << 30, "dtype": "f32", "iters_per_step": 16,
+                     "seed": seed}
+    return out
 
 
 if __name__ == "__main__":
