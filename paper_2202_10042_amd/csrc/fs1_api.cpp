@@ -510,7 +510,12 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const bool absorb = o.domain == FS1_LOG;
   const int dt = o.dtype;
   const size_t es = dt == FS1_F64 ? 8 : 4;
-  const int R = pick_run_length(dt, absorb, h / eps);
+  int R = pick_run_length(dt, absorb, h / eps);
+  // the fused one-launch-per-half path picks its own run length where it applies
+  if (absorb && !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
+    const int rf = fused_run_length(dt, h / eps, n);
+    if (rf > 0) R = rf;
+  }
   const int64_t C = int64_t(kBlock) * R;
   const int64_t nchunks = (n + C - 1) / C;
   if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));

@@ -211,9 +211,11 @@ __device__ __forceinline__ void local_scan(const T (&x)[R], int ex, const Lam<T>
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int eb = block_max_int(local_exponent<T, R>(x, ex), smax);
-  hs.ein = (eb == kExpZero) ? 0 : eb;
+  // an all-zero chunk keeps the zero exponent: its frame then comes from the
+  // carries alone (see frame_apply)
+  hs.ein = eb;
 #pragma unroll
-  for (int j = 0; j < R; ++j) hs.xf[j] = ldx(x[j], ex - hs.ein);
+  for (int j = 0; j < R; ++j) hs.xf[j] = (eb == kExpZero) ? T(0) : ldx(x[j], ex - hs.ein);
   T f, b;
   run_aggs<T, R>(hs.xf, L, f, b);
 #pragma unroll
@@ -272,7 +274,8 @@ __device__ __forceinline__ int half_apply(const ChunkAgg* A, int nchunks, const 
   int eap = hs.ein;
   if (cf.m != 0.0) eap = max(eap, cf.e);
   if (cb.m != 0.0) eap = max(eap, cb.e);
-  const int sh = hs.ein - eap;  // <= 0: rescale the chunk-frame quantities
+  if (eap == kExpZero) eap = 0;  // nothing nonzero reaches this chunk
+  const int sh = (hs.ein == kExpZero) ? 0 : hs.ein - eap;  // <= 0: rescale the chunk-frame quantities
   T accf = T(ldexp(cf.m, cf.e - eap));
   T accb = T(ldexp(cb.m, cb.e - eap));
   for (int v = 0; v < w; ++v) accf = fma(D.wave, accf, ldx(sf[v], sh));
@@ -297,7 +300,8 @@ __device__ __forceinline__ int frame_apply(const Lam<T>& L, const FastDec<T>& D,
   int eap = hs.ein;
   if (cf.m != 0.0) eap = max(eap, cf.e);
   if (cb.m != 0.0) eap = max(eap, cb.e);
-  const int sh = hs.ein - eap;
+  if (eap == kExpZero) eap = 0;  // nothing nonzero reaches this chunk
+  const int sh = (hs.ein == kExpZero) ? 0 : hs.ein - eap;  // chunk-local values are all zero then
   T accf = T(ldexp(cf.m, cf.e - eap));
   T accb = T(ldexp(cb.m, cb.e - eap));
   for (int v = 0; v < w; ++v) accf = fma(D.wave, accf, ldx(sf[v], sh));

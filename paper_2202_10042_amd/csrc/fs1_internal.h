@@ -135,6 +135,8 @@ hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_ma
 // One launch per half-iteration with in-kernel chunk carries (log domain,
 // chunk frame valid, moderate chunk count).
 bool usable_fused(const SolveBufs& b, double c);
+// Run length for the fused path at this size (0: the fused path does not apply).
+int fused_run_length(int dtype, double c, int64_t n);
 hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
 hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
                              double tol, bool psi, hipStream_t s, hipEvent_t ev0 = nullptr,
