@@ -524,15 +524,20 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   // workspace layout
   SolveBufs b{};
   unsigned* bar = nullptr;
+  const int64_t npad = nchunks * C;  // vectors are allocated to whole chunks
+  double* mu64 = nullptr;
+  double* nu64 = nullptr;
   auto layout = [&](Carve& w) {
-    b.vF = w.take(n * es);
-    b.vG[0] = w.take(n * es);
-    b.vG[1] = w.take(n * es);
+    b.vF = w.take(npad * es);
+    b.vG[0] = w.take(npad * es);
+    b.vG[1] = w.take(npad * es);
     b.eF = static_cast<int*>(w.take(nruns * sizeof(int)));
     b.eG[0] = static_cast<int*>(w.take(nruns * sizeof(int)));
     b.eG[1] = static_cast<int*>(w.take(nruns * sizeof(int)));
-    b.mu32 = dt == FS1_F32 ? w.take(n * sizeof(float)) : nullptr;
-    b.nu32 = dt == FS1_F32 ? w.take(n * sizeof(float)) : nullptr;
+    b.mu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
+    b.nu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
+    mu64 = static_cast<double*>(w.take(npad * sizeof(double)));
+    nu64 = static_cast<double*>(w.take(npad * sizeof(double)));
     b.aggF = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
     b.aggG = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
     b.carry = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
@@ -556,8 +561,11 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   b.n = n;
   b.nchunks = nchunks;
   b.R = R;
-  b.mu = mu;
-  b.nu = nu;
+  b.npad = npad;
+  b.mu_src = mu;
+  b.nu_src = nu;
+  b.mu = mu64;
+  b.nu = nu64;
   b.err_hist = o.err_history;
   hipStream_t s = ctx->stream;
   Ctrl* hc = ctx->hctrl;

@@ -288,12 +288,16 @@ struct Vec16<float> {
   static constexpr int n = 4;
 };
 
+// The vector-or-guarded choice is made per wavefront (a ballot over the
+// active lanes), not per lane: a divergent choice would run both sides and
+// make the guarded side wait for every load still in flight, since both write
+// the same registers.
 template <typename T, int R>
 __device__ __forceinline__ void load_run(const T* __restrict__ p, int64_t base, int64_t n,
                                          T (&x)[R], T fill) {
   constexpr int V = Vec16<T>::n;
   if constexpr (R % V == 0) {
-    if (base + R <= n) {
+    if (__builtin_amdgcn_ballot_w64(base + R > n) == 0) {
       using VT = typename Vec16<T>::type;
       const VT* q = reinterpret_cast<const VT*>(p + base);
 #pragma unroll
@@ -321,7 +325,7 @@ __device__ __forceinline__ void store_run(T* __restrict__ p, int64_t base, int64
                                           const T (&x)[R]) {
   constexpr int V = Vec16<T>::n;
   if constexpr (R % V == 0) {
-    if (base + R <= n) {
+    if (__builtin_amdgcn_ballot_w64(base + R > n) == 0) {
       using VT = typename Vec16<T>::type;
       VT* q = reinterpret_cast<VT*>(p + base);
 #pragma unroll
@@ -344,6 +348,53 @@ __device__ __forceinline__ void store_run(T* __restrict__ p, int64_t base, int64
 #pragma unroll
   for (int j = 0; j < R; ++j)
     if (base + j < n) p[base + j] = x[j];
+}
+
+// Run loads and stores on arrays allocated to whole chunks whose entries past
+// n hold zeros (every run of the grid lies inside the allocation): plain
+// 16-byte vector accesses, with no branch or select that would make the
+// kernel wait for a load before it needs the value.
+template <typename T, int R>
+__device__ __forceinline__ void load_run_z(const T* __restrict__ p, int64_t base, T (&x)[R]) {
+  constexpr int V = Vec16<T>::n;
+  static_assert(R % V == 0, "padded runs are whole 16-byte vectors");
+  using VT = typename Vec16<T>::type;
+  const VT* q = reinterpret_cast<const VT*>(p + base);
+#pragma unroll
+  for (int i = 0; i < R / V; ++i) {
+    const VT v = q[i];
+    if constexpr (V == 2) {
+      x[2 * i] = v.x;
+      x[2 * i + 1] = v.y;
+    } else {
+      x[4 * i] = v.x;
+      x[4 * i + 1] = v.y;
+      x[4 * i + 2] = v.z;
+      x[4 * i + 3] = v.w;
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void store_run_z(T* __restrict__ p, int64_t base, const T (&x)[R]) {
+  constexpr int V = Vec16<T>::n;
+  static_assert(R % V == 0, "padded runs are whole 16-byte vectors");
+  using VT = typename Vec16<T>::type;
+  VT* q = reinterpret_cast<VT*>(p + base);
+#pragma unroll
+  for (int i = 0; i < R / V; ++i) {
+    VT v;
+    if constexpr (V == 2) {
+      v.x = x[2 * i];
+      v.y = x[2 * i + 1];
+    } else {
+      v.x = x[4 * i];
+      v.y = x[4 * i + 1];
+      v.z = x[4 * i + 2];
+      v.w = x[4 * i + 3];
+    }
+    q[i] = v;
+  }
 }
 
 // ===========================================================================

@@ -345,9 +345,13 @@ __device__ __forceinline__ void update_frame(const T (&mg)[R], const T (&y)[R], 
 // Chunk aggregates of values given on one frame (exponent e for the whole
 // chunk), by weighted reductions instead of scans: the forward aggregate is
 // sum_t af(t) lambda^{(255 - t) R}, the backward one sum_t ab(t) lambda^{t R}.
+// With `part` non-null the same reduction also sums each thread's `err` (in a
+// fixed order) and thread 0 stores the total to part[blockIdx.x].
 template <typename T, int R>
 __device__ __forceinline__ void publish_frame(const T (&q)[R], int e, const Lam<T>& L,
-                                              const FastDec<T>& D, T* sf, T* sb, ChunkAgg* A) {
+                                              const FastDec<T>& D, T* sf, T* sb, ChunkAgg* A,
+                                              double err = 0.0, double* sred = nullptr,
+                                              double* part = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   T f, b;
@@ -358,13 +362,21 @@ __device__ __forceinline__ void publish_frame(const T (&q)[R], int e, const Lam<
   for (int d = kWave / 2; d >= 1; d >>= 1) {
     f += __shfl_xor(f, d);
     b += __shfl_xor(b, d);
+    if (part) err += __shfl_xor(err, d);
   }
   if (lane == 0) {
     sf[w] = f;
     sb[w] = b;
+    if (part) sred[w] = err;
   }
   __syncthreads();
   publish<T>(D, sf, sb, e, A);
+  if (part && threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int v = 0; v < kNW; ++v) t += sred[v];
+    part[blockIdx.x] = t;
+  }
 }
 
 // New run values q = marg / y (zero marginal -> zero), renormalised so that the

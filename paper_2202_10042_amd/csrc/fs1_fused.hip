@@ -1,18 +1,21 @@
 // fs1_fused.hip -- one kernel launch per half-iteration of Algorithm 1.
 //
 // Each workgroup owns one chunk.  A launch of k_fused
+//   * recomputes its chunk carries from the chunk aggregates the previous
+//     launch published (the whole workgroup, extended range), while the
+//     chunk's own data is still arriving,
+//   * runs the in-chunk recursions of Sec. 3, eq. (recursion) on a per-chunk
+//     frame (fs1_frame.h),
+//   * writes its share of the stopping error (psi-half of checked iterations),
 //   * takes the stop decision of Algorithm 1 for the current iteration (every
 //     workgroup sums the previous launch's per-chunk error shares in the same
-//     fixed order, so all of them decide alike),
-//   * recomputes its chunk carries from the chunk aggregates the previous
-//     launch published (the whole workgroup, extended range; the aggregates
-//     are loaded at kernel start so the loads overlap the chunk's scans),
-//   * runs the in-chunk recursions of Sec. 3, eq. (recursion) on a per-chunk
-//     frame (fs1_frame.h) and the Sinkhorn update of Sec. 2
-//     (psi = nu / K^T phi, or phi = mu / K psi),
-//   * writes its share of the stopping error (psi-half of checked iterations),
-//   * publishes the chunk aggregates of the new vector for the next launch.
-// Kernel boundaries order everything: no inter-workgroup waiting.
+//     fixed order, so all of them decide alike) -- last, so that its loads are
+//     hidden behind the arithmetic -- and unless it stops,
+//   * applies the Sinkhorn update of Sec. 2 (psi = nu / K^T phi, or
+//     phi = mu / K psi), stores it and publishes the chunk aggregates of the
+//     new vector for the next launch.
+// Launches after the stop still do the arithmetic but store nothing.  Kernel
+// boundaries order everything: no inter-workgroup waiting.
 #include "fs1_device.h"
 #include "fs1_frame.h"
 #include "fs1_internal.h"
@@ -62,98 +65,115 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t base = run * R;
-  const int64_t n = a.n;
   const bool want_err = (MODE == F_ERR) || (MODE == F_PSI && a.check);
 
-  // Every global load of the launch is issued here, before any use, so the
-  // launch pays one memory round trip instead of one per phase.
-  // The stop and failure flags were written by earlier launches (kernel
-  // boundaries order them), so one plain load per workgroup suffices.
+  // Every global load of the launch is issued here, before any use, oldest
+  // first: the stop flags and error shares (needed last), the chunk
+  // aggregates (needed first, for the carries), the chunk's own data.  The
+  // flags were written by earlier launches (kernel boundaries order them).
   int done = 0, fail = 0;
-  double share = 0.0;
+  double sh4[kMaxFusedChunks / kBlock];  // this thread's error shares, chunks tid + 256 i
   if constexpr (MODE != F_ERR) {
-    if (threadIdx.x < kWave) {
-      if (lane == 0) {
-        done = a.ctrl->done;
-        fail = a.ctrl->fail;
+    if (threadIdx.x == 0) {
+      done = a.ctrl->done;
+      fail = a.ctrl->fail;
+    }
+    if (MODE == F_PHI && a.check) {
+#pragma unroll
+      for (int i = 0; i < kMaxFusedChunks / kBlock; ++i) {
+        const int c = int(threadIdx.x) + i * kBlock;
+        sh4[i] = c < a.nchunks ? a.part[c] : 0.0;
       }
-      if (MODE == F_PHI && a.check)
-        for (int c = lane; c < a.nchunks; c += kWave) share += a.part[c];
     }
   }
   CarryItems<kCarryMax> items;
   carry_prefetch<kCarryMax>(a.A_in, blockIdx.x, a.nchunks, items);
+  // (every vector is allocated to whole chunks and zero past n: plain vector
+  // loads)
   T x[R];
-  load_run<T, R>(static_cast<const T*>(a.vin), base, n, x, T(0));
+  load_run_z<T, R>(static_cast<const T*>(a.vin), base, x);
   const int ex = a.ein[run];
   T own[R];
   double m64[R];
   int eo = 0;
   if (want_err) {
-    load_run<T, R>(static_cast<const T*>(a.vown), base, n, own, T(0));
+    load_run_z<T, R>(static_cast<const T*>(a.vown), base, own);
     eo = a.eown[run];
   }
-  if (want_err || sizeof(T) == 8) load_run<double, R>(a.m64, base, n, m64, 0.0);
+  if (want_err || sizeof(T) == 8) load_run_z<double, R>(a.m64, base, m64);
   T mg[R];
   if constexpr (MODE != F_ERR) {
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
       for (int j = 0; j < R; ++j) mg[j] = T(m64[j]);
     } else {
-      load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, n, mg, T(0));
+      load_run_z<T, R>(reinterpret_cast<const T*>(a.m32), base, mg);
     }
   }
 
-  if constexpr (MODE != F_ERR) {
-    // 3: already stopped; 2: a scaling became non-finite; 1: err(l) <= tol
-    if (threadIdx.x < kWave) {
-      done = __shfl(done, 0);
-      fail = __shfl(fail, 0);
-      int dec = 0;
-      if (done) {
-        dec = 3;
-      } else if (fail) {
-        dec = 2;
-      } else if (MODE == F_PHI && a.check) {
-        double s = share;
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-        if (lane == 0 && blockIdx.x == 0) {
-          a.ctrl->last_err = s;
-          a.ctrl->last_check = a.l;
-          if (a.err_hist) a.err_hist[a.l] = s;
-        }
-        if (!(s > a.tol)) dec = 1;
-      }
-      if (lane == 0) sdec = dec;
-    }
-    __syncthreads();
-    if (sdec) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (sdec == 1) a.ctrl->stop_iter = a.l;
-        a.ctrl->done = 1;
-      }
-      return;
-    }
-  }
-
+  // chunk carries first: they need only the aggregates, so this work runs
+  // while the chunk's own data is still arriving
+  carry_finish<kCarryMax>(items, blockIdx.x, a.cpow, red4, scar);
   const Lam<T> L = lam_of<T>(k);
   const FastDec<T> D = make_fast_dec<T>(k, lane);
   HalfState<T, R> hs;
   local_scan<T, R>(x, ex, L, D, sf, sb, smax, hs);
-  carry_finish<kCarryMax>(items, blockIdx.x, a.cpow, red4, scar);
   T y[R];
   const int eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
 
+  // this thread's share of the stopping error (entries past n are zero and
+  // add nothing); reduced with the chunk aggregates at the end
+  double es = 0.0;
   if (want_err) {
-    // entries past n load as zero and add nothing
-    double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < R; ++j) s += fabs(ldexp(double(own[j]) * double(y[j]), eo + eap) - m64[j]);
-    const double tot = block_sum<kNW>(s, red);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+    for (int j = 0; j < R; ++j) es += fabs(ldexp(double(own[j]) * double(y[j]), eo + eap) - m64[j]);
   }
-  if constexpr (MODE == F_ERR) return;
+  if constexpr (MODE == F_ERR) {
+    const double tot = block_sum<kNW>(es, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+    return;
+  }
+
+  // Stop decision of Algorithm 1, taken before anything is stored.
+  // 3: already stopped; 2: a scaling became non-finite; 1: err(l) <= tol.
+  // Every workgroup sums the same shares with the same tree, so all decide
+  // alike.
+  if (MODE == F_PHI && a.check) {
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxFusedChunks / kBlock; ++i) e += sh4[i];
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
+    if (lane == 0) red[threadIdx.x / kWave] = e;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int dec = 0;
+    if (done) {
+      dec = 3;
+    } else if (fail) {
+      dec = 2;
+    } else if (MODE == F_PHI && a.check) {
+      double e = 0.0;
+#pragma unroll
+      for (int v = 0; v < kNW; ++v) e += red[v];
+      if (blockIdx.x == 0) {
+        a.ctrl->last_err = e;
+        a.ctrl->last_check = a.l;
+        if (a.err_hist) a.err_hist[a.l] = e;
+      }
+      if (!(e > a.tol)) dec = 1;
+    }
+    sdec = dec;
+  }
+  __syncthreads();
+  if (sdec) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && sdec != 3) {
+      if (sdec == 1) a.ctrl->stop_iter = a.l;
+      a.ctrl->done = 1;
+    }
+    return;
+  }
 
   // the new vector is q * 2^-eap: every run of the chunk gets exponent -eap
   T q[R];
@@ -163,10 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
     atomicOr(&a.ctrl->fail, 1);
     atomicMin(&a.ctrl->fail_iter, a.l);
   }
-  store_run<T, R>(static_cast<T*>(a.vout), base, n, q);
+  store_run_z<T, R>(static_cast<T*>(a.vout), base, q);
   a.eout[run] = -eap;
-  // aggregates of the new vector for the next launch
-  publish_frame<T, R>(q, -eap, L, D, sf, sb, a.A_out);
+  // aggregates of the new vector for the next launch, and the error share
+  publish_frame<T, R>(q, -eap, L, D, sf, sb, a.A_out, es, red, want_err ? a.part : nullptr);
 }
 
 // Chunk aggregates of a stored vector (initial state, finalisation).
@@ -180,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_publish(const T* __restrict__ v,
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   T x[R];
-  load_run<T, R>(v, run * R, n, x, T(0));
+  load_run_z<T, R>(v, run * R, x);
   const Lam<T> L = lam_of<T>(k);
   const FastDec<T> D = make_fast_dec<T>(k, lane);
   HalfState<T, R> hs;

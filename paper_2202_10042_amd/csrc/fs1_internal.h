@@ -106,13 +106,16 @@ struct SolveBufs {
   int absorb;         // 1: log-domain (per-run exponents renormalised every half)
   int64_t n;
   int64_t nchunks;
+  int64_t npad;       // nchunks * chunk length: every vector is allocated to whole chunks
   int R;
-  const double* mu;   // caller marginals (binary64)
+  const double* mu_src;  // the caller's marginals (read by the set-up only)
+  const double* nu_src;
+  const double* mu;   // binary64 copies, zero-padded to npad
   const double* nu;
-  void* mu32;         // float copies (dtype 1)
+  void* mu32;         // float copies (dtype 1), zero-padded
   void* nu32;
-  void* vF;           // phi values (n)
-  void* vG[2];        // psi values, double-buffered (n)
+  void* vF;           // phi values (npad)
+  void* vG[2];        // psi values, double-buffered (npad)
   int* eF;            // phi run exponents (nruns)
   int* eG[2];         // psi run exponents
   ChunkAgg* aggF;     // chunk aggregates of phi

@@ -499,17 +499,25 @@ __global__ __launch_bounds__(kBlock) void k_cost_apply(const T* __restrict__ vph
 // ===========================================================================
 __global__ __launch_bounds__(256) void k_setup(const double* __restrict__ mu,
                                                const double* __restrict__ nu, int64_t n,
+                                               int64_t npad, double* __restrict__ mu64,
+                                               double* __restrict__ nu64,
                                                float* __restrict__ mu32,
                                                float* __restrict__ nu32, Ctrl* ctrl) {
   __shared__ double red[4];
   double sm = 0.0, sn = 0.0;
   int bad = 0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npad;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const double a = mu[i], b = nu[i];
+    double a = 0.0, b = 0.0;  // zero padding past n
+    if (i < n) {
+      a = mu[i];
+      b = nu[i];
+    }
     bad |= !(isfinite(a) && a >= 0.0) || !(isfinite(b) && b >= 0.0);
     sm += a;
     sn += b;
+    mu64[i] = a;
+    nu64[i] = b;
     if (mu32) {
       mu32[i] = float(a);
       nu32[i] = float(b);
@@ -526,12 +534,13 @@ __global__ __launch_bounds__(256) void k_setup(const double* __restrict__ mu,
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(T* __restrict__ vf, T* __restrict__ vg, int* ef,
-                                              int* eg, int64_t n, int64_t nruns, Ctrl* ctrl) {
+                                              int* eg, int64_t n, int64_t npad, int64_t nruns,
+                                              Ctrl* ctrl) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const T v = T(1.0 / double(n));
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    vf[i] = v;
-    vg[i] = v;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npad; i += stride) {
+    vf[i] = i < n ? v : T(0);
+    vg[i] = i < n ? v : T(0);
   }
   if (ef) {
     for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < nruns; r += stride) {
@@ -752,9 +761,10 @@ struct SolveOps {
   }
   static hipError_t init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
     const int64_t nruns = b.nchunks * kBlock;
-    const unsigned g = unsigned(std::min<int64_t>((std::max(b.n, nruns) + 255) / 256, 4096));
+    const unsigned g = unsigned(std::min<int64_t>((std::max(b.npad, nruns) + 255) / 256, 4096));
     k_init<T><<<g, 256, 0, s>>>(static_cast<T*>(b.vF), static_cast<T*>(b.vG[0]),
-                                AB ? b.eF : nullptr, AB ? b.eG[0] : nullptr, b.n, nruns, b.ctrl);
+                                AB ? b.eF : nullptr, AB ? b.eG[0] : nullptr, b.n, b.npad, nruns,
+                                b.ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return setup_aggF(b, k, s);
@@ -790,8 +800,9 @@ static hipError_t dispatch(const SolveBufs& b, F&& f) {
 }
 
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s) {
-  const unsigned g = unsigned(std::min<int64_t>((b.n + 255) / 256, 2048));
-  k_setup<<<g, 256, 0, s>>>(b.mu, b.nu, b.n, static_cast<float*>(b.mu32),
+  const unsigned g = unsigned(std::min<int64_t>((b.npad + 255) / 256, 2048));
+  k_setup<<<g, 256, 0, s>>>(b.mu_src, b.nu_src, b.n, b.npad, const_cast<double*>(b.mu),
+                            const_cast<double*>(b.nu), static_cast<float*>(b.mu32),
                             static_cast<float*>(b.nu32), b.ctrl);
   return hipGetLastError();
 }
