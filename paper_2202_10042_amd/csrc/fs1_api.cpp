@@ -153,12 +153,12 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
   if (nchunks > int64_t(INT32_MAX)) return set_err(FS1_ERR_INVALID_ARG, "n too large");
   Carve cv(nullptr);
   cv.take(nchunks * sizeof(ChunkAgg));
-  cv.take(nchunks * sizeof(ChunkAgg));
+  cv.take(carry_buffer_bytes(nchunks));
   st = ensure_ws(ctx, cv.off);
   if (st) return st;
   Carve w(ctx->ws);
   ChunkAgg* agg = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
-  ChunkAgg* carry = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+  ChunkAgg* carry = static_cast<ChunkAgg*>(w.take(carry_buffer_bytes(nchunks)));
   const ScanConsts k = make_scan_consts(h, eps, R);
   const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
   hipError_t e = log ? launch_kv_log(dt, x, y, n, k, kc, agg, carry, ctx->stream)
@@ -540,7 +540,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     nu64 = static_cast<double*>(w.take(npad * sizeof(double)));
     b.aggF = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
     b.aggG = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
-    b.carry = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
+    b.carry = static_cast<ChunkAgg*>(w.take(carry_buffer_bytes(nchunks)));
     b.agg2 = w.take(nchunks * 48);
     b.carry2 = w.take(nchunks * 48);
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));

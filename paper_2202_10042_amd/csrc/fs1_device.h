@@ -177,6 +177,32 @@ struct S2 {
   }
 };
 
+// Carry of chunk c from the carry buffer: under the two-level scan the stored
+// value covers the chunk's own group of 1024 chunks, and the group's carry
+// (stored after the chunk carries) is added, moved to the chunk: forward by
+// j chunks, backward by (chunks in the group) - 1 - j.
+__device__ __forceinline__ ChunkAgg chunk_carry(const ChunkAgg* carry, const CarryFix& cf,
+                                                int64_t c) {
+  ChunkAgg lc = carry[c];
+  if (!cf.two_level) return lc;
+  constexpr int64_t G = kCarryBlock;
+  const int64_t ng = (cf.nchunks + G - 1) / G;
+  const int64_t g = c / G, j = c - g * G;
+  const int64_t gact = min(G, cf.nchunks - g * G);
+  const ChunkAgg gc = carry[cf.nchunks + ng + g];
+  XF<double> pf = {1.0, 0}, pb = {1.0, 0};
+#pragma unroll
+  for (int s = 0; s < 11; ++s) {
+    if ((j >> s) & 1) pf = {pf.m * cf.cpow[s].m, pf.e + cf.cpow[s].e};
+    if (((gact - 1 - j) >> s) & 1) pb = {pb.m * cf.cpow[s].m, pb.e + cf.cpow[s].e};
+  }
+  const XF<double> f = xadd(XF<double>{lc.f.m, lc.f.e}, xmul(XF<double>{gc.f.m, gc.f.e}, pf));
+  const XF<double> b = xadd(XF<double>{lc.b.m, lc.b.e}, xmul(XF<double>{gc.b.m, gc.b.e}, pb));
+  lc.f = to64(xnorm(f));
+  lc.b = to64(xnorm(b));
+  return lc;
+}
+
 // lambda^(l * unit) from the binary expansion of l (unit = the lane span).
 template <typename T>
 __device__ __forceinline__ Dec<T> lane_pow(int l, const Dec<T>* dec) {

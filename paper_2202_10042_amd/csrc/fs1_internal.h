@@ -50,14 +50,34 @@ struct ScanConsts {
   Decay step1;       // lambda itself (one grid step), in extended range
 };
 
-// Constants of the single-block carry scan over chunk aggregates.
+// Constants of the carry scan over chunk aggregates: the single-block scan
+// (group chunks per thread) for up to 1024 chunks per thread group, and the
+// two-level scan (groups of 1024 chunks, then the groups) beyond.
 struct CarryConsts {
   int64_t nchunks;
-  int64_t group;     // chunks per thread
+  int64_t group;     // chunks per thread (single-block scan)
   int64_t chunk_len; // elements per chunk
   Decay chunk;       // lambda^(chunk length)
   Decay step[7];     // lambda^(group * chunk length * 2^s), s = 0..6
+  Decay cpow[11];    // lambda^(chunk length * 2^s), s = 0..10
+  Decay gstep[7];    // lambda^(1024 * chunk length * 2^s), s = 0..6
+  int two_level;     // 1: carries from groups of 1024 chunks, then across groups
+  int pad;
 };
+
+// What a chunk kernel needs to complete its carry under the two-level scan:
+// the group's carry (stored after the chunk carries) moved to the chunk.
+struct CarryFix {
+  int64_t nchunks;
+  int two_level;
+  int pad;
+  Decay cpow[11];    // lambda^(chunk length * 2^s)
+};
+CarryFix carry_fix_of(const CarryConsts& kc);
+
+// Bytes of the carry buffer for nchunks chunks: the carries, then the group
+// aggregates, group carries and group error shares of the two-level scan.
+size_t carry_buffer_bytes(int64_t nchunks);
 
 // Device-side control block of one solve.
 struct Ctrl {

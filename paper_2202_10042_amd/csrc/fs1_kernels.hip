@@ -79,7 +79,29 @@ CarryConsts make_carry_consts(double h, double eps, int64_t chunk_len, int64_t n
   kc.chunk = make_decay(double(chunk_len), h / eps);
   for (int s = 0; s < 7; ++s)
     kc.step[s] = make_decay(double(kc.group) * double(chunk_len) * double(1 << s), h / eps);
+  for (int s = 0; s < 11; ++s) kc.cpow[s] = make_decay(double(chunk_len) * double(1 << s), h / eps);
+  for (int s = 0; s < 7; ++s)
+    kc.gstep[s] = make_decay(double(kCarryBlock) * double(chunk_len) * double(1 << s), h / eps);
+  const int64_t ng = (nchunks + kCarryBlock - 1) / kCarryBlock;
+  kc.two_level = (nchunks > kCarryBlock && ng <= kCarryBlock) ? 1 : 0;
   return kc;
+}
+
+CarryFix carry_fix_of(const CarryConsts& kc) {
+  CarryFix f{};
+  f.nchunks = kc.nchunks;
+  f.two_level = kc.two_level;
+  for (int s = 0; s < 11; ++s) f.cpow[s] = kc.cpow[s];
+  return f;
+}
+
+namespace {
+int64_t carry_groups(int64_t nchunks) { return (nchunks + kCarryBlock - 1) / kCarryBlock; }
+}  // namespace
+
+size_t carry_buffer_bytes(int64_t nchunks) {
+  const int64_t g = carry_groups(nchunks);
+  return size_t(nchunks + 2 * g) * sizeof(ChunkAgg) + size_t(g) * sizeof(double);
 }
 
 int pick_run_length(int dtype, bool absorb, double c) {
@@ -195,6 +217,131 @@ __global__ __launch_bounds__(kCarryBlock) void k_carry(const ChunkAgg* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-level carries for more than 1024 chunks: every group of 1024 chunks is
+// scanned by its own workgroup (one chunk per thread, so the work is log-deep
+// instead of the single-block scan's serial walk over `group` chunks per
+// thread), then one workgroup scans the group aggregates; each chunk kernel
+// adds its group's carry moved to it when it loads its own (chunk_carry).
+// Same semantics and modes as k_carry.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kCarryBlock) void k_carry_groups(
+    const ChunkAgg* __restrict__ agg, ChunkAgg* __restrict__ carry, ChunkAgg* __restrict__ gagg,
+    double* __restrict__ gpart, CarryConsts kc, const Ctrl* ctrl,
+    const double* __restrict__ part, int check) {
+  constexpr int NW = kCarryBlock / kWave;
+  __shared__ ScanLds<S1<double>, NW> sh;
+  __shared__ double red[NW];
+  if constexpr (MODE != 0) {
+    if (ctrl->done || ctrl->fail) return;
+  }
+  const int64_t c = int64_t(blockIdx.x) * kCarryBlock + threadIdx.x;
+  const bool in = c < kc.nchunks;
+  if constexpr (MODE == 2) {
+    if (check) {
+      const double tot = block_sum<NW>(in ? part[c] : 0.0, red);
+      if (threadIdx.x == 0) gpart[blockIdx.x] = tot;
+    }
+  }
+  S1<double> f = S1<double>::zero(), b = S1<double>::zero();
+  if (in) {
+    f = S1<double>{{agg[c].f.m, agg[c].f.e}};
+    b = S1<double>{{agg[c].b.m, agg[c].b.e}};
+  }
+  Dec<double> dec[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) dec[s] = dec_of<double>(kc.cpow[s], double(kc.chunk_len) * double(1 << s));
+  // (the last group's zero tail only moves its forward aggregate, which feeds
+  // no later group)
+  S1<double> cf, cb, af, ab;
+  block_scan<S1<double>, NW, double>(f, b, dec, S1<double>::zero(), S1<double>::zero(), &cf, &cb,
+                                     &af, &ab, sh);
+  if (in) {
+    carry[c].f = to64(cf.v);
+    carry[c].b = to64(cb.v);
+  }
+  if (threadIdx.x == 0) {
+    gagg[blockIdx.x].f = to64(af.v);
+    gagg[blockIdx.x].b = to64(ab.v);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kCarryBlock) void k_carry_top(const ChunkAgg* __restrict__ gagg,
+                                                           ChunkAgg* __restrict__ gcarry,
+                                                           int ngroups, CarryConsts kc, Ctrl* ctrl,
+                                                           const double* __restrict__ gpart,
+                                                           double* err_hist, int l, int check,
+                                                           double tol) {
+  constexpr int NW = kCarryBlock / kWave;
+  __shared__ ScanLds<S1<double>, NW> sh;
+  __shared__ double red[NW];
+  __shared__ int stop;
+  const int t = threadIdx.x;
+  if constexpr (MODE != 0) {
+    if (ctrl->done) return;
+    if (ctrl->fail) {
+      if (t == 0) ctrl->done = 1;
+      return;
+    }
+  }
+  if constexpr (MODE == 2) {
+    if (check) {
+      const double tot = block_sum<NW>(t < ngroups ? gpart[t] : 0.0, red);
+      if (t == 0) {
+        ctrl->last_err = tot;
+        ctrl->last_check = l;
+        if (err_hist) err_hist[l] = tot;
+        stop = !(tot > tol);
+        if (stop) {
+          ctrl->done = 1;
+          ctrl->stop_iter = l;
+        }
+      }
+      __syncthreads();
+      if (stop) return;
+    }
+  }
+  S1<double> f = S1<double>::zero(), b = S1<double>::zero();
+  if (t < ngroups) {
+    f = S1<double>{{gagg[t].f.m, gagg[t].f.e}};
+    b = S1<double>{{gagg[t].b.m, gagg[t].b.e}};
+  }
+  Dec<double> dec[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s)
+    dec[s] = dec_of<double>(kc.gstep[s], double(kCarryBlock) * double(kc.chunk_len) * double(1 << s));
+  S1<double> cf, cb;
+  block_scan<S1<double>, NW, double>(f, b, dec, S1<double>::zero(), S1<double>::zero(), &cf, &cb,
+                                     nullptr, nullptr, sh);
+  if (t < ngroups) {
+    gcarry[t].f = to64(cf.v);
+    gcarry[t].b = to64(cb.v);
+  }
+}
+
+// Chunk carries from chunk aggregates (single-block scan up to 1024 chunks,
+// two-level scan beyond).  `carry` holds carry_buffer_bytes(nchunks).
+template <int MODE>
+hipError_t launch_carry(const ChunkAgg* agg, ChunkAgg* carry, const CarryConsts& kc, Ctrl* ctrl,
+                        const double* part, double* err_hist, int l, int check, double tol,
+                        hipStream_t s) {
+  if (!kc.two_level) {
+    k_carry<MODE><<<1, kCarryBlock, 0, s>>>(agg, carry, kc, ctrl, part, err_hist, l, check, tol);
+    return hipGetLastError();
+  }
+  const int64_t ng = carry_groups(kc.nchunks);
+  ChunkAgg* gagg = carry + kc.nchunks;
+  ChunkAgg* gcar = gagg + ng;
+  double* gpart = reinterpret_cast<double*>(gcar + ng);
+  k_carry_groups<MODE><<<unsigned(ng), kCarryBlock, 0, s>>>(agg, carry, gagg, gpart, kc, ctrl, part,
+                                                           check);
+  k_carry_top<MODE><<<1, kCarryBlock, 0, s>>>(gagg, gcar, int(ng), kc, ctrl, gpart, err_hist, l,
+                                              check, tol);
+  return hipGetLastError();
+}
+
 // ===========================================================================
 // k_kv_apply: y = K x (plain) or ly = ln K e^lx (log)
 // ===========================================================================
@@ -202,7 +349,8 @@ template <typename T, int R, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
                                                      T* __restrict__ y_out, int64_t n,
                                                      ScanConsts k,
-                                                     const ChunkAgg* __restrict__ carry) {
+                                                     const ChunkAgg* __restrict__ carry,
+                                                     CarryFix cfix) {
   __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   T x[R];
@@ -213,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
   run_aggs<T, R>(x, L, af, ab);
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
-  const ChunkAgg cg = carry[blockIdx.x];
+  const ChunkAgg cg = chunk_carry(carry, cfix, blockIdx.x);
   S1<T> cf, cb;
   block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
                                        S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
@@ -283,27 +431,66 @@ struct HalfArgs {
   int64_t n;
   int l;
   int check;
+  CarryFix cfix;
 };
+
+// Solve vectors are allocated to whole chunks and hold zeros past n: runs are
+// read and written as whole 16-byte vectors where the run length allows.
+template <typename T, int R>
+__device__ __forceinline__ void solve_load(const T* p, int64_t base, int64_t n, T (&x)[R]) {
+  if constexpr (R % Vec16<T>::n == 0) {
+    load_run_z<T, R>(p, base, x);
+  } else {
+    load_run<T, R>(p, base, n, x, T(0));
+  }
+}
+template <typename T, int R>
+__device__ __forceinline__ void solve_store(T* p, int64_t base, int64_t n, const T (&x)[R]) {
+  if constexpr (R % Vec16<T>::n == 0) {
+    store_run_z<T, R>(p, base, x);
+  } else {
+    store_run<T, R>(p, base, n, x);
+  }
+}
 
 template <typename T, int R, bool ABSORB, int MODE>
 __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
   __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
   __shared__ double red[kBlock / kWave];
-  if constexpr (MODE != MODE_ERR) {
-    if (a.ctrl->done) return;
-  }
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t base = run * R;
   const int64_t n = a.n;
+  const bool want_err = (MODE == MODE_ERR) || (MODE == MODE_PSI && a.check);
+  // every global load is issued before any of them is waited for
+  int done = 0;
+  if constexpr (MODE != MODE_ERR) done = a.ctrl->done;
   T x[R];
-  int E;
-  load_input<T, R, ABSORB ? IN_SCALED : IN_PLAIN>(a.vin, a.ein, run, n, x, E);
+  solve_load<T, R>(a.vin, base, n, x);
+  const int E = ABSORB ? a.ein[run] : 0;
+  T own[R];
+  int eo = 0;
+  if (want_err) {
+    solve_load<T, R>(a.vown, base, n, own);
+    eo = ABSORB ? a.eown[run] : 0;
+  }
+  double m64[R];
+  if (want_err || sizeof(T) == 8) solve_load<double, R>(a.m64, base, n, m64);
+  T mg[R];
+  if constexpr (MODE != MODE_ERR) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) mg[j] = T(m64[j]);
+    } else {
+      solve_load<T, R>(reinterpret_cast<const T*>(a.m32), base, n, mg);
+    }
+  }
+  const ChunkAgg cg = chunk_carry(a.carry, a.cfix, blockIdx.x);
+  if (done) return;
   const Lam<T> L = lam_of<T>(k);
   T af, ab;
   run_aggs<T, R>(x, L, af, ab);
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
-  const ChunkAgg cg = a.carry[blockIdx.x];
   S1<T> cf, cb;
   block_scan<S1<T>, kBlock / kWave, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec,
                                        S1<T>{from64<T>(cg.f)}, S1<T>{from64<T>(cg.b)}, &cf, &cb,
@@ -320,21 +507,14 @@ __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
   T y[R];  // (K in)_j * 2^-eref
   run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
 
-  // error term sum_j | own_j (K in)_j - marg_j |, binary64
-  const bool want_err = (MODE == MODE_ERR) || (MODE == MODE_PSI && a.check);
+  // error term sum_j | own_j (K in)_j - marg_j |, binary64 (entries past n
+  // are zero and add nothing)
   if (want_err) {
-    T own[R];
-    load_run<T, R>(a.vown, base, n, own, T(0));
-    double mg[R];
-    load_run<double, R>(a.m64, base, n, mg, 0.0);
-    const int eo = ABSORB ? a.eown[run] : 0;
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      if (base + j < n) {
-        const double pr = ldexp(double(own[j]) * double(y[j]), eo + eref);
-        s += fabs(pr - mg[j]);
-      }
+      const double pr = ldexp(double(own[j]) * double(y[j]), eo + eref);
+      s += fabs(pr - m64[j]);
     }
     const double tot = block_sum<kBlock / kWave>(s, red);
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
@@ -342,12 +522,6 @@ __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
   if constexpr (MODE == MODE_ERR) return;
 
   // update: out_j = marg_j / (K in)_j  (zero marginal -> zero scaling)
-  T mg[R];
-  if constexpr (sizeof(T) == 8) {
-    load_run<T, R>(reinterpret_cast<const T*>(a.m64), base, n, mg, T(0));
-  } else {
-    load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, n, mg, T(0));
-  }
   T q[R];
   bool bad = false;
 #pragma unroll
@@ -369,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_half(HalfArgs<T> a, ScanConsts k) {
     Eo = kq - eref;
     a.eout[run] = Eo;
   }
-  store_run<T, R>(a.vout, base, n, q);
+  solve_store<T, R>(a.vout, base, n, q);
   if (bad) {
     atomicOr(&a.ctrl->fail, 1);
     atomicMin(&a.ctrl->fail_iter, a.l);
@@ -604,9 +778,12 @@ static hipError_t kv_plain_t(const void* x, void* y, int64_t n, const ScanConsts
                              hipStream_t s) {
   const unsigned g = grid_of(kc.nchunks);
   k_agg<T, R, IN_PLAIN><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg);
-  k_carry<0><<<1, kCarryBlock, 0, s>>>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0);
+  {
+    const hipError_t e = launch_carry<0>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0, s);
+    if (e != hipSuccess) return e;
+  }
   k_kv_apply<T, R, false><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), static_cast<T*>(y), n,
-                                               k, carry);
+                                               k, carry, carry_fix_of(kc));
   return hipGetLastError();
 }
 
@@ -616,9 +793,12 @@ static hipError_t kv_log_t(const void* x, void* y, int64_t n, const ScanConsts& 
                            hipStream_t s) {
   const unsigned g = grid_of(kc.nchunks);
   k_agg<T, R, IN_LOG><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg);
-  k_carry<0><<<1, kCarryBlock, 0, s>>>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0);
+  {
+    const hipError_t e = launch_carry<0>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0, s);
+    if (e != hipSuccess) return e;
+  }
   k_kv_apply<T, R, true><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), static_cast<T*>(y), n,
-                                              k, carry);
+                                              k, carry, carry_fix_of(kc));
   return hipGetLastError();
 }
 
@@ -662,8 +842,10 @@ struct SolveOps {
         static_cast<const T*>(b.vF), b.eF, b.n, k, b.aggF);
     return hipGetLastError();
   }
-  static HalfArgs<T> args(const SolveBufs& b, int mode, int l, int check, int gbuf) {
+  static HalfArgs<T> args(const SolveBufs& b, const CarryConsts& kc, int mode, int l, int check,
+                          int gbuf) {
     HalfArgs<T> a{};
+    a.cfix = carry_fix_of(kc);
     a.n = b.n;
     a.l = l;
     a.check = check;
@@ -697,22 +879,28 @@ struct SolveOps {
   static hipError_t half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
                              int l, int check, double tol, hipStream_t s, hipEvent_t ev0,
                              hipEvent_t ev1) {
-    k_carry<1><<<1, kCarryBlock, 0, s>>>(b.aggF, b.carry, kc, b.ctrl, nullptr, nullptr, l, 0,
-                                         tol);
+    {
+      const hipError_t e =
+          launch_carry<1>(b.aggF, b.carry, kc, b.ctrl, nullptr, nullptr, l, 0, tol, s);
+      if (e != hipSuccess) return e;
+    }
     if (ev0) (void)hipEventRecord(ev0, s);
     k_half<T, R, AB, MODE_PSI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
-        args(b, MODE_PSI, l, check, 0), k);
+        args(b, kc, MODE_PSI, l, check, 0), k);
     if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
   }
   static hipError_t half_phi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
                              int l, int check, double tol, hipStream_t s, hipEvent_t ev0,
                              hipEvent_t ev1) {
-    k_carry<2><<<1, kCarryBlock, 0, s>>>(b.aggG, b.carry, kc, b.ctrl, b.part, b.err_hist, l,
-                                         check, tol);
+    {
+      const hipError_t e =
+          launch_carry<2>(b.aggG, b.carry, kc, b.ctrl, b.part, b.err_hist, l, check, tol, s);
+      if (e != hipSuccess) return e;
+    }
     if (ev0) (void)hipEventRecord(ev0, s);
     k_half<T, R, AB, MODE_PHI><<<grid_of(b.nchunks), kBlock, 0, s>>>(
-        args(b, MODE_PHI, l, check, 0), k);
+        args(b, kc, MODE_PHI, l, check, 0), k);
     if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
   }
@@ -725,9 +913,13 @@ struct SolveOps {
     const int* eG = b.eG[gbuf];
     // nu side: | psi (K^T phi) - nu |
     k_agg<T, R, AB ? IN_SCALED : IN_PLAIN><<<g, kBlock, 0, s>>>(vF, eF, b.n, k, b.aggF);
-    k_carry<0><<<1, kCarryBlock, 0, s>>>(b.aggF, b.carry, kc, nullptr, nullptr, nullptr, 0, 0,
-                                         0.0);
+    {
+      const hipError_t e =
+          launch_carry<0>(b.aggF, b.carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0, s);
+      if (e != hipSuccess) return e;
+    }
     HalfArgs<T> a{};
+    a.cfix = carry_fix_of(kc);
     a.n = b.n;
     a.ctrl = b.ctrl;
     a.carry = b.carry;
@@ -741,8 +933,11 @@ struct SolveOps {
     k_sum<<<1, 1024, 0, s>>>(b.part, b.nchunks, 1.0, &b.ctrl->err_final);
     // mu side: | phi (K psi) - mu |
     k_agg<T, R, AB ? IN_SCALED : IN_PLAIN><<<g, kBlock, 0, s>>>(vG, eG, b.n, k, b.aggG);
-    k_carry<0><<<1, kCarryBlock, 0, s>>>(b.aggG, b.carry, kc, nullptr, nullptr, nullptr, 0, 0,
-                                         0.0);
+    {
+      const hipError_t e =
+          launch_carry<0>(b.aggG, b.carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0, s);
+      if (e != hipSuccess) return e;
+    }
     a.vin = vG;
     a.ein = eG;
     a.vown = vF;

@@ -196,3 +196,39 @@ def test_kv_log_full_size_sampled(eps, dt):
     ref = oracle.kv_log_dense(lx, h, eps, rows=rows)
     tol = 64 * U64 * (1 + np.abs(ref)) if dt == "f64" else 4e-6 + 2 * U32 * np.abs(ref)
     assert np.all(np.abs(y[rows] - ref) <= tol)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_kv_two_level_carries(dt):
+    """More than 1024 chunks: carries go through groups of 1024 chunks and then
+    across the groups.  Rows are sampled around chunk and group boundaries."""
+    fs1 = _fs1()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    u = U64 if dt == "f64" else U32
+    clen = 2048 if dt == "f64" else 4096          # chunk length (256 threads x R)
+    rng = np.random.default_rng(99)
+    for n in (1024 * clen + 17, 3 * 1024 * clen - 5):
+        rows = np.unique(np.concatenate([
+            np.arange(0, 8), np.arange(n - 8, n),
+            *[np.arange(g * 1024 * clen - 4, g * 1024 * clen + 4) for g in (1, 2)],
+            *[np.arange(k * clen - 2, k * clen + 2) for k in (1, 511, 1023, 1025, 2047)],
+            rng.integers(0, n, size=16)]))
+        rows = rows[(rows >= 0) & (rows < n)]
+        for c in (1e-7, 3e-3):
+            _say(f"kv two-level dt={dt} n={n} c={c}")
+            h = 1.0 / n
+            eps = h / c
+            x = rng.random(n) + 0.1
+            if dt == "f32":
+                x = x.astype(np.float32).astype(np.float64)
+            y = fs1.fs1_kv_apply(dev(x, tdt), h, eps).double().cpu().numpy()
+            ref = oracle.kv_dense(x, h, eps, rows=rows)
+            err = np.max(np.abs(y[rows] - ref) / ref)
+            assert err <= (64 * u if dt == "f64" else 256 * u), (n, c, err)
+            lx = np.log(x) + 0.5 * c * np.arange(n) * (1 if c < 1e-3 else -1)
+            if dt == "f32":
+                lx = lx.astype(np.float32).astype(np.float64)
+            ly = fs1.fs1_kv_apply_log(dev(lx, tdt), h, eps).double().cpu().numpy()
+            lref = oracle.kv_log_dense(lx, h, eps, rows=rows)
+            tol = 64 * U64 * (1 + np.abs(lref)) if dt == "f64" else 4e-6 + 2 * U32 * np.abs(lref)
+            assert np.all(np.abs(ly[rows] - lref) <= tol), (n, c)

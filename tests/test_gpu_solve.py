@@ -251,3 +251,25 @@ def test_solve_full_size_f64_log(eps, path):
     r32 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
                         solver=path)
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_solve_two_level_carries_general_path(dtype):
+    """A grid of more than 1024 chunks on the general path (two-level carries)
+    against the sequential oracle at a fixed iteration count."""
+    fs1 = _fs1()
+    n = 2_500_003
+    mu, nu = inputs.mixture_pair(n, 4, 21)
+    eps = 1e-3
+    its = 12
+    _say(f"two-level solve {dtype} n={n}")
+    ref = oracle.fs1_log(mu, nu, 1.0 / n, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="log",
+                      solver="general")
+    assert r.status == 0 and r.iterations == its
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10 if dtype == "f64" else 1e-5)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6 if dtype == "f64" else 1e-3)
+    # and the same grid through the default solver selection
+    r2 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="log")
+    assert r2.w1 == pytest.approx(ref.w1, rel=1e-10 if dtype == "f64" else 1e-5)
+
