@@ -188,11 +188,12 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   std::sort(rs.begin(), rs.end(), [](int a, int b) { return a > b; });
   rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
   std::vector<BatchGroup> groups;
+  std::vector<std::vector<int>> members;  // instances of each group
   std::vector<InstInfo> info(B);
-  std::vector<int> chunk_inst;
   int64_t chunk = 0, elem = 0;
   for (int r : rs) {
-    BatchGroup g{r, int(chunk), 0, nullptr, 0};
+    BatchGroup g{r, nullptr, 0};
+    members.emplace_back();
     const int64_t C = int64_t(kBlock) * r;
     for (int32_t i = 0; i < B; ++i) {
       if (rlen[i] != r) continue;
@@ -202,22 +203,20 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
         return set_err(FS1_ERR_INVALID_ARG, "batch too large");
       info[i] = make_inst_info(mu + offsets[i], nu + offsets[i], elem, n, int(chunk), r,
                                1.0 / double(n), eps[i], tol[i], 0);
-      chunk_inst.insert(chunk_inst.end(), size_t(nch), int(i));
+      members.back().push_back(int(i));
       chunk += nch;
       elem += nch * C;
     }
-    g.nchunks = int(chunk - g.chunk0);
     groups.push_back(g);
   }
   const int ngroups = int(groups.size());
   const int64_t nchunks = chunk, nruns = chunk * kBlock, nelem = elem;
 
   BatchBufs z{};
-  int* clist = nullptr;  // device chunk lists of the groups (active instances only)
+  ChunkRef* clist = nullptr;  // device chunk lists of the groups (running instances only)
   auto layout = [&](Carve& w) {
     z.inst = static_cast<InstInfo*>(w.take(size_t(B) * sizeof(InstInfo)));
     z.st = static_cast<InstState*>(w.take(size_t(B) * sizeof(InstState)));
-    z.chunk_inst = static_cast<int*>(w.take(nchunks * sizeof(int)));
     z.iter_base = static_cast<int*>(w.take(2 * sizeof(int)));
     z.mu64 = static_cast<double*>(w.take(nelem * sizeof(double)));
     z.nu64 = static_cast<double*>(w.take(nelem * sizeof(double)));
@@ -235,7 +234,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     z.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     z.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     z.part3 = static_cast<double*>(w.take(nchunks * sizeof(double)));
-    clist = static_cast<int*>(w.take(nchunks * sizeof(int)));
+    clist = static_cast<ChunkRef*>(w.take(nchunks * sizeof(ChunkRef)));
   };
   {
     Carve probe(nullptr);
@@ -243,7 +242,8 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     int st = ensure_ws(ctx, probe.off);
     if (st) return st;
     // pinned staging: stop counters, the per-instance states, the chunk lists
-    st = ensure_hstage(ctx, 64 + size_t(B) * sizeof(InstState) + size_t(nchunks) * sizeof(int));
+    st = ensure_hstage(ctx,
+                       64 + size_t(B) * sizeof(InstState) + size_t(nchunks) * sizeof(ChunkRef));
     if (st) return st;
     Carve w(ctx->ws);
     layout(w);
@@ -267,11 +267,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(z.st, init.data(), size_t(B) * sizeof(InstState),
                          hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(z.chunk_inst, chunk_inst.data(), nchunks * sizeof(int),
-                         hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(z.iter_base, 0, 2 * sizeof(int), s));
-  HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, nullptr, B, s));
-
   // `count` iterations per replay; every instance stops by iteration itr_max
   const int count = std::max(1, std::min(o.sync_every, o.itr_max + 1));
   const int64_t max_rounds = (int64_t(o.itr_max) + count) / count + 1;
@@ -296,31 +292,37 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   char* hb = static_cast<char*>(ctx->hstage);
   int* hdone = reinterpret_cast<int*>(hb);
   InstState* hst = reinterpret_cast<InstState*>(hb + 64);
-  int* hlist = reinterpret_cast<int*>(hb + 64 + size_t(B) * sizeof(InstState));
-  // Launch over the chunks of the instances still running.  The lists are
-  // rebuilt (and the graph recaptured) whenever an eighth of the instances
-  // that were running at the last rebuild have stopped, so launches late in
-  // the batch do not dispatch the chunks of finished instances.
-  auto rebuild_lists = [&](bool all) -> int {
+  ChunkRef* hlist = reinterpret_cast<ChunkRef*>(hb + 64 + size_t(B) * sizeof(InstState));
+  // Launches run over the chunk records of the instances still running.  The
+  // lists are rebuilt (and the graph recaptured) whenever an eighth of the
+  // instances that were running at the last rebuild have stopped, so late
+  // launches do not carry the chunks of finished instances.
+  auto build_lists = [&](bool all) -> int {
     if (!all) {
       HIP_TRY(hipMemcpyAsync(hst, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
     }
     int64_t at = 0;
-    for (BatchGroup& g : groups) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
       const int64_t start = at;
-      for (int c = g.chunk0; c < g.chunk0 + g.nchunks; ++c)
-        if (all || !hst[chunk_inst[c]].done) hlist[at++] = c;
-      g.list = clist + start;
-      g.nlist = int(at - start);
+      for (int b : members[gi]) {
+        if (!all && hst[b].done) continue;
+        for (int j = 0; j < info[b].nch; ++j) hlist[at++] = chunk_ref(info[b], b, j);
+      }
+      groups[gi].list = clist + start;
+      groups[gi].nlist = int(at - start);
     }
     if (at > 0)
-      HIP_TRY(hipMemcpyAsync(clist, hlist, size_t(at) * sizeof(int), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(clist, hlist, size_t(at) * sizeof(ChunkRef), hipMemcpyHostToDevice,
+                             s));
     // the pinned list is read by that copy: finish it before the host writes again
     HIP_TRY(hipStreamSynchronize(s));
-    return capture();
+    return FS1_OK;
   };
-  int st = rebuild_lists(true);
+  int st = build_lists(true);
+  if (st) return st;
+  HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, nullptr, B, s));
+  st = capture();
   if (st) return st;
 
   hdone[0] = hdone[1] = 0;
@@ -339,7 +341,9 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
       stopped = hdone[(r - 1) & 1];
       if (stopped >= B) break;
       if (stopped - stopped_at_rebuild >= std::max(1, running_at_rebuild / 8)) {
-        st = rebuild_lists(false);
+        st = build_lists(false);
+        if (st) return st;
+        st = capture();
         if (st) return st;
         stopped = hdone[r & 1];  // the queued replay has completed
         if (stopped >= B) break;
@@ -352,10 +356,8 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   stopped = std::max(stopped, std::max(hdone[0], hdone[1]));
   if (stopped != B)
     return set_err(FS1_ERR_INTERNAL, "batched solve: %d of %d instances stopped", stopped, B);
-  for (BatchGroup& g : groups) {
-    g.list = nullptr;
-    g.nlist = 0;
-  }
+  st = build_lists(true);
+  if (st) return st;
 
   HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, nullptr, B, nullptr, s));
   InstState* hs = hst;

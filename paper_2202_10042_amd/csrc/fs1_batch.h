@@ -3,9 +3,10 @@
 //
 // Instances are stored chunk-aligned in padded work arrays: instance b owns
 // the global chunks [chunk0, chunk0 + nch) and the elements
-// [base, base + nch * 256 * R) (its run length R decides the chunk length).
-// Instances with the same R form a group whose chunks are contiguous, and one
-// launch per group covers them.
+// [base, base + nch * 256 * R) (its run length R decides the chunk length);
+// entries past its n hold zeros.  Instances with the same R form a group, and
+// one launch per group covers a list of chunk records (ChunkRef), one
+// workgroup per record.
 #pragma once
 
 #include "fs1_internal.h"
@@ -47,12 +48,25 @@ struct InstState {
   double w1;          // final transport cost
 };
 
+// One chunk of one instance, as a workgroup of a batched launch sees it: all
+// it needs to issue its loads at once.
+struct ChunkRef {
+  int64_t base;       // element of the chunk's first entry
+  int64_t lim;        // first element past the instance's n entries
+  int32_t c;          // global chunk (aggregates, shares, run exponents)
+  int32_t b;          // instance
+  int32_t j;          // chunk within the instance
+  int32_t nch;        // chunks of the instance
+  int32_t chunk0;     // the instance's first global chunk
+  int32_t l0;         // the instance's admission iteration
+};
+
+ChunkRef chunk_ref(const InstInfo& in, int b, int j);
+
 struct BatchGroup {
   int R;
-  int chunk0;         // first global chunk of the group
-  int nchunks;
-  const int* list;    // device list of the group's chunks to run, or null: all of them
-  int nlist;          // entries of `list`
+  const ChunkRef* list;  // device list of the chunks to run
+  int nlist;             // entries of `list`
 };
 
 struct BatchBufs {
@@ -63,7 +77,6 @@ struct BatchBufs {
   int64_t nelem;      // padded elements
   InstInfo* inst;
   InstState* st;
-  int* chunk_inst;    // global chunk -> instance
   int* iter_base;     // batch iteration counter (advanced on the device)
   int* ndone;         // instances stopped so far
   int* ring;          // optional: instance index of the k-th stop at ring[k % ring_cap]
@@ -88,15 +101,14 @@ InstInfo make_inst_info(const double* mu, const double* nu, int64_t base, int64_
                         int R, double h, double eps, double tol, int l0);
 
 // Instances ilist[0..count) (or 0..count-1 when ilist is null) and the chunks
-// of the groups (their lists, or all their chunks): pack the marginals, set
-// phi = psi = 1/n, validate each instance and publish the chunk aggregates of
-// phi.  `inst` / `st` must already hold the instances' descriptions and
-// initial states.
+// the groups list: pack the marginals, set phi = psi = 1/n, validate each
+// instance and publish the chunk aggregates of phi.  `inst` / `st` must
+// already hold the instances' descriptions and initial states.
 hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                               const int* ilist, int count, hipStream_t s);
-// `count` iterations (psi-half, phi-half) of every group (over its chunk list
-// when it has one), then advance the iteration counter by `count`.  Safe to
-// capture in a graph.
+// `count` iterations (psi-half, phi-half) of every group over its chunk
+// list, then advance the iteration counter by `count`.  Safe to capture in a
+// graph.
 hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                                    int count, hipStream_t s);
 // Final marginal errors and transport costs of the instances ilist[0..count)
@@ -105,7 +117,7 @@ hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups,
 hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                                  const int* ilist, int count, InstState* out, hipStream_t s);
 // Admission: copy count staged descriptions and states into the instance
-// slots idx[0..count) and map their chunks to them.
+// slots idx[0..count).
 hipError_t launch_batch_admit(const BatchBufs& z, const InstInfo* sinfo, const InstState* sstate,
                               const int* idx, int count, hipStream_t s);
 

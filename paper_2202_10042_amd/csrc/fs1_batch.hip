@@ -3,40 +3,34 @@
 //
 // Layout (fs1_batch.h): instance b owns chunks [chunk0_b, chunk0_b + nch_b) of
 // the padded work arrays; entries past n_b are zero and stay zero (a zero
-// marginal gives a zero scaling).  One launch per half-iteration and run-length
-// group covers every chunk of the group.  A workgroup looks up its instance,
-// takes that instance's stop decision (all workgroups of an instance sum the
-// same error shares in the same order, so they decide alike), computes its
-// chunk carries from that instance's chunk aggregates, and runs the
-// extended-range scans of eq. (recursion) with the instance's own lambda.  An
-// instance thus executes the same arithmetic whatever else is in the batch and
-// wherever it sits.  Iterations are counted on the device (iter_base), so a
-// fixed number of iterations can be captured in a HIP graph and replayed until
-// every instance has stopped.
+// marginal gives a zero scaling, and every store writes whole runs).  A
+// launch runs one workgroup per chunk record of its list.  A workgroup issues
+// all its loads at once (its record tells it where everything is), computes
+// its chunk carries from its instance's chunk aggregates, runs the
+// extended-range scans of eq. (recursion) with its instance's lambda, and
+// takes its instance's stop decision last, before storing anything (all
+// workgroups of an instance sum the same error shares with the same tree, so
+// they decide alike).  An instance thus executes the same arithmetic whatever
+// else is in the batch and wherever it sits.  Iterations are counted on the
+// device (iter_base), so a fixed number of iterations can be captured in a
+// HIP graph and replayed until every instance has stopped.
 #include <climits>
 
 #include "fs1_batch.h"
 #include "fs1_device.h"
+#include "fs1_frame.h"
 #include "fs1_internal.h"
 
 namespace fs1 {
 
 namespace {
 
-constexpr int kNW = kBlock / kWave;
+constexpr int kCarryItems = 8;                             // chunks per carry thread
+constexpr int kPrefetchChunks = kCarryItems * kBlock / 2;  // 1024
 
 enum BMode { B_PSI = 0, B_PHI = 1, B_ERR = 2 };
 // which of two buffers a kernel reads
 enum BSel { SEL_0 = 0, SEL_FINAL = 1, SEL_NEXT = 2, SEL_CUR = 3 };
-
-__device__ __forceinline__ XF<double> wave_xsum64(XF<double> v) {
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) {
-    const XF<double> o = {__shfl_xor(v.m, d), __shfl_xor(v.e, d)};
-    v = xadd(v, o);
-  }
-  return xnorm(v);
-}
 
 __device__ __forceinline__ S2<double> s2_wave_sum(S2<double> v) {
 #pragma unroll
@@ -44,43 +38,37 @@ __device__ __forceinline__ S2<double> s2_wave_sum(S2<double> v) {
   return v.norm();
 }
 
-// lambda^(chunk length * d) from the binary expansion of d
-__device__ __forceinline__ XF<double> pow_chunks(int64_t d, const Decay* p) {
-  XF<double> r = {1.0, 0};
-  for (int s = 0; d != 0 && s < kInstPow; ++s, d >>= 1)
-    if (d & 1) r = {r.m * p[s].m, r.e + p[s].e};
-  return r;
-}
-
-// Carries of local chunk j from the instance's chunk aggregates (extended
-// range): wave 0 the forward carry, wave 1 the backward one.
-__device__ __forceinline__ void inst_carries(const ChunkAgg* A, const InstInfo& in, int j,
+// Carries of chunk j of an instance from its chunk aggregates A[0..nch), for
+// instances of more than kPrefetchChunks chunks: wave 0 the forward carry,
+// wave 1 the backward one.
+__device__ __forceinline__ void inst_carries(const ChunkAgg* A, int j, int nch, const Decay* cpow,
                                              XF64* scar) {
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (w == 0) {
     XF<double> acc = xzero<double>();
     for (int i = lane; i < j; i += kWave) {
-      const XF64 v = A[in.chunk0 + i].f;
-      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_chunks(j - 1 - i, in.cpow)));
+      const XF64 v = A[i].f;
+      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_bits(j - 1 - i, cpow)));
     }
-    acc = wave_xsum64(acc);
+    acc = wave_xsum(acc);
     if (lane == 0) scar[0] = to64(acc);
   } else if (w == 1) {
     XF<double> acc = xzero<double>();
-    for (int i = j + 1 + lane; i < in.nch; i += kWave) {
-      const XF64 v = A[in.chunk0 + i].b;
-      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_chunks(i - j - 1, in.cpow)));
+    for (int i = j + 1 + lane; i < nch; i += kWave) {
+      const XF64 v = A[i].b;
+      acc = xadd(acc, xmul(XF<double>{v.m, v.e}, pow_bits(i - j - 1, cpow)));
     }
-    acc = wave_xsum64(acc);
+    acc = wave_xsum(acc);
     if (lane == 0) scar[1] = to64(acc);
   }
+  __syncthreads();
 }
 
 struct BArgs {
   const InstInfo* inst;
   InstState* st;
-  const int* chunk_inst;
+  const ChunkRef* list;
   const int* iter_base;
   int* ndone;
   int* ring;
@@ -96,8 +84,6 @@ struct BArgs {
   const ChunkAgg* A_in;   // chunk aggregates of vin
   ChunkAgg* A_out;        // chunk aggregates of vout (or of vin for k_bpublish)
   double* part;
-  const int* clist;       // global chunk of each workgroup, or null: chunk_off + blockIdx.x
-  int chunk_off;          // first global chunk of the launch's group
   int l_local;            // iteration = *iter_base + l_local - l0
   int itr_max;
   int check_every;
@@ -110,10 +96,6 @@ __device__ __forceinline__ int final_buf(const InstState& s, int itr_max) {
   return (s.stop_iter >= 0) ? (s.stop_iter & 1) : (itr_max & 1);
 }
 
-__device__ __forceinline__ int chunk_of(const BArgs& a) {
-  return a.clist ? a.clist[blockIdx.x] : a.chunk_off + int(blockIdx.x);
-}
-
 __device__ __forceinline__ int pick(int sel, int l, const InstState& s, int itr_max) {
   switch (sel) {
     case SEL_FINAL: return final_buf(s, itr_max);
@@ -123,99 +105,100 @@ __device__ __forceinline__ int pick(int sel, int l, const InstState& s, int itr_
   }
 }
 
-// One half of the Sinkhorn update (Sec. 2) for every chunk of a group:
+// Runs of the padded arrays: whole 16-byte vectors where the run length
+// allows (entries past n are zero), element by element otherwise.
+template <typename T, int R>
+__device__ __forceinline__ void bload(const T* p, int64_t base, int64_t lim, T (&x)[R]) {
+  if constexpr (R % Vec16<T>::n == 0) {
+    load_run_z<T, R>(p, base, x);
+  } else {
+    load_run<T, R>(p, base, lim, x, T(0));
+  }
+}
+template <typename T, int R>
+__device__ __forceinline__ void bstore(T* p, int64_t base, const T (&x)[R]) {
+  if constexpr (R % Vec16<T>::n == 0) {
+    store_run_z<T, R>(p, base, x);
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) p[base + j] = x[j];
+  }
+}
+
+// One half of the Sinkhorn update (Sec. 2) for the chunks of a list:
 //   B_PSI: psi^{l+1} = nu / K^T phi^l, error share of (phi^l, psi^l) when checked;
-//   B_PHI: phi^{l+1} = mu / K psi^{l+1}, after the stopping test of iteration l;
+//   B_PHI: stopping test of iteration l, then phi^{l+1} = mu / K psi^{l+1};
 //   B_ERR: error share only (finalisation).
 template <typename T, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   __shared__ ScanLds<S1<T>, kNW> sh;
   __shared__ double red[kNW];
   __shared__ XF64 scar[2];
+  __shared__ XF64 red4[kNW];
   __shared__ int sdec;
-  const int c = chunk_of(a);
-  const int b = a.chunk_inst[c];
-  const InstInfo& in = a.inst[b];
-  InstState& st = a.st[b];
-  const int j = c - in.chunk0;
+  const ChunkRef r = a.list[blockIdx.x];
+  const InstInfo& in = a.inst[r.b];
+  InstState& st = a.st[r.b];
   const int lane = threadIdx.x & (kWave - 1);
-  const int l = (MODE == B_ERR) ? 0 : *a.iter_base + a.l_local - in.l0;
+  const int l = (MODE == B_ERR) ? 0 : *a.iter_base + a.l_local - r.l0;
+  const bool checked = (l % a.check_every) == 0;
+  const bool want_err = (MODE == B_ERR) || (MODE == B_PSI && checked);
 
+  // Every global load is issued here, before any is waited for: the stop
+  // flags and error shares (needed last), the instance's chunk aggregates
+  // (needed first, for the carries), the chunk's own data.
+  int done = 0, fail = 0;
+  double shv = 0.0;  // this thread's part of the instance's error (phi-half)
   if constexpr (MODE != B_ERR) {
-    // 3: already stopped; 4: l reached itr_max; 2: a scaling became
-    // non-finite; 1: err(l) <= tol
-    if (threadIdx.x < kWave) {
-      int dec = 0;
-      if (st.done) {
-        dec = 3;
-      } else if (l >= a.itr_max) {
-        dec = 4;
-      } else if (st.fail) {
-        dec = 2;
-      } else if (MODE == B_PHI && (l % a.check_every) == 0) {
-        double e = 0.0;
-        for (int i = lane; i < in.nch; i += kWave) e += a.part[in.chunk0 + i];
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
-        if (j == 0 && lane == 0) {
-          st.last_err = e;
-          st.last_check = l;
-        }
-        if (!(e > in.tol)) dec = 1;
-      }
-      if (lane == 0) sdec = dec;
+    if (threadIdx.x == 0) {
+      done = st.done;
+      fail = st.fail;
     }
-    __syncthreads();
-    if (sdec) {
-      if (j == 0 && threadIdx.x == 0 && sdec != 3) {
-        if (sdec == 1) st.stop_iter = l;
-        if (sdec == 4) st.capped = 1;
-        st.done = 1;
-        const int pos = atomicAdd(a.ndone, 1);
-        if (a.ring) a.ring[pos % a.ring_cap] = b;
-      }
-      return;
-    }
+    if (MODE == B_PHI && checked)
+      for (int i = threadIdx.x; i < r.nch; i += kBlock) shv += a.part[r.chunk0 + i];
   }
-
-  // every global load of the workgroup is issued before the scans, so the
-  // launch pays one memory round trip rather than one per phase
-  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
-  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
-  const int64_t lim = in.base + in.n;  // entries past the instance are padding
-  const bool want_err = (MODE == B_ERR) || (MODE == B_PSI && (l % a.check_every) == 0);
+  const bool pre = r.nch <= kPrefetchChunks;
+  CarryItems<kCarryItems> items;
+  if (pre) carry_prefetch<kCarryItems>(a.A_in + r.chunk0, r.j, r.nch, items);
+  const int64_t base = r.base + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(r.c) * kBlock + threadIdx.x;
   const int si = pick(a.sel_in, l, st, a.itr_max);
   T x[R];
-  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, lim, x, T(0));
+  bload<T, R>(static_cast<const T*>(a.vin[si]), base, r.lim, x);
   const int E = a.ein[si][run];
   T own[R];
   int eo = 0;
   if (want_err) {
     const int so = pick(a.sel_own, l, st, a.itr_max);
-    load_run<T, R>(static_cast<const T*>(a.vown[so]), base, lim, own, T(0));
+    bload<T, R>(static_cast<const T*>(a.vown[so]), base, r.lim, own);
     eo = a.eown[so][run];
   }
   // binary64 marginal: the error term, and the update when T = double; the
-  // binary32 copy is the rounding of it, loaded only when the error is not due
+  // binary32 copy is its rounding, loaded only when the error is not due
   double m64[R];
   T mg[R];
-  if (want_err || sizeof(T) == 8) load_run<double, R>(a.m64, base, lim, m64, 0.0);
+  if (want_err || sizeof(T) == 8) bload<double, R>(a.m64, base, r.lim, m64);
   if constexpr (MODE != B_ERR) {
     if (sizeof(T) == 8 || want_err) {
 #pragma unroll
       for (int i = 0; i < R; ++i) mg[i] = T(m64[i]);
     } else {
-      load_run<T, R>(reinterpret_cast<const T*>(a.m32), base, lim, mg, T(0));
+      bload<T, R>(reinterpret_cast<const T*>(a.m32), base, r.lim, mg);
     }
   }
-  inst_carries(a.A_in, in, j, scar);
+
+  // chunk carries first: they need only the aggregates
+  if (pre) {
+    carry_finish<kCarryItems>(items, r.j, in.cpow, red4, scar);
+  } else {
+    inst_carries(a.A_in + r.chunk0, r.j, r.nch, in.cpow, scar);
+  }
   const ScanConsts& k = in.k;
   const Lam<T> L = lam_of<T>(k);
   T af, ab;
   run_aggs<T, R>(x, L, af, ab);
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
-  __syncthreads();
   const XF64 cf64 = scar[0], cb64 = scar[1];
   S1<T> cf, cb;
   block_scan<S1<T>, kNW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>{from64<T>(cf64)},
@@ -231,15 +214,57 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
 
   if (want_err) {
-    // padding loads as zero and adds nothing
+    // padding is zero and adds nothing
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      s += fabs(ldexp(double(own[i]) * double(y[i]), eo + eref) - m64[i]);
+    for (int i = 0; i < R; ++i) s += fabs(ldexp(double(own[i]) * double(y[i]), eo + eref) - m64[i]);
     const double tot = block_sum<kNW>(s, red);
-    if (threadIdx.x == 0) a.part[c] = tot;
+    if (threadIdx.x == 0) a.part[r.c] = tot;
   }
   if constexpr (MODE == B_ERR) return;
+
+  // Stop decision of Algorithm 1, taken before anything is stored.
+  // 3: already stopped; 4: l reached itr_max; 2: a scaling became
+  // non-finite; 1: err(l) <= tol.
+  const bool test = MODE == B_PHI && checked;
+  if (test) {
+    double e = shv;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
+    if (lane == 0) red[threadIdx.x / kWave] = e;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int dec = 0;
+    if (done) {
+      dec = 3;
+    } else if (l >= a.itr_max) {
+      dec = 4;
+    } else if (fail) {
+      dec = 2;
+    } else if (test) {
+      double e = 0.0;
+#pragma unroll
+      for (int v = 0; v < kNW; ++v) e += red[v];
+      if (r.j == 0) {
+        st.last_err = e;
+        st.last_check = l;
+      }
+      if (!(e > in.tol)) dec = 1;
+    }
+    sdec = dec;
+  }
+  __syncthreads();
+  if (sdec) {
+    if (r.j == 0 && threadIdx.x == 0 && sdec != 3) {
+      if (sdec == 1) st.stop_iter = l;
+      if (sdec == 4) st.capped = 1;
+      st.done = 1;
+      const int pos = atomicAdd(a.ndone, 1);
+      if (a.ring) a.ring[pos % a.ring_cap] = r.b;
+    }
+    return;
+  }
 
   // update: out = marg / (K vin)  (zero marginal -> zero scaling), with the
   // power-of-two part of the run absorbed into its exponent
@@ -258,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   for (int i = 0; i < R; ++i) q[i] = ldx(q[i], -kq);
   const int Eo = kq - eref;
   const int sw = pick(a.sel_out, l, st, a.itr_max);
-  store_run<T, R>(static_cast<T*>(a.vout[sw]), base, lim, q);
+  bstore<T, R>(static_cast<T*>(a.vout[sw]), base, q);
   a.eout[sw][run] = Eo;
   if (bad) {
     atomicOr(&st.fail, 1);
@@ -270,8 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   block_scan<S1<T>, kNW, T>(S1<T>{{nf, Eo}}, S1<T>{{nb, Eo}}, dec, S1<T>::zero(), S1<T>::zero(),
                             nullptr, nullptr, &gf, &gb, sh);
   if (threadIdx.x == 0) {
-    a.A_out[c].f = to64(gf.v);
-    a.A_out[c].b = to64(gb.v);
+    a.A_out[r.c].f = to64(gf.v);
+    a.A_out[r.c].b = to64(gb.v);
   }
 }
 
@@ -279,15 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
   __shared__ ScanLds<S1<T>, kNW> sh;
-  const int c = chunk_of(a);
-  const int b = a.chunk_inst[c];
-  const InstInfo& in = a.inst[b];
-  const int j = c - in.chunk0;
-  const int si = pick(a.sel_in, 0, a.st[b], a.itr_max);
-  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
-  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  const ChunkRef r = a.list[blockIdx.x];
+  const InstInfo& in = a.inst[r.b];
+  const int si = pick(a.sel_in, 0, a.st[r.b], a.itr_max);
+  const int64_t base = r.base + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(r.c) * kBlock + threadIdx.x;
   T x[R];
-  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, in.base + in.n, x, T(0));
+  bload<T, R>(static_cast<const T*>(a.vin[si]), base, r.lim, x);
   const int E = a.ein[si][run];
   const Lam<T> L = lam_of<T>(in.k);
   T af, ab;
@@ -298,8 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
   block_scan<S1<T>, kNW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(), S1<T>::zero(),
                             nullptr, nullptr, &gf, &gb, sh);
   if (threadIdx.x == 0) {
-    a.A_out[c].f = to64(gf.v);
-    a.A_out[c].b = to64(gb.v);
+    a.A_out[r.c].f = to64(gf.v);
+    a.A_out[r.c].b = to64(gb.v);
   }
 }
 
@@ -310,15 +333,13 @@ __global__ __launch_bounds__(kBlock) void k_bpublish(BArgs a) {
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bcost_agg(BArgs a, ChunkAgg2* agg2) {
   __shared__ ScanLds<S2<T>, kNW> sh;
-  const int c = chunk_of(a);
-  const int b = a.chunk_inst[c];
-  const InstInfo& in = a.inst[b];
-  const int j = c - in.chunk0;
-  const int si = final_buf(a.st[b], a.itr_max);
-  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
-  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  const ChunkRef r = a.list[blockIdx.x];
+  const InstInfo& in = a.inst[r.b];
+  const int si = final_buf(a.st[r.b], a.itr_max);
+  const int64_t base = r.base + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(r.c) * kBlock + threadIdx.x;
   T x[R];
-  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, in.base + in.n, x, T(0));
+  bload<T, R>(static_cast<const T*>(a.vin[si]), base, r.lim, x);
   const int E = a.ein[si][run];
   const Lam<T> L = lam_of<T>(in.k);
   T fp, fd, bp, bd;
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_bcost_agg(BArgs a, ChunkAgg2* agg2) 
     ChunkAgg2 o;
     s2_put_fwd(o, gf);
     s2_put_bwd(o, gb);
-    agg2[c] = o;
+    agg2[r.c] = o;
   }
 }
 
@@ -341,42 +362,36 @@ __global__ __launch_bounds__(kBlock) void k_bcost_apply(BArgs a, const ChunkAgg2
   __shared__ ScanLds<S2<T>, kNW> sh;
   __shared__ double red[kNW];
   __shared__ S2<double> scar[2];
-  const int c = chunk_of(a);
-  const int b = a.chunk_inst[c];
-  const InstInfo& in = a.inst[b];
-  const int j = c - in.chunk0;
+  const ChunkRef r = a.list[blockIdx.x];
+  const InstInfo& in = a.inst[r.b];
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int si = final_buf(a.st[b], a.itr_max);
-  const int64_t base = in.base + int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
-  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
-  const int64_t lim = in.base + in.n;
+  const int si = final_buf(a.st[r.b], a.itr_max);
+  const int64_t base = r.base + int64_t(threadIdx.x) * R;
+  const int64_t run = int64_t(r.c) * kBlock + threadIdx.x;
   // chunk carries of the two-state recursion: a state moved by D elements
   // with zero input is (p, d) -> lambda^D (p, d + D p)
   const double C = double(kBlock) * R;
+  const ChunkAgg2* A2 = agg2 + r.chunk0;
   if (w == 0) {
     S2<double> acc = S2<double>::zero();
-    for (int i = lane; i < j; i += kWave) {
-      const ChunkAgg2 v = agg2[in.chunk0 + i];
-      const XF<double> p = pow_chunks(j - 1 - i, in.cpow);
-      acc = acc.add(
-          s2_fwd<double>(v).shift(Dec<double>{p.m, p.e, C * double(j - 1 - i)}));
+    for (int i = lane; i < r.j; i += kWave) {
+      const XF<double> p = pow_bits(r.j - 1 - i, in.cpow);
+      acc = acc.add(s2_fwd<double>(A2[i]).shift(Dec<double>{p.m, p.e, C * double(r.j - 1 - i)}));
     }
     acc = s2_wave_sum(acc);
     if (lane == 0) scar[0] = acc;
   } else if (w == 1) {
     S2<double> acc = S2<double>::zero();
-    for (int i = j + 1 + lane; i < in.nch; i += kWave) {
-      const ChunkAgg2 v = agg2[in.chunk0 + i];
-      const XF<double> p = pow_chunks(i - j - 1, in.cpow);
-      acc = acc.add(
-          s2_bwd<double>(v).shift(Dec<double>{p.m, p.e, C * double(i - j - 1)}));
+    for (int i = r.j + 1 + lane; i < r.nch; i += kWave) {
+      const XF<double> p = pow_bits(i - r.j - 1, in.cpow);
+      acc = acc.add(s2_bwd<double>(A2[i]).shift(Dec<double>{p.m, p.e, C * double(i - r.j - 1)}));
     }
     acc = s2_wave_sum(acc);
     if (lane == 0) scar[1] = acc;
   }
   T x[R];
-  load_run<T, R>(static_cast<const T*>(a.vin[si]), base, lim, x, T(0));
+  bload<T, R>(static_cast<const T*>(a.vin[si]), base, r.lim, x);
   const int E = a.ein[si][run];
   const Lam<T> L = lam_of<T>(in.k);
   T fp, fd, bp, bd;
@@ -397,31 +412,30 @@ __global__ __launch_bounds__(kBlock) void k_bcost_apply(BArgs a, const ChunkAgg2
   run_cost<T, R>(xf, ldx(lcf.p.m, lcf.p.e - eref), ldx(lcf.d.m, lcf.d.e - eref),
                  ldx(lcb.p.m, lcb.p.e - eref), ldx(lcb.d.m, lcb.d.e - eref), L, wv);
   T ph[R];
-  load_run<T, R>(static_cast<const T*>(a.vown[0]), base, lim, ph, T(0));
+  bload<T, R>(static_cast<const T*>(a.vown[0]), base, r.lim, ph);
   const int ep = a.eown[0][run];
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < R; ++i) s += ldexp(double(ph[i]) * double(wv[i]), ep + eref);
   const double tot = block_sum<kNW>(s, red);
-  if (threadIdx.x == 0) a.part[c] = tot;
+  if (threadIdx.x == 0) a.part[r.c] = tot;
 }
 
 // ---------------------------------------------------------------------------
 // Set-up and finalisation
 // ---------------------------------------------------------------------------
 // Pack the caller's marginals chunk-aligned (binary64, plus binary32 copies),
-// set phi = psi = 1/n with exponent 0, and write per-chunk masses.
+// set phi = psi = 1/n with exponent 0 and zeros past n, and write per-chunk
+// masses.
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, double* mu64, double* nu64, float* mu32,
                                                    float* nu32, T* vF, T* vG0, int* eF,
                                                    int* eG0, double* pmu, double* pnu) {
   __shared__ double red[kNW];
-  const int c = chunk_of(a);
-  const int b = a.chunk_inst[c];
-  const InstInfo& in = a.inst[b];
-  const int j = c - in.chunk0;
-  const int64_t local0 = int64_t(j) * kBlock * R + int64_t(threadIdx.x) * R;
-  const int64_t base = in.base + local0;
+  const ChunkRef r = a.list[blockIdx.x];
+  const InstInfo& in = a.inst[r.b];
+  const int64_t local0 = int64_t(r.j) * kBlock * R + int64_t(threadIdx.x) * R;
+  const int64_t base = r.base + int64_t(threadIdx.x) * R;
   const T init = T(1.0 / double(in.n));
   double sm = 0.0, sn = 0.0;
   int bad = 0;
@@ -445,15 +459,15 @@ __global__ __launch_bounds__(kBlock) void k_bsetup(BArgs a, double* mu64, double
     sm += u;
     sn += v;
   }
-  const int64_t run = int64_t(c) * kBlock + threadIdx.x;
+  const int64_t run = int64_t(r.c) * kBlock + threadIdx.x;
   eF[run] = 0;
   eG0[run] = 0;
   const double tm = block_sum<kNW>(sm, red);
   const double tn = block_sum<kNW>(sn, red);
-  if (bad) atomicOr(&a.st[b].bad_input, 1);
+  if (bad) atomicOr(&a.st[r.b].bad_input, 1);
   if (threadIdx.x == 0) {
-    pmu[c] = tm;
-    pnu[c] = tn;
+    pmu[r.c] = tm;
+    pnu[r.c] = tn;
   }
 }
 
@@ -508,18 +522,14 @@ __global__ void k_bfinal(const InstInfo* inst, InstState* st, const double* perr
   if (out) out[t] = st[b];
 }
 
-// Admission: one workgroup per new instance copies its staged description and
-// state into its slot and maps its chunks to it.
+// Admission: one thread per new instance copies its staged description and
+// state into its slot.
 __global__ void k_badmit(const InstInfo* sinfo, const InstState* sstate, const int* idx,
-                         InstInfo* inst, InstState* st, int* chunk_inst) {
-  const int t = blockIdx.x;
-  const int b = idx[t];
-  if (threadIdx.x == 0) {
-    inst[b] = sinfo[t];
-    st[b] = sstate[t];
-  }
-  const InstInfo& in = sinfo[t];
-  for (int i = threadIdx.x; i < in.nch; i += blockDim.x) chunk_inst[in.chunk0 + i] = b;
+                         int count, InstInfo* inst, InstState* st) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  inst[idx[t]] = sinfo[t];
+  st[idx[t]] = sstate[t];
 }
 
 template <typename T, int R>
@@ -528,18 +538,16 @@ struct BatchOps {
     BArgs a{};
     a.inst = z.inst;
     a.st = z.st;
-    a.chunk_inst = z.chunk_inst;
+    a.list = g.list;
     a.iter_base = z.iter_base;
     a.ndone = z.ndone;
     a.ring = z.ring;
     a.ring_cap = z.ring_cap;
     a.itr_max = z.itr_max;
     a.check_every = z.check_every;
-    a.chunk_off = g.chunk0;
-    a.clist = g.list;
     return a;
   }
-  static unsigned grid(const BatchGroup& g) { return unsigned(g.list ? g.nlist : g.nchunks); }
+  static unsigned grid(const BatchGroup& g) { return unsigned(g.nlist); }
   static void set_phi_in(BArgs& a, const BatchBufs& z) {
     a.vin[0] = a.vin[1] = z.vF;
     a.ein[0] = a.ein[1] = z.eF;
@@ -602,7 +610,7 @@ struct BatchOps {
     return hipGetLastError();
   }
   static hipError_t finalize(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
-    const unsigned grid = BatchOps::grid(g);
+    const unsigned gr = grid(g);
     // nu side: | psi (K^T phi) - nu |; the aggregates of the final phi are in aggF
     BArgs a = base(z, g);
     set_phi_in(a, z);
@@ -614,12 +622,12 @@ struct BatchOps {
     a.m64 = z.nu64;
     a.A_in = z.aggF;
     a.part = z.part;
-    k_bhalf<T, R, B_ERR><<<grid, kBlock, 0, s>>>(a);
+    k_bhalf<T, R, B_ERR><<<gr, kBlock, 0, s>>>(a);
     // aggregates of the final psi, then mu side: | phi (K psi) - mu |
     BArgs p = base(z, g);
     set_psi_in(p, z, SEL_FINAL);
     p.A_out = z.aggG;
-    k_bpublish<T, R><<<grid, kBlock, 0, s>>>(p);
+    k_bpublish<T, R><<<gr, kBlock, 0, s>>>(p);
     BArgs m = base(z, g);
     set_psi_in(m, z, SEL_FINAL);
     m.vown[0] = m.vown[1] = z.vF;
@@ -627,15 +635,15 @@ struct BatchOps {
     m.m64 = z.mu64;
     m.A_in = z.aggG;
     m.part = z.part2;
-    k_bhalf<T, R, B_ERR><<<grid, kBlock, 0, s>>>(m);
+    k_bhalf<T, R, B_ERR><<<gr, kBlock, 0, s>>>(m);
     // transport cost
     BArgs w = base(z, g);
     set_psi_in(w, z, SEL_FINAL);
     w.vown[0] = w.vown[1] = z.vF;
     w.eown[0] = w.eown[1] = z.eF;
     w.part = z.part3;
-    k_bcost_agg<T, R><<<grid, kBlock, 0, s>>>(w, static_cast<ChunkAgg2*>(z.agg2));
-    k_bcost_apply<T, R><<<grid, kBlock, 0, s>>>(w, static_cast<const ChunkAgg2*>(z.agg2));
+    k_bcost_agg<T, R><<<gr, kBlock, 0, s>>>(w, static_cast<ChunkAgg2*>(z.agg2));
+    k_bcost_apply<T, R><<<gr, kBlock, 0, s>>>(w, static_cast<const ChunkAgg2*>(z.agg2));
     return hipGetLastError();
   }
 };
@@ -658,6 +666,8 @@ hipError_t bdispatch(int dtype, int R, F&& f) {
   }
 }
 
+bool group_empty(const BatchGroup& g) { return g.nlist == 0; }
+
 }  // namespace
 
 InstInfo make_inst_info(const double* mu, const double* nu, int64_t base, int64_t n, int chunk0,
@@ -678,9 +688,19 @@ InstInfo make_inst_info(const double* mu, const double* nu, int64_t base, int64_
   return in;
 }
 
-namespace {
-bool group_empty(const BatchGroup& g) { return g.list ? g.nlist == 0 : g.nchunks == 0; }
-}  // namespace
+ChunkRef chunk_ref(const InstInfo& in, int b, int j) {
+  ChunkRef r{};
+  const int64_t C = int64_t(kBlock) * in.k.R;
+  r.base = in.base + int64_t(j) * C;
+  r.lim = in.base + in.n;
+  r.c = in.chunk0 + j;
+  r.b = b;
+  r.j = j;
+  r.nch = in.nch;
+  r.chunk0 = in.chunk0;
+  r.l0 = in.l0;
+  return r;
+}
 
 hipError_t launch_batch_setup(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                               const int* ilist, int count, hipStream_t s) {
@@ -739,7 +759,8 @@ hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, i
 hipError_t launch_batch_admit(const BatchBufs& z, const InstInfo* sinfo, const InstState* sstate,
                               const int* idx, int count, hipStream_t s) {
   if (count > 0)
-    k_badmit<<<unsigned(count), 256, 0, s>>>(sinfo, sstate, idx, z.inst, z.st, z.chunk_inst);
+    k_badmit<<<unsigned((count + 255) / 256), 256, 0, s>>>(sinfo, sstate, idx, count, z.inst,
+                                                          z.st);
   return hipGetLastError();
 }
 

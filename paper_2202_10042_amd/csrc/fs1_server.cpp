@@ -111,8 +111,8 @@ struct fs1_server {
   size_t bytes_per_slot = 0;
   RangeAlloc slots, chunks;
   BatchBufs z{};
-  int* alist = nullptr;        // chunk lists of the admitted requests, per run length
-  int* wlist = nullptr;        // chunk lists of a set-up or a finalisation
+  ChunkRef* alist = nullptr;   // chunk lists of the admitted requests, per run length
+  ChunkRef* wlist = nullptr;   // chunk lists of a set-up or a finalisation
   int* dilist = nullptr;       // instance list of a set-up or a finalisation
   InstInfo* dsinfo = nullptr;  // admission staging
   InstState* dsstate = nullptr;
@@ -122,13 +122,13 @@ struct fs1_server {
   InstState* hsstate = nullptr;
   InstState* hgather = nullptr;
   int* hilist = nullptr;
-  int* hlist = nullptr;
+  ChunkRef* hlist = nullptr;
   int* hring = nullptr;
   int* hcount = nullptr;
   std::deque<Request> queue;
   std::vector<Active> act;     // by instance slot
   std::vector<int> free_inst;
-  std::map<int, std::vector<int>> running;  // run length -> chunk ids of admitted requests
+  std::map<int, std::vector<ChunkRef>> running;  // run length -> chunks of admitted requests
   std::vector<BatchGroup> groups;           // the launch groups over alist
   int64_t next_ticket = 0, steps = 0, completed_total = 0, consumed = 0, nactive = 0;
   int iter_base = 0;
@@ -168,9 +168,8 @@ void carve(fs1_server* v, Carve& w) {
   z.part = static_cast<double*>(w.take(nc * 8));
   z.part2 = static_cast<double*>(w.take(nc * 8));
   z.part3 = static_cast<double*>(w.take(nc * 8));
-  z.chunk_inst = static_cast<int*>(w.take(nc * 4));
-  v->alist = static_cast<int*>(w.take(nc * 4));
-  v->wlist = static_cast<int*>(w.take(nc * 4));
+  v->alist = static_cast<ChunkRef*>(w.take(nc * sizeof(ChunkRef)));
+  v->wlist = static_cast<ChunkRef*>(w.take(nc * sizeof(ChunkRef)));
   z.inst = static_cast<InstInfo*>(w.take(ni * sizeof(InstInfo)));
   z.st = static_cast<InstState*>(w.take(ni * sizeof(InstState)));
   v->dsinfo = static_cast<InstInfo*>(w.take(ni * sizeof(InstInfo)));
@@ -212,20 +211,20 @@ fs1_result to_result(const InstState& t, const Active& a, int itr_max) {
   return r;
 }
 
-// Lists per run length of the given chunk id sets, uploaded to `dev`.
-int upload_groups(fs1_server* v, const std::map<int, std::vector<int>>& by_r, int* dev,
+// Launch lists per run length of the given chunk records, uploaded to `dev`.
+int upload_groups(fs1_server* v, const std::map<int, std::vector<ChunkRef>>& by_r, ChunkRef* dev,
                   std::vector<BatchGroup>* out) {
   out->clear();
   int64_t at = 0;
   for (const auto& kv : by_r) {
     if (kv.second.empty()) continue;
-    std::memcpy(v->hlist + at, kv.second.data(), kv.second.size() * sizeof(int));
-    BatchGroup g{kv.first, 0, 0, dev + at, int(kv.second.size())};
+    std::memcpy(v->hlist + at, kv.second.data(), kv.second.size() * sizeof(ChunkRef));
+    BatchGroup g{kv.first, dev + at, int(kv.second.size())};
     out->push_back(g);
     at += int64_t(kv.second.size());
   }
   if (at > 0) {
-    HIP_TRY(hipMemcpyAsync(dev, v->hlist, size_t(at) * sizeof(int), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(dev, v->hlist, size_t(at) * sizeof(ChunkRef), hipMemcpyHostToDevice,
                            v->ctx->stream));
     // the pinned list is read by that copy: finish it before the host reuses it
     HIP_TRY(hipStreamSynchronize(v->ctx->stream));
@@ -235,7 +234,7 @@ int upload_groups(fs1_server* v, const std::map<int, std::vector<int>>& by_r, in
 
 int admit(fs1_server* v) {
   const int dt = v->o.dtype;
-  std::map<int, std::vector<int>> fresh;
+  std::map<int, std::vector<ChunkRef>> fresh;
   int count = 0;
   while (!v->queue.empty() && !v->free_inst.empty()) {
     const Request& q = v->queue.front();
@@ -268,11 +267,12 @@ int admit(fs1_server* v) {
     t.last_check = -1;
     t.last_err = NAN;
     v->hilist[count] = b;
-    std::vector<int>& fl = fresh[R];
-    std::vector<int>& rl = v->running[R];
+    std::vector<ChunkRef>& fl = fresh[R];
+    std::vector<ChunkRef>& rl = v->running[R];
     for (int i = 0; i < nch; ++i) {
-      fl.push_back(int(c0) + i);
-      rl.push_back(int(c0) + i);
+      const ChunkRef r = chunk_ref(v->hsinfo[count], b, i);
+      fl.push_back(r);
+      rl.push_back(r);
     }
     ++count;
     ++v->nactive;
@@ -329,14 +329,15 @@ int retire(fs1_server* v, int32_t* produced) {
   const int cap = v->o.max_active;
   HIP_TRY(hipMemcpyAsync(v->hring, v->z.ring, size_t(cap) * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  std::map<int, std::vector<int>> fin;
+  std::map<int, std::vector<ChunkRef>> fin;
   int count = 0;
   for (int64_t k = v->consumed; k < total; ++k) {
     const int b = v->hring[k % cap];
     v->hilist[count++] = b;
     const Active& a = v->act[b];
-    std::vector<int>& l = fin[a.R];
-    for (int i = 0; i < a.nch; ++i) l.push_back(a.chunk0 + i);
+    std::vector<ChunkRef>& l = fin[a.R];
+    for (const ChunkRef& r : v->running[a.R])
+      if (r.b == b) l.push_back(r);
   }
   v->consumed = total;
   HIP_TRY(hipMemcpyAsync(v->dilist, v->hilist, count * sizeof(int), hipMemcpyHostToDevice, s));
@@ -360,9 +361,8 @@ int retire(fs1_server* v, int32_t* produced) {
     // give the request's resources back and drop its chunks from the launches
     v->slots.release(a.slot0, a.nslot);
     v->chunks.release(a.chunk0, a.nch);
-    std::vector<int>& rl = v->running[a.R];
-    rl.erase(std::remove_if(rl.begin(), rl.end(),
-                            [&](int c0) { return c0 >= a.chunk0 && c0 < a.chunk0 + a.nch; }),
+    std::vector<ChunkRef>& rl = v->running[a.R];
+    rl.erase(std::remove_if(rl.begin(), rl.end(), [&](const ChunkRef& r) { return r.b == b; }),
              rl.end());
     a = Active{};
     v->free_inst.push_back(b);
@@ -411,7 +411,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   // slots that fit the budget: per slot 256 entries of every element array,
   // one chunk id (256 run exponents x 3, aggregates, shares, lists)
   v->bytes_per_slot = size_t(kSlot) * elem_bytes(o.dtype) + 3 * kBlock * 4 +
-                      2 * sizeof(ChunkAgg) + 48 + 3 * 8 + 3 * 4;
+                      2 * sizeof(ChunkAgg) + 48 + 3 * 8 + 2 * sizeof(ChunkRef);
   const size_t fixed = size_t(o.max_active) * (2 * sizeof(InstInfo) + 3 * sizeof(InstState) + 8) +
                        (size_t(32) << 10);
   v->nslots = o.hbm_budget > int64_t(fixed)
@@ -441,7 +441,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   v->z.nelem = v->nslots * kSlot;
   const size_t ni = size_t(o.max_active);
   const size_t hbytes = ni * (sizeof(InstInfo) + 2 * sizeof(InstState) + 2 * sizeof(int)) +
-                        size_t(v->nslots) * sizeof(int) + 256;
+                        size_t(v->nslots) * sizeof(ChunkRef) + 256;
   e = hipHostMalloc(reinterpret_cast<void**>(&v->hmem), hbytes, hipHostMallocDefault);
   if (e != hipSuccess) {
     (void)hipFree(v->mem);
@@ -462,7 +462,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   h += ni * sizeof(int);
   v->hring = reinterpret_cast<int*>(h);
   h += ni * sizeof(int);
-  v->hlist = reinterpret_cast<int*>(h);
+  v->hlist = reinterpret_cast<ChunkRef*>(h);
   v->slots.reset(v->nslots);
   v->chunks.reset(v->nslots);
   v->act.assign(ni, Active{});
