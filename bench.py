@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--n", type=int, default=N_C2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--cpu-iters", type=int, default=80)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="a 256 MiB device copy, then one fixed 300-iteration solve of the "
