@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the Poisson request stream through the server")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-paper-workloads", action="store_true",
+                    help="skip the Sec. 5.1 / 5.2 workloads at the paper's sizes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -259,12 +261,61 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_study(fs1, ctx, inputs, np, torch, args.serve_seconds)
 
+    if not args.no_paper_workloads:
+        out["paper_workloads"] = paper_workloads_study(fs1, ctx, inputs, np, torch)
+
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle.fs1_log, {args.cpu_iters} iterations at N={n} ...")
         out["cpu_baseline"] = cpu_baseline(mu_np, nu_np, h, args.eps, args.cpu_iters)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} grid-pts*it/s")
 
     print(json.dumps(out), flush=True)
+
+
+# The paper's FS-1 and dense Sinkhorn times (seconds per solve, its CPU; Sec. 5,
+# Tables 1 and 2), quoted as context for the GPU times on the same workloads.
+PAPER_TIMES = {
+    "table1": {500: (8.70e-3, 7.68e-2), 2000: (4.25e-2, 2.81e0), 8000: (1.53e-1, 4.80e1)},
+    "table2": {500: (4.90e-3, 2.30e-2), 2000: (1.52e-2, 1.36e0), 8000: (5.96e-2, 2.81e1)},
+}
+
+
+def paper_workloads_study(fs1, ctx, inputs, np, torch):
+    """Sec. 5.1 (uniform random marginals on [-3, 3], eps = 1e-3, 1000
+    iterations) and Sec. 5.2 (Ricker wavelets, eps = 1e-2, 500 iterations) at
+    N = 500, 2000, 8000: binary64 solves with a fixed iteration count, plain
+    (as in the paper) and log domain; best of three timed solves each."""
+    spec = {"table1": (lambda n: inputs.paper_uniform_pair(n, 0), 1e-3, 1000),
+            "table2": (lambda n: inputs.ricker_pair(n), 1e-2, 500)}
+    rows = []
+    for name, (gen, eps, its) in spec.items():
+        for n in (500, 2000, 8000):
+            u, v, h = gen(n)
+            mu = torch.tensor(u, dtype=torch.float64, device="cuda")
+            nu = torch.tensor(v, dtype=torch.float64, device="cuda")
+            for domain in ("plain", "log"):
+                best, r = None, None
+                for rep in range(4):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = fs1.fs1_solve(mu, nu, eps, 0.0, h=h, itr_max=its, dtype="f64",
+                                      domain=domain, sync_every=64, ctx=ctx)
+                    torch.cuda.synchronize()
+                    w = time.perf_counter() - t0
+                    if rep > 0:
+                        best = w if best is None else min(best, w)
+                pf, pd = PAPER_TIMES[name][n]
+                rows.append({"workload": name, "n": n, "eps": eps, "iterations": r.iterations,
+                             "domain": domain, "status": r.status, "w1": r.w1,
+                             "marginal_err": r.marginal_err, "gpu_s": best,
+                             "paper_fs1_cpu_s": pf, "paper_dense_cpu_s": pd,
+                             "speedup_vs_paper_fs1": pf / best})
+                log(f"{name} n={n} {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
+                    f"(paper's FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
+    return {"rows": rows,
+            "note": "paper times: FS-1 and dense Sinkhorn on the paper's CPU (context, not a "
+                    "target); GPU: one MI355X, binary64, fixed iteration counts, inputs "
+                    "resident in HBM"}
 
 
 def large_n_study(fs1, ctx, inputs, np, torch):

@@ -134,6 +134,7 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 #define FS1_FLAG_GENERAL 2
 #define FS1_FLAG_PERSISTENT 4
 #define FS1_FLAG_NO_GRAPH 8
+#define FS1_FLAG_NO_RESIDENT 16
 
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
@@ -147,14 +148,19 @@ typedef struct {
                              (performance only; results do not depend on it)      */
     int32_t flags;        /* bit 0 (FS1_FLAG_POTENTIALS): return potentials (see
                              potentials_out).  Solver selection (results agree to
-                             rounding; FS1_LOG only): by default a grid of at most
-                             4096 chunks whose chunk frame fits the working
-                             precision runs one fused kernel per half-iteration;
-                             bit 1 (FS1_FLAG_GENERAL) forces the general path
-                             (extended-range scans, separate carry kernel);
-                             bit 2 (FS1_FLAG_PERSISTENT) asks for the single-launch
-                             persistent solver when the grid fits in the registers
-                             of the co-resident workgroups                       */
+                             rounding): by default a grid of at most 1024 runs
+                             (n <= 1024 R; R = 8 in binary64, up to 16 in
+                             binary32) runs the whole solve in one workgroup and
+                             one launch (both domains); otherwise, in FS1_LOG, a
+                             grid of at most 1024 chunks whose chunk frame fits
+                             the working precision runs one fused kernel per
+                             half-iteration; bit 1 (FS1_FLAG_GENERAL) forces the
+                             general path (extended-range scans, separate carry
+                             kernel); bit 2 (FS1_FLAG_PERSISTENT) asks for the
+                             single-launch persistent solver when the grid fits
+                             in the registers of the co-resident workgroups;
+                             bit 4 (FS1_FLAG_NO_RESIDENT) skips the one-workgroup
+                             solver                                               */
     double *potentials_out; /* device, 2n doubles: F = ln phi (n), then G = ln psi
                              (n), written when flags bit 0 is set; -inf where the
                              scaling is zero                                        */

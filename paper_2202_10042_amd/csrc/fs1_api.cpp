@@ -513,13 +513,20 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const int dt = o.dtype;
   const size_t es = dt == FS1_F64 ? 8 : 4;
   int R = pick_run_length(dt, absorb, h / eps);
+  // grids of at most 1024 runs: the whole solve in one resident workgroup
+  const int rr = (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT))
+                     ? 0
+                     : resident_run_length(n, R);
+  if (rr > 0) R = rr;
+  const int res_threads = rr > 0 ? resident_threads(n, R) : 0;
   // the fused one-launch-per-half path picks its own run length where it applies
-  if (absorb && !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
+  if (res_threads == 0 && absorb && !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
     const int rf = fused_run_length(dt, h / eps, n);
     if (rf > 0) R = rf;
   }
   const int64_t C = int64_t(kBlock) * R;
-  const int64_t nchunks = (n + C - 1) / C;
+  // the resident workgroup's runs are allocated whole
+  const int64_t nchunks = res_threads ? res_threads / kBlock : (n + C - 1) / C;
   if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));
   const int64_t nruns = nchunks * kBlock;
 
@@ -608,18 +615,25 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // Mid-size grids whose vectors fit in the registers of the co-resident
   // workgroups run all iterations in one cooperative launch.
-  const bool persistent = (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
-  const bool fused = !persistent && !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+  const bool resident = res_threads > 0 && usable_resident(b);
+  const bool persistent =
+      !resident && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
+  const bool fused =
+      !resident && !persistent && !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
   if (fused) HIP_TRY(launch_fused_init(b, k, s));
-  if (persistent) {
+  if (persistent || resident) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
       e0 = ctx->events[0];
       e1 = ctx->events[1];
       HIP_TRY(hipEventRecord(e0, s));
     }
-    HIP_TRY(hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), s));
-    HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, bar, s));
+    if (resident) {
+      HIP_TRY(launch_resident(b, k, o.itr_max, o.check_every, tol, s));
+    } else {
+      HIP_TRY(hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), s));
+      HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, bar, s));
+    }
     if (prof) HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -638,8 +652,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
 
   // Algorithm 1: while l < itr_max and err(l) > tol
-  int l = persistent ? o.itr_max : 0;
-  bool stopped = persistent;
+  int l = (persistent || resident) ? o.itr_max : 0;
+  bool stopped = persistent || resident;
   int batch = 0;
   while (l < o.itr_max && !stopped) {
     const int l0 = l;
@@ -686,8 +700,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
   int l_final = o.itr_max;
   if (hc->done && hc->stop_iter >= 0) l_final = hc->stop_iter;
-  // the persistent kernel leaves its final psi in buffer 0
-  const int gbuf = persistent ? 0 : (l_final & 1);
+  // the persistent and resident kernels leave their final psi in buffer 0
+  const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
 
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));

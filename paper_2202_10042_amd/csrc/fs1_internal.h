@@ -149,6 +149,17 @@ struct SolveBufs {
   double* err_hist;   // optional (itr_max + 1)
 };
 
+// Resident solve: the whole solve in one workgroup and one launch, for n <=
+// 1024 R.  resident_run_length() gives the run length to use for a grid of n
+// whose exponent margin allows runs up to rmax (0: the grid does not fit),
+// resident_threads() the workgroup size (256 or 1024, 0 if n does not fit);
+// the vectors must be allocated to exactly that many runs.
+int resident_run_length(int64_t n, int rmax);
+int resident_threads(int64_t n, int R);
+bool usable_resident(const SolveBufs& b);
+hipError_t launch_resident(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,
+                           double tol, hipStream_t s);
+
 // Persistent solve (all iterations in one cooperative launch; state kept in
 // registers).  usable_persistent() tells whether the configuration fits.
 bool usable_persistent(const SolveBufs& b, double c);

@@ -35,6 +35,7 @@ FS1_FLAG_POTENTIALS = 1
 FS1_FLAG_GENERAL = 2
 FS1_FLAG_PERSISTENT = 4
 FS1_FLAG_NO_GRAPH = 8
+FS1_FLAG_NO_RESIDENT = 16
 
 # every symbol include/fs1.h declares
 EXPORTS = (
@@ -298,16 +299,18 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
               raise_on_error: bool = False) -> Result:
     """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
 
-    solver: "auto" (fused one-launch-per-half kernels when they apply),
-    "general" (extended-range scans with a separate carry kernel) or
-    "persistent" (single cooperative launch when the grid fits)."""
+    solver: "auto" (the whole solve in one workgroup and one launch when
+    n <= 1024 R, else fused one-launch-per-half kernels when they apply),
+    "fused" (as "auto" without the one-workgroup solver), "general"
+    (extended-range scans with a separate carry kernel) or "persistent"
+    (single cooperative launch when the grid fits)."""
     import torch
     ctx = ctx or default_context()
     n = mu.numel()
     if nu.numel() != n:
         raise ValueError("mu and nu must have the same length")
     o = make_opts(h, itr_max, dtype, domain, check_every, sync_every)
-    o.flags |= {"auto": 0, "general": FS1_FLAG_GENERAL,
+    o.flags |= {"auto": 0, "fused": FS1_FLAG_NO_RESIDENT, "general": FS1_FLAG_GENERAL,
                 "persistent": FS1_FLAG_PERSISTENT}[solver]
     pot = hist = None
     if potentials:

@@ -40,9 +40,11 @@ def _pot_close(got, ref_lin, mask, atol):
     assert np.max(np.abs(g - ref)) <= atol, float(np.max(np.abs(g - ref)))
 
 
-# solver paths: "auto" (fused one-launch-per-half kernels where they apply),
-# "general" (extended-range scans + carry kernel), "persistent" (one launch)
-PATHS = ["auto", "general", "persistent"]
+# solver paths: "auto" (one resident workgroup for n <= 1024 R, else fused
+# one-launch-per-half kernels where they apply), "fused" (auto without the
+# resident workgroup), "general" (extended-range scans + carry kernel),
+# "persistent" (one cooperative launch)
+PATHS = ["auto", "fused", "general", "persistent"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -251,6 +253,47 @@ def test_solve_full_size_f64_log(eps, path):
     r32 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f32", domain="log",
                         solver=path)
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
+
+
+@pytest.mark.parametrize("domain", ["plain", "log"])
+@pytest.mark.parametrize("dtype,n", [("f64", 2047), ("f64", 2048), ("f64", 2049), ("f64", 5000),
+                                     ("f64", 8192), ("f32", 4096), ("f32", 4097), ("f32", 8192)])
+def test_resident_workgroup_sizes(dtype, n, domain):
+    """The one-workgroup solver at the edges of its two workgroup sizes (256
+    threads up to 256 R entries, 1024 threads up to 1024 R with R <= 8)
+    against the oracle at a fixed iteration count and against the general
+    path (same arithmetic, other association order)."""
+    fs1 = _fs1()
+    mu, nu = inputs.mixture_pair(n, 3, n)
+    h = 1.0 / n
+    # plain binary32 overflows at small eps (scalings reach e^(1/eps)), as the
+    # paper's unstabilised iteration does: a larger eps there
+    eps = 5e-2 if (dtype == "f32" and domain == "plain") else 2e-3
+    its = 40
+    _say(f"resident {dtype} {domain} n={n}")
+    ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain=domain,
+                      potentials=True)
+    g = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain=domain,
+                      solver="general")
+    assert r.status == 0 and g.status == 0 and r.iterations == its
+    rel = 1e-10 if dtype == "f64" else 1e-5
+    assert r.w1 == pytest.approx(ref.w1, rel=rel)
+    assert r.w1 == pytest.approx(g.w1, rel=1e-12 if dtype == "f64" else 1e-5)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6 if dtype == "f64" else 1e-2,
+                                           abs=1e-12 if dtype == "f64" else 1e-6)
+    m = nu > 0
+    assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= (1e-9 if dtype == "f64" else 1e-4)
+    # to tolerance: the stop decision of Algorithm 1 inside the launch
+    t = fs1.fs1_solve(dev(mu), dev(nu), eps, 1e-6, itr_max=5000, dtype=dtype, domain=domain)
+    tg = fs1.fs1_solve(dev(mu), dev(nu), eps, 1e-6, itr_max=5000, dtype=dtype, domain=domain,
+                       solver="general")
+    assert t.status == 0 and t.converged == tg.converged
+    # binary64: the stop may move by one where err(l) is within rounding of
+    # tol; binary32: its rounding noise on err (~1e-8 here) spans a few
+    # iterations of the slow final decrease
+    slack = 1 if dtype == "f64" else max(1, tg.iterations // 50)
+    assert abs(t.iterations - tg.iterations) <= slack
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
