@@ -177,12 +177,19 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   const size_t es = dt == FS1_F64 ? 8 : 4;
   hipStream_t s = ctx->stream;
 
-  // run length of each instance: a function of (n, eps, dtype) only, so an
-  // instance's arithmetic does not depend on the rest of the batch
-  std::vector<int> rlen(B);
+  // run length of each instance, and whether one workgroup holds all of it
+  // (resident: all its iterations in one launch): a function of (n, eps,
+  // dtype) only, so an instance's arithmetic does not depend on the rest of
+  // the batch
+  std::vector<int> rlen(B), rthreads(B, 0);
   for (int32_t i = 0; i < B; ++i) {
-    const double n = double(offsets[i + 1] - offsets[i]);
-    rlen[i] = pick_run_length(dt, true, (1.0 / n) / eps[i]);
+    const int64_t n = offsets[i + 1] - offsets[i];
+    rlen[i] = pick_run_length(dt, true, (1.0 / double(n)) / eps[i]);
+    const int rr = resident_run_length(n, rlen[i]);
+    if (rr > 0) {
+      rlen[i] = rr;
+      rthreads[i] = resident_threads(n, rr);
+    }
   }
   std::vector<int> rs(rlen);
   std::sort(rs.begin(), rs.end(), [](int a, int b) { return a > b; });
@@ -198,11 +205,13 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     for (int32_t i = 0; i < B; ++i) {
       if (rlen[i] != r) continue;
       const int64_t n = offsets[i + 1] - offsets[i];
-      const int64_t nch = (n + C - 1) / C;
+      // a resident instance is allocated to exactly its workgroup's runs
+      const int64_t nch = rthreads[i] ? rthreads[i] / kBlock : (n + C - 1) / C;
       if (chunk + nch > int64_t(INT32_MAX) / kBlock)
         return set_err(FS1_ERR_INVALID_ARG, "batch too large");
       info[i] = make_inst_info(mu + offsets[i], nu + offsets[i], elem, n, int(chunk), r,
                                1.0 / double(n), eps[i], tol[i], 0);
+      info[i].nch = int32_t(nch);
       members.back().push_back(int(i));
       chunk += nch;
       elem += nch * C;
@@ -211,9 +220,26 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   }
   const int ngroups = int(groups.size());
   const int64_t nchunks = chunk, nruns = chunk * kBlock, nelem = elem;
+  // resident classes (R, workgroup size), the larger workgroups first
+  std::vector<ResGroup> rgroups;
+  std::vector<int> rorder;  // instances of the classes, consecutive
+  for (int nt : {1024, 256}) {
+    for (int r : rs) {
+      ResGroup g{r, nt, nullptr, 0};
+      for (int32_t i = 0; i < B; ++i) {
+        if (rthreads[i] == nt && rlen[i] == r) {
+          rorder.push_back(int(i));
+          ++g.count;
+        }
+      }
+      if (g.count > 0) rgroups.push_back(g);
+    }
+  }
+  const int nres = int(rorder.size());
 
   BatchBufs z{};
   ChunkRef* clist = nullptr;  // device chunk lists of the groups (running instances only)
+  int* rlist = nullptr;       // device instance lists of the resident classes
   auto layout = [&](Carve& w) {
     z.inst = static_cast<InstInfo*>(w.take(size_t(B) * sizeof(InstInfo)));
     z.st = static_cast<InstState*>(w.take(size_t(B) * sizeof(InstState)));
@@ -235,6 +261,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     z.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     z.part3 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     clist = static_cast<ChunkRef*>(w.take(nchunks * sizeof(ChunkRef)));
+    rlist = static_cast<int*>(w.take(size_t(std::max(nres, 1)) * sizeof(int)));
   };
   {
     Carve probe(nullptr);
@@ -242,8 +269,8 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     int st = ensure_ws(ctx, probe.off);
     if (st) return st;
     // pinned staging: stop counters, the per-instance states, the chunk lists
-    st = ensure_hstage(ctx,
-                       64 + size_t(B) * sizeof(InstState) + size_t(nchunks) * sizeof(ChunkRef));
+    st = ensure_hstage(ctx, 64 + size_t(B) * sizeof(InstState) +
+                                size_t(nchunks) * sizeof(ChunkRef) + size_t(nres) * sizeof(int));
     if (st) return st;
     Carve w(ctx->ws);
     layout(w);
@@ -297,8 +324,11 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   // lists are rebuilt (and the graph recaptured) whenever an eighth of the
   // instances that were running at the last rebuild have stopped, so late
   // launches do not carry the chunks of finished instances.
-  auto build_lists = [&](bool all) -> int {
-    if (!all) {
+  // all = true: every instance (set-up, finalisation); otherwise the chunks
+  // of the shared launches: instances that are not resident and, once
+  // `running` is set, have not stopped.
+  auto build_lists = [&](bool all, bool running) -> int {
+    if (running) {
       HIP_TRY(hipMemcpyAsync(hst, z.st, size_t(B) * sizeof(InstState), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
     }
@@ -306,7 +336,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       const int64_t start = at;
       for (int b : members[gi]) {
-        if (!all && hst[b].done) continue;
+        if (!all && (rthreads[b] || (running && hst[b].done))) continue;
         for (int j = 0; j < info[b].nch; ++j) hlist[at++] = chunk_ref(info[b], b, j);
       }
       groups[gi].list = clist + start;
@@ -319,9 +349,36 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
     HIP_TRY(hipStreamSynchronize(s));
     return FS1_OK;
   };
-  int st = build_lists(true);
+  int st = build_lists(true, false);
   if (st) return st;
   HIP_TRY(launch_batch_setup(z, groups.data(), ngroups, nullptr, B, s));
+  // resident instances: their own launches on a second stream, beside the
+  // shared launches of the others
+  if (nres > 0) {
+    int* hr = reinterpret_cast<int*>(hlist + nchunks);
+    std::memcpy(hr, rorder.data(), size_t(nres) * sizeof(int));
+    HIP_TRY(hipMemcpyAsync(rlist, hr, size_t(nres) * sizeof(int), hipMemcpyHostToDevice, s));
+    int at = 0;
+    for (ResGroup& g : rgroups) {
+      g.ilist = rlist + at;
+      at += g.count;
+    }
+    for (hipStream_t& a : ctx->aux)
+      if (!a) HIP_TRY(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    for (hipEvent_t& e : ctx->rev)
+      if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ctx->rev[0], s));
+    // the two workgroup sizes run side by side
+    for (int k = 0; k < 2; ++k) {
+      hipStream_t a = ctx->aux[k];
+      HIP_TRY(hipStreamWaitEvent(a, ctx->rev[0], 0));
+      for (const ResGroup& g : rgroups)
+        if (g.nt == (k == 0 ? 1024 : 256)) HIP_TRY(launch_batch_resident(z, &g, 1, a));
+      HIP_TRY(hipEventRecord(ctx->rev[1 + k], a));
+    }
+  }
+  st = build_lists(false, false);
+  if (st) return st;
   st = capture();
   if (st) return st;
 
@@ -341,7 +398,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
       stopped = hdone[(r - 1) & 1];
       if (stopped >= B) break;
       if (stopped - stopped_at_rebuild >= std::max(1, running_at_rebuild / 8)) {
-        st = build_lists(false);
+        st = build_lists(false, true);
         if (st) return st;
         st = capture();
         if (st) return st;
@@ -352,11 +409,17 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
       }
     }
   }
+  if (nres > 0) {
+    // the shared launches may finish first: wait for the resident ones
+    HIP_TRY(hipStreamWaitEvent(s, ctx->rev[1], 0));
+    HIP_TRY(hipStreamWaitEvent(s, ctx->rev[2], 0));
+    HIP_TRY(hipMemcpyAsync(&hdone[0], z.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   stopped = std::max(stopped, std::max(hdone[0], hdone[1]));
   if (stopped != B)
     return set_err(FS1_ERR_INTERNAL, "batched solve: %d of %d instances stopped", stopped, B);
-  st = build_lists(true);
+  st = build_lists(true, false);
   if (st) return st;
 
   HIP_TRY(launch_batch_finalize(z, groups.data(), ngroups, nullptr, B, nullptr, s));
@@ -420,9 +483,15 @@ int fs1_ctx_destroy(fs1_ctx* c) {
   if (!c) return FS1_OK;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (hipStream_t a : c->aux)
+    if (a) (void)hipStreamSynchronize(a);
   for (hipEvent_t e : c->bev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->rev)
+    if (e) (void)hipEventDestroy(e);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  for (hipStream_t a : c->aux)
+    if (a) (void)hipStreamDestroy(a);
   if (c->hstage) (void)hipHostFree(c->hstage);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hctrl) (void)hipHostFree(c->hctrl);

@@ -116,6 +116,19 @@ hipError_t launch_batch_iterations(const BatchBufs& z, const BatchGroup* groups,
 // states are then gathered to out[0..count).
 hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, int ngroups,
                                  const int* ilist, int count, InstState* out, hipStream_t s);
+// Resident instances (at most 1024 runs, allocated to exactly nt / 256 chunks
+// of run length R): one workgroup of nt threads per instance runs all its
+// iterations in one launch; on return each instance is stopped (done, stop
+// iteration / failure / cap, ndone counted) with its final state in place for
+// launch_batch_finalize.  Instances already stopped (invalid) are skipped.
+struct ResGroup {
+  int R;
+  int nt;             // 256 or 1024
+  const int* ilist;   // device list of instances
+  int count;
+};
+hipError_t launch_batch_resident(const BatchBufs& z, const ResGroup* groups, int ngroups,
+                                 hipStream_t s);
 // Admission: copy count staged descriptions and states into the instance
 // slots idx[0..count).
 hipError_t launch_batch_admit(const BatchBufs& z, const InstInfo* sinfo, const InstState* sstate,

@@ -20,6 +20,7 @@
 #include "fs1_device.h"
 #include "fs1_frame.h"
 #include "fs1_internal.h"
+#include "fs1_resident.h"
 
 namespace fs1 {
 
@@ -532,6 +533,114 @@ __global__ void k_badmit(const InstInfo* sinfo, const InstState* sstate, const i
   st[idx[t]] = sstate[t];
 }
 
+// ---------------------------------------------------------------------------
+// Resident instances (at most 1024 runs): one workgroup runs every iteration
+// of its instance with the state in registers (fs1_resident.h), then leaves
+// the final state where the finalisation kernels read it: phi in vF, psi in
+// the buffer final_buf() names.
+// ---------------------------------------------------------------------------
+struct BResArgs {
+  const InstInfo* inst;
+  InstState* st;
+  const int* ilist;       // instances of this launch, one per workgroup
+  int* ndone;
+  int* ring;
+  int ring_cap;
+  void* vF;
+  void* vG[2];
+  int* eF;
+  int* eG[2];
+  const double* mu64;
+  const double* nu64;
+  const float* mu32;
+  const float* nu32;
+  int itr_max;
+  int check_every;
+};
+
+template <typename T, int R, int NT>
+__global__ __launch_bounds__(NT) void k_bresident(BResArgs a) {
+  __shared__ ResidentLds<T, NT / kWave> S;
+  const int b = a.ilist[blockIdx.x];
+  const InstInfo& in = a.inst[b];
+  InstState& st = a.st[b];
+  if (st.done) return;  // stopped at set-up (invalid input); the same value in every thread
+  const int t = threadIdx.x;
+  const int64_t base = in.base + int64_t(t) * R;
+  const int64_t run = int64_t(in.chunk0) * kBlock + t;
+  T ph[R], ps[R], mu[R], nu[R];
+  res_load<T, R>(static_cast<const T*>(a.vF), base, ph);
+  res_load<T, R>(static_cast<const T*>(a.vG[0]), base, ps);
+  int eph = a.eF[run];
+  int eps = a.eG[0][run];
+  if constexpr (sizeof(T) == 8) {
+    res_load<T, R>(reinterpret_cast<const T*>(a.mu64), base, mu);
+    res_load<T, R>(reinterpret_cast<const T*>(a.nu64), base, nu);
+  } else {
+    res_load<T, R>(reinterpret_cast<const T*>(a.mu32), base, mu);
+    res_load<T, R>(reinterpret_cast<const T*>(a.nu32), base, nu);
+  }
+  InstState* sp = &st;
+  const ResidentEnd end = resident_iterate<T, R, true, NT>(
+      ph, eph, ps, eps, mu, nu, a.nu64 + base, in.k, in.tol, a.itr_max, a.check_every, S,
+      [&](int l, double err) {
+        sp->last_err = err;
+        sp->last_check = l;
+      });
+  const int fb = (end.stop_iter >= 0) ? (end.stop_iter & 1) : (a.itr_max & 1);
+  res_store<T, R>(static_cast<T*>(a.vF), base, ph);
+  res_store<T, R>(static_cast<T*>(a.vG[fb]), base, ps);
+  a.eF[run] = eph;
+  a.eG[fb][run] = eps;
+  if (t == 0) {
+    if (end.fail_iter >= 0) {
+      st.fail = 1;
+      st.fail_iter = end.fail_iter;
+    } else if (end.stop_iter >= 0) {
+      st.stop_iter = end.stop_iter;
+    } else {
+      st.capped = 1;
+    }
+    st.done = 1;
+    const int pos = atomicAdd(a.ndone, 1);
+    if (a.ring) a.ring[pos % a.ring_cap] = b;
+  }
+}
+
+template <typename T, int R, int NT>
+hipError_t bresident_t(const BResArgs& a, int count, hipStream_t s) {
+  k_bresident<T, R, NT><<<unsigned(count), NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bresident(const BResArgs& a, int R, int nt, int count, hipStream_t s) {
+  if (nt == 256) {
+    switch (R) {
+      case 16:
+        if constexpr (sizeof(T) == 4) return bresident_t<T, 16, 256>(a, count, s);
+        return hipErrorInvalidValue;
+      case 8: return bresident_t<T, 8, 256>(a, count, s);
+      case 4:
+        if constexpr (sizeof(T) == 4) return bresident_t<T, 4, 256>(a, count, s);
+        return hipErrorInvalidValue;
+      case 1: return bresident_t<T, 1, 256>(a, count, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (nt == 1024) {
+    switch (R) {
+      case 8: return bresident_t<T, 8, 1024>(a, count, s);
+      case 4:
+        if constexpr (sizeof(T) == 4) return bresident_t<T, 4, 1024>(a, count, s);
+        return hipErrorInvalidValue;
+      case 1: return bresident_t<T, 1, 1024>(a, count, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int R>
 struct BatchOps {
   static BArgs base(const BatchBufs& z, const BatchGroup& g) {
@@ -611,7 +720,13 @@ struct BatchOps {
   }
   static hipError_t finalize(const BatchBufs& z, const BatchGroup& g, hipStream_t s) {
     const unsigned gr = grid(g);
-    // nu side: | psi (K^T phi) - nu |; the aggregates of the final phi are in aggF
+    // aggregates of the final phi (a resident instance leaves them stale; for
+    // the others this recomputes what the last phi-half published, bit for bit)
+    BArgs p0 = base(z, g);
+    set_phi_in(p0, z);
+    p0.A_out = z.aggF;
+    k_bpublish<T, R><<<gr, kBlock, 0, s>>>(p0);
+    // nu side: | psi (K^T phi) - nu |
     BArgs a = base(z, g);
     set_phi_in(a, z);
     a.vown[0] = z.vG[0];
@@ -753,6 +868,37 @@ hipError_t launch_batch_finalize(const BatchBufs& z, const BatchGroup* groups, i
   if (count > 0)
     k_bfinal<<<unsigned((count + 255) / 256), 256, 0, s>>>(z.inst, z.st, z.part, z.part2,
                                                           z.part3, ilist, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_resident(const BatchBufs& z, const ResGroup* groups, int ngroups,
+                                 hipStream_t s) {
+  BResArgs a{};
+  a.inst = z.inst;
+  a.st = z.st;
+  a.ndone = z.ndone;
+  a.ring = z.ring;
+  a.ring_cap = z.ring_cap;
+  a.vF = z.vF;
+  a.vG[0] = z.vG[0];
+  a.vG[1] = z.vG[1];
+  a.eF = z.eF;
+  a.eG[0] = z.eG[0];
+  a.eG[1] = z.eG[1];
+  a.mu64 = z.mu64;
+  a.nu64 = z.nu64;
+  a.mu32 = static_cast<const float*>(z.mu32);
+  a.nu32 = static_cast<const float*>(z.nu32);
+  a.itr_max = z.itr_max;
+  a.check_every = z.check_every;
+  for (int i = 0; i < ngroups; ++i) {
+    const ResGroup& g = groups[i];
+    if (g.count <= 0) continue;
+    a.ilist = g.ilist;
+    const hipError_t e = z.dtype == 0 ? bresident<double>(a, g.R, g.nt, g.count, s)
+                                      : bresident<float>(a, g.R, g.nt, g.count, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

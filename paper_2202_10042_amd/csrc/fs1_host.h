@@ -30,6 +30,9 @@ struct fs1_ctx {
   size_t hstage_size = 0;
   hipStream_t capture = nullptr;  // stream used only to capture iteration graphs
   hipEvent_t bev[2] = {nullptr, nullptr};
+  // resident instances: one stream per workgroup size, beside the shared launches
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipEvent_t rev[3] = {nullptr, nullptr, nullptr};  // set-up done / each stream done
 };
 
 namespace fs1 {
