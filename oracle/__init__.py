@@ -21,6 +21,11 @@ What each routine follows in the paper:
   all of phi and psi is absorbed at every step.
 * ``cost_*`` / ``marginal_err_*``: the returned double sum and the stopping-test
   double sum of Algorithm 1, literally (``*_dense``) and by recursions (``*_fs1``).
+* ``kv2_*``, ``sinkhorn2_dense``, ``fs1_2d``, ``cost2_*``, ``marginal_err2_*``:
+  the two-dimensional problem of Sec. 4 on an n1 x n2 grid in column-major order
+  (entry (i, j) at i + n1 j): K dense from its definition, or Algorithm 2 (the
+  1-D recursions along the first axis, then eq. (2d recursion) across columns);
+  the cost as the literal double sum or split along the two axes.
 
 Pins: every routine is checked in ``tests/test_oracle_pins.py`` against facts the
 paper or the mathematics fixes (closed form of K 1 from the stability analysis of
@@ -86,6 +91,14 @@ def _load():
         "or_fs1": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_fs1_log": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_kv2_dense": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
+        "or_kv2_fs1": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
+        "or_marginal_err2_dense": (d, [i64, i64, p, p, p, d, d, d]),
+        "or_marginal_err2_fs1": (d, [i64, i64, p, p, p, d, d, d]),
+        "or_cost2_dense": (d, [i64, i64, p, p, d, d, d]),
+        "or_cost2_fs1": (d, [i64, i64, p, p, d, d, d]),
+        "or_sinkhorn2_dense": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
+        "or_fs1_2d": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -273,3 +286,84 @@ def plan_log(F, G, h, eps) -> np.ndarray:
         t = F[:, None] + G[None, :] - d * (h / eps)
     t = np.where(np.isnan(t), -np.inf, t)
     return np.exp(t)
+
+
+# --------------------------------------------------------------------------
+# two dimensions (Sec. 4, Algorithm 2); arrays are n1 x n2 in column-major
+# order, flattened: entry (i, j) at i + n1 j
+# --------------------------------------------------------------------------
+
+def _grid2(x, n1, n2) -> np.ndarray:
+    x = _f64(x).reshape(-1)
+    if x.size != n1 * n2:
+        raise ValueError("array size must be n1 * n2")
+    return x
+
+
+def kv2_dense(x, n1: int, n2: int, h1: float, h2: float, eps: float) -> np.ndarray:
+    x = _grid2(x, n1, n2)
+    y = np.empty_like(x)
+    _load().or_kv2_dense(n1, n2, _ptr(x), h1, h2, eps, _ptr(y))
+    return y
+
+
+def kv2_fs1(x, n1: int, n2: int, h1: float, h2: float, eps: float) -> np.ndarray:
+    x = _grid2(x, n1, n2)
+    y = np.empty_like(x)
+    _load().or_kv2_fs1(n1, n2, _ptr(x), h1, h2, eps, _ptr(y))
+    return y
+
+
+def marginal_err2_dense(phi, psi, nu, n1, n2, h1, h2, eps) -> float:
+    phi, psi, nu = _grid2(phi, n1, n2), _grid2(psi, n1, n2), _grid2(nu, n1, n2)
+    return float(_load().or_marginal_err2_dense(n1, n2, _ptr(phi), _ptr(psi), _ptr(nu),
+                                                h1, h2, eps))
+
+
+def marginal_err2_fs1(phi, psi, nu, n1, n2, h1, h2, eps) -> float:
+    phi, psi, nu = _grid2(phi, n1, n2), _grid2(psi, n1, n2), _grid2(nu, n1, n2)
+    return float(_load().or_marginal_err2_fs1(n1, n2, _ptr(phi), _ptr(psi), _ptr(nu),
+                                              h1, h2, eps))
+
+
+def cost2_dense(phi, psi, n1, n2, h1, h2, eps) -> float:
+    phi, psi = _grid2(phi, n1, n2), _grid2(psi, n1, n2)
+    return float(_load().or_cost2_dense(n1, n2, _ptr(phi), _ptr(psi), h1, h2, eps))
+
+
+def cost2_fs1(phi, psi, n1, n2, h1, h2, eps) -> float:
+    phi, psi = _grid2(phi, n1, n2), _grid2(psi, n1, n2)
+    return float(_load().or_cost2_fs1(n1, n2, _ptr(phi), _ptr(psi), h1, h2, eps))
+
+
+def _solve2(fname, mu, nu, n1, n2, h1, h2, eps, tol, itr_max) -> OracleResult:
+    mu, nu = _grid2(mu, n1, n2), _grid2(nu, n1, n2)
+    a = np.empty(n1 * n2)
+    b = np.empty(n1 * n2)
+    res = np.zeros(5)
+    st = getattr(_load(), fname)(n1, n2, _ptr(mu), _ptr(nu), h1, h2, eps, tol, int(itr_max),
+                                 _ptr(a), _ptr(b), _ptr(res))
+    if st == -1:
+        raise ValueError(f"{fname}: invalid argument")
+    if st == -4:
+        raise MemoryError(fname)
+    return OracleResult(float(res[0]), float(res[1]), int(res[2]), int(res[3]),
+                        bool(res[4]), a, b)
+
+
+def sinkhorn2_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve2("or_sinkhorn2_dense", mu, nu, n1, n2, h1, h2, eps, tol, itr_max)
+
+
+def fs1_2d(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    return _solve2("or_fs1_2d", mu, nu, n1, n2, h1, h2, eps, tol, itr_max)
+
+
+def plan2(phi, psi, n1, n2, h1, h2, eps) -> np.ndarray:
+    """P_{(i,j),(k,l)} = phi_(i,j) exp(-(|i-k| h1 + |j-l| h2)/eps) psi_(k,l), as an
+    (n1 n2) x (n1 n2) matrix over the column-major flattening."""
+    phi, psi = _grid2(phi, n1, n2), _grid2(psi, n1, n2)
+    r = np.arange(n1 * n2)
+    i, j = r % n1, r // n1
+    d = (np.abs(i[:, None] - i[None, :]) * h1 + np.abs(j[:, None] - j[None, :]) * h2)
+    return phi[:, None] * np.exp(-d / eps) * psi[None, :]

@@ -526,6 +526,232 @@ int or_fs1_log(int64_t n, const double *mu, const double *nu, double h, double e
     return st;
 }
 
+/* ========================================================================= */
+/* Two dimensions (Sec. 4, Algorithm 2).                                      */
+/* Histograms on an n1 x n2 grid, flattened in column-major order: entry      */
+/* (i, j) sits at i + n1 j; i runs along the first axis (spacing h1,           */
+/* lambda1 = e^{-h1/eps}), j along the second (h2, lambda2 = e^{-h2/eps}).     */
+/* The kernel of the 2-D problem is                                            */
+/*   K_{(i,j),(k,l)} = exp(-(|i-k| h1 + |j-l| h2) / eps),                      */
+/* i.e. the block matrix of Sec. 4 with blocks lambda2^{|j-l|} K0, K0 the 1-D  */
+/* kernel of the first axis.                                                   */
+/* ========================================================================= */
+
+/* Table of the distinct entries exp(-(di h1 + dj h2)/eps), di < n1, dj < n2:
+ * each entry of K is read from it by its two index distances. */
+static double *kernel_table2(int64_t n1, int64_t n2, double h1, double h2, double eps) {
+    double *t = (double *)malloc((size_t)(n1 * n2) * sizeof(double));
+    if (!t) return NULL;
+    for (int64_t dj = 0; dj < n2; ++dj)
+        for (int64_t di = 0; di < n1; ++di)
+            t[di + n1 * dj] = exp(-((double)di * h1 + (double)dj * h2) / eps);
+    return t;
+}
+
+/* y = K x with K dense (every one of the (n1 n2)^2 entries used). */
+int or_kv2_dense(int64_t n1, int64_t n2, const double *x, double h1, double h2,
+                 double eps, double *y) {
+    if (n1 < 1 || n2 < 1) return OR_ERR_INVALID_ARG;
+    double *t = kernel_table2(n1, n2, h1, h2, eps);
+    if (!t) return OR_ERR_NO_MEMORY;
+    const int64_t n = n1 * n2;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = r % n1, j = r / n1;
+        nsum acc = {0.0, 0.0};
+        for (int64_t l = 0; l < n2; ++l) {
+            const int64_t dj = l > j ? l - j : j - l;
+            for (int64_t k = 0; k < n1; ++k) {
+                const int64_t di = k > i ? k - i : i - k;
+                nadd(&acc, t[di + n1 * dj] * x[k + n1 * l]);
+            }
+        }
+        y[r] = nval(&acc);
+    }
+    free(t);
+    return OR_OK;
+}
+
+/* y = K x by Algorithm 2: K0 (the 1-D recursions of Sec. 3 with h = h1)
+ * applied to every column, then the recursions of eq. (2d recursion) across
+ * the columns:
+ *   r_1 = K0 x_1,  r_{j+1} = lambda2 r_j + K0 x_{j+1},
+ *   s_{n2} = 0,    s_j = lambda2 (s_{j+1} + K0 x_{j+1}),
+ *   (K x)_j = r_j + s_j   (columns j = 1..n2 in the paper's numbering). */
+int or_kv2_fs1(int64_t n1, int64_t n2, const double *x, double h1, double h2,
+               double eps, double *y) {
+    if (n1 < 1 || n2 < 1) return OR_ERR_INVALID_ARG;
+    const double lam2 = exp(-h2 / eps);
+    double *kx = (double *)malloc((size_t)(n1 * n2) * sizeof(double));
+    double *r = (double *)malloc((size_t)n1 * sizeof(double));
+    double *s = (double *)malloc((size_t)(n1 * n2) * sizeof(double));
+    if (!kx || !r || !s) { free(kx); free(r); free(s); return OR_ERR_NO_MEMORY; }
+    for (int64_t j = 0; j < n2; ++j) or_kv_fs1(n1, x + n1 * j, h1, eps, kx + n1 * j);
+    /* backward part s, last column first */
+    for (int64_t i = 0; i < n1; ++i) s[i + n1 * (n2 - 1)] = 0.0;
+    for (int64_t j = n2 - 2; j >= 0; --j)
+        for (int64_t i = 0; i < n1; ++i)
+            s[i + n1 * j] = lam2 * (s[i + n1 * (j + 1)] + kx[i + n1 * (j + 1)]);
+    /* forward part r, first column first */
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i) {
+            r[i] = (j == 0) ? kx[i] : lam2 * r[i] + kx[i + n1 * j];
+            y[i + n1 * j] = r[i] + s[i + n1 * j];
+        }
+    free(kx); free(r); free(s);
+    return OR_OK;
+}
+
+/* Algorithm 2's stopping-test sum with K dense:
+ *   err = sum_{(i,j)} | psi_(i,j) sum_{(k,l)} K_{(i,j),(k,l)} phi_(k,l) - nu_(i,j) | */
+double or_marginal_err2_dense(int64_t n1, int64_t n2, const double *phi, const double *psi,
+                              const double *nu, double h1, double h2, double eps) {
+    const int64_t n = n1 * n2;
+    double *kt = (double *)malloc((size_t)n * sizeof(double));
+    if (!kt || or_kv2_dense(n1, n2, phi, h1, h2, eps, kt) != OR_OK) { free(kt); return NAN; }
+    nsum err = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) nadd(&err, fabs(psi[r] * kt[r] - nu[r]));
+    free(kt);
+    return nval(&err);
+}
+
+double or_marginal_err2_fs1(int64_t n1, int64_t n2, const double *phi, const double *psi,
+                            const double *nu, double h1, double h2, double eps) {
+    const int64_t n = n1 * n2;
+    double *kt = (double *)malloc((size_t)n * sizeof(double));
+    if (!kt || or_kv2_fs1(n1, n2, phi, h1, h2, eps, kt) != OR_OK) { free(kt); return NAN; }
+    nsum err = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) nadd(&err, fabs(psi[r] * kt[r] - nu[r]));
+    free(kt);
+    return nval(&err);
+}
+
+/* Algorithm 2's returned value, literally:
+ *   W = sum_{(i,j),(k,l)} phi_(i,j) psi_(k,l) K_{(i,j),(k,l)} (|i-k| h1 + |j-l| h2) */
+double or_cost2_dense(int64_t n1, int64_t n2, const double *phi, const double *psi,
+                      double h1, double h2, double eps) {
+    double *t = kernel_table2(n1, n2, h1, h2, eps);
+    if (!t) return NAN;
+    const int64_t n = n1 * n2;
+    double w = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : w)
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = r % n1, j = r / n1;
+        nsum acc = {0.0, 0.0};
+        for (int64_t l = 0; l < n2; ++l) {
+            const int64_t dj = l > j ? l - j : j - l;
+            for (int64_t k = 0; k < n1; ++k) {
+                const int64_t di = k > i ? k - i : i - k;
+                nadd(&acc, t[di + n1 * dj] * psi[k + n1 * l] *
+                               ((double)di * h1 + (double)dj * h2));
+            }
+        }
+        w += phi[r] * nval(&acc);
+    }
+    free(t);
+    return w;
+}
+
+/* (C x)_i = sum_k lambda^{|i-k|} |i-k| x_k by the recursions of or_cost_fs1:
+ *   L_0 = 0, L_{i+1} = lambda (L_i + p_i);  U_{n-1} = 0, U_{i-1} = lambda (U_i + q_i + x_i). */
+static int cost_kernel_fs1(int64_t n, const double *x, double lam, double *out) {
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    double *U = (double *)malloc((size_t)n * sizeof(double));
+    if (!q || !U) { free(q); free(U); return OR_ERR_NO_MEMORY; }
+    q[n - 1] = 0.0;
+    for (int64_t k = n - 2; k >= 0; --k) q[k] = lam * (q[k + 1] + x[k + 1]);
+    U[n - 1] = 0.0;
+    for (int64_t i = n - 1; i >= 1; --i) U[i - 1] = lam * (U[i] + q[i] + x[i]);
+    double p = 0.0, L = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        p = (i == 0) ? x[0] : lam * p + x[i];
+        out[i] = L + U[i];
+        L = lam * (L + p);
+    }
+    free(q); free(U);
+    return OR_OK;
+}
+
+/* The same W in O(n1 n2): the cost |i-k| h1 + |j-l| h2 splits the sum into
+ *   h1 sum phi . (K2 (x) C1) psi  +  h2 sum phi . (C2 (x) K1) psi,
+ * with C_a the 1-D kernel lambda_a^{|d|} |d| of axis a and K_a its Gibbs
+ * kernel, each applied by its recursions along its own axis. */
+double or_cost2_fs1(int64_t n1, int64_t n2, const double *phi, const double *psi,
+                    double h1, double h2, double eps) {
+    const int64_t n = n1 * n2;
+    const double lam1 = exp(-h1 / eps), lam2 = exp(-h2 / eps);
+    double *a = (double *)malloc((size_t)n * sizeof(double));
+    double *row = (double *)malloc((size_t)n2 * sizeof(double));
+    double *row2 = (double *)malloc((size_t)n2 * sizeof(double));
+    if (!a || !row || !row2) { free(a); free(row); free(row2); return NAN; }
+    nsum w1 = {0.0, 0.0}, w2 = {0.0, 0.0};
+    /* term 1: C1 along the first axis, then K2 along the second */
+    for (int64_t j = 0; j < n2; ++j) cost_kernel_fs1(n1, psi + n1 * j, lam1, a + n1 * j);
+    for (int64_t i = 0; i < n1; ++i) {
+        for (int64_t j = 0; j < n2; ++j) row[j] = a[i + n1 * j];
+        or_kv_fs1(n2, row, h2, eps, row2);
+        for (int64_t j = 0; j < n2; ++j) nadd(&w1, phi[i + n1 * j] * row2[j]);
+    }
+    /* term 2: K1 along the first axis, then C2 along the second */
+    for (int64_t j = 0; j < n2; ++j) or_kv_fs1(n1, psi + n1 * j, h1, eps, a + n1 * j);
+    for (int64_t i = 0; i < n1; ++i) {
+        for (int64_t j = 0; j < n2; ++j) row[j] = a[i + n1 * j];
+        cost_kernel_fs1(n2, row, lam2, row2);
+        for (int64_t j = 0; j < n2; ++j) nadd(&w2, phi[i + n1 * j] * row2[j]);
+    }
+    free(a); free(row); free(row2);
+    return h1 * nval(&w1) + h2 * nval(&w2);
+}
+
+/* Algorithm 2 (2-D FS-1) with K applied densely (dense = 1) or by the
+ * recursions (dense = 0): phi = psi = 1/(n1 n2); while it < itr_max and
+ * err > tol: psi <- nu / (K^T phi); phi <- mu / (K psi).  Returns W as above. */
+static int solve2(int dense, int64_t n1, int64_t n2, const double *mu, const double *nu,
+                  double h1, double h2, double eps, double tol, int64_t itr_max,
+                  double *phi, double *psi, double *res) {
+    if (n1 < 1 || n2 < 1 || !(h1 > 0) || !(h2 > 0) || !(eps > 0) || itr_max < 0)
+        return OR_ERR_INVALID_ARG;
+    const int64_t n = n1 * n2;
+    double *den = (double *)malloc((size_t)n * sizeof(double));
+    if (!den) return OR_ERR_NO_MEMORY;
+    for (int64_t r = 0; r < n; ++r) phi[r] = psi[r] = 1.0 / (double)n;
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = dense ? or_marginal_err2_dense(n1, n2, phi, psi, nu, h1, h2, eps)
+                       : or_marginal_err2_fs1(n1, n2, phi, psi, nu, h1, h2, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        if (dense) or_kv2_dense(n1, n2, phi, h1, h2, eps, den);   /* K^T phi (K symmetric) */
+        else or_kv2_fs1(n1, n2, phi, h1, h2, eps, den);
+        if (divide_update(n, nu, den, psi)) { st = OR_ERR_NONFINITE; break; }
+        if (dense) or_kv2_dense(n1, n2, psi, h1, h2, eps, den);   /* K psi */
+        else or_kv2_fs1(n1, n2, psi, h1, h2, eps, den);
+        if (divide_update(n, mu, den, phi)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = dense ? or_marginal_err2_dense(n1, n2, phi, psi, nu, h1, h2, eps)
+                    : or_marginal_err2_fs1(n1, n2, phi, psi, nu, h1, h2, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = NAN;
+    if (st == OR_OK)
+        w = dense ? or_cost2_dense(n1, n2, phi, psi, h1, h2, eps)
+                  : or_cost2_fs1(n1, n2, phi, psi, h1, h2, eps);
+    pack_result(res, w, err, it, st, conv);
+    free(den);
+    return st;
+}
+
+int or_sinkhorn2_dense(int64_t n1, int64_t n2, const double *mu, const double *nu, double h1,
+                       double h2, double eps, double tol, int64_t itr_max, double *phi,
+                       double *psi, double *res) {
+    return solve2(1, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, phi, psi, res);
+}
+
+int or_fs1_2d(int64_t n1, int64_t n2, const double *mu, const double *nu, double h1, double h2,
+              double eps, double tol, int64_t itr_max, double *phi, double *psi, double *res) {
+    return solve2(0, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, phi, psi, res);
+}
+
 /* Number of OpenMP threads the dense routines use (1 without OpenMP). */
 int or_num_threads(void) {
 #ifdef _OPENMP

@@ -94,6 +94,24 @@ def paper_uniform_pair(n: int, seed: int) -> tuple[np.ndarray, np.ndarray, float
     return u / u.sum(), v / v.sum(), 6.0 / (n - 1)
 
 
+def paper_uniform_2d(n1: int, n2: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Sec. 5.3 workload: u, v ~ U[0,1] on an n1 x n2 grid (h1 = h2 = 1 in the
+    paper), each L1-normalised; flattened in column-major order (entry (i, j)
+    at i + n1 j)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, size=(n2, n1)).reshape(-1)
+    v = rng.uniform(0.0, 1.0, size=(n2, n1)).reshape(-1)
+    return u / u.sum(), v / v.sum()
+
+
+def product_pair_2d(n1: int, n2: int, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Product histograms mu = mu1 (x) mu2, nu = nu1 (x) nu2 from the 1-D
+    mixtures of n1 (seed s) and n2 (seed s + 2) points, column-major."""
+    m1, v1 = mixture_pair(n1, k, seed)
+    m2, v2 = mixture_pair(n2, k, seed + 2)
+    return np.outer(m2, m1).reshape(-1), np.outer(v2, v1).reshape(-1)
+
+
 def ricker_pair(n: int, shift: float = -1.2032, delta: float = 1e-3,
                 t0: float = -4.0, t1: float = 4.0, f0: float = 1.0, amp: float = 1.0):
     """Sec. 5.2 workload: R(t) and R(t - s), squared and normalised by eq. (ricker).
