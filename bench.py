@@ -126,7 +126,7 @@ def main():
                     help="skip the Poisson request stream through the server")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-paper-workloads", action="store_true",
-                    help="skip the Sec. 5.1 / 5.2 workloads at the paper's sizes")
+                    help="skip the Sec. 5.1 / 5.2 / 5.3 workloads at the paper's sizes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -277,6 +277,9 @@ def main():
 PAPER_TIMES = {
     "table1": {500: (8.70e-3, 7.68e-2), 2000: (4.25e-2, 2.81e0), 8000: (1.53e-1, 4.80e1)},
     "table2": {500: (4.90e-3, 2.30e-2), 2000: (1.52e-2, 1.36e0), 8000: (5.96e-2, 2.81e1)},
+    # Sec. 5.3, Table 3 (N x N grids)
+    "table3": {10: (1.27e-2, 8.02e-2), 20: (2.01e-2, 6.73e-1), 40: (7.38e-2, 1.38e1),
+               80: (2.64e-1, 4.78e2), 160: (1.08e0, 1.38e4)},
 }
 
 
@@ -312,6 +315,29 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
                              "speedup_vs_paper_fs1": pf / best})
                 log(f"{name} n={n} {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
                     f"(paper's FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
+    # Sec. 5.3: uniform random marginals on N x N grids, h1 = h2 = 1, eps = 0.01,
+    # 1000 iterations, Algorithm 2 (plain binary64)
+    for n in (10, 20, 40, 80, 160):
+        u, v = inputs.paper_uniform_2d(n, n, 0)
+        mu = torch.tensor(u, dtype=torch.float64, device="cuda")
+        nu = torch.tensor(v, dtype=torch.float64, device="cuda")
+        best, r = None, None
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fs1.fs1_solve_2d(mu, nu, n, n, 1.0, 1.0, 0.01, 0.0, itr_max=1000, sync_every=64,
+                                 ctx=ctx)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            if rep > 0:
+                best = w if best is None else min(best, w)
+        pf, pd = PAPER_TIMES["table3"][n]
+        rows.append({"workload": "table3", "n": f"{n}x{n}", "eps": 0.01, "iterations": r.iterations,
+                     "domain": "plain", "status": r.status, "w1": r.w1,
+                     "marginal_err": r.marginal_err, "gpu_s": best, "paper_fs1_cpu_s": pf,
+                     "paper_dense_cpu_s": pd, "speedup_vs_paper_fs1": pf / best})
+        log(f"table3 {n}x{n}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
+            f"(paper's 2-D FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
     return {"rows": rows,
             "note": "paper times: FS-1 and dense Sinkhorn on the paper's CPU (context, not a "
                     "target); GPU: one MI355X, binary64, fixed iteration counts, inputs "

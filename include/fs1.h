@@ -217,6 +217,40 @@ int fs1_solve_batched(fs1_ctx *ctx, const double *mu_packed, const double *nu_pa
                       const double *tol, const fs1_opts *opts, fs1_result *out);
 
 /* ------------------------------------------------------------------------ */
+/* Two dimensions (Sec. 4, Algorithm 2).  A histogram on an n1 x n2 grid is   */
+/* an array of n1 n2 entries in column-major order: entry (i, j) at          */
+/* i + n1 j, i along the first axis (spacing h1), j along the second (h2).   */
+/* The kernel is K_{(i,j),(k,l)} = lambda1^{|i-k|} lambda2^{|j-l|},          */
+/* lambda_a = exp(-h_a / eps): the block matrix of Sec. 4, applied by the    */
+/* 1-D recursions along every column and then eq. (2d recursion) across the  */
+/* columns.  1 <= n1, n2 <= 8192; h1, h2 > 0 and finite; eps > 0 and finite  */
+/* (else FS1_ERR_INVALID_ARG before any launch).                             */
+/* ------------------------------------------------------------------------ */
+
+/* y = K x for device arrays x, y of n1 n2 entries of dtype dt (FS1_F64 or
+ * FS1_F32), plain arithmetic; x and y must not overlap.  Asynchronous on the
+ * context stream. */
+int fs1_kv_apply_2d(fs1_ctx *ctx, const void *x, void *y, int64_t n1, int64_t n2, double h1,
+                    double h2, double eps, int dt);
+
+/* Algorithm 2 (2-D FS-1): phi = psi = 1/(n1 n2); while iterations < itr_max
+ * and err = sum | psi (K^T phi) - nu | > tol: psi = nu / (K^T phi), then
+ * phi = mu / (K psi).  Returns the transport cost
+ *   w1 = sum phi_(i,j) psi_(k,l) K_{(i,j),(k,l)} (|i-k| h1 + |j-l| h2).
+ * mu, nu: device binary64 arrays of n1 n2 entries (column-major), finite,
+ * >= 0, equal mass to 1e-10 relative.  opts as for fs1_solve except: domain
+ * must be FS1_PLAIN (Algorithm 2's arithmetic; FS1_LOG is
+ * FS1_ERR_INVALID_ARG), opts->h is ignored (h1, h2 given); a small grid
+ * (n1 n2 <= 4096, n1 + n2 <= 128) runs the whole solve in one workgroup (the
+ * paper's sequential recursions, one line per thread) unless
+ * FS1_FLAG_NO_RESIDENT is set, other grids one workgroup per line and pass;
+ * potentials_out receives ln phi then
+ * ln psi (2 n1 n2 doubles).  Blocking; error behaviour as fs1_solve. */
+int fs1_solve_2d(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n1, int64_t n2,
+                 double h1, double h2, double eps, double tol, const fs1_opts *opts,
+                 fs1_result *out);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: a request loop with continuous batching (a library addition, not */
 /* part of the paper).  Each request is one solve as fs1_solve in the log    */
 /* domain (h = 1/n).  Requests wait in a queue and are admitted in           */

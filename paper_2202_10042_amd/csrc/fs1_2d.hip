@@ -1,0 +1,805 @@
+// fs1_2d.hip -- two-dimensional FS-1 (Sec. 4, Algorithm 2) on an n1 x n2 grid.
+//
+// Layout: column-major, entry (i, j) at i + n1 j; i runs along the first axis
+// (spacing h1, lambda1 = e^{-h1/eps}), j along the second (h2, lambda2).  The
+// kernel is the Kronecker product K = K2 (x) K1 (the block matrix of Sec. 4),
+// so K x is the 1-D recursions of Sec. 3 along every column (first axis) and
+// then the recursions of eq. (2d recursion) across the columns, which are the
+// same 1-D recursions along every row (second axis).  Each pass runs one
+// workgroup per line: a column is contiguous, a row is strided by n1.  A line
+// of up to 1024 R entries is held by one workgroup (thread t owns the line
+// positions [t R, t R + R)) and scanned with the extended-range block scan of
+// the 1-D path; there are no chunk carries.
+//
+// The transport cost splits along the axes: with C_a the 1-D kernel
+// lambda_a^{|d|} |d| of axis a,
+//   W = h1 <phi, (K2 (x) C1) psi> + h2 <phi, (C2 (x) K1) psi>,
+// and C_a x is the two-state recursion of the 1-D cost.
+//
+// Plain domain (Algorithm 2 as written): scalings are plain numbers, and a
+// non-finite or zero-denominator scaling ends the solve.
+#include <cmath>
+#include <cstring>
+
+#include "fs1_device.h"
+#include "fs1_host.h"
+#include "fs1_internal.h"
+
+namespace fs1 {
+
+namespace {
+
+constexpr int kR2 = 8;  // entries per thread of a line
+
+enum LineMode { L_APPLY = 0, L_COST = 1, L_UPDATE = 2, L_ERR = 3, L_DOT = 4, L_COSTDOT = 5 };
+
+struct LineArgs {
+  const void* x;        // input of the pass
+  void* y;              // output (APPLY, COST, UPDATE)
+  const void* own;      // ERR, DOT, COSTDOT, checked UPDATE: the vector the product multiplies
+  const double* m64;    // marginal, binary64 (UPDATE with T = double; ERR; checked UPDATE)
+  const float* m32;     // marginal, binary32 (UPDATE with T = float)
+  double* part;         // per-line shares (ERR, DOT, COSTDOT, checked UPDATE)
+  Ctrl* ctrl;
+  int64_t line_step;    // offset of line L's first entry: L * line_step
+  int64_t stride;       // offset between consecutive entries of a line
+  int len;              // entries per line
+  int l;                // iteration (failure record)
+  int check;            // UPDATE: also the error share of Algorithm 2's stopping test
+  int guard;            // return at once once the solve has stopped or failed
+};
+
+template <typename T, int R, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
+  constexpr int NW = NT / kWave;
+  __shared__ ScanLds<S1<T>, NW> sh;
+  __shared__ ScanLds<S2<T>, NW> sh2;
+  __shared__ double red[NW];
+  if (a.guard && (a.ctrl->done || a.ctrl->fail)) return;  // the same value in every thread
+  const int64_t base = int64_t(blockIdx.x) * a.line_step;
+  const int p0 = int(threadIdx.x) * R;
+  const T* xin = static_cast<const T*>(a.x);
+  T x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = (p0 + r < a.len) ? xin[base + int64_t(p0 + r) * a.stride] : T(0);
+  const Lam<T> L = lam_of<T>(k);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  const Dec<T> step = step_decay<T>(k);
+  T y[R];
+  int eref = 0;
+  if constexpr (MODE == L_COST || MODE == L_COSTDOT) {
+    // (C x)_i = sum_k lambda^{|i-k|} |i-k| x_k: the two-state recursion
+    T fp, fd, bp, bd;
+    run_aggs2<T, R>(x, L, fp, fd, bp, bd);
+    S2<T> cf, cb;
+    block_scan<S2<T>, NW, T>(S2<T>::of(fp, fd, 0), S2<T>::of(bp, bd, 0), dec, S2<T>::zero(),
+                             S2<T>::zero(), &cf, &cb, nullptr, nullptr, sh2);
+    const S2<T> lcf = cf.shift(step), lcb = cb.shift(step);
+    eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, 0), k);
+    T xf[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) xf[r] = ldx(x[r], -eref);
+    run_cost<T, R>(xf, ldx(lcf.p.m, lcf.p.e - eref), ldx(lcf.d.m, lcf.d.e - eref),
+                   ldx(lcb.p.m, lcb.p.e - eref), ldx(lcb.d.m, lcb.d.e - eref), L, y);
+  } else {
+    // (K x)_i = sum_k lambda^{|i-k|} x_k: the forward and backward recursions
+    T af, ab;
+    run_aggs<T, R>(x, L, af, ab);
+    S1<T> cf, cb;
+    block_scan<S1<T>, NW, T>(S1<T>{{af, 0}}, S1<T>{{ab, 0}}, dec, S1<T>::zero(), S1<T>::zero(),
+                             &cf, &cb, nullptr, nullptr, sh);
+    const S1<T> lcf = cf.shift(step), lcb = cb.shift(step);
+    run_apply<T, R>(x, ldx(lcf.v.m, lcf.v.e), ldx(lcb.v.m, lcb.v.e), L, y);
+  }
+  // y * 2^eref is the product at this thread's positions (eref = 0 except for
+  // the cost recursion's frame)
+  T* yout = static_cast<T*>(a.y);
+  if constexpr (MODE == L_APPLY || MODE == L_COST) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (p0 + r < a.len) yout[base + int64_t(p0 + r) * a.stride] = ldx(y[r], eref);
+    return;
+  }
+  const T* own = static_cast<const T*>(a.own);
+  if constexpr (MODE == L_DOT || MODE == L_COSTDOT) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (p0 + r < a.len)
+        s += ldexp(double(own[base + int64_t(p0 + r) * a.stride]) * double(y[r]), eref);
+    const double tot = block_sum<NW>(s, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+    return;
+  }
+  // ERR, UPDATE: | own * (K x) - marg | and marg / (K x)
+  const bool want_err = (MODE == L_ERR) || a.check;
+  if (want_err) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (p0 + r < a.len) {
+        const int64_t q = base + int64_t(p0 + r) * a.stride;
+        s += fabs(double(own[q]) * double(y[r]) - a.m64[q]);
+      }
+    const double tot = block_sum<NW>(s, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+  }
+  if constexpr (MODE == L_UPDATE) {
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (p0 + r < a.len) {
+        const int64_t q = base + int64_t(p0 + r) * a.stride;
+        const T mg = (sizeof(T) == 8) ? T(a.m64[q]) : T(a.m32[q]);
+        const T v = (mg == T(0)) ? T(0) : mg / y[r];
+        bad |= !isfinite(v);
+        yout[q] = v;
+      }
+    if (bad) {
+      atomicOr(&a.ctrl->fail, 1);
+      atomicMin(&a.ctrl->fail_iter, a.l);
+    }
+  }
+}
+
+// Stop decision of Algorithm 2 for iteration l: err(l) is the fixed-order sum
+// of the per-line shares the psi-half wrote.
+__global__ __launch_bounds__(256) void k_decide2(const double* part, int nlines, Ctrl* ctrl,
+                                                 double tol, int l, double* err_hist) {
+  __shared__ double red[4];
+  if (ctrl->done || ctrl->fail) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nlines; i += 256) s += part[i];
+  const double tot = block_sum<4>(s, red);
+  if (threadIdx.x == 0) {
+    ctrl->last_err = tot;
+    ctrl->last_check = l;
+    if (err_hist) err_hist[l] = tot;
+    if (!(tot > tol)) {
+      ctrl->stop_iter = l;
+      ctrl->done = 1;
+    }
+  }
+}
+
+// out[0] = scale * (fixed-order sum of part[0..n))
+__global__ __launch_bounds__(256) void k_sum2(const double* part, int n, double scale,
+                                              double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  const double tot = block_sum<4>(s, red);
+  if (threadIdx.x == 0) out[0] = scale * tot;
+}
+
+template <typename T>
+__global__ void k_fill2(T* a, T* b, int64_t n, T v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = v;
+    b[i] = v;
+  }
+}
+
+// F = ln phi, G = ln psi (binary64; -inf where a scaling is zero)
+template <typename T>
+__global__ void k_log2(const T* a, const T* b, int64_t n, double* out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[i] = log(double(a[i]));
+    out[n + i] = log(double(b[i]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small grids (n1 n2 <= 4096, short lines): the whole of Algorithm 2 in one
+// workgroup of NT threads (the fewest of 64, 256, 1024 that hold the grid at 4
+// entries each).  Thread t keeps the entries t + NT r (r < 4) of phi, psi, mu
+// and nu in registers; a product K v goes through two LDS arrays, one pass per
+// axis, each line run by one thread with the paper's sequential recursions
+// (Sec. 3: p_k = lambda p_{k-1} + x_k, q_k = lambda (q_{k+1} + x_{k+1})), so
+// the arithmetic is the sequential algorithm's, line by line.
+// ---------------------------------------------------------------------------
+constexpr int kRes2MaxThreads = 1024;
+constexpr int kRes2Per = 4;  // entries per thread: n1 n2 <= 4 x threads (64, 256 or 1024)
+
+constexpr int64_t kRes2MaxSpan = 128;  // n1 + n2
+
+struct Res2Args {
+  const double* mu;
+  const double* nu;
+  const float* mu32;
+  const float* nu32;
+  void* vF;      // in: initial phi; out: final phi
+  void* vG;      // in: initial psi; out: final psi
+  Ctrl* ctrl;
+  double* err_hist;
+  int n1, n2;
+  int itr_max;
+  int check_every;
+  double tol;
+  double lam1, lam2;
+};
+
+// one line of `len` entries at X[base + k stride]: Y = (forward + backward)
+// recursions, taken a group of entries at a time (16 binary32 / 8 binary64:
+// what the registers hold beside the state) so that each group's LDS loads
+// are issued together ahead of its dependent chain
+template <typename T>
+__device__ __forceinline__ void seq_line(const T* X, T* Y, int base, int stride, int len, T lam) {
+  constexpr int kSeqGroup = sizeof(T) == 8 ? 8 : 16;
+  T r = T(0);
+  for (int k0 = 0; k0 < len; k0 += kSeqGroup) {
+    T v[kSeqGroup];
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u)
+      v[u] = (k0 + u < len) ? X[base + (k0 + u) * stride] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u) {
+      r = lam * r + v[u];
+      v[u] = r;
+    }
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u)
+      if (k0 + u < len) Y[base + (k0 + u) * stride] = v[u];
+  }
+  T q = T(0);
+  for (int k0 = len - 1; k0 >= 0; k0 -= kSeqGroup) {
+    T v[kSeqGroup], w[kSeqGroup];
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u) {
+      const bool in = k0 - u >= 0;
+      v[u] = in ? X[base + (k0 - u) * stride] : T(0);
+      w[u] = in ? Y[base + (k0 - u) * stride] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u) {
+      w[u] += q;
+      q = lam * (q + v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kSeqGroup; ++u)
+      if (k0 - u >= 0) Y[base + (k0 - u) * stride] = w[u];
+  }
+}
+
+// X <- K X (column-major n1 x n2 in LDS), through Y
+template <typename T, int NT>
+__device__ __forceinline__ void seq_kv2(T* X, T* Y, int n1, int n2, T lam1, T lam2) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  for (int j = t; j < n2; j += NT) seq_line<T>(X, Y, j * n1, 1, n1, lam1);
+  __syncthreads();
+  for (int i = t; i < n1; i += NT) seq_line<T>(Y, X, i, n1, n2, lam2);
+  __syncthreads();
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
+  extern __shared__ __align__(16) unsigned char lds2[];
+  __shared__ double red[NT / kWave];
+  __shared__ int sstop;
+  const int n = a.n1 * a.n2;
+  T* X = reinterpret_cast<T*>(lds2);
+  T* Y = X + n;
+  const int t = threadIdx.x;
+  const T lam1 = T(a.lam1), lam2 = T(a.lam2);
+  T ph[kRes2Per], ps[kRes2Per], mu[kRes2Per], nu[kRes2Per];
+  double nu64[kRes2Per];  // the stopping test's binary64 nu, kept in registers
+#pragma unroll
+  for (int r = 0; r < kRes2Per; ++r) {
+    const int e = t + NT * r;
+    const bool in = e < n;
+    ph[r] = in ? static_cast<const T*>(a.vF)[e] : T(0);
+    ps[r] = in ? static_cast<const T*>(a.vG)[e] : T(0);
+    nu64[r] = in ? a.nu[e] : 0.0;
+    if constexpr (sizeof(T) == 8) {
+      mu[r] = in ? T(a.mu[e]) : T(0);
+      nu[r] = T(nu64[r]);
+    } else {
+      mu[r] = in ? T(a.mu32[e]) : T(0);
+      nu[r] = in ? T(a.nu32[e]) : T(0);
+    }
+  }
+  int l = 0, stop_iter = -1, fail_iter = -1;
+  for (; l < a.itr_max; ++l) {
+    // psi-half: K^T phi^l (K is symmetric)
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) X[e] = ph[r];
+    }
+    seq_kv2<T, NT>(X, Y, a.n1, a.n2, lam1, lam2);
+    if ((l % a.check_every) == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRes2Per; ++r) {
+        const int e = t + NT * r;
+        if (e < n) s += fabs(double(ps[r]) * double(X[e]) - nu64[r]);
+      }
+      const double tot = block_sum<NT / kWave>(s, red);
+      if (t == 0) {
+        a.ctrl->last_err = tot;
+        a.ctrl->last_check = l;
+        if (a.err_hist) a.err_hist[l] = tot;
+        sstop = !(tot > a.tol);
+      }
+      __syncthreads();
+      if (sstop) {
+        stop_iter = l;
+        break;
+      }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) {
+        ps[r] = (nu[r] == T(0)) ? T(0) : nu[r] / X[e];
+        bad |= !isfinite(ps[r]);
+      }
+    }
+    // phi-half: K psi^{l+1}
+    __syncthreads();  // every read of X above is done
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) X[e] = ps[r];
+    }
+    seq_kv2<T, NT>(X, Y, a.n1, a.n2, lam1, lam2);
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) {
+        ph[r] = (mu[r] == T(0)) ? T(0) : mu[r] / X[e];
+        bad |= !isfinite(ph[r]);
+      }
+    }
+    // a non-finite scaling in either half ends the solve (abnormal termination)
+    if (__syncthreads_or(bad ? 1 : 0)) {
+      fail_iter = l;
+      break;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRes2Per; ++r) {
+    const int e = t + NT * r;
+    if (e < n) {
+      static_cast<T*>(a.vF)[e] = ph[r];
+      static_cast<T*>(a.vG)[e] = ps[r];
+    }
+  }
+  if (t == 0) {
+    if (stop_iter >= 0) {
+      a.ctrl->done = 1;
+      a.ctrl->stop_iter = stop_iter;
+    }
+    if (fail_iter >= 0) {
+      a.ctrl->done = 1;
+      a.ctrl->fail = 1;
+      a.ctrl->fail_iter = fail_iter;
+    }
+  }
+}
+
+// LDS bytes of the one-workgroup solver, or 0 if the grid does not fit it on
+// this device
+int res2d_threads(int64_t n) {
+  for (int nt : {64, 256, kRes2MaxThreads})
+    if (n <= int64_t(nt) * kRes2Per) return nt;
+  return 0;
+}
+
+size_t res2d_lds(int64_t n1, int64_t n2, int dt) {
+  const int64_t n = n1 * n2;
+  if (res2d_threads(n) == 0) return 0;
+  // an iteration walks both line lengths sequentially: beyond this the
+  // per-line launches (fixed cost per pass) are faster
+  if (n1 + n2 > kRes2MaxSpan) return 0;
+  const size_t bytes = size_t(2 * n) * (dt == FS1_F64 ? 8 : 4);
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  // room for the kernel's own reduction arrays
+  return bytes + 1024 <= size_t(lim) ? bytes : 0;
+}
+
+template <typename T, int NT>
+hipError_t launch_res2d_t(const Res2Args& a, size_t lds, hipStream_t s) {
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_res2d<T, NT>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
+  k_res2d<T, NT><<<1, NT, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_res2d(const Res2Args& a, size_t lds, hipStream_t s) {
+  switch (res2d_threads(int64_t(a.n1) * a.n2)) {
+    case 64: return launch_res2d_t<T, 64>(a, lds, s);
+    case 256: return launch_res2d_t<T, 256>(a, lds, s);
+    case kRes2MaxThreads: return launch_res2d_t<T, kRes2MaxThreads>(a, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One pass over the lines of one axis.
+struct Axis {
+  int64_t nlines;
+  int64_t line_step;
+  int64_t stride;
+  int len;
+  ScanConsts k;
+};
+
+template <typename T, int MODE>
+hipError_t run_pass(const Axis& ax, LineArgs a, hipStream_t s) {
+  a.line_step = ax.line_step;
+  a.stride = ax.stride;
+  a.len = ax.len;
+  const unsigned g = unsigned(ax.nlines);
+  if (ax.len <= 256 * kR2) {
+    k_line<T, kR2, 256, MODE><<<g, 256, 0, s>>>(a, ax.k);
+  } else {
+    k_line<T, kR2, 1024, MODE><<<g, 1024, 0, s>>>(a, ax.k);
+  }
+  return hipGetLastError();
+}
+
+struct Grid2 {
+  int64_t n1, n2;
+  Axis ax1, ax2;
+};
+
+Grid2 make_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps) {
+  Grid2 g;
+  g.n1 = n1;
+  g.n2 = n2;
+  // columns: n2 lines of n1 contiguous entries; rows: n1 lines strided by n1
+  g.ax1 = Axis{n2, n1, 1, int(n1), make_scan_consts(h1, eps, kR2)};
+  g.ax2 = Axis{n1, 1, n1, int(n2), make_scan_consts(h2, eps, kR2)};
+  return g;
+}
+
+int check_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps) {
+  using host::set_err;
+  const int64_t lmax = int64_t(1024) * kR2;
+  if (n1 < 1 || n2 < 1) return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be >= 1");
+  if (n1 > lmax || n2 > lmax)
+    return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be <= %lld (got %lld x %lld)",
+                   (long long)lmax, (long long)n1, (long long)n2);
+  if (!(h1 > 0.0) || !std::isfinite(h1) || !(h2 > 0.0) || !std::isfinite(h2))
+    return set_err(FS1_ERR_INVALID_ARG, "h1 and h2 must be finite and > 0");
+  if (!(eps > 0.0) || !std::isfinite(eps))
+    return set_err(FS1_ERR_INVALID_ARG, "eps must be finite and > 0");
+  if (double(std::max(n1, n2)) * (std::max(h1, h2) / eps) > 1.0e8)
+    return set_err(FS1_ERR_INVALID_ARG, "n h / eps exceeds 1e8 along an axis");
+  return FS1_OK;
+}
+
+template <typename T>
+hipError_t kv2(const Grid2& g, const void* x, void* y, void* t, hipStream_t s) {
+  LineArgs a{};
+  a.x = x;
+  a.y = t;
+  hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+  if (e != hipSuccess) return e;
+  a.x = t;
+  a.y = y;
+  return run_pass<T, L_APPLY>(g.ax2, a, s);
+}
+
+struct Bufs2 {
+  void* vF;
+  void* vG[2];
+  void* t;
+  double* mu;       // caller's marginals, binary64
+  double* nu;
+  float* mu32;      // binary32 copies (T = float)
+  float* nu32;
+  double* part;     // n1 + n2 shares per line kind
+  double* part2;
+  double* sums;     // [0] err, [1] mu err, [2] cost term 1, [3] cost term 2
+  Ctrl* ctrl;
+};
+
+template <typename T>
+struct Ops2 {
+  // psi^{l+1} = nu / K^T phi^l into vG[(l+1)&1] (and the error of (phi^l, psi^l) when checked)
+  static hipError_t psi_half(const Grid2& g, const Bufs2& b, int l, int check, hipStream_t s) {
+    LineArgs a{};
+    a.ctrl = b.ctrl;
+    a.guard = 1;
+    a.l = l;
+    a.x = b.vF;
+    a.y = b.t;
+    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.y = b.vG[(l + 1) & 1];
+    a.own = b.vG[l & 1];
+    a.m64 = b.nu;
+    a.m32 = b.nu32;
+    a.part = b.part;
+    a.check = check;
+    return run_pass<T, L_UPDATE>(g.ax2, a, s);
+  }
+  // phi^{l+1} = mu / K psi^{l+1}
+  static hipError_t phi_half(const Grid2& g, const Bufs2& b, int l, hipStream_t s) {
+    LineArgs a{};
+    a.ctrl = b.ctrl;
+    a.guard = 1;
+    a.l = l;
+    a.x = b.vG[(l + 1) & 1];
+    a.y = b.t;
+    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.y = b.vF;
+    a.m64 = b.mu;
+    a.m32 = b.mu32;
+    return run_pass<T, L_UPDATE>(g.ax2, a, s);
+  }
+  // final errors (both sides) and the transport cost of (phi, psi = vG[gbuf])
+  static hipError_t finalize(const Grid2& g, const Bufs2& b, int gbuf, double h1, double h2,
+                             hipStream_t s) {
+    const int nl = int(g.ax2.nlines);
+    LineArgs a{};
+    a.ctrl = b.ctrl;
+    // nu side: sum | psi (K^T phi) - nu |
+    a.x = b.vF;
+    a.y = b.t;
+    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.own = b.vG[gbuf];
+    a.m64 = b.nu;
+    a.part = b.part;
+    e = run_pass<T, L_ERR>(g.ax2, a, s);
+    if (e != hipSuccess) return e;
+    k_sum2<<<1, 256, 0, s>>>(b.part, nl, 1.0, b.sums + 0);
+    // mu side: sum | phi (K psi) - mu |
+    a.x = b.vG[gbuf];
+    a.y = b.t;
+    e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.own = b.vF;
+    a.m64 = b.mu;
+    a.part = b.part2;
+    e = run_pass<T, L_ERR>(g.ax2, a, s);
+    if (e != hipSuccess) return e;
+    k_sum2<<<1, 256, 0, s>>>(b.part2, nl, 1.0, b.sums + 1);
+    // cost, first axis: h1 <phi, (K2 (x) C1) psi>
+    a.x = b.vG[gbuf];
+    a.y = b.t;
+    e = run_pass<T, L_COST>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.own = b.vF;
+    a.part = b.part;
+    e = run_pass<T, L_DOT>(g.ax2, a, s);
+    if (e != hipSuccess) return e;
+    k_sum2<<<1, 256, 0, s>>>(b.part, nl, h1, b.sums + 2);
+    // cost, second axis: h2 <phi, (C2 (x) K1) psi>
+    a.x = b.vG[gbuf];
+    a.y = b.t;
+    e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    if (e != hipSuccess) return e;
+    a.x = b.t;
+    a.own = b.vF;
+    a.part = b.part2;
+    e = run_pass<T, L_COSTDOT>(g.ax2, a, s);
+    if (e != hipSuccess) return e;
+    k_sum2<<<1, 256, 0, s>>>(b.part2, nl, h2, b.sums + 3);
+    return hipGetLastError();
+  }
+};
+
+template <typename F>
+hipError_t dispatch2(int dt, F&& f) {
+  return dt == 0 ? f(Ops2<double>{}) : f(Ops2<float>{});
+}
+
+}  // namespace
+
+int kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
+                double h2, double eps, int dt) {
+  using namespace host;
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (!x || !y) return set_err(FS1_ERR_INVALID_ARG, "null array");
+  if (dt != FS1_F64 && dt != FS1_F32) return set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", dt);
+  int st = check_grid2(n1, n2, h1, h2, eps);
+  if (st) return st;
+  const int64_t n = n1 * n2;
+  const size_t es = dt == FS1_F64 ? 8 : 4;
+  const char* xb = static_cast<const char*>(x);
+  const char* yb = static_cast<const char*>(y);
+  if (xb < yb + n * es && yb < xb + n * es)
+    return set_err(FS1_ERR_INVALID_ARG, "x and y must not overlap");
+  st = ensure_ws(ctx, size_t(n) * es);
+  if (st) return st;
+  const Grid2 g = make_grid2(n1, n2, h1, h2, eps);
+  const hipError_t e = dt == FS1_F64 ? kv2<double>(g, x, y, ctx->ws, ctx->stream)
+                                     : kv2<float>(g, x, y, ctx->ws, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "fs1_kv_apply_2d launch");
+  return FS1_OK;
+}
+
+int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2, double h1,
+             double h2, double eps, double tol, const fs1_opts& o, fs1_result* out) {
+  using namespace host;
+  auto finish = [&](int st) {
+    out->status = st;
+    return st;
+  };
+  if (!mu || !nu) return finish(set_err(FS1_ERR_INVALID_ARG, "null marginal"));
+  if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype));
+  if (o.domain != FS1_PLAIN)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "the 2-D solve runs in the plain domain only"));
+  if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
+  if ((o.flags & FS1_FLAG_POTENTIALS) && !o.potentials_out)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
+  int st = check_grid2(n1, n2, h1, h2, eps);
+  if (st) return finish(st);
+  const int dt = o.dtype;
+  const int64_t n = n1 * n2;
+  const size_t es = dt == FS1_F64 ? 8 : 4;
+  const int64_t nl = std::max(n1, n2);
+
+  Bufs2 b{};
+  auto layout = [&](Carve& w) {
+    b.vF = w.take(size_t(n) * es);
+    b.vG[0] = w.take(size_t(n) * es);
+    b.vG[1] = w.take(size_t(n) * es);
+    b.t = w.take(size_t(n) * es);
+    b.mu = static_cast<double*>(w.take(size_t(n) * 8));
+    b.nu = static_cast<double*>(w.take(size_t(n) * 8));
+    b.mu32 = dt == FS1_F32 ? static_cast<float*>(w.take(size_t(n) * 4)) : nullptr;
+    b.nu32 = dt == FS1_F32 ? static_cast<float*>(w.take(size_t(n) * 4)) : nullptr;
+    b.part = static_cast<double*>(w.take(size_t(nl) * 8));
+    b.part2 = static_cast<double*>(w.take(size_t(nl) * 8));
+    b.sums = static_cast<double*>(w.take(4 * 8));
+    b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
+  };
+  {
+    Carve probe(nullptr);
+    layout(probe);
+    st = ensure_ws(ctx, probe.off);
+    if (st) return finish(st);
+    Carve w(ctx->ws);
+    layout(w);
+  }
+  hipStream_t s = ctx->stream;
+  Ctrl* hc = ctx->hctrl;
+  // validation and copies of the marginals (the 1-D set-up kernel over n entries)
+  SolveBufs sb{};
+  sb.dtype = dt;
+  sb.n = n;
+  sb.npad = n;
+  sb.mu_src = mu;
+  sb.nu_src = nu;
+  sb.mu = b.mu;
+  sb.nu = b.nu;
+  sb.mu32 = b.mu32;
+  sb.nu32 = b.nu32;
+  sb.ctrl = b.ctrl;
+  HIP_TRY(hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), s));
+  HIP_TRY(launch_setup(sb, s));
+  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc->bad_input)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must be finite and >= 0"));
+  if (!(hc->sum_mu > 0.0) || !(hc->sum_nu > 0.0))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must have positive mass"));
+  if (std::fabs(hc->sum_mu - hc->sum_nu) > 1e-10 * hc->sum_mu)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "unequal masses: sum mu = %.17g, sum nu = %.17g",
+                          hc->sum_mu, hc->sum_nu));
+  // control block: running, no stop, no failure
+  Ctrl c0{};
+  c0.stop_iter = -1;
+  c0.fail_iter = INT32_MAX;
+  c0.last_check = -1;
+  c0.last_err = NAN;
+  *hc = c0;
+  HIP_TRY(hipMemcpyAsync(b.ctrl, hc, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  if (o.err_history)
+    HIP_TRY(hipMemsetAsync(o.err_history, 0xFF, sizeof(double) * (size_t(o.itr_max) + 1), s));
+  const unsigned gf = unsigned((n + 255) / 256);
+  if (dt == FS1_F64) {
+    k_fill2<double><<<gf, 256, 0, s>>>(static_cast<double*>(b.vF), static_cast<double*>(b.vG[0]),
+                                       n, 1.0 / double(n));
+  } else {
+    k_fill2<float><<<gf, 256, 0, s>>>(static_cast<float*>(b.vF), static_cast<float*>(b.vG[0]), n,
+                                      float(1.0 / double(n)));
+  }
+  HIP_TRY(hipGetLastError());
+  // the ctrl upload reads the pinned mirror: finish it before the host reuses it
+  HIP_TRY(hipStreamSynchronize(s));
+
+  const Grid2 g = make_grid2(n1, n2, h1, h2, eps);
+  // small grids: every iteration in one workgroup; it leaves psi in buffer 0
+  const size_t lds = (o.flags & FS1_FLAG_NO_RESIDENT) ? 0 : res2d_lds(n1, n2, dt);
+  bool resident = false;
+  if (lds > 0) {
+    Res2Args ra{};
+    ra.mu = b.mu;
+    ra.nu = b.nu;
+    ra.mu32 = b.mu32;
+    ra.nu32 = b.nu32;
+    ra.vF = b.vF;
+    ra.vG = b.vG[0];
+    ra.ctrl = b.ctrl;
+    ra.err_hist = o.err_history;
+    ra.n1 = int(n1);
+    ra.n2 = int(n2);
+    ra.itr_max = o.itr_max;
+    ra.check_every = o.check_every;
+    ra.tol = tol;
+    ra.lam1 = std::exp(-h1 / eps);
+    ra.lam2 = std::exp(-h2 / eps);
+    const hipError_t e = dt == FS1_F64 ? launch_res2d<double>(ra, lds, s)
+                                       : launch_res2d<float>(ra, lds, s);
+    if (e != hipSuccess) return finish(hip_fail(e, "2-D one-workgroup solve"));
+    resident = true;
+  }
+  // Algorithm 2: while l < itr_max and err(l) > tol
+  int l = resident ? o.itr_max : 0;
+  bool stopped = resident;
+  while (l < o.itr_max && !stopped) {
+    const int l_end = std::min(o.itr_max, l + o.sync_every);
+    for (; l < l_end; ++l) {
+      const int check = (l % o.check_every) == 0;
+      HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::psi_half(g, b, l, check, s); }));
+      if (check) {
+        k_decide2<<<1, 256, 0, s>>>(b.part, int(g.ax2.nlines), b.ctrl, tol, l, o.err_history);
+        HIP_TRY(hipGetLastError());
+      }
+      HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::phi_half(g, b, l, s); }));
+    }
+    HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stopped = hc->done != 0 || hc->fail != 0;
+  }
+  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hc->fail) {
+    out->iterations = hc->fail_iter;
+    out->converged = 0;
+    return finish(set_err(FS1_ERR_NONFINITE,
+                          "a scaling became non-finite at iteration %d (abnormal termination)",
+                          hc->fail_iter + 1));
+  }
+  const int l_final = (hc->done && hc->stop_iter >= 0) ? hc->stop_iter : o.itr_max;
+  const int gbuf = resident ? 0 : (l_final & 1);
+  HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::finalize(g, b, gbuf, h1, h2, s); }));
+  if (o.flags & FS1_FLAG_POTENTIALS) {
+    if (dt == FS1_F64) {
+      k_log2<double><<<gf, 256, 0, s>>>(static_cast<const double*>(b.vF),
+                                        static_cast<const double*>(b.vG[gbuf]), n,
+                                        o.potentials_out);
+    } else {
+      k_log2<float><<<gf, 256, 0, s>>>(static_cast<const float*>(b.vF),
+                                       static_cast<const float*>(b.vG[gbuf]), n,
+                                       o.potentials_out);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  double sums[4];
+  HIP_TRY(hipMemcpyAsync(sums, b.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->marginal_err = sums[0];
+  out->mu_err = sums[1];
+  out->w1 = sums[2] + sums[3];
+  out->iterations = l_final;
+  out->converged = !(sums[0] > tol) ? 1 : 0;
+  return finish((std::isfinite(out->w1) && std::isfinite(out->marginal_err)) ? FS1_OK
+                                                                             : FS1_ERR_NONFINITE);
+}
+
+}  // namespace fs1

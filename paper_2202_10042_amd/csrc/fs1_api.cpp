@@ -787,6 +787,33 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   return finish(FS1_OK);
 }
 
+int fs1_kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
+                    double h2, double eps, int dt) {
+  return fs1::kv_apply_2d(ctx, x, y, n1, n2, h1, h2, eps, dt);
+}
+
+int fs1_solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2,
+                 double h1, double h2, double eps, double tol, const fs1_opts* opts_in,
+                 fs1_result* out) {
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  if (!out) return set_err(FS1_ERR_INVALID_ARG, "null result pointer");
+  std::memset(out, 0, sizeof(*out));
+  out->w1 = NAN;
+  out->marginal_err = NAN;
+  out->mu_err = NAN;
+  fs1_opts o;
+  fs1_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (o.itr_max < 0) o.itr_max = 10000;
+  if (o.check_every < 1) o.check_every = 1;
+  if (o.sync_every < 1) o.sync_every = 16;
+  if ((mu && !aligned16(mu)) || (nu && !aligned16(nu))) {
+    out->status = set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
+    return out->status;
+  }
+  return fs1::solve_2d(ctx, mu, nu, n1, n2, h1, h2, eps, tol, o, out);
+}
+
 int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
                       const int64_t* offsets, int32_t B, const double* eps, const double* tol,
                       const fs1_opts* opts, fs1_result* out) {

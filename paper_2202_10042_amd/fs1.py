@@ -43,7 +43,8 @@ EXPORTS = (
     "fs1_ctx_kernel_stats", "fs1_last_error", "fs1_version", "fs1_kv_apply",
     "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
-    "fs1_server_step", "fs1_server_poll", "fs1_server_get_info",
+    "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
+    "fs1_solve_2d",
 )
 
 
@@ -172,6 +173,11 @@ def load(path: str = LIB_PATH):
     lib.fs1_server_poll.restype = ctypes.c_int
     lib.fs1_server_get_info.argtypes = [vp, ctypes.POINTER(ServerInfo)]
     lib.fs1_server_get_info.restype = ctypes.c_int
+    lib.fs1_kv_apply_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, ctypes.c_int]
+    lib.fs1_kv_apply_2d.restype = ctypes.c_int
+    lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(CResult)]
+    lib.fs1_solve_2d.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -323,6 +329,60 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
     r = CResult()
     st = load().fs1_solve(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps), float(tol),
                           ctypes.byref(o), ctypes.byref(r))
+    if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
+            raise_on_error and st != FS1_OK):
+        raise Fs1Error(st, last_error())
+    res = Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), st)
+    if pot is not None and st == FS1_OK:
+        res.F, res.G = pot[:n], pot[n:]
+    if hist is not None:
+        res.err_history = hist
+    return res
+
+
+def fs1_kv_apply_2d(x, n1: int, n2: int, h1: float, h2: float, eps: float, out=None,
+                    ctx: Optional[Context] = None):
+    """y = K x on an n1 x n2 grid (column-major flattening, entry (i, j) at
+    i + n1 j), K = exp(-(|i-k| h1 + |j-l| h2)/eps)  (float64 or float32)."""
+    import torch
+    ctx = ctx or default_context()
+    if x.numel() != n1 * n2:
+        raise ValueError("x must hold n1 * n2 entries")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(load().fs1_kv_apply_2d(ctx.handle, _dev(x, "x"), _dev(out, "out"), int(n1), int(n2),
+                                  float(h1), float(h2), float(eps), _dtype_code(x)))
+    return out
+
+
+def fs1_solve_2d(mu, nu, n1: int, n2: int, h1: float, h2: float, eps: float, tol: float,
+                 itr_max: int = 10000, dtype: str = "f64", check_every: int = 1,
+                 sync_every: int = 16, potentials: bool = False, err_history: bool = False,
+                 solver: str = "auto", ctx: Optional[Context] = None,
+                 raise_on_error: bool = False) -> Result:
+    """Algorithm 2 (2-D FS-1) on device float64 marginals of n1 * n2 entries
+    (column-major), plain domain.  solver: "auto" (one workgroup for small
+    grids, n1 n2 <= 4096 and n1 + n2 <= 128, else one launch per line pass)
+    or "lines" (always the per-line launches)."""
+    import torch
+    ctx = ctx or default_context()
+    n = n1 * n2
+    if mu.numel() != n or nu.numel() != n:
+        raise ValueError("mu and nu must hold n1 * n2 entries")
+    o = make_opts(None, itr_max, dtype, "plain", check_every, sync_every)
+    o.flags |= {"auto": 0, "lines": FS1_FLAG_NO_RESIDENT}[solver]
+    pot = hist = None
+    if potentials:
+        pot = torch.empty(2 * n, dtype=torch.float64, device=mu.device)
+        o.flags |= FS1_FLAG_POTENTIALS
+        o.potentials_out = pot.data_ptr()
+    if err_history:
+        hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)
+        o.err_history = hist.data_ptr()
+    r = CResult()
+    st = load().fs1_solve_2d(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), int(n1), int(n2),
+                             float(h1), float(h2), float(eps), float(tol), ctypes.byref(o),
+                             ctypes.byref(r))
     if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
             raise_on_error and st != FS1_OK):
         raise Fs1Error(st, last_error())

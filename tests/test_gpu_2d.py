@@ -1,0 +1,249 @@
+"""GPU parity of the two-dimensional path (Sec. 4, Algorithm 2) against the
+2-D oracle, through the C ABI (fs1_kv_apply_2d, fs1_solve_2d).
+
+Grids are n1 x n2 in column-major order (entry (i, j) at i + n1 j).
+Tolerances:
+  * kv_apply_2d on positive inputs, elementwise relative: 256 u (two 1-D
+    passes, each within the 1-D bound of 64 u, plus rounding of the order of
+    summation), u = 2^-53 or 2^-24;
+  * solve, binary64, fixed iteration count: |dW|/W <= 1e-10, ln phi and ln psi
+    within 1e-9 of the oracle's on entries with positive marginal, marginal
+    error 1e-6 relative;
+  * binary32 scans against the binary64 oracle: |dW|/W <= 1e-5;
+  * the printed plan differences of Table 3: ||P_gpu - P_dense||_F within
+    1e-11 ||P||_F (rounding level; printed beside the paper's figure).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_10042_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def _fs1():
+    from paper_2202_10042_amd import fs1
+    return fs1
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a, dtype=None):
+    return torch.tensor(np.asarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n1,n2,h1,h2,eps", [
+    (1, 1, 0.1, 0.1, 0.5), (1, 300, 0.01, 0.02, 0.05), (300, 1, 0.02, 0.01, 0.05),
+    (37, 53, 0.01, 0.02, 0.05), (129, 64, 1.0, 1.0, 0.5), (2048, 3, 0.001, 0.2, 0.01),
+    (2049, 5, 0.001, 0.2, 0.01), (5, 3000, 0.3, 0.0005, 0.01), (700, 900, 0.002, 0.001, 0.01)])
+def test_kv_apply_2d(dtype, n1, n2, h1, h2, eps):
+    fs1 = _fs1()
+    rng = np.random.default_rng(n1 * 7 + n2)
+    x = rng.random(n1 * n2) + 1e-3
+    _say(f"kv2 {dtype} {n1}x{n2}")
+    ref = oracle.kv2_dense(x, n1, n2, h1, h2, eps) if n1 * n2 <= 20000 else \
+        oracle.kv2_fs1(x, n1, n2, h1, h2, eps)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    xin = dev(x, tdt)
+    y = fs1.fs1_kv_apply_2d(xin, n1, n2, h1, h2, eps).double().cpu().numpy()
+    # binary32: compare with the product of the rounded input
+    if dtype == "f32":
+        xr = xin.double().cpu().numpy()
+        ref = oracle.kv2_dense(xr, n1, n2, h1, h2, eps) if n1 * n2 <= 20000 else \
+            oracle.kv2_fs1(xr, n1, n2, h1, h2, eps)
+    u = U64 if dtype == "f64" else U32
+    rel = np.max(np.abs(y - ref) / ref)
+    assert rel <= 256 * u, rel
+
+
+def test_kv_apply_2d_tiny_lambda():
+    # h/eps = 100 along both axes (the Table 3 setting): lambda = e^-100, in
+    # binary64 the neighbours contribute e^-100 relative and beyond 7 cells
+    # nothing representable
+    fs1 = _fs1()
+    n1, n2 = 40, 30
+    x = np.random.default_rng(1).random(n1 * n2) + 0.5
+    y = fs1.fs1_kv_apply_2d(dev(x), n1, n2, 1.0, 1.0, 0.01).cpu().numpy()
+    ref = oracle.kv2_dense(x, n1, n2, 1.0, 1.0, 0.01)
+    assert np.max(np.abs(y - ref) / ref) <= 256 * U64
+
+
+def _pot_close(got, ref_lin, mask, atol):
+    g = got[mask]
+    r = np.log(ref_lin[mask])
+    assert np.max(np.abs(g - r)) <= atol, float(np.max(np.abs(g - r)))
+
+
+SOLVERS = ["auto", "lines"]  # one workgroup (n1 n2 <= 8192) / one launch per line pass
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("n1,n2,h1,h2,eps,its,dense", [
+    (13, 7, 0.1, 0.15, 0.05, 30, True), (1, 40, 0.5, 0.02, 0.03, 25, True),
+    (40, 1, 0.02, 0.5, 0.03, 25, True), (24, 31, 1.0 / 24, 1.0 / 31, 0.01, 60, True),
+    (150, 90, 1.0 / 150, 1.0 / 90, 5e-3, 40, False), (300, 200, 0.003, 0.005, 0.01, 20, False),
+    (2100, 4, 5e-4, 0.3, 0.05, 10, False)])
+def test_solve_2d_fixed_iterations(n1, n2, h1, h2, eps, its, dense, solver):
+    fs1 = _fs1()
+    mu, nu = inputs.product_pair_2d(n1, n2, 3, n1 + n2)
+    # break the product structure so the test does not only see 1-D problems
+    rng = np.random.default_rng(n1 * n2)
+    mu = mu * (1.0 + 0.3 * rng.random(mu.size))
+    nu = nu * (1.0 + 0.3 * rng.random(nu.size))
+    mu /= mu.sum()
+    nu /= nu.sum()
+    _say(f"solve2d {n1}x{n2} its={its}")
+    f = oracle.sinkhorn2_dense if dense else oracle.fs1_2d
+    ref = f(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its, potentials=True,
+                         solver=solver)
+    assert r.status == 0 and r.iterations == its == ref.iterations
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-13)
+    assert r.mu_err <= 1e-12
+    _pot_close(r.F.cpu().numpy(), ref.a, mu > 0, 1e-9)
+    _pot_close(r.G.cpu().numpy(), ref.b, nu > 0, 1e-9)
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("n", [10, 20, 40, 80, 160])
+def test_table3_workload(n, solver):
+    """Sec. 5.3, Table 3: uniform random marginals on an n x n grid, h = 1,
+    eps = 0.01, 1000 iterations, plain binary64."""
+    fs1 = _fs1()
+    g = json.load(open(GOLDEN))
+    h, eps, its = g["table3_h"], g["table3_eps"], g["table3_iterations"]
+    u, v = inputs.paper_uniform_2d(n, n, 0)
+    _say(f"table3 n={n}: oracle")
+    ref = (oracle.sinkhorn2_dense if n <= 40 else oracle.fs1_2d)(u, v, n, n, h, h, eps, tol=0.0,
+                                                                  itr_max=its)
+    assert ref.status == 0
+    _say(f"table3 n={n}: gpu")
+    r = fs1.fs1_solve_2d(dev(u), dev(v), n, n, h, h, eps, 0.0, itr_max=its, potentials=True,
+                         solver=solver)
+    assert r.status == 0 and r.iterations == its
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+    F, G = r.F.cpu().numpy(), r.G.cpu().numpy()
+    _pot_close(F, ref.a, u > 0, 1e-9)
+    _pot_close(G, ref.b, v > 0, 1e-9)
+    if n <= 80:
+        P = oracle.plan2(np.exp(F), np.exp(G), n, n, h, h, eps)
+        Pref = oracle.plan2(ref.a, ref.b, n, n, h, h, eps)
+        d = float(np.linalg.norm(P - Pref))
+        nP = float(np.linalg.norm(Pref))
+        del P, Pref
+        _say(f"table3 n={n} {solver}: ||dP||_F = {d:.3e} (paper prints "
+             f"{g['table3_plan_diff'][str(n)]:.2e} for FS-1 against dense), ||P||_F = {nP:.3e}")
+        assert d <= 1e-11 * nP
+
+
+def test_solve_2d_product_marginals_match_1d_gpu():
+    # mu = mu1 (x) mu2, nu = nu1 (x) nu2: W_2D = W_1D(axis 1) + W_1D(axis 2)
+    # at every iteration count (the iterates are products of the 1-D ones)
+    fs1 = _fs1()
+    n1, n2 = 1500, 700
+    h1, h2, eps = 1.0 / n1, 1.0 / n2, 3e-3
+    m1, v1 = inputs.mixture_pair(n1, 3, 21)
+    m2, v2 = inputs.mixture_pair(n2, 4, 23)
+    mu = np.outer(m2, m1).reshape(-1)
+    nu = np.outer(v2, v1).reshape(-1)
+    for its in (3, 30):
+        a = fs1.fs1_solve(dev(m1), dev(v1), eps, 0.0, h=h1, itr_max=its, domain="plain")
+        b = fs1.fs1_solve(dev(m2), dev(v2), eps, 0.0, h=h2, itr_max=its, domain="plain")
+        r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its)
+        assert r.status == 0 and a.status == 0 and b.status == 0
+        assert r.w1 == pytest.approx(a.w1 + b.w1, rel=1e-10)
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_to_tolerance_and_history(solver):
+    fs1 = _fs1()
+    n1, n2, h1, h2, eps = 30, 25, 1.0 / 30, 1.0 / 25, 0.02
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 3)
+    ref = oracle.sinkhorn2_dense(mu, nu, n1, n2, h1, h2, eps, tol=1e-9, itr_max=3000)
+    assert ref.converged
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 1e-9, itr_max=3000, solver=solver)
+    assert r.status == 0 and r.converged and abs(r.iterations - ref.iterations) <= 1
+    assert r.marginal_err <= 1e-9
+    # the same stop whatever the host polling interval; check_every k stops at
+    # the first multiple of k with err <= tol
+    for se in (1, 7, 64):
+        s = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 1e-9, itr_max=3000,
+                             sync_every=se, solver=solver)
+        assert s.iterations == r.iterations and s.w1 == r.w1
+    c = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 1e-9, itr_max=3000,
+                         check_every=5, solver=solver)
+    assert c.iterations % 5 == 0 and r.iterations <= c.iterations < r.iterations + 5
+    h = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=9,
+                         err_history=True, solver=solver).err_history.cpu().numpy()
+    for l in range(9):
+        o = oracle.sinkhorn2_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=l)
+        assert h[l] == pytest.approx(o.marginal_err, rel=1e-9, abs=1e-15)
+    assert np.isnan(h[9])
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_f32_against_f64_oracle(solver):
+    # plain binary32 holds scalings up to about e^88, which the iteration
+    # exceeds at small eps (they grow like e^(W/eps)): moderate eps here
+    fs1 = _fs1()
+    for n1, n2, eps, its in ((64, 48, 0.1, 50), (700, 300, 0.08, 20)):
+        mu, nu = inputs.product_pair_2d(n1, n2, 3, 5)
+        rng = np.random.default_rng(4)
+        mu = mu * (1 + 0.2 * rng.random(mu.size)); mu /= mu.sum()
+        nu = nu * (1 + 0.2 * rng.random(nu.size)); nu /= nu.sum()
+        h1, h2 = 1.0 / n1, 1.0 / n2
+        ref = oracle.fs1_2d(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+        r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its, dtype="f32",
+                             solver=solver)
+        assert r.status == 0
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_failure_and_arguments(solver):
+    fs1 = _fs1()
+    # Dirac masses far apart at a tiny eps: the plain iteration must terminate
+    # abnormally, as the oracle does
+    n1, n2 = 20, 20
+    mu = np.zeros(n1 * n2)
+    nu = np.zeros(n1 * n2)
+    mu[0] = 1.0
+    nu[n1 * n2 - 1] = 1.0
+    o = oracle.sinkhorn2_dense(mu, nu, n1, n2, 1.0, 1.0, 0.02, tol=0.0, itr_max=5)
+    assert o.status == -2
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, 1.0, 1.0, 0.02, 0.0, itr_max=5, solver=solver)
+    assert r.status == fs1.FS1_ERR_NONFINITE and r.iterations == o.iterations
+    # Dirac masses within reach: exact W after one iteration
+    mu[:] = 0.0
+    nu[:] = 0.0
+    mu[3 + n1 * 4] = 1.0
+    nu[7 + n1 * 2] = 1.0
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, 0.1, 0.2, 0.05, 0.0, itr_max=1, solver=solver)
+    assert r.status == 0 and r.w1 == pytest.approx(4 * 0.1 + 2 * 0.2, rel=1e-13)
+    x = dev(np.full(12, 1.0 / 12))
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve_2d(x, x, 3, 4, 0.1, 0.1, -1.0, 0.0)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve_2d(x, x, 3, 4, 0.0, 0.1, 0.1, 0.0)
+    bad = dev(np.r_[np.full(11, 1.0 / 11), 0.0] * 2)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve_2d(x, bad, 3, 4, 0.1, 0.1, 0.1, 0.0)
+    big = torch.full((8193 * 2,), 1.0 / (8193 * 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve_2d(big, big, 8193, 2, 0.1, 0.1, 0.1, 0.0)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply_2d(big, 2, 8193, 0.1, 0.1, 0.1)
