@@ -91,6 +91,7 @@ def _load():
         "or_fs1": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_fs1_log": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_fs1_absorb": (ctypes.c_int, [i64, p, p, d, d, d, i64, d, p, p, p, p, p]),
         "or_kv2_dense": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
         "or_kv2_fs1": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
         "or_marginal_err2_dense": (d, [i64, i64, p, p, p, d, d, d]),
@@ -267,6 +268,52 @@ def fs1(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
 
 def fs1_log(mu, nu, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
     return _solve("or_fs1_log", mu, nu, h, eps, tol, itr_max)
+
+
+@dataclass
+class AbsorbResult:
+    w1: float
+    marginal_err: float
+    iterations: int
+    status: int
+    converged: bool
+    absorptions: int     # how many times the tau test fired
+    phit: np.ndarray     # scaled vectors and absorbed potentials:
+    psit: np.ndarray     #   phi = e^{alpha/eps} phit, psi = e^{beta/eps} psit
+    alpha: np.ndarray
+    beta: np.ndarray
+
+    @property
+    def F(self) -> np.ndarray:
+        """ln phi = alpha/eps + ln phit."""
+        with np.errstate(divide="ignore"):
+            return self.alpha / self._eps + np.log(self.phit)
+
+    @property
+    def G(self) -> np.ndarray:
+        with np.errstate(divide="ignore"):
+            return self.beta / self._eps + np.log(self.psit)
+
+
+def fs1_absorb(mu, nu, h, eps, tol=0.0, itr_max=1000, tau=1e3) -> AbsorbResult:
+    """Stabilised FS-1 (Sec. 2 and Sec. 3 remarks): absorbed potentials alpha,
+    beta and scaled vectors, absorption whenever max(phit) or max(psit) > tau,
+    the products with the rescaled kernel by the recursions with per-element
+    coefficients that replace lines 5-6 and 10-11 of Algorithm 1."""
+    mu, nu = _f64(mu), _f64(nu)
+    n = mu.size
+    phit, psit, alpha, beta = (np.empty(n) for _ in range(4))
+    res = np.zeros(6)
+    st = _load().or_fs1_absorb(n, _ptr(mu), _ptr(nu), h, eps, tol, int(itr_max), tau,
+                               _ptr(phit), _ptr(psit), _ptr(alpha), _ptr(beta), _ptr(res))
+    if st == -1:
+        raise ValueError("or_fs1_absorb: invalid argument")
+    if st == -4:
+        raise MemoryError("or_fs1_absorb")
+    r = AbsorbResult(float(res[0]), float(res[1]), int(res[2]), int(res[3]), bool(res[4]),
+                     int(res[5]), phit, psit, alpha, beta)
+    r._eps = eps
+    return r
 
 
 def plan_linear(phi, psi, h, eps) -> np.ndarray:

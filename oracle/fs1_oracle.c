@@ -526,6 +526,126 @@ int or_fs1_log(int64_t n, const double *mu, const double *nu, double h, double e
     return st;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Stabilised FS-1 (Sec. 2 and Sec. 3 remarks on log-domain stabilisation).   */
+/* The scalings are kept as phi_i = e^{alpha_i/eps} phit_i and                 */
+/* psi_j = e^{beta_j/eps} psit_j, i.e. the kernel is rescaled to               */
+/*   Kt = diag(e^{alpha/eps}) K diag(e^{beta/eps})                            */
+/* and the iteration runs on (phit, psit).  Whenever the largest entry of     */
+/* phit or psit exceeds tau, both are absorbed:                               */
+/*   alpha += eps ln phit, beta += eps ln psit, phit = psit = 1                */
+/* (the remark writes alpha += ln phi; with K rescaled by e^{alpha/eps} the   */
+/* consistent update carries the factor eps).  Entries that are exactly zero  */
+/* (zero marginal) stay zero and keep their potential.  The products with Kt  */
+/* use the recursions that replace lines 5-6 and 10-11 of Algorithm 1:        */
+/*   r_{i+1} = lambda e^{(beta_{i+1}-beta_i)/eps} r_i                          */
+/*             + e^{(alpha_{i+1}+beta_{i+1})/eps} phit_{i+1}                   */
+/*   s_i     = lambda e^{(beta_i-beta_{i+1})/eps}                              */
+/*             (s_{i+1} + e^{(alpha_{i+1}+beta_{i+1})/eps} phit_{i+1})         */
+/* and the same with alpha and beta exchanged for p, q (Kt psit).  The        */
+/* absorption test runs at the top of every iteration.                         */
+/* ------------------------------------------------------------------------- */
+
+/* y = Kt^T x (side = 0: coefficients from beta, the K^T phi of the psi-half)
+ * or y = Kt x (side = 1: from alpha).  `own` are the potentials of the
+ * output side, `oth` those of the input side: the diagonal factor is
+ * e^{(own_k + oth_k)/eps}. */
+static void kv_absorbed(int64_t n, const double *x, const double *own, const double *oth,
+                        double lam, double eps, double *y) {
+    double *s = (double *)malloc((size_t)n * sizeof(double));
+    if (!s) return;
+    s[n - 1] = 0.0;
+    for (int64_t k = n - 2; k >= 0; --k) {
+        const double d = exp((own[k + 1] + oth[k + 1]) / eps) * x[k + 1];
+        s[k] = lam * exp((own[k] - own[k + 1]) / eps) * (s[k + 1] + d);
+    }
+    double r = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        const double d = exp((own[k] + oth[k]) / eps) * x[k];
+        r = (k == 0) ? d : lam * exp((own[k] - own[k - 1]) / eps) * r + d;
+        y[k] = r + s[k];
+    }
+    free(s);
+}
+
+static double maxabs(int64_t n, const double *v) {
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = fabs(v[i]) > m ? fabs(v[i]) : m;
+    return m;
+}
+
+static void absorb(int64_t n, double *pot, double *v, double eps) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (v[i] > 0.0) {
+            pot[i] += eps * log(v[i]);
+            v[i] = 1.0;
+        }
+    }
+}
+
+/* Algorithm 1 with the stabilisation.  Outputs: phit, psit (length n),
+ * alpha, beta (length n), res as for the other solvers plus res[5] = the
+ * number of absorptions.  The returned W and err are those of the true
+ * scalings phi = e^{alpha/eps} phit, psi = e^{beta/eps} psit. */
+int or_fs1_absorb(int64_t n, const double *mu, const double *nu, double h, double eps,
+                  double tol, int64_t itr_max, double tau, double *phit, double *psit,
+                  double *alpha, double *beta, double *res) {
+    if (n < 1 || !(h > 0) || !(eps > 0) || itr_max < 0 || !(tau > 0)) return OR_ERR_INVALID_ARG;
+    const double lam = exp(-h / eps);
+    double *den = (double *)malloc((size_t)n * sizeof(double));
+    if (!den) return OR_ERR_NO_MEMORY;
+    for (int64_t i = 0; i < n; ++i) {
+        phit[i] = psit[i] = 1.0 / (double)n;
+        alpha[i] = beta[i] = 0.0;
+    }
+    int64_t it = 0, nabs = 0;
+    int st = OR_OK, conv = 0;
+    /* err = sum_j | psit_j (Kt^T phit)_j - nu_j | */
+    kv_absorbed(n, phit, beta, alpha, lam, eps, den);
+    nsum e0 = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) nadd(&e0, fabs(psit[j] * den[j] - nu[j]));
+    double err = nval(&e0);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        if (maxabs(n, phit) > tau || maxabs(n, psit) > tau) {
+            absorb(n, alpha, phit, eps);
+            absorb(n, beta, psit, eps);
+            ++nabs;
+        }
+        kv_absorbed(n, phit, beta, alpha, lam, eps, den);   /* Kt^T phit: r + s */
+        if (divide_update(n, nu, den, psit)) { st = OR_ERR_NONFINITE; break; }
+        kv_absorbed(n, psit, alpha, beta, lam, eps, den);   /* Kt psit: p + q */
+        if (divide_update(n, mu, den, phit)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        kv_absorbed(n, phit, beta, alpha, lam, eps, den);
+        nsum e = {0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) nadd(&e, fabs(psit[j] * den[j] - nu[j]));
+        err = nval(&e);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = NAN;
+    if (st == OR_OK) {
+        /* W = sum_{i,j} phi_i psi_j K_ij |i-j| h, each term formed from its
+         * logarithm ln phit_i + ln psit_j + (alpha_i + beta_j - |i-j| h)/eps
+         * (the factors alone can overflow where their product does not) */
+        nsum acc = {0.0, 0.0};
+        for (int64_t i = 0; i < n; ++i) {
+            if (phit[i] == 0.0) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                if (psit[j] == 0.0 || i == j) continue;
+                const double d = (double)(i > j ? i - j : j - i);
+                nadd(&acc, exp(log(phit[i]) + log(psit[j]) + (alpha[i] + beta[j] - d * h) / eps) *
+                               d * h);
+            }
+        }
+        w = nval(&acc);
+    }
+    pack_result(res, w, err, it, st, conv);
+    res[5] = (double)nabs;
+    free(den);
+    return st;
+}
+
 /* ========================================================================= */
 /* Two dimensions (Sec. 4, Algorithm 2).                                      */
 /* Histograms on an n1 x n2 grid, flattened in column-major order: entry      */

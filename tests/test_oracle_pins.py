@@ -449,3 +449,64 @@ def test_stopping_rule():
     zero = oracle.fs1(mu, nu, h, 0.01, tol=0.0, itr_max=0)
     assert zero.iterations == 0 and zero.w1 == pytest.approx(
         oracle.cost_dense(np.full(n, 1 / n), np.full(n, 1 / n), h, 0.01), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Stabilised FS-1 (Sec. 2 and Sec. 3 remarks): absorbed potentials with a
+# threshold tau.  In exact arithmetic the iterates are those of the plain
+# iteration whatever tau is, so every tau must give the log-domain oracle's
+# result; the stabilisation must let the Ricker pair of Sec. 5.2 run at
+# eps = 1e-3, where the unstabilised iteration terminates abnormally.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("eps,its", [(0.01, 40), (1e-3, 150)])
+def test_absorb_equals_log_for_every_tau(eps, its):
+    n = 250
+    mu, nu = inputs.mixture_pair(n, 3, 6)
+    h = 1.0 / n
+    ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
+    m = nu > 0
+    counts = []
+    for tau in (1e300, 1e3, 10.0, 1.0 + 1e-9):
+        r = oracle.fs1_absorb(mu, nu, h, eps, tol=0.0, itr_max=its, tau=tau)
+        assert r.status == 0 and r.iterations == its
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-12)
+        # (both errors may sit at the rounding floor, ~1e-15)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-8, abs=1e-13)
+        assert np.max(np.abs(r.G[m] - ref.b[m])) <= 1e-9
+        counts.append(r.absorptions)
+    # never for an unreachable threshold, more often the lower the threshold
+    assert counts[0] == 0 < counts[1] <= counts[2] <= counts[3]
+
+
+def test_absorb_runs_where_plain_fails():
+    u, v, dt = inputs.ricker_pair(500)
+    assert oracle.fs1(u, v, dt, 1e-3, tol=0.0, itr_max=500).status == -2
+    a = oracle.fs1_absorb(u, v, dt, 1e-3, tol=0.0, itr_max=500, tau=1e3)
+    lg = oracle.fs1_log(u, v, dt, 1e-3, tol=0.0, itr_max=500)
+    assert a.status == 0 and a.absorptions > 0
+    assert a.w1 == pytest.approx(lg.w1, rel=1e-10)
+    # The threshold form cannot help before anything has been absorbed: Dirac
+    # masses 92 cells apart at h/eps = 10 need lambda^92 = e^-920 in the first
+    # product, which underflows in the recursion (the block-floating log
+    # domain of the GPU path carries it in extended range instead).
+    n, i, j = 100, 3, 95
+    mu, nu = inputs.dirac_pair(n, i, j)
+    h = 1.0 / n
+    assert oracle.fs1_absorb(mu, nu, h, h / 10, tol=0.0, itr_max=3, tau=1.5).status == -2
+    assert oracle.fs1_log(mu, nu, h, h / 10, tol=0.0, itr_max=3).w1 == pytest.approx(
+        abs(i - j) * h, rel=1e-12)
+
+
+def test_absorb_stopping_rule_and_zero_entries():
+    n = 200
+    mu, nu = inputs.mixture_pair(n, 2, 9)
+    mu[10:30] = 0.0
+    nu[150:160] = 0.0
+    mu /= mu.sum()
+    nu /= nu.sum()
+    h = 1.0 / n
+    ref = oracle.sinkhorn_dense(mu, nu, h, 0.01, tol=1e-9, itr_max=5000)
+    r = oracle.fs1_absorb(mu, nu, h, 0.01, tol=1e-9, itr_max=5000, tau=100.0)
+    assert r.status == 0 and r.converged and abs(r.iterations - ref.iterations) <= 1
+    assert np.all(r.phit[10:30] == 0.0) and np.all(np.isfinite(r.alpha))
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-8)
