@@ -59,11 +59,17 @@ typedef enum {
     FS1_PLAIN = 0, /* Algorithm 1 as printed: scalings phi, psi in plain floating
                       point; overflow/underflow ends the solve with
                       FS1_ERR_NONFINITE */
-    FS1_LOG = 1    /* log-domain stabilised FS-1: phi and psi are kept as
+    FS1_LOG = 1,   /* log-domain stabilised FS-1: phi and psi are kept as
                       e^{alpha} * phi~ with the power-of-two part absorbed into a
                       per-run exponent at every half-iteration (the absorption of
                       the Sec. 2 and Sec. 3 remarks, threshold tau -> 0); results
                       equal the plain iteration in exact arithmetic */
+    FS1_ABSORB = 2 /* the stabilised FS-1 of the Sec. 2 and Sec. 3 remarks with
+                      a finite threshold: scaled vectors phit, psit in the
+                      working precision and binary64 potentials alpha, beta
+                      (phi = e^{alpha/eps} phit), both absorbed whenever the
+                      largest scaled entry exceeds opts->tau; fs1_solve only,
+                      grids of at most 1024 runs (one workgroup) */
 } fs1_domain;
 
 typedef struct fs1_ctx fs1_ctx;
@@ -166,9 +172,11 @@ typedef struct {
                              scaling is zero                                        */
     double *err_history;  /* device, itr_max + 1 doubles or NULL: err at every
                              checked iteration l (index l), NaN elsewhere         */
+    double tau;           /* FS1_ABSORB: absorption threshold on the scaled
+                             vectors (> 0, finite; default 1e3)                   */
 } fs1_opts;
 
-/* Fill *o with the defaults (h = 1/n, itr_max 10000, FS1_F64, FS1_PLAIN,
+/* Fill *o with the defaults (h = 1/n, itr_max 10000, FS1_F64, FS1_PLAIN, tau 1e3,
  * check_every 1, sync_every 16, no potentials, no history). */
 int fs1_opts_default(fs1_opts *o);
 
@@ -180,7 +188,7 @@ typedef struct {
     int32_t iterations;   /* completed (psi, phi) pairs                             */
     int32_t converged;    /* 1 if marginal_err <= tol at the returned state         */
     int32_t status;       /* same value as the return code                           */
-    int32_t reserved;
+    int32_t absorptions;  /* FS1_ABSORB: times the tau test fired (else 0)       */
 } fs1_result;
 
 /* mu, nu: device binary64 arrays of n entries, finite, >= 0, not all zero,

@@ -543,6 +543,7 @@ int fs1_opts_default(fs1_opts* o) {
   o->flags = 0;
   o->potentials_out = nullptr;
   o->err_history = nullptr;
+  o->tau = 1e3;
   return FS1_OK;
 }
 
@@ -570,15 +571,22 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     return finish(set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned"));
   if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
     return finish(set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype));
-  if (o.domain != FS1_PLAIN && o.domain != FS1_LOG)
+  if (o.domain != FS1_PLAIN && o.domain != FS1_LOG && o.domain != FS1_ABSORB)
     return finish(set_err(FS1_ERR_INVALID_ARG, "bad domain %d", o.domain));
+  const bool tau_mode = o.domain == FS1_ABSORB;
+  if (tau_mode && !(o.tau > 0.0 && std::isfinite(o.tau)))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "tau must be finite and > 0"));
+  if (tau_mode && (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT)))
+    return finish(set_err(FS1_ERR_INVALID_ARG,
+                          "the absorption variant runs in the one-workgroup solver only"));
   if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
   if ((o.flags & 1) && !o.potentials_out)
     return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
   int st = check_h_eps(n, h, eps);
   if (st) return finish(st);
 
-  const bool absorb = o.domain == FS1_LOG;
+  // the threshold variant stores its final state in the log domain's layout
+  const bool absorb = o.domain == FS1_LOG || o.domain == FS1_ABSORB;
   const int dt = o.dtype;
   const size_t es = dt == FS1_F64 ? 8 : 4;
   int R = pick_run_length(dt, absorb, h / eps);
@@ -588,6 +596,10 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
                      : resident_run_length(n, R);
   if (rr > 0) R = rr;
   const int res_threads = rr > 0 ? resident_threads(n, R) : 0;
+  if (tau_mode && res_threads == 0)
+    return finish(set_err(FS1_ERR_INVALID_ARG,
+                          "the absorption variant needs n <= 1024 runs (n = %lld, run %d)",
+                          (long long)n, R));
   // the fused one-launch-per-half path picks its own run length where it applies
   if (res_threads == 0 && absorb && !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
     const int rf = fused_run_length(dt, h / eps, n);
@@ -645,6 +657,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   b.mu = mu64;
   b.nu = nu64;
   b.err_hist = o.err_history;
+  b.tau = tau_mode ? o.tau : 0.0;
+  b.inv_eps = 1.0 / eps;
   hipStream_t s = ctx->stream;
   Ctrl* hc = ctx->hctrl;
 
@@ -781,6 +795,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   out->mu_err = hc->mu_err;
   out->iterations = l_final;
   out->converged = !(hc->err_final > tol) ? 1 : 0;
+  out->absorptions = tau_mode ? hc->absorptions : 0;
   if (!std::isfinite(hc->w1) || !std::isfinite(hc->err_final)) {
     return finish(set_err(FS1_ERR_NONFINITE, "non-finite cost or marginal error"));
   }

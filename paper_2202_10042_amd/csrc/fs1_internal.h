@@ -89,7 +89,7 @@ struct Ctrl {
   int barrier_timeout;  // persistent solve: a grid barrier wait gave up
   int iters_done;    // persistent solve: completed iterations at exit
   int fail_half[2];  // persistent solve: failure seen in a psi-half [0] / phi-half [1]
-  int pad;
+  int absorptions;   // threshold stabilisation: how many times the tau test fired
   double last_err;   // err at last_check
   double w1;         // transport cost (finalisation)
   double err_final;  // nu-side marginal error (finalisation)
@@ -147,6 +147,8 @@ struct SolveBufs {
   double* part2;      // second partial array (mu-side error)
   Ctrl* ctrl;
   double* err_hist;   // optional (itr_max + 1)
+  double tau;         // > 0: the threshold-absorption variant (resident solver)
+  double inv_eps;     // 1 / eps
 };
 
 // Resident solve: the whole solve in one workgroup and one launch, for n <=

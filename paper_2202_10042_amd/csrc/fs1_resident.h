@@ -165,4 +165,156 @@ __device__ __forceinline__ ResidentEnd resident_iterate(T (&ph)[R], int& eph, T 
   return end;
 }
 
+// ---------------------------------------------------------------------------
+// The threshold form of the stabilisation (Sec. 2 and Sec. 3 remarks): the
+// scalings are phi = e^{alpha/eps} phit and psi = e^{beta/eps} psit with
+// binary64 potentials and scaled vectors in T; whenever the largest scaled
+// entry exceeds tau both vectors are absorbed (alpha += eps ln phit, phit = 1;
+// zero entries stay zero).  A product with the rescaled kernel
+// diag(e^{alpha/eps}) K diag(e^{beta/eps}) is the product of K with
+// e^{pot/eps} v, which each run packs into its shared exponent; the run
+// recursions then cover the coefficients lambda e^{(beta_{i+1}-beta_i)/eps} of
+// the remark exactly.
+// ---------------------------------------------------------------------------
+
+// x_j 2^E = v_j e^{pot_j / eps} over this thread's run (E shared by the run;
+// 0 for a run of zeros)
+template <typename T, int R>
+__device__ __forceinline__ int tau_pack(const T (&v)[R], const double (&pot)[R], double inv_eps,
+                                        T (&x)[R]) {
+  double m[R];
+  int k[R];
+  int E = kExpZero;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const double t = pot[j] * inv_eps * kLog2E;
+    const double fl = floor(t);
+    k[j] = int(fl);
+    m[j] = double(v[j]) * exp2(t - fl);
+    if (v[j] > T(0)) E = max(E, k[j]);
+  }
+  if (E == kExpZero) E = 0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = (v[j] > T(0)) ? T(ldexp(m[j], k[j] - E)) : T(0);
+  return E;
+}
+
+// 2^(u) * a for a binary64 a and a real exponent u (u may exceed the range of
+// 2^u in binary64 while the product does not)
+__device__ __forceinline__ double scale2(double a, double u) {
+  const double fl = floor(u);
+  return ldexp(a * exp2(u - fl), int(fl));
+}
+
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) r = fmax(r, sh[i]);
+  __syncthreads();
+  return r;  // in every thread
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void tau_absorb(T (&v)[R], double (&pot)[R], double eps) {
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (v[j] > T(0)) {
+      pot[j] += eps * log(double(v[j]));
+      v[j] = T(1);
+    }
+}
+
+// v_j = marg_j / (e^{pot_j/eps} y_j 2^eref), formed in binary64
+template <typename T, int R>
+__device__ __forceinline__ void tau_update(const T (&mg)[R], const T (&y)[R], int eref,
+                                           const double (&pot)[R], double inv_eps, T (&v)[R],
+                                           bool& bad) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (mg[j] == T(0)) {
+      v[j] = T(0);
+      continue;
+    }
+    const double q = scale2(double(mg[j]) / double(y[j]), -(double(eref) + pot[j] * inv_eps * kLog2E));
+    v[j] = T(q);
+    bad |= !isfinite(v[j]);
+  }
+}
+
+// Algorithm 1 with the threshold stabilisation, from (pt, al), (qt, be);
+// the absorption test runs at the top of every iteration.  On return the
+// state is the one Algorithm 1 returns; *nabs counts the absorptions.
+template <typename T, int R, int NT, typename OnCheck>
+__device__ __forceinline__ ResidentEnd resident_iterate_tau(
+    T (&pt)[R], double (&al)[R], T (&qt)[R], double (&be)[R], const T (&mu)[R], const T (&nu)[R],
+    const double* nu64, const ScanConsts& k, double tol, double tau, double eps, int itr_max,
+    int check_every, ResidentLds<T, NT / kWave>& S, OnCheck on_check, int* nabs) {
+  constexpr int NW = NT / kWave;
+  const double inv_eps = 1.0 / eps;
+  const Lam<T> L = lam_of<T>(k);
+  Dec<T> dec[7];
+  lane_decays<T>(k, dec);
+  const Dec<T> step = step_decay<T>(k);
+  ResidentEnd end{0, -1, -1};
+  T x[R], y[R];
+  int l = 0, na = 0;
+  for (; l < itr_max; ++l) {
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) mx = fmax(mx, fmax(fabs(double(pt[j])), fabs(double(qt[j]))));
+    if (block_max<NW>(mx, S.red) > tau) {
+      tau_absorb<T, R>(pt, al, eps);
+      tau_absorb<T, R>(qt, be, eps);
+      ++na;
+    }
+    // psi-half: Kt^T phit = e^{beta/eps} K (e^{alpha/eps} phit)
+    int E = tau_pack<T, R>(pt, al, inv_eps, x);
+    int eref = res_apply<T, R, true, NW>(x, E, L, dec, step, S.sh, y);
+    if ((l % check_every) == 0) {
+      double nv[R];
+      if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) nv[j] = double(nu[j]);
+      } else {
+        res_load<double, R>(nu64, 0, nv);
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        s += fabs(scale2(double(qt[j]) * double(y[j]), double(eref) + be[j] * inv_eps * kLog2E) -
+                  nv[j]);
+      const double tot = block_sum<NW>(s, S.red);
+      if (threadIdx.x == 0) {
+        on_check(l, tot);
+        S.stop = !(tot > tol);
+      }
+      __syncthreads();
+      if (S.stop) {
+        end.stop_iter = l;
+        break;
+      }
+    }
+    bool bad = false;
+    tau_update<T, R>(nu, y, eref, be, inv_eps, qt, bad);
+    // phi-half: Kt psit = e^{alpha/eps} K (e^{beta/eps} psit)
+    E = tau_pack<T, R>(qt, be, inv_eps, x);
+    eref = res_apply<T, R, true, NW>(x, E, L, dec, step, S.sh, y);
+    tau_update<T, R>(mu, y, eref, al, inv_eps, pt, bad);
+    if (__syncthreads_or(bad ? 1 : 0)) {
+      end.fail_iter = l;
+      break;
+    }
+  }
+  end.l = l;
+  *nabs = na;
+  return end;
+}
+
 }  // namespace fs1

@@ -76,6 +76,70 @@ __global__ __launch_bounds__(NT) void k_resident(ResidentArgs a, ScanConsts k) {
   }
 }
 
+// The threshold form of the stabilisation (fs1_resident.h): the state enters
+// as the plain iteration's initial vectors (exponents 0, potentials 0) and
+// leaves in the log domain's layout (per-run exponents) for the common
+// finalisation.
+template <typename T, int R, int NT>
+__global__ __launch_bounds__(NT) void k_resident_tau(ResidentArgs a, ScanConsts k, double tau,
+                                                     double eps) {
+  __shared__ ResidentLds<T, NT / kWave> S;
+  const int t = threadIdx.x;
+  const int64_t base = int64_t(t) * R;
+  T pt[R], qt[R], mu[R], nu[R];
+  double al[R], be[R];
+  res_load<T, R>(static_cast<const T*>(a.vF), base, pt);
+  res_load<T, R>(static_cast<const T*>(a.vG), base, qt);
+  const int e0f = a.eF[t], e0g = a.eG[t];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    pt[j] = ldx(pt[j], e0f);
+    qt[j] = ldx(qt[j], e0g);
+    al[j] = 0.0;
+    be[j] = 0.0;
+  }
+  if constexpr (sizeof(T) == 8) {
+    res_load<T, R>(reinterpret_cast<const T*>(a.mu), base, mu);
+    res_load<T, R>(reinterpret_cast<const T*>(a.nu), base, nu);
+  } else {
+    res_load<T, R>(reinterpret_cast<const T*>(a.mu32), base, mu);
+    res_load<T, R>(reinterpret_cast<const T*>(a.nu32), base, nu);
+  }
+  Ctrl* ctrl = a.ctrl;
+  double* hist = a.err_hist;
+  int nabs = 0;
+  const ResidentEnd end = resident_iterate_tau<T, R, NT>(
+      pt, al, qt, be, mu, nu, a.nu + base, k, a.tol, tau, eps, a.itr_max, a.check_every, S,
+      [&](int l, double err) {
+        ctrl->last_err = err;
+        ctrl->last_check = l;
+        if (hist) hist[l] = err;
+      },
+      &nabs);
+  // final state in the log domain's layout: each run's values e^{pot/eps} v
+  // with one shared exponent
+  T x[R];
+  const int ef = tau_pack<T, R>(pt, al, 1.0 / eps, x);
+  res_store<T, R>(static_cast<T*>(a.vF), base, x);
+  a.eF[t] = ef;
+  const int eg = tau_pack<T, R>(qt, be, 1.0 / eps, x);
+  res_store<T, R>(static_cast<T*>(a.vG), base, x);
+  a.eG[t] = eg;
+  if (t == 0) {
+    ctrl->iters_done = (end.stop_iter >= 0) ? end.stop_iter : end.l;
+    ctrl->absorptions = nabs;
+    if (end.stop_iter >= 0) {
+      ctrl->done = 1;
+      ctrl->stop_iter = end.stop_iter;
+    }
+    if (end.fail_iter >= 0) {
+      ctrl->done = 1;
+      ctrl->fail = 1;
+      ctrl->fail_iter = end.fail_iter;
+    }
+  }
+}
+
 template <typename T, int R, bool ABSORB>
 hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,
                       double tol, hipStream_t s) {
@@ -94,11 +158,19 @@ hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int 
   a.check_every = check_every;
   a.tol = tol;
   const int nt = resident_threads(b.n, R);
+  const bool tau_mode = b.tau > 0.0;
+  const double eps = 1.0 / b.inv_eps;
   if (nt == 256) {
-    k_resident<T, R, ABSORB, 256><<<1, 256, 0, s>>>(a, k);
+    if (tau_mode && ABSORB)
+      k_resident_tau<T, R, 256><<<1, 256, 0, s>>>(a, k, b.tau, eps);
+    else
+      k_resident<T, R, ABSORB, 256><<<1, 256, 0, s>>>(a, k);
   } else if constexpr (R <= 8) {
     if (nt != 1024) return hipErrorInvalidValue;
-    k_resident<T, R, ABSORB, 1024><<<1, 1024, 0, s>>>(a, k);
+    if (tau_mode && ABSORB)
+      k_resident_tau<T, R, 1024><<<1, 1024, 0, s>>>(a, k, b.tau, eps);
+    else
+      k_resident<T, R, ABSORB, 1024><<<1, 1024, 0, s>>>(a, k);
   } else {
     return hipErrorInvalidValue;
   }

@@ -31,6 +31,7 @@ FS1_F64 = 0
 FS1_F32 = 1
 FS1_PLAIN = 0
 FS1_LOG = 1
+FS1_ABSORB = 2
 FS1_FLAG_POTENTIALS = 1
 FS1_FLAG_GENERAL = 2
 FS1_FLAG_PERSISTENT = 4
@@ -65,6 +66,7 @@ class Opts(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("potentials_out", ctypes.c_void_p),
         ("err_history", ctypes.c_void_p),
+        ("tau", ctypes.c_double),
     ]
 
 
@@ -76,7 +78,7 @@ class CResult(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("converged", ctypes.c_int32),
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("absorptions", ctypes.c_int32),
     ]
 
 
@@ -117,6 +119,7 @@ class Result:
     F: Optional[object] = None        # torch tensor ln(phi) when requested
     G: Optional[object] = None        # torch tensor ln(psi) when requested
     err_history: Optional[object] = None
+    absorptions: int = 0              # domain "absorb": times the tau test fired
 
 
 _lib = None
@@ -292,7 +295,7 @@ def make_opts(h: Optional[float] = None, itr_max: int = 10000, dtype: str = "f64
     o.h = float(h) if h else 0.0
     o.itr_max = int(itr_max)
     o.dtype = {"f64": FS1_F64, "f32": FS1_F32}[dtype]
-    o.domain = {"plain": FS1_PLAIN, "log": FS1_LOG}[domain]
+    o.domain = {"plain": FS1_PLAIN, "log": FS1_LOG, "absorb": FS1_ABSORB}[domain]
     o.check_every = int(check_every)
     o.sync_every = int(sync_every)
     return o
@@ -302,9 +305,12 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
               dtype: str = "f64", domain: str = "plain", check_every: int = 1,
               sync_every: int = 16, potentials: bool = False, err_history: bool = False,
               solver: str = "auto", ctx: Optional[Context] = None,
-              raise_on_error: bool = False) -> Result:
+              raise_on_error: bool = False, tau: float = 1e3) -> Result:
     """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
 
+    domain: "plain" (Algorithm 1 as printed), "log" (stabilised, absorption
+    at every half-iteration) or "absorb" (the stabilisation with threshold
+    tau; grids of at most 1024 runs).
     solver: "auto" (the whole solve in one workgroup and one launch when
     n <= 1024 R, else fused one-launch-per-half kernels when they apply),
     "fused" (as "auto" without the one-workgroup solver), "general"
@@ -316,6 +322,7 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
     if nu.numel() != n:
         raise ValueError("mu and nu must have the same length")
     o = make_opts(h, itr_max, dtype, domain, check_every, sync_every)
+    o.tau = float(tau)
     o.flags |= {"auto": 0, "fused": FS1_FLAG_NO_RESIDENT, "general": FS1_FLAG_GENERAL,
                 "persistent": FS1_FLAG_PERSISTENT}[solver]
     pot = hist = None
@@ -333,6 +340,7 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
             raise_on_error and st != FS1_OK):
         raise Fs1Error(st, last_error())
     res = Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), st)
+    res.absorptions = int(r.absorptions)
     if pot is not None and st == FS1_OK:
         res.F, res.G = pot[:n], pot[n:]
     if hist is not None:

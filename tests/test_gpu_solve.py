@@ -316,3 +316,65 @@ def test_solve_two_level_carries_general_path(dtype):
     r2 = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="log")
     assert r2.w1 == pytest.approx(ref.w1, rel=1e-10 if dtype == "f64" else 1e-5)
 
+
+
+# ---------------------------------------------------------------------------
+# The threshold form of the stabilisation (domain "absorb": scaled vectors
+# with binary64 potentials, absorption when the largest scaled entry exceeds
+# tau) against the oracle's stabilised FS-1 with the same tau.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,eps,its,tau", [(300, 1e-2, 60, 1e3), (300, 1e-3, 200, 10.0),
+                                          (2049, 1e-3, 120, 1e3), (5000, 5e-4, 80, 1e3)])
+def test_absorb_domain_against_oracle(dtype, n, eps, its, tau):
+    fs1 = _fs1()
+    mu, nu = inputs.mixture_pair(n, 3, n + 1)
+    h = 1.0 / n
+    _say(f"absorb {dtype} n={n} eps={eps} tau={tau}")
+    ref = oracle.fs1_absorb(mu, nu, h, eps, tol=0.0, itr_max=its, tau=tau)
+    assert ref.status == 0
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="absorb",
+                      tau=tau, potentials=True)
+    assert r.status == 0 and r.iterations == its
+    m = nu > 0
+    if dtype == "f64":
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.G[m])) <= 1e-9
+        # the test max > tau is taken on values equal to rounding
+        assert abs(r.absorptions - ref.absorptions) <= 1
+    else:
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.G[m])) <= 1e-4
+    assert ref.absorptions > 0
+
+
+def test_absorb_domain_ricker_and_stop():
+    # Sec. 5.2: at eps = 1e-3 the unstabilised iteration terminates abnormally
+    # and the stabilised one does not
+    fs1 = _fs1()
+    u, v, dt = inputs.ricker_pair(500)
+    p = fs1.fs1_solve(dev(u), dev(v), 1e-3, 0.0, h=dt, itr_max=500, domain="plain")
+    assert p.status == fs1.FS1_ERR_NONFINITE
+    ref = oracle.fs1_absorb(u, v, dt, 1e-3, tol=0.0, itr_max=500, tau=1e3)
+    r = fs1.fs1_solve(dev(u), dev(v), 1e-3, 0.0, h=dt, itr_max=500, domain="absorb", tau=1e3)
+    assert r.status == 0 and r.absorptions > 0
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-9)
+    # to tolerance
+    n = 400
+    mu, nu = inputs.mixture_pair(n, 2, 3)
+    ref = oracle.fs1_absorb(mu, nu, 1.0 / n, 0.01, tol=1e-9, itr_max=5000, tau=100.0)
+    r = fs1.fs1_solve(dev(mu), dev(nu), 0.01, 1e-9, itr_max=5000, domain="absorb", tau=100.0)
+    assert r.status == 0 and r.converged and abs(r.iterations - ref.iterations) <= 1
+
+
+def test_absorb_domain_arguments():
+    fs1 = _fs1()
+    x = dev(np.full(100, 0.01))
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", tau=0.0)
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", solver="general")
+    big = dev(np.full(9000, 1.0 / 9000))
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_solve(big, big, 0.01, 0.0, itr_max=5, domain="absorb")
