@@ -230,8 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   const bool test = MODE == B_PHI && checked;
   if (test) {
     double e = shv;
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
+    e = wave_sum(e);
     if (lane == 0) red[threadIdx.x / kWave] = e;
     __syncthreads();
   }

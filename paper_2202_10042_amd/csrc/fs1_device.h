@@ -279,14 +279,75 @@ __device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const 
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront data movement without the LDS crossbar: DPP row shifts (within
+// rows of 16 lanes), whole-wave shifts by one lane, and readlane.  A lane with
+// no source lane reads `old`.
+// ---------------------------------------------------------------------------
+constexpr int kDppRowShr = 0x110;   // + n: lane i reads lane i - n of its row
+constexpr int kDppRowShl = 0x100;   // + n: lane i reads lane i + n of its row
+constexpr int kDppWaveShr1 = 0x138; // lane i reads lane i - 1
+constexpr int kDppWaveShl1 = 0x130; // lane i reads lane i + 1
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v, float old = 0.0f) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v), __float_as_int(old)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v, double old = 0.0) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned long long o = static_cast<unsigned long long>(__double_as_longlong(old));
+  const unsigned lo = unsigned(dpp_i32<CTRL>(int(unsigned(u)), int(unsigned(o))));
+  const unsigned hi = unsigned(dpp_i32<CTRL>(int(unsigned(u >> 32)), int(unsigned(o >> 32))));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v, int old = 0) {
+  return dpp_i32<CTRL>(v, old);
+}
+
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), l));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), l));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum over the 64 lanes, the same value in every lane, in a fixed order: each
+// row of 16 lanes by four shifted adds (its total lands in its last lane), then
+// the four row totals.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp<kDppRowShr + 1>(v);
+  v += dpp<kDppRowShr + 2>(v);
+  v += dpp<kDppRowShr + 4>(v);
+  v += dpp<kDppRowShr + 8>(v);
+  return (lane_read(v, 15) + lane_read(v, 31)) + (lane_read(v, 47) + lane_read(v, 63));
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, dpp<kDppRowShr + 1>(v, v));
+  v = max(v, dpp<kDppRowShr + 2>(v, v));
+  v = max(v, dpp<kDppRowShr + 4>(v, v));
+  v = max(v, dpp<kDppRowShr + 8>(v, v));
+  return max(max(lane_read(v, 15), lane_read(v, 31)), max(lane_read(v, 47), lane_read(v, 63)));
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic block sum of a double (fixed reduction order).
 // ---------------------------------------------------------------------------
 template <int NW>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_down(v, d);
+  v = wave_sum(v);
   if (lane == 0) sh[w] = v;
   __syncthreads();
   double t = 0.0;

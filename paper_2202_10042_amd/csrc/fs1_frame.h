@@ -26,6 +26,8 @@ struct FastDec {
   T wave;      // lambda^(64 R)
   T lane_f;    // lambda^(lane R)
   T lane_b;    // lambda^((63 - lane) R)
+  T row_f;     // lambda^(((lane mod 16) + 1) R): from the last lane of the row before
+  T row_b;     // lambda^((16 - lane mod 16) R): from the first lane of the row after
 };
 
 template <typename T>
@@ -54,14 +56,62 @@ __device__ __forceinline__ FastDec<T> make_fast_dec(const ScanConsts& k, int lan
   }
   D.lane_f = T(ldexp(mf, ef));
   D.lane_b = T(ldexp(mb, eb));
+  const int nf = (lane & 15) + 1, nb = 16 - (lane & 15);  // both in [1, 16]
+  mf = mb = 1.0;
+  ef = eb = 0;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    if ((nf >> s) & 1) {
+      mf *= k.lane[s].m;
+      ef += k.lane[s].e;
+    }
+    if ((nb >> s) & 1) {
+      mb *= k.lane[s].m;
+      eb += k.lane[s].e;
+    }
+  }
+  D.row_f = T(ldexp(mf, ef));
+  D.row_b = T(ldexp(mb, eb));
   return D;
+}
+
+// Inclusive decayed scans over the 64 lanes of a wavefront, forward
+// (f_i = sum_{k <= i} lambda^{(i-k) R} v_k) and backward
+// (b_i = sum_{k >= i} lambda^{(k-i) R} v_k): within each row of 16 lanes by
+// shifted multiply-adds, then the rows before (after) a row enter through
+// its first (last) lane's neighbour, read once per wavefront.
+template <typename T>
+__device__ __forceinline__ T wave_fscan(T f, const FastDec<T>& D, int lane) {
+  f = fma(D.step[0], dpp<kDppRowShr + 1>(f), f);
+  f = fma(D.step[1], dpp<kDppRowShr + 2>(f), f);
+  f = fma(D.step[2], dpp<kDppRowShr + 4>(f), f);
+  f = fma(D.step[3], dpp<kDppRowShr + 8>(f), f);
+  const T p15 = lane_read(f, 15);
+  const T p31 = fma(D.step[4], p15, lane_read(f, 31));
+  const T p47 = fma(D.step[4], p31, lane_read(f, 47));
+  const int row = lane >> 4;
+  const T c = row == 0 ? T(0) : (row == 1 ? p15 : (row == 2 ? p31 : p47));
+  return fma(D.row_f, c, f);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_bscan(T b, const FastDec<T>& D, int lane) {
+  b = fma(D.step[0], dpp<kDppRowShl + 1>(b), b);
+  b = fma(D.step[1], dpp<kDppRowShl + 2>(b), b);
+  b = fma(D.step[2], dpp<kDppRowShl + 4>(b), b);
+  b = fma(D.step[3], dpp<kDppRowShl + 8>(b), b);
+  const T s48 = lane_read(b, 48);
+  const T s32 = fma(D.step[4], s48, lane_read(b, 32));
+  const T s16 = fma(D.step[4], s32, lane_read(b, 16));
+  const int row = lane >> 4;
+  const T c = row == 3 ? T(0) : (row == 2 ? s48 : (row == 1 ? s32 : s16));
+  return fma(D.row_b, c, b);
 }
 
 __device__ __forceinline__ int block_max_int(int v, int* sh) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
+  v = wave_max(v);
   if (lane == 0) sh[w] = v;
   __syncthreads();
   int r = sh[0];
@@ -71,15 +121,23 @@ __device__ __forceinline__ int block_max_int(int v, int* sh) {
   return r;
 }
 
-// xfloat sum over the 64 lanes (same tree in every lane: every lane returns
-// the same value).
+// xfloat sum over the 64 lanes (every lane returns the same value): each row
+// by shifted adds (lanes without a source read a zero), then the four row
+// totals in order.
+template <int CTRL>
+__device__ __forceinline__ XF<double> xdpp(XF<double> v) {
+  return {dpp<CTRL>(v.m, 0.0), dpp<CTRL>(v.e, kExpZero)};
+}
+
 __device__ __forceinline__ XF<double> wave_xsum(XF<double> v) {
+  v = xnorm(xadd(v, xdpp<kDppRowShr + 1>(v)));
+  v = xnorm(xadd(v, xdpp<kDppRowShr + 2>(v)));
+  v = xnorm(xadd(v, xdpp<kDppRowShr + 4>(v)));
+  v = xnorm(xadd(v, xdpp<kDppRowShr + 8>(v)));
+  XF<double> r[4];
 #pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) {
-    const XF<double> o = {__shfl_xor(v.m, d), __shfl_xor(v.e, d)};
-    v = xadd(v, o);
-  }
-  return xnorm(v);
+  for (int q = 0; q < 4; ++q) r[q] = {lane_read(v.m, 16 * q + 15), lane_read(v.e, 16 * q + 15)};
+  return xnorm(xadd(xnorm(xadd(r[0], r[1])), xnorm(xadd(r[2], r[3]))));
 }
 
 __device__ __forceinline__ XF<double> pow_bits(int64_t d, const Decay* p) {
@@ -218,18 +276,11 @@ __device__ __forceinline__ void local_scan(const T (&x)[R], int ex, const Lam<T>
   for (int j = 0; j < R; ++j) hs.xf[j] = (eb == kExpZero) ? T(0) : ldx(x[j], ex - hs.ein);
   T f, b;
   run_aggs<T, R>(hs.xf, L, f, b);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 1 << s;
-    const T of = __shfl_up(f, d);
-    const T ob = __shfl_down(b, d);
-    if (lane >= d) f = fma(D.step[s], of, f);
-    if (lane + d < kWave) b = fma(D.step[s], ob, b);
-  }
-  T ef = __shfl_up(f, 1);
-  T eb2 = __shfl_down(b, 1);
-  hs.exf = (lane == 0) ? T(0) : ef;
-  hs.exb = (lane == kWave - 1) ? T(0) : eb2;
+  f = wave_fscan<T>(f, D, lane);
+  b = wave_bscan<T>(b, D, lane);
+  // exclusive values: the neighbouring lane's inclusive value (0 at the ends)
+  hs.exf = dpp<kDppWaveShr1>(f);
+  hs.exb = dpp<kDppWaveShl1>(b);
   if (lane == kWave - 1) sf[w] = f;
   if (lane == 0) sb[w] = b;
   __syncthreads();
@@ -358,12 +409,9 @@ __device__ __forceinline__ void publish_frame(const T (&q)[R], int e, const Lam<
   run_aggs<T, R>(q, L, f, b);
   f *= D.lane_b;
   b *= D.lane_f;
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) {
-    f += __shfl_xor(f, d);
-    b += __shfl_xor(b, d);
-    if (part) err += __shfl_xor(err, d);
-  }
+  f = wave_sum(f);
+  b = wave_sum(b);
+  if (part) err = wave_sum(err);
   if (lane == 0) {
     sf[w] = f;
     sb[w] = b;

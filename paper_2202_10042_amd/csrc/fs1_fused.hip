@@ -142,8 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxFusedChunks / kBlock; ++i) e += sh4[i];
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) e += __shfl_xor(e, d);
+    e = wave_sum(e);
     if (lane == 0) red[threadIdx.x / kWave] = e;
     __syncthreads();
   }
