@@ -33,10 +33,14 @@ enum BMode { B_PSI = 0, B_PHI = 1, B_ERR = 2 };
 // which of two buffers a kernel reads
 enum BSel { SEL_0 = 0, SEL_FINAL = 1, SEL_NEXT = 2, SEL_CUR = 3 };
 
+// sum over the 64 lanes, the same in every lane: rows by DPP shifts, then the
+// four row totals in order
 __device__ __forceinline__ S2<double> s2_wave_sum(S2<double> v) {
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) v = v.add(v.shfl_xor(d));
-  return v.norm();
+  v = v.add(v.move<kDppRowShr + 1>());
+  v = v.add(v.move<kDppRowShr + 2>());
+  v = v.add(v.move<kDppRowShr + 4>());
+  v = v.add(v.move<kDppRowShr + 8>()).norm();
+  return v.lane(15).add(v.lane(31)).norm().add(v.lane(47).add(v.lane(63)).norm()).norm();
 }
 
 // Carries of chunk j of an instance from its chunk aggregates A[0..nch), for

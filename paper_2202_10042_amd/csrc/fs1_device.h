@@ -86,6 +86,78 @@ __device__ __forceinline__ T xval(XF<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront data movement without the LDS crossbar: DPP row shifts (within
+// rows of 16 lanes), whole-wave shifts by one lane, and readlane.  A lane with
+// no source lane reads `old`.
+// ---------------------------------------------------------------------------
+constexpr int kDppRowShr = 0x110;   // + n: lane i reads lane i - n of its row
+constexpr int kDppRowShl = 0x100;   // + n: lane i reads lane i + n of its row
+constexpr int kDppWaveShr1 = 0x138; // lane i reads lane i - 1
+constexpr int kDppWaveShl1 = 0x130; // lane i reads lane i + 1
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v, float old = 0.0f) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v), __float_as_int(old)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v, double old = 0.0) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned long long o = static_cast<unsigned long long>(__double_as_longlong(old));
+  const unsigned lo = unsigned(dpp_i32<CTRL>(int(unsigned(u)), int(unsigned(o))));
+  const unsigned hi = unsigned(dpp_i32<CTRL>(int(unsigned(u >> 32)), int(unsigned(o >> 32))));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v, int old = 0) {
+  return dpp_i32<CTRL>(v, old);
+}
+
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), l));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), l));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum over the 64 lanes, the same value in every lane, in a fixed order: each
+// row of 16 lanes by four shifted adds (its total lands in its last lane), then
+// the four row totals.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp<kDppRowShr + 1>(v);
+  v += dpp<kDppRowShr + 2>(v);
+  v += dpp<kDppRowShr + 4>(v);
+  v += dpp<kDppRowShr + 8>(v);
+  return (lane_read(v, 15) + lane_read(v, 31)) + (lane_read(v, 47) + lane_read(v, 63));
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, dpp<kDppRowShr + 1>(v, v));
+  v = max(v, dpp<kDppRowShr + 2>(v, v));
+  v = max(v, dpp<kDppRowShr + 4>(v, v));
+  v = max(v, dpp<kDppRowShr + 8>(v, v));
+  return max(max(lane_read(v, 15), lane_read(v, 31)), max(lane_read(v, 47), lane_read(v, 63)));
+}
+
+// An extended number moved by DPP: a lane without a source lane reads zero.
+template <int CTRL, typename T>
+__device__ __forceinline__ XF<T> xmove(XF<T> v) {
+  return {dpp<CTRL>(v.m, T(0)), dpp<CTRL>(v.e, kExpZero)};
+}
+template <typename T>
+__device__ __forceinline__ XF<T> xlane(XF<T> v, int l) {
+  return {lane_read(v.m, l), lane_read(v.e, l)};
+}
+
+// ---------------------------------------------------------------------------
 // Decays lambda^D
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -136,12 +208,11 @@ struct S1 {
   __device__ __forceinline__ S1 shift(const Dec<T>& d) const { return {xmul(v, XF<T>{d.m, d.e})}; }
   __device__ __forceinline__ S1 add(const S1& o) const { return {xadd(v, o.v)}; }
   __device__ __forceinline__ S1 norm() const { return {xnorm(v)}; }
-  __device__ __forceinline__ S1 shfl_up(int d) const {
-    return {{__shfl_up(v.m, d), __shfl_up(v.e, d)}};
+  template <int CTRL>
+  __device__ __forceinline__ S1 move() const {
+    return {xmove<CTRL>(v)};
   }
-  __device__ __forceinline__ S1 shfl_down(int d) const {
-    return {{__shfl_down(v.m, d), __shfl_down(v.e, d)}};
-  }
+  __device__ __forceinline__ S1 lane(int l) const { return {xlane(v, l)}; }
 };
 
 // ---------------------------------------------------------------------------
@@ -165,16 +236,11 @@ struct S2 {
   }
   __device__ __forceinline__ S2 add(const S2& o) const { return {xadd(p, o.p), xadd(d, o.d)}; }
   __device__ __forceinline__ S2 norm() const { return {xnorm(p), xnorm(d)}; }
-  __device__ __forceinline__ S2 shfl_up(int dd) const {
-    return {{__shfl_up(p.m, dd), __shfl_up(p.e, dd)}, {__shfl_up(d.m, dd), __shfl_up(d.e, dd)}};
+  template <int CTRL>
+  __device__ __forceinline__ S2 move() const {
+    return {xmove<CTRL>(p), xmove<CTRL>(d)};
   }
-  __device__ __forceinline__ S2 shfl_down(int dd) const {
-    return {{__shfl_down(p.m, dd), __shfl_down(p.e, dd)},
-            {__shfl_down(d.m, dd), __shfl_down(d.e, dd)}};
-  }
-  __device__ __forceinline__ S2 shfl_xor(int dd) const {
-    return {{__shfl_xor(p.m, dd), __shfl_xor(p.e, dd)}, {__shfl_xor(d.m, dd), __shfl_xor(d.e, dd)}};
-  }
+  __device__ __forceinline__ S2 lane(int l) const { return {xlane(p, l), xlane(d, l)}; }
 };
 
 // Carry of chunk c from the carry buffer: under the two-level scan the stored
@@ -242,20 +308,37 @@ __device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const 
   const int w = threadIdx.x / kWave;
   S incf = tf.norm();
   S incb = tb.norm();
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 1 << s;
-    const S of = incf.shfl_up(d);
-    const S ob = incb.shfl_down(d);
-    if (lane >= d) incf = incf.add(of.shift(dec[s]));
-    if (lane + d < kWave) incb = incb.add(ob.shift(dec[s]));
-  }
+  // within rows of 16 lanes (DPP row shifts; a lane without a source adds zero)
+  incf = incf.add(incf.template move<kDppRowShr + 1>().shift(dec[0]));
+  incb = incb.add(incb.template move<kDppRowShl + 1>().shift(dec[0]));
+  incf = incf.add(incf.template move<kDppRowShr + 2>().shift(dec[1]));
+  incb = incb.add(incb.template move<kDppRowShl + 2>().shift(dec[1]));
+  incf = incf.add(incf.template move<kDppRowShr + 4>().shift(dec[2]));
+  incb = incb.add(incb.template move<kDppRowShl + 4>().shift(dec[2]));
+  incf = incf.add(incf.template move<kDppRowShr + 8>().shift(dec[3]));
+  incb = incb.add(incb.template move<kDppRowShl + 8>().shift(dec[3]));
   incf = incf.norm();
   incb = incb.norm();
-  S exf = incf.shfl_up(1);
-  S exb = incb.shfl_down(1);
-  if (lane == 0) exf = S::zero();
-  if (lane == kWave - 1) exb = S::zero();
+  // across rows: the rows before (after) a row enter through the last (first)
+  // lane of its neighbour row, read once per wavefront
+  const int row = lane >> 4;
+  {
+    const S p15 = incf.lane(15);
+    const S p31 = incf.lane(31).add(p15.shift(dec[4])).norm();
+    const S p47 = incf.lane(47).add(p31.shift(dec[4])).norm();
+    const S c = row == 0 ? S::zero() : (row == 1 ? p15 : (row == 2 ? p31 : p47));
+    incf = incf.add(c.shift(lane_pow((lane & 15) + 1, dec))).norm();
+  }
+  {
+    const S s48 = incb.lane(48);
+    const S s32 = incb.lane(32).add(s48.shift(dec[4])).norm();
+    const S s16 = incb.lane(16).add(s32.shift(dec[4])).norm();
+    const S c = row == 3 ? S::zero() : (row == 2 ? s48 : (row == 1 ? s32 : s16));
+    incb = incb.add(c.shift(lane_pow(16 - (lane & 15), dec))).norm();
+  }
+  // exclusive values: the neighbouring lane's inclusive value (zero at the ends)
+  const S exf = incf.template move<kDppWaveShr1>();
+  const S exb = incb.template move<kDppWaveShl1>();
   if (lane == kWave - 1) sh.f[w] = incf;
   if (lane == 0) sh.b[w] = incb;
   __syncthreads();
@@ -276,68 +359,6 @@ __device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const 
     *agg_b = ab.norm();
   }
   __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Wavefront data movement without the LDS crossbar: DPP row shifts (within
-// rows of 16 lanes), whole-wave shifts by one lane, and readlane.  A lane with
-// no source lane reads `old`.
-// ---------------------------------------------------------------------------
-constexpr int kDppRowShr = 0x110;   // + n: lane i reads lane i - n of its row
-constexpr int kDppRowShl = 0x100;   // + n: lane i reads lane i + n of its row
-constexpr int kDppWaveShr1 = 0x138; // lane i reads lane i - 1
-constexpr int kDppWaveShl1 = 0x130; // lane i reads lane i + 1
-
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int v, int old) {
-  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v, float old = 0.0f) {
-  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v), __float_as_int(old)));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v, double old = 0.0) {
-  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
-  const unsigned long long o = static_cast<unsigned long long>(__double_as_longlong(old));
-  const unsigned lo = unsigned(dpp_i32<CTRL>(int(unsigned(u)), int(unsigned(o))));
-  const unsigned hi = unsigned(dpp_i32<CTRL>(int(unsigned(u >> 32)), int(unsigned(o >> 32))));
-  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-template <int CTRL>
-__device__ __forceinline__ int dpp(int v, int old = 0) {
-  return dpp_i32<CTRL>(v, old);
-}
-
-__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ float lane_read(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double lane_read(double v, int l) {
-  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
-  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), l));
-  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), l));
-  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-
-// Sum over the 64 lanes, the same value in every lane, in a fixed order: each
-// row of 16 lanes by four shifted adds (its total lands in its last lane), then
-// the four row totals.
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  v += dpp<kDppRowShr + 1>(v);
-  v += dpp<kDppRowShr + 2>(v);
-  v += dpp<kDppRowShr + 4>(v);
-  v += dpp<kDppRowShr + 8>(v);
-  return (lane_read(v, 15) + lane_read(v, 31)) + (lane_read(v, 47) + lane_read(v, 63));
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-  v = max(v, dpp<kDppRowShr + 1>(v, v));
-  v = max(v, dpp<kDppRowShr + 2>(v, v));
-  v = max(v, dpp<kDppRowShr + 4>(v, v));
-  v = max(v, dpp<kDppRowShr + 8>(v, v));
-  return max(max(lane_read(v, 15), lane_read(v, 31)), max(lane_read(v, 47), lane_read(v, 63)));
 }
 
 // ---------------------------------------------------------------------------
