@@ -613,7 +613,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // workspace layout
   SolveBufs b{};
-  unsigned* bar = nullptr;
+  int* epoch = nullptr;  // persistent solve: per-chunk publication flags
   const int64_t npad = nchunks * C;  // vectors are allocated to whole chunks
   double* mu64 = nullptr;
   double* nu64 = nullptr;
@@ -636,7 +636,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
-    bar = static_cast<unsigned*>(w.take(2 * sizeof(unsigned)));
+    epoch = static_cast<int*>(w.take(size_t(std::max<int64_t>(nchunks, 1)) * sizeof(int)));
   };
   {
     Carve probe(nullptr);
@@ -714,8 +714,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     if (resident) {
       HIP_TRY(launch_resident(b, k, o.itr_max, o.check_every, tol, s));
     } else {
-      HIP_TRY(hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), s));
-      HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, bar, s));
+      HIP_TRY(hipMemsetAsync(epoch, 0, size_t(nchunks) * sizeof(int), s));
+      HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, epoch, s));
     }
     if (prof) HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));

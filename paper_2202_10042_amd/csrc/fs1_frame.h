@@ -196,7 +196,7 @@ struct CarryItems {
   int lo, hi;  // segment [lo, hi)
 };
 
-template <int CMAX>
+template <int CMAX, bool AGENT = false>
 __device__ __forceinline__ void carry_prefetch(const ChunkAgg* A, int b, int nchunks,
                                                CarryItems<CMAX>& it) {
   const bool fwd = threadIdx.x < kBlock / 2;
@@ -210,9 +210,15 @@ __device__ __forceinline__ void carry_prefetch(const ChunkAgg* A, int b, int nch
   for (int i = 0; i < CMAX; ++i) {
     const int c = it.lo + i;
     if (c < it.hi) {
-      const XF64 v = fwd ? A[c].f : A[c].b;
-      it.m[i] = v.m;
-      it.e[i] = v.e;
+      const XF64* src = fwd ? &A[c].f : &A[c].b;
+      if constexpr (AGENT) {
+        // device-coherent loads of aggregates written by this launch
+        it.m[i] = __hip_atomic_load(&src->m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it.e[i] = __hip_atomic_load(&src->e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        it.m[i] = src->m;
+        it.e[i] = src->e;
+      }
     } else {
       it.m[i] = 0.0;
       it.e[i] = kExpZero;
@@ -288,7 +294,7 @@ __device__ __forceinline__ void local_scan(const T (&x)[R], int ex, const Lam<T>
 
 // The chunk's forward / backward aggregates from the per-wave aggregates
 // (thread 0 stores them to A[blockIdx.x]).
-template <typename T>
+template <typename T, bool AGENT = false>
 __device__ __forceinline__ void publish(const FastDec<T>& D, const T* sf, const T* sb, int ein,
                                         ChunkAgg* A) {
   if (threadIdx.x == 0) {
@@ -297,8 +303,18 @@ __device__ __forceinline__ void publish(const FastDec<T>& D, const T* sf, const 
     for (int v = 0; v < kNW; ++v) gf = fma(D.wave, gf, sf[v]);
 #pragma unroll
     for (int v = kNW - 1; v >= 0; --v) gb = fma(D.wave, gb, sb[v]);
-    A[blockIdx.x].f = to64(xnorm(gf, ein));
-    A[blockIdx.x].b = to64(xnorm(gb, ein));
+    const XF64 f = to64(xnorm(gf, ein));
+    const XF64 bk = to64(xnorm(gb, ein));
+    if constexpr (AGENT) {
+      // device-coherent stores: read by other workgroups of the same launch
+      __hip_atomic_store(&A[blockIdx.x].f.m, f.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A[blockIdx.x].f.e, f.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A[blockIdx.x].b.m, bk.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A[blockIdx.x].b.e, bk.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      A[blockIdx.x].f = f;
+      A[blockIdx.x].b = bk;
+    }
   }
 }
 

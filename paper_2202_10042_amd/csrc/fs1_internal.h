@@ -165,8 +165,9 @@ hipError_t launch_resident(const SolveBufs& b, const ScanConsts& k, int itr_max,
 // Persistent solve (all iterations in one cooperative launch; state kept in
 // registers).  usable_persistent() tells whether the configuration fits.
 bool usable_persistent(const SolveBufs& b, double c);
+// epoch: nchunks ints, zero before the launch (per-chunk publication flags)
 hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_max,
-                             int check_every, double tol, unsigned* bar, hipStream_t s);
+                             int check_every, double tol, int* epoch, hipStream_t s);
 
 // One launch per half-iteration with in-kernel chunk carries (log domain,
 // chunk frame valid, moderate chunk count).

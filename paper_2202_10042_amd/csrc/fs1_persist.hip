@@ -6,14 +6,15 @@
 // psi and the marginals of its chunk in registers for the whole solve.  A
 // half-iteration is
 //   (1) the chunk's forward / backward recursion aggregates (Sec. 3,
-//       eq. (recursion)) of the vector fed to K, published to global memory;
-//   (2) one grid barrier;
+//       eq. (recursion)) of the vector fed to K, published to global memory
+//       with a per-chunk epoch flag (no central counter);
+//   (2) a wait, by every workgroup, for the flags of all chunks;
 //   (3) the chunk carries, recomputed by every workgroup from all published
 //       aggregates, and the in-chunk recursions with those carries;
 //   (4) the Sinkhorn update (Sec. 2: psi = nu / K^T phi, then phi = mu / K psi)
 //       and, on checked iterations, the chunk's share of Algorithm 1's stopping
 //       error.
-// After the barrier of each phi-half every workgroup sums the error shares in
+// After the wait of each phi-half every workgroup sums the error shares in
 // the same fixed order, so all of them take the same stop decision.
 //
 // Inside a chunk the recursions run in plain floating point relative to one
@@ -31,7 +32,8 @@ namespace fs1 {
 
 namespace {
 
-constexpr int kMaxPersistChunks = 2048;
+constexpr int kCarryMaxP = 8;
+constexpr int kMaxPersistChunks = kCarryMaxP * kBlock / 2;  // 1024: the carry prefetch's reach
 // log2 span budget of the per-chunk frame (see the file comment)
 constexpr double kFrameLog2Span64 = 900.0;
 constexpr double kFrameLog2Span32 = 80.0;
@@ -49,7 +51,7 @@ struct PersistArgs {
   ChunkAgg* A1;           // chunk aggregates of psi (phi-halves)
   double* part;           // per-chunk stopping-error shares
   Ctrl* ctrl;
-  unsigned* bar;          // grid barrier: [0] arrivals, [1] generation
+  int* epoch;             // per chunk: the last half whose aggregates it published
   double* err_hist;
   int64_t n;
   int nchunks;
@@ -59,45 +61,46 @@ struct PersistArgs {
   Decay cpow[20];         // lambda^(chunk length * 2^s)
 };
 
-// Grid barrier over co-resident workgroups (cooperative launch).  The
-// arriving thread publishes its workgroup's global writes (device-scope
-// release), the last arrival advances the generation, and the others wait for
-// it with a bounded spin: a wait that exceeds the bound sets
-// ctrl->barrier_timeout and returns, so no wavefront can hang.
-// Returns false (in every thread of the workgroup) once any workgroup has given
-// up waiting; the caller then leaves its iteration loop, so after one bounded
-// wait every workgroup runs to completion.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, Ctrl* ctrl,
-                                             int* sflag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
+// Publication of one half's chunk aggregates (and error shares) between
+// co-resident workgroups (cooperative launch), without a central counter.
+// Everything that crosses workgroups (aggregates, shares, flags) is written
+// and read with relaxed device-scope atomics, which on gfx950 are plain
+// loads and stores marked device-coherent (sc1): they write through and read
+// past the per-XCD L2, so no L2 write-back or invalidate is needed.  The
+// barrier below waits for every wave's stores to complete before thread 0
+// sets the workgroup's epoch flag to `gen`; the first wave then polls, with
+// a bounded spin, until every chunk's flag reaches `gen`.  A wait that exceeds the
+// bound sets ctrl->barrier_timeout; every workgroup that sees it (or times out
+// itself) returns false, and the caller leaves its iteration loop, so after
+// at most one bounded wait every workgroup runs to completion.
+__device__ __forceinline__ bool publish_sync(int* epoch, int gen, int nchunks, Ctrl* ctrl) {
+  __shared__ int sok;
+  __syncthreads();  // this workgroup's aggregates and shares are written
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&epoch[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // the first wavefront polls every chunk's flag (relaxed device-coherent
+  // loads, all of a round issued together) until all have reached gen
+  if (threadIdx.x < kWave) {
     int ok = 1;
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (__hip_atomic_load(&ctrl->barrier_timeout, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT) ||
-            ++spins > (1u << 22)) {
-          __hip_atomic_store(&ctrl->barrier_timeout, 1, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
+    unsigned spins = 0;
+    for (;;) {
+      int mn = INT_MAX;
+      for (int c = threadIdx.x; c < nchunks; c += kWave)
+        mn = min(mn, __hip_atomic_load(&epoch[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (__all(mn >= gen)) break;
+      if (++spins > (1u << 22) ||
+          __hip_atomic_load(&ctrl->barrier_timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (threadIdx.x == 0)
+          __hip_atomic_store(&ctrl->barrier_timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
-    *sflag = ok;
+    if (threadIdx.x == 0) sok = ok;
   }
   __syncthreads();
-  return *sflag != 0;
+  return sok != 0;
 }
 
 template <typename T, int R>
@@ -107,14 +110,14 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
   __shared__ int smax[kNW];
   __shared__ double red[kNW];
   __shared__ XF64 scar[2];
+  __shared__ XF64 red4[kNW];
   __shared__ int sdec;
-  __shared__ int sbar;
 
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t base = run * R;
   const int64_t n = a.n;
-  const unsigned nblocks = gridDim.x;
+  int gen = 0;  // halves published so far
 
   // register-resident state
   T ph[R], ps[R], pso[R], mu[R], nu[R];
@@ -144,8 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
     const bool check = (l % a.check_every) == 0;
     // ---------------- psi-half: psi <- nu / K^T phi ----------------
     local_scan<T, R>(ph, eph, L, D, sf, sb, smax, hs);
-    publish<T>(D, sf, sb, hs.ein, a.A0);
-    if (!grid_barrier(a.bar, nblocks, a.ctrl, &sbar)) break;
+    publish<T, true>(D, sf, sb, hs.ein, a.A0);
+    if (!publish_sync(a.epoch, ++gen, a.nchunks, a.ctrl)) break;
     // failures of the previous phi-half: that slot is written only before this
     // barrier, so every workgroup reads the same value
     if (threadIdx.x == 0)
@@ -155,7 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       failed = true;
       break;
     }
-    int eap = half_apply<T, R>(a.A0, a.nchunks, a.cpow, L, D, sf, sb, scar, hs, y);
+    CarryItems<kCarryMaxP> items;
+    carry_prefetch<kCarryMaxP, true>(a.A0, blockIdx.x, a.nchunks, items);
+    carry_finish<kCarryMaxP>(items, blockIdx.x, a.cpow, red4, scar);
+    int eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     if (check) {
       double s = 0.0;
       double nu64[R];
@@ -164,7 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       for (int j = 0; j < R; ++j)
         if (base + j < n) s += fabs(ldexp(double(ps[j]) * double(y[j]), eps + eap) - nu64[j]);
       const double tot = block_sum<kNW>(s, red);
-      if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&a.part[blockIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     bool bad = false;
     T q[R];
@@ -184,8 +191,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
 
     // ---------------- phi-half: phi <- mu / K psi ----------------
     local_scan<T, R>(ps, eps, L, D, sf, sb, smax, hs);
-    publish<T>(D, sf, sb, hs.ein, a.A1);
-    if (!grid_barrier(a.bar, nblocks, a.ctrl, &sbar)) break;
+    publish<T, true>(D, sf, sb, hs.ein, a.A1);
+    if (!publish_sync(a.epoch, ++gen, a.nchunks, a.ctrl)) break;
     // stopping test of iteration l (every workgroup sums the same shares in
     // the same order) and the failure flag
     if (threadIdx.x < kWave) {
@@ -194,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
                                   __HIP_MEMORY_SCOPE_AGENT) ? 2 : 0;
       if (check && !dec) {
         double s = 0.0;
-        for (int c = lane; c < a.nchunks; c += kWave) s += a.part[c];
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        for (int c = lane; c < a.nchunks; c += kWave)
+          s += __hip_atomic_load(&a.part[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s = wave_sum(s);
         if (lane == 0) {
           if (blockIdx.x == 0) {
             a.ctrl->last_err = s;
@@ -221,7 +228,9 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       stop_iter = l;
       break;
     }
-    eap = half_apply<T, R>(a.A1, a.nchunks, a.cpow, L, D, sf, sb, scar, hs, y);
+    carry_prefetch<kCarryMaxP, true>(a.A1, blockIdx.x, a.nchunks, items);
+    carry_finish<kCarryMaxP>(items, blockIdx.x, a.cpow, red4, scar);
+    eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     bad = false;
     const int ef = update_run<T, R>(mu, y, eap, q, bad);
     if (bad) {
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
 
 template <typename T, int R>
 hipError_t persist_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,
-                     double tol, unsigned* bar, hipStream_t s) {
+                     double tol, int* epoch, hipStream_t s) {
   PersistArgs a{};
   a.mu = b.mu;
   a.nu = b.nu;
@@ -264,7 +273,7 @@ hipError_t persist_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int c
   a.A1 = b.aggG;
   a.part = b.part;
   a.ctrl = b.ctrl;
-  a.bar = bar;
+  a.epoch = epoch;
   a.err_hist = b.err_hist;
   a.n = b.n;
   a.nchunks = int(b.nchunks);
@@ -310,9 +319,9 @@ bool usable_persistent(const SolveBufs& b, double c) {
 }
 
 hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_max,
-                             int check_every, double tol, unsigned* bar, hipStream_t s) {
-  if (b.dtype == 0) return persist_t<double, 8>(b, k, itr_max, check_every, tol, bar, s);
-  return persist_t<float, 16>(b, k, itr_max, check_every, tol, bar, s);
+                             int check_every, double tol, int* epoch, hipStream_t s) {
+  if (b.dtype == 0) return persist_t<double, 8>(b, k, itr_max, check_every, tol, epoch, s);
+  return persist_t<float, 16>(b, k, itr_max, check_every, tol, epoch, s);
 }
 
 }  // namespace fs1
