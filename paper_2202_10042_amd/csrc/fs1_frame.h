@@ -196,9 +196,14 @@ struct CarryItems {
   int lo, hi;  // segment [lo, hi)
 };
 
-template <int CMAX, bool AGENT = false>
+// Plain loads of published aggregates (a previous launch wrote them).
+struct PlainLoad {
+  __device__ XF64 operator()(const XF64* p) const { return *p; }
+};
+
+template <int CMAX, typename Load = PlainLoad>
 __device__ __forceinline__ void carry_prefetch(const ChunkAgg* A, int b, int nchunks,
-                                               CarryItems<CMAX>& it) {
+                                               CarryItems<CMAX>& it, Load load = Load()) {
   const bool fwd = threadIdx.x < kBlock / 2;
   const int u = threadIdx.x & (kBlock / 2 - 1);
   const int first = fwd ? 0 : b + 1;
@@ -210,15 +215,9 @@ __device__ __forceinline__ void carry_prefetch(const ChunkAgg* A, int b, int nch
   for (int i = 0; i < CMAX; ++i) {
     const int c = it.lo + i;
     if (c < it.hi) {
-      const XF64* src = fwd ? &A[c].f : &A[c].b;
-      if constexpr (AGENT) {
-        // device-coherent loads of aggregates written by this launch
-        it.m[i] = __hip_atomic_load(&src->m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        it.e[i] = __hip_atomic_load(&src->e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        it.m[i] = src->m;
-        it.e[i] = src->e;
-      }
+      const XF64 v = load(fwd ? &A[c].f : &A[c].b);
+      it.m[i] = v.m;
+      it.e[i] = v.e;
     } else {
       it.m[i] = 0.0;
       it.e[i] = kExpZero;
@@ -292,30 +291,25 @@ __device__ __forceinline__ void local_scan(const T (&x)[R], int ex, const Lam<T>
   __syncthreads();
 }
 
-// The chunk's forward / backward aggregates from the per-wave aggregates
-// (thread 0 stores them to A[blockIdx.x]).
-template <typename T, bool AGENT = false>
+// The chunk's forward / backward aggregates (extended range, normalised) from
+// the per-wave aggregates.
+template <typename T>
+__device__ __forceinline__ void chunk_aggs(const FastDec<T>& D, const T* sf, const T* sb, int ein,
+                                           XF64& f, XF64& b) {
+  T gf = T(0), gb = T(0);
+#pragma unroll
+  for (int v = 0; v < kNW; ++v) gf = fma(D.wave, gf, sf[v]);
+#pragma unroll
+  for (int v = kNW - 1; v >= 0; --v) gb = fma(D.wave, gb, sb[v]);
+  f = to64(xnorm(gf, ein));
+  b = to64(xnorm(gb, ein));
+}
+
+// Thread 0 stores the chunk's aggregates to A[blockIdx.x].
+template <typename T>
 __device__ __forceinline__ void publish(const FastDec<T>& D, const T* sf, const T* sb, int ein,
                                         ChunkAgg* A) {
-  if (threadIdx.x == 0) {
-    T gf = T(0), gb = T(0);
-#pragma unroll
-    for (int v = 0; v < kNW; ++v) gf = fma(D.wave, gf, sf[v]);
-#pragma unroll
-    for (int v = kNW - 1; v >= 0; --v) gb = fma(D.wave, gb, sb[v]);
-    const XF64 f = to64(xnorm(gf, ein));
-    const XF64 bk = to64(xnorm(gb, ein));
-    if constexpr (AGENT) {
-      // device-coherent stores: read by other workgroups of the same launch
-      __hip_atomic_store(&A[blockIdx.x].f.m, f.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A[blockIdx.x].f.e, f.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A[blockIdx.x].b.m, bk.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A[blockIdx.x].b.e, bk.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      A[blockIdx.x].f = f;
-      A[blockIdx.x].b = bk;
-    }
-  }
+  if (threadIdx.x == 0) chunk_aggs<T>(D, sf, sb, ein, A[blockIdx.x].f, A[blockIdx.x].b);
 }
 
 // Phase 3 of a half: chunk carries (waves 0 and 1), frame alignment, in-chunk

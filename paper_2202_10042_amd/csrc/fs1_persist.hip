@@ -103,6 +103,77 @@ __device__ __forceinline__ bool publish_sync(int* epoch, int gen, int nchunks, C
   return sok != 0;
 }
 
+// Device-coherent loads of aggregates published by this launch.
+struct CoherentLoad {
+  __device__ XF64 operator()(const XF64* p) const {
+    XF64 v;
+    v.m = __hip_atomic_load(const_cast<double*>(&p->m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v.e = __hip_atomic_load(const_cast<int*>(&p->e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v.pad = 0;
+    return v;
+  }
+};
+
+// Thread 0 stores the chunk's aggregates with device-coherent stores.
+template <typename T>
+__device__ __forceinline__ void publish_coherent(const FastDec<T>& D, const T* sf, const T* sb,
+                                                 int ein, ChunkAgg* A) {
+  if (threadIdx.x == 0) {
+    XF64 f, b;
+    chunk_aggs<T>(D, sf, sb, ein, f, b);
+    ChunkAgg* p = A + blockIdx.x;
+    __hip_atomic_store(&p->f.m, f.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->f.e, f.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->b.m, b.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->b.e, b.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Chunk carries from the prefetched segments with a table of decays
+// lambda^(C d) (C the chunk length; mantissas in tdm, exponents in tde): the
+// forward carry of chunk b is the sum over c < b of lambda^(C (b-1-c)) F_c,
+// the backward one the sum over c > b of lambda^(C (c-b-1)) B_c.  The terms
+// are independent: each wave takes the largest exponent of its terms (an
+// integer max), sums the terms aligned to it in binary64, and the two waves
+// of a direction are combined in extended range (forward into scar[0],
+// backward into scar[1]).
+template <int CMAX>
+__device__ __forceinline__ void carry_finish_tab(const CarryItems<CMAX>& it, int b,
+                                                 const double* tdm, const int* tde, XF64* red4,
+                                                 XF64* scar) {
+  const bool fwd = threadIdx.x < kBlock / 2;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  double tm[CMAX];
+  int te[CMAX];
+  int emax = kExpZero;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    const int c = it.lo + i;
+    if (c < it.hi && it.m[i] != 0.0) {
+      const int d = fwd ? b - 1 - c : c - b - 1;
+      tm[i] = it.m[i] * tdm[d];
+      te[i] = it.e[i] + tde[d];
+      emax = max(emax, te[i]);
+    } else {
+      tm[i] = 0.0;
+      te[i] = kExpZero;
+    }
+  }
+  emax = wave_max(emax);
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) s += ldexp(tm[i], te[i] - emax);
+  s = wave_sum(s);
+  if (lane == 0) red4[w] = to64(xnorm(s, emax));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scar[0] = to64(xnorm(xadd(XF<double>{red4[0].m, red4[0].e}, XF<double>{red4[1].m, red4[1].e})));
+    scar[1] = to64(xnorm(xadd(XF<double>{red4[2].m, red4[2].e}, XF<double>{red4[3].m, red4[3].e})));
+  }
+  __syncthreads();
+}
+
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k) {
   __shared__ T sf[kNW];
@@ -112,6 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
   __shared__ XF64 scar[2];
   __shared__ XF64 red4[kNW];
   __shared__ int sdec;
+  __shared__ double tdm[kMaxPersistChunks];  // lambda^(C d), d = 0..nchunks-1
+  __shared__ int tde[kMaxPersistChunks];
 
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -136,6 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
 #pragma unroll
   for (int j = 0; j < R; ++j) pso[j] = ps[j];
 
+  for (int d = threadIdx.x; d < a.nchunks; d += kBlock) {
+    const XF<double> p = xnorm(pow_bits(d, a.cpow));
+    tdm[d] = p.m;
+    tde[d] = p.e;
+  }  // read after local_scan's barrier
   const Lam<T> L = lam_of<T>(k);
   const FastDec<T> D = make_fast_dec<T>(k, lane);
   HalfState<T, R> hs;
@@ -147,10 +225,13 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
     const bool check = (l % a.check_every) == 0;
     // ---------------- psi-half: psi <- nu / K^T phi ----------------
     local_scan<T, R>(ph, eph, L, D, sf, sb, smax, hs);
-    publish<T, true>(D, sf, sb, hs.ein, a.A0);
+    publish_coherent<T>(D, sf, sb, hs.ein, a.A0);
     if (!publish_sync(a.epoch, ++gen, a.nchunks, a.ctrl)) break;
-    // failures of the previous phi-half: that slot is written only before this
-    // barrier, so every workgroup reads the same value
+    // the carry loads and the failure flag of the previous phi-half travel
+    // together; that slot is written only before the wait, so every
+    // workgroup reads the same value
+    CarryItems<kCarryMaxP> items;
+    carry_prefetch<kCarryMaxP>(a.A0, blockIdx.x, a.nchunks, items, CoherentLoad());
     if (threadIdx.x == 0)
       sdec = __hip_atomic_load(&a.ctrl->fail_half[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -158,17 +239,22 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       failed = true;
       break;
     }
-    CarryItems<kCarryMaxP> items;
-    carry_prefetch<kCarryMaxP, true>(a.A0, blockIdx.x, a.nchunks, items);
-    carry_finish<kCarryMaxP>(items, blockIdx.x, a.cpow, red4, scar);
+    carry_finish_tab<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
     int eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     if (check) {
       double s = 0.0;
-      double nu64[R];
-      load_run<double, R>(a.nu, base, n, nu64, 0.0);
+      if constexpr (sizeof(T) == 8) {
+        // binary64: the registers already hold nu
 #pragma unroll
-      for (int j = 0; j < R; ++j)
-        if (base + j < n) s += fabs(ldexp(double(ps[j]) * double(y[j]), eps + eap) - nu64[j]);
+        for (int j = 0; j < R; ++j)
+          if (base + j < n) s += fabs(ldexp(ps[j] * y[j], eps + eap) - nu[j]);
+      } else {
+        double nu64[R];
+        load_run<double, R>(a.nu, base, n, nu64, 0.0);
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (base + j < n) s += fabs(ldexp(double(ps[j]) * double(y[j]), eps + eap) - nu64[j]);
+      }
       const double tot = block_sum<kNW>(s, red);
       if (threadIdx.x == 0)
         __hip_atomic_store(&a.part[blockIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -191,45 +277,52 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
 
     // ---------------- phi-half: phi <- mu / K psi ----------------
     local_scan<T, R>(ps, eps, L, D, sf, sb, smax, hs);
-    publish<T, true>(D, sf, sb, hs.ein, a.A1);
+    publish_coherent<T>(D, sf, sb, hs.ein, a.A1);
     if (!publish_sync(a.epoch, ++gen, a.nchunks, a.ctrl)) break;
-    // stopping test of iteration l (every workgroup sums the same shares in
-    // the same order) and the failure flag
-    if (threadIdx.x < kWave) {
-      // failures of this iteration's psi-half (slot written only before the barrier)
-      int dec = __hip_atomic_load(&a.ctrl->fail_half[0], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT) ? 2 : 0;
-      if (check && !dec) {
-        double s = 0.0;
-        for (int c = lane; c < a.nchunks; c += kWave)
-          s += __hip_atomic_load(&a.part[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = wave_sum(s);
-        if (lane == 0) {
-          if (blockIdx.x == 0) {
-            a.ctrl->last_err = s;
-            a.ctrl->last_check = l;
-            if (a.err_hist) a.err_hist[l] = s;
-          }
-          if (!(s > a.tol)) dec = 1;
+    // the carry loads, the failure flag of this iteration's psi-half (written
+    // only before the wait) and the error shares of its stopping test travel
+    // together; every thread sums its shares in chunk order and the block in
+    // wave order, so every workgroup takes the same decision
+    carry_prefetch<kCarryMaxP>(a.A1, blockIdx.x, a.nchunks, items, CoherentLoad());
+    {
+      double s = 0.0;
+      if (check) {
+#pragma unroll
+        for (int i = 0; i < kMaxPersistChunks / kBlock; ++i) {
+          const int c = int(threadIdx.x) + i * kBlock;
+          if (c < a.nchunks)
+            s += __hip_atomic_load(&a.part[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      if (lane == 0) sdec = dec;
+      if (threadIdx.x == 0)
+        sdec = __hip_atomic_load(&a.ctrl->fail_half[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s = wave_sum(s);
+      if (lane == 0) red[threadIdx.x / kWave] = s;
     }
     __syncthreads();
-    if (sdec == 2) {
+    if (sdec) {
       failed = true;
       break;
     }
-    if (sdec == 1) {
-      // stop with (phi^l, psi^l): undo this iteration's psi update
+    if (check) {
+      double err = 0.0;
 #pragma unroll
-      for (int j = 0; j < R; ++j) ps[j] = pso[j];
-      eps = epso;
-      stop_iter = l;
-      break;
+      for (int v = 0; v < kNW; ++v) err += red[v];
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctrl->last_err = err;
+        a.ctrl->last_check = l;
+        if (a.err_hist) a.err_hist[l] = err;
+      }
+      if (!(err > a.tol)) {
+        // stop with (phi^l, psi^l): undo this iteration's psi update
+#pragma unroll
+        for (int j = 0; j < R; ++j) ps[j] = pso[j];
+        eps = epso;
+        stop_iter = l;
+        break;
+      }
     }
-    carry_prefetch<kCarryMaxP, true>(a.A1, blockIdx.x, a.nchunks, items);
-    carry_finish<kCarryMaxP>(items, blockIdx.x, a.cpow, red4, scar);
+    carry_finish_tab<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
     eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     bad = false;
     const int ef = update_run<T, R>(mu, y, eap, q, bad);

@@ -255,6 +255,47 @@ def test_solve_full_size_f64_log(eps, path):
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_persistent_single_launch_full_size(dtype):
+    # N = 2^20 at eps 1e-3 to tol 1e-8 (1e-6 in binary32, whose rounding
+    # floor is near 1e-7): the persistent solver must take its one cooperative
+    # launch (512 chunks in binary64, 256 in binary32) and agree with the
+    # fused per-half kernels; only the summation order of the stopping error
+    # differs, so the stop may move by one iteration
+    fs1 = _fs1()
+    n = 1 << 20
+    tol = 1e-8 if dtype == "f64" else 1e-6
+    mu, nu = inputs.mixture_pair(n, inputs.random_k(1), 1)
+    ctx = fs1.Context()
+    ctx.set_profiling(1)
+    _say(f"persistent full size {dtype}")
+    r = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, tol, itr_max=5000, dtype=dtype, domain="log",
+                      solver="persistent", sync_every=64, ctx=ctx)
+    _, launches, _ = ctx.kernel_stats()
+    assert launches == 1
+    f = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, tol, itr_max=5000, dtype=dtype, domain="log",
+                      solver="fused", sync_every=64)
+    assert r.status == 0 and f.status == 0
+    assert r.iterations < 5000 and abs(r.iterations - f.iterations) <= 1
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    if r.iterations == f.iterations:
+        assert r.w1 == pytest.approx(f.w1, rel=rel)
+    # the stop test runs in the working precision, the reported error in
+    # binary64: in binary32 the two differ by a few per cent
+    assert r.marginal_err <= (tol if dtype == "f64" else 1.1 * tol)
+    # a fixed iteration count: same iterates, agreement to rounding
+    r = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=37, dtype=dtype, domain="log",
+                      solver="persistent", potentials=True)
+    f = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=37, dtype=dtype, domain="log",
+                      solver="fused", potentials=True)
+    assert r.iterations == f.iterations == 37
+    assert r.w1 == pytest.approx(f.w1, rel=rel)
+    assert r.marginal_err == pytest.approx(f.marginal_err, rel=1e-6 if dtype == "f64" else 1e-2)
+    m = nu > 0
+    tol_pot = 1e-9 if dtype == "f64" else 1e-3
+    assert np.max(np.abs(r.G.cpu().numpy()[m] - f.G.cpu().numpy()[m])) <= tol_pot
+
+
 @pytest.mark.parametrize("domain", ["plain", "log"])
 @pytest.mark.parametrize("dtype,n", [("f64", 2047), ("f64", 2048), ("f64", 2049), ("f64", 5000),
                                      ("f64", 8192), ("f32", 4096), ("f32", 4097), ("f32", 8192)])
