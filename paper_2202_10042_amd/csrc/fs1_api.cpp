@@ -635,6 +635,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.carry2 = w.take(nchunks * 48);
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
+    b.dtab = static_cast<XF64*>(w.take(nchunks * sizeof(XF64)));
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
     epoch = static_cast<int*>(w.take(size_t(std::max<int64_t>(nchunks, 1)) * sizeof(int)));
   };
@@ -703,6 +704,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
       !resident && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
   const bool fused =
       !resident && !persistent && !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+  if (fused || persistent) HIP_TRY(launch_decay_table(b, k, s));
   if (fused) HIP_TRY(launch_fused_init(b, k, s));
   if (persistent || resident) {
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -196,6 +196,13 @@ struct CarryItems {
   int lo, hi;  // segment [lo, hi)
 };
 
+// Decays lambda^(C d) of the items of a segment (carry_table).
+template <int CMAX>
+struct CarryDecays {
+  double m[CMAX];
+  int e[CMAX];
+};
+
 // Plain loads of published aggregates (a previous launch wrote them).
 struct PlainLoad {
   __device__ XF64 operator()(const XF64* p) const { return *p; }
@@ -225,6 +232,26 @@ __device__ __forceinline__ void carry_prefetch(const ChunkAgg* A, int b, int nch
   }
 }
 
+// The decays of a prefetched segment from the table tab[d] = lambda^(C d)
+// (C the chunk length): d = b-1-c forward, c-b-1 backward.
+template <int CMAX>
+__device__ __forceinline__ void carry_table(const XF64* tab, int b, const CarryItems<CMAX>& it,
+                                            CarryDecays<CMAX>& dc) {
+  const bool fwd = threadIdx.x < kBlock / 2;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    const int c = it.lo + i;
+    if (c < it.hi) {
+      const XF64 t = tab[fwd ? b - 1 - c : c - b - 1];
+      dc.m[i] = t.m;
+      dc.e[i] = t.e;
+    } else {
+      dc.m[i] = 0.0;
+      dc.e[i] = 0;
+    }
+  }
+}
+
 // Combine the prefetched segments: forward carry into scar[0], backward into
 // scar[1] (both extended-range, normalised).
 template <int CMAX>
@@ -250,6 +277,47 @@ __device__ __forceinline__ void carry_finish(const CarryItems<CMAX>& it, int b,
   }
   acc = wave_xsum(acc);
   if (lane == 0) red4[w] = to64(acc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scar[0] = to64(xnorm(xadd(XF<double>{red4[0].m, red4[0].e}, XF<double>{red4[1].m, red4[1].e})));
+    scar[1] = to64(xnorm(xadd(XF<double>{red4[2].m, red4[2].e}, XF<double>{red4[3].m, red4[3].e})));
+  }
+  __syncthreads();
+}
+
+// Combine the prefetched segments with their table decays (carry_table):
+// the forward carry of chunk b is the sum over c < b of
+// lambda^(C (b-1-c)) F_c, the backward one the sum over c > b of
+// lambda^(C (c-b-1)) B_c.  The terms are independent: each wave takes the
+// largest exponent of its terms (an integer max), sums the terms aligned to
+// it in binary64, and the two waves of a direction are combined in extended
+// range (forward into scar[0], backward into scar[1]).
+template <int CMAX>
+__device__ __forceinline__ void carry_finish_tab(const CarryItems<CMAX>& it,
+                                                 const CarryDecays<CMAX>& dc, XF64* red4,
+                                                 XF64* scar) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  double tm[CMAX];
+  int te[CMAX];
+  int emax = kExpZero;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    if (it.lo + i < it.hi && it.m[i] != 0.0) {
+      tm[i] = it.m[i] * dc.m[i];
+      te[i] = it.e[i] + dc.e[i];
+      emax = max(emax, te[i]);
+    } else {
+      tm[i] = 0.0;
+      te[i] = kExpZero;
+    }
+  }
+  emax = wave_max(emax);
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) s += ldexp(tm[i], te[i] - emax);
+  s = wave_sum(s);
+  if (lane == 0) red4[w] = to64(xnorm(s, emax));
   __syncthreads();
   if (threadIdx.x == 0) {
     scar[0] = to64(xnorm(xadd(XF<double>{red4[0].m, red4[0].e}, XF<double>{red4[1].m, red4[1].e})));

@@ -50,7 +50,7 @@ struct FusedArgs {
   int l;
   int check;
   double tol;
-  Decay cpow[20];         // lambda^(chunk length * 2^s)
+  const XF64* dtab;       // lambda^(chunk length * d), d < nchunks
 };
 
 template <typename T, int R, int MODE>
@@ -88,6 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
   }
   CarryItems<kCarryMax> items;
   carry_prefetch<kCarryMax>(a.A_in, blockIdx.x, a.nchunks, items);
+  CarryDecays<kCarryMax> decs;
+  carry_table<kCarryMax>(a.dtab, blockIdx.x, items, decs);
   // (every vector is allocated to whole chunks and zero past n: plain vector
   // loads)
   T x[R];
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
 
   // chunk carries first: they need only the aggregates, so this work runs
   // while the chunk's own data is still arriving
-  carry_finish<kCarryMax>(items, blockIdx.x, a.cpow, red4, scar);
+  carry_finish_tab<kCarryMax>(items, decs, red4, scar);
   const Lam<T> L = lam_of<T>(k);
   const FastDec<T> D = make_fast_dec<T>(k, lane);
   HalfState<T, R> hs;
@@ -217,8 +219,7 @@ struct FusedOps {
     a.n = b.n;
     a.nchunks = int(b.nchunks);
     a.tol = tol;
-    for (int i = 0; i < 20; ++i)
-      a.cpow[i] = make_decay(double(kBlock) * double(R) * double(1ll << i), k.c);
+    a.dtab = b.dtab;
     return a;
   }
   static hipError_t half(const SolveBufs& b, const ScanConsts& k, int l, int check, double tol,
@@ -295,6 +296,29 @@ template <typename F>
 hipError_t fused_dispatch(const SolveBufs& b, F&& f) {
   if (b.dtype == 0) return b.R == 4 ? f(FusedOps<double, 4>{}) : f(FusedOps<double, 8>{});
   return b.R == 8 ? f(FusedOps<float, 8>{}) : f(FusedOps<float, 16>{});
+}
+
+namespace {
+struct DecayTableArgs {
+  XF64* tab;
+  int n;
+  Decay cpow[20];  // lambda^(chunk length * 2^s)
+};
+
+__global__ __launch_bounds__(kBlock) void k_decay_table(DecayTableArgs a) {
+  const int d = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (d < a.n) a.tab[d] = to64(xnorm(pow_bits(d, a.cpow)));
+}
+}  // namespace
+
+hipError_t launch_decay_table(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
+  DecayTableArgs a{};
+  a.tab = b.dtab;
+  a.n = int(b.nchunks);
+  for (int i = 0; i < 20; ++i)
+    a.cpow[i] = make_decay(double(kBlock) * double(b.R) * double(1ll << i), k.c);
+  k_decay_table<<<unsigned((b.nchunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {

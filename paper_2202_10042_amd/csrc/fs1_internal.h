@@ -143,6 +143,7 @@ struct SolveBufs {
   ChunkAgg* carry;    // chunk carries of the current half
   void* agg2;         // two-state chunk aggregates (transport cost)
   void* carry2;       // two-state chunk carries (transport cost)
+  XF64* dtab;         // lambda^(chunk length * d), d < nchunks (fused / persistent carries)
   double* part;       // per-chunk partial sums (error / cost)
   double* part2;      // second partial array (mu-side error)
   Ctrl* ctrl;
@@ -175,6 +176,8 @@ bool usable_fused(const SolveBufs& b, double c);
 // Run length for the fused path at this size (0: the fused path does not apply).
 int fused_run_length(int dtype, double c, int64_t n);
 hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+// b.dtab[d] = lambda^(kBlock * b.R * d) for d < b.nchunks (fused and persistent solvers)
+hipError_t launch_decay_table(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
 hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
                              double tol, bool psi, hipStream_t s, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);

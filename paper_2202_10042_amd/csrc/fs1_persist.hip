@@ -58,7 +58,7 @@ struct PersistArgs {
   int itr_max;
   int check_every;
   double tol;
-  Decay cpow[20];         // lambda^(chunk length * 2^s)
+  const XF64* dtab;       // lambda^(chunk length * d), d < nchunks
 };
 
 // Publication of one half's chunk aggregates (and error shares) between
@@ -129,8 +129,8 @@ __device__ __forceinline__ void publish_coherent(const FastDec<T>& D, const T* s
   }
 }
 
-// Chunk carries from the prefetched segments with a table of decays
-// lambda^(C d) (C the chunk length; mantissas in tdm, exponents in tde): the
+// Chunk carries from the prefetched segments with the decay table in LDS
+// (lambda^(C d), C the chunk length; mantissas in tdm, exponents in tde): the
 // forward carry of chunk b is the sum over c < b of lambda^(C (b-1-c)) F_c,
 // the backward one the sum over c > b of lambda^(C (c-b-1)) B_c.  The terms
 // are independent: each wave takes the largest exponent of its terms (an
@@ -138,7 +138,7 @@ __device__ __forceinline__ void publish_coherent(const FastDec<T>& D, const T* s
 // of a direction are combined in extended range (forward into scar[0],
 // backward into scar[1]).
 template <int CMAX>
-__device__ __forceinline__ void carry_finish_tab(const CarryItems<CMAX>& it, int b,
+__device__ __forceinline__ void carry_finish_lds(const CarryItems<CMAX>& it, int b,
                                                  const double* tdm, const int* tde, XF64* red4,
                                                  XF64* scar) {
   const bool fwd = threadIdx.x < kBlock / 2;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
   for (int j = 0; j < R; ++j) pso[j] = ps[j];
 
   for (int d = threadIdx.x; d < a.nchunks; d += kBlock) {
-    const XF<double> p = xnorm(pow_bits(d, a.cpow));
+    const XF64 p = a.dtab[d];
     tdm[d] = p.m;
     tde[d] = p.e;
   }  // read after local_scan's barrier
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
       failed = true;
       break;
     }
-    carry_finish_tab<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
+    carry_finish_lds<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
     int eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     if (check) {
       double s = 0.0;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs a, ScanConsts k)
         break;
       }
     }
-    carry_finish_tab<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
+    carry_finish_lds<kCarryMaxP>(items, blockIdx.x, tdm, tde, red4, scar);
     eap = frame_apply<T, R>(L, D, sf, sb, scar, hs, y);
     bad = false;
     const int ef = update_run<T, R>(mu, y, eap, q, bad);
@@ -373,8 +373,7 @@ hipError_t persist_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int c
   a.itr_max = itr_max;
   a.check_every = check_every;
   a.tol = tol;
-  for (int i = 0; i < 20; ++i)
-    a.cpow[i] = make_decay(double(kBlock) * double(R) * double(1ll << i), k.c);
+  a.dtab = b.dtab;
   ScanConsts kk = k;
   void* args[] = {&a, &kk};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<T, R>),
