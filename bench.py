@@ -250,6 +250,24 @@ def main():
                                  "grid_pts_it_per_s": n * r.iterations / w})
                 log(f"variant {dt} eps={eps}: {r.iterations} it, err {r.marginal_err:.3e}, "
                     f"w1 {r.w1:.12g}, {w * 1e3:.1f} ms")
+        # the same workload in the other solvers: the threshold-absorption
+        # variant (tau = 1e3, general path) and the single-launch persistent one
+        for label, kw in (("absorb tau=1e3", dict(domain="absorb", tau=1e3)),
+                          ("persistent", dict(domain="log", solver="persistent"))):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fs1.fs1_solve(mu, nu, args.eps, args.tol, itr_max=args.itr_max, dtype="f64",
+                                  sync_every=64, ctx=ctx, **kw)
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+            variants.append({"dtype": "f64", "eps": args.eps, "solver": label,
+                             "iterations": r.iterations, "converged": r.converged,
+                             "marginal_err": r.marginal_err, "w1": r.w1,
+                             "absorptions": r.absorptions, "ms": round(w * 1e3, 2),
+                             "grid_pts_it_per_s": n * r.iterations / w})
+            log(f"variant {label}: {r.iterations} it, err {r.marginal_err:.3e}, "
+                f"w1 {r.w1:.12g}, {w * 1e3:.1f} ms")
         out["variants"] = variants
 
     if args.large:
@@ -287,7 +305,8 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
     """Sec. 5.1 (uniform random marginals on [-3, 3], eps = 1e-3, 1000
     iterations) and Sec. 5.2 (Ricker wavelets, eps = 1e-2, 500 iterations) at
     N = 500, 2000, 8000: binary64 solves with a fixed iteration count, plain
-    (as in the paper) and log domain; best of three timed solves each."""
+    (as in the paper), log domain and the threshold-absorption variant (tau =
+    1e3); best of three timed solves each."""
     spec = {"table1": (lambda n: inputs.paper_uniform_pair(n, 0), 1e-3, 1000),
             "table2": (lambda n: inputs.ricker_pair(n), 1e-2, 500)}
     rows = []
@@ -296,7 +315,7 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
             u, v, h = gen(n)
             mu = torch.tensor(u, dtype=torch.float64, device="cuda")
             nu = torch.tensor(v, dtype=torch.float64, device="cuda")
-            for domain in ("plain", "log"):
+            for domain in ("plain", "log", "absorb"):
                 best, r = None, None
                 for rep in range(4):
                     torch.cuda.synchronize()
@@ -310,6 +329,7 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
                 pf, pd = PAPER_TIMES[name][n]
                 rows.append({"workload": name, "n": n, "eps": eps, "iterations": r.iterations,
                              "domain": domain, "status": r.status, "w1": r.w1,
+                             "absorptions": r.absorptions,
                              "marginal_err": r.marginal_err, "gpu_s": best,
                              "paper_fs1_cpu_s": pf, "paper_dense_cpu_s": pd,
                              "speedup_vs_paper_fs1": pf / best})

@@ -68,8 +68,10 @@ typedef enum {
                       a finite threshold: scaled vectors phit, psit in the
                       working precision and binary64 potentials alpha, beta
                       (phi = e^{alpha/eps} phit), both absorbed whenever the
-                      largest scaled entry exceeds opts->tau; fs1_solve only,
-                      grids of at most 1024 runs (one workgroup) */
+                      largest scaled entry exceeds opts->tau; fs1_solve only;
+                      grids of at most 1024 runs in one workgroup, larger ones
+                      (or FS1_FLAG_GENERAL / FS1_FLAG_NO_RESIDENT) on the
+                      general path; FS1_FLAG_PERSISTENT is FS1_ERR_INVALID_ARG */
 } fs1_domain;
 
 typedef struct fs1_ctx fs1_ctx;

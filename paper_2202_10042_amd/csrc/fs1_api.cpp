@@ -23,6 +23,7 @@
 #include "fs1_batch.h"
 #include "fs1_host.h"
 #include "fs1_internal.h"
+#include "fs1_tau.h"
 
 using namespace fs1;
 
@@ -576,9 +577,9 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const bool tau_mode = o.domain == FS1_ABSORB;
   if (tau_mode && !(o.tau > 0.0 && std::isfinite(o.tau)))
     return finish(set_err(FS1_ERR_INVALID_ARG, "tau must be finite and > 0"));
-  if (tau_mode && (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT)))
+  if (tau_mode && (o.flags & FS1_FLAG_PERSISTENT))
     return finish(set_err(FS1_ERR_INVALID_ARG,
-                          "the absorption variant runs in the one-workgroup solver only"));
+                          "the absorption variant has no persistent solver"));
   if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
   if ((o.flags & 1) && !o.potentials_out)
     return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
@@ -596,12 +597,9 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
                      : resident_run_length(n, R);
   if (rr > 0) R = rr;
   const int res_threads = rr > 0 ? resident_threads(n, R) : 0;
-  if (tau_mode && res_threads == 0)
-    return finish(set_err(FS1_ERR_INVALID_ARG,
-                          "the absorption variant needs n <= 1024 runs (n = %lld, run %d)",
-                          (long long)n, R));
   // the fused one-launch-per-half path picks its own run length where it applies
-  if (res_threads == 0 && absorb && !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
+  if (res_threads == 0 && absorb && !tau_mode &&
+      !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
     const int rf = fused_run_length(dt, h / eps, n);
     if (rf > 0) R = rf;
   }
@@ -613,6 +611,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // workspace layout
   SolveBufs b{};
+  TauBufs tb{};
   int* epoch = nullptr;  // persistent solve: per-chunk publication flags
   const int64_t npad = nchunks * C;  // vectors are allocated to whole chunks
   double* mu64 = nullptr;
@@ -637,6 +636,13 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.dtab = static_cast<XF64*>(w.take(nchunks * sizeof(XF64)));
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
+    if (tau_mode) {  // (the one-workgroup solver does not use them)
+      tb.potF = static_cast<double*>(w.take(npad * sizeof(double)));
+      tb.potG = static_cast<double*>(w.take(npad * sizeof(double)));
+      tb.pmF = static_cast<double*>(w.take(nchunks * sizeof(double)));
+      tb.pmG = static_cast<double*>(w.take(nchunks * sizeof(double)));
+      tb.absorb = static_cast<int*>(w.take(sizeof(int)));
+    }
     epoch = static_cast<int*>(w.take(size_t(std::max<int64_t>(nchunks, 1)) * sizeof(int)));
   };
   {
@@ -700,10 +706,18 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   // Mid-size grids whose vectors fit in the registers of the co-resident
   // workgroups run all iterations in one cooperative launch.
   const bool resident = res_threads > 0 && usable_resident(b);
+  // the absorption variant runs the general path where the grid does not fit
+  // one workgroup
+  const bool tau_general = tau_mode && !resident;
   const bool persistent =
-      !resident && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
-  const bool fused =
-      !resident && !persistent && !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+      !resident && !tau_general && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
+  const bool fused = !resident && !persistent && !tau_general &&
+                     !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+  if (tau_general) {
+    tb.tau = o.tau;
+    tb.eps = eps;
+    HIP_TRY(launch_tau_init(b, tb, s));
+  }
   if (fused || persistent) HIP_TRY(launch_decay_table(b, k, s));
   if (fused) HIP_TRY(launch_fused_init(b, k, s));
   if (persistent || resident) {
@@ -753,6 +767,9 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
       if (fused) {
         HIP_TRY(launch_fused_half(b, k, l, check, tol, true, s));
         HIP_TRY(launch_fused_half(b, k, l, check, tol, false, s));
+      } else if (tau_general) {
+        HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, true, s));
+        HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, false, s));
       } else {
         HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s));
         HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s));
@@ -788,6 +805,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   // the persistent and resident kernels leave their final psi in buffer 0
   const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
 
+  if (tau_general) HIP_TRY(launch_tau_finish(b, tb, gbuf, s));
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));

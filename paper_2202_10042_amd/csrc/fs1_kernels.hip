@@ -23,6 +23,7 @@
 
 #include "fs1_device.h"
 #include "fs1_internal.h"
+#include "fs1_tau.h"
 
 namespace fs1 {
 
@@ -340,6 +341,13 @@ hipError_t launch_carry(const ChunkAgg* agg, ChunkAgg* carry, const CarryConsts&
   k_carry_top<MODE><<<1, kCarryBlock, 0, s>>>(gagg, gcar, int(ng), kc, ctrl, gpart, err_hist, l,
                                               check, tol);
   return hipGetLastError();
+}
+
+hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
+                              const CarryConsts& kc, Ctrl* ctrl, const double* part,
+                              double* err_hist, int l, int check, double tol, hipStream_t s) {
+  if (mode == 1) return launch_carry<1>(agg, carry, kc, ctrl, part, err_hist, l, check, tol, s);
+  return launch_carry<2>(agg, carry, kc, ctrl, part, err_hist, l, check, tol, s);
 }
 
 // ===========================================================================

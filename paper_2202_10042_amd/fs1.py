@@ -310,7 +310,8 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
 
     domain: "plain" (Algorithm 1 as printed), "log" (stabilised, absorption
     at every half-iteration) or "absorb" (the stabilisation with threshold
-    tau; grids of at most 1024 runs).
+    tau: one workgroup for n <= 1024 R, else the general path; no persistent
+    solver).
     solver: "auto" (the whole solve in one workgroup and one launch when
     n <= 1024 R, else fused one-launch-per-half kernels when they apply),
     "fused" (as "auto" without the one-workgroup solver), "general"

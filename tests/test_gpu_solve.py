@@ -415,7 +415,100 @@ def test_absorb_domain_arguments():
     with pytest.raises(fs1.Fs1Error):
         fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", tau=0.0)
     with pytest.raises(fs1.Fs1Error):
-        fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", solver="general")
-    big = dev(np.full(9000, 1.0 / 9000))
+        fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", tau=float("inf"))
     with pytest.raises(fs1.Fs1Error):
-        fs1.fs1_solve(big, big, 0.01, 0.0, itr_max=5, domain="absorb")
+        fs1.fs1_solve(x, x, 0.01, 0.0, itr_max=5, domain="absorb", solver="persistent")
+
+
+# The threshold form on the multi-workgroup (general) path.  One chunk carries
+# 256 R entries (R = 8 in binary64, 16 in binary32).  Grids that fit one
+# workgroup are sent to the general path by the solver choice and compared
+# with the stabilised oracle (absorption counts included); larger grids
+# (n = 20011, 300007, and 2^21 + 3, which has more than 1024 chunks in
+# binary64 and takes the two-level carry scan) are compared with the
+# log-domain oracle, whose iterates are the same in exact arithmetic (the
+# stabilised oracle's transport cost is a literal double sum, too slow there).
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,eps,its,tau", [(5000, 5e-4, 80, 1e3), (6007, 2e-4, 60, 10.0)])
+def test_absorb_general_path_against_oracle(dtype, n, eps, its, tau):
+    fs1 = _fs1()
+    mu, nu = inputs.mixture_pair(n, 4, n + 5)
+    h = 1.0 / n
+    _say(f"absorb general {dtype} n={n} eps={eps} tau={tau}")
+    ref = oracle.fs1_absorb(mu, nu, h, eps, tol=0.0, itr_max=its, tau=tau)
+    assert ref.status == 0 and ref.absorptions > 0
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="absorb",
+                      tau=tau, potentials=True, solver="general")
+    assert r.status == 0 and r.iterations == its
+    m = nu > 0
+    if dtype == "f64":
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.G[m])) <= 1e-8
+        assert np.max(np.abs(r.F.cpu().numpy()[mu > 0] - ref.F[mu > 0])) <= 1e-8
+        # the test max > tau is taken on values equal to rounding
+        assert abs(r.absorptions - ref.absorptions) <= 1
+    else:
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.G[m])) <= 1e-3
+        assert r.absorptions > 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,eps,its,tau", [(20011, 1e-4, 60, 1e3), (20011, 1e-4, 60, 10.0),
+                                          (300007, 2e-5, 40, 1e3), ((1 << 21) + 3, 1e-5, 8, 10.0)])
+def test_absorb_general_path_large(dtype, n, eps, its, tau):
+    fs1 = _fs1()
+    mu, nu = inputs.mixture_pair(n, 4, n + 5)
+    h = 1.0 / n
+    _say(f"absorb general large {dtype} n={n} eps={eps} tau={tau}")
+    ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="absorb",
+                      tau=tau, potentials=True)
+    assert r.status == 0 and r.iterations == its and r.absorptions > 0
+    m = nu > 0
+    if dtype == "f64":
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-9)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= 1e-8
+    else:
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= 1e-3
+
+
+def test_absorb_general_path_matches_one_workgroup():
+    # n = 4096 fits one workgroup; the general path must give the same
+    # iterates up to rounding and the same absorption count
+    fs1 = _fs1()
+    n = 4096
+    mu, nu = inputs.mixture_pair(n, 3, 17)
+    _say("absorb general vs one workgroup")
+    a = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=150, domain="absorb", tau=50.0,
+                      potentials=True)
+    b = fs1.fs1_solve(dev(mu), dev(nu), 1e-3, 0.0, itr_max=150, domain="absorb", tau=50.0,
+                      potentials=True, solver="general")
+    assert a.status == 0 and b.status == 0 and a.absorptions > 2
+    assert abs(a.absorptions - b.absorptions) <= 1
+    assert b.w1 == pytest.approx(a.w1, rel=1e-11)
+    m = nu > 0
+    assert np.max(np.abs(a.G.cpu().numpy()[m] - b.G.cpu().numpy()[m])) <= 1e-9
+
+
+def test_absorb_general_path_to_tolerance():
+    # to tolerance with frequent absorptions (tau = 2): the state returned at
+    # the stop must be consistent (absorbed vectors with their new
+    # potentials), and W, err and the stop iteration match the oracle's
+    fs1 = _fs1()
+    n = 12001
+    mu, nu = inputs.mixture_pair(n, 3, 9)
+    _say("absorb general to tolerance")
+    ref = oracle.fs1_log(mu, nu, 1.0 / n, 1e-2, tol=1e-8, itr_max=4000)
+    r = fs1.fs1_solve(dev(mu), dev(nu), 1e-2, 1e-8, itr_max=4000, domain="absorb", tau=2.0,
+                      potentials=True)
+    assert ref.converged and r.status == 0 and r.converged and r.absorptions > 10
+    assert abs(r.iterations - ref.iterations) <= 1
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-9)
+    assert r.marginal_err <= 1e-8
+    if r.iterations == ref.iterations:
+        m = nu > 0
+        assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= 1e-8
