@@ -609,6 +609,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));
   const int64_t nruns = nchunks * kBlock;
 
+  // grids small enough for the fused path (usable_fused decides later)
+  const bool fused_size = res_threads == 0 && absorb && !tau_mode && nchunks <= 1024;
   // workspace layout
   SolveBufs b{};
   TauBufs tb{};
@@ -635,6 +637,12 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.dtab = static_cast<XF64*>(w.take(nchunks * sizeof(XF64)));
+    if (fused_size) {  // the fused path's marginals in its tile layout
+      b.tmu = static_cast<double*>(w.take(npad * sizeof(double)));
+      b.tnu = static_cast<double*>(w.take(npad * sizeof(double)));
+      b.tmu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
+      b.tnu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
+    }
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
     if (tau_mode) {  // (the one-workgroup solver does not use them)
       tb.potF = static_cast<double*>(w.take(npad * sizeof(double)));
@@ -711,7 +719,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const bool tau_general = tau_mode && !resident;
   const bool persistent =
       !resident && !tau_general && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
-  const bool fused = !resident && !persistent && !tau_general &&
+  const bool fused = fused_size && !resident && !persistent && !tau_general &&
                      !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
   if (tau_general) {
     tb.tau = o.tau;
@@ -806,6 +814,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
 
   if (tau_general) HIP_TRY(launch_tau_finish(b, tb, gbuf, s));
+  if (fused) HIP_TRY(launch_fused_finish(b, gbuf, s));
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
