@@ -609,8 +609,6 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));
   const int64_t nruns = nchunks * kBlock;
 
-  // grids small enough for the fused path (usable_fused decides later)
-  const bool fused_size = res_threads == 0 && absorb && !tau_mode && nchunks <= 1024;
   // workspace layout
   SolveBufs b{};
   TauBufs tb{};
@@ -637,12 +635,6 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.part = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.part2 = static_cast<double*>(w.take(nchunks * sizeof(double)));
     b.dtab = static_cast<XF64*>(w.take(nchunks * sizeof(XF64)));
-    if (fused_size) {  // the fused path's marginals in its tile layout
-      b.tmu = static_cast<double*>(w.take(npad * sizeof(double)));
-      b.tnu = static_cast<double*>(w.take(npad * sizeof(double)));
-      b.tmu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
-      b.tnu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
-    }
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
     if (tau_mode) {  // (the one-workgroup solver does not use them)
       tb.potF = static_cast<double*>(w.take(npad * sizeof(double)));
@@ -719,8 +711,12 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const bool tau_general = tau_mode && !resident;
   const bool persistent =
       !resident && !tau_general && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
-  const bool fused = fused_size && !resident && !persistent && !tau_general &&
+  const bool fused = !resident && !persistent && !tau_general &&
                      !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
+  // the fused path, and the general path where solve_tiled(), iterate on the
+  // tile layout
+  const bool tiled =
+      fused || (!resident && !persistent && !tau_general && solve_tiled(b));
   if (tau_general) {
     tb.tau = o.tau;
     tb.eps = eps;
@@ -728,6 +724,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
   if (fused || persistent) HIP_TRY(launch_decay_table(b, k, s));
   if (fused) HIP_TRY(launch_fused_init(b, k, s));
+  if (tiled) HIP_TRY(launch_relayout(b, true, 0, s));
   if (persistent || resident) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
@@ -814,7 +811,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
 
   if (tau_general) HIP_TRY(launch_tau_finish(b, tb, gbuf, s));
-  if (fused) HIP_TRY(launch_fused_finish(b, gbuf, s));
+  if (tiled) HIP_TRY(launch_relayout(b, false, gbuf, s));
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));

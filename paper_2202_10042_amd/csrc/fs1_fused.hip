@@ -19,6 +19,7 @@
 #include "fs1_device.h"
 #include "fs1_frame.h"
 #include "fs1_internal.h"
+#include "fs1_tile.h"
 
 namespace fs1 {
 
@@ -31,89 +32,6 @@ constexpr double kFrameLog2Span32 = 80.0;
 
 enum FusedMode { F_PSI = 0, F_PHI = 1, F_ERR = 2 };
 
-// The fused path keeps its vectors in a wave-interleaved layout: the 64 runs
-// of R entries of a wavefront form a tile of 64 R entries in which entry j of
-// lane i's run sits at  tile + (j / V) 64 V + i V + j % V  (V entries per 16
-// bytes).  The k-th 16-byte load or store of every lane then covers one
-// contiguous kilobyte (per-thread runs would touch every 64-byte segment four
-// times, once per instruction), while each thread still holds its own run.
-// Tile of run `run`: entries from (run - lane) R.
-template <typename T, int R>
-__device__ __forceinline__ void tile_load(const T* __restrict__ p, int64_t run, int lane,
-                                          T (&x)[R]) {
-  constexpr int V = Vec16<T>::n;
-  static_assert(R % V == 0, "runs are whole 16-byte vectors");
-  using VT = typename Vec16<T>::type;
-  const VT* q = reinterpret_cast<const VT*>(p + (run - lane) * R) + lane;
-#pragma unroll
-  for (int i = 0; i < R / V; ++i) {
-    const VT v = q[i * kWave];
-    if constexpr (V == 2) {
-      x[2 * i] = v.x;
-      x[2 * i + 1] = v.y;
-    } else {
-      x[4 * i] = v.x;
-      x[4 * i + 1] = v.y;
-      x[4 * i + 2] = v.z;
-      x[4 * i + 3] = v.w;
-    }
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void tile_store(T* __restrict__ p, int64_t run, int lane,
-                                           const T (&x)[R]) {
-  constexpr int V = Vec16<T>::n;
-  static_assert(R % V == 0, "runs are whole 16-byte vectors");
-  using VT = typename Vec16<T>::type;
-  VT* q = reinterpret_cast<VT*>(p + (run - lane) * R) + lane;
-#pragma unroll
-  for (int i = 0; i < R / V; ++i) {
-    VT v;
-    if constexpr (V == 2) {
-      v.x = x[2 * i];
-      v.y = x[2 * i + 1];
-    } else {
-      v.x = x[4 * i];
-      v.y = x[4 * i + 1];
-      v.z = x[4 * i + 2];
-      v.w = x[4 * i + 3];
-    }
-    q[i * kWave] = v;
-  }
-}
-
-// In-place change of layout of a vector of whole chunks (runs -> tiles or
-// back).  A wave's tile holds exactly the wave's runs, and the barrier makes
-// every load of the workgroup complete before any store.
-template <typename T, int R, bool TO_TILES>
-__global__ __launch_bounds__(kBlock) void k_relayout(T* v) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  T x[R];
-  if constexpr (TO_TILES) {
-    load_run_z<T, R>(v, run * R, x);
-  } else {
-    tile_load<T, R>(v, run, lane, x);
-  }
-  __syncthreads();
-  if constexpr (TO_TILES) {
-    tile_store<T, R>(v, run, lane, x);
-  } else {
-    store_run_z<T, R>(v, run * R, x);
-  }
-}
-
-// Copy of a vector of whole chunks into the tile layout.
-template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_tile_copy(const T* __restrict__ src,
-                                                      T* __restrict__ dst) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  T x[R];
-  load_run_z<T, R>(src, run * R, x);
-  tile_store<T, R>(dst, run, lane, x);
-}
 
 struct FusedArgs {
   const void* vin;        // vector fed to K (values, per-run exponents)
@@ -174,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
   CarryDecays<kCarryMax> decs;
   carry_table<kCarryMax>(a.dtab, blockIdx.x, items, decs);
   // (every vector is allocated to whole chunks and zero past n, in the tile
-  // layout: plain vector loads)
+  // layout of fs1_tile.h: plain vector loads)
   T x[R];
   tile_load<T, R>(static_cast<const T*>(a.vin), run, lane, x);
   const int ex = a.ein[run];
@@ -314,8 +232,8 @@ struct FusedOps {
     if (psi) {
       a.vin = b.vF;
       a.ein = b.eF;
-      a.m64 = b.tnu;
-      a.m32 = static_cast<const float*>(b.tnu32);
+      a.m64 = b.nu;
+      a.m32 = static_cast<const float*>(b.nu32);
       a.vout = b.vG[nxt];
       a.eout = b.eG[nxt];
       a.vown = b.vG[cur];
@@ -325,8 +243,8 @@ struct FusedOps {
     } else {
       a.vin = b.vG[nxt];
       a.ein = b.eG[nxt];
-      a.m64 = b.tmu;
-      a.m32 = static_cast<const float*>(b.tmu32);
+      a.m64 = b.mu;
+      a.m32 = static_cast<const float*>(b.mu32);
       a.vout = b.vF;
       a.eout = b.eF;
       a.A_in = b.aggG;
@@ -338,28 +256,6 @@ struct FusedOps {
     else
       k_fused<T, R, F_PHI><<<unsigned(b.nchunks), kBlock, 0, s>>>(a, k);
     if (ev1) (void)hipEventRecord(ev1, s);
-    return hipGetLastError();
-  }
-  // the state and the marginals into the tile layout (after publish_state)
-  static hipError_t to_tiles(const SolveBufs& b, hipStream_t s) {
-    const unsigned g = unsigned(b.nchunks);
-    k_relayout<T, R, true><<<g, kBlock, 0, s>>>(static_cast<T*>(b.vF));
-    k_relayout<T, R, true><<<g, kBlock, 0, s>>>(static_cast<T*>(b.vG[0]));
-    k_tile_copy<double, R><<<g, kBlock, 0, s>>>(b.mu, b.tmu);
-    k_tile_copy<double, R><<<g, kBlock, 0, s>>>(b.nu, b.tnu);
-    if constexpr (sizeof(T) == 4) {
-      k_tile_copy<float, R><<<g, kBlock, 0, s>>>(static_cast<const float*>(b.mu32),
-                                                 static_cast<float*>(b.tmu32));
-      k_tile_copy<float, R><<<g, kBlock, 0, s>>>(static_cast<const float*>(b.nu32),
-                                                 static_cast<float*>(b.tnu32));
-    }
-    return hipGetLastError();
-  }
-  // the final state back to runs, for the common finalisation
-  static hipError_t from_tiles(const SolveBufs& b, int gbuf, hipStream_t s) {
-    const unsigned g = unsigned(b.nchunks);
-    k_relayout<T, R, false><<<g, kBlock, 0, s>>>(static_cast<T*>(b.vF));
-    k_relayout<T, R, false><<<g, kBlock, 0, s>>>(static_cast<T*>(b.vG[gbuf]));
     return hipGetLastError();
   }
   static hipError_t publish_state(const SolveBufs& b, const ScanConsts& k, const void* v,
@@ -442,15 +338,8 @@ hipError_t launch_decay_table(const SolveBufs& b, const ScanConsts& k, hipStream
 }
 
 hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
-  return fused_dispatch(b, [&](auto ops) {
-    const hipError_t e = decltype(ops)::publish_state(b, k, b.vF, b.eF, b.aggF, s);
-    if (e != hipSuccess) return e;
-    return decltype(ops)::to_tiles(b, s);
-  });
-}
-
-hipError_t launch_fused_finish(const SolveBufs& b, int gbuf, hipStream_t s) {
-  return fused_dispatch(b, [&](auto ops) { return decltype(ops)::from_tiles(b, gbuf, s); });
+  return fused_dispatch(
+      b, [&](auto ops) { return decltype(ops)::publish_state(b, k, b.vF, b.eF, b.aggF, s); });
 }
 
 hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,

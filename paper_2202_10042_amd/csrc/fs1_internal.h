@@ -144,10 +144,6 @@ struct SolveBufs {
   void* agg2;         // two-state chunk aggregates (transport cost)
   void* carry2;       // two-state chunk carries (transport cost)
   XF64* dtab;         // lambda^(chunk length * d), d < nchunks (fused / persistent carries)
-  double* tmu;        // fused path: mu, nu in its wave-interleaved tile layout (npad)
-  double* tnu;
-  void* tmu32;        // ... and their binary32 copies (dtype 1)
-  void* tnu32;
   double* part;       // per-chunk partial sums (error / cost)
   double* part2;      // second partial array (mu-side error)
   Ctrl* ctrl;
@@ -179,11 +175,7 @@ hipError_t launch_persistent(const SolveBufs& b, const ScanConsts& k, int itr_ma
 bool usable_fused(const SolveBufs& b, double c);
 // Run length for the fused path at this size (0: the fused path does not apply).
 int fused_run_length(int dtype, double c, int64_t n);
-// The initial aggregates, then the state (vF, vG[0]) and the marginals (into
-// tmu, tnu and their binary32 copies) to the fused path's tile layout;
-// launch_fused_finish turns the final state (vF, vG[gbuf]) back into runs.
 hipError_t launch_fused_init(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
-hipError_t launch_fused_finish(const SolveBufs& b, int gbuf, hipStream_t s);
 // b.dtab[d] = lambda^(kBlock * b.R * d) for d < b.nchunks (fused and persistent solvers)
 hipError_t launch_decay_table(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
 hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
@@ -192,6 +184,13 @@ hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int
 
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
 hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+// The fused path iterates on vectors in the tile layout of fs1_tile.h, and so
+// does the general path where solve_tiled() (binary64, run length a whole
+// number of 16-byte vectors): launch_relayout turns vF, vG[gbuf] and the
+// marginal copies (mu, nu and their binary32 copies) into tiles (to_tiles) or
+// back, in place.
+bool solve_tiled(const SolveBufs& b);
+hipError_t launch_relayout(const SolveBufs& b, bool to_tiles, int gbuf, hipStream_t s);
 // psi-half of iteration l: psi^{l+1} = nu / (K^T phi^l); error of (phi^l, psi^l)
 // when `check`.
 // ev0 / ev1 (optional): events recorded just before and just after the
