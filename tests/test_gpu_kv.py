@@ -175,6 +175,8 @@ def test_kv_invalid_arguments():
         fs1.fs1_kv_apply(x[1:], 0.1, 0.1)     # misaligned view
     with pytest.raises(fs1.Fs1Error):
         fs1.fs1_kv_apply(x, 0.1, 0.1, out=x)  # aliasing
+    with pytest.raises(fs1.Fs1Error):
+        fs1.fs1_kv_apply(x[:0], 0.1, 0.1)     # empty
 
 
 @pytest.mark.parametrize("eps", [1e-3, 1e-4])

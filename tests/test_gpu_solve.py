@@ -173,6 +173,11 @@ def test_solve_invalid_marginals():
         fs1.fs1_solve(dev(bad), dev(nu), 0.01, 0.0, itr_max=2)
     with pytest.raises(fs1.Fs1Error):
         fs1.fs1_solve(dev(np.zeros(n)), dev(np.zeros(n)), 0.01, 0.0, itr_max=2)
+    # an empty grid is an argument error, not a launch
+    empty = dev(np.zeros(0))
+    for domain in ("plain", "log", "absorb"):
+        with pytest.raises(fs1.Fs1Error):
+            fs1.fs1_solve(empty, empty, 0.01, 0.0, itr_max=2, domain=domain)
 
 
 @pytest.mark.parametrize("path", PATHS)
