@@ -596,7 +596,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
                      ? 0
                      : resident_run_length(n, R);
   if (rr > 0) R = rr;
-  const int res_threads = rr > 0 ? resident_threads(n, R) : 0;
+  const int res_threads = rr > 0 ? solve_resident_threads(n, R) : 0;
   // the fused one-launch-per-half path picks its own run length where it applies
   if (res_threads == 0 && absorb && !tau_mode &&
       !(o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT))) {
@@ -605,7 +605,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
   const int64_t C = int64_t(kBlock) * R;
   // the resident workgroup's runs are allocated whole
-  const int64_t nchunks = res_threads ? res_threads / kBlock : (n + C - 1) / C;
+  const int64_t nchunks = res_threads ? std::max(res_threads, kBlock) / kBlock : (n + C - 1) / C;
   if (nchunks > int64_t(INT32_MAX)) return finish(set_err(FS1_ERR_INVALID_ARG, "n too large"));
   const int64_t nruns = nchunks * kBlock;
 

@@ -339,6 +339,18 @@ __device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const 
   // exclusive values: the neighbouring lane's inclusive value (zero at the ends)
   const S exf = incf.template move<kDppWaveShr1>();
   const S exb = incb.template move<kDppWaveShl1>();
+  if constexpr (NW == 1) {
+    // one wavefront: its totals are read from its end lanes, no LDS exchange
+    if (cf) {
+      *cf = bcf.shift(lane_pow(lane, dec)).add(exf).norm();
+      *cb = bcb.shift(lane_pow(kWave - 1 - lane, dec)).add(exb).norm();
+    }
+    if (agg_f) {
+      *agg_f = incf.lane(kWave - 1).norm();
+      *agg_b = incb.lane(0).norm();
+    }
+    return;
+  }
   if (lane == kWave - 1) sh.f[w] = incf;
   if (lane == 0) sh.b[w] = incb;
   __syncthreads();
@@ -369,6 +381,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   v = wave_sum(v);
+  if constexpr (NW == 1) return v;  // one wavefront: every lane holds the sum
   if (lane == 0) sh[w] = v;
   __syncthreads();
   double t = 0.0;

@@ -212,6 +212,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   const int w = threadIdx.x / kWave;
 #pragma unroll
   for (int d = kWave / 2; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+  if constexpr (NW == 1) return v;  // one wavefront: every lane holds the maximum
   if (lane == 0) sh[w] = v;
   __syncthreads();
   double r = sh[0];

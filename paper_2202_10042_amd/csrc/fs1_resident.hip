@@ -6,6 +6,8 @@
 // no kernel boundary.  The arithmetic is the general path's (per-run
 // exponents renormalised every half in the log domain, plain floating point
 // otherwise), so the results agree with it to rounding.
+#include <algorithm>
+
 #include "fs1_device.h"
 #include "fs1_internal.h"
 #include "fs1_resident.h"
@@ -157,10 +159,15 @@ hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int 
   a.itr_max = itr_max;
   a.check_every = check_every;
   a.tol = tol;
-  const int nt = resident_threads(b.n, R);
+  const int nt = solve_resident_threads(b.n, R);
   const bool tau_mode = b.tau > 0.0;
   const double eps = 1.0 / b.inv_eps;
-  if (nt == 256) {
+  if (nt == kWave) {
+    if (tau_mode && ABSORB)
+      k_resident_tau<T, R, kWave><<<1, kWave, 0, s>>>(a, k, b.tau, eps);
+    else
+      k_resident<T, R, ABSORB, kWave><<<1, kWave, 0, s>>>(a, k);
+  } else if (nt == 256) {
     if (tau_mode && ABSORB)
       k_resident_tau<T, R, 256><<<1, 256, 0, s>>>(a, k, b.tau, eps);
     else
@@ -206,6 +213,13 @@ int resident_threads(int64_t n, int R) {
   return 0;
 }
 
+int solve_resident_threads(int64_t n, int R) {
+  // a grid of at most 64 runs is one wavefront: its scans and reductions never
+  // leave the wave's registers
+  if (n <= int64_t(kWave) * R) return kWave;
+  return resident_threads(n, R);
+}
+
 int resident_run_length(int64_t n, int rmax) {
   if (n <= int64_t(256) * rmax) return rmax;
   const int r = rmax < 8 ? rmax : 8;
@@ -215,9 +229,10 @@ int resident_run_length(int64_t n, int rmax) {
 bool usable_resident(const SolveBufs& b) {
   const bool r_ok = b.dtype == 0 ? (b.R == 8 || b.R == 1)
                                  : (b.R == 16 || b.R == 8 || b.R == 4 || b.R == 1);
-  const int nt = resident_threads(b.n, b.R);
-  // the state must cover whole allocated runs: nt threads x R entries
-  return r_ok && nt > 0 && b.npad == int64_t(nt) * b.R;
+  const int nt = solve_resident_threads(b.n, b.R);
+  // the allocation is whole chunks (at least one): nt threads x R entries
+  // rounded up to a chunk
+  return r_ok && nt > 0 && b.npad == int64_t(std::max(nt, kBlock)) * b.R;
 }
 
 hipError_t launch_resident(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,

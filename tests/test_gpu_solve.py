@@ -302,13 +302,15 @@ def test_persistent_single_launch_full_size(dtype):
 
 
 @pytest.mark.parametrize("domain", ["plain", "log"])
-@pytest.mark.parametrize("dtype,n", [("f64", 2047), ("f64", 2048), ("f64", 2049), ("f64", 5000),
-                                     ("f64", 8192), ("f32", 4096), ("f32", 4097), ("f32", 8192)])
+@pytest.mark.parametrize("dtype,n", [("f64", 511), ("f64", 512), ("f64", 513), ("f32", 1024),
+                                     ("f32", 1025), ("f64", 2047), ("f64", 2048), ("f64", 2049),
+                                     ("f64", 5000), ("f64", 8192), ("f32", 4096), ("f32", 4097),
+                                     ("f32", 8192)])
 def test_resident_workgroup_sizes(dtype, n, domain):
-    """The one-workgroup solver at the edges of its two workgroup sizes (256
-    threads up to 256 R entries, 1024 threads up to 1024 R with R <= 8)
-    against the oracle at a fixed iteration count and against the general
-    path (same arithmetic, other association order)."""
+    """The one-workgroup solver at the edges of its three workgroup sizes (one
+    wavefront up to 64 R entries, 256 threads up to 256 R, 1024 threads up to
+    1024 R with R <= 8) against the oracle at a fixed iteration count and
+    against the general path (same arithmetic, other association order)."""
     fs1 = _fs1()
     mu, nu = inputs.mixture_pair(n, 3, n)
     h = 1.0 / n
