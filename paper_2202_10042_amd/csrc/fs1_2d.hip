@@ -224,43 +224,51 @@ struct Res2Args {
 
 // one line of `len` entries at X[base + k stride]: Y = (forward + backward)
 // recursions, taken a group of entries at a time (16 binary32 / 8 binary64:
-// what the registers hold beside the state) so that each group's LDS loads
-// are issued together ahead of its dependent chain
+// what the registers hold beside the state): a whole group's LDS loads are
+// issued together, unconditionally, ahead of its dependent chain, and the
+// entries past the last whole group follow one at a time
 template <typename T>
 __device__ __forceinline__ void seq_line(const T* X, T* Y, int base, int stride, int len, T lam) {
-  constexpr int kSeqGroup = sizeof(T) == 8 ? 8 : 16;
+  constexpr int G = sizeof(T) == 8 ? 8 : 16;
   T r = T(0);
-  for (int k0 = 0; k0 < len; k0 += kSeqGroup) {
-    T v[kSeqGroup];
+  int k = 0;
+  for (; k + G <= len; k += G) {
+    T v[G];
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u)
-      v[u] = (k0 + u < len) ? X[base + (k0 + u) * stride] : T(0);
+    for (int u = 0; u < G; ++u) v[u] = X[base + (k + u) * stride];
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u) {
+    for (int u = 0; u < G; ++u) {
       r = lam * r + v[u];
       v[u] = r;
     }
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u)
-      if (k0 + u < len) Y[base + (k0 + u) * stride] = v[u];
+    for (int u = 0; u < G; ++u) Y[base + (k + u) * stride] = v[u];
   }
+  for (; k < len; ++k) {
+    r = lam * r + X[base + k * stride];
+    Y[base + k * stride] = r;
+  }
+  // backward: Y_k += q_k with q_{len-1} = 0, q_k = lam (q_{k+1} + X_{k+1})
   T q = T(0);
-  for (int k0 = len - 1; k0 >= 0; k0 -= kSeqGroup) {
-    T v[kSeqGroup], w[kSeqGroup];
+  k = len - 1;
+  for (; k + 1 >= G; k -= G) {
+    T v[G], w[G];
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u) {
-      const bool in = k0 - u >= 0;
-      v[u] = in ? X[base + (k0 - u) * stride] : T(0);
-      w[u] = in ? Y[base + (k0 - u) * stride] : T(0);
+    for (int u = 0; u < G; ++u) {
+      v[u] = X[base + (k - u) * stride];
+      w[u] = Y[base + (k - u) * stride];
     }
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u) {
+    for (int u = 0; u < G; ++u) {
       w[u] += q;
       q = lam * (q + v[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kSeqGroup; ++u)
-      if (k0 - u >= 0) Y[base + (k0 - u) * stride] = w[u];
+    for (int u = 0; u < G; ++u) Y[base + (k - u) * stride] = w[u];
+  }
+  for (; k >= 0; --k) {
+    Y[base + k * stride] += q;
+    q = lam * (q + X[base + k * stride]);
   }
 }
 
