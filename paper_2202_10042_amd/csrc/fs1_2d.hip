@@ -47,6 +47,13 @@ struct LineArgs {
   int l;                // iteration (failure record)
   int check;            // UPDATE: also the error share of Algorithm 2's stopping test
   int guard;            // return at once once the solve has stopped or failed
+  // APPLY with decide: first take the stop decision of iteration l from the
+  // nparts shares in part (every workgroup sums them in the same order;
+  // workgroup 0 records it) and return at once when it stops
+  int decide;
+  int nparts;
+  double tol;
+  double* err_hist;
 };
 
 template <typename T, int R, int NT, int MODE>
@@ -55,7 +62,29 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   __shared__ ScanLds<S1<T>, NW> sh;
   __shared__ ScanLds<S2<T>, NW> sh2;
   __shared__ double red[NW];
+  __shared__ int sstop;
   if (a.guard && (a.ctrl->done || a.ctrl->fail)) return;  // the same value in every thread
+  if constexpr (MODE == L_APPLY) {
+    if (a.decide) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < a.nparts; i += NT) s += a.part[i];
+      const double tot = block_sum<NW>(s, red);  // valid in thread 0
+      if (threadIdx.x == 0) {
+        sstop = !(tot > a.tol);
+        if (blockIdx.x == 0) {
+          a.ctrl->last_err = tot;
+          a.ctrl->last_check = a.l;
+          if (a.err_hist) a.err_hist[a.l] = tot;
+          if (sstop) {
+            a.ctrl->stop_iter = a.l;
+            a.ctrl->done = 1;
+          }
+        }
+      }
+      __syncthreads();
+      if (sstop) return;
+    }
+  }
   const int64_t base = int64_t(blockIdx.x) * a.line_step;
   const int p0 = int(threadIdx.x) * R;
   const T* xin = static_cast<const T*>(a.x);
@@ -139,26 +168,6 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     if (bad) {
       atomicOr(&a.ctrl->fail, 1);
       atomicMin(&a.ctrl->fail_iter, a.l);
-    }
-  }
-}
-
-// Stop decision of Algorithm 2 for iteration l: err(l) is the fixed-order sum
-// of the per-line shares the psi-half wrote.
-__global__ __launch_bounds__(256) void k_decide2(const double* part, int nlines, Ctrl* ctrl,
-                                                 double tol, int l, double* err_hist) {
-  __shared__ double red[4];
-  if (ctrl->done || ctrl->fail) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nlines; i += 256) s += part[i];
-  const double tot = block_sum<4>(s, red);
-  if (threadIdx.x == 0) {
-    ctrl->last_err = tot;
-    ctrl->last_check = l;
-    if (err_hist) err_hist[l] = tot;
-    if (!(tot > tol)) {
-      ctrl->stop_iter = l;
-      ctrl->done = 1;
     }
   }
 }
@@ -450,7 +459,10 @@ hipError_t run_pass(const Axis& ax, LineArgs a, hipStream_t s) {
   a.stride = ax.stride;
   a.len = ax.len;
   const unsigned g = unsigned(ax.nlines);
-  if (ax.len <= 256 * kR2) {
+  if (ax.len <= kWave * kR2) {
+    // one wavefront: its scans and reductions stay in registers
+    k_line<T, kR2, kWave, MODE><<<g, kWave, 0, s>>>(a, ax.k);
+  } else if (ax.len <= 256 * kR2) {
     k_line<T, kR2, 256, MODE><<<g, 256, 0, s>>>(a, ax.k);
   } else {
     k_line<T, kR2, 1024, MODE><<<g, 1024, 0, s>>>(a, ax.k);
@@ -536,16 +548,24 @@ struct Ops2 {
     a.check = check;
     return run_pass<T, L_UPDATE>(g.ax2, a, s);
   }
-  // phi^{l+1} = mu / K psi^{l+1}
-  static hipError_t phi_half(const Grid2& g, const Bufs2& b, int l, hipStream_t s) {
+  // phi^{l+1} = mu / K psi^{l+1}; when checked, its first pass takes the stop
+  // decision of iteration l from the psi-half's shares first
+  static hipError_t phi_half(const Grid2& g, const Bufs2& b, int l, int check, double tol,
+                             double* err_hist, hipStream_t s) {
     LineArgs a{};
     a.ctrl = b.ctrl;
     a.guard = 1;
     a.l = l;
     a.x = b.vG[(l + 1) & 1];
     a.y = b.t;
+    a.decide = check;
+    a.part = b.part;
+    a.nparts = int(g.ax2.nlines);
+    a.tol = tol;
+    a.err_hist = err_hist;
     hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
     if (e != hipSuccess) return e;
+    a.decide = 0;
     a.x = b.t;
     a.y = b.vF;
     a.m64 = b.mu;
@@ -764,11 +784,9 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     for (; l < l_end; ++l) {
       const int check = (l % o.check_every) == 0;
       HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::psi_half(g, b, l, check, s); }));
-      if (check) {
-        k_decide2<<<1, 256, 0, s>>>(b.part, int(g.ax2.nlines), b.ctrl, tol, l, o.err_history);
-        HIP_TRY(hipGetLastError());
-      }
-      HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::phi_half(g, b, l, s); }));
+      HIP_TRY(dispatch2(dt, [&](auto ops) {
+        return decltype(ops)::phi_half(g, b, l, check, tol, o.err_history, s);
+      }));
     }
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
