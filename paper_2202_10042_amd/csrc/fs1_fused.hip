@@ -2,8 +2,9 @@
 //
 // Each workgroup owns one chunk.  A launch of k_fused
 //   * recomputes its chunk carries from the chunk aggregates the previous
-//     launch published (the whole workgroup, extended range), while the
-//     chunk's own data is still arriving,
+//     launch published (the whole workgroup, as independent terms weighted by
+//     the per-solve table of decays lambda^(C d), in extended range), while
+//     the chunk's own data is still arriving,
 //   * runs the in-chunk recursions of Sec. 3, eq. (recursion) on a per-chunk
 //     frame (fs1_frame.h),
 //   * writes its share of the stopping error (psi-half of checked iterations),
@@ -15,7 +16,9 @@
 //     phi = mu / K psi), stores it and publishes the chunk aggregates of the
 //     new vector for the next launch.
 // Launches after the stop still do the arithmetic but store nothing.  Kernel
-// boundaries order everything: no inter-workgroup waiting.
+// boundaries order everything: no inter-workgroup waiting.  The vectors and
+// marginals are in the tile layout of fs1_tile.h throughout the fused
+// iterations (converted in place before the first launch and after the last).
 #include "fs1_device.h"
 #include "fs1_frame.h"
 #include "fs1_internal.h"
