@@ -260,6 +260,31 @@ def test_solve_full_size_f64_log(eps, path):
     assert r32.status == 0 and r32.w1 == pytest.approx(ref.w1, rel=1e-5)
 
 
+@pytest.mark.parametrize("dtype,c", [("f64", 0.5), ("f64", 0.05), ("f32", 0.02), ("f32", 0.005)])
+def test_fused_run_lengths(dtype, c):
+    # the fused path's run length follows h/eps = c (binary64: 8 entries while
+    # a chunk frame of 2048 entries fits, else 4; binary32: 16, else 8), on a
+    # ragged grid of several chunks, against the log-domain oracle
+    fs1 = _fs1()
+    n = 30011
+    h = 1.0 / n
+    eps = h / c
+    mu, nu = inputs.mixture_pair(n, 3, 77)
+    _say(f"fused run lengths {dtype} c={c}")
+    its = 25
+    ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="log",
+                      potentials=True, solver="fused")
+    g = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype=dtype, domain="log",
+                      solver="general")
+    assert r.status == 0 and r.iterations == its
+    rel = 1e-10 if dtype == "f64" else 1e-5
+    assert r.w1 == pytest.approx(ref.w1, rel=rel)
+    assert r.w1 == pytest.approx(g.w1, rel=1e-12 if dtype == "f64" else 1e-5)
+    m = nu > 0
+    assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= (1e-9 if dtype == "f64" else 1e-4)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_persistent_single_launch_full_size(dtype):
     # N = 2^20 at eps 1e-3 to tol 1e-8 (1e-6 in binary32, whose rounding
