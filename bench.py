@@ -38,7 +38,8 @@ N_C2 = 1 << 20
 SEED = 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_10042_amd", "csrc", f)
-                  for f in ("fs1_fused.hip", "fs1_frame.h", "fs1_device.h", "fs1_internal.h")]
+                  for f in ("fs1_fused.hip", "fs1_frame.h", "fs1_device.h", "fs1_internal.h",
+                            "fs1_tile.h")]
 
 
 def log(*a):

@@ -188,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
     atomicOr(&a.ctrl->fail, 1);
     atomicMin(&a.ctrl->fail_iter, a.l);
   }
-  tile_store<T, R>(static_cast<T*>(a.vout), run, lane, q);
-  a.eout[run] = -eap;
+  tile_store_nt<T, R>(static_cast<T*>(a.vout), run, lane, q);
+  __builtin_nontemporal_store(-eap, &a.eout[run]);
   // aggregates of the new vector for the next launch, and the error share
   publish_frame<T, R>(q, -eap, L, D, sf, sb, a.A_out, es, red, want_err ? a.part : nullptr);
 }

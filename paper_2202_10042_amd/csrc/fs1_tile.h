@@ -36,6 +36,21 @@ __device__ __forceinline__ void tile_load(const T* __restrict__ p, int64_t run, 
   }
 }
 
+// Non-temporal stores of a run in the tile layout: the lines are not left
+// dirty in the XCD's L2 for the write-back at the end of the kernel (the
+// fused path's new vectors; 3.9% per iteration at N = 2^20 in binary64).
+template <typename T, int R>
+__device__ __forceinline__ void tile_store_nt(T* __restrict__ p, int64_t run, int lane,
+                                              const T (&x)[R]) {
+  constexpr int V = Vec16<T>::n;
+  static_assert(R % V == 0, "runs are whole 16-byte vectors");
+  T* q = p + (run - lane) * R + lane * V;
+#pragma unroll
+  for (int i = 0; i < R / V; ++i)
+#pragma unroll
+    for (int u = 0; u < V; ++u) __builtin_nontemporal_store(x[i * V + u], q + i * kWave * V + u);
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void tile_store(T* __restrict__ p, int64_t run, int lane,
                                            const T (&x)[R]) {
