@@ -299,7 +299,8 @@ def fs1_absorb(mu, nu, h, eps, tol=0.0, itr_max=1000, tau=1e3) -> AbsorbResult:
     """Stabilised FS-1 (Sec. 2 and Sec. 3 remarks): absorbed potentials alpha,
     beta and scaled vectors, absorption whenever max(phit) or max(psit) > tau,
     the products with the rescaled kernel by the recursions with per-element
-    coefficients that replace lines 5-6 and 10-11 of Algorithm 1."""
+    coefficients that replace the recursions of the two kernel products of
+    Algorithm 1."""
     mu, nu = _f64(mu), _f64(nu)
     n = mu.size
     phit, psit, alpha, beta = (np.empty(n) for _ in range(4))

@@ -537,7 +537,7 @@ int or_fs1_log(int64_t n, const double *mu, const double *nu, double h, double e
 /* (the remark writes alpha += ln phi; with K rescaled by e^{alpha/eps} the   */
 /* consistent update carries the factor eps).  Entries that are exactly zero  */
 /* (zero marginal) stay zero and keep their potential.  The products with Kt  */
-/* use the recursions that replace lines 5-6 and 10-11 of Algorithm 1:        */
+/* use the recursions that replace those of Algorithm 1's two products:      */
 /*   r_{i+1} = lambda e^{(beta_{i+1}-beta_i)/eps} r_i                          */
 /*             + e^{(alpha_{i+1}+beta_{i+1})/eps} phit_{i+1}                   */
 /*   s_i     = lambda e^{(beta_i-beta_{i+1})/eps}                              */
