@@ -131,7 +131,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); libfs1 has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
