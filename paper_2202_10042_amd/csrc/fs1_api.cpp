@@ -592,9 +592,16 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const size_t es = dt == FS1_F64 ? 8 : 4;
   int R = pick_run_length(dt, absorb, h / eps);
   // grids of at most 1024 runs: the whole solve in one resident workgroup
-  const int rr = (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT))
-                     ? 0
-                     : resident_run_length(n, R);
+  int rr = (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT))
+               ? 0
+               : resident_run_length(n, R);
+  // binary64 grids of 2049 to 8192 entries: runs of 16 on 256 or 512 threads
+  // instead of runs of 8 on 1024 threads (fewer waves in every workgroup-wide
+  // step; below 2049 entries runs of 8 on fewer threads are faster).  The
+  // threshold variant keeps runs of 8.
+  if (rr == 8 && dt == FS1_F64 && !tau_mode && n > int64_t(256) * 8 &&
+      n <= int64_t(512) * 16 && (!absorb || 15.0 * (h / eps) <= 600.0))
+    rr = 16;
   if (rr > 0) R = rr;
   const int res_threads = rr > 0 ? solve_resident_threads(n, R) : 0;
   // the fused one-launch-per-half path picks its own run length where it applies

@@ -1035,6 +1035,8 @@ struct SolveOps {
 template <typename F>
 static hipError_t dispatch(const SolveBufs& b, F&& f) {
   if (b.dtype == 0) {
+    if (b.R == 16)
+      return b.absorb ? f(SolveOps<double, 16, true>{}) : f(SolveOps<double, 16, false>{});
     if (b.R == 8) return b.absorb ? f(SolveOps<double, 8, true>{}) : f(SolveOps<double, 8, false>{});
     if (b.R == 4) return b.absorb ? f(SolveOps<double, 4, true>{}) : f(SolveOps<double, 4, false>{});
     return b.absorb ? f(SolveOps<double, 1, true>{}) : f(SolveOps<double, 1, false>{});

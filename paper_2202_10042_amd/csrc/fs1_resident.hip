@@ -142,6 +142,11 @@ __global__ __launch_bounds__(NT) void k_resident_tau(ResidentArgs a, ScanConsts 
   }
 }
 
+// run lengths the threshold variant is built for (binary64 runs of 16 are
+// chosen only for the log and plain domains)
+template <typename T, int R>
+constexpr bool kTauRuns = !(sizeof(T) == 8 && R == 16);
+
 template <typename T, int R, bool ABSORB>
 hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,
                       double tol, hipStream_t s) {
@@ -163,15 +168,31 @@ hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int 
   const bool tau_mode = b.tau > 0.0;
   const double eps = 1.0 / b.inv_eps;
   if (nt == kWave) {
-    if (tau_mode && ABSORB)
-      k_resident_tau<T, R, kWave><<<1, kWave, 0, s>>>(a, k, b.tau, eps);
-    else
-      k_resident<T, R, ABSORB, kWave><<<1, kWave, 0, s>>>(a, k);
+    if constexpr (kTauRuns<T, R>) {
+      if (tau_mode && ABSORB) {
+        k_resident_tau<T, R, kWave><<<1, kWave, 0, s>>>(a, k, b.tau, eps);
+        return hipGetLastError();
+      }
+    }
+    if (tau_mode) return hipErrorInvalidValue;
+    k_resident<T, R, ABSORB, kWave><<<1, kWave, 0, s>>>(a, k);
   } else if (nt == 256) {
-    if (tau_mode && ABSORB)
-      k_resident_tau<T, R, 256><<<1, 256, 0, s>>>(a, k, b.tau, eps);
-    else
-      k_resident<T, R, ABSORB, 256><<<1, 256, 0, s>>>(a, k);
+    if constexpr (kTauRuns<T, R>) {
+      if (tau_mode && ABSORB) {
+        k_resident_tau<T, R, 256><<<1, 256, 0, s>>>(a, k, b.tau, eps);
+        return hipGetLastError();
+      }
+    }
+    if (tau_mode) return hipErrorInvalidValue;
+    k_resident<T, R, ABSORB, 256><<<1, 256, 0, s>>>(a, k);
+  } else if (nt == 512) {
+    // binary64 runs of 16 in the log or plain domain only
+    if constexpr (R == 16 && sizeof(T) == 8) {
+      if (tau_mode) return hipErrorInvalidValue;
+      k_resident<T, R, ABSORB, 512><<<1, 512, 0, s>>>(a, k);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if constexpr (R <= 8) {
     if (nt != 1024) return hipErrorInvalidValue;
     if (tau_mode && ABSORB)
@@ -189,6 +210,7 @@ hipError_t resident_r(const SolveBufs& b, const ScanConsts& k, int itr_max, int 
                       double tol, hipStream_t s) {
   if constexpr (sizeof(T) == 8) {
     switch (b.R) {
+      case 16: return resident_t<T, 16, ABSORB>(b, k, itr_max, check_every, tol, s);
       case 8: return resident_t<T, 8, ABSORB>(b, k, itr_max, check_every, tol, s);
       case 1: return resident_t<T, 1, ABSORB>(b, k, itr_max, check_every, tol, s);
       default: return hipErrorInvalidValue;
@@ -217,6 +239,9 @@ int solve_resident_threads(int64_t n, int R) {
   // a grid of at most 64 runs is one wavefront: its scans and reductions never
   // leave the wave's registers
   if (n <= int64_t(kWave) * R) return kWave;
+  if (n <= int64_t(256) * R) return 256;
+  // binary64 runs of 16 (chosen for grids above 2048 entries): 512 threads
+  if (R == 16 && n <= int64_t(512) * R) return 512;
   return resident_threads(n, R);
 }
 
@@ -227,7 +252,7 @@ int resident_run_length(int64_t n, int rmax) {
 }
 
 bool usable_resident(const SolveBufs& b) {
-  const bool r_ok = b.dtype == 0 ? (b.R == 8 || b.R == 1)
+  const bool r_ok = b.dtype == 0 ? (b.R == 16 || b.R == 8 || b.R == 1)
                                  : (b.R == 16 || b.R == 8 || b.R == 4 || b.R == 1);
   const int nt = solve_resident_threads(b.n, b.R);
   // the allocation is whole chunks (at least one): nt threads x R entries

@@ -329,13 +329,15 @@ def test_persistent_single_launch_full_size(dtype):
 @pytest.mark.parametrize("domain", ["plain", "log"])
 @pytest.mark.parametrize("dtype,n", [("f64", 511), ("f64", 512), ("f64", 513), ("f32", 1024),
                                      ("f32", 1025), ("f64", 2047), ("f64", 2048), ("f64", 2049),
-                                     ("f64", 5000), ("f64", 8192), ("f32", 4096), ("f32", 4097),
-                                     ("f32", 8192)])
+                                     ("f64", 4096), ("f64", 4097), ("f64", 5000), ("f64", 8192),
+                                     ("f64", 8193), ("f32", 4096), ("f32", 4097), ("f32", 8192)])
 def test_resident_workgroup_sizes(dtype, n, domain):
-    """The one-workgroup solver at the edges of its three workgroup sizes (one
+    """The one-workgroup solver at the edges of its workgroup sizes (one
     wavefront up to 64 R entries, 256 threads up to 256 R, 1024 threads up to
-    1024 R with R <= 8) against the oracle at a fixed iteration count and
-    against the general path (same arithmetic, other association order)."""
+    1024 R with R <= 8; binary64 grids of 2049 to 8192 entries take runs of 16
+    on 256 or 512 threads) against the oracle at a fixed iteration count and
+    against the general path (same arithmetic, other association order).  A
+    grid of 8193 binary64 entries is past the one-workgroup limit."""
     fs1 = _fs1()
     mu, nu = inputs.mixture_pair(n, 3, n)
     h = 1.0 / n
