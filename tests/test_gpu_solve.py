@@ -371,6 +371,33 @@ def test_resident_workgroup_sizes(dtype, n, domain):
     assert abs(t.iterations - tg.iterations) <= slack
 
 
+@pytest.mark.parametrize("c", [39.0, 41.0])
+def test_resident_runs_of_16_exponent_bound(c):
+    """Binary64 log-domain grids of 2049 to 8192 entries take runs of 16 only
+    while 15 h/eps stays inside the scaled arithmetic's exponent range (h/eps
+    <= 40); beyond it they keep runs of 8 on 1024 threads.  Both sides of the
+    bound against the oracle and the general path."""
+    fs1 = _fs1()
+    n, its = 3000, 20
+    mu, nu = inputs.mixture_pair(n, 3, 7)
+    h = 1.0 / n
+    eps = h / c
+    _say(f"resident runs of 16 bound c={c}")
+    ref = oracle.fs1_log(mu, nu, h, eps, tol=0.0, itr_max=its)
+    r = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f64", domain="log",
+                      potentials=True)
+    g = fs1.fs1_solve(dev(mu), dev(nu), eps, 0.0, itr_max=its, dtype="f64", domain="log",
+                      solver="general")
+    assert r.status == 0 and g.status == 0 and r.iterations == its
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+    assert r.w1 == pytest.approx(g.w1, rel=1e-12)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+    m = nu > 0
+    # at eps = h / 40 the potentials reach a few hundred: the bound is relative
+    scale = max(1.0, float(np.max(np.abs(ref.b[m]))))
+    assert np.max(np.abs(r.G.cpu().numpy()[m] - ref.b[m])) <= 1e-11 * scale
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_solve_two_level_carries_general_path(dtype):
     """A grid of more than 1024 chunks on the general path (two-level carries)
