@@ -595,12 +595,14 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   int rr = (o.flags & (FS1_FLAG_GENERAL | FS1_FLAG_PERSISTENT | FS1_FLAG_NO_RESIDENT))
                ? 0
                : resident_run_length(n, R);
-  // binary64 grids of 2049 to 8192 entries: runs of 16 on 256 or 512 threads
-  // instead of runs of 8 on 1024 threads (fewer waves in every workgroup-wide
-  // step; below 2049 entries runs of 8 on fewer threads are faster).  The
+  // runs of 16 on 256 or 512 threads instead of runs of 8 on 1024 threads
+  // (fewer waves in every workgroup-wide step): binary64 grids of 2049 to
+  // 8192 entries (below 2049 entries runs of 8 on fewer threads are faster),
+  // binary32 grids of 4097 to 8192 entries where its run length is 16.  The
   // threshold variant keeps runs of 8.
-  if (rr == 8 && dt == FS1_F64 && !tau_mode && n > int64_t(256) * 8 &&
-      n <= int64_t(512) * 16 && (!absorb || 15.0 * (h / eps) <= 600.0))
+  if (rr == 8 && !tau_mode && n <= int64_t(512) * 16 &&
+      ((dt == FS1_F64 && n > int64_t(256) * 8 && (!absorb || 15.0 * (h / eps) <= 600.0)) ||
+       (dt == FS1_F32 && R == 16)))
     rr = 16;
   if (rr > 0) R = rr;
   const int res_threads = rr > 0 ? solve_resident_threads(n, R) : 0;

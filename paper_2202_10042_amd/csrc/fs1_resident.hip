@@ -186,8 +186,8 @@ hipError_t resident_t(const SolveBufs& b, const ScanConsts& k, int itr_max, int 
     if (tau_mode) return hipErrorInvalidValue;
     k_resident<T, R, ABSORB, 256><<<1, 256, 0, s>>>(a, k);
   } else if (nt == 512) {
-    // binary64 runs of 16 in the log or plain domain only
-    if constexpr (R == 16 && sizeof(T) == 8) {
+    // runs of 16 in the log or plain domain only
+    if constexpr (R == 16) {
       if (tau_mode) return hipErrorInvalidValue;
       k_resident<T, R, ABSORB, 512><<<1, 512, 0, s>>>(a, k);
     } else {
@@ -240,7 +240,7 @@ int solve_resident_threads(int64_t n, int R) {
   // leave the wave's registers
   if (n <= int64_t(kWave) * R) return kWave;
   if (n <= int64_t(256) * R) return 256;
-  // binary64 runs of 16 (chosen for grids above 2048 entries): 512 threads
+  // runs of 16 (chosen up to 8192 entries): 512 threads
   if (R == 16 && n <= int64_t(512) * R) return 512;
   return resident_threads(n, R);
 }

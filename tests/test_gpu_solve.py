@@ -334,8 +334,8 @@ def test_persistent_single_launch_full_size(dtype):
 def test_resident_workgroup_sizes(dtype, n, domain):
     """The one-workgroup solver at the edges of its workgroup sizes (one
     wavefront up to 64 R entries, 256 threads up to 256 R, 1024 threads up to
-    1024 R with R <= 8; binary64 grids of 2049 to 8192 entries take runs of 16
-    on 256 or 512 threads) against the oracle at a fixed iteration count and
+    1024 R with R <= 8; binary64 grids of 2049 to 8192 entries and binary32
+    grids of 4097 to 8192 take runs of 16 on 256 or 512 threads) against the oracle at a fixed iteration count and
     against the general path (same arithmetic, other association order).  A
     grid of 8193 binary64 entries is past the one-workgroup limit."""
     fs1 = _fs1()
