@@ -156,10 +156,12 @@ typedef struct {
                              (performance only; results do not depend on it)      */
     int32_t flags;        /* bit 0 (FS1_FLAG_POTENTIALS): return potentials (see
                              potentials_out).  Solver selection (results agree to
-                             rounding): by default a grid of at most 1024 runs
-                             (n <= 1024 R; R = 8 in binary64, up to 16 in
-                             binary32) runs the whole solve in one workgroup and
-                             one launch (both domains); otherwise, in FS1_LOG, a
+                             rounding): by default a grid of at most 8192
+                             entries (fewer where h/eps limits the run length R
+                             in the log domain: n <= 1024 R) runs the whole
+                             solve in one workgroup and one launch (runs of 8 or
+                             16 entries per thread; all domains); otherwise, in
+                             FS1_LOG, a
                              grid of at most 1024 chunks whose chunk frame fits
                              the working precision runs one fused kernel per
                              half-iteration; bit 1 (FS1_FLAG_GENERAL) forces the
