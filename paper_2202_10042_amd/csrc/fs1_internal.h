@@ -160,7 +160,8 @@ struct SolveBufs {
 int resident_run_length(int64_t n, int rmax);
 int resident_threads(int64_t n, int R);
 // The single solve's workgroup: one wavefront (64 threads) when n <= 64 R,
-// else resident_threads(); its allocation is max(threads, 256) runs.
+// 256 threads when n <= 256 R, 512 threads for runs of 16 up to 512 R, else
+// resident_threads(); its allocation is max(threads, 256) runs.
 int solve_resident_threads(int64_t n, int R);
 bool usable_resident(const SolveBufs& b);
 hipError_t launch_resident(const SolveBufs& b, const ScanConsts& k, int itr_max, int check_every,
