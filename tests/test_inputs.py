@@ -29,6 +29,16 @@ def test_shifted_noisy_pair():
     assert 0.03 < shift < 0.07
 
 
+def test_blocked_density_equals_one_pass():
+    # grids longer than one block are evaluated on several threads: the values
+    # must be those of a single pass, bit for bit
+    n = 2 * inputs._BLOCK + 12345
+    x, _ = inputs.grid(n)
+    prm = inputs._mixture_params(np.random.default_rng(5), 8)
+    assert np.array_equal(inputs._mixture_density(x, *prm),
+                          inputs._mixture_density_block(x, *prm))
+
+
 def test_paper_uniform_and_ricker():
     u, v, dx = inputs.paper_uniform_pair(500, 0)
     assert dx == 6.0 / 499 and abs(u.sum() - 1) < 1e-14 and abs(v.sum() - 1) < 1e-14
