@@ -102,9 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
   T own[R];
   double m64[R];
   int eo = 0;
-  if (want_err) {
-    tile_load<T, R>(static_cast<const T*>(a.vown), run, lane, own);
-    eo = a.eown[run];
+  if constexpr (MODE != F_PHI) {
+    // issued on every psi-half (from the input vector where no error is due:
+    // the same lines as x), so that the number of loads behind the chunk
+    // aggregates does not depend on the check and the carries below wait for
+    // the aggregates only
+    const T* vo = static_cast<const T*>(want_err ? a.vown : a.vin);
+    tile_load<T, R>(vo, run, lane, own);
+    eo = (want_err ? a.eown : a.ein)[run];
   }
   if (want_err || sizeof(T) == 8) tile_load<double, R>(a.m64, run, lane, m64);
   T mg[R];
@@ -116,6 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
       tile_load<T, R>(reinterpret_cast<const T*>(a.m32), run, lane, mg);
     }
   }
+  // every load is in flight before the carry arithmetic starts: keep the
+  // instruction scheduler from moving that arithmetic above the data loads
+  __builtin_amdgcn_sched_barrier(0);
 
   // chunk carries first: they need only the aggregates, so this work runs
   // while the chunk's own data is still arriving
