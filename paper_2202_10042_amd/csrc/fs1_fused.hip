@@ -111,7 +111,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
     tile_load<T, R>(vo, run, lane, own);
     eo = (want_err ? a.eown : a.ein)[run];
   }
-  if (want_err || sizeof(T) == 8) tile_load<double, R>(a.m64, run, lane, m64);
+  // (binary32: on every psi-half, used where the error is due, for the same
+  // reason as the own vector)
+  if (MODE != F_PHI || sizeof(T) == 8) tile_load<double, R>(a.m64, run, lane, m64);
   T mg[R];
   if constexpr (MODE != F_ERR) {
     if constexpr (sizeof(T) == 8) {
