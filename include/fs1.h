@@ -100,6 +100,14 @@ int fs1_ctx_set_profiling(fs1_ctx *ctx, int enable);
 int fs1_ctx_kernel_stats(fs1_ctx *ctx, double *total_ms, int64_t *launches,
                          double *alg_bytes);
 
+/* Diagnostic STREAM-style copy of `bytes` bytes from src to dst (device
+ * arrays, 16-byte aligned, not overlapping; bytes a multiple of 16), the
+ * attainable-bandwidth reference for the half-iteration kernels, which read
+ * and write whole vectors once per half as a copy does.  flags bit 0: use
+ * non-temporal loads and stores.  Asynchronous on the context stream.  Not part
+ * of the method. */
+int fs1_stream_copy(fs1_ctx *ctx, const void *src, void *dst, int64_t bytes, int flags);
+
 /* Thread-local message describing the last failure on this host thread. */
 const char *fs1_last_error(void);
 /* Library version string. */
@@ -122,10 +130,10 @@ int fs1_kv_apply(fs1_ctx *ctx, const void *x, void *y, int64_t n, double h, doub
 /* ly_i = ln sum_j exp(lx_j - |i-j| h/eps): the recursions of eq. (recursion)
  * on logarithms (log-sum-exp semiring), as used by the log-domain stabilised
  * method.  lx, ly: device arrays of n elements of dtype dt; must not overlap.
- * lx may hold -inf (a zero of x); all -inf gives all -inf, never NaN.  A +inf or
- * NaN entry makes the outputs it reaches non-finite (+inf or NaN, which one is
- * unspecified).  Finite entries must satisfy |lx_j| < 1e8; n h / eps <= 1e8.
- * Asynchronous on the context stream. */
+ * lx may hold -inf (a zero of x); all -inf gives all -inf, never NaN.  Every
+ * kernel entry is positive, so a NaN entry makes every output NaN, and
+ * otherwise a +inf entry makes every output +inf.  Finite entries must satisfy
+ * |lx_j| < 1e8; n h / eps <= 1e8.  Asynchronous on the context stream. */
 int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h,
                      double eps, int dt);
 

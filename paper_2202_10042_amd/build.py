@@ -8,13 +8,14 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfs1.so")
 SOURCES = ["fs1_kernels.hip", "fs1_fused.hip", "fs1_persist.hip", "fs1_resident.hip",
-           "fs1_batch.hip", "fs1_2d.hip", "fs1_tau.hip", "fs1_api.cpp", "fs1_server.cpp"]
+           "fs1_batch.hip", "fs1_2d.hip", "fs1_tau.hip", "fs1_stream.hip", "fs1_api.cpp", "fs1_server.cpp"]
 ARCH = os.environ.get("FS1_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,14 +36,17 @@ def build(verbose: bool = False) -> str:
         "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     ]
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(out_dir, src + ".o")
-        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
+    objs = [os.path.join(out_dir, src + ".o") for src in SOURCES]
+    cmds = [[hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+            for src, obj in zip(SOURCES, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    # one compiler process per source, a few at a time
+    jobs = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        for cmd in ex.map(lambda c: (subprocess.run(c, check=True), c)[1], cmds):
+            pass
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -155,14 +155,16 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
   Carve cv(nullptr);
   cv.take(nchunks * sizeof(ChunkAgg));
   cv.take(carry_buffer_bytes(nchunks));
+  cv.take(2 * sizeof(int));
   st = ensure_ws(ctx, cv.off);
   if (st) return st;
   Carve w(ctx->ws);
   ChunkAgg* agg = static_cast<ChunkAgg*>(w.take(nchunks * sizeof(ChunkAgg)));
   ChunkAgg* carry = static_cast<ChunkAgg*>(w.take(carry_buffer_bytes(nchunks)));
+  int* special = static_cast<int*>(w.take(2 * sizeof(int)));
   const ScanConsts k = make_scan_consts(h, eps, R);
   const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
-  hipError_t e = log ? launch_kv_log(dt, x, y, n, k, kc, agg, carry, ctx->stream)
+  hipError_t e = log ? launch_kv_log(dt, x, y, n, k, kc, agg, carry, special, ctx->stream)
                      : launch_kv_plain(dt, x, y, n, k, kc, agg, carry, ctx->stream);
   if (e != hipSuccess) return hip_fail(e, log ? "fs1_kv_apply_log launch" : "fs1_kv_apply launch");
   return FS1_OK;
@@ -699,8 +701,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
 
   // diagnostic timing: events around every half-iteration kernel of a batch
   const bool prof = ctx->profiling != 0;
-  if (prof && ctx->events.size() < 2) {
-    while (ctx->events.size() < 2) {
+  if (prof && ctx->events.size() < 4) {
+    while (ctx->events.size() < 4) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e));
       ctx->events.push_back(e);
@@ -768,14 +770,17 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   int l = (persistent || resident) ? o.itr_max : 0;
   bool stopped = persistent || resident;
   int batch = 0;
+  // diagnostic timing: the fused path's launches are short, so whole polling
+  // batches are bracketed (back-to-back kernels run without gaps, and batch
+  // time / launches is the average kernel duration without per-launch event
+  // overhead); the general path's half-iteration kernel is bracketed alone,
+  // in the first iteration of a timed batch (its carry kernels are not counted)
+  const bool per_launch = !fused && !tau_general;
   while (l < o.itr_max && !stopped) {
     const int l0 = l;
     const int l_end = std::min(o.itr_max, l + o.sync_every);
-    // diagnostic timing brackets whole polling batches (every `profiling`-th
-    // one): back-to-back kernels run without gaps, so batch time / launches is
-    // the average kernel duration without per-launch event overhead
     const bool timed = prof && (batch % ctx->profiling) == 0;
-    if (timed) HIP_TRY(hipEventRecord(ctx->events[0], s));
+    if (timed && !per_launch) HIP_TRY(hipEventRecord(ctx->events[0], s));
     for (; l < l_end; ++l) {
       const int check = (l % o.check_every) == 0;
       if (fused) {
@@ -785,11 +790,14 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
         HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, true, s));
         HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, false, s));
       } else {
-        HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s));
-        HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s));
+        const bool ev = timed && l == l0;
+        HIP_TRY(launch_half_psi(b, k, kc, l, check, tol, s, ev ? ctx->events[0] : nullptr,
+                                ev ? ctx->events[1] : nullptr));
+        HIP_TRY(launch_half_phi(b, k, kc, l, check, tol, s, ev ? ctx->events[2] : nullptr,
+                                ev ? ctx->events[3] : nullptr));
       }
     }
-    if (timed) HIP_TRY(hipEventRecord(ctx->events[1], s));
+    if (timed && !per_launch) HIP_TRY(hipEventRecord(ctx->events[1], s));
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stopped = hc->done != 0;
@@ -797,11 +805,20 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     // once; only batches in which every launch did its work are counted
     if (timed && !stopped) {
       float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
-      ctx->prof_ms += ms;
-      ctx->prof_launches += 2 * (l - l0);
-      for (int i = l0; i < l; ++i)
-        ctx->prof_bytes += 2.0 * bytes_half + ((i % o.check_every) == 0 ? bytes_check : 0.0);
+      if (per_launch) {
+        float ms2 = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+        HIP_TRY(hipEventElapsedTime(&ms2, ctx->events[2], ctx->events[3]));
+        ctx->prof_ms += double(ms) + double(ms2);
+        ctx->prof_launches += 2;
+        ctx->prof_bytes += 2.0 * bytes_half + ((l0 % o.check_every) == 0 ? bytes_check : 0.0);
+      } else {
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+        ctx->prof_ms += ms;
+        ctx->prof_launches += 2 * (l - l0);
+        for (int i = l0; i < l; ++i)
+          ctx->prof_bytes += 2.0 * bytes_half + ((i % o.check_every) == 0 ? bytes_check : 0.0);
+      }
     }
     ++batch;
   }

@@ -115,9 +115,10 @@ int pick_run_length(int dtype, bool absorb, double c);  // R for a solve / log a
 hipError_t launch_kv_plain(int dtype, const void* x, void* y, int64_t n, const ScanConsts& k,
                            const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
                            hipStream_t s);
-// Kernel application on logarithms.
+// Kernel application on logarithms.  special: two ints of scratch (whether an
+// input is +inf, whether one is NaN).
 hipError_t launch_kv_log(int dtype, const void* lx, void* ly, int64_t n, const ScanConsts& k,
-                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry, int* special,
                          hipStream_t s);
 
 // One solve's device buffers.

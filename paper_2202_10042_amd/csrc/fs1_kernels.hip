@@ -120,15 +120,30 @@ int pick_run_length(int dtype, bool absorb, double c) {
 // ===========================================================================
 // k_agg: chunk aggregates of a vector
 // ===========================================================================
+// IN_LOG with `special` set: special[0] |= 1 if an input is +inf, special[1]
+// |= 1 if one is NaN (both zero before the launch).
 template <typename T, int R, int IN>
 __global__ __launch_bounds__(kBlock) void k_agg(const T* __restrict__ v, const int* __restrict__ ex,
                                                 int64_t n, ScanConsts k,
-                                                ChunkAgg* __restrict__ agg) {
+                                                ChunkAgg* __restrict__ agg,
+                                                int* __restrict__ special = nullptr) {
   __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   T x[R];
   int E;
   load_input<T, R, IN>(v, ex, run, n, x, E);
+  if constexpr (IN == IN_LOG) {
+    // a finite logarithm maps to a value of at most 2 in its run's frame, so
+    // only +inf and NaN inputs give +inf or NaN here
+    bool pinf = false, nan = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      pinf |= isinf(x[j]) && x[j] > T(0);
+      nan |= isnan(x[j]);
+    }
+    if (special && pinf) atomicOr(&special[0], 1);
+    if (special && nan) atomicOr(&special[1], 1);
+  }
   const Lam<T> L = lam_of<T>(k);
   T af, ab;
   run_aggs<T, R>(x, L, af, ab);
@@ -354,14 +369,28 @@ hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
 // ===========================================================================
 // k_kv_apply: y = K x (plain) or ly = ln K e^lx (log)
 // ===========================================================================
+// LOG: `special` as set by k_agg over the same input.  Every kernel entry is
+// positive, so one +inf logarithm makes every output +inf and one NaN makes
+// every output NaN; those outputs are written directly.
 template <typename T, int R, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_kv_apply(const T* __restrict__ x_in,
                                                      T* __restrict__ y_out, int64_t n,
                                                      ScanConsts k,
                                                      const ChunkAgg* __restrict__ carry,
-                                                     CarryFix cfix) {
+                                                     CarryFix cfix,
+                                                     const int* __restrict__ special = nullptr) {
   __shared__ ScanLds<S1<T>, kBlock / kWave> sh;
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if constexpr (LOG) {
+    const int sp_nan = special[1], sp_inf = special[0];
+    if (sp_nan | sp_inf) {
+      T y[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) y[j] = sp_nan ? T(NAN) : T(INFINITY);
+      store_run<T, R>(y_out, run * R, n, y);
+      return;
+    }
+  }
   T x[R];
   int E;
   load_input<T, R, LOG ? IN_LOG : IN_PLAIN>(x_in, nullptr, run, n, x, E);
@@ -812,18 +841,25 @@ static hipError_t kv_plain_t(const void* x, void* y, int64_t n, const ScanConsts
   return hipGetLastError();
 }
 
+__global__ void k_zero_ints(int* p, int count) {
+  if (int(threadIdx.x) < count) p[threadIdx.x] = 0;
+}
+
 template <typename T, int R>
 static hipError_t kv_log_t(const void* x, void* y, int64_t n, const ScanConsts& k,
-                           const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                           const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry, int* special,
                            hipStream_t s) {
   const unsigned g = grid_of(kc.nchunks);
-  k_agg<T, R, IN_LOG><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg);
+  // (a kernel, not a memset: the call may be captured into a graph)
+  k_zero_ints<<<1, 64, 0, s>>>(special, 2);
+  k_agg<T, R, IN_LOG><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), nullptr, n, k, agg,
+                                           special);
   {
     const hipError_t e = launch_carry<0>(agg, carry, kc, nullptr, nullptr, nullptr, 0, 0, 0.0, s);
     if (e != hipSuccess) return e;
   }
   k_kv_apply<T, R, true><<<g, kBlock, 0, s>>>(static_cast<const T*>(x), static_cast<T*>(y), n,
-                                              k, carry, carry_fix_of(kc));
+                                              k, carry, carry_fix_of(kc), special);
   return hipGetLastError();
 }
 
@@ -843,17 +879,17 @@ hipError_t launch_kv_plain(int dtype, const void* x, void* y, int64_t n, const S
 }
 
 hipError_t launch_kv_log(int dtype, const void* x, void* y, int64_t n, const ScanConsts& k,
-                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry,
+                         const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry, int* special,
                          hipStream_t s) {
   if (dtype == 0) {
-    if (k.R == 8) return kv_log_t<double, 8>(x, y, n, k, kc, agg, carry, s);
-    return kv_log_t<double, 1>(x, y, n, k, kc, agg, carry, s);
+    if (k.R == 8) return kv_log_t<double, 8>(x, y, n, k, kc, agg, carry, special, s);
+    return kv_log_t<double, 1>(x, y, n, k, kc, agg, carry, special, s);
   }
   switch (k.R) {
-    case 16: return kv_log_t<float, 16>(x, y, n, k, kc, agg, carry, s);
-    case 8: return kv_log_t<float, 8>(x, y, n, k, kc, agg, carry, s);
-    case 4: return kv_log_t<float, 4>(x, y, n, k, kc, agg, carry, s);
-    default: return kv_log_t<float, 1>(x, y, n, k, kc, agg, carry, s);
+    case 16: return kv_log_t<float, 16>(x, y, n, k, kc, agg, carry, special, s);
+    case 8: return kv_log_t<float, 8>(x, y, n, k, kc, agg, carry, special, s);
+    case 4: return kv_log_t<float, 4>(x, y, n, k, kc, agg, carry, special, s);
+    default: return kv_log_t<float, 1>(x, y, n, k, kc, agg, carry, special, s);
   }
 }
 

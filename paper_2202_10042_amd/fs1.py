@@ -45,7 +45,7 @@ EXPORTS = (
     "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
-    "fs1_solve_2d",
+    "fs1_solve_2d", "fs1_stream_copy",
 )
 
 
@@ -181,6 +181,8 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
+    lib.fs1_stream_copy.argtypes = [vp, vp, vp, i64, ctypes.c_int]
+    lib.fs1_stream_copy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -286,6 +288,18 @@ def fs1_kv_apply_log(lx, h: float, eps: float, out=None, ctx: Optional[Context] 
     _check(load().fs1_kv_apply_log(ctx.handle, _dev(lx, "lx"), _dev(out, "out"), lx.numel(),
                                    float(h), float(eps), _dtype_code(lx)))
     return out
+
+
+def fs1_stream_copy(src, dst, nontemporal: bool = False, ctx: Optional[Context] = None):
+    """Diagnostic device copy of src into dst (same number of bytes), the
+    attainable-bandwidth reference of the benchmark."""
+    ctx = ctx or default_context()
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst must have the same size in bytes")
+    _check(load().fs1_stream_copy(ctx.handle, _dev(src, "src"), _dev(dst, "dst"), nb,
+                                  1 if nontemporal else 0))
+    return dst
 
 
 def make_opts(h: Optional[float] = None, itr_max: int = 10000, dtype: str = "f64",

@@ -148,14 +148,22 @@ def test_log_special_values():
     y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
     ref = 3.0 - np.abs(np.arange(n) - 1234) * 0.05
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
-    _say("kv_log +inf and NaN make the outputs non-finite")
-    lx = np.zeros(n)
-    lx[10] = np.inf
-    y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
-    assert not np.any(np.isfinite(y)) and not np.any(y == -np.inf)
-    lx[10] = np.nan
-    y = fs1.fs1_kv_apply_log(dev(lx), h, eps).cpu().numpy()
-    assert np.all(np.isnan(y))
+    _say("kv_log: a +inf input makes every output +inf, a NaN every output NaN")
+    for dt in (torch.float64, torch.float32):
+        for pos in (0, 10, 2047, 2048, n - 1):
+            lx = np.zeros(n)
+            lx[pos] = np.inf
+            y = fs1.fs1_kv_apply_log(dev(lx, dt), h, eps).double().cpu().numpy()
+            assert np.all(y == np.inf), (dt, pos)
+            lx[(pos + 7) % n] = -np.inf
+            y = fs1.fs1_kv_apply_log(dev(lx, dt), h, eps).double().cpu().numpy()
+            assert np.all(y == np.inf), (dt, pos)
+            lx[(pos + 3) % n] = np.nan
+            y = fs1.fs1_kv_apply_log(dev(lx, dt), h, eps).double().cpu().numpy()
+            assert np.all(np.isnan(y)), (dt, pos)
+        # the flags of one call do not leak into the next
+        y = fs1.fs1_kv_apply_log(torch.zeros(n, dtype=dt, device="cuda"), h, eps)
+        assert torch.all(torch.isfinite(y))
     x = np.ones(n)
     x[4000] = np.nan
     y = fs1.fs1_kv_apply(dev(x), h, eps).cpu().numpy()
