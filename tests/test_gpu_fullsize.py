@@ -1,0 +1,208 @@
+"""Parity of fs1_solve at the full single-pair sizes: N = 2^20 (eps = 1e-3 and
+1e-4) and the large pair N = 1e8 (eps = 1e-4), log domain.
+
+Three checks that do not depend on a long sequential recursion of the oracle:
+
+  * one half-iteration at a time: from the GPU's own potentials (F^l, G^l) after
+    l iterations, the oracle's dense log-sum-exp (the definition of K, Sec. 2)
+    gives the next update of Algorithm 1 on sampled rows,
+        G^{l+1}_j = ln nu_j - LSE_i (F^l_i - |i-j| h/eps),
+        F^{l+1}_i = ln mu_i - LSE_j (G^{l+1}_j - |i-j| h/eps),
+    which the GPU's (F^{l+1}, G^{l+1}) after l+1 iterations must match.  Rows:
+    both ends, chunk and group boundaries of every chunk length the solvers
+    use, and random rows.  Tolerance (absolute, binary64): 64 u (1 + |ref_j|)
+    for the scan and the rounding of the result, plus 64 u max|input| for the
+    rounding of the GPU's potentials that feed the reference (a log-sum-exp
+    moves by at most the largest change of its arguments); binary32 scans:
+    4e-6 + 2 u32 |ref_j| (the binary32 kernel-application bound) plus the same
+    input term.
+  * the transport cost and the marginal error of the GPU's final state,
+    evaluated by the oracle's O(n) functionals on the returned potentials:
+    W to 1e-10 relative (binary64), err to 1e-6 relative + 1e-12;
+  * fixed-iteration parity with the sequential oracle (Algorithm 1 in the log
+    domain) over 50 iterations at N = 2^20: W to 1e-10 relative and the
+    potentials to 1e-9 absolute in binary64 (the sequential oracle agrees with
+    its own plain-domain form to 2e-13 in W and 4e-12 in the potentials
+    there), W to 1e-5 relative in binary32.
+
+And one against a closed form: at convergence (tol 1e-8) of the N = 2^20,
+eps = 1e-3 single pair, the entropic cost lies above the unregularised W1 of
+the CDF formula and within eps min(H(mu), H(nu)) of it, widened by
+2 C_max err for the marginal error left (C_max = (n - 1) h).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_10042_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+N_C2 = 1 << 20
+N_C4 = 100_000_000
+
+
+def _fs1():
+    from paper_2202_10042_amd import fs1
+    return fs1
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def sample_rows(n, seed, k=24):
+    """Both ends, chunk boundaries of chunk lengths 1024, 2048 and 4096 (runs
+    of 4, 8 or 16 on 256 threads), group boundaries of 1024 such chunks, and
+    random rows."""
+    rng = np.random.default_rng(seed)
+    r = [np.arange(0, 4), np.arange(n - 4, n)]
+    for clen in (1024, 2048, 4096):
+        for m in (1, 2, 511, 512, 1023, 1024, 1025):
+            b = m * clen
+            r.append(np.arange(b - 2, b + 2))
+        for g in (1, 2, 7):
+            b = g * 1024 * clen
+            r.append(np.arange(b - 2, b + 2))
+    r.append(rng.integers(0, n, size=k))
+    rows = np.unique(np.concatenate(r))
+    return rows[(rows >= 0) & (rows < n)]
+
+
+def _solve_pot(fs1, mu, nu, eps, its, dtype, solver):
+    r = fs1.fs1_solve(mu, nu, eps, 0.0, itr_max=its, dtype=dtype, domain="log",
+                      potentials=True, solver=solver, sync_every=64)
+    assert r.status == 0 and r.iterations == its, r
+    return r
+
+
+def _check_half_steps(fs1, mu_np, nu_np, mu, nu, eps, l, dtype, solver, seed):
+    n = mu_np.size
+    h = 1.0 / n
+    rows = sample_rows(n, seed)
+    a = _solve_pot(fs1, mu, nu, eps, l, dtype, solver)
+    F0 = a.F.cpu().numpy()
+    del a
+    b = _solve_pot(fs1, mu, nu, eps, l + 1, dtype, solver)
+    F1 = b.F.cpu().numpy()
+    G1 = b.G.cpu().numpy()
+    del b
+    # psi-half of iteration l: G^{l+1} from F^l
+    refG = np.log(nu_np[rows]) - oracle.kv_log_dense(F0, h, eps, rows=rows)
+    # phi-half: F^{l+1} from G^{l+1}
+    refF = np.log(mu_np[rows]) - oracle.kv_log_dense(G1, h, eps, rows=rows)
+    for name, got, ref, lx in (("G", G1[rows], refG, F0), ("F", F1[rows], refF, G1)):
+        inp = 64 * U64 * float(np.max(np.abs(lx)))
+        if dtype == "f64":
+            tol = 64 * U64 * (1 + np.abs(ref)) + inp
+        else:
+            tol = 4e-6 + 2 * U32 * np.abs(ref) + inp
+        d = np.abs(got - ref)
+        worst = int(np.argmax(d / tol))
+        _say(f"  {name}: max |d| {d.max():.3e}, worst row {rows[worst]} ratio {d[worst] / tol[worst]:.3f}")
+        assert np.all(d <= tol), (name, int(rows[worst]), float(d[worst]), float(tol[worst]))
+
+
+@pytest.mark.parametrize("solver", ["auto", "general"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+def test_half_steps_c2_dense_rows(eps, dtype, solver):
+    fs1 = _fs1()
+    mu_np, nu_np = inputs.mixture_pair(N_C2, 4, 5)
+    mu, nu = dev(mu_np), dev(nu_np)
+    for l in (0, 5, 49):
+        _say(f"half steps N=2^20 eps={eps} {dtype} {solver} l={l}")
+        _check_half_steps(fs1, mu_np, nu_np, mu, nu, eps, l, dtype, solver, seed=l + 3)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_half_steps_c4_dense_rows(dtype):
+    # the large pair: N = 1e8 (not a power of two), eps = 1e-4
+    fs1 = _fs1()
+    _say(f"half steps N=1e8 eps=1e-4 {dtype}: inputs")
+    mu_np, nu_np = inputs.shifted_noisy_pair(N_C4, 8, 3)
+    mu, nu = dev(mu_np), dev(nu_np)
+    _say(f"half steps N=1e8 eps=1e-4 {dtype} l=5")
+    _check_half_steps(fs1, mu_np, nu_np, mu, nu, 1e-4, 5, dtype, "auto", seed=11)
+    del mu, nu
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("solver", ["auto", "general", "persistent"])
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+def test_c2_sequential_50_iterations(eps, solver):
+    fs1 = _fs1()
+    n = N_C2
+    its = 50
+    mu_np, nu_np = inputs.mixture_pair(n, 4, 5)
+    h = 1.0 / n
+    _say(f"sequential oracle N=2^20 eps={eps} {its} iterations")
+    ref = oracle.fs1_log(mu_np, nu_np, h, eps, tol=0.0, itr_max=its)
+    mu, nu = dev(mu_np), dev(nu_np)
+    _say(f"  gpu f64 {solver}")
+    r = _solve_pot(fs1, mu, nu, eps, its, "f64", solver)
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+    dF = np.max(np.abs(r.F.cpu().numpy() - ref.a))
+    dG = np.max(np.abs(r.G.cpu().numpy() - ref.b))
+    _say(f"  |dW|/W {abs(r.w1 - ref.w1) / ref.w1:.2e}, max |dF| {dF:.2e}, max |dG| {dG:.2e}")
+    assert dF <= 1e-9 and dG <= 1e-9
+    _say(f"  gpu f32 {solver}")
+    r32 = _solve_pot(fs1, mu, nu, eps, its, "f32", solver)
+    _say(f"  f32 |dW|/W {abs(r32.w1 - ref.w1) / ref.w1:.2e}")
+    assert r32.w1 == pytest.approx(ref.w1, rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("eps,its", [(1e-3, 200), (1e-4, 60)])
+def test_functionals_of_gpu_state(eps, its, dtype):
+    # W and err of the returned state, evaluated by the oracle's O(n)
+    # recursions on the GPU's own potentials
+    fs1 = _fs1()
+    n = N_C2
+    h = 1.0 / n
+    mu_np, nu_np = inputs.mixture_pair(n, 4, 5)
+    _say(f"functionals N=2^20 eps={eps} its={its} {dtype}")
+    r = _solve_pot(fs1, dev(mu_np), dev(nu_np), eps, its, dtype, "auto")
+    F = r.F.cpu().numpy()
+    G = r.G.cpu().numpy()
+    w = oracle.cost_fs1_log(F, G, h, eps)
+    e = oracle.marginal_err_fs1_log(F, G, nu_np, h, eps)
+    _say(f"  W gpu {r.w1:.15g} oracle {w:.15g}; err gpu {r.marginal_err:.10g} oracle {e:.10g}")
+    # binary32: the potentials carry binary32 scalings, and W, err are
+    # computed from the same values on both sides (binary64 sums)
+    assert r.w1 == pytest.approx(w, rel=1e-10 if dtype == "f64" else 1e-6)
+    assert r.marginal_err == pytest.approx(e, rel=1e-6, abs=1e-12 if dtype == "f64" else 1e-7)
+
+
+def test_c2_converged_entropic_bound():
+    # the single-pair workload: N = 2^20, eps = 1e-3, tol 1e-8
+    fs1 = _fs1()
+    n = N_C2
+    h = 1.0 / n
+    eps = 1e-3
+    k = inputs.random_k(1)
+    mu_np, nu_np = inputs.mixture_pair(n, k, 1)
+    _say(f"converged bound N=2^20 K={k} eps={eps}")
+    r = fs1.fs1_solve(dev(mu_np), dev(nu_np), eps, 1e-8, itr_max=5000, dtype="f64", domain="log",
+                      sync_every=64)
+    assert r.status == 0 and r.converged and r.marginal_err <= 1e-8, r
+    w1 = float(np.sum(np.abs(np.cumsum(mu_np - nu_np))) * h)
+    ent = lambda p: float(-np.sum(p[p > 0] * np.log(p[p > 0])))
+    cmax = (n - 1) * h
+    slack = 2 * cmax * r.marginal_err
+    bias = r.w1 - w1
+    bound = eps * min(ent(mu_np), ent(nu_np))
+    _say(f"  iterations {r.iterations}, W {r.w1:.12g}, W1(cdf) {w1:.12g}, bias {bias:.3e}, "
+         f"bound {bound:.3e}")
+    assert -slack <= bias <= bound + slack
