@@ -634,6 +634,10 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
     b.eF = static_cast<int*>(w.take(nruns * sizeof(int)));
     b.eG[0] = static_cast<int*>(w.take(nruns * sizeof(int)));
     b.eG[1] = static_cast<int*>(w.take(nruns * sizeof(int)));
+    b.xF = static_cast<ChunkExp*>(w.take(nchunks * sizeof(ChunkExp)));
+    b.xG[0] = static_cast<ChunkExp*>(w.take(nchunks * sizeof(ChunkExp)));
+    b.xG[1] = static_cast<ChunkExp*>(w.take(nchunks * sizeof(ChunkExp)));
+    b.lanetab = w.take(kWave * 32);
     b.mu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
     b.nu32 = dt == FS1_F32 ? w.take(npad * sizeof(float)) : nullptr;
     mu64 = static_cast<double*>(w.take(npad * sizeof(double)));
@@ -724,10 +728,13 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
       !resident && !tau_general && (o.flags & FS1_FLAG_PERSISTENT) && usable_persistent(b, h / eps);
   const bool fused = !resident && !persistent && !tau_general &&
                      !(o.flags & FS1_FLAG_GENERAL) && usable_fused(b, h / eps);
-  // the fused path, and the general path where solve_tiled(), iterate on the
-  // tile layout
+  // larger grids in the log domain: the streaming large-grid kernel
+  const bool large = !resident && !persistent && !tau_general && !fused &&
+                     !(o.flags & FS1_FLAG_GENERAL) && usable_large(b, h / eps);
+  // the fused and large-grid paths, and the general path where
+  // solve_tiled(), iterate on the tile layout
   const bool tiled =
-      fused || (!resident && !persistent && !tau_general && solve_tiled(b));
+      fused || large || (!resident && !persistent && !tau_general && solve_tiled(b));
   if (tau_general) {
     tb.tau = o.tau;
     tb.eps = eps;
@@ -736,6 +743,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   if (fused || persistent) HIP_TRY(launch_decay_table(b, k, s));
   if (fused) HIP_TRY(launch_fused_init(b, k, s));
   if (tiled) HIP_TRY(launch_relayout(b, true, 0, s));
+  if (large) HIP_TRY(launch_large_pack(b, k, s));
   if (persistent || resident) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
@@ -786,6 +794,12 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
       if (fused) {
         HIP_TRY(launch_fused_half(b, k, l, check, tol, true, s));
         HIP_TRY(launch_fused_half(b, k, l, check, tol, false, s));
+      } else if (large) {
+        const bool ev = timed && l == l0;
+        HIP_TRY(launch_large_half(b, k, kc, l, check, tol, true, s,
+                                  ev ? ctx->events[0] : nullptr, ev ? ctx->events[1] : nullptr));
+        HIP_TRY(launch_large_half(b, k, kc, l, check, tol, false, s,
+                                  ev ? ctx->events[2] : nullptr, ev ? ctx->events[3] : nullptr));
       } else if (tau_general) {
         HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, true, s));
         HIP_TRY(launch_tau_half(b, tb, k, kc, l, check, tol, false, s));
@@ -837,6 +851,7 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
 
   if (tau_general) HIP_TRY(launch_tau_finish(b, tb, gbuf, s));
+  if (large) HIP_TRY(launch_large_unpack(b, gbuf, s));
   if (tiled) HIP_TRY(launch_relayout(b, false, gbuf, s));
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));

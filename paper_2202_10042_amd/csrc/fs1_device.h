@@ -188,6 +188,33 @@ struct Lam {
   __device__ __forceinline__ T mul(T a) const { return use_mu ? fma(-mu, a, a) : lam * a; }
 };
 
+// The same step with the choice made at compile time (kernels instantiated
+// for both forms, so the unrolled recursions carry no select per step).
+template <typename T, bool MU>
+struct LamC {
+  T lam;
+  T mu;
+  __device__ __forceinline__ T axpy(T a, T x) const {
+    if constexpr (MU) {
+      return fma(-mu, a, a + x);
+    } else {
+      return fma(lam, a, x);
+    }
+  }
+  __device__ __forceinline__ T mul(T a) const {
+    if constexpr (MU) {
+      return fma(-mu, a, a);
+    } else {
+      return lam * a;
+    }
+  }
+};
+
+template <typename T, bool MU>
+__device__ __forceinline__ LamC<T, MU> lamc_of(const ScanConsts& k) {
+  return LamC<T, MU>{T(k.lam), T(k.mu)};
+}
+
 template <typename T>
 __device__ __forceinline__ Lam<T> lam_of(const ScanConsts& k) {
   Lam<T> l;
@@ -575,8 +602,8 @@ __device__ __forceinline__ void load_input(const T* __restrict__ v, const int* _
   }
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void run_aggs(const T (&x)[R], const Lam<T>& L, T& af, T& ab) {
+template <typename T, int R, typename LT>
+__device__ __forceinline__ void run_aggs(const T (&x)[R], const LT& L, T& af, T& ab) {
   T a = T(0), b = T(0);
 #pragma unroll
   for (int j = 0; j < R; ++j) a = L.axpy(a, x[j]);
@@ -611,8 +638,8 @@ __device__ __forceinline__ int local_exponent(const T (&x)[R], int E) {
 // backward state after the run).  Callers form them in extended range
 // (step_in), so a lambda below the working precision's normal range (large
 // h/eps, where runs have length 1) never multiplies a plain value.
-template <typename T, int R>
-__device__ __forceinline__ void run_apply(const T (&xf)[R], T lcf, T lcb, const Lam<T>& L,
+template <typename T, int R, typename LT>
+__device__ __forceinline__ void run_apply(const T (&xf)[R], T lcf, T lcb, const LT& L,
                                           T (&y)[R]) {
   T A = lcf + xf[0];
   y[0] = A;

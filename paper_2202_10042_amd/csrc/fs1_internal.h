@@ -121,6 +121,13 @@ hipError_t launch_kv_log(int dtype, const void* lx, void* ly, int64_t n, const S
                          const CarryConsts& kc, ChunkAgg* agg, ChunkAgg* carry, int* special,
                          hipStream_t s);
 
+// One exponent for a whole chunk of a vector (the large-grid solver): the
+// values are v_j * 2^store, all below 2^frame (frame = kExpZero: all zero).
+struct ChunkExp {
+  int store;
+  int frame;
+};
+
 // One solve's device buffers.
 struct SolveBufs {
   int dtype;          // 0 double, 1 float
@@ -139,6 +146,9 @@ struct SolveBufs {
   void* vG[2];        // psi values, double-buffered (npad)
   int* eF;            // phi run exponents (nruns)
   int* eG[2];         // psi run exponents
+  ChunkExp* xF;       // phi chunk exponents (large-grid solver; nchunks)
+  ChunkExp* xG[2];    // psi chunk exponents
+  void* lanetab;      // lane-dependent decays of the large-grid solver (64 x 32 bytes)
   ChunkAgg* aggF;     // chunk aggregates of phi
   ChunkAgg* aggG;     // chunk aggregates of psi
   ChunkAgg* carry;    // chunk carries of the current half
@@ -186,6 +196,26 @@ hipError_t launch_decay_table(const SolveBufs& b, const ScanConsts& k, hipStream
 hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int check,
                              double tol, bool psi, hipStream_t s, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
+
+// The solve's chunk-carry launches (fs1_kernels.hip): mode 1 for a psi-half
+// (returns at once when the solve has stopped), mode 2 for a phi-half (closes
+// the stopping test of iteration l first).
+hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
+                              const CarryConsts& kc, Ctrl* ctrl, const double* part,
+                              double* err_hist, int l, int check, double tol, hipStream_t s);
+
+// Large grids in the log domain (more chunks than the fused path takes, chunk
+// frame valid): one k_large launch per half-iteration after the carry
+// kernels, vectors in the tile layout with one exponent per chunk.
+// launch_large_pack turns vF / vG[0] (per-run exponents) into that form
+// before the first half, launch_large_unpack writes the per-run exponents of
+// vF / vG[gbuf] back from it after the last.
+bool usable_large(const SolveBufs& b, double c);
+hipError_t launch_large_pack(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+hipError_t launch_large_unpack(const SolveBufs& b, int gbuf, hipStream_t s);
+hipError_t launch_large_half(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc,
+                             int l, int check, double tol, bool psi, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
 hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);

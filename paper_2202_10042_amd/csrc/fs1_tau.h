@@ -44,11 +44,4 @@ hipError_t launch_tau_half(const SolveBufs& b, const TauBufs& t, const ScanConst
 // layout, in place, for the common finalisation.
 hipError_t launch_tau_finish(const SolveBufs& b, const TauBufs& t, int gbuf, hipStream_t s);
 
-// The solve's chunk-carry launches (fs1_kernels.hip): mode 1 for a psi-half
-// (returns at once when the solve has stopped), mode 2 for a phi-half (closes
-// the stopping test of iteration l first).
-hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
-                              const CarryConsts& kc, Ctrl* ctrl, const double* part,
-                              double* err_hist, int l, int check, double tol, hipStream_t s);
-
 }  // namespace fs1

@@ -206,3 +206,75 @@ def test_c2_converged_entropic_bound():
     _say(f"  iterations {r.iterations}, W {r.w1:.12g}, W1(cdf) {w1:.12g}, bias {bias:.3e}, "
          f"bound {bound:.3e}")
     assert -slack <= bias <= bound + slack
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,eps", [(2 * 1024 * 2048 + 3, 1e-3), (1024 * 4096 + 4097, 3e-4),
+                                   (3 * 1024 * 4096 - 1, 1e-4)])
+def test_large_grid_path(n, eps, dtype):
+    """Grids of more than 1024 chunks (the large-grid kernel with the two-level
+    carries, one exponent per chunk) against the sequential oracle over 12
+    iterations and the dense half-step on sampled rows; the general path
+    (extended-range scans) as a second opinion."""
+    fs1 = _fs1()
+    h = 1.0 / n
+    its = 12
+    mu_np, nu_np = inputs.mixture_pair(n, 5, 17)
+    mu, nu = dev(mu_np), dev(nu_np)
+    _say(f"large grid n={n} eps={eps} {dtype}: sequential oracle")
+    ref = oracle.fs1_log(mu_np, nu_np, h, eps, tol=0.0, itr_max=its)
+    r = _solve_pot(fs1, mu, nu, eps, its, dtype, "auto")
+    g = _solve_pot(fs1, mu, nu, eps, its, dtype, "general")
+    _say(f"  W gpu {r.w1:.15g} general {g.w1:.15g} oracle {ref.w1:.15g}")
+    if dtype == "f64":
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-10)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+        assert np.max(np.abs(r.F.cpu().numpy() - ref.a)) <= 1e-9
+        assert np.max(np.abs(r.G.cpu().numpy() - ref.b)) <= 1e-9
+        assert r.w1 == pytest.approx(g.w1, rel=1e-11)
+    else:
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-4)
+    del r, g
+    _check_half_steps(fs1, mu_np, nu_np, mu, nu, eps, 7, dtype, "auto", seed=n % 97)
+
+
+def test_large_grid_to_tolerance_and_history():
+    """The large-grid path stops where Algorithm 1 stops: the error history
+    matches the general path's at every checked iteration, and both stop at
+    the same iteration (check_every 1 and 3)."""
+    fs1 = _fs1()
+    n = 2 * 1024 * 2048 + 3
+    mu_np, nu_np = inputs.mixture_pair(n, 3, 23)
+    mu, nu = dev(mu_np), dev(nu_np)
+    for ce in (1, 3):
+        _say(f"large grid to tolerance check_every={ce}")
+        a = fs1.fs1_solve(mu, nu, 1e-2, 1e-7, itr_max=400, dtype="f64", domain="log",
+                          check_every=ce, err_history=True, sync_every=7)
+        b = fs1.fs1_solve(mu, nu, 1e-2, 1e-7, itr_max=400, dtype="f64", domain="log",
+                          check_every=ce, err_history=True, sync_every=64, solver="general")
+        assert a.status == 0 and b.status == 0 and a.converged and b.converged
+        assert a.iterations == b.iterations and a.iterations % ce == 0
+        ha = a.err_history.cpu().numpy()[:a.iterations + 1]
+        hb = b.err_history.cpu().numpy()[:b.iterations + 1]
+        m = ~np.isnan(hb)
+        assert np.array_equal(m, ~np.isnan(ha))
+        np.testing.assert_allclose(ha[m], hb[m], rtol=1e-9, atol=1e-15)
+        assert a.marginal_err <= 1e-7
+        assert a.w1 == pytest.approx(b.w1, rel=1e-11)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_large_grid_bitwise_repeatable(dtype):
+    """Two runs of the same large-grid solve give the same bits (W, err and
+    both potentials): no result depends on the order in which workgroups
+    run."""
+    fs1 = _fs1()
+    n = 3 * 1024 * 4096 - 1
+    mu_np, nu_np = inputs.mixture_pair(n, 4, 29)
+    mu, nu = dev(mu_np), dev(nu_np)
+    _say(f"large grid repeatable {dtype}")
+    a = _solve_pot(fs1, mu, nu, 1e-4, 40, dtype, "auto")
+    b = _solve_pot(fs1, mu, nu, 1e-4, 40, dtype, "auto")
+    assert a.w1 == b.w1 and a.marginal_err == b.marginal_err
+    assert torch.equal(a.F, b.F) and torch.equal(a.G, b.G)
