@@ -91,6 +91,7 @@ def _load():
         "or_fs1": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_fs1_log": (ctypes.c_int, [i64, p, p, d, d, d, i64, p, p, p]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_set_num_threads": (None, [ctypes.c_int]),
         "or_fs1_absorb": (ctypes.c_int, [i64, p, p, d, d, d, i64, d, p, p, p, p, p]),
         "or_kv2_dense": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
         "or_kv2_fs1": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
@@ -119,6 +120,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Thread count of the OpenMP loops of the dense routines."""
+    _load().or_set_num_threads(int(k))
 
 
 # --------------------------------------------------------------------------

@@ -872,6 +872,16 @@ int or_fs1_2d(int64_t n1, int64_t n2, const double *mu, const double *nu, double
     return solve2(0, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, phi, psi, res);
 }
 
+/* Thread count of the OpenMP loops (timing on a stated number of cores). */
+void or_set_num_threads(int k) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(k > 0 ? k : 1);
+#else
+    (void)k;
+#endif
+}
+
 /* Number of OpenMP threads the dense routines use (1 without OpenMP). */
 int or_num_threads(void) {
 #ifdef _OPENMP

@@ -19,21 +19,33 @@ def test_more_than_one_gpu_is_refused():
     assert p.stdout == ""
 
 
-def test_traffic_record_follows_the_kernel_sources(monkeypatch):
+def test_traffic_record_follows_the_kernel_sources(monkeypatch, tmp_path):
+    srcs = ["fs1_large.hip", "fs1_frame.h"]
+    rec = {"entries": {"c4:f64": {"kernel_sources": srcs,
+                                  "kernel_source_sha": bench.source_hash(srcs),
+                                  "bytes_per_launch": 123}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic("f64", "c4") == 123
+    assert bench.measured_traffic("f32", "c4") is None  # no such record
+    rec["entries"]["c4:f64"]["kernel_source_sha"] = "0" * 16  # sources changed since
+    p.write_text(json.dumps(rec))
+    assert bench.measured_traffic("f64", "c4") is None
+
+
+def test_committed_traffic_records_name_existing_sources():
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        return
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
-    want = rec["entries"]["c2:f64"]["bytes_per_launch"]
-    # the record describes a per-launch volume near the algorithmic bytes
-    assert 1.0 <= want / rec["entries"]["c2:f64"]["alg_bytes_per_launch"] < 1.5
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["kernel_source_sha"])
-    assert bench.measured_traffic("f64", "c2") == want
-    assert bench.measured_traffic("f32", "c2") is None  # no such record
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic("f64", "c2") is None  # sources changed since
+    for key, e in rec["entries"].items():
+        assert all(os.path.exists(os.path.join(bench.CSRC, s)) for s in e["kernel_sources"]), key
+        assert 1.0 <= e["bytes_per_launch"] / e["alg_bytes_per_launch"] < 1.5, key
 
 
-def test_kernel_source_hash_covers_the_fused_kernel_sources():
-    names = {os.path.basename(p) for p in bench.KERNEL_SOURCES}
-    assert {"fs1_fused.hip", "fs1_frame.h", "fs1_device.h", "fs1_tile.h"} <= names
-    assert all(os.path.exists(p) for p in bench.KERNEL_SOURCES)
-    assert len(bench.kernel_source_hash()) == 16
+def test_algorithmic_bytes_per_point():
+    # binary64: psi-half 32 B (phi, nu, old psi, new psi), phi-half 24 B
+    assert bench.ALG_BYTES_PER_POINT["f64"] == 28
+    # binary32: psi-half 4 + 4 + 4 + 4 + 8 (binary64 nu for the error), phi-half 12
+    assert bench.ALG_BYTES_PER_POINT["f32"] == 18
