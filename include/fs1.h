@@ -213,6 +213,21 @@ typedef struct {
 int fs1_solve(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
               double tol, const fs1_opts *opts, fs1_result *out);
 
+/* fs1_solve on a fixed device workspace, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, results and errors as
+ * fs1_solve, except: the workspace is a library-owned device array of 64 MiB
+ * per GPU (allocated with the code object, held until the process ends), so a
+ * grid needing more (above about 1.6e6 entries in binary64, 1.8e6 in binary32,
+ * 1.16e6 with FS1_ABSORB) fails with FS1_ERR_INVALID_ARG before any launch
+ * (the message states the bytes needed); diagnostic timing
+ * (fs1_ctx_set_profiling) is not recorded; the context's device must be the
+ * current device.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (other streams or host threads) race; calls in sequence
+ * do not.  Allocates no device or pinned host memory. */
+int fs1_solve_noalloc(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
+                      double tol, const fs1_opts *opts, fs1_result *out);
+
 /* Ragged batch of independent solves (Algorithm 1 per instance).  Instance b
  * occupies [offsets[b], offsets[b+1]) of mu_packed / nu_packed (device
  * binary64; the arrays themselves 16-byte aligned, instances anywhere in them);

@@ -552,6 +552,16 @@ int fs1_opts_default(fs1_opts* o) {
 
 int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
               const fs1_opts* opts_in, fs1_result* out) {
+  return fs1::host::solve_on(ctx, mu, nu, n, eps, tol, opts_in, out, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace fs1 {
+namespace host {
+
+int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
+             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap) {
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   if (!out) return set_err(FS1_ERR_INVALID_ARG, "null result pointer");
   std::memset(out, 0, sizeof(*out));
@@ -663,9 +673,19 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   {
     Carve probe(nullptr);
     layout(probe);
-    st = ensure_ws(ctx, probe.off);
-    if (st) return finish(st);
-    Carve w(ctx->ws);
+    char* base = fixed_ws;
+    if (fixed_ws) {
+      if (probe.off > fixed_cap)
+        return finish(set_err(FS1_ERR_INVALID_ARG,
+                              "the solve needs %zu bytes of workspace, more than the %zu "
+                              "bytes available",
+                              probe.off, fixed_cap));
+    } else {
+      st = ensure_ws(ctx, probe.off);
+      if (st) return finish(st);
+      base = ctx->ws;
+    }
+    Carve w(base);
     layout(w);
   }
   b.dtype = dt;
@@ -704,7 +724,8 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   HIP_TRY(launch_init_state(b, k, s));
 
   // diagnostic timing: events around every half-iteration kernel of a batch
-  const bool prof = ctx->profiling != 0;
+  // (a fixed workspace means the caller cannot allocate: no timing events)
+  const bool prof = ctx->profiling != 0 && !fixed_ws;
   if (prof && ctx->events.size() < 4) {
     while (ctx->events.size() < 4) {
       hipEvent_t e;
@@ -868,6 +889,11 @@ int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, doubl
   }
   return finish(FS1_OK);
 }
+
+}  // namespace host
+}  // namespace fs1
+
+extern "C" {
 
 int fs1_kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
                     double h2, double eps, int dt) {

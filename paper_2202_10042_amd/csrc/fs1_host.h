@@ -52,6 +52,13 @@ int check_h_eps(int64_t n, double h, double eps);
 int capture_iterations(fs1_ctx* ctx, const BatchBufs& z, const std::vector<BatchGroup>& groups,
                        int count, hipGraphExec_t* out);
 
+// Body of fs1_solve.  fixed_ws == nullptr: workspace from the context (grown on
+// demand); otherwise the solve runs on fixed_ws (device memory of fixed_cap
+// bytes) and allocates nothing, failing with FS1_ERR_INVALID_ARG if the grid
+// needs more.
+int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
+             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap);
+
 // Bump allocator over a workspace (a null base only measures).
 struct Carve {
   char* base;

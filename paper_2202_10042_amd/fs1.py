@@ -45,7 +45,7 @@ EXPORTS = (
     "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
-    "fs1_solve_2d", "fs1_stream_copy",
+    "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc",
 )
 
 
@@ -181,6 +181,8 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
+    lib.fs1_solve_noalloc.argtypes = lib.fs1_solve.argtypes
+    lib.fs1_solve_noalloc.restype = ctypes.c_int
     lib.fs1_stream_copy.argtypes = [vp, vp, vp, i64, ctypes.c_int]
     lib.fs1_stream_copy.restype = ctypes.c_int
     _lib = lib
@@ -319,8 +321,11 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
               dtype: str = "f64", domain: str = "plain", check_every: int = 1,
               sync_every: int = 16, potentials: bool = False, err_history: bool = False,
               solver: str = "auto", ctx: Optional[Context] = None,
-              raise_on_error: bool = False, tau: float = 1e3) -> Result:
+              raise_on_error: bool = False, tau: float = 1e3, noalloc: bool = False) -> Result:
     """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
+
+    noalloc: call fs1_solve_noalloc (the library's fixed 64 MiB workspace per
+    GPU instead of the context's; the output tensors are still allocated here).
 
     domain: "plain" (Algorithm 1 as printed), "log" (stabilised, absorption
     at every half-iteration) or "absorb" (the stabilisation with threshold
@@ -349,8 +354,9 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
         hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)
         o.err_history = hist.data_ptr()
     r = CResult()
-    st = load().fs1_solve(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps), float(tol),
-                          ctypes.byref(o), ctypes.byref(r))
+    call = load().fs1_solve_noalloc if noalloc else load().fs1_solve
+    st = call(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps), float(tol),
+              ctypes.byref(o), ctypes.byref(r))
     if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
             raise_on_error and st != FS1_OK):
         raise Fs1Error(st, last_error())
