@@ -76,10 +76,27 @@ typedef enum {
 
 typedef struct fs1_ctx fs1_ctx;
 
+/* Device memory from the caller's allocator (e.g. a framework's caching
+ * allocator): alloc returns `bytes` of device memory on the context's device,
+ * 16-byte aligned, usable on the context's stream (NULL when it has none);
+ * free gives back a block alloc returned.  Both are called on the host thread
+ * that makes the library call. */
+typedef void *(*fs1_alloc_fn)(size_t bytes, void *user);
+typedef void (*fs1_free_fn)(void *ptr, void *user);
+
 /* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL =
  * null stream) on the device current at the time of the call.  The context
  * owns its workspace (grown on demand, freed by fs1_ctx_destroy). */
 int fs1_ctx_create(void *stream, fs1_ctx **out);
+/* As fs1_ctx_create, with every device allocation of the context -- the
+ * solve workspace (O(n) scalars plus O(n / chunk) carry words, grown on demand;
+ * the old block is freed after the stream has finished with it) and the pool
+ * of a server created on it -- taken from alloc and given back through
+ * free_fn (by fs1_ctx_destroy, fs1_server_destroy or a workspace regrowth).
+ * alloc and free_fn are both given or both NULL (then hipMalloc / hipFree);
+ * otherwise FS1_ERR_INVALID_ARG.  Pinned host staging still comes from HIP. */
+int fs1_ctx_create_with_allocator(void *stream, fs1_alloc_fn alloc, fs1_free_fn free_fn,
+                                  void *user, fs1_ctx **out);
 int fs1_ctx_destroy(fs1_ctx *ctx);
 /* Rebind the context to another stream (e.g. the caller's current stream). */
 int fs1_ctx_set_stream(fs1_ctx *ctx, void *stream);
@@ -186,10 +203,28 @@ typedef struct {
                              checked iteration l (index l), NaN elsewhere         */
     double tau;           /* FS1_ABSORB: absorption threshold on the scaled
                              vectors (> 0, finite; default 1e3)                   */
+    /* Scalings in split form: phi_i = m[i] 2^e[i], psi_j = m[n+j] 2^e[n+j]
+     * (m: 2n doubles, e: 2n int32, device arrays, 16-byte aligned).        */
+    const double *warm_m;   /* warm start: with warm_e, Algorithm 1 starts from
+                               these (phi^0, psi^0) instead of 1/n; NULL: 1/n.
+                               m finite and >= 0, |e| <= 2^20 (else
+                               FS1_ERR_INVALID_ARG); in FS1_PLAIN every m 2^e
+                               must be finite in the working precision.  Not
+                               with FS1_ABSORB.                                   */
+    const int32_t *warm_e;
+    double *state_m;        /* the final (phi, psi) in the same split form, or
+                               NULL.  Exact: a solve of k iterations followed by a
+                               warm-started solve of j more gives the same bits
+                               (W, errors, potentials, state) as one solve of
+                               k + j iterations with the same dtype, domain and
+                               solver flags.                                      */
+    int32_t *state_e;
 } fs1_opts;
 
 /* Fill *o with the defaults (h = 1/n, itr_max 10000, FS1_F64, FS1_PLAIN, tau 1e3,
- * check_every 1, sync_every 16, no potentials, no history). */
+ * check_every 1, sync_every 16, no potentials, no history, no warm start, no
+ * state output).  fs1_solve_batched, fs1_solve_2d and the server ignore the
+ * warm-start and state fields. */
 int fs1_opts_default(fs1_opts *o);
 
 typedef struct {

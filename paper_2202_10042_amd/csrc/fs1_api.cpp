@@ -54,22 +54,49 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+int dev_alloc(fs1_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  if (c->alloc) {
+    void* p = c->alloc(bytes, c->alloc_user);
+    if (!p) return set_err(FS1_ERR_NO_MEMORY, "the caller's allocator returned no memory for %zu bytes", bytes);
+    if (!aligned16(p)) {
+      c->free(p, c->alloc_user);
+      return set_err(FS1_ERR_NO_MEMORY, "the caller's allocator returned memory that is not 16-byte aligned");
+    }
+    *out = p;
+    return FS1_OK;
+  }
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return set_err(FS1_ERR_NO_MEMORY, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return FS1_OK;
+}
+
+void dev_free(fs1_ctx* c, void* p) {
+  if (!p) return;
+  if (c->free)
+    c->free(p, c->alloc_user);
+  else
+    (void)hipFree(p);
+}
+
 // Grow the context workspace to at least `bytes` (stream-synchronised when the
 // old buffer is released, because earlier asynchronous calls may still use it).
 int ensure_ws(fs1_ctx* c, size_t bytes) {
   if (bytes <= c->ws_size) return FS1_OK;
   if (c->ws) {
     HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipFree(c->ws));
+    dev_free(c, c->ws);
     c->ws = nullptr;
     c->ws_size = 0;
   }
   const size_t sz = round_up(bytes, size_t(1) << 20);
-  hipError_t e = hipMalloc(&c->ws, sz);
-  if (e != hipSuccess) {
-    c->ws = nullptr;
-    return set_err(FS1_ERR_NO_MEMORY, "hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
-  }
+  void* p = nullptr;
+  const int st = dev_alloc(c, sz, &p);
+  if (st) return st;
+  c->ws = static_cast<char*>(p);
   c->ws_size = sz;
   return FS1_OK;
 }
@@ -463,11 +490,21 @@ const char* fs1_last_error(void) { return last_error_text(); }
 const char* fs1_version(void) { return "fs1 0.1 (gfx950)"; }
 
 int fs1_ctx_create(void* stream, fs1_ctx** out) {
+  return fs1_ctx_create_with_allocator(stream, nullptr, nullptr, nullptr, out);
+}
+
+int fs1_ctx_create_with_allocator(void* stream, fs1_alloc_fn alloc, fs1_free_fn free_fn,
+                                  void* user, fs1_ctx** out) {
   if (!out) return set_err(FS1_ERR_INVALID_ARG, "null output pointer");
   *out = nullptr;
+  if (!alloc != !free_fn)
+    return set_err(FS1_ERR_INVALID_ARG, "give both allocator callbacks or neither");
   fs1_ctx* c = new (std::nothrow) fs1_ctx();
   if (!c) return set_err(FS1_ERR_NO_MEMORY, "context allocation failed");
   c->stream = static_cast<hipStream_t>(stream);
+  c->alloc = alloc;
+  c->free = free_fn;
+  c->alloc_user = user;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;
@@ -496,7 +533,7 @@ int fs1_ctx_destroy(fs1_ctx* c) {
   for (hipStream_t a : c->aux)
     if (a) (void)hipStreamDestroy(a);
   if (c->hstage) (void)hipHostFree(c->hstage);
-  if (c->ws) (void)hipFree(c->ws);
+  if (c->ws) dev_free(c, c->ws);
   if (c->hctrl) (void)hipHostFree(c->hctrl);
   delete c;
   return FS1_OK;
@@ -595,6 +632,16 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
   if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
   if ((o.flags & 1) && !o.potentials_out)
     return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
+  const bool warm = o.warm_m != nullptr || o.warm_e != nullptr;
+  if (warm && (!o.warm_m || !o.warm_e))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "a warm start needs both warm_m and warm_e"));
+  if (warm && tau_mode)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "no warm start in the absorption variant"));
+  if ((o.state_m != nullptr) != (o.state_e != nullptr))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "the state output needs both state_m and state_e"));
+  if ((warm && (!aligned16(o.warm_m) || !aligned16(o.warm_e))) ||
+      (o.state_m && (!aligned16(o.state_m) || !aligned16(o.state_e))))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned"));
   int st = check_h_eps(n, h, eps);
   if (st) return finish(st);
 
@@ -707,10 +754,16 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
   // a1: validate the marginals on the device (finite, >= 0, equal mass)
   HIP_TRY(hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), s));
   HIP_TRY(launch_setup(b, s));
+  // a warm start writes the state now (and checks it with the marginals)
+  if (warm) HIP_TRY(launch_warm(b, o.warm_m, o.warm_e, s));
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (hc->bad_input)
+  if (hc->bad_input & 1)
     return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must be finite and >= 0"));
+  if (hc->bad_input & 2)
+    return finish(set_err(FS1_ERR_INVALID_ARG,
+                          "warm start: mantissas must be finite and >= 0, |exponents| <= 2^20, "
+                          "and (plain domain) every scaling finite in the working precision"));
   if (!(hc->sum_mu > 0.0) || !(hc->sum_nu > 0.0))
     return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must have positive mass"));
   if (std::fabs(hc->sum_mu - hc->sum_nu) > 1e-10 * hc->sum_mu)
@@ -721,7 +774,7 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
 
   const ScanConsts k = make_scan_consts(h, eps, R);
   const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
-  HIP_TRY(launch_init_state(b, k, s));
+  HIP_TRY(launch_init_state(b, k, warm, s));
 
   // diagnostic timing: events around every half-iteration kernel of a batch
   // (a fixed workspace means the caller cannot allocate: no timing events)
@@ -876,6 +929,7 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
   if (tiled) HIP_TRY(launch_relayout(b, false, gbuf, s));
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
+  if (o.state_m) HIP_TRY(launch_state_out(b, gbuf, o.state_m, o.state_e, s));
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   out->w1 = hc->w1;
@@ -963,6 +1017,10 @@ int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_pa
     so.flags = 0;
     so.potentials_out = nullptr;
     so.err_history = nullptr;
+    so.warm_m = nullptr;
+    so.warm_e = nullptr;
+    so.state_m = nullptr;
+    so.state_e = nullptr;
     for (int32_t i = 0; i < B; ++i) {
       const int64_t a = offsets[i];
       if (!aligned16(mu_packed + a) || !aligned16(nu_packed + a)) {

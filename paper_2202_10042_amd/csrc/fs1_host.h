@@ -16,6 +16,10 @@
 struct fs1_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
+  // caller's device allocator (fs1_ctx_create_with_allocator); null: hipMalloc
+  fs1_alloc_fn alloc = nullptr;
+  fs1_free_fn free = nullptr;
+  void* alloc_user = nullptr;
   char* ws = nullptr;      // device workspace
   size_t ws_size = 0;
   fs1::Ctrl* hctrl = nullptr;  // pinned host mirror of the control block
@@ -44,6 +48,10 @@ int hip_fail(hipError_t e, const char* what);
 const char* last_error_text();
 
 bool aligned16(const void* p);
+// Device memory of a context: from the caller's allocator when it gave one,
+// else hipMalloc / hipFree.
+int dev_alloc(fs1_ctx* c, size_t bytes, void** out);
+void dev_free(fs1_ctx* c, void* p);
 size_t round_up(size_t x, size_t a);
 int ensure_ws(fs1_ctx* c, size_t bytes);
 int ensure_hstage(fs1_ctx* c, size_t bytes);

@@ -20,6 +20,8 @@
 // arithmetic is the same whenever it was admitted and whatever runs beside it.
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -424,12 +426,17 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   }
   Carve probe(nullptr);
   carve(v, probe);
-  hipError_t e = hipMalloc(&v->mem, probe.off);
-  if (e != hipSuccess) {
-    delete v;
-    return set_err(FS1_ERR_NO_MEMORY, "hipMalloc(%zu) for the server pool failed: %s",
-                   probe.off, hipGetErrorString(e));
+  {
+    void* pool = nullptr;
+    const int st = dev_alloc(ctx, probe.off, &pool);
+    if (st) {
+      delete v;
+      return set_err(st, "server pool of %zu bytes: %s", probe.off,
+                     std::string(last_error_text()).c_str());
+    }
+    v->mem = static_cast<char*>(pool);
   }
+  hipError_t e = hipSuccess;
   Carve w(v->mem);
   carve(v, w);
   v->z.ndone = v->z.iter_base + 1;
@@ -444,7 +451,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
                         size_t(v->nslots) * sizeof(ChunkRef) + 256;
   e = hipHostMalloc(reinterpret_cast<void**>(&v->hmem), hbytes, hipHostMallocDefault);
   if (e != hipSuccess) {
-    (void)hipFree(v->mem);
+    dev_free(ctx, v->mem);
     delete v;
     return set_err(FS1_ERR_NO_MEMORY, "hipHostMalloc(%zu) failed: %s", hbytes,
                    hipGetErrorString(e));
@@ -471,7 +478,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipHostFree(v->hmem);
-    (void)hipFree(v->mem);
+    dev_free(ctx, v->mem);
     delete v;
     return hip_fail(e, "server initialisation");
   }
@@ -484,7 +491,7 @@ int fs1_server_destroy(fs1_server* v) {
   (void)hipStreamSynchronize(v->ctx->stream);
   if (v->gexec) (void)hipGraphExecDestroy(v->gexec);
   if (v->hmem) (void)hipHostFree(v->hmem);
-  if (v->mem) (void)hipFree(v->mem);
+  if (v->mem) dev_free(v->ctx, v->mem);
   delete v;
   return FS1_OK;
 }

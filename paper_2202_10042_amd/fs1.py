@@ -45,8 +45,12 @@ EXPORTS = (
     "fs1_kv_apply_log", "fs1_opts_default", "fs1_solve", "fs1_solve_batched",
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
-    "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc",
+    "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc", "fs1_ctx_create_with_allocator",
 )
+
+# fs1_alloc_fn / fs1_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Fs1Error(RuntimeError):
@@ -67,6 +71,10 @@ class Opts(ctypes.Structure):
         ("potentials_out", ctypes.c_void_p),
         ("err_history", ctypes.c_void_p),
         ("tau", ctypes.c_double),
+        ("warm_m", ctypes.c_void_p),
+        ("warm_e", ctypes.c_void_p),
+        ("state_m", ctypes.c_void_p),
+        ("state_e", ctypes.c_void_p),
     ]
 
 
@@ -120,6 +128,7 @@ class Result:
     G: Optional[object] = None        # torch tensor ln(psi) when requested
     err_history: Optional[object] = None
     absorptions: int = 0              # domain "absorb": times the tau test fired
+    state: Optional[tuple] = None     # (m, e): final phi, psi in split form when requested
 
 
 _lib = None
@@ -137,6 +146,8 @@ def load(path: str = LIB_PATH):
     vp, i64, d, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32
     lib.fs1_ctx_create.argtypes = [vp, ctypes.POINTER(vp)]
     lib.fs1_ctx_create.restype = ctypes.c_int
+    lib.fs1_ctx_create_with_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp, ctypes.POINTER(vp)]
+    lib.fs1_ctx_create_with_allocator.restype = ctypes.c_int
     lib.fs1_ctx_destroy.argtypes = [vp]
     lib.fs1_ctx_destroy.restype = ctypes.c_int
     lib.fs1_ctx_set_stream.argtypes = [vp, vp]
@@ -199,9 +210,13 @@ def _check(st: int):
 
 
 class Context:
-    """A libfs1 context bound to a HIP stream (default: torch's current stream)."""
+    """A libfs1 context bound to a HIP stream (default: torch's current stream).
 
-    def __init__(self, stream=None):
+    allocator="torch": the context's device memory (solve workspace, server
+    pools) comes from PyTorch's caching allocator through the library's
+    allocator callbacks, on the context's current stream."""
+
+    def __init__(self, stream=None, allocator: Optional[str] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libfs1 needs a ROCm GPU; none is visible")
@@ -210,7 +225,27 @@ class Context:
             stream = torch.cuda.current_stream()
         self._stream_obj = stream
         h = ctypes.c_void_p()
-        _check(lib.fs1_ctx_create(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        if allocator is None:
+            _check(lib.fs1_ctx_create(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        elif allocator == "torch":
+            device = torch.cuda.current_device()
+
+            def _alloc(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device,
+                                                              self._stream_obj)
+                except RuntimeError:
+                    return None
+
+            def _free(ptr, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._callbacks = (ALLOC_FN(_alloc), FREE_FN(_free))  # kept alive with the context
+            _check(lib.fs1_ctx_create_with_allocator(ctypes.c_void_p(stream.cuda_stream),
+                                                     self._callbacks[0], self._callbacks[1],
+                                                     None, ctypes.byref(h)))
+        else:
+            raise ValueError(f"unknown allocator {allocator!r}")
         self.handle = h
 
     def set_stream(self, stream):
@@ -321,8 +356,14 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
               dtype: str = "f64", domain: str = "plain", check_every: int = 1,
               sync_every: int = 16, potentials: bool = False, err_history: bool = False,
               solver: str = "auto", ctx: Optional[Context] = None,
-              raise_on_error: bool = False, tau: float = 1e3, noalloc: bool = False) -> Result:
+              raise_on_error: bool = False, tau: float = 1e3, noalloc: bool = False,
+              warm=None, state: bool = False) -> Result:
     """Algorithm 1 (FS-1) on device marginals mu, nu (float64 tensors).
+
+    warm: (m, e) device tensors (float64 and int32, 2n entries each, phi then
+    psi): start from phi_i = m[i] 2^e[i], psi_j = m[n+j] 2^e[n+j] instead of
+    1/n.  state: return the final (phi, psi) in that split form as
+    Result.state (a later solve warm-started from it continues bit for bit).
 
     noalloc: call fs1_solve_noalloc (the library's fixed 64 MiB workspace per
     GPU instead of the context's; the output tensors are still allocated here).
@@ -353,6 +394,19 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
     if err_history:
         hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)
         o.err_history = hist.data_ptr()
+    if warm is not None:
+        wm, we = warm
+        if wm.numel() != 2 * n or we.numel() != 2 * n or wm.dtype != torch.float64 or \
+                we.dtype != torch.int32:
+            raise ValueError("warm start: (float64, int32) tensors of 2n entries")
+        o.warm_m = _dev(wm, "warm_m").value
+        o.warm_e = _dev(we, "warm_e").value
+    st_m = st_e = None
+    if state:
+        st_m = torch.empty(2 * n, dtype=torch.float64, device=mu.device)
+        st_e = torch.empty(2 * n, dtype=torch.int32, device=mu.device)
+        o.state_m = st_m.data_ptr()
+        o.state_e = st_e.data_ptr()
     r = CResult()
     call = load().fs1_solve_noalloc if noalloc else load().fs1_solve
     st = call(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps), float(tol),
@@ -366,6 +420,8 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
         res.F, res.G = pot[:n], pot[n:]
     if hist is not None:
         res.err_history = hist
+    if st_m is not None and st == FS1_OK:
+        res.state = (st_m, st_e)
     return res
 
 

@@ -46,12 +46,13 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "fs1.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fs1_opts),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(fs1_opts),
          offsetof(fs1_opts, itr_max), offsetof(fs1_opts, check_every),
          offsetof(fs1_opts, flags), offsetof(fs1_opts, potentials_out),
          offsetof(fs1_opts, err_history), sizeof(fs1_result),
          offsetof(fs1_result, iterations), offsetof(fs1_result, status),
-         offsetof(fs1_result, mu_err));
+         offsetof(fs1_result, mu_err), offsetof(fs1_opts, warm_m), offsetof(fs1_opts, warm_e),
+         offsetof(fs1_opts, state_m), offsetof(fs1_opts, state_e));
   return 0;
 }
 ''')
@@ -63,7 +64,8 @@ int main(void) {
     O, R = fs1.Opts, fs1.CResult
     want = [ctypes.sizeof(O), O.itr_max.offset, O.check_every.offset, O.flags.offset,
             O.potentials_out.offset, O.err_history.offset, ctypes.sizeof(R),
-            R.iterations.offset, R.status.offset, R.mu_err.offset]
+            R.iterations.offset, R.status.offset, R.mu_err.offset, O.warm_m.offset,
+            O.warm_e.offset, O.state_m.offset, O.state_e.offset]
     assert got == want
 
 
@@ -80,6 +82,14 @@ def test_validation_before_any_launch():
     assert lib.fs1_opts_default(ctypes.byref(o)) == 0
     assert o.itr_max == 10000 and o.check_every == 1 and o.dtype == 0 and o.domain == 0
     assert lib.fs1_version().decode().startswith("fs1")
+    # allocator callbacks come in pairs (checked before any device call)
+    h = ctypes.c_void_p()
+    alloc = fs1.ALLOC_FN(lambda n, u: None)
+    st = lib.fs1_ctx_create_with_allocator(None, alloc, fs1.FREE_FN(), None, ctypes.byref(h))
+    assert st == fs1.FS1_ERR_INVALID_ARG and "callbacks" in fs1.last_error()
+    # the no-allocation solve validates its context first
+    st = lib.fs1_solve_noalloc(None, None, None, 10, 0.1, 0.0, None, ctypes.byref(r))
+    assert st == fs1.FS1_ERR_INVALID_ARG
 
 
 def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
