@@ -204,7 +204,12 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a, ScanConsts k) {
   publish_frame<T, R>(q, -eap, L, D, sf, sb, a.A_out, es, red, want_err ? a.part : nullptr);
 }
 
-// Chunk aggregates of a stored vector (initial state, finalisation).
+// Chunk aggregates of a stored vector (initial or warm-start state), by the
+// same weighted reductions that k_fused publishes with (publish_frame), on the
+// chunk's frame: the values of a vector handed from one solve to the next by
+// the warm start give the aggregates the continuing solve had, bit for bit
+// (the two representations differ by a power of two per run, which every
+// step of the reduction carries exactly).
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_publish(const T* __restrict__ v,
                                                     const int* __restrict__ ex, int64_t n,
@@ -216,11 +221,14 @@ __global__ __launch_bounds__(kBlock) void k_publish(const T* __restrict__ v,
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   T x[R];
   load_run_z<T, R>(v, run * R, x);
+  const int e = ex[run];
+  const int eb = block_max_int(local_exponent<T, R>(x, e), smax);
+  T xf[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) xf[j] = (eb == kExpZero) ? T(0) : ldx(x[j], e - eb);
   const Lam<T> L = lam_of<T>(k);
   const FastDec<T> D = make_fast_dec<T>(k, lane);
-  HalfState<T, R> hs;
-  local_scan<T, R>(x, ex[run], L, D, sf, sb, smax, hs);
-  publish<T>(D, sf, sb, hs.ein, A);
+  publish_frame<T, R>(xf, eb == kExpZero ? 0 : eb, L, D, sf, sb, A);
 }
 
 template <typename T, int R>

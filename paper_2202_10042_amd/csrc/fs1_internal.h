@@ -218,7 +218,15 @@ hipError_t launch_large_half(const SolveBufs& b, const ScanConsts& k, const Carr
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 hipError_t launch_setup(const SolveBufs& b, hipStream_t s);
-hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s);
+// Initial state phi = psi = 1/n (warm = false) and phi's chunk aggregates;
+// with warm = true only the aggregates (launch_warm has written the state).
+hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, bool warm, hipStream_t s);
+// Warm start from split scalings (m: 2n doubles, e: 2n ints; phi then psi);
+// bad input sets bit 1 of ctrl->bad_input.  Resets the control block's
+// iteration fields as the initial state does.
+hipError_t launch_warm(const SolveBufs& b, const double* m, const int* e, hipStream_t s);
+// Final phi and psi = vG[gbuf] (run layout) in split form into m, e (2n each).
+hipError_t launch_state_out(const SolveBufs& b, int gbuf, double* m, int* e, hipStream_t s);
 // The fused path iterates on vectors in the tile layout of fs1_tile.h, and so
 // does the general path where solve_tiled() (binary64, run length a whole
 // number of 16-byte vectors): launch_relayout turns vF, vG[gbuf] and the

@@ -790,6 +790,87 @@ __global__ __launch_bounds__(256) void k_init(T* __restrict__ vf, T* __restrict_
   }
 }
 
+// Warm start: (phi, psi) from split scalings m 2^e (Algorithm 1 started from a
+// given pair instead of 1/n).  One thread per run of the solve's layout.  With
+// per-run exponents (ef, eg non-null) a run takes the largest exponent of its
+// entries and holds the mantissas shifted to it (exact, up to entries below
+// the working precision of the run); in plain arithmetic the values are
+// m 2^e themselves.  Entries past n are zero.  Invalid input (m not finite or
+// negative, |e| > 2^20, a plain value that overflows) sets bit 1 of
+// ctrl->bad_input.
+template <typename T>
+__global__ __launch_bounds__(256) void k_warm(const double* __restrict__ m,
+                                              const int* __restrict__ e, int64_t n, int R,
+                                              int64_t nruns, T* __restrict__ vf,
+                                              T* __restrict__ vg, int* ef, int* eg,
+                                              Ctrl* ctrl) {
+  constexpr int kMaxExp = 1 << 20;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  int bad = 0;
+  for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < nruns; r += stride) {
+    const int64_t base = r * R;
+    for (int side = 0; side < 2; ++side) {
+      const double* ms = m + side * n;
+      const int* es = e + side * n;
+      T* v = side ? vg : vf;
+      int* ex = side ? eg : ef;
+      int E = kExpZero;
+      for (int j = 0; j < R && base + j < n; ++j) {
+        const double mm = ms[base + j];
+        const int ee = es[base + j];
+        if (!(isfinite(mm) && mm >= 0.0) || ee > kMaxExp || ee < -kMaxExp) {
+          bad = 1;
+        } else if (mm > 0.0) {
+          int k;
+          frexp(mm, &k);
+          E = max(E, ee + k);
+        }
+      }
+      if (E == kExpZero) E = 0;
+      for (int j = 0; j < R; ++j) {
+        const int64_t i = base + j;
+        T val = T(0);
+        if (i < n) {
+          const double mm = ms[i];
+          const int ee = es[i];
+          if (isfinite(mm) && mm > 0.0 && ee <= kMaxExp && ee >= -kMaxExp) {
+            val = ex ? T(ldexp(mm, ee - E)) : T(ldexp(mm, ee));
+            if (!isfinite(val)) bad = 1;
+          }
+        }
+        v[i] = val;
+      }
+      if (ex) ex[r] = E;
+    }
+  }
+  if (bad) atomicOr(&ctrl->bad_input, 2);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->done = 0;
+    ctrl->stop_iter = -1;
+    ctrl->fail = 0;
+    ctrl->fail_iter = INT_MAX;
+    ctrl->last_check = -1;
+    ctrl->last_err = NAN;
+    ctrl->barrier_timeout = 0;
+    ctrl->iters_done = 0;
+    ctrl->fail_half[0] = 0;
+    ctrl->fail_half[1] = 0;
+  }
+}
+
+// Final (phi or psi) in split form: m[i] = v[i], e[i] = the run exponent (0 in
+// plain arithmetic); the vector in runs of R.
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_out(const T* __restrict__ v,
+                                                   const int* __restrict__ ex, int R, int64_t n,
+                                                   double* __restrict__ m, int* __restrict__ e) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    m[i] = double(v[i]);
+    e[i] = ex ? ex[i / R] : 0;
+  }
+}
+
 // out = scale * sum(part[0..np)) in a fixed order
 __global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ part, int64_t np,
                                               double scale, double* out) {
@@ -1047,15 +1128,34 @@ struct SolveOps {
     }
     return hipGetLastError();
   }
-  static hipError_t init(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
-    const int64_t nruns = b.nchunks * kBlock;
-    const unsigned g = unsigned(std::min<int64_t>((std::max(b.npad, nruns) + 255) / 256, 4096));
-    k_init<T><<<g, 256, 0, s>>>(static_cast<T*>(b.vF), static_cast<T*>(b.vG[0]),
-                                AB ? b.eF : nullptr, AB ? b.eG[0] : nullptr, b.n, b.npad, nruns,
-                                b.ctrl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  static hipError_t init(const SolveBufs& b, const ScanConsts& k, bool warm, hipStream_t s) {
+    if (!warm) {
+      const int64_t nruns = b.nchunks * kBlock;
+      const unsigned g =
+          unsigned(std::min<int64_t>((std::max(b.npad, nruns) + 255) / 256, 4096));
+      k_init<T><<<g, 256, 0, s>>>(static_cast<T*>(b.vF), static_cast<T*>(b.vG[0]),
+                                  AB ? b.eF : nullptr, AB ? b.eG[0] : nullptr, b.n, b.npad,
+                                  nruns, b.ctrl);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     return setup_aggF(b, k, s);
+  }
+  static hipError_t warm(const SolveBufs& b, const double* m, const int* e, hipStream_t s) {
+    const int64_t nruns = b.nchunks * kBlock;
+    const unsigned g = unsigned(std::min<int64_t>((nruns + 255) / 256, 4096));
+    k_warm<T><<<g, 256, 0, s>>>(m, e, b.n, R, nruns, static_cast<T*>(b.vF),
+                                static_cast<T*>(b.vG[0]), AB ? b.eF : nullptr,
+                                AB ? b.eG[0] : nullptr, b.ctrl);
+    return hipGetLastError();
+  }
+  static hipError_t state_out(const SolveBufs& b, int gbuf, double* m, int* e, hipStream_t s) {
+    const unsigned g = unsigned(std::min<int64_t>((b.n + 255) / 256, 4096));
+    k_state_out<T><<<g, 256, 0, s>>>(static_cast<const T*>(b.vF), AB ? b.eF : nullptr, R, b.n,
+                                      m, e);
+    k_state_out<T><<<g, 256, 0, s>>>(static_cast<const T*>(b.vG[gbuf]),
+                                      AB ? b.eG[gbuf] : nullptr, R, b.n, m + b.n, e + b.n);
+    return hipGetLastError();
   }
   static hipError_t potentials(const SolveBufs& b, int gbuf, double* out, hipStream_t s) {
     const unsigned g = unsigned(std::min<int64_t>((b.n + 255) / 256, 4096));
@@ -1105,8 +1205,16 @@ hipError_t launch_relayout(const SolveBufs& b, bool to_tiles, int gbuf, hipStrea
   return dispatch(b, [&](auto ops) { return decltype(ops)::relayout(b, to_tiles, gbuf, s); });
 }
 
-hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
-  return dispatch(b, [&](auto ops) { return decltype(ops)::init(b, k, s); });
+hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, bool warm, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::init(b, k, warm, s); });
+}
+
+hipError_t launch_warm(const SolveBufs& b, const double* m, const int* e, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::warm(b, m, e, s); });
+}
+
+hipError_t launch_state_out(const SolveBufs& b, int gbuf, double* m, int* e, hipStream_t s) {
+  return dispatch(b, [&](auto ops) { return decltype(ops)::state_out(b, gbuf, m, e, s); });
 }
 
 hipError_t launch_half_psi(const SolveBufs& b, const ScanConsts& k, const CarryConsts& kc, int l,

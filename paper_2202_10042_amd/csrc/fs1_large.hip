@@ -203,13 +203,24 @@ __global__ __launch_bounds__(kBlock) void k_large(LargeArgs a, ScanConsts k) {
 
 // A vector in per-run exponents (tile layout) -> one exponent per chunk:
 // every run is rescaled to the chunk's largest exponent, so the values stay
-// below 1 and the chunk's frame is that exponent.
+// below 1 and the chunk's frame is that exponent.  With A non-null the
+// chunk's aggregates are published too, by the same weighted reductions that
+// k_large publishes its new vectors with: a vector handed from one solve to
+// the next by the warm start gives the aggregates the continuing solve had,
+// bit for bit (the representations differ by a power of two, which every
+// step of the reduction carries exactly).
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_large_pack(T* __restrict__ v,
                                                        const int* __restrict__ ex,
-                                                       ChunkExp* __restrict__ xout) {
+                                                       ChunkExp* __restrict__ xout,
+                                                       ChunkAgg* __restrict__ A,
+                                                       const void* __restrict__ lanetab,
+                                                       ScanConsts k) {
   __shared__ int smax[kNW];
+  __shared__ T pf[kNW];
+  __shared__ T pb[kNW];
   const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
   const int64_t run = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   T x[R];
   tile_load<T, R>(v, run, lane, x);
@@ -219,6 +230,22 @@ __global__ __launch_bounds__(kBlock) void k_large_pack(T* __restrict__ v,
   for (int j = 0; j < R; ++j) x[j] = (eb == kExpZero) ? T(0) : ldx(x[j], e - eb);
   tile_store<T, R>(v, run, lane, x);
   if (threadIdx.x == 0) xout[blockIdx.x] = ChunkExp{eb == kExpZero ? 0 : eb, eb};
+  if (A) {
+    const LaneDec<T> ld = static_cast<const LaneDec<T>*>(lanetab)[lane];
+    const FastDec<T> D = fast_dec_of<T>(k, ld);
+    const Lam<T> L = lam_of<T>(k);
+    T nf, nb;
+    run_aggs<T, R>(x, L, nf, nb);
+    nf = wave_sum(nf * D.lane_b);
+    nb = wave_sum(nb * D.lane_f);
+    if (lane == 0) {
+      pf[w] = nf;
+      pb[w] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) chunk_aggs<T>(D, pf, pb, eb == kExpZero ? 0 : eb, A[blockIdx.x].f,
+                                        A[blockIdx.x].b);
+  }
 }
 
 // One exponent per chunk -> per-run exponents (for the finalisation).
@@ -286,9 +313,10 @@ struct LargeOps {
   }
   static hipError_t pack(const SolveBufs& b, const ScanConsts& k, hipStream_t s) {
     k_lane_table<T><<<1, kWave, 0, s>>>(k, static_cast<LaneDec<T>*>(b.lanetab));
-    k_large_pack<T, R><<<unsigned(b.nchunks), kBlock, 0, s>>>(static_cast<T*>(b.vF), b.eF, b.xF);
-    k_large_pack<T, R><<<unsigned(b.nchunks), kBlock, 0, s>>>(static_cast<T*>(b.vG[0]), b.eG[0],
-                                                              b.xG[0]);
+    k_large_pack<T, R><<<unsigned(b.nchunks), kBlock, 0, s>>>(static_cast<T*>(b.vF), b.eF, b.xF,
+                                                              b.aggF, b.lanetab, k);
+    k_large_pack<T, R><<<unsigned(b.nchunks), kBlock, 0, s>>>(
+        static_cast<T*>(b.vG[0]), b.eG[0], b.xG[0], nullptr, b.lanetab, k);
     return hipGetLastError();
   }
 };
