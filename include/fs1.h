@@ -248,6 +248,26 @@ typedef struct {
 int fs1_solve(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
               double tol, const fs1_opts *opts, fs1_result *out);
 
+/* fs1_solve enqueued without any host synchronisation, for stream capture
+ * into a HIP graph and for pipelined callers.  The solve is the same (same
+ * kernels, same arithmetic, same results); its fs1_result is written to
+ * out_dev (device memory, 16-byte aligned) when the stream reaches the end of
+ * the solve.  All launches of itr_max iterations are enqueued -- those after
+ * the stopping test is met return at once -- so itr_max bounds the work;
+ * opts->sync_every and diagnostic timing do not apply.  The marginals are
+ * checked on the device: invalid ones give out_dev->status =
+ * FS1_ERR_INVALID_ARG (iterations 0, W NaN), a non-finite scaling
+ * FS1_ERR_NONFINITE with iterations = the failing iteration.  FS1_ABSORB and
+ * FS1_FLAG_PERSISTENT are FS1_ERR_INVALID_ARG.  The return value reports
+ * argument errors found on the host and launch failures only.  Under capture
+ * nothing is allocated, set by a memset node or synchronised, provided the
+ * context's workspace already fits the solve (an earlier call of the same
+ * size on the context, outside the capture, grows it); otherwise the call
+ * fails with FS1_ERR_INVALID_ARG.  Inputs and outputs must stay valid until
+ * the stream has run the solve. */
+int fs1_solve_async(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n, double eps,
+                    double tol, const fs1_opts *opts, fs1_result *out_dev);
+
 /* fs1_solve on a fixed device workspace, for callers that cannot allocate
  * device memory during the call (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Arguments, results and errors as

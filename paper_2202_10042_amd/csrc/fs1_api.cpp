@@ -589,7 +589,14 @@ int fs1_opts_default(fs1_opts* o) {
 
 int fs1_solve(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
               const fs1_opts* opts_in, fs1_result* out) {
-  return fs1::host::solve_on(ctx, mu, nu, n, eps, tol, opts_in, out, nullptr, 0);
+  return fs1::host::solve_on(ctx, mu, nu, n, eps, tol, opts_in, out, nullptr, 0, nullptr);
+}
+
+int fs1_solve_async(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps,
+                    double tol, const fs1_opts* opts, fs1_result* out_dev) {
+  if (!out_dev) return set_err(FS1_ERR_INVALID_ARG, "null result pointer");
+  fs1_result host{};
+  return fs1::host::solve_on(ctx, mu, nu, n, eps, tol, opts, &host, nullptr, 0, out_dev);
 }
 
 }  // extern "C"
@@ -598,7 +605,11 @@ namespace fs1 {
 namespace host {
 
 int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
-             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap) {
+             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap,
+             fs1_result* dev_out) {
+  // dev_out: the asynchronous solve (no host synchronisation, every launch
+  // issued, result written to device memory by a kernel)
+  const bool async = dev_out != nullptr;
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   if (!out) return set_err(FS1_ERR_INVALID_ARG, "null result pointer");
   std::memset(out, 0, sizeof(*out));
@@ -641,6 +652,12 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
     return finish(set_err(FS1_ERR_INVALID_ARG, "the state output needs both state_m and state_e"));
   if ((warm && (!aligned16(o.warm_m) || !aligned16(o.warm_e))) ||
       (o.state_m && (!aligned16(o.state_m) || !aligned16(o.state_e))))
+    return finish(set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned"));
+  if (async && (tau_mode || (o.flags & FS1_FLAG_PERSISTENT)))
+    return finish(set_err(FS1_ERR_INVALID_ARG,
+                          "the asynchronous solve has no absorption variant and no persistent "
+                          "solver"));
+  if (async && !aligned16(dev_out))
     return finish(set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned"));
   int st = check_h_eps(n, h, eps);
   if (st) return finish(st);
@@ -728,6 +745,17 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
                               "bytes available",
                               probe.off, fixed_cap));
     } else {
+      if (async && probe.off > ctx->ws_size) {
+        // growing the workspace synchronises the stream: not under capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(ctx->stream, &cs));
+        if (cs != hipStreamCaptureStatusNone)
+          return finish(set_err(FS1_ERR_INVALID_ARG,
+                                "the context's workspace (%zu bytes) is smaller than this solve "
+                                "needs (%zu) and the stream is capturing: run the solve once "
+                                "before the capture",
+                                ctx->ws_size, probe.off));
+      }
       st = ensure_ws(ctx, probe.off);
       if (st) return finish(st);
       base = ctx->ws;
@@ -752,25 +780,30 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
   Ctrl* hc = ctx->hctrl;
 
   // a1: validate the marginals on the device (finite, >= 0, equal mass)
-  HIP_TRY(hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), s));
+  if (async)
+    HIP_TRY(launch_async_reset(b, o.err_history, o.itr_max, s));
+  else
+    HIP_TRY(hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), s));
   HIP_TRY(launch_setup(b, s));
   // a warm start writes the state now (and checks it with the marginals)
   if (warm) HIP_TRY(launch_warm(b, o.warm_m, o.warm_e, s));
-  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hc->bad_input & 1)
-    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must be finite and >= 0"));
-  if (hc->bad_input & 2)
-    return finish(set_err(FS1_ERR_INVALID_ARG,
-                          "warm start: mantissas must be finite and >= 0, |exponents| <= 2^20, "
-                          "and (plain domain) every scaling finite in the working precision"));
-  if (!(hc->sum_mu > 0.0) || !(hc->sum_nu > 0.0))
-    return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must have positive mass"));
-  if (std::fabs(hc->sum_mu - hc->sum_nu) > 1e-10 * hc->sum_mu)
-    return finish(set_err(FS1_ERR_INVALID_ARG, "unequal masses: sum mu = %.17g, sum nu = %.17g",
-                          hc->sum_mu, hc->sum_nu));
-  if (o.err_history)
-    HIP_TRY(hipMemsetAsync(o.err_history, 0xFF, sizeof(double) * (size_t(o.itr_max) + 1), s));
+  if (!async) {
+    HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc->bad_input & 1)
+      return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must be finite and >= 0"));
+    if (hc->bad_input & 2)
+      return finish(set_err(FS1_ERR_INVALID_ARG,
+                            "warm start: mantissas must be finite and >= 0, |exponents| <= 2^20, "
+                            "and (plain domain) every scaling finite in the working precision"));
+    if (!(hc->sum_mu > 0.0) || !(hc->sum_nu > 0.0))
+      return finish(set_err(FS1_ERR_INVALID_ARG, "marginals must have positive mass"));
+    if (std::fabs(hc->sum_mu - hc->sum_nu) > 1e-10 * hc->sum_mu)
+      return finish(set_err(FS1_ERR_INVALID_ARG, "unequal masses: sum mu = %.17g, sum nu = %.17g",
+                            hc->sum_mu, hc->sum_nu));
+    if (o.err_history)
+      HIP_TRY(hipMemsetAsync(o.err_history, 0xFF, sizeof(double) * (size_t(o.itr_max) + 1), s));
+  }
 
   const ScanConsts k = make_scan_consts(h, eps, R);
   const CarryConsts kc = make_carry_consts(h, eps, C, nchunks);
@@ -778,7 +811,7 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
 
   // diagnostic timing: events around every half-iteration kernel of a batch
   // (a fixed workspace means the caller cannot allocate: no timing events)
-  const bool prof = ctx->profiling != 0 && !fixed_ws;
+  const bool prof = ctx->profiling != 0 && !fixed_ws && !async;
   if (prof && ctx->events.size() < 4) {
     while (ctx->events.size() < 4) {
       hipEvent_t e;
@@ -832,13 +865,15 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
       HIP_TRY(launch_persistent(b, k, o.itr_max, o.check_every, tol, epoch, s));
     }
     if (prof) HIP_TRY(hipEventRecord(e1, s));
+  }
+  if ((persistent || resident) && !async) {
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hc->barrier_timeout)
       return finish(set_err(FS1_ERR_INTERNAL, "persistent solve: grid barrier timed out"));
     if (prof) {
       float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
       const int its = hc->fail ? hc->fail_iter : hc->iters_done;
       ctx->prof_ms += ms;
       ctx->prof_launches += 1;
@@ -886,6 +921,9 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
       }
     }
     if (timed && !per_launch) HIP_TRY(hipEventRecord(ctx->events[1], s));
+    // (the asynchronous solve issues every launch: those after the stop
+    // return at once)
+    if (async) continue;
     HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stopped = hc->done != 0;
@@ -910,19 +948,25 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
     }
     ++batch;
   }
-  HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hc->fail) {
-    out->iterations = hc->fail_iter;
-    out->converged = 0;
-    return finish(set_err(FS1_ERR_NONFINITE,
-                          "a scaling became non-finite at iteration %d (abnormal termination)",
-                          hc->fail_iter + 1));
-  }
+  int gbuf = 0;
   int l_final = o.itr_max;
-  if (hc->done && hc->stop_iter >= 0) l_final = hc->stop_iter;
-  // the persistent and resident kernels leave their final psi in buffer 0
-  const int gbuf = (persistent || resident) ? 0 : (l_final & 1);
+  if (async) {
+    // the final psi's buffer is known on the device only: moved to buffer 0
+    if (!persistent && !resident) HIP_TRY(launch_select_psi(b, o.itr_max, s));
+  } else {
+    HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc->fail) {
+      out->iterations = hc->fail_iter;
+      out->converged = 0;
+      return finish(set_err(FS1_ERR_NONFINITE,
+                            "a scaling became non-finite at iteration %d (abnormal termination)",
+                            hc->fail_iter + 1));
+    }
+    if (hc->done && hc->stop_iter >= 0) l_final = hc->stop_iter;
+    // the persistent and resident kernels leave their final psi in buffer 0
+    gbuf = (persistent || resident) ? 0 : (l_final & 1);
+  }
 
   if (tau_general) HIP_TRY(launch_tau_finish(b, tb, gbuf, s));
   if (large) HIP_TRY(launch_large_unpack(b, gbuf, s));
@@ -930,6 +974,10 @@ int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double
   HIP_TRY(launch_finalize(b, k, kc, gbuf, h, s));
   if (o.flags & 1) HIP_TRY(launch_potentials(b, gbuf, o.potentials_out, s));
   if (o.state_m) HIP_TRY(launch_state_out(b, gbuf, o.state_m, o.state_e, s));
+  if (async) {
+    HIP_TRY(launch_result(b, dev_out, tol, o.itr_max, s));
+    return finish(FS1_OK);
+  }
   HIP_TRY(hipMemcpyAsync(hc, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   out->w1 = hc->w1;

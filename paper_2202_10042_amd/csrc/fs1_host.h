@@ -64,8 +64,12 @@ int capture_iterations(fs1_ctx* ctx, const BatchBufs& z, const std::vector<Batch
 // demand); otherwise the solve runs on fixed_ws (device memory of fixed_cap
 // bytes) and allocates nothing, failing with FS1_ERR_INVALID_ARG if the grid
 // needs more.
+// dev_out != nullptr: the asynchronous form (fs1_solve_async): no host
+// synchronisation, every iteration's launches issued, the result written to
+// dev_out (device memory) by a kernel; *out only reports argument errors.
 int solve_on(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n, double eps, double tol,
-             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap);
+             const fs1_opts* opts_in, fs1_result* out, char* fixed_ws, size_t fixed_cap,
+             fs1_result* dev_out = nullptr);
 
 // Bump allocator over a workspace (a null base only measures).
 struct Carve {

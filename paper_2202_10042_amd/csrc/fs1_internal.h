@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fs1.h"
+
 namespace fs1 {
 
 constexpr int kWave = 64;        // CDNA wavefront width
@@ -225,6 +227,14 @@ hipError_t launch_init_state(const SolveBufs& b, const ScanConsts& k, bool warm,
 // bad input sets bit 1 of ctrl->bad_input.  Resets the control block's
 // iteration fields as the initial state does.
 hipError_t launch_warm(const SolveBufs& b, const double* m, const int* e, hipStream_t s);
+// The asynchronous solve: the control block reset and the error history set
+// to NaN by kernels (no memset node in a captured graph); the final psi moved
+// to buffer 0 when the device-side iteration count is odd; the result written
+// to device memory.
+hipError_t launch_async_reset(const SolveBufs& b, double* err_hist, int itr_max, hipStream_t s);
+hipError_t launch_select_psi(const SolveBufs& b, int itr_max, hipStream_t s);
+hipError_t launch_result(const SolveBufs& b, fs1_result* out, double tol, int itr_max,
+                         hipStream_t s);
 // Final phi and psi = vG[gbuf] (run layout) in split form into m, e (2n each).
 hipError_t launch_state_out(const SolveBufs& b, int gbuf, double* m, int* e, hipStream_t s);
 // The fused path iterates on vectors in the tile layout of fs1_tile.h, and so

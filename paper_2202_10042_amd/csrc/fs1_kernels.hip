@@ -21,6 +21,7 @@
 #include <climits>
 #include <cmath>
 
+#include "fs1.h"
 #include "fs1_device.h"
 #include "fs1_internal.h"
 #include "fs1_tau.h"
@@ -869,6 +870,101 @@ __global__ __launch_bounds__(256) void k_state_out(const T* __restrict__ v,
     m[i] = double(v[i]);
     e[i] = ex ? ex[i / R] : 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// The asynchronous solve (no host synchronisation; capturable in a graph):
+// control-block reset, error-history fill, the final psi moved to buffer 0,
+// and the result written to device memory -- all as kernels.
+// ---------------------------------------------------------------------------
+__global__ void k_ctrl_reset(Ctrl* c) {
+  int* p = reinterpret_cast<int*>(c);
+  for (int i = threadIdx.x; i < int(sizeof(Ctrl) / sizeof(int)); i += blockDim.x) p[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_fill_nan(double* p, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    p[i] = NAN;
+}
+
+// Iterations Algorithm 1 completed: the stopping iteration, else itr_max.
+__device__ __forceinline__ int completed_iterations(const Ctrl* c, int itr_max) {
+  return (c->done && c->stop_iter >= 0) ? c->stop_iter : itr_max;
+}
+
+// When the final psi is in buffer 1 (an odd number of completed iterations),
+// copy it (values, run exponents, chunk exponents) to buffer 0.
+__global__ __launch_bounds__(256) void k_select_psi(uint4* __restrict__ v0,
+                                                    const uint4* __restrict__ v1, int64_t nv,
+                                                    int* __restrict__ e0,
+                                                    const int* __restrict__ e1, int64_t ne,
+                                                    ChunkExp* __restrict__ x0,
+                                                    const ChunkExp* __restrict__ x1, int64_t nx,
+                                                    const Ctrl* ctrl, int itr_max) {
+  if ((completed_iterations(ctrl, itr_max) & 1) == 0) return;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nv; i += stride)
+    v0[i] = v1[i];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < ne; i += stride)
+    e0[i] = e1[i];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nx; i += stride)
+    x0[i] = x1[i];
+}
+
+// The solve's result, as fs1_solve would return it, into device memory.
+__global__ void k_result(const Ctrl* c, fs1_result* out, double tol, int itr_max) {
+  if (threadIdx.x != 0) return;
+  fs1_result r;
+  r.w1 = c->w1;
+  r.marginal_err = c->err_final;
+  r.mu_err = c->mu_err;
+  r.iterations = completed_iterations(c, itr_max);
+  r.converged = !(c->err_final > tol) ? 1 : 0;
+  r.absorptions = 0;
+  r.status = FS1_OK;
+  const bool invalid = (c->bad_input != 0) || !(c->sum_mu > 0.0) || !(c->sum_nu > 0.0) ||
+                       fabs(c->sum_mu - c->sum_nu) > 1e-10 * c->sum_mu;
+  if (invalid) {
+    r.status = FS1_ERR_INVALID_ARG;
+    r.iterations = 0;
+  } else if (c->fail) {
+    r.status = FS1_ERR_NONFINITE;
+    r.iterations = c->fail_iter;
+  } else if (!isfinite(c->w1) || !isfinite(c->err_final)) {
+    r.status = FS1_ERR_NONFINITE;
+  }
+  if (r.status != FS1_OK) {
+    r.converged = 0;
+    if (invalid) r.w1 = r.marginal_err = r.mu_err = NAN;
+  }
+  *out = r;
+}
+
+hipError_t launch_async_reset(const SolveBufs& b, double* err_hist, int itr_max, hipStream_t s) {
+  k_ctrl_reset<<<1, 64, 0, s>>>(b.ctrl);
+  if (err_hist) {
+    const int64_t nh = int64_t(itr_max) + 1;
+    k_fill_nan<<<unsigned(std::min<int64_t>((nh + 255) / 256, 1024)), 256, 0, s>>>(err_hist, nh);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_select_psi(const SolveBufs& b, int itr_max, hipStream_t s) {
+  const int64_t es = b.dtype == 0 ? 8 : 4;
+  const int64_t nv = b.npad * es / 16;
+  const int64_t ne = b.nchunks * kBlock;
+  const unsigned g = unsigned(std::min<int64_t>((nv + 255) / 256, 8192));
+  k_select_psi<<<g, 256, 0, s>>>(static_cast<uint4*>(b.vG[0]), static_cast<const uint4*>(b.vG[1]),
+                                 nv, b.eG[0], b.eG[1], ne, b.xG[0], b.xG[1], b.nchunks, b.ctrl,
+                                 itr_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_result(const SolveBufs& b, fs1_result* out, double tol, int itr_max,
+                         hipStream_t s) {
+  k_result<<<1, 64, 0, s>>>(b.ctrl, out, tol, itr_max);
+  return hipGetLastError();
 }
 
 // out = scale * sum(part[0..np)) in a fixed order

@@ -46,6 +46,7 @@ EXPORTS = (
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
     "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc", "fs1_ctx_create_with_allocator",
+    "fs1_solve_async",
 )
 
 # fs1_alloc_fn / fs1_free_fn
@@ -192,6 +193,8 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
+    lib.fs1_solve_async.argtypes = lib.fs1_solve.argtypes
+    lib.fs1_solve_async.restype = ctypes.c_int
     lib.fs1_solve_noalloc.argtypes = lib.fs1_solve.argtypes
     lib.fs1_solve_noalloc.restype = ctypes.c_int
     lib.fs1_stream_copy.argtypes = [vp, vp, vp, i64, ctypes.c_int]
@@ -423,6 +426,54 @@ def fs1_solve(mu, nu, eps: float, tol: float, h: Optional[float] = None, itr_max
     if st_m is not None and st == FS1_OK:
         res.state = (st_m, st_e)
     return res
+
+
+def fs1_solve_async(mu, nu, eps: float, tol: float, out=None, h: Optional[float] = None,
+                    itr_max: int = 10000, dtype: str = "f64", domain: str = "log",
+                    check_every: int = 1, solver: str = "auto", potentials_out=None,
+                    err_history_out=None, ctx: Optional[Context] = None):
+    """Enqueue Algorithm 1 on the context stream with no host synchronisation
+    (fs1_solve_async; capturable in a graph).  out: a device uint8 tensor of
+    at least RESULT_BYTES bytes that receives the fs1_result (allocated here
+    when None); potentials_out / err_history_out: optional device float64
+    tensors of 2n / itr_max + 1 entries.  Returns `out`; read_result(out)
+    gives the Result once the stream has run."""
+    import torch
+    ctx = ctx or default_context()
+    n = mu.numel()
+    if nu.numel() != n:
+        raise ValueError("mu and nu must have the same length")
+    if out is None:
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=mu.device)
+    elif out.numel() * out.element_size() < RESULT_BYTES:
+        raise ValueError("out is too small for an fs1_result")
+    o = make_opts(h, itr_max, dtype, domain, check_every, 16)
+    o.flags |= {"auto": 0, "fused": FS1_FLAG_NO_RESIDENT, "general": FS1_FLAG_GENERAL}[solver]
+    if potentials_out is not None:
+        if potentials_out.numel() != 2 * n or potentials_out.dtype != torch.float64:
+            raise ValueError("potentials_out: 2n float64 entries")
+        o.flags |= FS1_FLAG_POTENTIALS
+        o.potentials_out = _dev(potentials_out, "potentials_out").value
+    if err_history_out is not None:
+        if err_history_out.numel() < itr_max + 1 or err_history_out.dtype != torch.float64:
+            raise ValueError("err_history_out: itr_max + 1 float64 entries")
+        o.err_history = _dev(err_history_out, "err_history_out").value
+    _check(load().fs1_solve_async(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), n, float(eps),
+                                  float(tol), ctypes.byref(o),
+                                  ctypes.cast(ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.POINTER(CResult))))
+    return out
+
+
+RESULT_BYTES = ctypes.sizeof(CResult)
+
+
+def read_result(out) -> Result:
+    """The Result an fs1_solve_async call wrote to the device tensor `out`
+    (copies it to the host: synchronises with the tensor's stream)."""
+    raw = bytes(out[:RESULT_BYTES].cpu().numpy().tobytes())
+    r = CResult.from_buffer_copy(raw)
+    return Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
 
 
 def fs1_kv_apply_2d(x, n1: int, n2: int, h1: float, h2: float, eps: float, out=None,
