@@ -202,6 +202,46 @@ def batch_hists(spec: BatchSpec):
     return mu, nu, offs
 
 
+def mixture_pairs_device(sizes, ks, seeds, torch, device="cuda"):
+    """Many (mu, nu) pairs at once on a GPU, by the recipe of mixture_pair:
+    pair i has sizes[i] cells, ks[i] components, mu from seeds[i] and nu from
+    seeds[i] + 1 (the same mixture parameters as mixture_pair draws); the
+    densities are evaluated in binary64 on the device (so the values equal
+    mixture_pair's to rounding).  Returns (mu, nu, offsets): packed device
+    tensors and the host offsets of the pairs."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    B = sizes.size
+    kmax = int(max(ks)) if B else 1
+    offs = np.zeros(B + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    total = int(offs[-1])
+    out = []
+    for side in (0, 1):
+        prm = np.zeros((B, kmax, 3))  # means, sds, weights (weight 0 pads)
+        prm[:, :, 1] = 1.0
+        for i in range(B):
+            m, sd, w = _mixture_params(np.random.default_rng(int(seeds[i]) + side), int(ks[i]))
+            prm[i, :len(m), 0] = m
+            prm[i, :len(m), 1] = sd
+            prm[i, :len(m), 2] = w
+        p = torch.tensor(prm, dtype=torch.float64, device=device)
+        szt = torch.tensor(sizes, device=device)
+        owner = torch.repeat_interleave(torch.arange(B, device=device), szt)
+        start = torch.tensor(offs[:-1], device=device)
+        idx = torch.arange(total, device=device, dtype=torch.int64) - start[owner]
+        x = (idx.double() + 0.5) / szt[owner].double()
+        dens = torch.zeros(total, dtype=torch.float64, device=device)
+        for k in range(kmax):
+            mk, sk, wk = p[owner, k, 0], p[owner, k, 1], p[owner, k, 2]
+            dens += wk * torch.exp(-0.5 * ((x - mk) / sk) ** 2) / (sk * math.sqrt(2.0 * math.pi))
+        dens += FLOOR
+        # one reduction per pair (a scatter-add into B sums would contend on
+        # B addresses)
+        sums = torch.stack([dens[int(offs[i]):int(offs[i + 1])].sum() for i in range(B)])
+        out.append(dens / sums[owner])
+    return out[0], out[1], offs
+
+
 def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate on [0, duration)."""
     rng = np.random.default_rng(seed)

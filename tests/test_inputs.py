@@ -1,5 +1,6 @@
 """The seeded workload generators: determinism, normalisation, recipe."""
 import numpy as np
+import pytest
 
 from paper_2202_10042_amd import inputs
 
@@ -64,3 +65,14 @@ def test_poisson_arrivals():
     t = inputs.poisson_arrivals(20000.0, 1.0, 3)
     assert np.all(np.diff(t) > 0) and t[-1] < 1.0
     assert 19000 < t.size < 21000
+
+
+def test_device_mixture_pairs_follow_the_host_recipe():
+    torch = pytest.importorskip("torch")
+    sizes, ks, seeds = [128, 1000, 7, 4099], [3, 5, 4, 3], [10, 20, 30, 40]
+    mu, nu, offs = inputs.mixture_pairs_device(sizes, ks, seeds, torch, device="cpu")
+    assert list(offs) == [0, 128, 1128, 1135, 5234]
+    for i, (n, k, s) in enumerate(zip(sizes, ks, seeds)):
+        a, b = inputs.mixture_pair(n, k, s)
+        np.testing.assert_allclose(mu[offs[i]:offs[i + 1]].numpy(), a, rtol=1e-13)
+        np.testing.assert_allclose(nu[offs[i]:offs[i + 1]].numpy(), b, rtol=1e-13)
