@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfs1.so")
 SOURCES = ["fs1_kernels.hip", "fs1_fused.hip", "fs1_persist.hip", "fs1_resident.hip",
-           "fs1_batch.hip", "fs1_2d.hip", "fs1_tau.hip", "fs1_large.hip", "fs1_stream.hip", "fs1_noalloc.hip", "fs1_api.cpp", "fs1_server.cpp"]
+           "fs1_batch.hip", "fs1_2d.hip", "fs1_tau.hip", "fs1_large.hip", "fs1_stream.hip", "fs1_noalloc.hip", "fs1_api.cpp", "fs1_server.cpp", "fs1_tune.cpp"]
 ARCH = os.environ.get("FS1_OFFLOAD_ARCH", "gfx950")
 
 

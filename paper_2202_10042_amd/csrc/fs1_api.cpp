@@ -24,6 +24,7 @@
 #include "fs1_host.h"
 #include "fs1_internal.h"
 #include "fs1_tau.h"
+#include "fs1_tune.h"
 
 using namespace fs1;
 
@@ -200,9 +201,15 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
 // Ragged batch in the log domain: every instance keeps its own lambda, run
 // length, stopping test and iteration count; all of them advance in the same
 // launches (fs1_batch.hip).
+int batched_entry(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
+                  const int64_t* offsets, int32_t B, const double* eps, const double* tol,
+                  const fs1_opts* opts, fs1_result* out, const BatchCfg* force);
+
+// force (optional): one configuration for every instance (the tuner's
+// measurements), else batch_config() per instance.
 int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t* offsets,
                 int32_t B, const double* eps, const double* tol, const fs1_opts& o,
-                fs1_result* out) {
+                fs1_result* out, const BatchCfg* force = nullptr) {
   const int dt = o.dtype;
   const size_t es = dt == FS1_F64 ? 8 : 4;
   hipStream_t s = ctx->stream;
@@ -214,12 +221,9 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   std::vector<int> rlen(B), rthreads(B, 0);
   for (int32_t i = 0; i < B; ++i) {
     const int64_t n = offsets[i + 1] - offsets[i];
-    rlen[i] = pick_run_length(dt, true, (1.0 / double(n)) / eps[i]);
-    const int rr = resident_run_length(n, rlen[i]);
-    if (rr > 0) {
-      rlen[i] = rr;
-      rthreads[i] = resident_threads(n, rr);
-    }
+    const BatchCfg cfg = force ? *force : batch_config(dt, n, (1.0 / double(n)) / eps[i]);
+    rlen[i] = cfg.R;
+    rthreads[i] = cfg.nt;
   }
   std::vector<int> rs(rlen);
   std::sort(rs.begin(), rs.end(), [](int a, int b) { return a > b; });
@@ -1027,6 +1031,42 @@ int fs1_solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, i
 int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
                       const int64_t* offsets, int32_t B, const double* eps, const double* tol,
                       const fs1_opts* opts, fs1_result* out) {
+  return batched_entry(ctx, mu_packed, nu_packed, offsets, B, eps, tol, opts, out, nullptr);
+}
+
+int fs1_solve_batched_config(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
+                             const int64_t* offsets, int32_t B, const double* eps,
+                             const double* tol, const fs1_opts* opts, int32_t run_length,
+                             int32_t threads, fs1_result* out) {
+  if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  const int dt = opts ? opts->dtype : FS1_F64;
+  if (opts && opts->domain != FS1_LOG)
+    return set_err(FS1_ERR_INVALID_ARG, "a forced configuration needs the log domain");
+  if (threads == 0 ? !batch_shared_r_ok(dt, run_length)
+                   : !batch_resident_ok(dt, run_length, threads))
+    return set_err(FS1_ERR_INVALID_ARG, "no batched kernels for run length %d on %d threads",
+                   run_length, threads);
+  for (int32_t i = 0; i < B && offsets; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (eps && eps[i] > 0.0 &&
+        run_length > pick_run_length(dt, true, (1.0 / double(n)) / eps[i]))
+      return set_err(FS1_ERR_INVALID_ARG, "instance %d: run length %d exceeds what h/eps allows",
+                     i, run_length);
+    if (threads > 0 && n > int64_t(threads) * run_length)
+      return set_err(FS1_ERR_INVALID_ARG, "instance %d does not fit %d threads x %d", i, threads,
+                     run_length);
+  }
+  const BatchCfg cfg{run_length, threads};
+  return batched_entry(ctx, mu_packed, nu_packed, offsets, B, eps, tol, opts, out, &cfg);
+}
+
+}  // extern "C"
+
+namespace {
+
+int batched_entry(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
+                  const int64_t* offsets, int32_t B, const double* eps, const double* tol,
+                  const fs1_opts* opts, fs1_result* out, const BatchCfg* force) {
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   if (B < 0 || (B > 0 && (!offsets || !eps || !tol || !out || !mu_packed || !nu_packed)))
     return set_err(FS1_ERR_INVALID_ARG, "bad batch arguments");
@@ -1081,7 +1121,7 @@ int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_pa
     }
     return FS1_OK;
   }
-  return batch_solve(ctx, mu_packed, nu_packed, offsets, B, eps, tol, o, out);
+  return batch_solve(ctx, mu_packed, nu_packed, offsets, B, eps, tol, o, out, force);
 }
 
-}  // extern "C"
+}  // namespace

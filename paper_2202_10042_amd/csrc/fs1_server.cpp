@@ -35,6 +35,7 @@
 #include "fs1_batch.h"
 #include "fs1_host.h"
 #include "fs1_internal.h"
+#include "fs1_tune.h"
 
 using namespace fs1;
 using namespace fs1::host;
@@ -183,7 +184,7 @@ void carve(fs1_server* v, Carve& w) {
 }
 
 int64_t request_slots(int dt, int64_t n, double eps, int* R_out, int* nch_out) {
-  const int R = pick_run_length(dt, true, (1.0 / double(n)) / eps);
+  const int R = shared_run_length(dt, n, (1.0 / double(n)) / eps);
   const int64_t C = int64_t(kBlock) * R;
   const int64_t nch = (n + C - 1) / C;
   *R_out = R;

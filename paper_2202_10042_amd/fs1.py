@@ -46,7 +46,7 @@ EXPORTS = (
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
     "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc", "fs1_ctx_create_with_allocator",
-    "fs1_solve_async",
+    "fs1_solve_async", "fs1_solve_batched_config",
 )
 
 # fs1_alloc_fn / fs1_free_fn
@@ -193,6 +193,11 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
+    lib.fs1_solve_batched_config.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32,
+                                             ctypes.POINTER(d), ctypes.POINTER(d),
+                                             ctypes.POINTER(Opts), i32, i32,
+                                             ctypes.POINTER(CResult)]
+    lib.fs1_solve_batched_config.restype = ctypes.c_int
     lib.fs1_solve_async.argtypes = lib.fs1_solve.argtypes
     lib.fs1_solve_async.restype = ctypes.c_int
     lib.fs1_solve_noalloc.argtypes = lib.fs1_solve.argtypes
@@ -533,7 +538,8 @@ def fs1_solve_2d(mu, nu, n1: int, n2: int, h1: float, h2: float, eps: float, tol
 def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequence[float],
                       tol: Sequence[float], itr_max: int = 10000, dtype: str = "f64",
                       domain: str = "log", check_every: int = 1, sync_every: int = 16,
-                      graph: bool = True, ctx: Optional[Context] = None) -> list:
+                      graph: bool = True, ctx: Optional[Context] = None,
+                      config: Optional[tuple] = None) -> list:
     """Ragged batch: instance b is [offsets[b], offsets[b+1]) of the packed
     float64 device tensors; eps and tol per instance.  Returns one Result per
     instance (per-instance failures in Result.status).  With domain="log" all
@@ -552,8 +558,14 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
     if not graph:
         o.flags |= FS1_FLAG_NO_GRAPH
     res = (CResult * max(B, 1))()
-    _check(load().fs1_solve_batched(ctx.handle, _dev(mu_packed, "mu"), _dev(nu_packed, "nu"),
-                                    offs, B, e, t, ctypes.byref(o), res))
+    if config is None:
+        _check(load().fs1_solve_batched(ctx.handle, _dev(mu_packed, "mu"), _dev(nu_packed, "nu"),
+                                        offs, B, e, t, ctypes.byref(o), res))
+    else:  # (run length, threads): fs1_solve_batched_config
+        _check(load().fs1_solve_batched_config(ctx.handle, _dev(mu_packed, "mu"),
+                                               _dev(nu_packed, "nu"), offs, B, e, t,
+                                               ctypes.byref(o), int(config[0]), int(config[1]),
+                                               res))
     return [Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
             for r in res[:B]]
 
