@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true",
                     help="only the request stream (60 s at 20k requests/s, then a sweep of "
                          "sustainable rates)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 4096-instance uneven batch (profiling runs)")
     ap.add_argument("--no-paper-workloads", action="store_true",
                     help="skip the Sec. 5.1 / 5.2 / 5.3 workloads at the paper's sizes")
     args = ap.parse_args()
@@ -284,6 +286,11 @@ def main():
     if args.serve_only:
         print(json.dumps({"serving": serving_study(fs1, ctx, inputs, np, torch,
                                                    args.serve_seconds)}), flush=True)
+        return
+
+    if args.batched_only:
+        print(json.dumps({"batched": batched_study(fs1, ctx, inputs, np, torch, args.batch)}),
+              flush=True)
         return
 
     n = N_C4
