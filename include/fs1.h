@@ -306,19 +306,20 @@ int fs1_solve_batched(fs1_ctx *ctx, const double *mu_packed, const double *nu_pa
                       const int64_t *offsets, int32_t B, const double *eps,
                       const double *tol, const fs1_opts *opts, fs1_result *out);
 
-/* fs1_solve_batched (FS1_LOG only) with one configuration forced on every
- * instance: run length `run_length` and, with threads = 256 or 1024, the
- * resident form (one workgroup of `threads` threads per instance for all its
- * iterations; every instance must then hold at most threads x run_length
- * entries), or threads = 0, the shared chunk launches.  For the project's
- * tuner, which times the candidates of each instance class with this call
- * and ships the fastest as the table fs1_solve_batched and the server use.
- * FS1_ERR_INVALID_ARG if the batched kernels are not built for the pair, an
- * instance does not fit, or h/eps does not allow the run length. */
+/* fs1_solve_batched (FS1_LOG only) with the configuration of every instance
+ * forced: run_length[b] and, with threads[b] = 256 or 1024, the resident form
+ * (one workgroup of threads[b] threads for all of instance b's iterations; the
+ * instance must then hold at most threads[b] x run_length[b] entries), or
+ * threads[b] = 0 (or threads NULL), the shared chunk launches.  run_length and
+ * threads are host arrays of B entries.  For the project's tuner, which times
+ * candidate configurations with this call and ships the fastest as the table
+ * that fs1_solve_batched and the server use.  FS1_ERR_INVALID_ARG if the
+ * batched kernels are not built for a pair, an instance does not fit, or h/eps
+ * does not allow the run length. */
 int fs1_solve_batched_config(fs1_ctx *ctx, const double *mu_packed, const double *nu_packed,
                              const int64_t *offsets, int32_t B, const double *eps,
-                             const double *tol, const fs1_opts *opts, int32_t run_length,
-                             int32_t threads, fs1_result *out);
+                             const double *tol, const fs1_opts *opts, const int32_t *run_length,
+                             const int32_t *threads, fs1_result *out);
 
 /* ------------------------------------------------------------------------ */
 /* Two dimensions (Sec. 4, Algorithm 2).  A histogram on an n1 x n2 grid is   */

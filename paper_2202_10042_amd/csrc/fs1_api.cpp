@@ -205,8 +205,8 @@ int batched_entry(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed
                   const int64_t* offsets, int32_t B, const double* eps, const double* tol,
                   const fs1_opts* opts, fs1_result* out, const BatchCfg* force);
 
-// force (optional): one configuration for every instance (the tuner's
-// measurements), else batch_config() per instance.
+// force (optional): the configuration of every instance (B entries; the
+// tuner's measurements), else batch_config() per instance.
 int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t* offsets,
                 int32_t B, const double* eps, const double* tol, const fs1_opts& o,
                 fs1_result* out, const BatchCfg* force = nullptr) {
@@ -221,7 +221,7 @@ int batch_solve(fs1_ctx* ctx, const double* mu, const double* nu, const int64_t*
   std::vector<int> rlen(B), rthreads(B, 0);
   for (int32_t i = 0; i < B; ++i) {
     const int64_t n = offsets[i + 1] - offsets[i];
-    const BatchCfg cfg = force ? *force : batch_config(dt, n, (1.0 / double(n)) / eps[i]);
+    const BatchCfg cfg = force ? force[i] : batch_config(dt, n, (1.0 / double(n)) / eps[i]);
     rlen[i] = cfg.R;
     rthreads[i] = cfg.nt;
   }
@@ -1036,28 +1036,30 @@ int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_pa
 
 int fs1_solve_batched_config(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
                              const int64_t* offsets, int32_t B, const double* eps,
-                             const double* tol, const fs1_opts* opts, int32_t run_length,
-                             int32_t threads, fs1_result* out) {
+                             const double* tol, const fs1_opts* opts, const int32_t* run_length,
+                             const int32_t* threads, fs1_result* out) {
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   const int dt = opts ? opts->dtype : FS1_F64;
   if (opts && opts->domain != FS1_LOG)
     return set_err(FS1_ERR_INVALID_ARG, "a forced configuration needs the log domain");
-  if (threads == 0 ? !batch_shared_r_ok(dt, run_length)
-                   : !batch_resident_ok(dt, run_length, threads))
-    return set_err(FS1_ERR_INVALID_ARG, "no batched kernels for run length %d on %d threads",
-                   run_length, threads);
-  for (int32_t i = 0; i < B && offsets; ++i) {
+  if (B > 0 && (!run_length || !offsets))
+    return set_err(FS1_ERR_INVALID_ARG, "bad batch arguments");
+  std::vector<BatchCfg> cfg(size_t(std::max(B, 0)));
+  for (int32_t i = 0; i < B; ++i) {
+    const int r = run_length[i];
+    const int nt = threads ? threads[i] : 0;
+    if (nt == 0 ? !batch_shared_r_ok(dt, r) : !batch_resident_ok(dt, r, nt))
+      return set_err(FS1_ERR_INVALID_ARG,
+                     "instance %d: no batched kernels for run length %d on %d threads", i, r, nt);
     const int64_t n = offsets[i + 1] - offsets[i];
-    if (eps && eps[i] > 0.0 &&
-        run_length > pick_run_length(dt, true, (1.0 / double(n)) / eps[i]))
+    if (eps && eps[i] > 0.0 && n > 0 && r > pick_run_length(dt, true, (1.0 / double(n)) / eps[i]))
       return set_err(FS1_ERR_INVALID_ARG, "instance %d: run length %d exceeds what h/eps allows",
-                     i, run_length);
-    if (threads > 0 && n > int64_t(threads) * run_length)
-      return set_err(FS1_ERR_INVALID_ARG, "instance %d does not fit %d threads x %d", i, threads,
-                     run_length);
+                     i, r);
+    if (nt > 0 && n > int64_t(nt) * r)
+      return set_err(FS1_ERR_INVALID_ARG, "instance %d does not fit %d threads x %d", i, nt, r);
+    cfg[size_t(i)] = BatchCfg{r, nt};
   }
-  const BatchCfg cfg{run_length, threads};
-  return batched_entry(ctx, mu_packed, nu_packed, offsets, B, eps, tol, opts, out, &cfg);
+  return batched_entry(ctx, mu_packed, nu_packed, offsets, B, eps, tol, opts, out, cfg.data());
 }
 
 }  // extern "C"

@@ -33,12 +33,7 @@ int clamp_r(int dtype, int R, int rmax) {
 
 }  // namespace
 
-int shared_run_length(int dtype, int64_t n, double c) {
-  const int rmax = pick_run_length(dtype, true, c);
-  const TuneRow* row = tune_row(dtype, n);
-  if (!row) return rmax;
-  return clamp_r(dtype, row->R_shared, rmax);
-}
+int shared_run_length(int dtype, int64_t n, double c) { return batch_config(dtype, n, c).R; }
 
 BatchCfg batch_config(int dtype, int64_t n, double c) {
   const int rmax = pick_run_length(dtype, true, c);

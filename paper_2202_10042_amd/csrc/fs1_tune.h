@@ -26,7 +26,11 @@ bool batch_resident_ok(int dtype, int R, int nt);
 
 // The batched solve's configuration of an instance of n entries and c = h/eps.
 BatchCfg batch_config(int dtype, int64_t n, double c);
-// The server runs every request in the shared launches: its run length.
+// The server runs every request in the shared launches, with the run length
+// the batched solve gives the instance.  A resident instance of one chunk
+// (n <= 256 R, on 256 threads) does the same arithmetic as a one-chunk shared
+// launch, so such a request's result equals the batched solve's bit for bit;
+// the measured table keeps every resident class within one chunk.
 int shared_run_length(int dtype, int64_t n, double c);
 
 }  // namespace fs1

@@ -195,8 +195,8 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.restype = ctypes.c_int
     lib.fs1_solve_batched_config.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32,
                                              ctypes.POINTER(d), ctypes.POINTER(d),
-                                             ctypes.POINTER(Opts), i32, i32,
-                                             ctypes.POINTER(CResult)]
+                                             ctypes.POINTER(Opts), ctypes.POINTER(i32),
+                                             ctypes.POINTER(i32), ctypes.POINTER(CResult)]
     lib.fs1_solve_batched_config.restype = ctypes.c_int
     lib.fs1_solve_async.argtypes = lib.fs1_solve.argtypes
     lib.fs1_solve_async.restype = ctypes.c_int
@@ -544,7 +544,10 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
     float64 device tensors; eps and tol per instance.  Returns one Result per
     instance (per-instance failures in Result.status).  With domain="log" all
     instances advance in the same launches, `sync_every` iterations per
-    replayed HIP graph (graph=False launches the kernels directly)."""
+    replayed HIP graph (graph=False launches the kernels directly).
+    config: (run length, threads) forced on every instance, or a list of such
+    pairs, one per instance (threads 0: shared chunk launches; 256 or 1024:
+    resident), through fs1_solve_batched_config."""
     ctx = ctx or default_context()
     B = len(offsets) - 1
     if len(eps) != B or len(tol) != B:
@@ -561,11 +564,16 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
     if config is None:
         _check(load().fs1_solve_batched(ctx.handle, _dev(mu_packed, "mu"), _dev(nu_packed, "nu"),
                                         offs, B, e, t, ctypes.byref(o), res))
-    else:  # (run length, threads): fs1_solve_batched_config
+    else:  # fs1_solve_batched_config
+        if len(config) == 2 and not isinstance(config[0], (tuple, list)):
+            config = [config] * B
+        if len(config) != B:
+            raise ValueError("config: one (run length, threads) pair, or one per instance")
+        rl = (ctypes.c_int32 * max(B, 1))(*[int(c[0]) for c in config])
+        th = (ctypes.c_int32 * max(B, 1))(*[int(c[1]) for c in config])
         _check(load().fs1_solve_batched_config(ctx.handle, _dev(mu_packed, "mu"),
                                                _dev(nu_packed, "nu"), offs, B, e, t,
-                                               ctypes.byref(o), int(config[0]), int(config[1]),
-                                               res))
+                                               ctypes.byref(o), rl, th, res))
     return [Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), r.status)
             for r in res[:B]]
 

@@ -261,3 +261,36 @@ def test_batched_c3_sample_fp32():
         assert r32[i].w1 == pytest.approx(ref.w1, rel=1e-5), i
         if r64[i].iterations == r32[i].iterations:
             assert r64[i].w1 == pytest.approx(ref.w1, rel=1e-10), i
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batched_forced_configurations(dtype):
+    # fs1_solve_batched_config: per-instance configurations forced by the
+    # caller.  The tuner's mirror of the library's choice reproduces the
+    # default call bit for bit; other configurations stay within the stated
+    # tolerance of the oracle; invalid ones are refused before any launch.
+    from paper_2202_10042_amd import tune
+    fs1 = _fs1()
+    spec = inputs.batch_spec(24, 128, 20000, [1e-2, 3e-3, 1e-3], seed=11)
+    mu, nu, offs = inputs.batch_hists(spec)
+    sizes = np.diff(offs).astype(int)
+    tol = [0.0] * 24
+    args = (dev(mu), dev(nu), offs, spec.eps, tol)
+    _say(f"batched forced configurations {dtype}")
+    base = fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype)
+    rows = tune.read_table()
+    mirror = [tune.instance_config(rows, dtype, int(n), float(e)) for n, e in zip(sizes, spec.eps)]
+    forced = fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=mirror)
+    for a, b in zip(base, forced):
+        assert _same(a, b), (a, b)
+    shared8 = fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=(8, 0))
+    for i in (0, 7, 23):
+        m, v = mu[offs[i]:offs[i + 1]], nu[offs[i]:offs[i + 1]]
+        ref = oracle.fs1_log(m, v, 1.0 / len(m), float(spec.eps[i]), tol=0.0, itr_max=60)
+        r = shared8[i]
+        assert r.status == 0 and r.iterations == ref.iterations
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-10 if dtype == "f64" else 1e-5)
+    with pytest.raises(RuntimeError):
+        fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=(3, 0))
+    with pytest.raises(RuntimeError):  # the largest instance does not fit one workgroup
+        fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=(8, 256))
