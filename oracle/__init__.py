@@ -101,6 +101,14 @@ def _load():
         "or_cost2_fs1": (d, [i64, i64, p, p, d, d, d]),
         "or_sinkhorn2_dense": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
         "or_fs1_2d": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
+        "or_kv2_log_dense": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
+        "or_kv2_fs1_log": (ctypes.c_int, [i64, i64, p, d, d, d, p]),
+        "or_marginal_err2_log_dense": (d, [i64, i64, p, p, p, d, d, d]),
+        "or_marginal_err2_fs1_log": (d, [i64, i64, p, p, p, d, d, d]),
+        "or_cost2_log_dense": (d, [i64, i64, p, p, d, d, d]),
+        "or_cost2_fs1_log": (d, [i64, i64, p, p, d, d, d]),
+        "or_sinkhorn2_log_dense": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
+        "or_fs1_2d_log": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -411,6 +419,54 @@ def sinkhorn2_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> Oracl
 
 def fs1_2d(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> OracleResult:
     return _solve2("or_fs1_2d", mu, nu, n1, n2, h1, h2, eps, tol, itr_max)
+
+
+def kv2_log_dense(lx, n1: int, n2: int, h1: float, h2: float, eps: float) -> np.ndarray:
+    """ln K e^lx on the 2-D grid, every term of the sum (max-shifted)."""
+    lx = _grid2(lx, n1, n2)
+    y = np.empty_like(lx)
+    _load().or_kv2_log_dense(n1, n2, _ptr(lx), h1, h2, eps, _ptr(y))
+    return y
+
+
+def kv2_fs1_log(lx, n1: int, n2: int, h1: float, h2: float, eps: float) -> np.ndarray:
+    """ln K e^lx by the 1-D log recursions along the columns, then the rows."""
+    lx = _grid2(lx, n1, n2)
+    y = np.empty_like(lx)
+    _load().or_kv2_fs1_log(n1, n2, _ptr(lx), h1, h2, eps, _ptr(y))
+    return y
+
+
+def marginal_err2_log_dense(F, G, nu, n1, n2, h1, h2, eps) -> float:
+    F, G, nu = _grid2(F, n1, n2), _grid2(G, n1, n2), _grid2(nu, n1, n2)
+    return float(_load().or_marginal_err2_log_dense(n1, n2, _ptr(F), _ptr(G), _ptr(nu),
+                                                    h1, h2, eps))
+
+
+def marginal_err2_fs1_log(F, G, nu, n1, n2, h1, h2, eps) -> float:
+    F, G, nu = _grid2(F, n1, n2), _grid2(G, n1, n2), _grid2(nu, n1, n2)
+    return float(_load().or_marginal_err2_fs1_log(n1, n2, _ptr(F), _ptr(G), _ptr(nu),
+                                                  h1, h2, eps))
+
+
+def cost2_log_dense(F, G, n1, n2, h1, h2, eps) -> float:
+    F, G = _grid2(F, n1, n2), _grid2(G, n1, n2)
+    return float(_load().or_cost2_log_dense(n1, n2, _ptr(F), _ptr(G), h1, h2, eps))
+
+
+def cost2_fs1_log(F, G, n1, n2, h1, h2, eps) -> float:
+    F, G = _grid2(F, n1, n2), _grid2(G, n1, n2)
+    return float(_load().or_cost2_fs1_log(n1, n2, _ptr(F), _ptr(G), h1, h2, eps))
+
+
+def sinkhorn2_log_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """Algorithm 2 on logarithms with dense products; .a = F = ln phi, .b = G = ln psi."""
+    return _solve2("or_sinkhorn2_log_dense", mu, nu, n1, n2, h1, h2, eps, tol, itr_max)
+
+
+def fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """Algorithm 2 on logarithms by the recursions; .a = F = ln phi, .b = G = ln psi."""
+    return _solve2("or_fs1_2d_log", mu, nu, n1, n2, h1, h2, eps, tol, itr_max)
 
 
 def plan2(phi, psi, n1, n2, h1, h2, eps) -> np.ndarray:

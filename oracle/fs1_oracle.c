@@ -872,6 +872,243 @@ int or_fs1_2d(int64_t n1, int64_t n2, const double *mu, const double *nu, double
     return solve2(0, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, phi, psi, res);
 }
 
+/* ========================================================================= */
+/* Two dimensions on logarithms: Algorithm 2 written on F = ln phi and        */
+/* G = ln psi, the limit of the absorption stabilisation (Sec. 2 and Sec. 3   */
+/* remarks) in which the whole of phi and psi is absorbed at every step, as   */
+/* in one dimension.  Same grid, kernel and layout as above.                  */
+/* ========================================================================= */
+
+/* ly = ln K e^lx with K dense: every one of the (n1 n2)^2 terms, max-shifted. */
+int or_kv2_log_dense(int64_t n1, int64_t n2, const double *lx, double h1, double h2,
+                     double eps, double *ly) {
+    if (n1 < 1 || n2 < 1 || !(h1 > 0) || !(h2 > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    const int64_t n = n1 * n2;
+    const double c1 = h1 / eps, c2 = h2 / eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = r % n1, j = r / n1;
+        double m = -INFINITY;
+        for (int64_t l = 0; l < n2; ++l)
+            for (int64_t k = 0; k < n1; ++k) {
+                const double d = (double)(k > i ? k - i : i - k) * c1 +
+                                 (double)(l > j ? l - j : j - l) * c2;
+                const double t = lx[k + n1 * l] - d;
+                if (t > m) m = t;
+            }
+        if (m == -INFINITY) { ly[r] = -INFINITY; continue; }
+        nsum acc = {0.0, 0.0};
+        for (int64_t l = 0; l < n2; ++l)
+            for (int64_t k = 0; k < n1; ++k) {
+                const double d = (double)(k > i ? k - i : i - k) * c1 +
+                                 (double)(l > j ? l - j : j - l) * c2;
+                nadd(&acc, exp(lx[k + n1 * l] - d - m));
+            }
+        ly[r] = m + log(nval(&acc));
+    }
+    return OR_OK;
+}
+
+/* The same product by Algorithm 2's structure: the 1-D log recursions
+ * (or_kv_fs1_log, spacing h1) along every column, then (spacing h2) along
+ * every row. */
+int or_kv2_fs1_log(int64_t n1, int64_t n2, const double *lx, double h1, double h2,
+                   double eps, double *ly) {
+    if (n1 < 1 || n2 < 1 || !(h1 > 0) || !(h2 > 0) || !(eps > 0)) return OR_ERR_INVALID_ARG;
+    const int64_t n = n1 * n2;
+    double *t = (double *)malloc((size_t)n * sizeof(double));
+    double *row = (double *)malloc((size_t)n2 * sizeof(double));
+    double *out = (double *)malloc((size_t)n2 * sizeof(double));
+    if (!t || !row || !out) { free(t); free(row); free(out); return OR_ERR_NO_MEMORY; }
+    for (int64_t j = 0; j < n2; ++j) or_kv_fs1_log(n1, lx + n1 * j, h1, eps, t + n1 * j);
+    for (int64_t i = 0; i < n1; ++i) {
+        for (int64_t j = 0; j < n2; ++j) row[j] = t[i + n1 * j];
+        or_kv_fs1_log(n2, row, h2, eps, out);
+        for (int64_t j = 0; j < n2; ++j) ly[i + n1 * j] = out[j];
+    }
+    free(t); free(row); free(out);
+    return OR_OK;
+}
+
+/* err = sum | exp(G + ln K^T e^F) - nu |, with the product dense (dense = 1)
+ * or by the recursions. */
+static double marginal_err2_log(int dense, int64_t n1, int64_t n2, const double *F,
+                                const double *G, const double *nu, double h1, double h2,
+                                double eps) {
+    const int64_t n = n1 * n2;
+    double *lk = (double *)malloc((size_t)n * sizeof(double));
+    if (!lk) return NAN;
+    if (dense) or_kv2_log_dense(n1, n2, F, h1, h2, eps, lk);
+    else or_kv2_fs1_log(n1, n2, F, h1, h2, eps, lk);
+    nsum err = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) {
+        const double v = (G[r] == -INFINITY || lk[r] == -INFINITY) ? 0.0 : exp(G[r] + lk[r]);
+        nadd(&err, fabs(v - nu[r]));
+    }
+    free(lk);
+    return nval(&err);
+}
+
+double or_marginal_err2_log_dense(int64_t n1, int64_t n2, const double *F, const double *G,
+                                  const double *nu, double h1, double h2, double eps) {
+    return marginal_err2_log(1, n1, n2, F, G, nu, h1, h2, eps);
+}
+
+double or_marginal_err2_fs1_log(int64_t n1, int64_t n2, const double *F, const double *G,
+                                const double *nu, double h1, double h2, double eps) {
+    return marginal_err2_log(0, n1, n2, F, G, nu, h1, h2, eps);
+}
+
+/* Algorithm 2's returned value on logarithms, literally:
+ *   W = sum exp(F_(i,j) + G_(k,l) - (|i-k| h1 + |j-l| h2)/eps) (|i-k| h1 + |j-l| h2). */
+double or_cost2_log_dense(int64_t n1, int64_t n2, const double *F, const double *G,
+                          double h1, double h2, double eps) {
+    const int64_t n = n1 * n2;
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!row) return NAN;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = r % n1, j = r / n1;
+        nsum acc = {0.0, 0.0};
+        if (F[r] != -INFINITY) {
+            for (int64_t l = 0; l < n2; ++l)
+                for (int64_t k = 0; k < n1; ++k) {
+                    const double g = G[k + n1 * l];
+                    if (g == -INFINITY) continue;
+                    const double d = (double)(k > i ? k - i : i - k) * h1 +
+                                     (double)(l > j ? l - j : j - l) * h2;
+                    nadd(&acc, exp(F[r] + g - d / eps) * d);
+                }
+        }
+        row[r] = nval(&acc);
+    }
+    nsum w = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) nadd(&w, row[r]);
+    free(row);
+    return nval(&w);
+}
+
+/* out_i = ln sum_k e^{X_k} lambda^{|i-k|} |i-k| along one line, by the
+ * logarithmic form of the cost recursions of or_cost_fs1_log:
+ *   lnL_0 = -inf, lnL_{i+1} = lse(lnL_i, A_i) - c;
+ *   lnU_{n-1} = -inf, lnU_{i-1} = lse(lnU_i, B_i, X_i) - c;
+ *   out_i = lse(lnL_i, lnU_i), with A, B the forward and strict backward
+ * log recursions of X. */
+static int cost_kernel_fs1_log(int64_t n, const double *X, double c, double *out) {
+    double *B = (double *)malloc((size_t)n * sizeof(double));
+    double *lU = (double *)malloc((size_t)n * sizeof(double));
+    if (!B || !lU) { free(B); free(lU); return OR_ERR_NO_MEMORY; }
+    B[n - 1] = -INFINITY;
+    for (int64_t k = n - 2; k >= 0; --k) {
+        const double t = lse2(B[k + 1], X[k + 1]);
+        B[k] = (t == -INFINITY) ? -INFINITY : t - c;
+    }
+    lU[n - 1] = -INFINITY;
+    for (int64_t i = n - 1; i >= 1; --i) {
+        const double t = lse2(lse2(lU[i], B[i]), X[i]);
+        lU[i - 1] = (t == -INFINITY) ? -INFINITY : t - c;
+    }
+    double A = -INFINITY, lL = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        A = (i == 0) ? X[0] : lse2(A == -INFINITY ? -INFINITY : A - c, X[i]);
+        out[i] = lse2(lL, lU[i]);
+        const double u = lse2(lL, A);
+        lL = (u == -INFINITY) ? -INFINITY : u - c;
+    }
+    free(B); free(lU);
+    return OR_OK;
+}
+
+/* The same W in O(n1 n2 (n1 + n2)) at most: the split of or_cost2_fs1,
+ *   h1 sum phi . (K2 (x) C1) psi  +  h2 sum phi . (C2 (x) K1) psi,
+ * with every product taken on logarithms along its own axis. */
+double or_cost2_fs1_log(int64_t n1, int64_t n2, const double *F, const double *G,
+                        double h1, double h2, double eps) {
+    const int64_t n = n1 * n2;
+    const double c1 = h1 / eps, c2 = h2 / eps;
+    double *a = (double *)malloc((size_t)n * sizeof(double));
+    double *row = (double *)malloc((size_t)n2 * sizeof(double));
+    double *row2 = (double *)malloc((size_t)n2 * sizeof(double));
+    if (!a || !row || !row2) { free(a); free(row); free(row2); return NAN; }
+    nsum w1 = {0.0, 0.0}, w2 = {0.0, 0.0};
+    /* term 1: C1 along the first axis, then K2 along the second */
+    for (int64_t j = 0; j < n2; ++j) cost_kernel_fs1_log(n1, G + n1 * j, c1, a + n1 * j);
+    for (int64_t i = 0; i < n1; ++i) {
+        for (int64_t j = 0; j < n2; ++j) row[j] = a[i + n1 * j];
+        or_kv_fs1_log(n2, row, h2, eps, row2);
+        for (int64_t j = 0; j < n2; ++j) {
+            const double f = F[i + n1 * j];
+            if (f != -INFINITY && row2[j] != -INFINITY) nadd(&w1, exp(f + row2[j]));
+        }
+    }
+    /* term 2: K1 along the first axis, then C2 along the second */
+    for (int64_t j = 0; j < n2; ++j) or_kv_fs1_log(n1, G + n1 * j, h1, eps, a + n1 * j);
+    for (int64_t i = 0; i < n1; ++i) {
+        for (int64_t j = 0; j < n2; ++j) row[j] = a[i + n1 * j];
+        cost_kernel_fs1_log(n2, row, c2, row2);
+        for (int64_t j = 0; j < n2; ++j) {
+            const double f = F[i + n1 * j];
+            if (f != -INFINITY && row2[j] != -INFINITY) nadd(&w2, exp(f + row2[j]));
+        }
+    }
+    free(a); free(row); free(row2);
+    return h1 * nval(&w1) + h2 * nval(&w2);
+}
+
+/* Algorithm 2 on logarithms with the products dense (dense = 1) or by the
+ * recursions: F = G = -ln(n1 n2); while it < itr_max and err > tol:
+ * G <- ln nu - ln K^T e^F; F <- ln mu - ln K e^G.  Returns W as above. */
+static int solve2_log(int dense, int64_t n1, int64_t n2, const double *mu, const double *nu,
+                      double h1, double h2, double eps, double tol, int64_t itr_max,
+                      double *F, double *G, double *res) {
+    if (n1 < 1 || n2 < 1 || !(h1 > 0) || !(h2 > 0) || !(eps > 0) || itr_max < 0)
+        return OR_ERR_INVALID_ARG;
+    const int64_t n = n1 * n2;
+    double *lmu = (double *)malloc((size_t)n * sizeof(double));
+    double *lnu = (double *)malloc((size_t)n * sizeof(double));
+    double *lden = (double *)malloc((size_t)n * sizeof(double));
+    if (!lmu || !lnu || !lden) { free(lmu); free(lnu); free(lden); return OR_ERR_NO_MEMORY; }
+    for (int64_t r = 0; r < n; ++r) {
+        lmu[r] = mu[r] > 0 ? log(mu[r]) : -INFINITY;
+        lnu[r] = nu[r] > 0 ? log(nu[r]) : -INFINITY;
+        F[r] = G[r] = -log((double)n);
+    }
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = marginal_err2_log(dense, n1, n2, F, G, nu, h1, h2, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        if (dense) or_kv2_log_dense(n1, n2, F, h1, h2, eps, lden);  /* K symmetric */
+        else or_kv2_fs1_log(n1, n2, F, h1, h2, eps, lden);
+        if (divide_update_log(n, lnu, lden, G)) { st = OR_ERR_NONFINITE; break; }
+        if (dense) or_kv2_log_dense(n1, n2, G, h1, h2, eps, lden);
+        else or_kv2_fs1_log(n1, n2, G, h1, h2, eps, lden);
+        if (divide_update_log(n, lmu, lden, F)) { st = OR_ERR_NONFINITE; break; }
+        ++it;
+        err = marginal_err2_log(dense, n1, n2, F, G, nu, h1, h2, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = NAN;
+    if (st == OR_OK)
+        w = dense ? or_cost2_log_dense(n1, n2, F, G, h1, h2, eps)
+                  : or_cost2_fs1_log(n1, n2, F, G, h1, h2, eps);
+    pack_result(res, w, err, it, st, conv);
+    free(lmu); free(lnu); free(lden);
+    return st;
+}
+
+int or_sinkhorn2_log_dense(int64_t n1, int64_t n2, const double *mu, const double *nu,
+                           double h1, double h2, double eps, double tol, int64_t itr_max,
+                           double *F, double *G, double *res) {
+    return solve2_log(1, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, F, G, res);
+}
+
+int or_fs1_2d_log(int64_t n1, int64_t n2, const double *mu, const double *nu, double h1,
+                  double h2, double eps, double tol, int64_t itr_max, double *F, double *G,
+                  double *res) {
+    return solve2_log(0, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, F, G, res);
+}
+
 /* Thread count of the OpenMP loops (timing on a stated number of cores). */
 void or_set_num_threads(int k) {
 #ifdef _OPENMP

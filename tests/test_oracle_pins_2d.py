@@ -184,3 +184,126 @@ def test_table3_plan_parity_fs1_vs_dense(n):
                           - oracle.plan2(b.a, b.b, n, n, h, h, eps))
     assert diff <= 10 * g["table3_plan_diff"][str(n)]
     assert a.w1 == pytest.approx(b.w1, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 on logarithms (F = ln phi, G = ln psi; the stabilised form)
+# --------------------------------------------------------------------------
+
+def _logsumexp_rows(M):
+    m = np.max(M, axis=1)
+    m = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore"):
+        return m + np.log(np.exp(M - m[:, None]).sum(axis=1))
+
+
+@pytest.mark.parametrize("n1,n2,h1,h2,eps", [(1, 1, 0.1, 0.2, 0.3), (7, 1, 0.1, 0.2, 0.3),
+                                             (1, 6, 0.1, 0.2, 0.3), (9, 5, 0.1, 0.25, 0.02),
+                                             (4, 11, 0.3, 0.05, 0.001)])
+def test_kv2_log_against_logsumexp_of_the_kernel(n1, n2, h1, h2, eps):
+    # ln (K e^x) with K_{xy} = exp(-d(x, y)/eps), written as a logsumexp over
+    # the distance matrix; -inf entries are zeros of e^x
+    rng = np.random.default_rng(n1 * 13 + n2)
+    lx = 30.0 * rng.standard_normal(n1 * n2)
+    lx[rng.random(n1 * n2) < 0.2] = -np.inf
+    D = _dist2d(n1, n2, h1, h2)
+    ref = _logsumexp_rows(lx[None, :] - D / eps)
+    for f in (oracle.kv2_log_dense, oracle.kv2_fs1_log):
+        got = f(lx, n1, n2, h1, h2, eps)
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), fin)
+        np.testing.assert_allclose(got[fin], ref[fin], rtol=0, atol=1e-12 * (1 + np.abs(ref[fin])).max())
+
+
+def test_log_2d_equals_plain_2d_where_plain_works():
+    # in exact arithmetic the log iterates are the logarithms of the plain ones
+    n1, n2, h1, h2, eps = 9, 7, 0.1, 0.15, 0.2
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 3)
+    for its in (1, 6, 30):
+        p = oracle.sinkhorn2_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+        for solver in ("sinkhorn2_log_dense", "fs1_2d_log"):
+            r = getattr(oracle, solver)(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+            assert r.status == 0 and r.iterations == its
+            assert r.w1 == pytest.approx(p.w1, rel=1e-12)
+            assert r.marginal_err == pytest.approx(p.marginal_err, rel=1e-9, abs=1e-15)
+            np.testing.assert_allclose(r.a, np.log(p.a), rtol=0, atol=1e-12)
+            np.testing.assert_allclose(r.b, np.log(p.b), rtol=0, atol=1e-12)
+
+
+def test_log_2d_small_eps_where_plain_fails():
+    # h/eps = 800 along an axis: lambda1 = e^-800 underflows in plain binary64
+    # (the plain products lose every transport along that axis); the log
+    # forms agree with each other and keep the marginal on the mu side exact
+    n1, n2, h1, h2, eps = 12, 5, 0.8, 0.3, 0.001
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 7)
+    a = oracle.sinkhorn2_log_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=40)
+    b = oracle.fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=40)
+    assert a.status == 0 and b.status == 0
+    assert b.w1 == pytest.approx(a.w1, rel=1e-11)
+    assert b.marginal_err == pytest.approx(a.marginal_err, rel=1e-8, abs=1e-14)
+    np.testing.assert_allclose(b.a, a.a, rtol=0, atol=1e-9 * np.abs(a.a).max())
+    P = np.exp(a.a[:, None] + a.b[None, :] - _dist2d(n1, n2, h1, h2) / eps)
+    np.testing.assert_allclose(P.sum(axis=1), mu, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("solver", ["sinkhorn2_log_dense", "fs1_2d_log"])
+def test_log_2d_reduces_to_1d(solver):
+    n = 40
+    mu, nu = inputs.mixture_pair(n, 2, 4)
+    r1 = oracle.fs1_log(mu, nu, 0.03, 0.002, tol=0.0, itr_max=15)
+    for n1, n2, h1, h2 in ((n, 1, 0.03, 0.7), (1, n, 0.7, 0.03)):
+        r = getattr(oracle, solver)(mu, nu, n1, n2, h1, h2, 0.002, tol=0.0, itr_max=15)
+        assert r.status == 0 and r.iterations == 15
+        assert r.w1 == pytest.approx(r1.w1, rel=1e-11)
+        np.testing.assert_allclose(r.a, r1.a, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("solver", ["sinkhorn2_log_dense", "fs1_2d_log"])
+def test_log_2d_dirac_at_tiny_eps(solver):
+    # one iteration moves the unit mass exactly, even where e^{-d/eps} is far
+    # below the binary64 range; the potentials then reach d/eps = 1.1e4, whose
+    # rounding (d/eps) u = 1.2e-12 bounds the relative accuracy of P
+    n1, n2, h1, h2 = 9, 7, 0.1, 0.15
+    mu = np.zeros(n1 * n2)
+    nu = np.zeros(n1 * n2)
+    mu[2 + n1 * 5] = 1.0
+    nu[7 + n1 * 1] = 1.0
+    for eps in (0.05, 1e-4):
+        r = getattr(oracle, solver)(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=1)
+        tol = 16 * (5 * h1 + 4 * h2) / eps * 2.0 ** -53
+        assert r.status == 0
+        assert r.w1 == pytest.approx(5 * h1 + 4 * h2, rel=max(tol, 1e-14))
+        assert r.marginal_err <= max(tol, 1e-15)
+
+
+@pytest.mark.parametrize("solver", ["sinkhorn2_log_dense", "fs1_2d_log"])
+def test_log_2d_product_marginals_split_into_1d(solver):
+    # as for the plain form, at an eps where the plain products underflow
+    n1, n2, h1, h2, eps = 24, 15, 1.0 / 24, 1.0 / 15, 2e-4
+    m1, v1 = inputs.mixture_pair(n1, 2, 11)
+    m2, v2 = inputs.mixture_pair(n2, 3, 13)
+    mu = np.outer(m2, m1).reshape(-1)
+    nu = np.outer(v2, v1).reshape(-1)
+    for its in (1, 7):
+        w1 = oracle.fs1_log(m1, v1, h1, eps, tol=0.0, itr_max=its).w1
+        w2 = oracle.fs1_log(m2, v2, h2, eps, tol=0.0, itr_max=its).w1
+        r = getattr(oracle, solver)(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+        assert r.status == 0
+        assert r.w1 == pytest.approx(w1 + w2, rel=1e-10)
+
+
+def test_log_2d_cost_and_err_against_numpy():
+    n1, n2, h1, h2, eps = 6, 8, 0.2, 0.35, 0.01
+    rng = np.random.default_rng(5)
+    F, G = 3.0 * rng.standard_normal(n1 * n2), 3.0 * rng.standard_normal(n1 * n2)
+    F[3] = -np.inf
+    G[10] = -np.inf
+    nu = rng.random(n1 * n2)
+    D = _dist2d(n1, n2, h1, h2)
+    P = np.exp(F[:, None] + G[None, :] - D / eps)
+    w = float((P * D).sum())
+    err = float(np.abs(P.sum(axis=0) - nu).sum())
+    for f in (oracle.cost2_log_dense, oracle.cost2_fs1_log):
+        assert f(F, G, n1, n2, h1, h2, eps) == pytest.approx(w, rel=1e-12)
+    for f in (oracle.marginal_err2_log_dense, oracle.marginal_err2_fs1_log):
+        assert f(F, G, nu, n1, n2, h1, h2, eps) == pytest.approx(err, rel=1e-12)
