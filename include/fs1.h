@@ -343,12 +343,17 @@ int fs1_kv_apply_2d(fs1_ctx *ctx, const void *x, void *y, int64_t n1, int64_t n2
  * phi = mu / (K psi).  Returns the transport cost
  *   w1 = sum phi_(i,j) psi_(k,l) K_{(i,j),(k,l)} (|i-k| h1 + |j-l| h2).
  * mu, nu: device binary64 arrays of n1 n2 entries (column-major), finite,
- * >= 0, equal mass to 1e-10 relative.  opts as for fs1_solve except: domain
- * must be FS1_PLAIN (Algorithm 2's arithmetic; FS1_LOG is
- * FS1_ERR_INVALID_ARG), opts->h is ignored (h1, h2 given); a small grid
+ * >= 0, equal mass to 1e-10 relative.  opts as for fs1_solve except:
+ * opts->h is ignored (h1, h2 given); domain FS1_PLAIN is Algorithm 2's
+ * arithmetic, FS1_LOG its stabilised form (the Sec. 3 remark on log-domain
+ * stabilisation carried to Algorithm 2: every scaling entry held as a
+ * mantissa and a binary exponent, so no product underflows at small eps; the
+ * same iterates in exact arithmetic; 16 bytes more workspace per grid
+ * point); FS1_ABSORB is FS1_ERR_INVALID_ARG.  In the plain domain a small grid
  * (n1 n2 <= 4096, n1 + n2 <= 128) runs the whole solve in one workgroup (the
  * paper's sequential recursions, one line per thread) unless
- * FS1_FLAG_NO_RESIDENT is set, other grids one workgroup per line and pass;
+ * FS1_FLAG_NO_RESIDENT is set; other grids, and every grid in the log
+ * domain, run one workgroup per line and pass;
  * potentials_out receives ln phi then
  * ln psi (2 n1 n2 doubles).  Blocking; error behaviour as fs1_solve. */
 int fs1_solve_2d(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n1, int64_t n2,

@@ -18,6 +18,14 @@
 //
 // Plain domain (Algorithm 2 as written): scalings are plain numbers, and a
 // non-finite or zero-denominator scaling ends the solve.
+//
+// Log domain (the stabilised form, Sec. 3 remark carried to Algorithm 2): every
+// scaling entry is a mantissa and an int32 binary exponent, so its logarithm
+// is ln m + e ln 2 and no product underflows however small eps is.  A pass
+// takes the largest exponent of each thread's R entries as the exponent of its
+// run and scans in extended range, as the 1-D log domain does; its output is
+// a mantissa per entry beside the run's frame exponent, and the update
+// normalises every new scaling entry to its own exponent.
 #include <cmath>
 #include <cstring>
 
@@ -37,6 +45,9 @@ struct LineArgs {
   const void* x;        // input of the pass
   void* y;              // output (APPLY, COST, UPDATE)
   const void* own;      // ERR, DOT, COSTDOT, checked UPDATE: the vector the product multiplies
+  const int* xe;        // log domain: binary exponents of x, y and own (one per entry)
+  int* ye;
+  const int* owne;
   const double* m64;    // marginal, binary64 (UPDATE with T = double; ERR; checked UPDATE)
   const float* m32;     // marginal, binary32 (UPDATE with T = float)
   double* part;         // per-line shares (ERR, DOT, COSTDOT, checked UPDATE)
@@ -56,7 +67,8 @@ struct LineArgs {
   double* err_hist;
 };
 
-template <typename T, int R, int NT, int MODE>
+// SC: the log domain (mantissas with per-entry exponents xe, ye, owne).
+template <typename T, int R, int NT, int MODE, bool SC>
 __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   constexpr int NW = NT / kWave;
   __shared__ ScanLds<S1<T>, NW> sh;
@@ -91,6 +103,21 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   T x[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = (p0 + r < a.len) ? xin[base + int64_t(p0 + r) * a.stride] : T(0);
+  // log domain: the run's exponent E is the largest of its entries' (zeros
+  // excluded), and the run's values are the mantissas moved to it
+  int E = 0;
+  if constexpr (SC) {
+    int xe[R];
+    int emax = kExpZero;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xe[r] = (p0 + r < a.len) ? a.xe[base + int64_t(p0 + r) * a.stride] : 0;
+      if (x[r] != T(0)) emax = max(emax, xe[r]);
+    }
+    E = (emax == kExpZero) ? 0 : emax;
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = (x[r] == T(0)) ? T(0) : ldx(x[r], xe[r] - E);
+  }
   const Lam<T> L = lam_of<T>(k);
   Dec<T> dec[7];
   lane_decays<T>(k, dec);
@@ -102,13 +129,13 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     T fp, fd, bp, bd;
     run_aggs2<T, R>(x, L, fp, fd, bp, bd);
     S2<T> cf, cb;
-    block_scan<S2<T>, NW, T>(S2<T>::of(fp, fd, 0), S2<T>::of(bp, bd, 0), dec, S2<T>::zero(),
+    block_scan<S2<T>, NW, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, S2<T>::zero(),
                              S2<T>::zero(), &cf, &cb, nullptr, nullptr, sh2);
     const S2<T> lcf = cf.shift(step), lcb = cb.shift(step);
-    eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, 0), k);
+    eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, E), k);
     T xf[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) xf[r] = ldx(x[r], -eref);
+    for (int r = 0; r < R; ++r) xf[r] = ldx(x[r], E - eref);
     run_cost<T, R>(xf, ldx(lcf.p.m, lcf.p.e - eref), ldx(lcf.d.m, lcf.d.e - eref),
                    ldx(lcb.p.m, lcb.p.e - eref), ldx(lcb.d.m, lcb.d.e - eref), L, y);
   } else {
@@ -116,27 +143,50 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     T af, ab;
     run_aggs<T, R>(x, L, af, ab);
     S1<T> cf, cb;
-    block_scan<S1<T>, NW, T>(S1<T>{{af, 0}}, S1<T>{{ab, 0}}, dec, S1<T>::zero(), S1<T>::zero(),
+    block_scan<S1<T>, NW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(), S1<T>::zero(),
                              &cf, &cb, nullptr, nullptr, sh);
     const S1<T> lcf = cf.shift(step), lcb = cb.shift(step);
-    run_apply<T, R>(x, ldx(lcf.v.m, lcf.v.e), ldx(lcb.v.m, lcb.v.e), L, y);
+    if constexpr (SC) {
+      // the product on the run's frame: the largest of the run's and the
+      // carries' exponents
+      eref = max(local_exponent<T, R>(x, E), max(lcf.v.e, lcb.v.e));
+      if (eref == kExpZero) eref = 0;
+      T xf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) xf[r] = ldx(x[r], E - eref);
+      run_apply<T, R>(xf, ldx(lcf.v.m, lcf.v.e - eref), ldx(lcb.v.m, lcb.v.e - eref), L, y);
+    } else {
+      run_apply<T, R>(x, ldx(lcf.v.m, lcf.v.e), ldx(lcb.v.m, lcb.v.e), L, y);
+    }
   }
-  // y * 2^eref is the product at this thread's positions (eref = 0 except for
-  // the cost recursion's frame)
+  // y * 2^eref is the product at this thread's positions (plain domain: eref
+  // = 0 except for the cost recursion's frame)
   T* yout = static_cast<T*>(a.y);
   if constexpr (MODE == L_APPLY || MODE == L_COST) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (p0 + r < a.len) yout[base + int64_t(p0 + r) * a.stride] = ldx(y[r], eref);
+      if (p0 + r < a.len) {
+        const int64_t q = base + int64_t(p0 + r) * a.stride;
+        if constexpr (SC) {
+          yout[q] = y[r];
+          a.ye[q] = eref;
+        } else {
+          yout[q] = ldx(y[r], eref);
+        }
+      }
     return;
   }
   const T* own = static_cast<const T*>(a.own);
+  // exponent of own at position q, beside the product's eref
+  auto own_exp = [&](int64_t q) { return SC ? a.owne[q] + eref : eref; };
   if constexpr (MODE == L_DOT || MODE == L_COSTDOT) {
     double s = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (p0 + r < a.len)
-        s += ldexp(double(own[base + int64_t(p0 + r) * a.stride]) * double(y[r]), eref);
+      if (p0 + r < a.len) {
+        const int64_t q = base + int64_t(p0 + r) * a.stride;
+        s += ldexp(double(own[q]) * double(y[r]), own_exp(q));
+      }
     const double tot = block_sum<NW>(s, red);
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
     return;
@@ -149,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     for (int r = 0; r < R; ++r)
       if (p0 + r < a.len) {
         const int64_t q = base + int64_t(p0 + r) * a.stride;
-        s += fabs(double(own[q]) * double(y[r]) - a.m64[q]);
+        s += fabs(ldexp(double(own[q]) * double(y[r]), own_exp(q)) - a.m64[q]);
       }
     const double tot = block_sum<NW>(s, red);
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
@@ -163,7 +213,15 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
         const T mg = (sizeof(T) == 8) ? T(a.m64[q]) : T(a.m32[q]);
         const T v = (mg == T(0)) ? T(0) : mg / y[r];
         bad |= !isfinite(v);
-        yout[q] = v;
+        if constexpr (SC) {
+          // marg / (y 2^eref) = v 2^-eref, normalised entry by entry
+          int kv = 0;
+          const T vm = (v == T(0) || !isfinite(v)) ? v : frx(v, &kv);
+          yout[q] = vm;
+          a.ye[q] = (v == T(0)) ? 0 : kv - eref;
+        } else {
+          yout[q] = v;
+        }
       }
     if (bad) {
       atomicOr(&a.ctrl->fail, 1);
@@ -191,14 +249,22 @@ __global__ void k_fill2(T* a, T* b, int64_t n, T v) {
   }
 }
 
-// F = ln phi, G = ln psi (binary64; -inf where a scaling is zero)
+// F = ln phi, G = ln psi (binary64; -inf where a scaling is zero); in the log
+// domain the entries are m 2^e with their exponents in ea, eb
 template <typename T>
-__global__ void k_log2(const T* a, const T* b, int64_t n, double* out) {
+__global__ void k_log2(const T* a, const T* b, const int* ea, const int* eb, int64_t n,
+                       double* out) {
+  constexpr double kLn2 = 0.69314718055994530942;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) {
-    out[i] = log(double(a[i]));
-    out[n + i] = log(double(b[i]));
+    out[i] = log(double(a[i])) + (ea ? double(ea[i]) * kLn2 : 0.0);
+    out[n + i] = log(double(b[i])) + (eb ? double(eb[i]) * kLn2 : 0.0);
   }
+}
+
+__global__ void k_zero_int(int* a, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -444,30 +510,40 @@ hipError_t launch_res2d(const Res2Args& a, size_t lds, hipStream_t s) {
   }
 }
 
-// One pass over the lines of one axis.
+// One pass over the lines of one axis.  R: entries per thread (kR2, or 1 in
+// the log domain where h/eps is too large for runs of kR2, as in 1-D).
 struct Axis {
   int64_t nlines;
   int64_t line_step;
   int64_t stride;
   int len;
+  int R;
   ScanConsts k;
 };
 
-template <typename T, int MODE>
+template <typename T, int R, int MODE, bool SC>
+hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
+  const unsigned g = unsigned(ax.nlines);
+  if (ax.len <= kWave * R) {
+    // one wavefront: its scans and reductions stay in registers
+    k_line<T, R, kWave, MODE, SC><<<g, kWave, 0, s>>>(a, ax.k);
+  } else if (ax.len <= 256 * R) {
+    k_line<T, R, 256, MODE, SC><<<g, 256, 0, s>>>(a, ax.k);
+  } else {
+    k_line<T, R, 1024, MODE, SC><<<g, 1024, 0, s>>>(a, ax.k);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE, bool SC = false>
 hipError_t run_pass(const Axis& ax, LineArgs a, hipStream_t s) {
   a.line_step = ax.line_step;
   a.stride = ax.stride;
   a.len = ax.len;
-  const unsigned g = unsigned(ax.nlines);
-  if (ax.len <= kWave * kR2) {
-    // one wavefront: its scans and reductions stay in registers
-    k_line<T, kR2, kWave, MODE><<<g, kWave, 0, s>>>(a, ax.k);
-  } else if (ax.len <= 256 * kR2) {
-    k_line<T, kR2, 256, MODE><<<g, 256, 0, s>>>(a, ax.k);
-  } else {
-    k_line<T, kR2, 1024, MODE><<<g, 1024, 0, s>>>(a, ax.k);
+  if constexpr (SC) {
+    if (ax.R == 1) return run_pass_r<T, 1, MODE, SC>(ax, a, s);
   }
-  return hipGetLastError();
+  return run_pass_r<T, kR2, MODE, SC>(ax, a, s);
 }
 
 struct Grid2 {
@@ -475,23 +551,42 @@ struct Grid2 {
   Axis ax1, ax2;
 };
 
-Grid2 make_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps) {
+// Entries per thread along an axis: kR2, except in the log domain where every
+// output of a run must stay within lambda^(R-1) of its largest contribution
+// inside the working precision (the 1-D bound on (R-1) h/eps), else 1.
+int line_run_length(bool log_domain, int dt, double h, double eps) {
+  if (!log_domain) return kR2;
+  return pick_run_length(dt, true, h / eps) >= kR2 ? kR2 : 1;
+}
+
+Grid2 make_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps,
+                 bool log_domain = false, int dt = FS1_F64) {
   Grid2 g;
   g.n1 = n1;
   g.n2 = n2;
+  const int r1 = line_run_length(log_domain, dt, h1, eps);
+  const int r2 = line_run_length(log_domain, dt, h2, eps);
   // columns: n2 lines of n1 contiguous entries; rows: n1 lines strided by n1
-  g.ax1 = Axis{n2, n1, 1, int(n1), make_scan_consts(h1, eps, kR2)};
-  g.ax2 = Axis{n1, 1, n1, int(n2), make_scan_consts(h2, eps, kR2)};
+  g.ax1 = Axis{n2, n1, 1, int(n1), r1, make_scan_consts(h1, eps, r1)};
+  g.ax2 = Axis{n1, 1, n1, int(n2), r2, make_scan_consts(h2, eps, r2)};
   return g;
 }
 
-int check_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps) {
+int check_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps,
+                bool log_domain = false, int dt = FS1_F64) {
   using host::set_err;
   const int64_t lmax = int64_t(1024) * kR2;
   if (n1 < 1 || n2 < 1) return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be >= 1");
   if (n1 > lmax || n2 > lmax)
     return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be <= %lld (got %lld x %lld)",
                    (long long)lmax, (long long)n1, (long long)n2);
+  // one workgroup holds a line: 1024 entries where the runs have length 1
+  if (log_domain && ((line_run_length(true, dt, h1, eps) == 1 && n1 > 1024) ||
+                     (line_run_length(true, dt, h2, eps) == 1 && n2 > 1024)))
+    return set_err(FS1_ERR_INVALID_ARG,
+                   "log domain: h/eps too large for runs of %d along an axis of more than 1024 "
+                   "entries",
+                   kR2);
   if (!(h1 > 0.0) || !std::isfinite(h1) || !(h2 > 0.0) || !std::isfinite(h2))
     return set_err(FS1_ERR_INVALID_ARG, "h1 and h2 must be finite and > 0");
   if (!(eps > 0.0) || !std::isfinite(eps))
@@ -517,6 +612,9 @@ struct Bufs2 {
   void* vF;
   void* vG[2];
   void* t;
+  int* eF;          // log domain: exponents of vF, vG, t (one per entry)
+  int* eG[2];
+  int* et;
   double* mu;       // caller's marginals, binary64
   double* nu;
   float* mu32;      // binary32 copies (T = float)
@@ -527,26 +625,40 @@ struct Bufs2 {
   Ctrl* ctrl;
 };
 
-template <typename T>
+// SC: the log domain, every vector with its per-entry exponents.
+template <typename T, bool SC>
 struct Ops2 {
+  // x of a pass with its exponents
+  static void in(LineArgs& a, const void* v, const int* e) {
+    a.x = v;
+    a.xe = e;
+  }
+  static void to(LineArgs& a, void* v, int* e) {
+    a.y = v;
+    a.ye = e;
+  }
+  static void with(LineArgs& a, const void* v, const int* e) {
+    a.own = v;
+    a.owne = e;
+  }
   // psi^{l+1} = nu / K^T phi^l into vG[(l+1)&1] (and the error of (phi^l, psi^l) when checked)
   static hipError_t psi_half(const Grid2& g, const Bufs2& b, int l, int check, hipStream_t s) {
     LineArgs a{};
     a.ctrl = b.ctrl;
     a.guard = 1;
     a.l = l;
-    a.x = b.vF;
-    a.y = b.t;
-    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    in(a, b.vF, b.eF);
+    to(a, b.t, b.et);
+    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
-    a.x = b.t;
-    a.y = b.vG[(l + 1) & 1];
-    a.own = b.vG[l & 1];
+    in(a, b.t, b.et);
+    to(a, b.vG[(l + 1) & 1], b.eG[(l + 1) & 1]);
+    with(a, b.vG[l & 1], b.eG[l & 1]);
     a.m64 = b.nu;
     a.m32 = b.nu32;
     a.part = b.part;
     a.check = check;
-    return run_pass<T, L_UPDATE>(g.ax2, a, s);
+    return run_pass<T, L_UPDATE, SC>(g.ax2, a, s);
   }
   // phi^{l+1} = mu / K psi^{l+1}; when checked, its first pass takes the stop
   // decision of iteration l from the psi-half's shares first
@@ -556,21 +668,21 @@ struct Ops2 {
     a.ctrl = b.ctrl;
     a.guard = 1;
     a.l = l;
-    a.x = b.vG[(l + 1) & 1];
-    a.y = b.t;
+    in(a, b.vG[(l + 1) & 1], b.eG[(l + 1) & 1]);
+    to(a, b.t, b.et);
     a.decide = check;
     a.part = b.part;
     a.nparts = int(g.ax2.nlines);
     a.tol = tol;
     a.err_hist = err_hist;
-    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
     a.decide = 0;
-    a.x = b.t;
-    a.y = b.vF;
+    in(a, b.t, b.et);
+    to(a, b.vF, b.eF);
     a.m64 = b.mu;
     a.m32 = b.mu32;
-    return run_pass<T, L_UPDATE>(g.ax2, a, s);
+    return run_pass<T, L_UPDATE, SC>(g.ax2, a, s);
   }
   // final errors (both sides) and the transport cost of (phi, psi = vG[gbuf])
   static hipError_t finalize(const Grid2& g, const Bufs2& b, int gbuf, double h1, double h2,
@@ -579,49 +691,49 @@ struct Ops2 {
     LineArgs a{};
     a.ctrl = b.ctrl;
     // nu side: sum | psi (K^T phi) - nu |
-    a.x = b.vF;
-    a.y = b.t;
-    hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    in(a, b.vF, b.eF);
+    to(a, b.t, b.et);
+    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
-    a.x = b.t;
-    a.own = b.vG[gbuf];
+    in(a, b.t, b.et);
+    with(a, b.vG[gbuf], b.eG[gbuf]);
     a.m64 = b.nu;
     a.part = b.part;
-    e = run_pass<T, L_ERR>(g.ax2, a, s);
+    e = run_pass<T, L_ERR, SC>(g.ax2, a, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part, nl, 1.0, b.sums + 0);
     // mu side: sum | phi (K psi) - mu |
-    a.x = b.vG[gbuf];
-    a.y = b.t;
-    e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    in(a, b.vG[gbuf], b.eG[gbuf]);
+    to(a, b.t, b.et);
+    e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
-    a.x = b.t;
-    a.own = b.vF;
+    in(a, b.t, b.et);
+    with(a, b.vF, b.eF);
     a.m64 = b.mu;
     a.part = b.part2;
-    e = run_pass<T, L_ERR>(g.ax2, a, s);
+    e = run_pass<T, L_ERR, SC>(g.ax2, a, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part2, nl, 1.0, b.sums + 1);
     // cost, first axis: h1 <phi, (K2 (x) C1) psi>
-    a.x = b.vG[gbuf];
-    a.y = b.t;
-    e = run_pass<T, L_COST>(g.ax1, a, s);
+    in(a, b.vG[gbuf], b.eG[gbuf]);
+    to(a, b.t, b.et);
+    e = run_pass<T, L_COST, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
-    a.x = b.t;
-    a.own = b.vF;
+    in(a, b.t, b.et);
+    with(a, b.vF, b.eF);
     a.part = b.part;
-    e = run_pass<T, L_DOT>(g.ax2, a, s);
+    e = run_pass<T, L_DOT, SC>(g.ax2, a, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part, nl, h1, b.sums + 2);
     // cost, second axis: h2 <phi, (C2 (x) K1) psi>
-    a.x = b.vG[gbuf];
-    a.y = b.t;
-    e = run_pass<T, L_APPLY>(g.ax1, a, s);
+    in(a, b.vG[gbuf], b.eG[gbuf]);
+    to(a, b.t, b.et);
+    e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
     if (e != hipSuccess) return e;
-    a.x = b.t;
-    a.own = b.vF;
+    in(a, b.t, b.et);
+    with(a, b.vF, b.eF);
     a.part = b.part2;
-    e = run_pass<T, L_COSTDOT>(g.ax2, a, s);
+    e = run_pass<T, L_COSTDOT, SC>(g.ax2, a, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part2, nl, h2, b.sums + 3);
     return hipGetLastError();
@@ -629,8 +741,9 @@ struct Ops2 {
 };
 
 template <typename F>
-hipError_t dispatch2(int dt, F&& f) {
-  return dt == 0 ? f(Ops2<double>{}) : f(Ops2<float>{});
+hipError_t dispatch2(int dt, bool log_domain, F&& f) {
+  if (log_domain) return dt == 0 ? f(Ops2<double, true>{}) : f(Ops2<float, true>{});
+  return dt == 0 ? f(Ops2<double, false>{}) : f(Ops2<float, false>{});
 }
 
 }  // namespace
@@ -668,12 +781,13 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   if (!mu || !nu) return finish(set_err(FS1_ERR_INVALID_ARG, "null marginal"));
   if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
     return finish(set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype));
-  if (o.domain != FS1_PLAIN)
-    return finish(set_err(FS1_ERR_INVALID_ARG, "the 2-D solve runs in the plain domain only"));
+  if (o.domain != FS1_PLAIN && o.domain != FS1_LOG)
+    return finish(set_err(FS1_ERR_INVALID_ARG, "the 2-D solve runs in the plain or log domain"));
+  const bool lg = o.domain == FS1_LOG;
   if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
   if ((o.flags & FS1_FLAG_POTENTIALS) && !o.potentials_out)
     return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
-  int st = check_grid2(n1, n2, h1, h2, eps);
+  int st = check_grid2(n1, n2, h1, h2, eps, o.domain == FS1_LOG, o.dtype);
   if (st) return finish(st);
   const int dt = o.dtype;
   const int64_t n = n1 * n2;
@@ -686,6 +800,12 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     b.vG[0] = w.take(size_t(n) * es);
     b.vG[1] = w.take(size_t(n) * es);
     b.t = w.take(size_t(n) * es);
+    if (lg) {
+      b.eF = static_cast<int*>(w.take(size_t(n) * 4));
+      b.eG[0] = static_cast<int*>(w.take(size_t(n) * 4));
+      b.eG[1] = static_cast<int*>(w.take(size_t(n) * 4));
+      b.et = static_cast<int*>(w.take(size_t(n) * 4));
+    }
     b.mu = static_cast<double*>(w.take(size_t(n) * 8));
     b.nu = static_cast<double*>(w.take(size_t(n) * 8));
     b.mu32 = dt == FS1_F32 ? static_cast<float*>(w.take(size_t(n) * 4)) : nullptr;
@@ -747,12 +867,19 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
                                       float(1.0 / double(n)));
   }
   HIP_TRY(hipGetLastError());
+  if (lg) {
+    // phi = psi = 1/n as mantissas with exponent 0
+    k_zero_int<<<gf, 256, 0, s>>>(b.eF, n);
+    k_zero_int<<<gf, 256, 0, s>>>(b.eG[0], n);
+    HIP_TRY(hipGetLastError());
+  }
   // the ctrl upload reads the pinned mirror: finish it before the host reuses it
   HIP_TRY(hipStreamSynchronize(s));
 
-  const Grid2 g = make_grid2(n1, n2, h1, h2, eps);
-  // small grids: every iteration in one workgroup; it leaves psi in buffer 0
-  const size_t lds = (o.flags & FS1_FLAG_NO_RESIDENT) ? 0 : res2d_lds(n1, n2, dt);
+  const Grid2 g = make_grid2(n1, n2, h1, h2, eps, lg, dt);
+  // small grids (plain domain): every iteration in one workgroup; it leaves
+  // psi in buffer 0
+  const size_t lds = (lg || (o.flags & FS1_FLAG_NO_RESIDENT)) ? 0 : res2d_lds(n1, n2, dt);
   bool resident = false;
   if (lds > 0) {
     Res2Args ra{};
@@ -783,8 +910,9 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     const int l_end = std::min(o.itr_max, l + o.sync_every);
     for (; l < l_end; ++l) {
       const int check = (l % o.check_every) == 0;
-      HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::psi_half(g, b, l, check, s); }));
-      HIP_TRY(dispatch2(dt, [&](auto ops) {
+      HIP_TRY(dispatch2(dt, lg,
+                        [&](auto ops) { return decltype(ops)::psi_half(g, b, l, check, s); }));
+      HIP_TRY(dispatch2(dt, lg, [&](auto ops) {
         return decltype(ops)::phi_half(g, b, l, check, tol, o.err_history, s);
       }));
     }
@@ -803,15 +931,18 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   }
   const int l_final = (hc->done && hc->stop_iter >= 0) ? hc->stop_iter : o.itr_max;
   const int gbuf = resident ? 0 : (l_final & 1);
-  HIP_TRY(dispatch2(dt, [&](auto ops) { return decltype(ops)::finalize(g, b, gbuf, h1, h2, s); }));
+  HIP_TRY(dispatch2(dt, lg,
+                    [&](auto ops) { return decltype(ops)::finalize(g, b, gbuf, h1, h2, s); }));
   if (o.flags & FS1_FLAG_POTENTIALS) {
+    const int* ea = lg ? b.eF : nullptr;
+    const int* eb = lg ? b.eG[gbuf] : nullptr;
     if (dt == FS1_F64) {
       k_log2<double><<<gf, 256, 0, s>>>(static_cast<const double*>(b.vF),
-                                        static_cast<const double*>(b.vG[gbuf]), n,
+                                        static_cast<const double*>(b.vG[gbuf]), ea, eb, n,
                                         o.potentials_out);
     } else {
       k_log2<float><<<gf, 256, 0, s>>>(static_cast<const float*>(b.vF),
-                                       static_cast<const float*>(b.vG[gbuf]), n,
+                                       static_cast<const float*>(b.vG[gbuf]), ea, eb, n,
                                        o.potentials_out);
     }
     HIP_TRY(hipGetLastError());

@@ -500,17 +500,19 @@ def fs1_solve_2d(mu, nu, n1: int, n2: int, h1: float, h2: float, eps: float, tol
                  itr_max: int = 10000, dtype: str = "f64", check_every: int = 1,
                  sync_every: int = 16, potentials: bool = False, err_history: bool = False,
                  solver: str = "auto", ctx: Optional[Context] = None,
-                 raise_on_error: bool = False) -> Result:
+                 raise_on_error: bool = False, domain: str = "plain") -> Result:
     """Algorithm 2 (2-D FS-1) on device float64 marginals of n1 * n2 entries
-    (column-major), plain domain.  solver: "auto" (one workgroup for small
-    grids, n1 n2 <= 4096 and n1 + n2 <= 128, else one launch per line pass)
-    or "lines" (always the per-line launches)."""
+    (column-major).  domain: "plain" (Algorithm 2's arithmetic) or "log" (its
+    stabilised form: scalings as mantissas with per-entry binary exponents).
+    solver: "auto" (plain domain: one workgroup for small grids, n1 n2 <= 4096
+    and n1 + n2 <= 128, else one launch per line pass) or "lines" (always the
+    per-line launches)."""
     import torch
     ctx = ctx or default_context()
     n = n1 * n2
     if mu.numel() != n or nu.numel() != n:
         raise ValueError("mu and nu must hold n1 * n2 entries")
-    o = make_opts(None, itr_max, dtype, "plain", check_every, sync_every)
+    o = make_opts(None, itr_max, dtype, domain, check_every, sync_every)
     o.flags |= {"auto": 0, "lines": FS1_FLAG_NO_RESIDENT}[solver]
     pot = hist = None
     if potentials:

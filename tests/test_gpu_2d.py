@@ -247,3 +247,136 @@ def test_solve_2d_failure_and_arguments(solver):
         fs1.fs1_solve_2d(big, big, 8193, 2, 0.1, 0.1, 0.1, 0.0)
     with pytest.raises(fs1.Fs1Error):
         fs1.fs1_kv_apply_2d(big, 2, 8193, 0.1, 0.1, 0.1)
+
+
+# --------------------------------------------------------------------------
+# the log domain (Algorithm 2's stabilised form): scalings as mantissas with
+# per-entry binary exponents.  Tolerances as for the plain solve, with the
+# potentials compared to 1e-9 (1 + max |F|): at small eps they reach d/eps,
+# whose rounding is the oracle's own.
+# --------------------------------------------------------------------------
+
+def _log_ref(mu, nu, n1, n2, h1, h2, eps, its):
+    if n1 * n2 <= 600:
+        return oracle.sinkhorn2_log_dense(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+    return oracle.fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=its)
+
+
+@pytest.mark.parametrize("n1,n2,h1,h2,eps,its", [
+    (1, 1, 0.1, 0.1, 0.01, 3), (12, 5, 0.8, 0.3, 0.001, 40), (17, 23, 0.05, 0.03, 1e-3, 30),
+    (64, 9, 1.0 / 64, 1.0 / 9, 2e-4, 25), (600, 3, 1.0 / 600, 0.1, 1e-3, 20),
+    (3, 1500, 0.2, 1.0 / 1500, 5e-4, 12), (100, 77, 0.01, 0.013, 1e-3, 15),
+    (2500, 2, 1.0 / 2500, 0.1, 1e-3, 8)])
+def test_solve_2d_log_against_oracle(n1, n2, h1, h2, eps, its):
+    fs1 = _fs1()
+    mu, nu = inputs.paper_uniform_2d(n1, n2, n1 + 3 * n2)
+    _say(f"solve2 log {n1}x{n2} eps={eps} its={its}")
+    ref = _log_ref(mu, nu, n1, n2, h1, h2, eps, its)
+    assert ref.status == 0
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its, domain="log",
+                         potentials=True)
+    assert r.status == 0 and r.iterations == ref.iterations
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-10, abs=1e-300)
+    assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
+    F, G = r.F.cpu().numpy(), r.G.cpu().numpy()
+    m, v = mu > 0, nu > 0
+    scale = 1.0 + max(np.abs(ref.a[m]).max(), np.abs(ref.b[v]).max())
+    assert np.max(np.abs(F[m] - ref.a[m])) <= 1e-9 * scale
+    assert np.max(np.abs(G[v] - ref.b[v])) <= 1e-9 * scale
+
+
+def test_solve_2d_log_equals_plain_where_plain_works():
+    fs1 = _fs1()
+    n1, n2, h1, h2, eps = 40, 33, 0.02, 0.03, 0.05
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 9)
+    for solver in ("lines", "auto"):
+        p = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=30,
+                             solver=solver)
+        lg = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=30,
+                              domain="log", solver=solver)
+        assert p.status == 0 and lg.status == 0
+        assert lg.w1 == pytest.approx(p.w1, rel=1e-12)
+        assert lg.marginal_err == pytest.approx(p.marginal_err, rel=1e-8)
+
+
+def test_solve_2d_log_small_eps_where_plain_fails():
+    # Dirac masses 6 and 4 cells apart along the axes at h/eps = 100 and 50:
+    # the plain products underflow and the plain solve ends abnormally; the
+    # log domain moves the mass exactly
+    fs1 = _fs1()
+    n1, n2, h1, h2, eps = 9, 7, 0.1, 0.05, 0.001
+    mu = np.zeros(n1 * n2)
+    nu = np.zeros(n1 * n2)
+    mu[1 + n1 * 5] = 1.0
+    nu[7 + n1 * 1] = 1.0
+    p = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=3, solver="lines")
+    assert p.status != 0
+    for dt in ("f64", "f32"):
+        r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=1,
+                             domain="log", dtype=dt)
+        assert r.status == 0
+        assert r.w1 == pytest.approx(6 * h1 + 4 * h2, rel=1e-12 if dt == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("n1,n2", [(30, 22), (150, 9)])
+def test_solve_2d_log_f32_against_f64_oracle(n1, n2):
+    fs1 = _fs1()
+    h1, h2, eps = 1.0 / n1, 1.0 / n2, 5e-4
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 21)
+    ref = _log_ref(mu, nu, n1, n2, h1, h2, eps, 20)
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=20, domain="log",
+                         dtype="f32")
+    assert r.status == 0 and r.iterations == 20
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
+
+
+def test_solve_2d_log_product_marginals_and_tolerance():
+    # product marginals: W_2D = W_1D(axis 1) + W_1D(axis 2) at every iteration
+    # count; then the same grid to tolerance 1e-8 against the oracle's stop
+    fs1 = _fs1()
+    n1, n2, eps = 48, 20, 1e-3
+    h1, h2 = 1.0 / n1, 1.0 / n2
+    m1, v1 = inputs.mixture_pair(n1, 2, 11)
+    m2, v2 = inputs.mixture_pair(n2, 3, 13)
+    mu = np.outer(m2, m1).reshape(-1)
+    nu = np.outer(v2, v1).reshape(-1)
+    for its in (1, 9):
+        w1 = oracle.fs1_log(m1, v1, h1, eps, tol=0.0, itr_max=its).w1
+        w2 = oracle.fs1_log(m2, v2, h2, eps, tol=0.0, itr_max=its).w1
+        r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its,
+                             domain="log")
+        assert r.status == 0 and r.w1 == pytest.approx(w1 + w2, rel=1e-10)
+    ref = oracle.fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=1e-8, itr_max=3000)
+    r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 1e-8, itr_max=3000,
+                         domain="log")
+    assert ref.converged and r.converged and r.marginal_err <= 1e-8
+    assert abs(r.iterations - ref.iterations) <= 1
+    assert r.w1 == pytest.approx(ref.w1, rel=1e-8)
+
+
+def test_solve_2d_log_arguments():
+    fs1 = _fs1()
+    mu, nu = inputs.paper_uniform_2d(4, 5, 1)
+    with pytest.raises(RuntimeError):
+        fs1.fs1_solve_2d(dev(mu), dev(nu), 4, 5, 0.1, 0.1, 0.01, 0.0, itr_max=3,
+                         domain="absorb")
+    # h/eps beyond the bound of runs of 8 needs one entry per thread, so a
+    # line holds at most 1024 entries
+    mu, nu = inputs.paper_uniform_2d(1100, 2, 1)
+    with pytest.raises(RuntimeError):
+        fs1.fs1_solve_2d(dev(mu), dev(nu), 1100, 2, 0.1, 0.1, 0.001, 0.0, itr_max=3,
+                         domain="log")
+
+
+def test_solve_2d_log_runs_of_one():
+    # h/eps = 100 along the first axis: runs of one entry there (binary64),
+    # against the oracle on a grid whose columns span several wavefronts
+    fs1 = _fs1()
+    n1, n2, h1, h2, eps = 700, 4, 0.1, 0.02, 0.001
+    mu, nu = inputs.paper_uniform_2d(n1, n2, 8)
+    ref = oracle.fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=0.0, itr_max=10)
+    for dt in ("f64", "f32"):
+        r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=10,
+                             domain="log", dtype=dt)
+        assert r.status == 0 and r.iterations == 10
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-10 if dt == "f64" else 1e-5)
