@@ -518,28 +518,31 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
                 log(f"{name} n={n} {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
                     f"(paper's FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
     # Sec. 5.3: uniform random marginals on N x N grids, h1 = h2 = 1, eps = 0.01,
-    # 1000 iterations, Algorithm 2 (plain binary64)
-    for n in (10, 20, 40, 80, 160):
-        u, v = inputs.paper_uniform_2d(n, n, 0)
-        mu = torch.tensor(u, dtype=torch.float64, device="cuda")
-        nu = torch.tensor(v, dtype=torch.float64, device="cuda")
-        best, r = None, None
-        for rep in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = fs1.fs1_solve_2d(mu, nu, n, n, 1.0, 1.0, 0.01, 0.0, itr_max=1000, sync_every=64,
-                                 ctx=ctx)
-            torch.cuda.synchronize()
-            w = time.perf_counter() - t0
-            if rep > 0:
-                best = w if best is None else min(best, w)
-        pf, pd = PAPER_TIMES["table3"][n]
-        rows.append({"workload": "table3", "n": f"{n}x{n}", "eps": 0.01, "iterations": r.iterations,
-                     "domain": "plain", "status": r.status, "w1": r.w1,
-                     "marginal_err": r.marginal_err, "gpu_s": best, "paper_fs1_cpu_s": pf,
-                     "paper_dense_cpu_s": pd, "speedup_vs_paper_fs1": pf / best})
-        log(f"table3 {n}x{n}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
-            f"(paper's 2-D FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
+    # 1000 iterations, Algorithm 2 (binary64; plain as the paper runs it, and its
+    # stabilised log-domain form)
+    for domain in ("plain", "log"):
+        for n in (10, 20, 40, 80, 160):
+            u, v = inputs.paper_uniform_2d(n, n, 0)
+            mu = torch.tensor(u, dtype=torch.float64, device="cuda")
+            nu = torch.tensor(v, dtype=torch.float64, device="cuda")
+            best, r = None, None
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fs1.fs1_solve_2d(mu, nu, n, n, 1.0, 1.0, 0.01, 0.0, itr_max=1000,
+                                     sync_every=64, ctx=ctx, domain=domain)
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+                if rep > 0:
+                    best = w if best is None else min(best, w)
+            pf, pd = PAPER_TIMES["table3"][n]
+            rows.append({"workload": "table3", "n": f"{n}x{n}", "eps": 0.01,
+                         "iterations": r.iterations, "domain": domain, "status": r.status,
+                         "w1": r.w1, "marginal_err": r.marginal_err, "gpu_s": best,
+                         "paper_fs1_cpu_s": pf, "paper_dense_cpu_s": pd,
+                         "speedup_vs_paper_fs1": pf / best})
+            log(f"table3 {n}x{n} {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
+                f"(paper's 2-D FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
     return {"rows": rows,
             "note": "paper times: FS-1 and dense Sinkhorn on the paper's CPU (one Intel Xeon "
                     "Gold 5117, 2.0 GHz, 14 cores; context, not a target); GPU: one MI355X, "
