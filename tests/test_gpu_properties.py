@@ -95,3 +95,37 @@ def test_log_solve_property(n, le, seed, its, f32, solver):
     m, v = mu > 0, nu > 0
     assert np.max(np.abs(F[m] - ref.a[m])) <= 1e-9
     assert np.max(np.abs(G[v] - ref.b[v])) <= 1e-9
+
+
+@settings(max_examples=12, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(sizes=st.lists(st.integers(min_value=1, max_value=6000), min_size=1, max_size=6),
+       les=st.lists(st.floats(min_value=math.log(1e-3), max_value=math.log(0.1)), min_size=6,
+                    max_size=6),
+       seed=st.integers(min_value=0, max_value=99999), its=st.integers(min_value=1, max_value=30),
+       f32=st.booleans())
+def test_batched_property(sizes, les, seed, its, f32):
+    # a random ragged batch at a fixed iteration count: every instance against
+    # the log-domain oracle (sequential for n > 600, dense below)
+    fs1 = _fs1()
+    B = len(sizes)
+    eps = [math.exp(v) for v in les[:B]]
+    _say(f"batched property sizes={sizes} its={its} f32={f32}")
+    pairs = [inputs.mixture_pair(n, 3, seed + 7 * i) if n > 2 else
+             (np.full(n, 1.0 / n), np.full(n, 1.0 / n)) for i, n in enumerate(sizes)]
+    offs = np.zeros(B + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    mu = np.concatenate([m for m, _ in pairs])
+    nu = np.concatenate([v for _, v in pairs])
+    res = fs1.fs1_solve_batched(dev(mu), dev(nu), offs, eps, [0.0] * B, itr_max=its,
+                                dtype="f32" if f32 else "f64")
+    for (m, v), e, r in zip(pairs, eps, res):
+        n = len(m)
+        ref = (oracle.fs1_log if n > 600 else oracle.sinkhorn_log_dense)(
+            m, v, 1.0 / n, e, tol=0.0, itr_max=its)
+        assert r.status == 0
+        if r.iterations != ref.iterations:
+            # the error reached exactly 0 on one side (rounding level)
+            assert max(r.marginal_err, ref.marginal_err) <= (1e-6 if f32 else 1e-15)
+            continue
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-5 if f32 else 1e-10, abs=1e-300)
