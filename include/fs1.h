@@ -168,6 +168,7 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 #define FS1_FLAG_PERSISTENT 4
 #define FS1_FLAG_NO_GRAPH 8
 #define FS1_FLAG_NO_RESIDENT 16
+#define FS1_FLAG_DEVICE_PARAMS 32
 
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
@@ -195,7 +196,9 @@ typedef struct {
                              single-launch persistent solver when the grid fits
                              in the registers of the co-resident workgroups;
                              bit 4 (FS1_FLAG_NO_RESIDENT) skips the one-workgroup
-                             solver                                               */
+                             solver; bit 5 (FS1_FLAG_DEVICE_PARAMS): the eps and tol
+                             arrays of fs1_solve_batched(_config) are device
+                             memory (copied to the host before any launch)         */
     double *potentials_out; /* device, 2n doubles: F = ln phi (n), then G = ln psi
                              (n), written when flags bit 0 is set; -inf where the
                              scaling is zero                                        */

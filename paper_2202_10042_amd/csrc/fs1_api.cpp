@@ -198,6 +198,24 @@ int kv_common(fs1_ctx* ctx, const void* x, void* y, int64_t n, double h, double 
   return FS1_OK;
 }
 
+// FS1_FLAG_DEVICE_PARAMS: the per-instance eps and tol live in device memory;
+// copy them to host vectors and point *eps, *tol there.
+int host_params(fs1_ctx* ctx, const fs1_opts* opts, int32_t B, const double** eps,
+                const double** tol, std::vector<double>& he, std::vector<double>& ht) {
+  if (!ctx || !opts || !(opts->flags & FS1_FLAG_DEVICE_PARAMS) || B <= 0) return FS1_OK;
+  if (!*eps || !*tol) return set_err(FS1_ERR_INVALID_ARG, "bad batch arguments");
+  he.resize(size_t(B));
+  ht.resize(size_t(B));
+  HIP_TRY(hipMemcpyAsync(he.data(), *eps, size_t(B) * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ht.data(), *tol, size_t(B) * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  *eps = he.data();
+  *tol = ht.data();
+  return FS1_OK;
+}
+
 // Ragged batch in the log domain: every instance keeps its own lambda, run
 // length, stopping test and iteration count; all of them advance in the same
 // launches (fs1_batch.hip).
@@ -1031,6 +1049,9 @@ int fs1_solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, i
 int fs1_solve_batched(fs1_ctx* ctx, const double* mu_packed, const double* nu_packed,
                       const int64_t* offsets, int32_t B, const double* eps, const double* tol,
                       const fs1_opts* opts, fs1_result* out) {
+  std::vector<double> he, ht;
+  const int st = host_params(ctx, opts, B, &eps, &tol, he, ht);
+  if (st) return st;
   return batched_entry(ctx, mu_packed, nu_packed, offsets, B, eps, tol, opts, out, nullptr);
 }
 
@@ -1039,6 +1060,9 @@ int fs1_solve_batched_config(fs1_ctx* ctx, const double* mu_packed, const double
                              const double* tol, const fs1_opts* opts, const int32_t* run_length,
                              const int32_t* threads, fs1_result* out) {
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
+  std::vector<double> he, ht;
+  const int pst = host_params(ctx, opts, B, &eps, &tol, he, ht);
+  if (pst) return pst;
   const int dt = opts ? opts->dtype : FS1_F64;
   if (opts && opts->domain != FS1_LOG)
     return set_err(FS1_ERR_INVALID_ARG, "a forced configuration needs the log domain");

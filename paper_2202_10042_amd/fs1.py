@@ -37,6 +37,7 @@ FS1_FLAG_GENERAL = 2
 FS1_FLAG_PERSISTENT = 4
 FS1_FLAG_NO_GRAPH = 8
 FS1_FLAG_NO_RESIDENT = 16
+FS1_FLAG_DEVICE_PARAMS = 32
 
 # every symbol include/fs1.h declares
 EXPORTS = (
@@ -170,8 +171,8 @@ def load(path: str = LIB_PATH):
     lib.fs1_opts_default.restype = ctypes.c_int
     lib.fs1_solve.argtypes = [vp, vp, vp, i64, d, d, ctypes.POINTER(Opts), ctypes.POINTER(CResult)]
     lib.fs1_solve.restype = ctypes.c_int
-    lib.fs1_solve_batched.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32,
-                                      ctypes.POINTER(d), ctypes.POINTER(d),
+    # eps and tol: host arrays, or device memory with FS1_FLAG_DEVICE_PARAMS
+    lib.fs1_solve_batched.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32, vp, vp,
                                       ctypes.POINTER(Opts), ctypes.POINTER(CResult)]
     lib.fs1_solve_batched.restype = ctypes.c_int
     lib.fs1_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
@@ -193,8 +194,7 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
-    lib.fs1_solve_batched_config.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32,
-                                             ctypes.POINTER(d), ctypes.POINTER(d),
+    lib.fs1_solve_batched_config.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32, vp, vp,
                                              ctypes.POINTER(Opts), ctypes.POINTER(i32),
                                              ctypes.POINTER(i32), ctypes.POINTER(CResult)]
     lib.fs1_solve_batched_config.restype = ctypes.c_int
@@ -557,9 +557,22 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
     if B > 0 and (int(offsets[-1]) > mu_packed.numel() or int(offsets[-1]) > nu_packed.numel()):
         raise ValueError("offsets run past the packed marginals")
     offs = (ctypes.c_int64 * (B + 1))(*[int(v) for v in offsets])
-    e = (ctypes.c_double * max(B, 1))(*[float(v) for v in eps])
-    t = (ctypes.c_double * max(B, 1))(*[float(v) for v in tol])
     o = make_opts(None, itr_max, dtype, domain, check_every, sync_every)
+    on_device = [getattr(v, "is_cuda", False) for v in (eps, tol)]
+    if any(on_device):
+        # device tensors of eps and tol: passed as they are (FS1_FLAG_DEVICE_PARAMS)
+        if not all(on_device):
+            raise ValueError("eps and tol must both be device tensors or both host sequences")
+        import torch
+        if eps.dtype != torch.float64 or tol.dtype != torch.float64:
+            raise TypeError("device eps and tol must be float64")
+        if eps.numel() != B or tol.numel() != B:
+            raise ValueError("eps and tol need one entry per instance")
+        e, t = _dev(eps, "eps"), _dev(tol, "tol")
+        o.flags |= FS1_FLAG_DEVICE_PARAMS
+    else:
+        e = (ctypes.c_double * max(B, 1))(*[float(v) for v in eps])
+        t = (ctypes.c_double * max(B, 1))(*[float(v) for v in tol])
     if not graph:
         o.flags |= FS1_FLAG_NO_GRAPH
     res = (CResult * max(B, 1))()

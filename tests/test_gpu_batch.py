@@ -294,3 +294,21 @@ def test_batched_forced_configurations(dtype):
         fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=(3, 0))
     with pytest.raises(RuntimeError):  # the largest instance does not fit one workgroup
         fs1.fs1_solve_batched(*args, itr_max=60, dtype=dtype, config=(8, 256))
+
+
+def test_batched_device_eps_and_tol():
+    # FS1_FLAG_DEVICE_PARAMS: eps and tol handed over as device arrays give the
+    # results of the host arrays bit for bit
+    fs1 = _fs1()
+    spec = inputs.batch_spec(9, 128, 9000, [1e-2, 3e-3], seed=17)
+    mu, nu, offs = inputs.batch_hists(spec)
+    tol = [1e-6] * 9
+    _say("batched device eps/tol")
+    host = fs1.fs1_solve_batched(dev(mu), dev(nu), offs, spec.eps, tol, itr_max=400,
+                                 dtype="f32")
+    on_dev = fs1.fs1_solve_batched(dev(mu), dev(nu), offs, dev(spec.eps), dev(tol),
+                                   itr_max=400, dtype="f32")
+    for a, b in zip(host, on_dev):
+        assert _same(a, b), (a, b)
+    with pytest.raises(ValueError):
+        fs1.fs1_solve_batched(dev(mu), dev(nu), offs, dev(spec.eps), tol, itr_max=10)
