@@ -202,6 +202,10 @@ hipError_t launch_fused_half(const SolveBufs& b, const ScanConsts& k, int l, int
 // The solve's chunk-carry launches (fs1_kernels.hip): mode 1 for a psi-half
 // (returns at once when the solve has stopped), mode 2 for a phi-half (closes
 // the stopping test of iteration l first).
+// k_carry_groups alone (two-level carries; the chunk kernel does the rest).
+hipError_t launch_carry_groups(int mode, const ChunkAgg* agg, ChunkAgg* carry,
+                               const CarryConsts& kc, Ctrl* ctrl, const double* part, int check,
+                               hipStream_t s);
 hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
                               const CarryConsts& kc, Ctrl* ctrl, const double* part,
                               double* err_hist, int l, int check, double tol, hipStream_t s);

@@ -360,6 +360,24 @@ hipError_t launch_carry(const ChunkAgg* agg, ChunkAgg* carry, const CarryConsts&
   return hipGetLastError();
 }
 
+// The first level of the two-level carries alone (the chunk kernel folds the
+// groups' aggregates and takes the stopping decision itself).
+hipError_t launch_carry_groups(int mode, const ChunkAgg* agg, ChunkAgg* carry,
+                               const CarryConsts& kc, Ctrl* ctrl, const double* part, int check,
+                               hipStream_t s) {
+  if (!kc.two_level) return hipErrorInvalidValue;
+  const int64_t ng = carry_groups(kc.nchunks);
+  ChunkAgg* gagg = carry + kc.nchunks;
+  double* gpart = reinterpret_cast<double*>(gagg + 2 * ng);
+  if (mode == 1)
+    k_carry_groups<1><<<unsigned(ng), kCarryBlock, 0, s>>>(agg, carry, gagg, gpart, kc, ctrl,
+                                                          part, check);
+  else
+    k_carry_groups<2><<<unsigned(ng), kCarryBlock, 0, s>>>(agg, carry, gagg, gpart, kc, ctrl,
+                                                          part, check);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_carry(int mode, const ChunkAgg* agg, ChunkAgg* carry,
                               const CarryConsts& kc, Ctrl* ctrl, const double* part,
                               double* err_hist, int l, int check, double tol, hipStream_t s) {

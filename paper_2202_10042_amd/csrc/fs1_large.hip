@@ -5,8 +5,13 @@
 // the old psi), write the new vector.  k_large does the whole half in one
 // pass over the chunk, on the chunk frame of fs1_frame.h (the in-chunk
 // recursions of Sec. 3, eq. (recursion), in plain arithmetic on one power of
-// two per chunk), with the chunk carries taken from the carry kernels'
-// output (the scan of the previous half's chunk aggregates):
+// two per chunk).  Its chunk carries come in two parts: those within its group
+// of 1024 chunks from k_carry_groups (the scan of the previous half's chunk
+// aggregates inside each group), and the groups' part, which every workgroup
+// folds itself from the groups' aggregates (a few dozen independent terms;
+// the phi-half of a checked iteration also sums the groups' error shares and
+// takes Algorithm 1's stop decision here, before any store), so no top-level
+// carry launch sits between the halves:
 //   * every vector of a chunk shares one exponent, so no per-run exponent is
 //     read or written (one pair of ints per chunk instead);
 //   * the producer of a vector records, beside that exponent, the largest
@@ -15,7 +20,8 @@
 //   * the update uses the refined reciprocal of fs1_frame.h;
 //   * the new vector's chunk aggregates, its frame and the stopping-test
 //     error share leave the chunk in one reduction at the end.
-// The stop flag is read first: a launch after the stop reads nothing else.
+// The stop and failure flags are read first: a launch after the stop reads
+// nothing else.
 // Vectors and marginals are in the tile layout of fs1_tile.h.
 #include "fs1_device.h"
 #include "fs1_frame.h"
@@ -37,15 +43,66 @@ struct LargeArgs {
   ChunkExp* xout;
   const void* vown;         // old psi (error term of checked psi-halves)
   const ChunkExp* xown;
-  const ChunkAgg* carry;    // chunk carries of vin (carry kernels)
+  const ChunkAgg* carry;    // carries of vin within each group of 1024 chunks
+  const ChunkAgg* gagg;     // the groups' aggregates (the same carry kernel)
+  const double* gpart;      // the groups' error shares (phi-half of a checked iteration)
   const void* lanetab;      // LaneDec<T>[64]: the lane-dependent decays
   ChunkAgg* A_out;          // chunk aggregates of vout
   double* part;             // per-chunk error shares
+  double* err_hist;
   Ctrl* ctrl;
+  double tol;
   int l;
   int check;
+  int ngroups;
   CarryFix cfix;
+  Decay gpow[10];           // lambda^(1024 C 2^s): moves between groups
 };
+
+// The carries of chunk b: its group's carries, folded here from the groups'
+// aggregates as independent terms (forward by wave 0, backward by wave 1,
+// into sg), and its carries within the group (from the carry kernel), to which
+// the group's are added moved to the chunk (after a barrier).
+__device__ __forceinline__ void group_fold(const LargeArgs& a, int b, XF64* sg) {
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = b / kCarryBlock;
+  if (w == 0) {
+    XF<double> acc = xzero<double>();
+    for (int i = lane; i < g; i += kWave) {
+      const XF64 v = a.gagg[i].f;
+      if (v.m != 0.0) acc = xnorm(xadd(acc, xmul(XF<double>{v.m, v.e}, pow_bits(g - 1 - i, a.gpow))));
+    }
+    acc = wave_xsum(acc);
+    if (lane == 0) sg[0] = to64(acc);
+  } else if (w == 1) {
+    XF<double> acc = xzero<double>();
+    for (int i = g + 1 + lane; i < a.ngroups; i += kWave) {
+      const XF64 v = a.gagg[i].b;
+      if (v.m != 0.0) acc = xnorm(xadd(acc, xmul(XF<double>{v.m, v.e}, pow_bits(i - g - 1, a.gpow))));
+    }
+    acc = wave_xsum(acc);
+    if (lane == 0) sg[1] = to64(acc);
+  }
+}
+
+__device__ __forceinline__ ChunkAgg chunk_carry_folded(const LargeArgs& a, int b, const ChunkAgg& lc,
+                                                       const XF64* sg) {
+  const int64_t g = b / kCarryBlock, j = b - g * kCarryBlock;
+  const int64_t gact = min(int64_t(kCarryBlock), a.cfix.nchunks - g * kCarryBlock);
+  XF<double> pf = {1.0, 0}, pb = {1.0, 0};
+#pragma unroll
+  for (int s = 0; s < 11; ++s) {
+    if ((j >> s) & 1) pf = {pf.m * a.cfix.cpow[s].m, pf.e + a.cfix.cpow[s].e};
+    if (((gact - 1 - j) >> s) & 1) pb = {pb.m * a.cfix.cpow[s].m, pb.e + a.cfix.cpow[s].e};
+  }
+  const XF<double> f = xadd(XF<double>{lc.f.m, lc.f.e}, xmul(XF<double>{sg[0].m, sg[0].e}, pf));
+  const XF<double> bk = xadd(XF<double>{lc.b.m, lc.b.e}, xmul(XF<double>{sg[1].m, sg[1].e}, pb));
+  ChunkAgg r;
+  r.f = to64(xnorm(f));
+  r.b = to64(xnorm(bk));
+  return r;
+}
 
 // The lane-dependent decays of FastDec (fs1_frame.h), formed once per solve.
 template <typename T>
@@ -82,9 +139,15 @@ __global__ __launch_bounds__(kBlock) void k_large(LargeArgs a, ScanConsts k) {
   __shared__ T pb[kNW];     // a wave may publish while another still reads sf, sb)
   __shared__ double sred[kNW];
   __shared__ int smax[kNW];
-  // written by the carry kernel of this half (stopping test met, or a failure
-  // seen) before this launch
+  __shared__ XF64 sg[2];      // the group's carries
+  __shared__ double serr;     // err(l) (phi-half of a checked iteration)
+  // stopped by an earlier launch (stopping test met, or a failure seen: the
+  // first launch after a failure records the stop)
   if (a.ctrl->done) return;
+  if (a.ctrl->fail) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->done = 1;
+    return;
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int b = blockIdx.x;
@@ -109,8 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_large(LargeArgs a, ScanConsts k) {
   } else {
     tile_load<T, R>(reinterpret_cast<const T*>(a.m32), run, lane, mg);
   }
-  const ChunkAgg cg = chunk_carry(a.carry, a.cfix, b);
+  const ChunkAgg lc = a.carry[b];
   const LaneDec<T> ld = static_cast<const LaneDec<T>*>(a.lanetab)[lane];
+  // the groups' part of the carries, and the stopping-test sum of the groups'
+  // error shares (every workgroup adds them in the same order)
+  group_fold(a, b, sg);
+  if (MODE == L_PHI && a.check && w == 2) {
+    double e = 0.0;
+    for (int i = lane; i < a.ngroups; i += kWave) e += a.gpart[i];
+    e = wave_sum(e);
+    if (lane == 0) serr = e;
+  }
 
   const LamC<T, MU> L = lamc_of<T, MU>(k);
   const FastDec<T> D = fast_dec_of<T>(k, ld);
@@ -129,6 +201,24 @@ __global__ __launch_bounds__(kBlock) void k_large(LargeArgs a, ScanConsts k) {
   if (lane == kWave - 1) sf[w] = f;
   if (lane == 0) sb[w] = g;
   __syncthreads();
+
+  // Stop decision of Algorithm 1 for iteration l, taken before anything is
+  // stored: every workgroup has the same sum.
+  if (MODE == L_PHI && a.check) {
+    const double e = serr;
+    const bool stop = !(e > a.tol);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.ctrl->last_err = e;
+      a.ctrl->last_check = a.l;
+      if (a.err_hist) a.err_hist[a.l] = e;
+      if (stop) {
+        a.ctrl->stop_iter = a.l;
+        a.ctrl->done = 1;
+      }
+    }
+    if (stop) return;
+  }
+  const ChunkAgg cg = chunk_carry_folded(a, b, lc, sg);
 
   // output frame: the larger of the input frame and the carries' exponents
   int eap = zin ? kExpZero : xi.frame;
@@ -263,16 +353,24 @@ struct LargeOps {
     LargeArgs a{};
     a.cfix = carry_fix_of(kc);
     a.carry = b.carry;
+    a.ngroups = int((kc.nchunks + kCarryBlock - 1) / kCarryBlock);
+    a.gagg = b.carry + kc.nchunks;
+    a.gpart = reinterpret_cast<const double*>(b.carry + kc.nchunks + 2 * a.ngroups);
+    for (int s2 = 0; s2 < 10; ++s2)
+      a.gpow[s2] = make_decay(double(kCarryBlock) * double(kc.chunk_len) * double(1 << s2),
+                              k.c);
     a.lanetab = b.lanetab;
     a.part = b.part;
+    a.err_hist = b.err_hist;
+    a.tol = tol;
     a.ctrl = b.ctrl;
     a.l = l;
     a.check = check;
     const int cur = l & 1, nxt = (l + 1) & 1;
     hipError_t e;
     if (psi) {
-      // carries of phi^l (skipped once stopped)
-      e = launch_solve_carry(1, b.aggF, b.carry, kc, b.ctrl, nullptr, nullptr, l, 0, tol, s);
+      // carries of phi^l within the groups (skipped once stopped)
+      e = launch_carry_groups(1, b.aggF, b.carry, kc, b.ctrl, nullptr, 0, s);
       a.vin = b.vF;
       a.xin = b.xF;
       a.m64 = b.nu;
@@ -283,9 +381,9 @@ struct LargeOps {
       a.xown = b.xG[cur];
       a.A_out = b.aggG;
     } else {
-      // closes the stopping test of iteration l, then the carries of psi^{l+1}
-      e = launch_solve_carry(2, b.aggG, b.carry, kc, b.ctrl, b.part, b.err_hist, l, check, tol,
-                             s);
+      // the groups' shares of the stopping error of iteration l, and the
+      // carries of psi^{l+1} within the groups; k_large takes the decision
+      e = launch_carry_groups(2, b.aggG, b.carry, kc, b.ctrl, b.part, check, s);
       a.vin = b.vG[nxt];
       a.xin = b.xG[nxt];
       a.m64 = b.mu;

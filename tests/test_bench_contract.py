@@ -49,3 +49,14 @@ def test_algorithmic_bytes_per_point():
     assert bench.ALG_BYTES_PER_POINT["f64"] == 28
     # binary32: psi-half 4 + 4 + 4 + 4 + 8 (binary64 nu for the error), phi-half 12
     assert bench.ALG_BYTES_PER_POINT["f32"] == 18
+
+
+def test_source_hash_ignores_comments_only():
+    # a counter record stays valid across comment edits, not across code edits
+    a = "int f(int x) { // twice\n  return 2 * x; /* doubled */ }\n"
+    b = "// a new header comment\nint f(int x) {\n  return 2 * x;  // still doubled\n}\n"
+    c = "int f(int x) { return 3 * x; }\n"
+    d = 'const char* s = "// not a comment"; int g;'
+    assert bench.code_text(a) == bench.code_text(b)
+    assert bench.code_text(a) != bench.code_text(c)
+    assert "// not a comment" in bench.code_text(d)
