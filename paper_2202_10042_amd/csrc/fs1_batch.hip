@@ -70,6 +70,49 @@ __device__ __forceinline__ void inst_carries(const ChunkAgg* A, int j, int nch, 
   __syncthreads();
 }
 
+// Chunk carries of chunk b of an instance from the prefetched aggregates of
+// its other chunks (carry_prefetch; threads 0..127 forward, 128..255
+// backward): each thread folds its segment in extended range as carry_finish
+// does, then each wavefront aligns its lanes' partial sums to their largest
+// exponent (an integer maximum) and adds them in binary64 in a fixed tree;
+// a wavefront without a term skips that.  Forward carry into scar[0] (waves 0
+// and 1), backward into scar[1] (waves 2 and 3).
+template <int CMAX>
+__device__ __forceinline__ void bcarry_finish(const CarryItems<CMAX>& it, int b,
+                                              const Decay* cpow, XF64* red4, XF64* scar) {
+  const bool fwd = threadIdx.x < kBlock / 2;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const XF<double> cd = {cpow[0].m, cpow[0].e};
+  XF<double> acc = xzero<double>();
+  if (it.lo < it.hi) {
+    if (fwd) {
+#pragma unroll
+      for (int i = 0; i < CMAX; ++i)
+        if (it.lo + i < it.hi) acc = xnorm(xadd(xmul(acc, cd), XF<double>{it.m[i], it.e[i]}));
+      acc = xmul(acc, pow_bits(b - it.hi, cpow));  // end of chunk hi-1 -> end of chunk b-1
+    } else {
+#pragma unroll
+      for (int i = CMAX - 1; i >= 0; --i)
+        if (it.lo + i < it.hi) acc = xnorm(xadd(xmul(acc, cd), XF<double>{it.m[i], it.e[i]}));
+      acc = xmul(acc, pow_bits(it.lo - (b + 1), cpow));  // start of lo -> start of b+1
+    }
+  }
+  const bool has = acc.m != 0.0;
+  XF64 tot{0.0, kExpZero, 0};
+  if (__ballot(has) != 0) {
+    const int emax = wave_max(has ? acc.e : kExpZero);
+    tot = XF64{wave_sum(has ? ldexp(acc.m, acc.e - emax) : 0.0), emax, 0};
+  }
+  if (lane == 0) red4[w] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scar[0] = to64(xnorm(xadd(XF<double>{red4[0].m, red4[0].e}, XF<double>{red4[1].m, red4[1].e})));
+    scar[1] = to64(xnorm(xadd(XF<double>{red4[2].m, red4[2].e}, XF<double>{red4[3].m, red4[3].e})));
+  }
+  __syncthreads();
+}
+
 struct BArgs {
   const InstInfo* inst;
   InstState* st;
@@ -194,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
 
   // chunk carries first: they need only the aggregates
   if (pre) {
-    carry_finish<kCarryItems>(items, r.j, in.cpow, red4, scar);
+    bcarry_finish<kCarryItems>(items, r.j, in.cpow, red4, scar);
   } else {
     inst_carries(a.A_in + r.chunk0, r.j, r.nch, in.cpow, scar);
   }
