@@ -312,3 +312,25 @@ def test_batched_device_eps_and_tol():
         assert _same(a, b), (a, b)
     with pytest.raises(ValueError):
         fs1.fs1_solve_batched(dev(mu), dev(nu), offs, dev(spec.eps), tol, itr_max=10)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batched_instance_beyond_prefetch_carries(dtype):
+    # an instance of more than 1024 chunks (runs of 8 in binary64: 2048 entries
+    # per chunk; runs of 16 in binary32: 4096) takes its carries from the
+    # instance's aggregates by the whole-wavefront sums, beside a small one
+    fs1 = _fs1()
+    n_big = 2_500_000 if dtype == "f64" else 4_300_000
+    m1, v1 = inputs.mixture_pair(n_big, 4, 31)
+    m2, v2 = inputs.mixture_pair(3000, 3, 32)
+    mu, nu, offs = _pack([(m1, v1), (m2, v2)])
+    eps = [1e-3, 1e-2]
+    its = 6
+    _say(f"batched large instance {dtype} n={n_big}")
+    res = fs1.fs1_solve_batched(dev(mu), dev(nu), offs, eps, [0.0, 0.0], itr_max=its,
+                                dtype=dtype)
+    for (m, v), e, r in zip([(m1, v1), (m2, v2)], eps, res):
+        ref = oracle.fs1_log(m, v, 1.0 / len(m), e, tol=0.0, itr_max=its)
+        assert r.status == 0 and r.iterations == its
+        assert r.w1 == pytest.approx(ref.w1, rel=1e-9 if dtype == "f64" else 1e-5)
+        assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-5 if dtype == "f64" else 1e-3)
