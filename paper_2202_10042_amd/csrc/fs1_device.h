@@ -346,6 +346,39 @@ __device__ __forceinline__ void block_scan(S tf, S tb, const Dec<T>* dec, const 
   incb = incb.add(incb.template move<kDppRowShl + 8>().shift(dec[3]));
   incf = incf.norm();
   incb = incb.norm();
+  if (!cf && agg_f) {
+    // totals only: the wavefront's forward total is its last lane's value
+    // after the cross-row step below and the backward total its first lane's,
+    // formed here directly by the same operations in the same order (the
+    // lane power there is lambda^(16 R) = dec[4] for both), without the
+    // per-lane step that only the prefixes need
+    const S p15 = incf.lane(15);
+    const S p31 = incf.lane(31).add(p15.shift(dec[4])).norm();
+    const S p47 = incf.lane(47).add(p31.shift(dec[4])).norm();
+    const S wf = incf.lane(kWave - 1).add(p47.shift(dec[4])).norm();
+    const S s48 = incb.lane(48);
+    const S s32 = incb.lane(32).add(s48.shift(dec[4])).norm();
+    const S s16 = incb.lane(16).add(s32.shift(dec[4])).norm();
+    const S wb = incb.lane(0).add(s16.shift(dec[4])).norm();
+    if constexpr (NW == 1) {
+      *agg_f = wf.norm();
+      *agg_b = wb.norm();
+      return;
+    }
+    if (lane == 0) {
+      sh.f[w] = wf;
+      sh.b[w] = wb;
+    }
+    __syncthreads();
+    S af = S::zero();
+    S ab = S::zero();
+    for (int v = 0; v < NW; ++v) af = af.shift(dec[6]).add(sh.f[v]);
+    for (int v = NW - 1; v >= 0; --v) ab = ab.shift(dec[6]).add(sh.b[v]);
+    *agg_f = af.norm();
+    *agg_b = ab.norm();
+    __syncthreads();
+    return;
+  }
   // across rows: the rows before (after) a row enter through the last (first)
   // lane of its neighbour row, read once per wavefront
   const int row = lane >> 4;
