@@ -271,15 +271,34 @@ __global__ void k_zero_int(int* a, int64_t n) {
 // Small grids (n1 n2 <= 4096, short lines): the whole of Algorithm 2 in one
 // workgroup of NT threads (the fewest of 64, 256, 1024 that hold the grid at 4
 // entries each).  Thread t keeps the entries t + NT r (r < 4) of phi, psi, mu
-// and nu in registers; a product K v goes through two LDS arrays, one pass per
-// axis, each line run by one thread with the paper's sequential recursions
-// (Sec. 3: p_k = lambda p_{k-1} + x_k, q_k = lambda (q_{k+1} + x_{k+1})), so
-// the arithmetic is the sequential algorithm's, line by line.
+// and nu in registers; a product K v goes through three LDS arrays (columns
+// padded to an odd length), one pass per axis, with the paper's sequential
+// recursions along each line (Sec. 3: p_k = lambda p_{k-1} + x_k and the
+// backward sum), the two directions of a line run side by side by two
+// threads, so the arithmetic is the sequential algorithm's, line by line.
+//
+// SC (the log domain): every scaling entry, and every entry of a product, is
+// an extended number (mantissa, int32 exponent), in registers and in two more
+// LDS arrays of exponents, and the recursions run in extended arithmetic entry
+// by entry with lambda itself extended, so nothing underflows however large
+// h/eps is; the update normalises each new scaling entry as the per-line
+// passes do.
 // ---------------------------------------------------------------------------
 constexpr int kRes2MaxThreads = 1024;
 constexpr int kRes2Per = 4;  // entries per thread: n1 n2 <= 4 x threads (64, 256 or 1024)
 
-constexpr int64_t kRes2MaxSpan = 128;  // n1 + n2
+// Largest n1 + n2 for the one-workgroup solver (an iteration walks both line
+// lengths sequentially, while the per-line launches take about 20 us (log
+// domain) to 25 us (plain) an iteration at any of these sizes), measured on
+// square and elongated grids at h/eps = 100: plain up to 16 x 256 wins, 8 x
+// 500 loses; in the log domain the extended recursions cost more per entry
+// (binary64 at 1024 threads runs groups of two to stay in registers).
+constexpr int64_t kRes2MaxSpan = 384;       // plain domain
+constexpr int64_t kRes2MaxSpanLog64 = 80;   // log domain, binary64
+constexpr int64_t kRes2MaxSpanLog32 = 128;  // log domain, binary32
+
+// LDS distance between columns: n1 made odd
+__host__ __device__ inline int res2d_ld(int n1) { return n1 | 1; }
 
 struct Res2Args {
   const double* mu;
@@ -288,6 +307,8 @@ struct Res2Args {
   const float* nu32;
   void* vF;      // in: initial phi; out: final phi
   void* vG;      // in: initial psi; out: final psi
+  int* eF;       // log domain: exponents of vF and vG (in and out)
+  int* eG;
   Ctrl* ctrl;
   double* err_hist;
   int n1, n2;
@@ -295,80 +316,139 @@ struct Res2Args {
   int check_every;
   double tol;
   double lam1, lam2;
+  Decay xlam1, xlam2;  // log domain: lambda1, lambda2 as extended numbers
 };
 
-// one line of `len` entries at X[base + k stride]: Y = (forward + backward)
-// recursions, taken a group of entries at a time (16 binary32 / 8 binary64:
-// what the registers hold beside the state): a whole group's LDS loads are
-// issued together, unconditionally, ahead of its dependent chain, and the
-// entries past the last whole group follow one at a time
+// An LDS entry as an extended number: a zero mantissa takes the exponent of
+// zero, so that it never sets the exponent of a sum.
 template <typename T>
-__device__ __forceinline__ void seq_line(const T* X, T* Y, int base, int stride, int len, T lam) {
-  constexpr int G = sizeof(T) == 8 ? 8 : 16;
+__device__ __forceinline__ XF<T> xentry(T m, int e) {
+  return {m, m == T(0) ? kExpZero : e};
+}
+
+// One direction of a line's recursion, r_k = lambda r_{k-1} + x_k over the
+// entries p0 + k step (k < len; step < 0 runs the line backwards), written to
+// O.  A group of G entries at a time: the group's LDS loads are issued
+// together, unconditionally, ahead of its dependent chain; the entries past
+// the last whole group follow one at a time.
+// SC: extended arithmetic, the exponents in XE / OE, lambda as xlam; the
+// running sum is normalised once per group (a step multiplies the mantissa by
+// lambda's, in [1, 2), and an addition at most doubles it, so G steps stay far
+// inside the range of T).
+template <typename T, int G, bool SC>
+__device__ __forceinline__ void seq_scan(const T* X, const int* XE, T* O, int* OE, int p0,
+                                         int step, int len, T lam, XF<T> xlam) {
   T r = T(0);
+  XF<T> xr = xzero<T>();
   int k = 0;
   for (; k + G <= len; k += G) {
     T v[G];
-#pragma unroll
-    for (int u = 0; u < G; ++u) v[u] = X[base + (k + u) * stride];
+    int ve[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-      r = lam * r + v[u];
-      v[u] = r;
+      v[u] = X[p0 + (k + u) * step];
+      if constexpr (SC) ve[u] = XE[p0 + (k + u) * step];
     }
 #pragma unroll
-    for (int u = 0; u < G; ++u) Y[base + (k + u) * stride] = v[u];
+    for (int u = 0; u < G; ++u) {
+      if constexpr (SC) {
+        xr = xadd(xmul(xr, xlam), xentry(v[u], ve[u]));
+        v[u] = xr.m;
+        ve[u] = xr.e;
+      } else {
+        r = lam * r + v[u];
+        v[u] = r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      O[p0 + (k + u) * step] = v[u];
+      if constexpr (SC) OE[p0 + (k + u) * step] = ve[u];
+    }
+    if constexpr (SC) xr = xnorm(xr);
   }
   for (; k < len; ++k) {
-    r = lam * r + X[base + k * stride];
-    Y[base + k * stride] = r;
-  }
-  // backward: Y_k += q_k with q_{len-1} = 0, q_k = lam (q_{k+1} + X_{k+1})
-  T q = T(0);
-  k = len - 1;
-  for (; k + 1 >= G; k -= G) {
-    T v[G], w[G];
-#pragma unroll
-    for (int u = 0; u < G; ++u) {
-      v[u] = X[base + (k - u) * stride];
-      w[u] = Y[base + (k - u) * stride];
+    const int q = p0 + k * step;
+    if constexpr (SC) {
+      xr = xadd(xmul(xr, xlam), xentry(X[q], XE[q]));
+      O[q] = xr.m;
+      OE[q] = xr.e;
+    } else {
+      r = lam * r + X[q];
+      O[q] = r;
     }
-#pragma unroll
-    for (int u = 0; u < G; ++u) {
-      w[u] += q;
-      q = lam * (q + v[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < G; ++u) Y[base + (k - u) * stride] = w[u];
-  }
-  for (; k >= 0; --k) {
-    Y[base + k * stride] += q;
-    q = lam * (q + X[base + k * stride]);
   }
 }
 
-// X <- K X (column-major n1 x n2 in LDS), through Y
-template <typename T, int NT>
-__device__ __forceinline__ void seq_kv2(T* X, T* Y, int n1, int n2, T lam1, T lam2) {
-  const int t = threadIdx.x;
-  __syncthreads();
-  for (int j = t; j < n2; j += NT) seq_line<T>(X, Y, j * n1, 1, n1, lam1);
-  __syncthreads();
-  for (int i = t; i < n1; i += NT) seq_line<T>(Y, X, i, n1, n2, lam2);
-  __syncthreads();
+// The 1-D product along the lines of one axis, from X into Y and Z: for each
+// line, one thread runs the forward recursion into Y and another the backward
+// one (inclusive, s_k = lambda s_{k+1} + x_k) into Z, side by side; the
+// product is then y_k = f_k + lambda s_{k+1} (Sec. 3: the backward sum of the
+// paper is lambda s_{k+1}).  nlines lines of len entries, line L at L lstep,
+// entries estep apart.
+template <typename T, int NT, int G, bool SC>
+__device__ __forceinline__ void seq_axis(const T* X, const int* XE, T* Y, int* YE, T* Z, int* ZE,
+                                         int nlines, int lstep, int len, int estep, T lam,
+                                         XF<T> xlam) {
+  for (int w = threadIdx.x; w < 2 * nlines; w += NT) {
+    const bool fw = w < nlines;
+    const int L = fw ? w : w - nlines;
+    seq_scan<T, G, SC>(X, XE, fw ? Y : Z, fw ? YE : ZE, L * lstep + (fw ? 0 : (len - 1) * estep),
+                       fw ? estep : -estep, len, lam, xlam);
+  }
 }
 
-template <typename T, int NT>
+// y_k = f_k + lambda s_{k+1} at LDS position q (s_{k+1} at q + estep; none at
+// the line's last entry)
+template <typename T>
+__device__ __forceinline__ T seq_combine(const T* Y, const T* Z, int q, int estep, bool last,
+                                         T lam) {
+  return last ? Y[q] : Y[q] + lam * Z[q + estep];
+}
+
+template <typename T>
+__device__ __forceinline__ XF<T> seq_combine_x(const T* Y, const int* YE, const T* Z,
+                                               const int* ZE, int q, int estep, bool last,
+                                               XF<T> lam) {
+  const XF<T> f{Y[q], YE[q]};
+  return last ? f : xadd(f, xmul(XF<T>{Z[q + estep], ZE[q + estep]}, lam));
+}
+
+constexpr int GX64 = 2;  // group of the binary64 log-domain recursions at 1024 threads
+
+template <typename T, int NT, bool SC>
 __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   extern __shared__ __align__(16) unsigned char lds2[];
   __shared__ double red[NT / kWave];
   __shared__ int sstop;
   const int n = a.n1 * a.n2;
+  // columns ld = n1 | 1 entries apart in LDS: an odd stride spreads the
+  // lanes that walk different columns over the banks
+  const int ld = res2d_ld(a.n1);
+  const int nl = ld * a.n2;
   T* X = reinterpret_cast<T*>(lds2);
-  T* Y = X + n;
+  T* Y = X + nl;
+  T* Z = Y + nl;
+  int* XE = reinterpret_cast<int*>(Z + nl);  // log domain only
+  int* YE = XE + nl;
+  int* ZE = YE + nl;
   const int t = threadIdx.x;
+  // LDS position of the entries t + NT r, and whether each is the last of its
+  // column / of its row
+  int off[kRes2Per];
+  bool last1[kRes2Per], last2[kRes2Per];
+#pragma unroll
+  for (int r = 0; r < kRes2Per; ++r) {
+    const int e = t + NT * r;
+    const int i = e % a.n1, j = e / a.n1;
+    off[r] = i + ld * j;
+    last1[r] = i + 1 == a.n1;
+    last2[r] = j + 1 == a.n2;
+  }
   const T lam1 = T(a.lam1), lam2 = T(a.lam2);
+  const XF<T> xl1{T(a.xlam1.m), a.xlam1.e}, xl2{T(a.xlam2.m), a.xlam2.e};
   T ph[kRes2Per], ps[kRes2Per], mu[kRes2Per], nu[kRes2Per];
+  int phe[kRes2Per], pse[kRes2Per];  // log domain: exponents of ph, ps
   double nu64[kRes2Per];  // the stopping test's binary64 nu, kept in registers
 #pragma unroll
   for (int r = 0; r < kRes2Per; ++r) {
@@ -376,6 +456,8 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     const bool in = e < n;
     ph[r] = in ? static_cast<const T*>(a.vF)[e] : T(0);
     ps[r] = in ? static_cast<const T*>(a.vG)[e] : T(0);
+    phe[r] = (SC && in) ? a.eF[e] : 0;
+    pse[r] = (SC && in) ? a.eG[e] : 0;
     nu64[r] = in ? a.nu[e] : 0.0;
     if constexpr (sizeof(T) == 8) {
       mu[r] = in ? T(a.mu[e]) : T(0);
@@ -385,21 +467,95 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
       nu[r] = in ? T(a.nu32[e]) : T(0);
     }
   }
-  int l = 0, stop_iter = -1, fail_iter = -1;
-  for (; l < a.itr_max; ++l) {
-    // psi-half: K^T phi^l (K is symmetric)
+  // entries per group of the line recursions (binary64 in the log domain at
+  // 1024 threads: fewer, which keeps the kernel within its 128 registers per
+  // lane)
+  constexpr int G = !SC ? (sizeof(T) == 8 ? 8 : 16)
+                        : ((sizeof(T) == 8 && NT == kRes2MaxThreads) ? GX64 : 8);
+  // K v (v = ph or ps with its exponents) at this thread's entries into
+  // pm (and pe): the recursions along the columns (X -> Y, Z), their
+  // combination into X, the recursions along the rows (X -> Y, Z), and the
+  // combination of those at the thread's own entries
+  T pm[kRes2Per];
+  int pe[kRes2Per];
+  auto product = [&](const T* v, const int* ve) {
 #pragma unroll
     for (int r = 0; r < kRes2Per; ++r) {
       const int e = t + NT * r;
-      if (e < n) X[e] = ph[r];
+      if (e < n) {
+        X[off[r]] = v[r];
+        if constexpr (SC) XE[off[r]] = ve[r];
+      }
     }
-    seq_kv2<T, NT>(X, Y, a.n1, a.n2, lam1, lam2);
+    __syncthreads();
+    seq_axis<T, NT, G, SC>(X, XE, Y, YE, Z, ZE, a.n2, ld, a.n1, 1, lam1, xl1);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) {
+        if constexpr (SC) {
+          const XF<T> c = seq_combine_x(Y, YE, Z, ZE, off[r], 1, last1[r], xl1);
+          X[off[r]] = c.m;
+          XE[off[r]] = c.e;
+        } else {
+          X[off[r]] = seq_combine(Y, Z, off[r], 1, last1[r], lam1);
+        }
+      }
+    }
+    __syncthreads();
+    seq_axis<T, NT, G, SC>(X, XE, Y, YE, Z, ZE, a.n1, 1, a.n2, ld, lam2, xl2);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) {
+        if constexpr (SC) {
+          const XF<T> c = seq_combine_x(Y, YE, Z, ZE, off[r], ld, last2[r], xl2);
+          pm[r] = c.m;
+          pe[r] = c.e;
+        } else {
+          pm[r] = seq_combine(Y, Z, off[r], ld, last2[r], lam2);
+          pe[r] = 0;
+        }
+      }
+    }
+  };
+  // v <- marg / (K v'), entry by entry (normalised to its own exponent in
+  // the log domain); returns whether any entry is not finite
+  auto update = [&](T* v, int* ve, const T* marg) {
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kRes2Per; ++r) {
+      const int e = t + NT * r;
+      if (e < n) {
+        const T q = (marg[r] == T(0)) ? T(0) : marg[r] / pm[r];
+        bad |= !isfinite(q);
+        if constexpr (SC) {
+          int kq = 0;
+          v[r] = (q == T(0) || !isfinite(q)) ? q : frx(q, &kq);
+          ve[r] = (q == T(0)) ? 0 : kq - pe[r];
+        } else {
+          v[r] = q;
+        }
+      }
+    }
+    return bad;
+  };
+  int l = 0, stop_iter = -1, fail_iter = -1;
+  for (; l < a.itr_max; ++l) {
+    // psi-half: K^T phi^l (K is symmetric)
+    product(ph, phe);
     if ((l % a.check_every) == 0) {
       double s = 0.0;
 #pragma unroll
       for (int r = 0; r < kRes2Per; ++r) {
         const int e = t + NT * r;
-        if (e < n) s += fabs(double(ps[r]) * double(X[e]) - nu64[r]);
+        if (e < n) {
+          double pv = double(ps[r]) * double(pm[r]);
+          if constexpr (SC) pv = ldexp(pv, pse[r] + pe[r]);
+          s += fabs(pv - nu64[r]);
+        }
       }
       const double tot = block_sum<NT / kWave>(s, red);
       if (t == 0) {
@@ -414,31 +570,11 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
         break;
       }
     }
-    bool bad = false;
-#pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
-      const int e = t + NT * r;
-      if (e < n) {
-        ps[r] = (nu[r] == T(0)) ? T(0) : nu[r] / X[e];
-        bad |= !isfinite(ps[r]);
-      }
-    }
-    // phi-half: K psi^{l+1}
-    __syncthreads();  // every read of X above is done
-#pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
-      const int e = t + NT * r;
-      if (e < n) X[e] = ps[r];
-    }
-    seq_kv2<T, NT>(X, Y, a.n1, a.n2, lam1, lam2);
-#pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
-      const int e = t + NT * r;
-      if (e < n) {
-        ph[r] = (mu[r] == T(0)) ? T(0) : mu[r] / X[e];
-        bad |= !isfinite(ph[r]);
-      }
-    }
+    bool bad = update(ps, pse, nu);
+    // phi-half: K psi^{l+1} (its first LDS writes go to X, which no thread
+    // reads after the row recursions)
+    product(ps, pse);
+    bad |= update(ph, phe, mu);
     // a non-finite scaling in either half ends the solve (abnormal termination)
     if (__syncthreads_or(bad ? 1 : 0)) {
       fail_iter = l;
@@ -451,6 +587,10 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     if (e < n) {
       static_cast<T*>(a.vF)[e] = ph[r];
       static_cast<T*>(a.vG)[e] = ps[r];
+      if constexpr (SC) {
+        a.eF[e] = phe[r];
+        a.eG[e] = pse[r];
+      }
     }
   }
   if (t == 0) {
@@ -474,13 +614,18 @@ int res2d_threads(int64_t n) {
   return 0;
 }
 
-size_t res2d_lds(int64_t n1, int64_t n2, int dt) {
+size_t res2d_lds(int64_t n1, int64_t n2, int dt, bool log_domain) {
   const int64_t n = n1 * n2;
   if (res2d_threads(n) == 0) return 0;
   // an iteration walks both line lengths sequentially: beyond this the
   // per-line launches (fixed cost per pass) are faster
-  if (n1 + n2 > kRes2MaxSpan) return 0;
-  const size_t bytes = size_t(2 * n) * (dt == FS1_F64 ? 8 : 4);
+  const int64_t span = !log_domain ? kRes2MaxSpan
+                                   : (dt == FS1_F64 ? kRes2MaxSpanLog64 : kRes2MaxSpanLog32);
+  if (n1 + n2 > span) return 0;
+  // X, Y and Z (columns padded to an odd length), and in the log domain
+  // their exponents
+  const size_t bytes = size_t(3) * size_t(res2d_ld(int(n1))) * size_t(n2) *
+                       ((dt == FS1_F64 ? 8 : 4) + (log_domain ? 4 : 0));
   int dev = 0, lim = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -489,23 +634,23 @@ size_t res2d_lds(int64_t n1, int64_t n2, int dt) {
   return bytes + 1024 <= size_t(lim) ? bytes : 0;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool SC>
 hipError_t launch_res2d_t(const Res2Args& a, size_t lds, hipStream_t s) {
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_res2d<T, NT>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_res2d<T, NT, SC>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  k_res2d<T, NT><<<1, NT, lds, s>>>(a);
+  k_res2d<T, NT, SC><<<1, NT, lds, s>>>(a);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool SC>
 hipError_t launch_res2d(const Res2Args& a, size_t lds, hipStream_t s) {
   switch (res2d_threads(int64_t(a.n1) * a.n2)) {
-    case 64: return launch_res2d_t<T, 64>(a, lds, s);
-    case 256: return launch_res2d_t<T, 256>(a, lds, s);
-    case kRes2MaxThreads: return launch_res2d_t<T, kRes2MaxThreads>(a, lds, s);
+    case 64: return launch_res2d_t<T, 64, SC>(a, lds, s);
+    case 256: return launch_res2d_t<T, 256, SC>(a, lds, s);
+    case kRes2MaxThreads: return launch_res2d_t<T, kRes2MaxThreads, SC>(a, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -877,9 +1022,8 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   HIP_TRY(hipStreamSynchronize(s));
 
   const Grid2 g = make_grid2(n1, n2, h1, h2, eps, lg, dt);
-  // small grids (plain domain): every iteration in one workgroup; it leaves
-  // psi in buffer 0
-  const size_t lds = (lg || (o.flags & FS1_FLAG_NO_RESIDENT)) ? 0 : res2d_lds(n1, n2, dt);
+  // small grids: every iteration in one workgroup; it leaves psi in buffer 0
+  const size_t lds = (o.flags & FS1_FLAG_NO_RESIDENT) ? 0 : res2d_lds(n1, n2, dt, lg);
   bool resident = false;
   if (lds > 0) {
     Res2Args ra{};
@@ -889,6 +1033,8 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     ra.nu32 = b.nu32;
     ra.vF = b.vF;
     ra.vG = b.vG[0];
+    ra.eF = b.eF;
+    ra.eG = b.eG[0];
     ra.ctrl = b.ctrl;
     ra.err_hist = o.err_history;
     ra.n1 = int(n1);
@@ -898,8 +1044,16 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     ra.tol = tol;
     ra.lam1 = std::exp(-h1 / eps);
     ra.lam2 = std::exp(-h2 / eps);
-    const hipError_t e = dt == FS1_F64 ? launch_res2d<double>(ra, lds, s)
-                                       : launch_res2d<float>(ra, lds, s);
+    ra.xlam1 = make_decay(1.0, h1 / eps);
+    ra.xlam2 = make_decay(1.0, h2 / eps);
+    hipError_t e;
+    if (lg) {
+      e = dt == FS1_F64 ? launch_res2d<double, true>(ra, lds, s)
+                        : launch_res2d<float, true>(ra, lds, s);
+    } else {
+      e = dt == FS1_F64 ? launch_res2d<double, false>(ra, lds, s)
+                        : launch_res2d<float, false>(ra, lds, s);
+    }
     if (e != hipSuccess) return finish(hip_fail(e, "2-D one-workgroup solve"));
     resident = true;
   }

@@ -87,7 +87,8 @@ def _pot_close(got, ref_lin, mask, atol):
     assert np.max(np.abs(g - r)) <= atol, float(np.max(np.abs(g - r)))
 
 
-SOLVERS = ["auto", "lines"]  # one workgroup (n1 n2 <= 8192) / one launch per line pass
+# one workgroup (n1 n2 <= 4096 and a short enough n1 + n2) / one launch per line pass
+SOLVERS = ["auto", "lines"]
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -95,7 +96,7 @@ SOLVERS = ["auto", "lines"]  # one workgroup (n1 n2 <= 8192) / one launch per li
     (13, 7, 0.1, 0.15, 0.05, 30, True), (1, 40, 0.5, 0.02, 0.03, 25, True),
     (40, 1, 0.02, 0.5, 0.03, 25, True), (24, 31, 1.0 / 24, 1.0 / 31, 0.01, 60, True),
     (150, 90, 1.0 / 150, 1.0 / 90, 5e-3, 40, False), (300, 200, 0.003, 0.005, 0.01, 20, False),
-    (2100, 4, 5e-4, 0.3, 0.05, 10, False)])
+    (2100, 4, 5e-4, 0.3, 0.05, 10, False), (12, 300, 0.05, 0.003, 0.02, 15, False)])
 def test_solve_2d_fixed_iterations(n1, n2, h1, h2, eps, its, dense, solver):
     fs1 = _fs1()
     mu, nu = inputs.product_pair_2d(n1, n2, 3, n1 + n2)
@@ -266,15 +267,17 @@ def _log_ref(mu, nu, n1, n2, h1, h2, eps, its):
     (1, 1, 0.1, 0.1, 0.01, 3), (12, 5, 0.8, 0.3, 0.001, 40), (17, 23, 0.05, 0.03, 1e-3, 30),
     (64, 9, 1.0 / 64, 1.0 / 9, 2e-4, 25), (600, 3, 1.0 / 600, 0.1, 1e-3, 20),
     (3, 1500, 0.2, 1.0 / 1500, 5e-4, 12), (100, 77, 0.01, 0.013, 1e-3, 15),
-    (2500, 2, 1.0 / 2500, 0.1, 1e-3, 8)])
-def test_solve_2d_log_against_oracle(n1, n2, h1, h2, eps, its):
+    (2500, 2, 1.0 / 2500, 0.1, 1e-3, 8), (40, 40, 1.0, 1.0, 0.01, 30),
+    (64, 64, 1.0 / 64, 1.0 / 64, 1e-4, 12), (33, 95, 0.5, 0.25, 0.002, 10)])
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_log_against_oracle(n1, n2, h1, h2, eps, its, solver):
     fs1 = _fs1()
     mu, nu = inputs.paper_uniform_2d(n1, n2, n1 + 3 * n2)
-    _say(f"solve2 log {n1}x{n2} eps={eps} its={its}")
+    _say(f"solve2 log {n1}x{n2} eps={eps} its={its} {solver}")
     ref = _log_ref(mu, nu, n1, n2, h1, h2, eps, its)
     assert ref.status == 0
     r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its, domain="log",
-                         potentials=True)
+                         potentials=True, solver=solver)
     assert r.status == 0 and r.iterations == ref.iterations
     assert r.w1 == pytest.approx(ref.w1, rel=1e-10, abs=1e-300)
     assert r.marginal_err == pytest.approx(ref.marginal_err, rel=1e-6, abs=1e-12)
@@ -299,7 +302,8 @@ def test_solve_2d_log_equals_plain_where_plain_works():
         assert lg.marginal_err == pytest.approx(p.marginal_err, rel=1e-8)
 
 
-def test_solve_2d_log_small_eps_where_plain_fails():
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_log_small_eps_where_plain_fails(solver):
     # Dirac masses 6 and 4 cells apart along the axes at h/eps = 100 and 50:
     # the plain products underflow and the plain solve ends abnormally; the
     # log domain moves the mass exactly
@@ -313,24 +317,26 @@ def test_solve_2d_log_small_eps_where_plain_fails():
     assert p.status != 0
     for dt in ("f64", "f32"):
         r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=1,
-                             domain="log", dtype=dt)
+                             domain="log", dtype=dt, solver=solver)
         assert r.status == 0
         assert r.w1 == pytest.approx(6 * h1 + 4 * h2, rel=1e-12 if dt == "f64" else 1e-6)
 
 
-@pytest.mark.parametrize("n1,n2", [(30, 22), (150, 9)])
-def test_solve_2d_log_f32_against_f64_oracle(n1, n2):
+@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("n1,n2", [(30, 22), (150, 9), (64, 64), (40, 88)])
+def test_solve_2d_log_f32_against_f64_oracle(n1, n2, solver):
     fs1 = _fs1()
     h1, h2, eps = 1.0 / n1, 1.0 / n2, 5e-4
     mu, nu = inputs.paper_uniform_2d(n1, n2, 21)
     ref = _log_ref(mu, nu, n1, n2, h1, h2, eps, 20)
     r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=20, domain="log",
-                         dtype="f32")
+                         dtype="f32", solver=solver)
     assert r.status == 0 and r.iterations == 20
     assert r.w1 == pytest.approx(ref.w1, rel=1e-5)
 
 
-def test_solve_2d_log_product_marginals_and_tolerance():
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solve_2d_log_product_marginals_and_tolerance(solver):
     # product marginals: W_2D = W_1D(axis 1) + W_1D(axis 2) at every iteration
     # count; then the same grid to tolerance 1e-8 against the oracle's stop
     fs1 = _fs1()
@@ -344,11 +350,11 @@ def test_solve_2d_log_product_marginals_and_tolerance():
         w1 = oracle.fs1_log(m1, v1, h1, eps, tol=0.0, itr_max=its).w1
         w2 = oracle.fs1_log(m2, v2, h2, eps, tol=0.0, itr_max=its).w1
         r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 0.0, itr_max=its,
-                             domain="log")
+                             domain="log", solver=solver)
         assert r.status == 0 and r.w1 == pytest.approx(w1 + w2, rel=1e-10)
     ref = oracle.fs1_2d_log(mu, nu, n1, n2, h1, h2, eps, tol=1e-8, itr_max=3000)
     r = fs1.fs1_solve_2d(dev(mu), dev(nu), n1, n2, h1, h2, eps, 1e-8, itr_max=3000,
-                         domain="log")
+                         domain="log", solver=solver)
     assert ref.converged and r.converged and r.marginal_err <= 1e-8
     assert abs(r.iterations - ref.iterations) <= 1
     assert r.w1 == pytest.approx(ref.w1, rel=1e-8)
