@@ -26,6 +26,10 @@ What each routine follows in the paper:
   (entry (i, j) at i + n1 j): K dense from its definition, or Algorithm 2 (the
   1-D recursions along the first axis, then eq. (2d recursion) across columns);
   the cost as the literal double sum or split along the two axes.
+* ``kvn_*``, ``sinkhornn_*``, ``fs1_nd*``, ``costn_*``, ``marginal_errn_*``: the
+  same on D axes (first axis fastest; Sec. 4 says the construction extends to
+  higher dimensions without writing it out): K = K_{D-1} (x) ... (x) K_0 by the
+  1-D recursions along each axis in turn, the cost split into one term per axis.
 
 Pins: every routine is checked in ``tests/test_oracle_pins.py`` against facts the
 paper or the mathematics fixes (closed form of K 1 from the stability analysis of
@@ -109,6 +113,22 @@ def _load():
         "or_cost2_fs1_log": (d, [i64, i64, p, p, d, d, d]),
         "or_sinkhorn2_log_dense": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
         "or_fs1_2d_log": (ctypes.c_int, [i64, i64, p, p, d, d, d, d, i64, p, p, p]),
+        "or_kvn_dense": (ctypes.c_int, [ctypes.c_int, p, p, p, d, p]),
+        "or_kvn_fs1": (ctypes.c_int, [ctypes.c_int, p, p, p, d, p]),
+        "or_kvn_log_dense": (ctypes.c_int, [ctypes.c_int, p, p, p, d, p]),
+        "or_kvn_fs1_log": (ctypes.c_int, [ctypes.c_int, p, p, p, d, p]),
+        "or_marginal_errn_dense": (d, [ctypes.c_int, p, p, p, p, p, d]),
+        "or_marginal_errn_fs1": (d, [ctypes.c_int, p, p, p, p, p, d]),
+        "or_marginal_errn_log_dense": (d, [ctypes.c_int, p, p, p, p, p, d]),
+        "or_marginal_errn_fs1_log": (d, [ctypes.c_int, p, p, p, p, p, d]),
+        "or_costn_dense": (d, [ctypes.c_int, p, p, p, p, d]),
+        "or_costn_fs1": (d, [ctypes.c_int, p, p, p, p, d]),
+        "or_costn_log_dense": (d, [ctypes.c_int, p, p, p, p, d]),
+        "or_costn_fs1_log": (d, [ctypes.c_int, p, p, p, p, d]),
+        "or_sinkhornn_dense": (ctypes.c_int, [ctypes.c_int, p, p, p, p, d, d, i64, p, p, p]),
+        "or_fs1_nd": (ctypes.c_int, [ctypes.c_int, p, p, p, p, d, d, i64, p, p, p]),
+        "or_sinkhornn_log_dense": (ctypes.c_int, [ctypes.c_int, p, p, p, p, d, d, i64, p, p, p]),
+        "or_fs1_nd_log": (ctypes.c_int, [ctypes.c_int, p, p, p, p, d, d, i64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -477,3 +497,137 @@ def plan2(phi, psi, n1, n2, h1, h2, eps) -> np.ndarray:
     i, j = r % n1, r // n1
     d = (np.abs(i[:, None] - i[None, :]) * h1 + np.abs(j[:, None] - j[None, :]) * h2)
     return phi[:, None] * np.exp(-d / eps) * psi[None, :]
+
+
+# ---------------------------------------------------------------------------
+# D dimensions (Sec. 4 carried to any number of axes): grids n_0 x ... x
+# n_{D-1} with the first axis fastest, spacings h_a, the L1 ground cost.
+# ---------------------------------------------------------------------------
+
+def _gridn(x, dims):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    if x.size != int(np.prod(dims)):
+        raise ValueError("array size must be the product of dims")
+    return x
+
+
+def _dimsh(dims, h):
+    dims = np.ascontiguousarray(dims, dtype=np.int64).reshape(-1)
+    h = np.ascontiguousarray(h, dtype=np.float64).reshape(-1)
+    if dims.size != h.size or dims.size < 1:
+        raise ValueError("dims and h must have the same length >= 1")
+    return dims, h
+
+
+def _kvn(fname, x, dims, h, eps):
+    dims, h = _dimsh(dims, h)
+    x = _gridn(x, dims)
+    y = np.empty_like(x)
+    st = getattr(_load(), fname)(int(dims.size), _ptr(dims), _ptr(x), _ptr(h), eps, _ptr(y))
+    if st != 0:
+        raise ValueError(f"{fname}: status {st}")
+    return y
+
+
+def kvn_dense(x, dims, h, eps: float) -> np.ndarray:
+    """K x on the D-dimensional grid, K formed entry by entry."""
+    return _kvn("or_kvn_dense", x, dims, h, eps)
+
+
+def kvn_fs1(x, dims, h, eps: float) -> np.ndarray:
+    """K x by the 1-D recursions along axis 0, then 1, ..."""
+    return _kvn("or_kvn_fs1", x, dims, h, eps)
+
+
+def kvn_log_dense(lx, dims, h, eps: float) -> np.ndarray:
+    """ln K e^lx, every term (max-shifted)."""
+    return _kvn("or_kvn_log_dense", lx, dims, h, eps)
+
+
+def kvn_fs1_log(lx, dims, h, eps: float) -> np.ndarray:
+    """ln K e^lx by the 1-D log recursions along each axis in turn."""
+    return _kvn("or_kvn_fs1_log", lx, dims, h, eps)
+
+
+def _errn(fname, a, b, nu, dims, h, eps) -> float:
+    dims, h = _dimsh(dims, h)
+    a, b, nu = _gridn(a, dims), _gridn(b, dims), _gridn(nu, dims)
+    return float(getattr(_load(), fname)(int(dims.size), _ptr(dims), _ptr(a), _ptr(b), _ptr(nu),
+                                          _ptr(h), eps))
+
+
+def marginal_errn_dense(phi, psi, nu, dims, h, eps) -> float:
+    return _errn("or_marginal_errn_dense", phi, psi, nu, dims, h, eps)
+
+
+def marginal_errn_fs1(phi, psi, nu, dims, h, eps) -> float:
+    return _errn("or_marginal_errn_fs1", phi, psi, nu, dims, h, eps)
+
+
+def marginal_errn_log_dense(F, G, nu, dims, h, eps) -> float:
+    return _errn("or_marginal_errn_log_dense", F, G, nu, dims, h, eps)
+
+
+def marginal_errn_fs1_log(F, G, nu, dims, h, eps) -> float:
+    return _errn("or_marginal_errn_fs1_log", F, G, nu, dims, h, eps)
+
+
+def _costn(fname, a, b, dims, h, eps) -> float:
+    dims, h = _dimsh(dims, h)
+    a, b = _gridn(a, dims), _gridn(b, dims)
+    return float(getattr(_load(), fname)(int(dims.size), _ptr(dims), _ptr(a), _ptr(b), _ptr(h),
+                                          eps))
+
+
+def costn_dense(phi, psi, dims, h, eps) -> float:
+    return _costn("or_costn_dense", phi, psi, dims, h, eps)
+
+
+def costn_fs1(phi, psi, dims, h, eps) -> float:
+    return _costn("or_costn_fs1", phi, psi, dims, h, eps)
+
+
+def costn_log_dense(F, G, dims, h, eps) -> float:
+    return _costn("or_costn_log_dense", F, G, dims, h, eps)
+
+
+def costn_fs1_log(F, G, dims, h, eps) -> float:
+    return _costn("or_costn_fs1_log", F, G, dims, h, eps)
+
+
+def _solven(fname, mu, nu, dims, h, eps, tol, itr_max) -> OracleResult:
+    dims, h = _dimsh(dims, h)
+    mu, nu = _gridn(mu, dims), _gridn(nu, dims)
+    n = mu.size
+    a = np.empty(n)
+    b = np.empty(n)
+    res = np.zeros(5)
+    st = getattr(_load(), fname)(int(dims.size), _ptr(dims), _ptr(mu), _ptr(nu), _ptr(h), eps,
+                                 tol, int(itr_max), _ptr(a), _ptr(b), _ptr(res))
+    if st == -1:
+        raise ValueError(f"{fname}: invalid argument")
+    if st == -4:
+        raise MemoryError(fname)
+    return OracleResult(float(res[0]), float(res[1]), int(res[2]), int(res[3]),
+                        bool(res[4]), a, b)
+
+
+def sinkhornn_dense(mu, nu, dims, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """Algorithm 2 on D axes with dense products."""
+    return _solven("or_sinkhornn_dense", mu, nu, dims, h, eps, tol, itr_max)
+
+
+def fs1_nd(mu, nu, dims, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """Algorithm 2 on D axes by the recursions along each axis."""
+    return _solven("or_fs1_nd", mu, nu, dims, h, eps, tol, itr_max)
+
+
+def sinkhornn_log_dense(mu, nu, dims, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """The log form with dense products; .a = F = ln phi, .b = G = ln psi."""
+    return _solven("or_sinkhornn_log_dense", mu, nu, dims, h, eps, tol, itr_max)
+
+
+def fs1_nd_log(mu, nu, dims, h, eps, tol=0.0, itr_max=1000) -> OracleResult:
+    """The log form by the recursions; .a = F = ln phi, .b = G = ln psi."""
+    return _solven("or_fs1_nd_log", mu, nu, dims, h, eps, tol, itr_max)
+

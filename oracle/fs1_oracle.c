@@ -1109,6 +1109,339 @@ int or_fs1_2d_log(int64_t n1, int64_t n2, const double *mu, const double *nu, do
     return solve2_log(0, n1, n2, mu, nu, h1, h2, eps, tol, itr_max, F, G, res);
 }
 
+/* ========================================================================= */
+/* D dimensions (Sec. 4: the construction of the 2-D case carried to any      */
+/* number of axes, which the paper states without writing it out).  A         */
+/* histogram on an n_0 x ... x n_{D-1} grid is flattened with the first axis  */
+/* fastest: entry (i_0, ..., i_{D-1}) at sum_a i_a s_a, s_a = n_0 ... n_{a-1}. */
+/* The ground cost is the L1 distance sum_a |i_a - j_a| h_a, so               */
+/*   K = K_{D-1} (x) ... (x) K_0,  K_a the 1-D Gibbs kernel of axis a,         */
+/* and K x is the 1-D recursions of Sec. 3 along every line of every axis in  */
+/* turn (for D = 2 this is Algorithm 2: columns first, then eq. (2d           */
+/* recursion) across them).  The cost splits into one term per axis:          */
+/*   W = sum_a h_a <phi, (K_{D-1} (x) .. C_a .. (x) K_0) psi>,                 */
+/* C_a the 1-D kernel lambda_a^{|d|} |d| applied along axis a.                */
+/* ========================================================================= */
+
+#define OR_MAX_DIM 8
+
+static int dims_ok(int ndim, const int64_t *dims, const double *h, double eps, int64_t *n) {
+    if (ndim < 1 || ndim > OR_MAX_DIM || !(eps > 0)) return 0;
+    int64_t t = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 1 || !(h[a] > 0)) return 0;
+        t *= dims[a];
+    }
+    *n = t;
+    return 1;
+}
+
+/* L1 distance (in units of eps) between entries r and q of the grid */
+static double grid_dist(int ndim, const int64_t *dims, const double *h, int64_t r, int64_t q) {
+    double d = 0.0;
+    for (int a = 0; a < ndim; ++a) {
+        const int64_t i = r % dims[a], j = q % dims[a];
+        d += (double)(i > j ? i - j : j - i) * h[a];
+        r /= dims[a];
+        q /= dims[a];
+    }
+    return d;
+}
+
+/* A 1-D operator on one line of len entries: y = op(x) with spacing h. */
+typedef int (*line_op)(int64_t len, const double *x, double h, double eps, double *y);
+
+static int kv_line(int64_t len, const double *x, double h, double eps, double *y) {
+    return or_kv_fs1(len, x, h, eps, y);
+}
+static int cost_line(int64_t len, const double *x, double h, double eps, double *y) {
+    return cost_kernel_fs1(len, x, exp(-h / eps), y);
+}
+static int kv_line_log(int64_t len, const double *x, double h, double eps, double *y) {
+    return or_kv_fs1_log(len, x, h, eps, y);
+}
+static int cost_line_log(int64_t len, const double *x, double h, double eps, double *y) {
+    return cost_kernel_fs1_log(len, x, h / eps, y);
+}
+
+/* out = op applied along every line of axis a (in and out may be the same
+ * array: each line is read whole before it is written). */
+static int along_axis(int ndim, const int64_t *dims, int a, const double *in, double *out,
+                      line_op op, double h, double eps) {
+    int64_t n = 1, s = 1;
+    for (int b = 0; b < ndim; ++b) {
+        n *= dims[b];
+        if (b < a) s *= dims[b];
+    }
+    const int64_t len = dims[a], nlines = n / len;
+    double *x = (double *)malloc((size_t)len * sizeof(double));
+    double *y = (double *)malloc((size_t)len * sizeof(double));
+    if (!x || !y) { free(x); free(y); return OR_ERR_NO_MEMORY; }
+    int st = OR_OK;
+    for (int64_t L = 0; L < nlines && st == OR_OK; ++L) {
+        const int64_t base = (L % s) + (L / s) * s * len;
+        for (int64_t k = 0; k < len; ++k) x[k] = in[base + k * s];
+        st = op(len, x, h, eps, y);
+        for (int64_t k = 0; k < len; ++k) out[base + k * s] = y[k];
+    }
+    free(x); free(y);
+    return st;
+}
+
+/* y = K x with K dense: every one of the n^2 entries formed from its
+ * definition exp(-sum_a |i_a - j_a| h_a / eps). */
+int or_kvn_dense(int ndim, const int64_t *dims, const double *x, const double *h, double eps,
+                 double *y) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return OR_ERR_INVALID_ARG;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t q = 0; q < n; ++q)
+            nadd(&acc, exp(-grid_dist(ndim, dims, h, r, q) / eps) * x[q]);
+        y[r] = nval(&acc);
+    }
+    return OR_OK;
+}
+
+/* y = K x by the 1-D recursions along axis 0, then axis 1, ... */
+int or_kvn_fs1(int ndim, const int64_t *dims, const double *x, const double *h, double eps,
+               double *y) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return OR_ERR_INVALID_ARG;
+    memcpy(y, x, (size_t)n * sizeof(double));
+    for (int a = 0; a < ndim; ++a) {
+        const int st = along_axis(ndim, dims, a, y, y, kv_line, h[a], eps);
+        if (st != OR_OK) return st;
+    }
+    return OR_OK;
+}
+
+/* ly = ln K e^lx, dense (max-shifted) */
+int or_kvn_log_dense(int ndim, const int64_t *dims, const double *lx, const double *h,
+                     double eps, double *ly) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return OR_ERR_INVALID_ARG;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        double m = -INFINITY;
+        for (int64_t q = 0; q < n; ++q) {
+            const double t = lx[q] - grid_dist(ndim, dims, h, r, q) / eps;
+            if (t > m) m = t;
+        }
+        if (m == -INFINITY) { ly[r] = -INFINITY; continue; }
+        nsum acc = {0.0, 0.0};
+        for (int64_t q = 0; q < n; ++q)
+            nadd(&acc, exp(lx[q] - grid_dist(ndim, dims, h, r, q) / eps - m));
+        ly[r] = m + log(nval(&acc));
+    }
+    return OR_OK;
+}
+
+/* the same product by the 1-D log recursions along each axis in turn */
+int or_kvn_fs1_log(int ndim, const int64_t *dims, const double *lx, const double *h,
+                   double eps, double *ly) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return OR_ERR_INVALID_ARG;
+    memcpy(ly, lx, (size_t)n * sizeof(double));
+    for (int a = 0; a < ndim; ++a) {
+        const int st = along_axis(ndim, dims, a, ly, ly, kv_line_log, h[a], eps);
+        if (st != OR_OK) return st;
+    }
+    return OR_OK;
+}
+
+/* K x (lg: ln K e^x), dense or by the recursions */
+static int kvn(int dense, int lg, int ndim, const int64_t *dims, const double *x,
+               const double *h, double eps, double *y) {
+    if (lg) return dense ? or_kvn_log_dense(ndim, dims, x, h, eps, y)
+                         : or_kvn_fs1_log(ndim, dims, x, h, eps, y);
+    return dense ? or_kvn_dense(ndim, dims, x, h, eps, y) : or_kvn_fs1(ndim, dims, x, h, eps, y);
+}
+
+/* The stopping-test sum err = sum | psi (K^T phi) - nu | (K symmetric) with
+ * the product dense or by the recursions; lg: phi, psi are F = ln phi,
+ * G = ln psi. */
+static double marginal_errn(int dense, int lg, int ndim, const int64_t *dims, const double *phi,
+                            const double *psi, const double *nu, const double *h, double eps) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return NAN;
+    double *kt = (double *)malloc((size_t)n * sizeof(double));
+    if (!kt) return NAN;
+    if (kvn(dense, lg, ndim, dims, phi, h, eps, kt) != OR_OK) { free(kt); return NAN; }
+    nsum err = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) {
+        double v;
+        if (lg) v = (psi[r] == -INFINITY || kt[r] == -INFINITY) ? 0.0 : exp(psi[r] + kt[r]);
+        else v = psi[r] * kt[r];
+        nadd(&err, fabs(v - nu[r]));
+    }
+    free(kt);
+    return nval(&err);
+}
+
+double or_marginal_errn_dense(int ndim, const int64_t *dims, const double *phi,
+                              const double *psi, const double *nu, const double *h, double eps) {
+    return marginal_errn(1, 0, ndim, dims, phi, psi, nu, h, eps);
+}
+double or_marginal_errn_fs1(int ndim, const int64_t *dims, const double *phi, const double *psi,
+                            const double *nu, const double *h, double eps) {
+    return marginal_errn(0, 0, ndim, dims, phi, psi, nu, h, eps);
+}
+double or_marginal_errn_log_dense(int ndim, const int64_t *dims, const double *F,
+                                  const double *G, const double *nu, const double *h,
+                                  double eps) {
+    return marginal_errn(1, 1, ndim, dims, F, G, nu, h, eps);
+}
+double or_marginal_errn_fs1_log(int ndim, const int64_t *dims, const double *F, const double *G,
+                                const double *nu, const double *h, double eps) {
+    return marginal_errn(0, 1, ndim, dims, F, G, nu, h, eps);
+}
+
+/* The returned value, literally: W = sum_{r,q} phi_r psi_q K_rq d(r, q)
+ * (lg: on logarithms, exp(F_r + G_q - d/eps) d). */
+static double costn_dense(int lg, int ndim, const int64_t *dims, const double *phi,
+                          const double *psi, const double *h, double eps) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return NAN;
+    double *row = (double *)malloc((size_t)n * sizeof(double));
+    if (!row) return NAN;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t q = 0; q < n; ++q) {
+            const double d = grid_dist(ndim, dims, h, r, q);
+            if (lg) {
+                if (phi[r] == -INFINITY || psi[q] == -INFINITY) continue;
+                nadd(&acc, exp(phi[r] + psi[q] - d / eps) * d);
+            } else {
+                nadd(&acc, phi[r] * psi[q] * exp(-d / eps) * d);
+            }
+        }
+        row[r] = nval(&acc);
+    }
+    nsum w = {0.0, 0.0};
+    for (int64_t r = 0; r < n; ++r) nadd(&w, row[r]);
+    free(row);
+    return nval(&w);
+}
+
+double or_costn_dense(int ndim, const int64_t *dims, const double *phi, const double *psi,
+                      const double *h, double eps) {
+    return costn_dense(0, ndim, dims, phi, psi, h, eps);
+}
+double or_costn_log_dense(int ndim, const int64_t *dims, const double *F, const double *G,
+                          const double *h, double eps) {
+    return costn_dense(1, ndim, dims, F, G, h, eps);
+}
+
+/* The same W by the split over the axes: term a applies C_a along axis a
+ * and K_b along every other axis b, then takes h_a <phi, .>. */
+static double costn_fs1(int lg, int ndim, const int64_t *dims, const double *phi,
+                        const double *psi, const double *h, double eps) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n)) return NAN;
+    double *t = (double *)malloc((size_t)n * sizeof(double));
+    if (!t) return NAN;
+    double w = 0.0;
+    for (int a = 0; a < ndim; ++a) {
+        memcpy(t, psi, (size_t)n * sizeof(double));
+        for (int b = 0; b < ndim; ++b) {
+            line_op op = lg ? (b == a ? cost_line_log : kv_line_log) : (b == a ? cost_line : kv_line);
+            if (along_axis(ndim, dims, b, t, t, op, h[b], eps) != OR_OK) { free(t); return NAN; }
+        }
+        nsum acc = {0.0, 0.0};
+        for (int64_t r = 0; r < n; ++r) {
+            if (lg) {
+                if (phi[r] != -INFINITY && t[r] != -INFINITY) nadd(&acc, exp(phi[r] + t[r]));
+            } else {
+                nadd(&acc, phi[r] * t[r]);
+            }
+        }
+        w += h[a] * nval(&acc);
+    }
+    free(t);
+    return w;
+}
+
+double or_costn_fs1(int ndim, const int64_t *dims, const double *phi, const double *psi,
+                    const double *h, double eps) {
+    return costn_fs1(0, ndim, dims, phi, psi, h, eps);
+}
+double or_costn_fs1_log(int ndim, const int64_t *dims, const double *F, const double *G,
+                        const double *h, double eps) {
+    return costn_fs1(1, ndim, dims, F, G, h, eps);
+}
+
+/* Algorithm 2 on D axes with the products dense (dense = 1) or by the
+ * recursions; lg: on logarithms (F, G), as the 2-D log form.  phi = psi =
+ * 1/n (F = G = -ln n); while it < itr_max and err > tol: psi <- nu / (K^T
+ * phi); phi <- mu / (K psi).  Returns W as above. */
+static int solve_n(int dense, int lg, int ndim, const int64_t *dims, const double *mu,
+                   const double *nu, const double *h, double eps, double tol, int64_t itr_max,
+                   double *phi, double *psi, double *res) {
+    int64_t n;
+    if (!dims_ok(ndim, dims, h, eps, &n) || itr_max < 0) return OR_ERR_INVALID_ARG;
+    double *lmu = (double *)malloc((size_t)n * sizeof(double));
+    double *lnu = (double *)malloc((size_t)n * sizeof(double));
+    double *den = (double *)malloc((size_t)n * sizeof(double));
+    if (!lmu || !lnu || !den) { free(lmu); free(lnu); free(den); return OR_ERR_NO_MEMORY; }
+    for (int64_t r = 0; r < n; ++r) {
+        lmu[r] = mu[r] > 0 ? log(mu[r]) : -INFINITY;
+        lnu[r] = nu[r] > 0 ? log(nu[r]) : -INFINITY;
+        phi[r] = psi[r] = lg ? -log((double)n) : 1.0 / (double)n;
+    }
+    int64_t it = 0;
+    int st = OR_OK, conv = 0;
+    double err = marginal_errn(dense, lg, ndim, dims, phi, psi, nu, h, eps);
+    while (it < itr_max) {
+        if (!(err > tol)) { conv = 1; break; }
+        /* psi-half: K^T phi (K is symmetric) */
+        if (kvn(dense, lg, ndim, dims, phi, h, eps, den) != OR_OK ||
+            (lg ? divide_update_log(n, lnu, den, psi) : divide_update(n, nu, den, psi))) {
+            st = OR_ERR_NONFINITE;
+            break;
+        }
+        /* phi-half: K psi */
+        if (kvn(dense, lg, ndim, dims, psi, h, eps, den) != OR_OK ||
+            (lg ? divide_update_log(n, lmu, den, phi) : divide_update(n, mu, den, phi))) {
+            st = OR_ERR_NONFINITE;
+            break;
+        }
+        ++it;
+        err = marginal_errn(dense, lg, ndim, dims, phi, psi, nu, h, eps);
+    }
+    if (st == OR_OK && it == itr_max && !(err > tol)) conv = 1;
+    double w = NAN;
+    if (st == OR_OK)
+        w = dense ? costn_dense(lg, ndim, dims, phi, psi, h, eps)
+                  : costn_fs1(lg, ndim, dims, phi, psi, h, eps);
+    pack_result(res, w, err, it, st, conv);
+    free(lmu); free(lnu); free(den);
+    return st;
+}
+
+int or_sinkhornn_dense(int ndim, const int64_t *dims, const double *mu, const double *nu,
+                       const double *h, double eps, double tol, int64_t itr_max, double *phi,
+                       double *psi, double *res) {
+    return solve_n(1, 0, ndim, dims, mu, nu, h, eps, tol, itr_max, phi, psi, res);
+}
+int or_fs1_nd(int ndim, const int64_t *dims, const double *mu, const double *nu,
+              const double *h, double eps, double tol, int64_t itr_max, double *phi,
+              double *psi, double *res) {
+    return solve_n(0, 0, ndim, dims, mu, nu, h, eps, tol, itr_max, phi, psi, res);
+}
+int or_sinkhornn_log_dense(int ndim, const int64_t *dims, const double *mu, const double *nu,
+                           const double *h, double eps, double tol, int64_t itr_max, double *F,
+                           double *G, double *res) {
+    return solve_n(1, 1, ndim, dims, mu, nu, h, eps, tol, itr_max, F, G, res);
+}
+int or_fs1_nd_log(int ndim, const int64_t *dims, const double *mu, const double *nu,
+                  const double *h, double eps, double tol, int64_t itr_max, double *F,
+                  double *G, double *res) {
+    return solve_n(0, 1, ndim, dims, mu, nu, h, eps, tol, itr_max, F, G, res);
+}
+
 /* Thread count of the OpenMP loops (timing on a stated number of cores). */
 void or_set_num_threads(int k) {
 #ifdef _OPENMP
