@@ -284,6 +284,8 @@ def main():
                     help="only the 4096-instance uneven batch (profiling runs)")
     ap.add_argument("--no-paper-workloads", action="store_true",
                     help="skip the Sec. 5.1 / 5.2 / 5.3 workloads at the paper's sizes")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="only the Sec. 5.1 / 5.2 / 5.3 workloads and the 3-D grids")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -316,6 +318,11 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched": batched_study(fs1, ctx, inputs, np, torch, args.batch)}),
+              flush=True)
+        return
+
+    if args.paper_only:
+        print(json.dumps({"paper_workloads": paper_workloads_study(fs1, ctx, inputs, np, torch)}),
               flush=True)
         return
 
@@ -569,6 +576,29 @@ def paper_workloads_study(fs1, ctx, inputs, np, torch):
                          "speedup_vs_paper_fs1": pf / best})
             log(f"table3 {n}x{n} {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve "
                 f"(paper's 2-D FS-1 on its CPU: {pf * 1e3:.1f} ms), w1 {r.w1:.12g}")
+    # the same recipe on N x N x N grids (Algorithm 2 on three axes; no paper
+    # time exists for it)
+    for domain in ("plain", "log"):
+        for n in (16, 32, 64, 128):
+            u, v = inputs.paper_uniform_nd((n, n, n), 0)
+            mu = torch.tensor(u, dtype=torch.float64, device="cuda")
+            nu = torch.tensor(v, dtype=torch.float64, device="cuda")
+            best, r = None, None
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fs1.fs1_solve_nd(mu, nu, (n, n, n), (1.0, 1.0, 1.0), 0.01, 0.0,
+                                     itr_max=1000, sync_every=64, ctx=ctx, domain=domain)
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+                if rep > 0:
+                    best = w if best is None else min(best, w)
+            rows.append({"workload": "grid3d", "n": f"{n}x{n}x{n}", "eps": 0.01,
+                         "iterations": r.iterations, "domain": domain, "status": r.status,
+                         "w1": r.w1, "marginal_err": r.marginal_err, "gpu_s": best,
+                         "grid_pts_it_per_s": n ** 3 * r.iterations / best})
+            log(f"grid3d {n}^3 {domain}: {r.iterations} it, {best * 1e3:.2f} ms per solve, "
+                f"w1 {r.w1:.12g}")
     return {"rows": rows,
             "note": "paper times: FS-1 and dense Sinkhorn on the paper's CPU (one Intel Xeon "
                     "Gold 5117, 2.0 GHz, 14 cores; context, not a target); GPU: one MI355X, "

@@ -352,15 +352,50 @@ int fs1_kv_apply_2d(fs1_ctx *ctx, const void *x, void *y, int64_t n1, int64_t n2
  * stabilisation carried to Algorithm 2: every scaling entry held as a
  * mantissa and a binary exponent, so no product underflows at small eps; the
  * same iterates in exact arithmetic; 16 bytes more workspace per grid
- * point); FS1_ABSORB is FS1_ERR_INVALID_ARG.  In the plain domain a small grid
- * (n1 n2 <= 4096, n1 + n2 <= 128) runs the whole solve in one workgroup (the
- * paper's sequential recursions, one line per thread) unless
- * FS1_FLAG_NO_RESIDENT is set; other grids, and every grid in the log
- * domain, run one workgroup per line and pass;
+ * point); FS1_ABSORB is FS1_ERR_INVALID_ARG.  A small grid (n1 n2 <= 4096;
+ * n1 + n2 <= 384 in the plain domain, <= 80 (binary64) or 128 (binary32) in
+ * the log domain) runs the whole solve in one workgroup (the paper's
+ * sequential recursions, the two directions of a line on two threads) unless
+ * FS1_FLAG_NO_RESIDENT is set; other grids run one workgroup per line and
+ * pass;
  * potentials_out receives ln phi then
  * ln psi (2 n1 n2 doubles).  Blocking; error behaviour as fs1_solve. */
 int fs1_solve_2d(fs1_ctx *ctx, const double *mu, const double *nu, int64_t n1, int64_t n2,
                  double h1, double h2, double eps, double tol, const fs1_opts *opts,
+                 fs1_result *out);
+
+/* ------------------------------------------------------------------------ */
+/* D dimensions (Sec. 4: the 2-D construction carried to any number of axes,  */
+/* which the paper states extends without writing it out).  A histogram on an */
+/* n_0 x ... x n_{D-1} grid, 1 <= D <= 4, is an array of n_0 ... n_{D-1}     */
+/* entries with the first axis fastest: entry (i_0, ..., i_{D-1}) at          */
+/* sum_a i_a n_0 ... n_{a-1}.  The ground cost is sum_a |i_a - j_a| h_a, so   */
+/* K = K_{D-1} (x) ... (x) K_0 and K x is the 1-D recursions of Sec. 3 along  */
+/* every line of each axis in turn (D = 2: Algorithm 2).  dims and h are host */
+/* arrays of D entries: 1 <= dims[a] <= 8192, h[a] > 0 and finite, eps > 0    */
+/* and finite, dims[a] h[a] / eps <= 1e8, at most 2^31 - 1 grid points (else  */
+/* FS1_ERR_INVALID_ARG before any launch).                                   */
+/* ------------------------------------------------------------------------ */
+
+/* y = K x for device arrays x, y of n_0 ... n_{D-1} entries of dtype dt
+ * (FS1_F64 or FS1_F32), plain arithmetic; x and y must not overlap.  No
+ * workspace (the first axis writes y, the others update it in place).
+ * Asynchronous on the context stream. */
+int fs1_kv_apply_nd(fs1_ctx *ctx, const void *x, void *y, int ndim, const int64_t *dims,
+                    const double *h, double eps, int dt);
+
+/* Algorithm 2 on D axes: phi = psi = 1/n; while iterations < itr_max and
+ * err = sum | psi (K^T phi) - nu | > tol: psi = nu / (K^T phi), then
+ * phi = mu / (K psi).  Returns w1 = sum phi_r psi_q K_rq (sum_a |r_a - q_a| h_a),
+ * evaluated as one term per axis, h_a <phi, (K .. C_a .. K) psi>, C_a the 1-D
+ * kernel lambda_a^{|d|} |d| along axis a.  mu, nu: device binary64 arrays of
+ * n entries, finite, >= 0, equal mass to 1e-10 relative.  opts, domains
+ * (FS1_PLAIN, FS1_LOG) and errors as fs1_solve_2d; for D = 2 this is
+ * fs1_solve_2d (the one-workgroup form included), for other D one workgroup
+ * per line and pass.  potentials_out receives ln phi then ln psi (2 n
+ * doubles).  Blocking. */
+int fs1_solve_nd(fs1_ctx *ctx, const double *mu, const double *nu, int ndim, const int64_t *dims,
+                 const double *h, double eps, double tol, const fs1_opts *opts,
                  fs1_result *out);
 
 /* ------------------------------------------------------------------------ */

@@ -52,15 +52,16 @@ struct LineArgs {
   const float* m32;     // marginal, binary32 (UPDATE with T = float)
   double* part;         // per-line shares (ERR, DOT, COSTDOT, checked UPDATE)
   Ctrl* ctrl;
-  int64_t line_step;    // offset of line L's first entry: L * line_step
+  int64_t inner;        // line L's first entry: (L mod inner) + (L div inner) outer
+  int64_t outer;
   int64_t stride;       // offset between consecutive entries of a line
   int len;              // entries per line
   int l;                // iteration (failure record)
   int check;            // UPDATE: also the error share of Algorithm 2's stopping test
   int guard;            // return at once once the solve has stopped or failed
-  // APPLY with decide: first take the stop decision of iteration l from the
-  // nparts shares in part (every workgroup sums them in the same order;
-  // workgroup 0 records it) and return at once when it stops
+  // decide: first take the stop decision of iteration l from the nparts
+  // shares in part (every workgroup sums them in the same order; workgroup 0
+  // records it) and return at once when it stops
   int decide;
   int nparts;
   double tol;
@@ -76,28 +77,28 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   __shared__ double red[NW];
   __shared__ int sstop;
   if (a.guard && (a.ctrl->done || a.ctrl->fail)) return;  // the same value in every thread
-  if constexpr (MODE == L_APPLY) {
-    if (a.decide) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < a.nparts; i += NT) s += a.part[i];
-      const double tot = block_sum<NW>(s, red);  // valid in thread 0
-      if (threadIdx.x == 0) {
-        sstop = !(tot > a.tol);
-        if (blockIdx.x == 0) {
-          a.ctrl->last_err = tot;
-          a.ctrl->last_check = a.l;
-          if (a.err_hist) a.err_hist[a.l] = tot;
-          if (sstop) {
-            a.ctrl->stop_iter = a.l;
-            a.ctrl->done = 1;
-          }
+  if (a.decide) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.nparts; i += NT) s += a.part[i];
+    const double tot = block_sum<NW>(s, red);  // valid in thread 0
+    if (threadIdx.x == 0) {
+      sstop = !(tot > a.tol);
+      if (blockIdx.x == 0) {
+        a.ctrl->last_err = tot;
+        a.ctrl->last_check = a.l;
+        if (a.err_hist) a.err_hist[a.l] = tot;
+        if (sstop) {
+          a.ctrl->stop_iter = a.l;
+          a.ctrl->done = 1;
         }
       }
-      __syncthreads();
-      if (sstop) return;
     }
+    __syncthreads();
+    if (sstop) return;
   }
-  const int64_t base = int64_t(blockIdx.x) * a.line_step;
+  const uint32_t line = blockIdx.x;
+  const uint32_t inner = uint32_t(a.inner);
+  const int64_t base = int64_t(line % inner) + int64_t(line / inner) * a.outer;
   const int p0 = int(threadIdx.x) * R;
   const T* xin = static_cast<const T*>(a.x);
   T x[R];
@@ -656,10 +657,13 @@ hipError_t launch_res2d(const Res2Args& a, size_t lds, hipStream_t s) {
 }
 
 // One pass over the lines of one axis.  R: entries per thread (kR2, or 1 in
-// the log domain where h/eps is too large for runs of kR2, as in 1-D).
+// the log domain where h/eps is too large for runs of kR2, as in 1-D).  The
+// lines of axis a of a grid n_0 x ... (first axis fastest) start at
+// (L mod s_a) + (L div s_a) s_a n_a, entries s_a = n_0 ... n_{a-1} apart.
 struct Axis {
   int64_t nlines;
-  int64_t line_step;
+  int64_t inner;
+  int64_t outer;
   int64_t stride;
   int len;
   int R;
@@ -682,7 +686,8 @@ hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
 
 template <typename T, int MODE, bool SC = false>
 hipError_t run_pass(const Axis& ax, LineArgs a, hipStream_t s) {
-  a.line_step = ax.line_step;
+  a.inner = ax.inner;
+  a.outer = ax.outer;
   a.stride = ax.stride;
   a.len = ax.len;
   if constexpr (SC) {
@@ -691,9 +696,26 @@ hipError_t run_pass(const Axis& ax, LineArgs a, hipStream_t s) {
   return run_pass_r<T, kR2, MODE, SC>(ax, a, s);
 }
 
-struct Grid2 {
-  int64_t n1, n2;
-  Axis ax1, ax2;
+// runtime mode -> the pass template
+template <typename T, bool SC>
+hipError_t run_mode(int mode, const Axis& ax, const LineArgs& a, hipStream_t s) {
+  switch (mode) {
+    case L_APPLY: return run_pass<T, L_APPLY, SC>(ax, a, s);
+    case L_COST: return run_pass<T, L_COST, SC>(ax, a, s);
+    case L_UPDATE: return run_pass<T, L_UPDATE, SC>(ax, a, s);
+    case L_ERR: return run_pass<T, L_ERR, SC>(ax, a, s);
+    case L_DOT: return run_pass<T, L_DOT, SC>(ax, a, s);
+    default: return run_pass<T, L_COSTDOT, SC>(ax, a, s);
+  }
+}
+
+constexpr int kMaxDim = 4;  // axes of a grid
+
+struct Grid {
+  int nd;
+  int64_t n;
+  int64_t max_lines;  // most lines of any axis
+  Axis ax[kMaxDim];
 };
 
 // Entries per thread along an axis: kR2, except in the log domain where every
@@ -704,53 +726,67 @@ int line_run_length(bool log_domain, int dt, double h, double eps) {
   return pick_run_length(dt, true, h / eps) >= kR2 ? kR2 : 1;
 }
 
-Grid2 make_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps,
-                 bool log_domain = false, int dt = FS1_F64) {
-  Grid2 g;
-  g.n1 = n1;
-  g.n2 = n2;
-  const int r1 = line_run_length(log_domain, dt, h1, eps);
-  const int r2 = line_run_length(log_domain, dt, h2, eps);
-  // columns: n2 lines of n1 contiguous entries; rows: n1 lines strided by n1
-  g.ax1 = Axis{n2, n1, 1, int(n1), r1, make_scan_consts(h1, eps, r1)};
-  g.ax2 = Axis{n1, 1, n1, int(n2), r2, make_scan_consts(h2, eps, r2)};
+Grid make_grid(int nd, const int64_t* dims, const double* h, double eps, bool log_domain = false,
+               int dt = FS1_F64) {
+  Grid g{};
+  g.nd = nd;
+  g.n = 1;
+  for (int a = 0; a < nd; ++a) g.n *= dims[a];
+  int64_t s = 1;
+  for (int a = 0; a < nd; ++a) {
+    const int r = line_run_length(log_domain, dt, h[a], eps);
+    g.ax[a] = Axis{g.n / dims[a], s, s * dims[a], s, int(dims[a]), r,
+                   make_scan_consts(h[a], eps, r)};
+    g.max_lines = std::max(g.max_lines, g.ax[a].nlines);
+    s *= dims[a];
+  }
   return g;
 }
 
-int check_grid2(int64_t n1, int64_t n2, double h1, double h2, double eps,
-                bool log_domain = false, int dt = FS1_F64) {
+int check_grid(int nd, const int64_t* dims, const double* h, double eps, bool log_domain = false,
+               int dt = FS1_F64) {
   using host::set_err;
   const int64_t lmax = int64_t(1024) * kR2;
-  if (n1 < 1 || n2 < 1) return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be >= 1");
-  if (n1 > lmax || n2 > lmax)
-    return set_err(FS1_ERR_INVALID_ARG, "n1 and n2 must be <= %lld (got %lld x %lld)",
-                   (long long)lmax, (long long)n1, (long long)n2);
-  // one workgroup holds a line: 1024 entries where the runs have length 1
-  if (log_domain && ((line_run_length(true, dt, h1, eps) == 1 && n1 > 1024) ||
-                     (line_run_length(true, dt, h2, eps) == 1 && n2 > 1024)))
-    return set_err(FS1_ERR_INVALID_ARG,
-                   "log domain: h/eps too large for runs of %d along an axis of more than 1024 "
-                   "entries",
-                   kR2);
-  if (!(h1 > 0.0) || !std::isfinite(h1) || !(h2 > 0.0) || !std::isfinite(h2))
-    return set_err(FS1_ERR_INVALID_ARG, "h1 and h2 must be finite and > 0");
+  if (nd < 1 || nd > kMaxDim)
+    return set_err(FS1_ERR_INVALID_ARG, "ndim must be 1 .. %d (got %d)", kMaxDim, nd);
+  if (!dims || !h) return set_err(FS1_ERR_INVALID_ARG, "null dims or spacings");
   if (!(eps > 0.0) || !std::isfinite(eps))
     return set_err(FS1_ERR_INVALID_ARG, "eps must be finite and > 0");
-  if (double(std::max(n1, n2)) * (std::max(h1, h2) / eps) > 1.0e8)
-    return set_err(FS1_ERR_INVALID_ARG, "n h / eps exceeds 1e8 along an axis");
+  int64_t n = 1;
+  for (int a = 0; a < nd; ++a) {
+    if (dims[a] < 1 || dims[a] > lmax)
+      return set_err(FS1_ERR_INVALID_ARG, "grid side %d must be 1 .. %lld (got %lld)", a,
+                     (long long)lmax, (long long)dims[a]);
+    // one workgroup holds a line: 1024 entries where the runs have length 1
+    if (log_domain && line_run_length(true, dt, h[a], eps) == 1 && dims[a] > 1024)
+      return set_err(FS1_ERR_INVALID_ARG,
+                     "log domain: h/eps too large for runs of %d along an axis of more than "
+                     "1024 entries",
+                     kR2);
+    if (!(h[a] > 0.0) || !std::isfinite(h[a]))
+      return set_err(FS1_ERR_INVALID_ARG, "spacings must be finite and > 0");
+    if (double(dims[a]) * (h[a] / eps) > 1.0e8)
+      return set_err(FS1_ERR_INVALID_ARG, "n h / eps exceeds 1e8 along an axis");
+    n *= dims[a];
+    // the lines of an axis are one launch's workgroups
+    if (n > (int64_t(1) << 31) - 1)
+      return set_err(FS1_ERR_INVALID_ARG, "the grid holds more than 2^31 - 1 points");
+  }
   return FS1_OK;
 }
 
+// y = K x: the first axis from x into y, the others in place (a pass reads
+// each entry of a line in the thread that writes it)
 template <typename T>
-hipError_t kv2(const Grid2& g, const void* x, void* y, void* t, hipStream_t s) {
+hipError_t kvn(const Grid& g, const void* x, void* y, hipStream_t s) {
   LineArgs a{};
-  a.x = x;
-  a.y = t;
-  hipError_t e = run_pass<T, L_APPLY>(g.ax1, a, s);
-  if (e != hipSuccess) return e;
-  a.x = t;
-  a.y = y;
-  return run_pass<T, L_APPLY>(g.ax2, a, s);
+  for (int d = 0; d < g.nd; ++d) {
+    a.x = d == 0 ? x : y;
+    a.y = y;
+    const hipError_t e = run_pass<T, L_APPLY>(g.ax[d], a, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 struct Bufs2 {
@@ -764,9 +800,9 @@ struct Bufs2 {
   double* nu;
   float* mu32;      // binary32 copies (T = float)
   float* nu32;
-  double* part;     // n1 + n2 shares per line kind
+  double* part;     // per-line shares of the last axis (as many as the most lines)
   double* part2;
-  double* sums;     // [0] err, [1] mu err, [2] cost term 1, [3] cost term 2
+  double* sums;     // [0] err, [1] mu err, [2 + a] cost term of axis a
   Ctrl* ctrl;
 };
 
@@ -786,101 +822,90 @@ struct Ops2 {
     a.own = v;
     a.owne = e;
   }
+  // The passes of a product K v (cost_axis >= 0: C along that axis instead
+  // of K) from x: every axis but the last from x (first) or t into t, then
+  // the last axis in mode `last` from t (or x for one axis), with the fields
+  // of a that the last pass needs already set.  `a` arrives with the first
+  // pass's fields (decide) and leaves them only to that pass.
+  static hipError_t passes(const Grid& g, const Bufs2& b, LineArgs a, const void* x,
+                           const int* xe, int cost_axis, int last, hipStream_t s) {
+    LineArgs f = a;  // first pass: may decide; later passes never do
+    for (int d = 0; d + 1 < g.nd; ++d) {
+      LineArgs p = d == 0 ? f : a;
+      if (d > 0) p.decide = 0;
+      // a middle pass carries no last-pass work
+      p.check = 0;
+      in(p, d == 0 ? x : b.t, d == 0 ? xe : b.et);
+      to(p, b.t, b.et);
+      const hipError_t e = run_mode<T, SC>(d == cost_axis ? L_COST : L_APPLY, g.ax[d], p, s);
+      if (e != hipSuccess) return e;
+    }
+    LineArgs p = a;
+    if (g.nd > 1) p.decide = 0;
+    in(p, g.nd == 1 ? x : b.t, g.nd == 1 ? xe : b.et);
+    return run_mode<T, SC>(last, g.ax[g.nd - 1], p, s);
+  }
   // psi^{l+1} = nu / K^T phi^l into vG[(l+1)&1] (and the error of (phi^l, psi^l) when checked)
-  static hipError_t psi_half(const Grid2& g, const Bufs2& b, int l, int check, hipStream_t s) {
+  static hipError_t psi_half(const Grid& g, const Bufs2& b, int l, int check, hipStream_t s) {
     LineArgs a{};
     a.ctrl = b.ctrl;
     a.guard = 1;
     a.l = l;
-    in(a, b.vF, b.eF);
-    to(a, b.t, b.et);
-    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    in(a, b.t, b.et);
     to(a, b.vG[(l + 1) & 1], b.eG[(l + 1) & 1]);
     with(a, b.vG[l & 1], b.eG[l & 1]);
     a.m64 = b.nu;
     a.m32 = b.nu32;
     a.part = b.part;
     a.check = check;
-    return run_pass<T, L_UPDATE, SC>(g.ax2, a, s);
+    return passes(g, b, a, b.vF, b.eF, -1, L_UPDATE, s);
   }
   // phi^{l+1} = mu / K psi^{l+1}; when checked, its first pass takes the stop
   // decision of iteration l from the psi-half's shares first
-  static hipError_t phi_half(const Grid2& g, const Bufs2& b, int l, int check, double tol,
+  static hipError_t phi_half(const Grid& g, const Bufs2& b, int l, int check, double tol,
                              double* err_hist, hipStream_t s) {
     LineArgs a{};
     a.ctrl = b.ctrl;
     a.guard = 1;
     a.l = l;
-    in(a, b.vG[(l + 1) & 1], b.eG[(l + 1) & 1]);
-    to(a, b.t, b.et);
     a.decide = check;
     a.part = b.part;
-    a.nparts = int(g.ax2.nlines);
+    a.nparts = int(g.ax[g.nd - 1].nlines);
     a.tol = tol;
     a.err_hist = err_hist;
-    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    a.decide = 0;
-    in(a, b.t, b.et);
     to(a, b.vF, b.eF);
     a.m64 = b.mu;
     a.m32 = b.mu32;
-    return run_pass<T, L_UPDATE, SC>(g.ax2, a, s);
+    return passes(g, b, a, b.vG[(l + 1) & 1], b.eG[(l + 1) & 1], -1, L_UPDATE, s);
   }
-  // final errors (both sides) and the transport cost of (phi, psi = vG[gbuf])
-  static hipError_t finalize(const Grid2& g, const Bufs2& b, int gbuf, double h1, double h2,
+  // final errors (both sides) and the transport cost of (phi, psi = vG[gbuf]):
+  // one term per axis, h_a <phi, (.. C_a ..) psi>
+  static hipError_t finalize(const Grid& g, const Bufs2& b, int gbuf, const double* h,
                              hipStream_t s) {
-    const int nl = int(g.ax2.nlines);
+    const int nl = int(g.ax[g.nd - 1].nlines);
     LineArgs a{};
     a.ctrl = b.ctrl;
     // nu side: sum | psi (K^T phi) - nu |
-    in(a, b.vF, b.eF);
-    to(a, b.t, b.et);
-    hipError_t e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    in(a, b.t, b.et);
     with(a, b.vG[gbuf], b.eG[gbuf]);
     a.m64 = b.nu;
     a.part = b.part;
-    e = run_pass<T, L_ERR, SC>(g.ax2, a, s);
+    hipError_t e = passes(g, b, a, b.vF, b.eF, -1, L_ERR, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part, nl, 1.0, b.sums + 0);
     // mu side: sum | phi (K psi) - mu |
-    in(a, b.vG[gbuf], b.eG[gbuf]);
-    to(a, b.t, b.et);
-    e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    in(a, b.t, b.et);
     with(a, b.vF, b.eF);
     a.m64 = b.mu;
     a.part = b.part2;
-    e = run_pass<T, L_ERR, SC>(g.ax2, a, s);
+    e = passes(g, b, a, b.vG[gbuf], b.eG[gbuf], -1, L_ERR, s);
     if (e != hipSuccess) return e;
     k_sum2<<<1, 256, 0, s>>>(b.part2, nl, 1.0, b.sums + 1);
-    // cost, first axis: h1 <phi, (K2 (x) C1) psi>
-    in(a, b.vG[gbuf], b.eG[gbuf]);
-    to(a, b.t, b.et);
-    e = run_pass<T, L_COST, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    in(a, b.t, b.et);
-    with(a, b.vF, b.eF);
-    a.part = b.part;
-    e = run_pass<T, L_DOT, SC>(g.ax2, a, s);
-    if (e != hipSuccess) return e;
-    k_sum2<<<1, 256, 0, s>>>(b.part, nl, h1, b.sums + 2);
-    // cost, second axis: h2 <phi, (C2 (x) K1) psi>
-    in(a, b.vG[gbuf], b.eG[gbuf]);
-    to(a, b.t, b.et);
-    e = run_pass<T, L_APPLY, SC>(g.ax1, a, s);
-    if (e != hipSuccess) return e;
-    in(a, b.t, b.et);
-    with(a, b.vF, b.eF);
-    a.part = b.part2;
-    e = run_pass<T, L_COSTDOT, SC>(g.ax2, a, s);
-    if (e != hipSuccess) return e;
-    k_sum2<<<1, 256, 0, s>>>(b.part2, nl, h2, b.sums + 3);
+    // cost terms
+    for (int c = 0; c < g.nd; ++c) {
+      double* part = (c & 1) ? b.part2 : b.part;
+      a.part = part;
+      e = passes(g, b, a, b.vG[gbuf], b.eG[gbuf], c, c == g.nd - 1 ? L_COSTDOT : L_DOT, s);
+      if (e != hipSuccess) return e;
+      k_sum2<<<1, 256, 0, s>>>(part, nl, h[c], b.sums + 2 + c);
+    }
     return hipGetLastError();
   }
 };
@@ -893,31 +918,35 @@ hipError_t dispatch2(int dt, bool log_domain, F&& f) {
 
 }  // namespace
 
-int kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
-                double h2, double eps, int dt) {
+int kv_apply_grid(fs1_ctx* ctx, const void* x, void* y, int nd, const int64_t* dims,
+                  const double* h, double eps, int dt) {
   using namespace host;
   if (!ctx) return set_err(FS1_ERR_INVALID_ARG, "null context");
   if (!x || !y) return set_err(FS1_ERR_INVALID_ARG, "null array");
   if (dt != FS1_F64 && dt != FS1_F32) return set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", dt);
-  int st = check_grid2(n1, n2, h1, h2, eps);
+  int st = check_grid(nd, dims, h, eps);
   if (st) return st;
-  const int64_t n = n1 * n2;
+  const Grid g = make_grid(nd, dims, h, eps);
   const size_t es = dt == FS1_F64 ? 8 : 4;
   const char* xb = static_cast<const char*>(x);
   const char* yb = static_cast<const char*>(y);
-  if (xb < yb + n * es && yb < xb + n * es)
+  if (xb < yb + g.n * es && yb < xb + g.n * es)
     return set_err(FS1_ERR_INVALID_ARG, "x and y must not overlap");
-  st = ensure_ws(ctx, size_t(n) * es);
-  if (st) return st;
-  const Grid2 g = make_grid2(n1, n2, h1, h2, eps);
-  const hipError_t e = dt == FS1_F64 ? kv2<double>(g, x, y, ctx->ws, ctx->stream)
-                                     : kv2<float>(g, x, y, ctx->ws, ctx->stream);
-  if (e != hipSuccess) return hip_fail(e, "fs1_kv_apply_2d launch");
+  const hipError_t e = dt == FS1_F64 ? kvn<double>(g, x, y, ctx->stream)
+                                     : kvn<float>(g, x, y, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel application on a grid");
   return FS1_OK;
 }
 
-int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2, double h1,
-             double h2, double eps, double tol, const fs1_opts& o, fs1_result* out) {
+int kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
+                double h2, double eps, int dt) {
+  const int64_t dims[2] = {n1, n2};
+  const double h[2] = {h1, h2};
+  return kv_apply_grid(ctx, x, y, 2, dims, h, eps, dt);
+}
+
+int solve_grid(fs1_ctx* ctx, const double* mu, const double* nu, int nd, const int64_t* dims,
+               const double* h, double eps, double tol, const fs1_opts& o, fs1_result* out) {
   using namespace host;
   auto finish = [&](int st) {
     out->status = st;
@@ -927,17 +956,18 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   if (o.dtype != FS1_F64 && o.dtype != FS1_F32)
     return finish(set_err(FS1_ERR_INVALID_ARG, "bad dtype %d", o.dtype));
   if (o.domain != FS1_PLAIN && o.domain != FS1_LOG)
-    return finish(set_err(FS1_ERR_INVALID_ARG, "the 2-D solve runs in the plain or log domain"));
+    return finish(set_err(FS1_ERR_INVALID_ARG, "a grid solve runs in the plain or log domain"));
   const bool lg = o.domain == FS1_LOG;
   if (!(tol >= 0.0)) return finish(set_err(FS1_ERR_INVALID_ARG, "tol must be >= 0"));
   if ((o.flags & FS1_FLAG_POTENTIALS) && !o.potentials_out)
     return finish(set_err(FS1_ERR_INVALID_ARG, "potentials requested without an output array"));
-  int st = check_grid2(n1, n2, h1, h2, eps, o.domain == FS1_LOG, o.dtype);
+  int st = check_grid(nd, dims, h, eps, o.domain == FS1_LOG, o.dtype);
   if (st) return finish(st);
   const int dt = o.dtype;
-  const int64_t n = n1 * n2;
+  const Grid g = make_grid(nd, dims, h, eps, lg, dt);
+  const int64_t n = g.n;
   const size_t es = dt == FS1_F64 ? 8 : 4;
-  const int64_t nl = std::max(n1, n2);
+  const int64_t nl = g.max_lines;
 
   Bufs2 b{};
   auto layout = [&](Carve& w) {
@@ -957,7 +987,7 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     b.nu32 = dt == FS1_F32 ? static_cast<float*>(w.take(size_t(n) * 4)) : nullptr;
     b.part = static_cast<double*>(w.take(size_t(nl) * 8));
     b.part2 = static_cast<double*>(w.take(size_t(nl) * 8));
-    b.sums = static_cast<double*>(w.take(4 * 8));
+    b.sums = static_cast<double*>(w.take((2 + kMaxDim) * 8));
     b.ctrl = static_cast<Ctrl*>(w.take(sizeof(Ctrl)));
   };
   {
@@ -1021,9 +1051,9 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   // the ctrl upload reads the pinned mirror: finish it before the host reuses it
   HIP_TRY(hipStreamSynchronize(s));
 
-  const Grid2 g = make_grid2(n1, n2, h1, h2, eps, lg, dt);
-  // small grids: every iteration in one workgroup; it leaves psi in buffer 0
-  const size_t lds = (o.flags & FS1_FLAG_NO_RESIDENT) ? 0 : res2d_lds(n1, n2, dt, lg);
+  // small 2-D grids: every iteration in one workgroup; it leaves psi in buffer 0
+  const size_t lds =
+      (nd != 2 || (o.flags & FS1_FLAG_NO_RESIDENT)) ? 0 : res2d_lds(dims[0], dims[1], dt, lg);
   bool resident = false;
   if (lds > 0) {
     Res2Args ra{};
@@ -1037,15 +1067,15 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     ra.eG = b.eG[0];
     ra.ctrl = b.ctrl;
     ra.err_hist = o.err_history;
-    ra.n1 = int(n1);
-    ra.n2 = int(n2);
+    ra.n1 = int(dims[0]);
+    ra.n2 = int(dims[1]);
     ra.itr_max = o.itr_max;
     ra.check_every = o.check_every;
     ra.tol = tol;
-    ra.lam1 = std::exp(-h1 / eps);
-    ra.lam2 = std::exp(-h2 / eps);
-    ra.xlam1 = make_decay(1.0, h1 / eps);
-    ra.xlam2 = make_decay(1.0, h2 / eps);
+    ra.lam1 = std::exp(-h[0] / eps);
+    ra.lam2 = std::exp(-h[1] / eps);
+    ra.xlam1 = make_decay(1.0, h[0] / eps);
+    ra.xlam2 = make_decay(1.0, h[1] / eps);
     hipError_t e;
     if (lg) {
       e = dt == FS1_F64 ? launch_res2d<double, true>(ra, lds, s)
@@ -1086,7 +1116,7 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
   const int l_final = (hc->done && hc->stop_iter >= 0) ? hc->stop_iter : o.itr_max;
   const int gbuf = resident ? 0 : (l_final & 1);
   HIP_TRY(dispatch2(dt, lg,
-                    [&](auto ops) { return decltype(ops)::finalize(g, b, gbuf, h1, h2, s); }));
+                    [&](auto ops) { return decltype(ops)::finalize(g, b, gbuf, h, s); }));
   if (o.flags & FS1_FLAG_POTENTIALS) {
     const int* ea = lg ? b.eF : nullptr;
     const int* eb = lg ? b.eG[gbuf] : nullptr;
@@ -1101,16 +1131,24 @@ int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64
     }
     HIP_TRY(hipGetLastError());
   }
-  double sums[4];
-  HIP_TRY(hipMemcpyAsync(sums, b.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
+  double sums[2 + kMaxDim];
+  HIP_TRY(hipMemcpyAsync(sums, b.sums, sizeof(double) * (2 + nd), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   out->marginal_err = sums[0];
   out->mu_err = sums[1];
-  out->w1 = sums[2] + sums[3];
+  out->w1 = 0.0;
+  for (int a = 0; a < nd; ++a) out->w1 += sums[2 + a];
   out->iterations = l_final;
   out->converged = !(sums[0] > tol) ? 1 : 0;
   return finish((std::isfinite(out->w1) && std::isfinite(out->marginal_err)) ? FS1_OK
                                                                              : FS1_ERR_NONFINITE);
+}
+
+int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2, double h1,
+             double h2, double eps, double tol, const fs1_opts& o, fs1_result* out) {
+  const int64_t dims[2] = {n1, n2};
+  const double h[2] = {h1, h2};
+  return solve_grid(ctx, mu, nu, 2, dims, h, eps, tol, o, out);
 }
 
 }  // namespace fs1

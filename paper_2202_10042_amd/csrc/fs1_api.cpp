@@ -1024,6 +1024,49 @@ int fs1_kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2
   return fs1::kv_apply_2d(ctx, x, y, n1, n2, h1, h2, eps, dt);
 }
 
+int fs1_kv_apply_nd(fs1_ctx* ctx, const void* x, void* y, int ndim, const int64_t* dims,
+                    const double* h, double eps, int dt) {
+  return fs1::kv_apply_grid(ctx, x, y, ndim, dims, h, eps, dt);
+}
+
+// the defaulting and checks of the grid solves before their bodies
+static bool grid_solve_prologue(fs1_ctx* ctx, const double* mu, const double* nu,
+                                const fs1_opts* opts_in, fs1_result* out, fs1_opts* o,
+                                int* st) {
+  if (!ctx) {
+    *st = set_err(FS1_ERR_INVALID_ARG, "null context");
+    return false;
+  }
+  if (!out) {
+    *st = set_err(FS1_ERR_INVALID_ARG, "null result pointer");
+    return false;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->w1 = NAN;
+  out->marginal_err = NAN;
+  out->mu_err = NAN;
+  fs1_opts_default(o);
+  if (opts_in) *o = *opts_in;
+  if (o->itr_max < 0) o->itr_max = 10000;
+  if (o->check_every < 1) o->check_every = 1;
+  if (o->sync_every < 1) o->sync_every = 16;
+  if ((mu && !aligned16(mu)) || (nu && !aligned16(nu))) {
+    out->status = set_err(FS1_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
+    *st = out->status;
+    return false;
+  }
+  return true;
+}
+
+int fs1_solve_nd(fs1_ctx* ctx, const double* mu, const double* nu, int ndim, const int64_t* dims,
+                 const double* h, double eps, double tol, const fs1_opts* opts_in,
+                 fs1_result* out) {
+  fs1_opts o;
+  int st = FS1_OK;
+  if (!grid_solve_prologue(ctx, mu, nu, opts_in, out, &o, &st)) return st;
+  return fs1::solve_grid(ctx, mu, nu, ndim, dims, h, eps, tol, o, out);
+}
+
 int fs1_solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2,
                  double h1, double h2, double eps, double tol, const fs1_opts* opts_in,
                  fs1_result* out) {

@@ -85,12 +85,16 @@ struct Carve {
 
 }  // namespace host
 
-// Two-dimensional FS-1 (fs1_2d.hip): the bodies of fs1_kv_apply_2d and
-// fs1_solve_2d (opts already defaulted, *out cleared).
+// FS-1 on grids (fs1_2d.hip): the bodies of fs1_kv_apply_2d / _nd and
+// fs1_solve_2d / _nd (opts already defaulted, *out cleared).
 int kv_apply_2d(fs1_ctx* ctx, const void* x, void* y, int64_t n1, int64_t n2, double h1,
                 double h2, double eps, int dt);
 int solve_2d(fs1_ctx* ctx, const double* mu, const double* nu, int64_t n1, int64_t n2, double h1,
              double h2, double eps, double tol, const fs1_opts& o, fs1_result* out);
+int kv_apply_grid(fs1_ctx* ctx, const void* x, void* y, int nd, const int64_t* dims,
+                  const double* h, double eps, int dt);
+int solve_grid(fs1_ctx* ctx, const double* mu, const double* nu, int nd, const int64_t* dims,
+               const double* h, double eps, double tol, const fs1_opts& o, fs1_result* out);
 
 }  // namespace fs1
 

@@ -47,7 +47,7 @@ EXPORTS = (
     "fs1_server_opts_default", "fs1_server_create", "fs1_server_destroy", "fs1_server_submit",
     "fs1_server_step", "fs1_server_poll", "fs1_server_get_info", "fs1_kv_apply_2d",
     "fs1_solve_2d", "fs1_stream_copy", "fs1_solve_noalloc", "fs1_ctx_create_with_allocator",
-    "fs1_solve_async", "fs1_solve_batched_config",
+    "fs1_solve_async", "fs1_solve_batched_config", "fs1_kv_apply_nd", "fs1_solve_nd",
 )
 
 # fs1_alloc_fn / fs1_free_fn
@@ -194,6 +194,11 @@ def load(path: str = LIB_PATH):
     lib.fs1_solve_2d.argtypes = [vp, vp, vp, i64, i64, d, d, d, d, ctypes.POINTER(Opts),
                                  ctypes.POINTER(CResult)]
     lib.fs1_solve_2d.restype = ctypes.c_int
+    lib.fs1_kv_apply_nd.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, d, ctypes.c_int]
+    lib.fs1_kv_apply_nd.restype = ctypes.c_int
+    lib.fs1_solve_nd.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, d, d, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(CResult)]
+    lib.fs1_solve_nd.restype = ctypes.c_int
     lib.fs1_solve_batched_config.argtypes = [vp, vp, vp, ctypes.POINTER(i64), i32, vp, vp,
                                              ctypes.POINTER(Opts), ctypes.POINTER(i32),
                                              ctypes.POINTER(i32), ctypes.POINTER(CResult)]
@@ -527,6 +532,72 @@ def fs1_solve_2d(mu, nu, n1: int, n2: int, h1: float, h2: float, eps: float, tol
     st = load().fs1_solve_2d(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), int(n1), int(n2),
                              float(h1), float(h2), float(eps), float(tol), ctypes.byref(o),
                              ctypes.byref(r))
+    if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
+            raise_on_error and st != FS1_OK):
+        raise Fs1Error(st, last_error())
+    res = Result(r.w1, r.marginal_err, r.mu_err, r.iterations, bool(r.converged), st)
+    if pot is not None and st == FS1_OK:
+        res.F, res.G = pot[:n], pot[n:]
+    if hist is not None:
+        res.err_history = hist
+    return res
+
+
+def _dims_h(dims, h):
+    if len(dims) != len(h):
+        raise ValueError("dims and h must have the same length")
+    cd = (ctypes.c_int64 * max(1, len(dims)))(*[int(v) for v in dims])
+    ch = (ctypes.c_double * max(1, len(h)))(*[float(v) for v in h])
+    n = 1
+    for v in dims:
+        n *= int(v)
+    return cd, ch, n
+
+
+def fs1_kv_apply_nd(x, dims: Sequence[int], h: Sequence[float], eps: float, out=None,
+                    ctx: Optional[Context] = None):
+    """y = K x on an n_0 x ... x n_{D-1} grid (first axis fastest),
+    K = exp(-sum_a |i_a - j_a| h_a / eps)  (float64 or float32)."""
+    import torch
+    ctx = ctx or default_context()
+    cd, ch, n = _dims_h(dims, h)
+    if x.numel() != n:
+        raise ValueError("x must hold prod(dims) entries")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(load().fs1_kv_apply_nd(ctx.handle, _dev(x, "x"), _dev(out, "out"), len(dims),
+                                  ctypes.addressof(cd), ctypes.addressof(ch), float(eps),
+                                  _dtype_code(x)))
+    return out
+
+
+def fs1_solve_nd(mu, nu, dims: Sequence[int], h: Sequence[float], eps: float, tol: float,
+                 itr_max: int = 10000, dtype: str = "f64", check_every: int = 1,
+                 sync_every: int = 16, potentials: bool = False, err_history: bool = False,
+                 solver: str = "auto", ctx: Optional[Context] = None,
+                 raise_on_error: bool = False, domain: str = "plain") -> Result:
+    """Algorithm 2 on D axes (first axis fastest) on device float64 marginals
+    of prod(dims) entries; arguments as fs1_solve_2d (solver "auto" takes the
+    one-workgroup form only for D = 2)."""
+    import torch
+    ctx = ctx or default_context()
+    cd, ch, n = _dims_h(dims, h)
+    if mu.numel() != n or nu.numel() != n:
+        raise ValueError("mu and nu must hold prod(dims) entries")
+    o = make_opts(None, itr_max, dtype, domain, check_every, sync_every)
+    o.flags |= {"auto": 0, "lines": FS1_FLAG_NO_RESIDENT}[solver]
+    pot = hist = None
+    if potentials:
+        pot = torch.empty(2 * n, dtype=torch.float64, device=mu.device)
+        o.flags |= FS1_FLAG_POTENTIALS
+        o.potentials_out = pot.data_ptr()
+    if err_history:
+        hist = torch.empty(itr_max + 1, dtype=torch.float64, device=mu.device)
+        o.err_history = hist.data_ptr()
+    r = CResult()
+    st = load().fs1_solve_nd(ctx.handle, _dev(mu, "mu"), _dev(nu, "nu"), len(dims),
+                             ctypes.addressof(cd), ctypes.addressof(ch), float(eps), float(tol),
+                             ctypes.byref(o), ctypes.byref(r))
     if st == FS1_ERR_INVALID_ARG or st == FS1_ERR_HIP or st == FS1_ERR_NO_MEMORY or (
             raise_on_error and st != FS1_OK):
         raise Fs1Error(st, last_error())

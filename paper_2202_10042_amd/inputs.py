@@ -124,6 +124,17 @@ def paper_uniform_2d(n1: int, n2: int, seed: int) -> tuple[np.ndarray, np.ndarra
     return u / u.sum(), v / v.sum()
 
 
+def paper_uniform_nd(dims, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """The Sec. 5.3 recipe on a grid of any number of axes: u, v ~ U[0,1] at
+    every grid point, each L1-normalised, flattened with the first axis
+    fastest."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(dims))
+    u = rng.uniform(0.0, 1.0, size=n)
+    v = rng.uniform(0.0, 1.0, size=n)
+    return u / u.sum(), v / v.sum()
+
+
 def product_pair_2d(n1: int, n2: int, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """Product histograms mu = mu1 (x) mu2, nu = nu1 (x) nu2 from the 1-D
     mixtures of n1 (seed s) and n2 (seed s + 2) points, column-major."""
