@@ -130,6 +130,7 @@ struct fs1_server {
   int* hcount = nullptr;
   std::deque<Request> queue;
   std::vector<Active> act;     // by instance slot
+  std::vector<char> retiring;  // by instance slot: stopped, being finalised
   std::vector<int> free_inst;
   std::map<int, std::vector<ChunkRef>> running;  // run length -> chunks of admitted requests
   std::vector<BatchGroup> groups;           // the launch groups over alist
@@ -337,10 +338,25 @@ int retire(fs1_server* v, int32_t* produced) {
   for (int64_t k = v->consumed; k < total; ++k) {
     const int b = v->hring[k % cap];
     v->hilist[count++] = b;
-    const Active& a = v->act[b];
-    std::vector<ChunkRef>& l = fin[a.R];
-    for (const ChunkRef& r : v->running[a.R])
-      if (r.b == b) l.push_back(r);
+    v->retiring[b] = 1;
+  }
+  // one stable pass per run length: the stopped requests' chunks go to the
+  // finalisation lists (each request's in chunk order; a chunk's finalisation
+  // reads only what earlier launches published, so the order across requests
+  // does not matter), the others stay in the running lists in their order
+  for (auto& kv : v->running) {
+    std::vector<ChunkRef>& rl = kv.second;
+    std::vector<ChunkRef>* l = nullptr;
+    size_t w = 0;
+    for (const ChunkRef& r : rl) {
+      if (v->retiring[r.b]) {
+        if (!l) l = &fin[kv.first];
+        l->push_back(r);
+      } else {
+        rl[w++] = r;
+      }
+    }
+    rl.resize(w);
   }
   v->consumed = total;
   HIP_TRY(hipMemcpyAsync(v->dilist, v->hilist, count * sizeof(int), hipMemcpyHostToDevice, s));
@@ -361,12 +377,10 @@ int retire(fs1_server* v, int32_t* produced) {
     c.admitted_step = a.admitted_step;
     c.completed_step = v->steps;
     v->done.push_back(c);
-    // give the request's resources back and drop its chunks from the launches
+    // give the request's resources back (its chunks left the launches above)
     v->slots.release(a.slot0, a.nslot);
     v->chunks.release(a.chunk0, a.nch);
-    std::vector<ChunkRef>& rl = v->running[a.R];
-    rl.erase(std::remove_if(rl.begin(), rl.end(), [&](const ChunkRef& r) { return r.b == b; }),
-             rl.end());
+    v->retiring[b] = 0;
     a = Active{};
     v->free_inst.push_back(b);
     --v->nactive;
@@ -474,6 +488,7 @@ int fs1_server_create(fs1_ctx* ctx, const fs1_server_opts* oin, fs1_server** out
   v->slots.reset(v->nslots);
   v->chunks.reset(v->nslots);
   v->act.assign(ni, Active{});
+  v->retiring.assign(ni, 0);
   for (int b = o.max_active - 1; b >= 0; --b) v->free_inst.push_back(b);
   e = hipMemsetAsync(v->z.iter_base, 0, 2 * sizeof(int), ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
