@@ -32,13 +32,13 @@
 #include "fs1_device.h"
 #include "fs1_host.h"
 #include "fs1_internal.h"
+#include "fs1_xcd.h"
 
 namespace fs1 {
 
 namespace {
 
 constexpr int kR2 = 8;  // entries per thread of a line
-constexpr uint32_t kXcds = 8;  // accelerator complex dies of the device
 
 enum LineMode { L_APPLY = 0, L_COST = 1, L_UPDATE = 2, L_ERR = 3, L_DOT = 4, L_COSTDOT = 5 };
 
@@ -97,13 +97,9 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     __syncthreads();
     if (sstop) return;
   }
-  // Workgroups go to the XCDs round-robin (workgroup b to XCD b mod 8), each
-  // with its own L2: give every XCD a contiguous range of lines, so that the
-  // adjacent lines of a strided axis (whose entries share cache lines) run in
-  // one L2.  A bijection of [0, gridDim.x).
-  const uint32_t nb = gridDim.x, wb = blockIdx.x;
-  const uint32_t per = nb / kXcds, rem = nb % kXcds, xcd = wb % kXcds;
-  const uint32_t line = xcd * per + min(xcd, rem) + wb / kXcds;
+  // every XCD a contiguous range of lines: the adjacent lines of a strided
+  // axis, whose entries share cache lines, run in one L2
+  const uint32_t line = xcd_contiguous(blockIdx.x, gridDim.x);
   const uint32_t inner = uint32_t(a.inner);
   const int64_t base = int64_t(line % inner) + int64_t(line / inner) * a.outer;
   const int p0 = int(threadIdx.x) * R;

@@ -21,6 +21,7 @@
 #include "fs1_frame.h"
 #include "fs1_internal.h"
 #include "fs1_resident.h"
+#include "fs1_xcd.h"
 
 namespace fs1 {
 
@@ -184,7 +185,9 @@ __global__ __launch_bounds__(kBlock) void k_bhalf(BArgs a) {
   __shared__ XF64 scar[2];
   __shared__ XF64 red4[kNW];
   __shared__ int sdec;
-  const ChunkRef r = a.list[blockIdx.x];
+  // every XCD a contiguous range of the list: an instance's consecutive
+  // chunks read the same published aggregates from one L2
+  const ChunkRef r = a.list[xcd_contiguous(blockIdx.x, gridDim.x)];
   const InstInfo& in = a.inst[r.b];
   InstState& st = a.st[r.b];
   const int lane = threadIdx.x & (kWave - 1);
