@@ -352,7 +352,8 @@ int fs1_kv_apply_2d(fs1_ctx *ctx, const void *x, void *y, int64_t n1, int64_t n2
  * stabilisation carried to Algorithm 2: every scaling entry held as a
  * mantissa and a binary exponent, so no product underflows at small eps; the
  * same iterates in exact arithmetic; 16 bytes more workspace per grid
- * point); FS1_ABSORB is FS1_ERR_INVALID_ARG.  A small grid (n1 n2 <= 4096;
+ * point); FS1_ABSORB is FS1_ERR_INVALID_ARG.  A small grid (n1 n2 <= 4096,
+ * or up to 8192 in the plain domain where three n1 x n2 arrays fit in LDS;
  * n1 + n2 <= 384 in the plain domain, <= 80 (binary64) or 128 (binary32) in
  * the log domain) runs the whole solve in one workgroup (the paper's
  * sequential recursions, the two directions of a line on two threads) unless

@@ -274,8 +274,9 @@ __global__ void k_zero_int(int* a, int64_t n) {
 // ---------------------------------------------------------------------------
 // Small grids (n1 n2 <= 4096, short lines): the whole of Algorithm 2 in one
 // workgroup of NT threads (the fewest of 64, 256, 1024 that hold the grid at 4
-// entries each).  Thread t keeps the entries t + NT r (r < 4) of phi, psi, mu
-// and nu in registers; a product K v goes through three LDS arrays (columns
+// entries each; in the plain domain up to 8192 points at 8 entries on 1024
+// threads, where the three LDS arrays fit).  Thread t keeps the entries
+// t + NT r (r < P) of phi, psi, mu and nu in registers; a product K v goes through three LDS arrays (columns
 // padded to an odd length), one pass per axis, with the paper's sequential
 // recursions along each line (Sec. 3: p_k = lambda p_{k-1} + x_k and the
 // backward sum), the two directions of a line run side by side by two
@@ -290,6 +291,8 @@ __global__ void k_zero_int(int* a, int64_t n) {
 // ---------------------------------------------------------------------------
 constexpr int kRes2MaxThreads = 1024;
 constexpr int kRes2Per = 4;  // entries per thread: n1 n2 <= 4 x threads (64, 256 or 1024)
+// plain domain, 4097 .. 8192 grid points: 8 entries on each of 1024 threads
+constexpr int kRes2PerWide = 8;
 
 // Largest n1 + n2 for the one-workgroup solver (an iteration walks both line
 // lengths sequentially, while the per-line launches take about 20 us (log
@@ -420,7 +423,7 @@ __device__ __forceinline__ XF<T> seq_combine_x(const T* Y, const int* YE, const 
 
 constexpr int GX64 = 2;  // group of the binary64 log-domain recursions at 1024 threads
 
-template <typename T, int NT, bool SC>
+template <typename T, int NT, bool SC, int P>
 __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   extern __shared__ __align__(16) unsigned char lds2[];
   __shared__ double red[NT / kWave];
@@ -439,10 +442,10 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   const int t = threadIdx.x;
   // LDS position of the entries t + NT r, and whether each is the last of its
   // column / of its row
-  int off[kRes2Per];
-  bool last1[kRes2Per], last2[kRes2Per];
+  int off[P];
+  bool last1[P], last2[P];
 #pragma unroll
-  for (int r = 0; r < kRes2Per; ++r) {
+  for (int r = 0; r < P; ++r) {
     const int e = t + NT * r;
     const int i = e % a.n1, j = e / a.n1;
     off[r] = i + ld * j;
@@ -451,22 +454,23 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   }
   const T lam1 = T(a.lam1), lam2 = T(a.lam2);
   const XF<T> xl1{T(a.xlam1.m), a.xlam1.e}, xl2{T(a.xlam2.m), a.xlam2.e};
-  T ph[kRes2Per], ps[kRes2Per], mu[kRes2Per], nu[kRes2Per];
-  int phe[kRes2Per], pse[kRes2Per];  // log domain: exponents of ph, ps
-  double nu64[kRes2Per];  // the stopping test's binary64 nu, kept in registers
+  T ph[P], ps[P], mu[P], nu[P];
+  int phe[P], pse[P];  // log domain: exponents of ph, ps
+  // the stopping test's binary64 nu (binary64 scalings: nu itself)
+  double nu64[sizeof(T) == 8 ? 1 : P];
 #pragma unroll
-  for (int r = 0; r < kRes2Per; ++r) {
+  for (int r = 0; r < P; ++r) {
     const int e = t + NT * r;
     const bool in = e < n;
     ph[r] = in ? static_cast<const T*>(a.vF)[e] : T(0);
     ps[r] = in ? static_cast<const T*>(a.vG)[e] : T(0);
     phe[r] = (SC && in) ? a.eF[e] : 0;
     pse[r] = (SC && in) ? a.eG[e] : 0;
-    nu64[r] = in ? a.nu[e] : 0.0;
     if constexpr (sizeof(T) == 8) {
       mu[r] = in ? T(a.mu[e]) : T(0);
-      nu[r] = T(nu64[r]);
+      nu[r] = in ? T(a.nu[e]) : T(0);
     } else {
+      nu64[r] = in ? a.nu[e] : 0.0;
       mu[r] = in ? T(a.mu32[e]) : T(0);
       nu[r] = in ? T(a.nu32[e]) : T(0);
     }
@@ -480,11 +484,11 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   // pm (and pe): the recursions along the columns (X -> Y, Z), their
   // combination into X, the recursions along the rows (X -> Y, Z), and the
   // combination of those at the thread's own entries
-  T pm[kRes2Per];
-  int pe[kRes2Per];
+  T pm[P];
+  int pe[P];
   auto product = [&](const T* v, const int* ve) {
 #pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
+    for (int r = 0; r < P; ++r) {
       const int e = t + NT * r;
       if (e < n) {
         X[off[r]] = v[r];
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     seq_axis<T, NT, G, SC>(X, XE, Y, YE, Z, ZE, a.n2, ld, a.n1, 1, lam1, xl1);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
+    for (int r = 0; r < P; ++r) {
       const int e = t + NT * r;
       if (e < n) {
         if constexpr (SC) {
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     seq_axis<T, NT, G, SC>(X, XE, Y, YE, Z, ZE, a.n1, 1, a.n2, ld, lam2, xl2);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
+    for (int r = 0; r < P; ++r) {
       const int e = t + NT * r;
       if (e < n) {
         if constexpr (SC) {
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
   auto update = [&](T* v, int* ve, const T* marg) {
     bool bad = false;
 #pragma unroll
-    for (int r = 0; r < kRes2Per; ++r) {
+    for (int r = 0; r < P; ++r) {
       const int e = t + NT * r;
       if (e < n) {
         const T q = (marg[r] == T(0)) ? T(0) : marg[r] / pm[r];
@@ -553,12 +557,12 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     if ((l % a.check_every) == 0) {
       double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < kRes2Per; ++r) {
+      for (int r = 0; r < P; ++r) {
         const int e = t + NT * r;
         if (e < n) {
           double pv = double(ps[r]) * double(pm[r]);
           if constexpr (SC) pv = ldexp(pv, pse[r] + pe[r]);
-          s += fabs(pv - nu64[r]);
+          s += fabs(pv - (sizeof(T) == 8 ? double(nu[r]) : nu64[sizeof(T) == 8 ? 0 : r]));
         }
       }
       const double tot = block_sum<NT / kWave>(s, red);
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_res2d(Res2Args a) {
     }
   }
 #pragma unroll
-  for (int r = 0; r < kRes2Per; ++r) {
+  for (int r = 0; r < P; ++r) {
     const int e = t + NT * r;
     if (e < n) {
       static_cast<T*>(a.vF)[e] = ph[r];
@@ -618,9 +622,16 @@ int res2d_threads(int64_t n) {
   return 0;
 }
 
+// entries per thread: kRes2Per, or kRes2PerWide (plain domain, 1024 threads)
+// for grids beyond 4 x 1024 points; 0 if the grid does not fit either
+int res2d_per(int64_t n, bool log_domain) {
+  if (res2d_threads(n) != 0) return kRes2Per;
+  return (!log_domain && n <= int64_t(kRes2MaxThreads) * kRes2PerWide) ? kRes2PerWide : 0;
+}
+
 size_t res2d_lds(int64_t n1, int64_t n2, int dt, bool log_domain) {
   const int64_t n = n1 * n2;
-  if (res2d_threads(n) == 0) return 0;
+  if (res2d_per(n, log_domain) == 0) return 0;
   // an iteration walks both line lengths sequentially: beyond this the
   // per-line launches (fixed cost per pass) are faster
   const int64_t span = !log_domain ? kRes2MaxSpan
@@ -638,23 +649,29 @@ size_t res2d_lds(int64_t n1, int64_t n2, int dt, bool log_domain) {
   return bytes + 1024 <= size_t(lim) ? bytes : 0;
 }
 
-template <typename T, int NT, bool SC>
+template <typename T, int NT, bool SC, int P>
 hipError_t launch_res2d_t(const Res2Args& a, size_t lds, hipStream_t s) {
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_res2d<T, NT, SC>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_res2d<T, NT, SC, P>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  k_res2d<T, NT, SC><<<1, NT, lds, s>>>(a);
+  k_res2d<T, NT, SC, P><<<1, NT, lds, s>>>(a);
   return hipGetLastError();
 }
 
 template <typename T, bool SC>
 hipError_t launch_res2d(const Res2Args& a, size_t lds, hipStream_t s) {
-  switch (res2d_threads(int64_t(a.n1) * a.n2)) {
-    case 64: return launch_res2d_t<T, 64, SC>(a, lds, s);
-    case 256: return launch_res2d_t<T, 256, SC>(a, lds, s);
-    case kRes2MaxThreads: return launch_res2d_t<T, kRes2MaxThreads, SC>(a, lds, s);
+  const int64_t n = int64_t(a.n1) * a.n2;
+  if constexpr (!SC) {
+    if (res2d_per(n, false) == kRes2PerWide)
+      return launch_res2d_t<T, kRes2MaxThreads, SC, kRes2PerWide>(a, lds, s);
+  }
+  switch (res2d_threads(n)) {
+    case 64: return launch_res2d_t<T, 64, SC, kRes2Per>(a, lds, s);
+    case 256: return launch_res2d_t<T, 256, SC, kRes2Per>(a, lds, s);
+    case kRes2MaxThreads: return launch_res2d_t<T, kRes2MaxThreads, SC, kRes2Per>(a, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

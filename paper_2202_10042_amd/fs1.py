@@ -509,7 +509,8 @@ def fs1_solve_2d(mu, nu, n1: int, n2: int, h1: float, h2: float, eps: float, tol
     """Algorithm 2 (2-D FS-1) on device float64 marginals of n1 * n2 entries
     (column-major).  domain: "plain" (Algorithm 2's arithmetic) or "log" (its
     stabilised form: scalings as mantissas with per-entry binary exponents).
-    solver: "auto" (one workgroup for small grids: n1 n2 <= 4096 and n1 + n2
+    solver: "auto" (one workgroup for small grids: n1 n2 <= 4096, or up to
+    8192 in the plain domain where the grid's three LDS arrays fit, and n1 + n2
     <= 384 in the plain domain, <= 80 (binary64) or 128 (binary32) in the log
     domain; else one launch per line pass) or "lines" (always the per-line
     launches)."""

@@ -96,7 +96,8 @@ SOLVERS = ["auto", "lines"]
     (13, 7, 0.1, 0.15, 0.05, 30, True), (1, 40, 0.5, 0.02, 0.03, 25, True),
     (40, 1, 0.02, 0.5, 0.03, 25, True), (24, 31, 1.0 / 24, 1.0 / 31, 0.01, 60, True),
     (150, 90, 1.0 / 150, 1.0 / 90, 5e-3, 40, False), (300, 200, 0.003, 0.005, 0.01, 20, False),
-    (2100, 4, 5e-4, 0.3, 0.05, 10, False), (12, 300, 0.05, 0.003, 0.02, 15, False)])
+    (2100, 4, 5e-4, 0.3, 0.05, 10, False), (12, 300, 0.05, 0.003, 0.02, 15, False),
+    (70, 81, 1.0 / 70, 1.0 / 81, 0.01, 20, False)])
 def test_solve_2d_fixed_iterations(n1, n2, h1, h2, eps, its, dense, solver):
     fs1 = _fs1()
     mu, nu = inputs.product_pair_2d(n1, n2, 3, n1 + n2)
@@ -201,7 +202,8 @@ def test_solve_2d_f32_against_f64_oracle(solver):
     # plain binary32 holds scalings up to about e^88, which the iteration
     # exceeds at small eps (they grow like e^(W/eps)): moderate eps here
     fs1 = _fs1()
-    for n1, n2, eps, its in ((64, 48, 0.1, 50), (700, 300, 0.08, 20)):
+    # (90, 85): 7650 points, 8 per thread in one workgroup under "auto"
+    for n1, n2, eps, its in ((64, 48, 0.1, 50), (90, 85, 0.1, 30), (700, 300, 0.08, 20)):
         mu, nu = inputs.product_pair_2d(n1, n2, 3, 5)
         rng = np.random.default_rng(4)
         mu = mu * (1 + 0.2 * rng.random(mu.size)); mu /= mu.sum()
