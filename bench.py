@@ -686,7 +686,8 @@ def serve_stream(fs1, ctx, inputs, np, torch, rate: float, seconds: float, seed:
     second over `seconds`; request i (in arrival order) is a distinct seeded
     mixture pair (N log-uniform in [128, 2^20], eps from {1e-2, 1e-3}, 3-5
     components, seeds base + 1000 + 2 i), generated on the device when the
-    client hands it to the server, tol 1e-6, binary32 scans, 64 GB budget.
+    client hands it to the server, tol 1e-6, binary32 scans, 64 GB budget,
+    overlapped steps (a step returns with its iterations enqueued).
     The client keeps arrived requests in its own queue and hands them over
     while the server's queue holds fewer than `hand_cap`; a request's latency
     runs from its arrival to the poll that returns its completion.  With
@@ -695,7 +696,7 @@ def serve_stream(fs1, ctx, inputs, np, torch, rate: float, seconds: float, seed:
     arr = inputs.poisson_arrivals(rate, seconds, seed)
     spec = inputs.batch_spec(len(arr), 128, 1 << 20, [1e-2, 1e-3], seed)
     srv = fs1.Server(hbm_budget=64 << 30, max_active=4096, dtype="f32", itr_max=10000,
-                     iters_per_step=16, ctx=ctx)
+                     iters_per_step=16, overlap=True, ctx=ctx)
     arrival_of = {}
     lat = []
     capped = 0
@@ -776,7 +777,7 @@ def serving_study(fs1, ctx, inputs, np, torch, seconds: float, full: bool = True
     out["highest_rate_meeting_p99"] = max(ok) if ok else None
     out["config"] = {"n_lo": 128, "n_hi": 1 << 20, "eps": [1e-2, 1e-3], "tol": 1e-6,
                      "hbm_budget_bytes": 64 << 30, "dtype": "f32", "iters_per_step": 16,
-                     "max_active": 4096, "seed": seed,
+                     "max_active": 4096, "overlapped_steps": True, "seed": seed,
                      "pairs": "distinct: request i of a run is seeded base + 1000 + 2 i and "
                               "generated on the device when handed to the server"}
     return out

@@ -169,6 +169,7 @@ int fs1_kv_apply_log(fs1_ctx *ctx, const void *lx, void *ly, int64_t n, double h
 #define FS1_FLAG_NO_GRAPH 8
 #define FS1_FLAG_NO_RESIDENT 16
 #define FS1_FLAG_DEVICE_PARAMS 32
+#define FS1_FLAG_SERVER_OVERLAP 64
 
 typedef struct {
     double h;             /* grid spacing; <= 0 selects 1/n                         */
@@ -423,7 +424,12 @@ typedef struct {
     int32_t check_every;     /* as fs1_opts (>= 1)                                  */
     int32_t iters_per_step;  /* iterations per fs1_server_step (>= 1)              */
     int32_t flags;           /* FS1_FLAG_NO_GRAPH: launch the kernels directly
-                                instead of replaying a captured graph              */
+                                instead of replaying a captured graph;
+                                FS1_FLAG_SERVER_OVERLAP: fs1_server_step returns
+                                once its iterations are enqueued, and the next
+                                call finalises the requests they stopped (so the
+                                caller's own work between calls overlaps the
+                                device's); every request's result is the same  */
 } fs1_server_opts;
 
 typedef struct {
@@ -465,7 +471,10 @@ int fs1_server_submit(fs1_server *srv, const double *mu, const double *nu, int64
 /* One step: admit queued requests (in order, stopping at the first that does
  * not fit), run iters_per_step iterations of every admitted request, finalise
  * the ones that stopped.  Blocks until the step's work is done.  *completed (may
- * be NULL) receives the number of completions this step produced. */
+ * be NULL) receives the number of completions this step produced.  With
+ * FS1_FLAG_SERVER_OVERLAP the step first waits for the previous call's
+ * iterations and finalises the requests they stopped (those are this call's
+ * completions), then admits and enqueues its own iterations and returns. */
 int fs1_server_step(fs1_server *srv, int32_t *completed);
 /* Move up to max completions, oldest first, into out (host array); *count
  * receives how many. */

@@ -139,6 +139,7 @@ struct fs1_server {
   std::deque<fs1_completion> done;
   hipGraphExec_t gexec = nullptr;
   bool dirty = true;
+  bool inflight = false;  // FS1_FLAG_SERVER_OVERLAP: iterations enqueued, not yet retired
 };
 
 namespace {
@@ -534,12 +535,23 @@ int fs1_server_submit(fs1_server* v, const double* mu, const double* nu, int64_t
 int fs1_server_step(fs1_server* v, int32_t* completed) {
   if (!v) return set_err(FS1_ERR_INVALID_ARG, "null server");
   if (completed) *completed = 0;
+  const bool overlap = (v->o.flags & FS1_FLAG_SERVER_OVERLAP) != 0;
+  if (v->inflight) {
+    // the previous call's iterations: wait for them and finalise what they stopped
+    v->inflight = false;
+    const int st = retire(v, completed);
+    if (st) return st;
+  }
   if (v->queue.empty() && v->nactive == 0) return FS1_OK;
   int st = admit(v);
   if (st) return st;
   st = run_iterations(v);
   if (st) return st;
   ++v->steps;
+  if (overlap) {
+    v->inflight = true;
+    return FS1_OK;
+  }
   return retire(v, completed);
 }
 

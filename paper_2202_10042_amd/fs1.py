@@ -38,6 +38,7 @@ FS1_FLAG_PERSISTENT = 4
 FS1_FLAG_NO_GRAPH = 8
 FS1_FLAG_NO_RESIDENT = 16
 FS1_FLAG_DEVICE_PARAMS = 32
+FS1_FLAG_SERVER_OVERLAP = 64
 
 # every symbol include/fs1.h declares
 EXPORTS = (
@@ -669,11 +670,13 @@ def fs1_solve_batched(mu_packed, nu_packed, offsets: Sequence[int], eps: Sequenc
 class Server:
     """Request loop with continuous batching (fs1_server_*): submit device
     marginal pairs, call step() repeatedly, poll() completions.  The binding
-    keeps each request's tensors alive until its completion is polled."""
+    keeps each request's tensors alive until its completion is polled.
+    overlap: step() returns once its iterations are enqueued and the next
+    call reports the completions they produce (FS1_FLAG_SERVER_OVERLAP)."""
 
     def __init__(self, hbm_budget: int = 1 << 30, max_active: int = 4096, dtype: str = "f32",
                  itr_max: int = 10000, check_every: int = 1, iters_per_step: int = 16,
-                 graph: bool = True, ctx: Optional[Context] = None):
+                 graph: bool = True, overlap: bool = False, ctx: Optional[Context] = None):
         lib = load()
         self.ctx = ctx or default_context()
         o = ServerOpts()
@@ -684,7 +687,7 @@ class Server:
         o.itr_max = int(itr_max)
         o.check_every = int(check_every)
         o.iters_per_step = int(iters_per_step)
-        o.flags = 0 if graph else FS1_FLAG_NO_GRAPH
+        o.flags = (0 if graph else FS1_FLAG_NO_GRAPH) | (FS1_FLAG_SERVER_OVERLAP if overlap else 0)
         h = ctypes.c_void_p()
         _check(lib.fs1_server_create(self.ctx.handle, ctypes.byref(o), ctypes.byref(h)))
         self.handle = h

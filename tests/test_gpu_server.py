@@ -91,6 +91,34 @@ def test_server_results_equal_alone_and_in_the_mix(dtype):
         assert _same(b, r_alone), (i, b, r_alone)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_server_overlapped_steps_same_results(dtype):
+    # FS1_FLAG_SERVER_OVERLAP: a step returns with its iterations enqueued and
+    # the next call reports what they stopped; every request's result is the
+    # blocking server's, bit for bit, and each completes at the same step
+    fs1 = _fs1()
+    reqs = _requests(10, 47)
+    held = [(dev(m), dev(v), e) for m, v, e in reqs]
+    out = {}
+    for overlap in (False, True):
+        _say(f"server overlap={overlap} {dtype}")
+        srv = fs1.Server(hbm_budget=256 << 20, max_active=64, dtype=dtype, itr_max=3000,
+                         iters_per_step=16, overlap=overlap)
+        tickets = []
+        for i, (m, v, e) in enumerate(held):
+            tickets.append(srv.submit(m, v, e, 1e-6))
+            if i % 3 == 2:
+                srv.step()
+        out[overlap] = (tickets, _drain(srv))
+        srv.close()
+    (tb, blocking), (to, overlapped) = out[False], out[True]
+    assert tb == to and sorted(overlapped) == to
+    for t in to:
+        (rb, ab, cb), (ro, ao, co) = blocking[t], overlapped[t]
+        assert _same(rb, ro), (t, rb, ro)
+        assert ao == ab and co == cb
+
+
 def test_server_matches_oracle_and_converges():
     fs1 = _fs1()
     reqs = _requests(8, 5, n_hi=8000)
