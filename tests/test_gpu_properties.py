@@ -132,3 +132,29 @@ def test_batched_property(sizes, les, seed, its, f32):
             assert max(r.marginal_err, ref.marginal_err) <= (1e-6 if f32 else 1e-15)
             continue
         assert r.w1 == pytest.approx(ref.w1, rel=1e-5 if f32 else 1e-10, abs=1e-300)
+
+
+@settings(max_examples=20, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(dims=st.lists(st.integers(min_value=1, max_value=40), min_size=1, max_size=4),
+       lcs=st.lists(st.floats(min_value=math.log(1e-3), max_value=math.log(50.0)),
+                    min_size=4, max_size=4),
+       seed=st.integers(min_value=0, max_value=2 ** 31 - 1), f32=st.booleans())
+def test_kv_apply_nd_property(dims, lcs, seed, f32):
+    # the product on up to four axes against the D-axis oracle's recursions
+    # (positive inputs): 64 u per axis plus summation order, 128 u D
+    fs1 = _fs1()
+    eps = 0.05
+    h = [math.exp(lc) * eps for lc in lcs[:len(dims)]]
+    n = int(np.prod(dims))
+    _say(f"kv_nd property dims={dims} seed={seed} f32={f32}")
+    rng = np.random.default_rng(seed)
+    x = rng.random(n) + 0.1
+    tdt = torch.float32 if f32 else torch.float64
+    if f32:
+        x = x.astype(np.float32).astype(np.float64)
+    y = fs1.fs1_kv_apply_nd(dev(x, tdt), dims, h, eps).double().cpu().numpy()
+    ref = oracle.kvn_fs1(x, dims, h, eps)
+    u = U32 if f32 else U64
+    tiny = (2.0 ** -149 if f32 else 2.0 ** -1074) * 4
+    assert np.all(np.abs(y - ref) <= 128 * u * len(dims) * ref + tiny)

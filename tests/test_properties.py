@@ -85,3 +85,30 @@ def test_log_fs1_equals_dense_log_sinkhorn(n, le, seed, its):
     assert a.iterations == b.iterations
     assert a.w1 == pytest.approx(b.w1, rel=1e-10, abs=1e-300)
     assert a.marginal_err == pytest.approx(b.marginal_err, rel=1e-7, abs=1e-13)
+
+
+dims_st = st.lists(st.integers(min_value=1, max_value=7), min_size=1, max_size=4)
+
+
+@settings(max_examples=60, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(dims=dims_st, lcs=st.lists(st.floats(min_value=math.log(1e-2), max_value=math.log(40.0)),
+                                  min_size=4, max_size=4), seed=seeds)
+def test_grid_recursions_equal_dense_definition(dims, lcs, seed):
+    # Sec. 4 on D axes: the per-axis recursions against K formed entry by
+    # entry, plain and on logarithms, and the split cost against the double sum
+    eps = 0.1
+    h = [math.exp(lc) * eps for lc in lcs[:len(dims)]]
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(dims))
+    x = rng.random(n) + 0.05
+    y = oracle.kvn_fs1(x, dims, h, eps)
+    ref = oracle.kvn_dense(x, dims, h, eps)
+    assert np.all(np.abs(y - ref) <= 8 * sum(dims) * 2.0 ** -53 * ref + 1e-300)
+    ly = oracle.kvn_fs1_log(np.log(x), dims, h, eps)
+    lref = oracle.kvn_log_dense(np.log(x), dims, h, eps)
+    assert np.all(np.abs(ly - lref) <= 8 * sum(dims) * 2.0 ** -53 * (1 + np.abs(lref)))
+    psi = rng.random(n)
+    w = oracle.costn_fs1(x, psi, dims, h, eps)
+    wd = oracle.costn_dense(x, psi, dims, h, eps)
+    assert w == pytest.approx(wd, rel=1e-12, abs=1e-300)
