@@ -39,6 +39,7 @@ namespace fs1 {
 namespace {
 
 constexpr int kR2 = 8;  // entries per thread of a line
+constexpr int kGroup = 16;  // adjacent lines per workgroup on strided axes (128 B in binary64)
 
 enum LineMode { L_APPLY = 0, L_COST = 1, L_UPDATE = 2, L_ERR = 3, L_DOT = 4, L_COSTDOT = 5 };
 
@@ -69,13 +70,57 @@ struct LineArgs {
   double* err_hist;
 };
 
+// The scan of block_scan (same contract: cf the forward state just before a
+// thread's run, cb the inclusive backward state just after it) for GL lines
+// per workgroup, line gi held by the threads gi + GL q (q < NQ, in line
+// order): Hillis-Steele steps over q in LDS, the step of distance 2^s
+// weighted by dec[s] = lambda^(R 2^s).
+template <typename S, int NQ, int GL>
+struct GroupLds {
+  S f[NQ][GL];
+  S b[NQ][GL];
+};
+
+template <typename S, int NQ, int GL, typename T>
+__device__ __forceinline__ void group_scan(S tf, S tb, const Dec<T>* dec, int gi, int q, S* cf,
+                                           S* cb, GroupLds<S, NQ, GL>& g) {
+  S f = tf.norm();
+  S b = tb.norm();
+#pragma unroll
+  for (int s = 0; (1 << s) < NQ; ++s) {
+    const int d = 1 << s;
+    g.f[q][gi] = f;
+    g.b[q][gi] = b;
+    __syncthreads();
+    if (q >= d) f = f.add(g.f[q - d][gi].shift(dec[s])).norm();
+    if (q + d < NQ) b = b.add(g.b[q + d][gi].shift(dec[s])).norm();
+    __syncthreads();
+  }
+  g.f[q][gi] = f;
+  g.b[q][gi] = b;
+  __syncthreads();
+  *cf = q > 0 ? g.f[q - 1][gi] : S::zero();
+  *cb = q + 1 < NQ ? g.b[q + 1][gi] : S::zero();
+  __syncthreads();
+}
+
 // SC: the log domain (mantissas with per-entry exponents xe, ye, owne).
-template <typename T, int R, int NT, int MODE, bool SC>
+// GL: lines per workgroup.  GL = 1: one line per workgroup, thread t holding
+// its positions [t R, t R + R).  GL = kGroup (strided axes whose line starts
+// are a multiple of kGroup entries apart): kGroup adjacent lines, line gi
+// held by the threads gi + kGroup q, so that the kGroup lanes of one load
+// read kGroup adjacent entries (one whole cache line in binary64).
+template <typename T, int R, int NT, int MODE, bool SC, int GL = 1>
 __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   constexpr int NW = NT / kWave;
+  constexpr int NQ = NT / GL;            // threads per line
+  constexpr int NQG = GL == 1 ? 1 : NQ;  // size of the grouped scan's LDS
   __shared__ ScanLds<S1<T>, NW> sh;
   __shared__ ScanLds<S2<T>, NW> sh2;
+  __shared__ GroupLds<S1<T>, NQG, GL> gsh;
+  __shared__ GroupLds<S2<T>, NQG, GL> gsh2;
   __shared__ double red[NW];
+  __shared__ double gred[GL == 1 ? 1 : NT];
   __shared__ int sstop;
   if (a.guard && (a.ctrl->done || a.ctrl->fail)) return;  // the same value in every thread
   if (a.decide) {
@@ -99,10 +144,12 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   }
   // every XCD a contiguous range of lines: the adjacent lines of a strided
   // axis, whose entries share cache lines, run in one L2
-  const uint32_t line = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int gi = GL == 1 ? 0 : int(threadIdx.x) % GL;  // line within the workgroup
+  const int tq = GL == 1 ? int(threadIdx.x) : int(threadIdx.x) / GL;  // thread of its line
+  const uint32_t line = xcd_contiguous(blockIdx.x, gridDim.x) * GL + uint32_t(gi);
   const uint32_t inner = uint32_t(a.inner);
   const int64_t base = int64_t(line % inner) + int64_t(line / inner) * a.outer;
-  const int p0 = int(threadIdx.x) * R;
+  const int p0 = tq * R;
   const T* xin = static_cast<const T*>(a.x);
   T x[R];
 #pragma unroll
@@ -133,8 +180,13 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     T fp, fd, bp, bd;
     run_aggs2<T, R>(x, L, fp, fd, bp, bd);
     S2<T> cf, cb;
-    block_scan<S2<T>, NW, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, S2<T>::zero(),
-                             S2<T>::zero(), &cf, &cb, nullptr, nullptr, sh2);
+    if constexpr (GL == 1) {
+      block_scan<S2<T>, NW, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, S2<T>::zero(),
+                               S2<T>::zero(), &cf, &cb, nullptr, nullptr, sh2);
+    } else {
+      group_scan<S2<T>, NQ, GL, T>(S2<T>::of(fp, fd, E), S2<T>::of(bp, bd, E), dec, gi, tq,
+                                   &cf, &cb, gsh2);
+    }
     const S2<T> lcf = cf.shift(step), lcb = cb.shift(step);
     eref = cost_frame<T, R>(lcf, lcb, local_exponent<T, R>(x, E), k);
     T xf[R];
@@ -147,8 +199,12 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
     T af, ab;
     run_aggs<T, R>(x, L, af, ab);
     S1<T> cf, cb;
-    block_scan<S1<T>, NW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(), S1<T>::zero(),
-                             &cf, &cb, nullptr, nullptr, sh);
+    if constexpr (GL == 1) {
+      block_scan<S1<T>, NW, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, S1<T>::zero(),
+                               S1<T>::zero(), &cf, &cb, nullptr, nullptr, sh);
+    } else {
+      group_scan<S1<T>, NQ, GL, T>(S1<T>{{af, E}}, S1<T>{{ab, E}}, dec, gi, tq, &cf, &cb, gsh);
+    }
     const S1<T> lcf = cf.shift(step), lcb = cb.shift(step);
     if constexpr (SC) {
       // the product on the run's frame: the largest of the run's and the
@@ -180,6 +236,21 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
       }
     return;
   }
+  // a line's share of a sum: the sum of its threads' parts, in part[line]
+  auto line_share = [&](double s) {
+    if constexpr (GL == 1) {
+      const double tot = block_sum<NW>(s, red);
+      if (threadIdx.x == 0) a.part[line] = tot;
+    } else {
+      gred[threadIdx.x] = s;
+      __syncthreads();
+      if (tq == 0) {
+        double tot = 0.0;
+        for (int v = 0; v < NQ; ++v) tot += gred[v * GL + gi];
+        a.part[line] = tot;
+      }
+    }
+  };
   const T* own = static_cast<const T*>(a.own);
   // exponent of own at position q, beside the product's eref
   auto own_exp = [&](int64_t q) { return SC ? a.owne[q] + eref : eref; };
@@ -191,8 +262,7 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
         const int64_t q = base + int64_t(p0 + r) * a.stride;
         s += ldexp(double(own[q]) * double(y[r]), own_exp(q));
       }
-    const double tot = block_sum<NW>(s, red);
-    if (threadIdx.x == 0) a.part[line] = tot;
+    line_share(s);
     return;
   }
   // ERR, UPDATE: | own * (K x) - marg | and marg / (K x)
@@ -205,8 +275,7 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
         const int64_t q = base + int64_t(p0 + r) * a.stride;
         s += fabs(ldexp(double(own[q]) * double(y[r]), own_exp(q)) - a.m64[q]);
       }
-    const double tot = block_sum<NW>(s, red);
-    if (threadIdx.x == 0) a.part[line] = tot;
+    line_share(s);
   }
   if constexpr (MODE == L_UPDATE) {
     bool bad = false;
@@ -693,6 +762,20 @@ struct Axis {
 template <typename T, int R, int MODE, bool SC>
 hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
   const unsigned g = unsigned(ax.nlines);
+  if constexpr (R == kR2) {
+    // a strided axis with line starts a multiple of kGroup entries apart,
+    // lines of at most 32 runs and enough lines for a group per compute unit:
+    // kGroup adjacent lines per workgroup
+    if (ax.inner % kGroup == 0 && ax.len <= 32 * R && ax.nlines >= int64_t(256) * kGroup) {
+      const unsigned gg = unsigned(ax.nlines / kGroup);
+      if (ax.len <= 8 * R) {
+        k_line<T, R, 8 * kGroup, MODE, SC, kGroup><<<gg, 8 * kGroup, 0, s>>>(a, ax.k);
+      } else {
+        k_line<T, R, 32 * kGroup, MODE, SC, kGroup><<<gg, 32 * kGroup, 0, s>>>(a, ax.k);
+      }
+      return hipGetLastError();
+    }
+  }
   if (ax.len <= kWave * R) {
     // one wavefront: its scans and reductions stay in registers
     k_line<T, R, kWave, MODE, SC><<<g, kWave, 0, s>>>(a, ax.k);

@@ -52,7 +52,13 @@ def _pair(dims, seed):
     ((5,), (0.1,), 0.05), ((3, 4, 5), (0.2, 0.1, 0.3), 0.07),
     ((2, 3, 2, 3), (0.5, 0.2, 0.3, 0.1), 0.2), ((700, 3, 2), (0.002, 0.3, 0.1), 0.05),
     ((3, 600, 2), (0.2, 0.003, 0.5), 0.05), ((2, 3, 1500), (0.4, 0.2, 0.001), 0.03),
-    ((33, 1, 65), (0.03, 1.0, 0.02), 0.01), ((17, 19, 23, 3), (0.05, 0.04, 0.03, 0.2), 0.02)])
+    ((33, 1, 65), (0.03, 1.0, 0.02), 0.01), ((17, 19, 23, 3), (0.05, 0.04, 0.03, 0.2), 0.02),
+    # strided axes whose lines start a multiple of 16 entries apart, with at
+    # least 4096 lines (16 adjacent lines per workgroup), lines of up to 64
+    # and 256 entries
+    ((256, 40, 20), (0.004, 0.025, 0.05), 0.02), ((4096, 40), (0.0003, 0.03), 0.01),
+    ((16, 16, 16, 16), (0.06, 0.05, 0.07, 0.04), 0.05), ((32, 200, 8), (0.03, 0.005, 0.1), 0.01),
+    ((64, 100, 64), (0.015, 0.01, 0.015), 0.01)])
 def test_kv_apply_nd(dtype, dims, h, eps):
     fs1 = _fs1()
     n = int(np.prod(dims))
@@ -88,7 +94,9 @@ def _pot_close(g, ref, mask, tol):
 @pytest.mark.parametrize("dims,h,eps,its", [
     ((13, 9, 7), (0.05, 0.08, 0.1), 0.03, 25), ((6, 5, 4, 3), (0.2, 0.25, 0.3, 0.4), 0.1, 20),
     ((40, 30, 20), (0.025, 0.033, 0.05), 0.01, 15), ((300, 4, 3), (0.003, 0.3, 0.4), 0.02, 10),
-    ((2, 2, 700), (0.5, 0.5, 0.0015), 0.01, 8), ((77,), (0.013,), 0.01, 30)])
+    ((2, 2, 700), (0.5, 0.5, 0.0015), 0.01, 8), ((77,), (0.013,), 0.01, 30),
+    ((256, 40, 20), (0.004, 0.025, 0.05), 0.01, 8), ((4096, 24), (0.00025, 0.04), 0.01, 10),
+    ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6)])
 def test_solve_nd_fixed_iterations(domain, dims, h, eps, its):
     fs1 = _fs1()
     mu, nu = _pair(dims, len(dims) * 7 + its)
