@@ -1,4 +1,4 @@
-// fs1_2d.hip -- two-dimensional FS-1 (Sec. 4, Algorithm 2) on an n1 x n2 grid.
+// fs1_2d.hip -- FS-1 on grids (Sec. 4, Algorithm 2): n1 x n2, and up to four axes.
 //
 // Layout: column-major, entry (i, j) at i + n1 j; i runs along the first axis
 // (spacing h1, lambda1 = e^{-h1/eps}), j along the second (h2, lambda2).  The
@@ -9,12 +9,20 @@
 // workgroup per line: a column is contiguous, a row is strided by n1.  A line
 // of up to 1024 R entries is held by one workgroup (thread t owns the line
 // positions [t R, t R + R)) and scanned with the extended-range block scan of
-// the 1-D path; there are no chunk carries.
+// the 1-D path; there are no chunk carries.  On strided axes with short lines
+// a workgroup takes 16 adjacent lines instead, so that its loads read whole
+// cache lines, and every XCD takes a contiguous range of lines.
+//
+// The same passes serve grids of up to four axes (Sec. 4 says the
+// construction extends to higher dimensions): axis a of an n_0 x ... grid
+// (first axis fastest) has lines whose entries lie s_a = n_0 ... n_{a-1}
+// apart, and K = K_{D-1} (x) ... (x) K_0 is one pass per axis.
 //
 // The transport cost splits along the axes: with C_a the 1-D kernel
 // lambda_a^{|d|} |d| of axis a,
-//   W = h1 <phi, (K2 (x) C1) psi> + h2 <phi, (C2 (x) K1) psi>,
-// and C_a x is the two-state recursion of the 1-D cost.
+//   W = h1 <phi, (K2 (x) C1) psi> + h2 <phi, (C2 (x) K1) psi>
+// (on D axes, one such term per axis), and C_a x is the two-state recursion
+// of the 1-D cost.
 //
 // Plain domain (Algorithm 2 as written): scalings are plain numbers, and a
 // non-finite or zero-denominator scaling ends the solve.
