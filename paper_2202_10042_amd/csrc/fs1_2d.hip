@@ -48,6 +48,7 @@ namespace {
 
 constexpr int kR2 = 8;  // entries per thread of a line
 constexpr int kGroup = 16;  // adjacent lines per workgroup on strided axes (128 B in binary64)
+constexpr int kGroupLong = 4;  // the same for lines of 33 .. 256 runs
 
 enum LineMode { L_APPLY = 0, L_COST = 1, L_UPDATE = 2, L_ERR = 3, L_DOT = 4, L_COSTDOT = 5 };
 
@@ -114,19 +115,22 @@ __device__ __forceinline__ void group_scan(S tf, S tb, const Dec<T>* dec, int gi
 
 // SC: the log domain (mantissas with per-entry exponents xe, ye, owne).
 // GL: lines per workgroup.  GL = 1: one line per workgroup, thread t holding
-// its positions [t R, t R + R).  GL = kGroup (strided axes whose line starts
-// are a multiple of kGroup entries apart): kGroup adjacent lines, line gi
-// held by the threads gi + kGroup q, so that the kGroup lanes of one load
-// read kGroup adjacent entries (one whole cache line in binary64).
+// its positions [t R, t R + R).  GL > 1 (strided axes whose line starts are a
+// multiple of GL entries apart): GL adjacent lines, line gi held by the
+// threads gi + GL q, so that the GL lanes of one load read GL adjacent
+// entries (kGroup = 16: one whole cache line in binary64; kGroupLong = 4 for
+// lines of up to 256 runs, a quarter line, the rest of which the next groups
+// on the same XCD read from its L2).
 template <typename T, int R, int NT, int MODE, bool SC, int GL = 1>
 __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   constexpr int NW = NT / kWave;
   constexpr int NQ = NT / GL;            // threads per line
   constexpr int NQG = GL == 1 ? 1 : NQ;  // size of the grouped scan's LDS
+  constexpr bool kCostMode = MODE == L_COST || MODE == L_COSTDOT;
   __shared__ ScanLds<S1<T>, NW> sh;
   __shared__ ScanLds<S2<T>, NW> sh2;
-  __shared__ GroupLds<S1<T>, NQG, GL> gsh;
-  __shared__ GroupLds<S2<T>, NQG, GL> gsh2;
+  __shared__ GroupLds<S1<T>, kCostMode ? 1 : NQG, GL> gsh;
+  __shared__ GroupLds<S2<T>, kCostMode ? NQG : 1, GL> gsh2;
   __shared__ double red[NW];
   __shared__ double gred[GL == 1 ? 1 : NT];
   __shared__ int sstop;
@@ -782,6 +786,22 @@ hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
         k_line<T, R, 32 * kGroup, MODE, SC, kGroup><<<gg, 32 * kGroup, 0, s>>>(a, ax.k);
       }
       return hipGetLastError();
+    }
+    // longer lines (up to 256 runs): kGroupLong adjacent lines per workgroup
+    // (not the cost recursion, whose two-state scan would need twice the LDS)
+    if constexpr (MODE != L_COST && MODE != L_COSTDOT) {
+      if (ax.inner % kGroupLong == 0 && ax.len > 32 * R && ax.len <= 256 * R &&
+          ax.nlines >= int64_t(256) * kGroupLong) {
+        const unsigned gg = unsigned(ax.nlines / kGroupLong);
+        if (ax.len <= 128 * R) {
+          k_line<T, R, 128 * kGroupLong, MODE, SC, kGroupLong>
+              <<<gg, 128 * kGroupLong, 0, s>>>(a, ax.k);
+        } else {
+          k_line<T, R, 256 * kGroupLong, MODE, SC, kGroupLong>
+              <<<gg, 256 * kGroupLong, 0, s>>>(a, ax.k);
+        }
+        return hipGetLastError();
+      }
     }
   }
   if (ax.len <= kWave * R) {

@@ -58,7 +58,9 @@ def _pair(dims, seed):
     # and 256 entries
     ((256, 40, 20), (0.004, 0.025, 0.05), 0.02), ((4096, 40), (0.0003, 0.03), 0.01),
     ((16, 16, 16, 16), (0.06, 0.05, 0.07, 0.04), 0.05), ((32, 200, 8), (0.03, 0.005, 0.1), 0.01),
-    ((64, 100, 64), (0.015, 0.01, 0.015), 0.01)])
+    ((64, 100, 64), (0.015, 0.01, 0.015), 0.01),
+    # lines of 33 .. 256 runs on a strided axis: 4 adjacent lines per workgroup
+    ((1024, 300), (0.001, 0.003), 0.01), ((1200, 1600), (0.0008, 0.0006), 0.005)])
 def test_kv_apply_nd(dtype, dims, h, eps):
     fs1 = _fs1()
     n = int(np.prod(dims))
@@ -96,7 +98,7 @@ def _pot_close(g, ref, mask, tol):
     ((40, 30, 20), (0.025, 0.033, 0.05), 0.01, 15), ((300, 4, 3), (0.003, 0.3, 0.4), 0.02, 10),
     ((2, 2, 700), (0.5, 0.5, 0.0015), 0.01, 8), ((77,), (0.013,), 0.01, 30),
     ((256, 40, 20), (0.004, 0.025, 0.05), 0.01, 8), ((4096, 24), (0.00025, 0.04), 0.01, 10),
-    ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6)])
+    ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6), ((1024, 300), (0.001, 0.003), 0.01, 5)])
 def test_solve_nd_fixed_iterations(domain, dims, h, eps, its):
     fs1 = _fs1()
     mu, nu = _pair(dims, len(dims) * 7 + its)
