@@ -774,7 +774,7 @@ struct Axis {
 template <typename T, int R, int MODE, bool SC>
 hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
   const unsigned g = unsigned(ax.nlines);
-  if constexpr (R == kR2) {
+  {
     // a strided axis with line starts a multiple of kGroup entries apart,
     // lines of at most 32 runs and enough lines for a group per compute unit:
     // kGroup adjacent lines per workgroup
@@ -793,7 +793,10 @@ hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
       if (ax.inner % kGroupLong == 0 && ax.len > 32 * R && ax.len <= 256 * R &&
           ax.nlines >= int64_t(256) * kGroupLong) {
         const unsigned gg = unsigned(ax.nlines / kGroupLong);
-        if (ax.len <= 128 * R) {
+        if (ax.len <= 64 * R) {
+          k_line<T, R, 64 * kGroupLong, MODE, SC, kGroupLong>
+              <<<gg, 64 * kGroupLong, 0, s>>>(a, ax.k);
+        } else if (ax.len <= 128 * R) {
           k_line<T, R, 128 * kGroupLong, MODE, SC, kGroupLong>
               <<<gg, 128 * kGroupLong, 0, s>>>(a, ax.k);
         } else {

@@ -98,7 +98,10 @@ def _pot_close(g, ref, mask, tol):
     ((40, 30, 20), (0.025, 0.033, 0.05), 0.01, 15), ((300, 4, 3), (0.003, 0.3, 0.4), 0.02, 10),
     ((2, 2, 700), (0.5, 0.5, 0.0015), 0.01, 8), ((77,), (0.013,), 0.01, 30),
     ((256, 40, 20), (0.004, 0.025, 0.05), 0.01, 8), ((4096, 24), (0.00025, 0.04), 0.01, 10),
-    ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6), ((1024, 300), (0.001, 0.003), 0.01, 5)])
+    ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6), ((1024, 300), (0.001, 0.003), 0.01, 5),
+    # h/eps = 100: runs of one entry in the log domain, 4 and 16 adjacent
+    # lines per workgroup on the strided axes
+    ((64, 64, 48), (1.0, 1.0, 1.0), 0.01, 5), ((32, 16, 512), (1.0, 1.0, 1.0), 0.01, 5)])
 def test_solve_nd_fixed_iterations(domain, dims, h, eps, its):
     fs1 = _fs1()
     mu, nu = _pair(dims, len(dims) * 7 + its)
