@@ -332,8 +332,10 @@ int fs1_solve_batched_config(fs1_ctx *ctx, const double *mu_packed, const double
 /* The kernel is K_{(i,j),(k,l)} = lambda1^{|i-k|} lambda2^{|j-l|},          */
 /* lambda_a = exp(-h_a / eps): the block matrix of Sec. 4, applied by the    */
 /* 1-D recursions along every column and then eq. (2d recursion) across the  */
-/* columns.  1 <= n1, n2 <= 8192; h1, h2 > 0 and finite; eps > 0 and finite  */
-/* (else FS1_ERR_INVALID_ARG before any launch).                             */
+/* columns.  1 <= n1, n2 <= 8192; h1, h2 > 0 and finite; eps > 0 and finite; */
+/* n_a h_a / eps <= 1e8 on each axis; in the log domain an axis with h/eps    */
+/* beyond the bound of runs of 8 holds at most 1024 entries (else             */
+/* FS1_ERR_INVALID_ARG before any launch).                                   */
 /* ------------------------------------------------------------------------ */
 
 /* y = K x for device arrays x, y of n1 n2 entries of dtype dt (FS1_F64 or
