@@ -751,7 +751,8 @@ def serving_study(fs1, ctx, inputs, np, torch, seconds: float, full: bool = True
     includes a queue that grows through the window), then at sustainable
     rates, drained: with `full`, a sweep of fractions of the measured
     capacity (12 s windows: a window's p99 rests on its slowest 1%, a few
-    dozen requests) for the highest rate that keeps p99 latency within the
+    dozen requests; finer steps around half the capacity, where the 3 s
+    target falls) for the highest rate that keeps p99 latency within the
     target; otherwise half of the capacity only."""
     seed = 77
     # warm-up: a few requests through the server (graph instantiation)
@@ -763,7 +764,8 @@ def serving_study(fs1, ctx, inputs, np, torch, seconds: float, full: bool = True
     log(f"serving at 20k req/s offered ({seconds:.0f} s): {cap:.1f} solves/s, p50 "
         f"{sat['p50_latency_ms']:.0f} ms p99 {sat['p99_latency_ms']:.0f} ms, "
         f"{sat['waiting_at_end']} waiting at the end")
-    rates = [0.5 * cap] if not full else [f * cap for f in (0.1, 0.2, 0.3, 0.4, 0.5, 0.75)]
+    rates = [0.5 * cap] if not full else [f * cap for f in (0.1, 0.2, 0.3, 0.4, 0.45, 0.5, 0.55,
+                                                            0.75)]
     sweep = []
     for i, rate in enumerate(rates):
         r = serve_stream(fs1, ctx, inputs, np, torch, rate, min(seconds, 12.0), seed + 1 + i,
