@@ -49,6 +49,7 @@ namespace {
 constexpr int kR2 = 8;  // entries per thread of a line
 constexpr int kGroup = 16;  // adjacent lines per workgroup on strided axes (128 B in binary64)
 constexpr int kGroupLong = 4;  // the same for lines of 33 .. 256 runs
+constexpr int kContThreads = 256;  // workgroup of the grouped short contiguous lines
 
 enum LineMode { L_APPLY = 0, L_COST = 1, L_UPDATE = 2, L_ERR = 3, L_DOT = 4, L_COSTDOT = 5 };
 
@@ -120,8 +121,10 @@ __device__ __forceinline__ void group_scan(S tf, S tb, const Dec<T>* dec, int gi
 // threads gi + GL q, so that the GL lanes of one load read GL adjacent
 // entries (kGroup = 16: one whole cache line in binary64; kGroupLong = 4 for
 // lines of up to 256 runs, a quarter line, the rest of which the next groups
-// on the same XCD read from its L2).
-template <typename T, int R, int NT, int MODE, bool SC, int GL = 1>
+// on the same XCD read from its L2).  CONT (short contiguous lines, the first
+// axis): GL lines one after another, line gi held by the threads gi NQ + q,
+// so that a workgroup streams GL lines instead of one.
+template <typename T, int R, int NT, int MODE, bool SC, int GL = 1, bool CONT = false>
 __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   constexpr int NW = NT / kWave;
   constexpr int NQ = NT / GL;            // threads per line
@@ -156,8 +159,9 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
   }
   // every XCD a contiguous range of lines: the adjacent lines of a strided
   // axis, whose entries share cache lines, run in one L2
-  const int gi = GL == 1 ? 0 : int(threadIdx.x) % GL;  // line within the workgroup
-  const int tq = GL == 1 ? int(threadIdx.x) : int(threadIdx.x) / GL;  // thread of its line
+  // line within the workgroup, and thread of its line
+  const int gi = GL == 1 ? 0 : (CONT ? int(threadIdx.x) / NQ : int(threadIdx.x) % GL);
+  const int tq = GL == 1 ? int(threadIdx.x) : (CONT ? int(threadIdx.x) % NQ : int(threadIdx.x) / GL);
   const uint32_t line = xcd_contiguous(blockIdx.x, gridDim.x) * GL + uint32_t(gi);
   const uint32_t inner = uint32_t(a.inner);
   const int64_t base = int64_t(line % inner) + int64_t(line / inner) * a.outer;
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_line(LineArgs a, ScanConsts k) {
       __syncthreads();
       if (tq == 0) {
         double tot = 0.0;
-        for (int v = 0; v < NQ; ++v) tot += gred[v * GL + gi];
+        for (int v = 0; v < NQ; ++v) tot += gred[CONT ? gi * NQ + v : v * GL + gi];
         a.part[line] = tot;
       }
     }
@@ -774,7 +778,34 @@ struct Axis {
 template <typename T, int R, int MODE, bool SC>
 hipError_t run_pass_r(const Axis& ax, const LineArgs& a, hipStream_t s) {
   const unsigned g = unsigned(ax.nlines);
-  {
+  if (ax.inner == 1) {
+    // short contiguous lines (the first axis): several one after another
+    // per workgroup of kContThreads, each on the fewest threads that hold it,
+    // where one line per workgroup would leave most of its lanes idle -- 16
+    // or 32 threads' worth in a one-wavefront workgroup, with a group per
+    // compute unit, or 128 threads' worth in a 256-thread workgroup, with
+    // 2048 groups (measured: with fewer lines, or 64 threads' worth, the
+    // one-line form's wavefront scan is faster than the group's LDS scan)
+    constexpr int NTc = kContThreads;
+    int nq = 16;
+    while (int64_t(nq) * R < ax.len && nq < 128) nq *= 2;
+    const int64_t gl = NTc / nq;
+    const bool fits = int64_t(nq) * R >= ax.len && ax.nlines % gl == 0;
+    if (fits && nq <= 32 && ax.nlines >= 256 * gl) {
+      const unsigned gg = unsigned(ax.nlines / gl);
+      if (nq == 16) {
+        k_line<T, R, NTc, MODE, SC, NTc / 16, true><<<gg, NTc, 0, s>>>(a, ax.k);
+      } else {
+        k_line<T, R, NTc, MODE, SC, NTc / 32, true><<<gg, NTc, 0, s>>>(a, ax.k);
+      }
+      return hipGetLastError();
+    }
+    if (fits && nq == 128 && ax.nlines >= 2048 * gl) {
+      k_line<T, R, NTc, MODE, SC, NTc / 128, true><<<unsigned(ax.nlines / gl), NTc, 0, s>>>(a,
+                                                                                      ax.k);
+      return hipGetLastError();
+    }
+  } else {
     // a strided axis with line starts a multiple of kGroup entries apart,
     // lines of at most 32 runs and enough lines for a group per compute unit:
     // kGroup adjacent lines per workgroup

@@ -60,7 +60,9 @@ def _pair(dims, seed):
     ((16, 16, 16, 16), (0.06, 0.05, 0.07, 0.04), 0.05), ((32, 200, 8), (0.03, 0.005, 0.1), 0.01),
     ((64, 100, 64), (0.015, 0.01, 0.015), 0.01),
     # lines of 33 .. 256 runs on a strided axis: 4 adjacent lines per workgroup
-    ((1024, 300), (0.001, 0.003), 0.01), ((1200, 1600), (0.0008, 0.0006), 0.005)])
+    ((1024, 300), (0.001, 0.003), 0.01), ((1200, 1600), (0.0008, 0.0006), 0.005),
+    # short first-axis lines, several per workgroup: 16 and 128 threads per line
+    ((600, 4096), (0.0015, 0.0003), 0.01), ((96, 4096), (0.01, 0.0003), 0.01)])
 def test_kv_apply_nd(dtype, dims, h, eps):
     fs1 = _fs1()
     n = int(np.prod(dims))
@@ -101,7 +103,8 @@ def _pot_close(g, ref, mask, tol):
     ((48, 96, 100), (0.02, 0.01, 0.01), 0.01, 6), ((1024, 300), (0.001, 0.003), 0.01, 5),
     # h/eps = 100: runs of one entry in the log domain, 4 and 16 adjacent
     # lines per workgroup on the strided axes
-    ((64, 64, 48), (1.0, 1.0, 1.0), 0.01, 5), ((32, 16, 512), (1.0, 1.0, 1.0), 0.01, 5)])
+    ((64, 64, 48), (1.0, 1.0, 1.0), 0.01, 5), ((32, 16, 512), (1.0, 1.0, 1.0), 0.01, 5),
+    ((128, 64, 64), (1.0, 1.0, 1.0), 0.01, 4)])
 def test_solve_nd_fixed_iterations(domain, dims, h, eps, its):
     fs1 = _fs1()
     mu, nu = _pair(dims, len(dims) * 7 + its)
