@@ -1,7 +1,7 @@
 """The oracle's C code under AddressSanitizer and UndefinedBehaviorSanitizer
 (host code only): a small driver calls every entry point on grids from 1 to a
 few hundred entries, with row lists at both ends, invalid arguments, the 2-D
-forms and the stabilised solver, and compares the O(n) recursions with the
+forms (plain and log), the forms on 1 to 4 axes and the stabilised solver, and compares the O(n) recursions with the
 dense definitions on the way.  Any out-of-bounds access, leak, overflow or
 other undefined behaviour aborts the driver."""
 import os
@@ -42,6 +42,22 @@ int or_sinkhorn2_dense(int64_t, int64_t, const double *, const double *, double,
                        double, int64_t, double *, double *, double *);
 int or_fs1_2d(int64_t, int64_t, const double *, const double *, double, double, double, double,
               int64_t, double *, double *, double *);
+int or_sinkhorn2_log_dense(int64_t, int64_t, const double *, const double *, double, double,
+                           double, double, int64_t, double *, double *, double *);
+int or_fs1_2d_log(int64_t, int64_t, const double *, const double *, double, double, double,
+                  double, int64_t, double *, double *, double *);
+int or_kvn_dense(int, const int64_t *, const double *, const double *, double, double *);
+int or_kvn_fs1(int, const int64_t *, const double *, const double *, double, double *);
+int or_kvn_log_dense(int, const int64_t *, const double *, const double *, double, double *);
+int or_kvn_fs1_log(int, const int64_t *, const double *, const double *, double, double *);
+int or_sinkhornn_dense(int, const int64_t *, const double *, const double *, const double *,
+                       double, double, int64_t, double *, double *, double *);
+int or_fs1_nd(int, const int64_t *, const double *, const double *, const double *, double,
+              double, int64_t, double *, double *, double *);
+int or_sinkhornn_log_dense(int, const int64_t *, const double *, const double *, const double *,
+                           double, double, int64_t, double *, double *, double *);
+int or_fs1_nd_log(int, const int64_t *, const double *, const double *, const double *, double,
+                  double, int64_t, double *, double *, double *);
 void or_set_num_threads(int);
 
 static uint64_t s = 88172645463325252ull;
@@ -106,6 +122,41 @@ int main(void) {
     hist(n, nu);
     CHECK(or_sinkhorn2_dense(n1, n2, mu, nu, 0.2, 0.1, 0.05, 1e-9, 30, a, b, res) == 0);
     CHECK(or_fs1_2d(n1, n2, mu, nu, 0.2, 0.1, 0.05, 1e-9, 30, a, b, res) == 0);
+    CHECK(or_sinkhorn2_log_dense(n1, n2, mu, nu, 0.2, 0.1, 0.01, 1e-9, 30, a, b, res) == 0);
+    CHECK(or_fs1_2d_log(n1, n2, mu, nu, 0.2, 0.1, 0.01, 1e-9, 30, a, b, res) == 0);
+  }
+  {
+    /* D axes: 1 to 4, with a singleton axis */
+    const int64_t dims_all[4][4] = {{7, 0, 0, 0}, {4, 5, 0, 0}, {3, 1, 4, 0}, {2, 3, 2, 3}};
+    const double hs[4] = {0.2, 0.1, 0.3, 0.15};
+    for (int d = 1; d <= 4; ++d) {
+      const int64_t *dims = dims_all[d - 1];
+      int64_t n = 1;
+      for (int a2 = 0; a2 < d; ++a2) n *= dims[a2];
+      double *x = malloc(n * sizeof *x), *y = malloc(n * sizeof *y), *z = malloc(n * sizeof *z);
+      double *mu = malloc(n * sizeof *mu), *nu = malloc(n * sizeof *nu);
+      double *a = malloc(n * sizeof *a), *b = malloc(n * sizeof *b);
+      double res[6];
+      for (int64_t i = 0; i < n; ++i) x[i] = 0.1 + urand();
+      CHECK(or_kvn_dense(d, dims, x, hs, 0.07, y) == 0);
+      CHECK(or_kvn_fs1(d, dims, x, hs, 0.07, z) == 0);
+      for (int64_t i = 0; i < n; ++i) CHECK(fabs(y[i] - z[i]) <= 1e-12 * y[i]);
+      for (int64_t i = 0; i < n; ++i) x[i] = (urand() < 0.2) ? -INFINITY : 3.0 * urand();
+      CHECK(or_kvn_log_dense(d, dims, x, hs, 0.07, y) == 0);
+      CHECK(or_kvn_fs1_log(d, dims, x, hs, 0.07, z) == 0);
+      hist(n, mu);
+      hist(n, nu);
+      CHECK(or_sinkhornn_dense(d, dims, mu, nu, hs, 0.07, 1e-9, 20, a, b, res) == 0);
+      CHECK(or_fs1_nd(d, dims, mu, nu, hs, 0.07, 1e-9, 20, a, b, res) == 0);
+      CHECK(or_sinkhornn_log_dense(d, dims, mu, nu, hs, 0.01, 1e-9, 20, a, b, res) == 0);
+      CHECK(or_fs1_nd_log(d, dims, mu, nu, hs, 0.01, 1e-9, 20, a, b, res) == 0);
+      CHECK(or_fs1_nd(d, dims, mu, nu, hs, -1.0, 1e-9, 20, a, b, res) != 0);
+      free(x); free(y); free(z); free(mu); free(nu); free(a); free(b);
+    }
+    const int64_t bad[2] = {3, 0};
+    double t[3], u[3];
+    CHECK(or_kvn_dense(2, bad, t, hs, 0.1, u) != 0);
+    CHECK(or_kvn_fs1(0, bad, t, hs, 0.1, u) != 0);
   }
   printf("ok\n");
   return 0;
